@@ -1,0 +1,713 @@
+/*
+ * tk_oracle.c -- serial FP64 reference implementation of the real-space AMOEBA
+ * pair terms (multipoles, Thole-damped dipole field, induced-dipole PCG,
+ * Halgren 14-7 and Lennard-Jones van der Waals, Ewald point charges).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  It shares no code, header, table or constant with the GPU
+ * library; only the test suite, the smoke check and the CPU leg of the
+ * benchmark may load it.  Every quantity is the plain definition evaluated
+ * pair by pair, in FP64, with no blocking, fusion or reordering; the one
+ * iteration (the conjugate-gradient solve) follows its algorithm step by step.
+ *
+ * Paper: "Raising the Performance of the Tinker-HP Molecular Modeling
+ * Package" (arXiv 1906.01211).  The paper names the terms but never writes
+ * their formulas: section "Polarizable AMOEBA force field" names permanent
+ * multipoles through quadrupoles, Thole-damped induced point dipoles and the
+ * Halgren buffered 14-7 vdW; section "Hotspots" (Table of the Rel profile)
+ * names the routines this file mirrors: the polarization mat-vec, the
+ * permanent-field right-hand side, the multipole energy, the 14-7 energy, the
+ * LJ 12-6 and charge-charge energies, and the cell-list neighbour builders.
+ * The only formula-level content is the 14-7 compute loop (Listing
+ * "calculation", section "Typical compute loop") and the neighbour selection
+ * mask (Listing "creationmask", section "Typical selection loop").  All other
+ * formulas are the textbook Ewald / multipole / Thole definitions, written out
+ * here; the readings taken where the paper is silent are listed in the
+ * design notes of the repository and restated at each function below.
+ *
+ * Conventions: r = r_j - r_i for a pair (i, j); forces are F = -dE/dx;
+ * units are Angstrom, elementary charge, kcal/mol.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_E_ARG (-1)
+#define OR_E_CUTOFF (-2)
+#define OR_E_CAPACITY (-3)
+#define OR_E_NOCONV (-4)
+#define OR_E_BREAKDOWN (-5)
+
+/* Reading: Coulomb constant e^2/(4 pi eps0) in kcal*A/(mol*e^2), and the
+ * e*A -> Debye factor.  The paper states neither. */
+static const double OR_COULOMB = 332.0637;
+static const double OR_DEBYE = 4.80320;
+static const double OR_SQRTPI = 1.7724538509055160273;
+
+double or_coulomb_constant(void) { return OR_COULOMB; }
+double or_debye_factor(void) { return OR_DEBYE; }
+
+/* ------------------------------------------------------------------------ */
+/* Geometry: minimum image in FP64.  The pair vector is d = x_j - x_i with
+ * d := d - L*rint(d/L) written as one fused multiply-add, and
+ * r^2 = fma(dx,dx, fma(dy,dy, dz*dz)).  (The paper's "image" routine wraps
+ * pair vectors; section "Hotspots".) */
+static void or_image(const double* xi, const double* xj, double box, double d[3],
+                     double* r2) {
+  for (int a = 0; a < 3; ++a) {
+    double t = xj[a] - xi[a];
+    d[a] = fma(-box, rint(t / box), t);
+  }
+  *r2 = fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour list (the cell-list builders of the Rel profile table; the
+ * selection of neighbours by cutoff, section "General Structure").
+ * Reading: the list is integer and exact.  Each coordinate is mapped to a
+ * 32-bit fraction of the box, u = floor(frac(x/L) * 2^32); the minimum-image
+ * difference is the wrapped 32-bit difference; a pair is listed iff
+ * dx^2+dy^2+dz^2 <= rq^2 in exact 64-bit integer arithmetic, with
+ * rq = floor((rc/L) * 2^32).  Rows hold j > i in ascending order (CSR). */
+int or_quantize(int n, const double* xyz, double box, uint32_t* u) {
+  if (n < 0 || !(box > 0.0) || !isfinite(box)) return OR_E_ARG;
+  for (int i = 0; i < 3 * n; ++i) {
+    double x = xyz[i];
+    if (!isfinite(x)) return OR_E_ARG;
+    double t = x / box;
+    double f = t - floor(t);
+    if (f >= 1.0) f = 0.0; /* t slightly below an integer can round f up to 1 */
+    u[i] = (uint32_t)(f * 4294967296.0);
+  }
+  return OR_OK;
+}
+
+uint32_t or_cutoff_quantum(double rc, double box) {
+  return (uint32_t)floor((rc / box) * 4294967296.0);
+}
+
+static int or_pair_in(const uint32_t* u, int i, int j, uint64_t rq2) {
+  uint64_t d2 = 0;
+  for (int a = 0; a < 3; ++a) {
+    int64_t d = (int32_t)(u[3 * j + a] - u[3 * i + a]);
+    d2 += (uint64_t)(d * d);
+  }
+  return d2 <= rq2;
+}
+
+static int or_list_args(int n, double box, double rc) {
+  if (n < 0 || !(box > 0.0) || !(rc > 0.0) || !isfinite(rc)) return OR_E_ARG;
+  if (rc > 0.5 * box) return OR_E_CUTOFF;
+  return OR_OK;
+}
+
+/* O(N^2) definition: every unordered pair is tested once. */
+int or_nblist_brute(int n, const double* xyz, double box, double rc, int32_t* row_ptr,
+                    int32_t* col, int64_t cap, int64_t* npairs) {
+  int st = or_list_args(n, box, rc);
+  if (st) return st;
+  uint32_t* u = (uint32_t*)malloc(sizeof(uint32_t) * 3 * (size_t)(n > 0 ? n : 1));
+  st = or_quantize(n, xyz, box, u);
+  if (st) { free(u); return st; }
+  uint64_t rq = or_cutoff_quantum(rc, box);
+  uint64_t rq2 = rq * rq;
+  int64_t np = 0;
+  for (int i = 0; i < n; ++i) {
+    row_ptr[i] = (int32_t)(np < cap ? np : cap);
+    for (int j = i + 1; j < n; ++j) {
+      if (or_pair_in(u, i, j, rq2)) {
+        if (np < cap) col[np] = j;
+        ++np;
+      }
+    }
+  }
+  row_ptr[n] = (int32_t)(np < cap ? np : cap);
+  *npairs = np;
+  free(u);
+  return np > cap ? OR_E_CAPACITY : OR_OK;
+}
+
+static int or_cmp_int(const void* a, const void* b) {
+  int x = *(const int*)a, y = *(const int*)b;
+  return (x > y) - (x < y);
+}
+
+/* Cell list: ncell = floor(L/rc) cells per dimension (each at least rc wide
+ * in the 32-bit fixed point), the unique cells among the 27 around the cell
+ * of i are scanned, and each row is sorted ascending. */
+int or_nblist_cell(int n, const double* xyz, double box, double rc, int32_t* row_ptr,
+                   int32_t* col, int64_t cap, int64_t* npairs) {
+  int st = or_list_args(n, box, rc);
+  if (st) return st;
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  uint32_t* u = (uint32_t*)malloc(sizeof(uint32_t) * 3 * nn);
+  st = or_quantize(n, xyz, box, u);
+  if (st) { free(u); return st; }
+  uint64_t rq = or_cutoff_quantum(rc, box);
+  uint64_t rq2 = rq * rq;
+  int nc = (int)floor(box / rc);
+  if (nc < 1) nc = 1;
+  int ncell = nc * nc * nc;
+  int* cell = (int*)malloc(sizeof(int) * nn);
+  int* cstart = (int*)calloc((size_t)ncell + 1, sizeof(int));
+  int* cfill = (int*)calloc((size_t)ncell, sizeof(int));
+  int* catom = (int*)malloc(sizeof(int) * nn);
+  for (int i = 0; i < n; ++i) {
+    int c[3];
+    for (int a = 0; a < 3; ++a) c[a] = (int)(((uint64_t)u[3 * i + a] * (uint64_t)nc) >> 32);
+    cell[i] = (c[0] * nc + c[1]) * nc + c[2];
+    cstart[cell[i] + 1]++;
+  }
+  for (int c = 0; c < ncell; ++c) cstart[c + 1] += cstart[c];
+  for (int i = 0; i < n; ++i) catom[cstart[cell[i]] + cfill[cell[i]]++] = i;
+  int* buf = (int*)malloc(sizeof(int) * nn);
+  int64_t np = 0;
+  for (int i = 0; i < n; ++i) {
+    int ci[3] = {cell[i] / (nc * nc), (cell[i] / nc) % nc, cell[i] % nc};
+    int nb[3][3], cnt[3];
+    for (int a = 0; a < 3; ++a) { /* unique neighbour cells per dimension */
+      cnt[a] = 0;
+      for (int o = -1; o <= 1; ++o) {
+        int v = ((ci[a] + o) % nc + nc) % nc, dup = 0;
+        for (int k = 0; k < cnt[a]; ++k) dup |= (nb[a][k] == v);
+        if (!dup) nb[a][cnt[a]++] = v;
+      }
+    }
+    int m = 0;
+    for (int x = 0; x < cnt[0]; ++x)
+      for (int y = 0; y < cnt[1]; ++y)
+        for (int z = 0; z < cnt[2]; ++z) {
+          int c = (nb[0][x] * nc + nb[1][y]) * nc + nb[2][z];
+          for (int k = cstart[c]; k < cstart[c + 1]; ++k) {
+            int j = catom[k];
+            if (j > i && or_pair_in(u, i, j, rq2)) buf[m++] = j;
+          }
+        }
+    qsort(buf, (size_t)m, sizeof(int), or_cmp_int);
+    row_ptr[i] = (int32_t)(np < cap ? np : cap);
+    for (int k = 0; k < m; ++k) {
+      if (np < cap) col[np] = buf[k];
+      ++np;
+    }
+  }
+  row_ptr[n] = (int32_t)(np < cap ? np : cap);
+  *npairs = np;
+  free(u); free(cell); free(cstart); free(cfill); free(catom); free(buf);
+  return np > cap ? OR_E_CAPACITY : OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Radial kernel families.  Ewald-screened:
+ *   B0 = erfc(beta r)/r,
+ *   Bn = [(2n-1) B(n-1) + (2 beta^2)^n exp(-beta^2 r^2)/(beta sqrt(pi))] / r^2;
+ * bare Coulomb Rn = (2n-1)!!/r^(2n+1) (= Bn at beta = 0).  Both families obey
+ * f(n+1) = -(1/r) d f(n)/dr, so the gradient of f(n) along r is -r f(n+1). */
+void or_radial(double r, double beta, int nmax, double* B, double* R) {
+  double r2 = r * r;
+  R[0] = 1.0 / r;
+  for (int k = 1; k <= nmax; ++k) R[k] = (2 * k - 1) * R[k - 1] / r2;
+  if (beta == 0.0) {
+    for (int k = 0; k <= nmax; ++k) B[k] = R[k];
+    return;
+  }
+  double ex = exp(-beta * beta * r2) / (beta * OR_SQRTPI);
+  double b2 = 2.0 * beta * beta, pw = 1.0;
+  B[0] = erfc(beta * r) / r;
+  for (int k = 1; k <= nmax; ++k) {
+    pw *= b2;
+    B[k] = ((2 * k - 1) * B[k - 1] + pw * ex) / r2;
+  }
+}
+
+/* Thole damping, exponential AMOEBA form.  Reading: pair parameter
+ * a_ij = min(a_i, a_j); x = a_ij * r^3 / sqrt(alpha_i alpha_j);
+ * l3 = 1 - e^-x, l5 = 1 - (1+x) e^-x, l7 = 1 - (1 + x + 0.6 x^2) e^-x;
+ * all three are 1 when alpha_i alpha_j = 0. */
+void or_thole(double r, double ai, double aj, double ti, double tj, double* l3,
+              double* l5, double* l7) {
+  double prod = ai * aj;
+  if (prod == 0.0) { *l3 = *l5 = *l7 = 1.0; return; }
+  double a = ti < tj ? ti : tj;
+  double x = a * r * r * r / sqrt(prod);
+  double e = exp(-x);
+  *l3 = 1.0 - e;
+  *l5 = 1.0 - (1.0 + x) * e;
+  *l7 = 1.0 - (1.0 + x + 0.6 * x * x) * e;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multipole pair energy and its gradient with respect to r = r_j - r_i.
+ * Site k carries (q, mu, Theta) with Theta symmetric and traceless; its
+ * potential at y is [q - mu.grad + Theta:grad grad] f0(|y - r_k|).  With
+ * d = mu.r, v = Theta r, Q = r.Theta.r the interaction is C * sum_n c_n g_n:
+ *   c0 = qi qj
+ *   c1 = qj di - qi dj + mui.muj
+ *   c2 = qi Qj + qj Qi - di dj + 2 (muj.vi - mui.vj + Thi:Thj)
+ *   c3 = di Qj - dj Qi - 4 vi.vj
+ *   c4 = Qi Qj
+ * and de/dr = C * sum_n [ (dc_n/dr) g_n - c_n r g(n+1) ].
+ * mpole layout per site: q, mux, muy, muz, Txx, Txy, Txz, Tyy, Tyz, Tzz. */
+static void or_unpack(const double* m, double* q, double mu[3], double th[3][3]) {
+  *q = m[0];
+  mu[0] = m[1]; mu[1] = m[2]; mu[2] = m[3];
+  th[0][0] = m[4]; th[0][1] = th[1][0] = m[5]; th[0][2] = th[2][0] = m[6];
+  th[1][1] = m[7]; th[1][2] = th[2][1] = m[8]; th[2][2] = m[9];
+}
+
+static double or_dot(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+static void or_matvec3(double th[3][3], const double x[3], double y[3]) {
+  for (int a = 0; a < 3; ++a) y[a] = th[a][0] * x[0] + th[a][1] * x[1] + th[a][2] * x[2];
+}
+
+void or_mpole_pair(const double r[3], const double* mi, const double* mj, const double* g,
+                   double* e, double de[3]) {
+  double qi, qj, ui[3], uj[3], ti[3][3], tj[3][3];
+  or_unpack(mi, &qi, ui, ti);
+  or_unpack(mj, &qj, uj, tj);
+  double di = or_dot(ui, r), dj = or_dot(uj, r);
+  double vi[3], vj[3];
+  or_matvec3(ti, r, vi);
+  or_matvec3(tj, r, vj);
+  double Qi = or_dot(r, vi), Qj = or_dot(r, vj);
+  double tt = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) tt += ti[a][b] * tj[a][b];
+  double c[5];
+  c[0] = qi * qj;
+  c[1] = qj * di - qi * dj + or_dot(ui, uj);
+  c[2] = qi * Qj + qj * Qi - di * dj + 2.0 * (or_dot(uj, vi) - or_dot(ui, vj) + tt);
+  c[3] = di * Qj - dj * Qi - 4.0 * or_dot(vi, vj);
+  c[4] = Qi * Qj;
+  double tivj[3], tjvi[3], tiuj[3], tjui[3];
+  or_matvec3(ti, vj, tivj);
+  or_matvec3(tj, vi, tjvi);
+  or_matvec3(ti, uj, tiuj);
+  or_matvec3(tj, ui, tjui);
+  double dc[5][3];
+  for (int a = 0; a < 3; ++a) {
+    dc[0][a] = 0.0;
+    dc[1][a] = qj * ui[a] - qi * uj[a];
+    dc[2][a] = 2.0 * qi * vj[a] + 2.0 * qj * vi[a] - dj * ui[a] - di * uj[a] +
+               2.0 * (tiuj[a] - tjui[a]);
+    dc[3][a] = Qj * ui[a] + 2.0 * di * vj[a] - Qi * uj[a] - 2.0 * dj * vi[a] -
+               4.0 * (tivj[a] + tjvi[a]);
+    dc[4][a] = 2.0 * Qj * vi[a] + 2.0 * Qi * vj[a];
+  }
+  double en = 0.0;
+  double gr[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k <= 4; ++k) {
+    en += c[k] * g[k];
+    for (int a = 0; a < 3; ++a) gr[a] += dc[k][a] * g[k] - c[k] * r[a] * g[k + 1];
+  }
+  *e = OR_COULOMB * en;
+  for (int a = 0; a < 3; ++a) de[a] = OR_COULOMB * gr[a];
+}
+
+static int or_pair_args(int n, double box, double rc) {
+  if (n < 0 || !(box > 0.0) || !(rc > 0.0)) return OR_E_ARG;
+  if (rc > 0.5 * box) return OR_E_CUTOFF;
+  return OR_OK;
+}
+
+/* Real-space Ewald permanent-multipole energy, forces and virial over the
+ * listed pairs with r <= rc (section "Hotspots": the multipolar permanent
+ * electrostatic energy and forces).  Reading: pairs with equal molid are
+ * excluded from the direct interaction; for them g_n = B_n - R_n (the Ewald
+ * correction that removes the screened part carried by reciprocal space);
+ * for all other pairs g_n = B_n.  energy[0] = total, energy[1] = sum over
+ * non-excluded pairs, energy[2] = sum of the exclusion corrections.
+ * Virial W_ab = sum over pairs of r_a * de/dr_b. */
+int or_empole_real(int n, const double* xyz, double box, const int32_t* molid,
+                   const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                   double beta, double rc, double* energy, double* force, double* virial) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  double rc2 = rc * rc;
+  energy[0] = energy[1] = energy[2] = 0.0;
+  for (int k = 0; k < 9; ++k) virial[k] = 0.0;
+  for (int k = 0; k < 3 * n; ++k) force[k] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int j = col[p];
+      double d[3], r2;
+      or_image(xyz + 3 * i, xyz + 3 * j, box, d, &r2);
+      if (!(r2 <= rc2)) continue;
+      double r = sqrt(r2), B[6], R[6], g[6];
+      or_radial(r, beta, 5, B, R);
+      int excl = molid[i] == molid[j];
+      for (int k = 0; k <= 5; ++k) g[k] = excl ? B[k] - R[k] : B[k];
+      double e, de[3];
+      or_mpole_pair(d, mpole + 10 * i, mpole + 10 * j, g, &e, de);
+      energy[excl ? 2 : 1] += e;
+      for (int a = 0; a < 3; ++a) {
+        force[3 * i + a] += de[a];
+        force[3 * j + a] -= de[a];
+        for (int b = 0; b < 3; ++b) virial[3 * a + b] += d[a] * de[b];
+      }
+    }
+  }
+  energy[0] = energy[1] + energy[2];
+  return OR_OK;
+}
+
+/* Point-charge Ewald real space: e = C qi qj g0 (the charge-charge routine of
+ * the CHARMM profile).  Same exclusion reading as above. */
+int or_echarge_real(int n, const double* xyz, double box, const int32_t* molid,
+                    const int32_t* row_ptr, const int32_t* col, const double* q, double beta,
+                    double rc, double* energy, double* force, double* virial) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  double rc2 = rc * rc;
+  energy[0] = energy[1] = energy[2] = 0.0;
+  for (int k = 0; k < 9; ++k) virial[k] = 0.0;
+  for (int k = 0; k < 3 * n; ++k) force[k] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int j = col[p];
+      double d[3], r2;
+      or_image(xyz + 3 * i, xyz + 3 * j, box, d, &r2);
+      if (!(r2 <= rc2)) continue;
+      double r = sqrt(r2), B[2], R[2];
+      or_radial(r, beta, 1, B, R);
+      int excl = molid[i] == molid[j];
+      double g0 = excl ? B[0] - R[0] : B[0];
+      double g1 = excl ? B[1] - R[1] : B[1];
+      double e = OR_COULOMB * q[i] * q[j] * g0;
+      energy[excl ? 2 : 1] += e;
+      for (int a = 0; a < 3; ++a) {
+        double de = -OR_COULOMB * q[i] * q[j] * g1 * d[a];
+        force[3 * i + a] += de;
+        force[3 * j + a] -= de;
+        for (int b = 0; b < 3; ++b) virial[3 * a + b] += d[a] * (-OR_COULOMB * q[i] * q[j] * g1 * d[b]);
+      }
+    }
+  }
+  energy[0] = energy[1] + energy[2];
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Permanent field (the right-hand side of the polarization equations;
+ * section "Hotspots").  Field at i from the multipoles of j, with
+ * T1 = -r g1, T2 = r r g2 - I g1, (T3:Theta)_a = -r_a Q g3 + 2 (Theta r)_a g2:
+ *   E_i += qj T1 + T2 muj + T3:Thj,     E_j += -qi T1 + T2 mui - T3:Thi,
+ * with g_n = B_n - (1 - s l_(2n+1)) R_n, s = 0 for equal molid, else 1
+ * (reading: no direct field inside a molecule, Ewald correction kept).
+ * Plus the Ewald self field c mu_i, c = 4 beta^3 / (3 sqrt(pi)).
+ * The field carries no Coulomb constant (units e/A^2). */
+int or_efield_direct(int n, const double* xyz, double box, const int32_t* molid,
+                     const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                     const double* polarity, const double* thole, double beta, double rc,
+                     double* field) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  double rc2 = rc * rc;
+  double cself = 4.0 * beta * beta * beta / (3.0 * OR_SQRTPI);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) field[3 * i + a] = cself * mpole[10 * i + 1 + a];
+  for (int i = 0; i < n; ++i) {
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int j = col[p];
+      double d[3], r2;
+      or_image(xyz + 3 * i, xyz + 3 * j, box, d, &r2);
+      if (!(r2 <= rc2)) continue;
+      double r = sqrt(r2), B[4], R[4], l3, l5, l7;
+      or_radial(r, beta, 3, B, R);
+      or_thole(r, polarity[i], polarity[j], thole[i], thole[j], &l3, &l5, &l7);
+      double s = molid[i] == molid[j] ? 0.0 : 1.0;
+      double g1 = B[1] - (1.0 - s * l3) * R[1];
+      double g2 = B[2] - (1.0 - s * l5) * R[2];
+      double g3 = B[3] - (1.0 - s * l7) * R[3];
+      double qi, qj, ui[3], uj[3], ti[3][3], tj[3][3];
+      or_unpack(mpole + 10 * i, &qi, ui, ti);
+      or_unpack(mpole + 10 * j, &qj, uj, tj);
+      double di = or_dot(ui, d), dj = or_dot(uj, d), vi[3], vj[3];
+      or_matvec3(ti, d, vi);
+      or_matvec3(tj, d, vj);
+      double Qi = or_dot(d, vi), Qj = or_dot(d, vj);
+      for (int a = 0; a < 3; ++a) {
+        double T1 = -d[a] * g1;
+        double T2uj = d[a] * dj * g2 - uj[a] * g1;
+        double T2ui = d[a] * di * g2 - ui[a] * g1;
+        double T3j = -d[a] * Qj * g3 + 2.0 * vj[a] * g2;
+        double T3i = -d[a] * Qi * g3 + 2.0 * vi[a] * g2;
+        field[3 * i + a] += qj * T1 + T2uj + T3j;
+        field[3 * j + a] += -qi * T1 + T2ui - T3i;
+      }
+    }
+  }
+  return OR_OK;
+}
+
+/* Mutual induced-dipole field (the polarization-solver mat-vec, the largest
+ * hotspot of the Rel profile).  For every listed pair with r <= rc, the same
+ * molecule included (reading: mutual scale 1):
+ *   E_i += T2 mu_j,  E_j += T2 mu_i,  g1 = B1 - (1-l3) R1, g2 = B2 - (1-l5) R2,
+ * plus the self field c mu_i.  include_diag = 0 returns this field (T + cI) mu;
+ * include_diag = 1 returns A mu = mu/alpha - (T + cI) mu, the operator of the
+ * polarization equations (zero rows for alpha = 0, reading). */
+int or_tmatvec(int n, const double* xyz, double box, const int32_t* row_ptr,
+               const int32_t* col, const double* polarity, const double* thole, double beta,
+               double rc, int include_diag, const double* mu, double* out) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  double rc2 = rc * rc;
+  double cself = 4.0 * beta * beta * beta / (3.0 * OR_SQRTPI);
+  double* fld = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+  for (int k = 0; k < 3 * n; ++k) fld[k] = cself * mu[k];
+  for (int i = 0; i < n; ++i) {
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int j = col[p];
+      double d[3], r2;
+      or_image(xyz + 3 * i, xyz + 3 * j, box, d, &r2);
+      if (!(r2 <= rc2)) continue;
+      double r = sqrt(r2), B[3], R[3], l3, l5, l7;
+      or_radial(r, beta, 2, B, R);
+      or_thole(r, polarity[i], polarity[j], thole[i], thole[j], &l3, &l5, &l7);
+      double g1 = B[1] - (1.0 - l3) * R[1];
+      double g2 = B[2] - (1.0 - l5) * R[2];
+      double di = or_dot(mu + 3 * i, d), dj = or_dot(mu + 3 * j, d);
+      for (int a = 0; a < 3; ++a) {
+        fld[3 * i + a] += d[a] * dj * g2 - mu[3 * j + a] * g1;
+        fld[3 * j + a] += d[a] * di * g2 - mu[3 * i + a] * g1;
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      int k = 3 * i + a;
+      if (!include_diag) out[k] = fld[k];
+      else out[k] = polarity[i] > 0.0 ? mu[k] / polarity[i] - fld[k] : 0.0;
+    }
+  free(fld);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Induced dipoles by preconditioned conjugate gradient (the polarization
+ * solver of section "Hotspots", which calls the mat-vec up to 12 times per
+ * step).  Reading: diagonal preconditioner M^-1 = alpha; initial guess
+ * alpha * E_perm unless a guess is given; the convergence measure is the RMS
+ * over polarizable atoms of the preconditioned residual z = alpha r, in Debye,
+ * checked before each mat-vec; E_pol = -1/2 C sum_i mu_i . E_perm_i. */
+typedef struct {
+  int32_t status, iters, refinements, converged;
+  double rms_debye, rms_true_debye, epol;
+} or_pcg_info;
+
+static double or_rmsd(int n, const double* z, int npol) {
+  if (npol == 0) return 0.0;
+  double s = 0.0;
+  for (int k = 0; k < 3 * n; ++k) s += z[k] * z[k];
+  return OR_DEBYE * sqrt(s / npol);
+}
+
+int or_polarize_pcg(int n, const double* xyz, double box, const int32_t* molid,
+                    const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                    const double* polarity, const double* thole, double beta, double rc,
+                    double tol_debye, int maxiter, const double* mu_guess, double* mu_out,
+                    or_pcg_info* info) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  if (maxiter < 0 || !(tol_debye >= 0.0)) return OR_E_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!(polarity[i] >= 0.0)) return OR_E_ARG;
+  size_t m = 3 * (size_t)(n > 0 ? n : 1);
+  double* b = (double*)malloc(sizeof(double) * m);
+  double* r = (double*)malloc(sizeof(double) * m);
+  double* z = (double*)malloc(sizeof(double) * m);
+  double* p = (double*)malloc(sizeof(double) * m);
+  double* q = (double*)malloc(sizeof(double) * m);
+  double* x = mu_out;
+  int npol = 0;
+  for (int i = 0; i < n; ++i) npol += polarity[i] > 0.0;
+  or_efield_direct(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, b);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      int k = 3 * i + a;
+      x[k] = mu_guess ? (polarity[i] > 0.0 ? mu_guess[k] : 0.0) : polarity[i] * b[k];
+    }
+  or_tmatvec(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, 1, x, q);
+  double rho = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      int k = 3 * i + a;
+      r[k] = polarity[i] > 0.0 ? b[k] - q[k] : 0.0;
+      z[k] = polarity[i] * r[k];
+      p[k] = z[k];
+      rho += r[k] * z[k];
+    }
+  int status = OR_OK, converged = 0, it = 0;
+  double rms = 0.0;
+  for (it = 0;; ++it) {
+    rms = or_rmsd(n, z, npol);
+    if (rms <= tol_debye) { converged = 1; break; }
+    if (it == maxiter) { status = OR_E_NOCONV; break; }
+    or_tmatvec(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, 1, p, q);
+    double gam = 0.0;
+    for (int k = 0; k < 3 * n; ++k) gam += p[k] * q[k];
+    if (!(gam > 0.0)) { status = OR_E_BREAKDOWN; break; }
+    double alpha = rho / gam, rho1 = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) {
+        int k = 3 * i + a;
+        x[k] += alpha * p[k];
+        r[k] -= alpha * q[k];
+        z[k] = polarity[i] * r[k];
+        rho1 += r[k] * z[k];
+      }
+    double bet = rho1 / rho;
+    for (int k = 0; k < 3 * n; ++k) p[k] = z[k] + bet * p[k];
+    rho = rho1;
+  }
+  /* final true residual, from a fresh mat-vec */
+  or_tmatvec(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, 1, x, q);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      int k = 3 * i + a;
+      z[k] = polarity[i] > 0.0 ? polarity[i] * (b[k] - q[k]) : 0.0;
+    }
+  double epol = 0.0;
+  for (int k = 0; k < 3 * n; ++k) epol += x[k] * b[k];
+  info->status = status;
+  info->iters = it;
+  info->refinements = 0;
+  info->converged = converged;
+  info->rms_debye = rms;
+  info->rms_true_debye = or_rmsd(n, z, npol);
+  info->epol = -0.5 * OR_COULOMB * epol;
+  free(b); free(r); free(z); free(p); free(q);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* van der Waals (the Halgren 14-7 and LJ 12-6 routines of the Rel profile).
+ * HAL, in the quantities of the paper's compute loop (Listing
+ * "calculation"): rv = R_ij, rv7 = rv^7, rik7 = r^7,
+ * invrho = 1/(rik7 + ghal rv7), invtmp = 1/(r + dhal rv):
+ *   e = eps_ij [(1+dhal) rv invtmp]^7 [(1+ghal) rv7 invrho - 2].
+ * Readings: R_ij = (Ri^3 + Rj^3)/(Ri^2 + Rj^2),
+ * eps_ij = 4 ei ej / (sqrt(ei) + sqrt(ej))^2, no hydrogen reduction.
+ * LJ: e = 4 eps_ij [(s/r)^12 - (s/r)^6], s = (si+sj)/2, eps_ij = sqrt(ei ej).
+ * Both: pairs with equal molid are skipped; the energy is multiplied by the
+ * taper S(x) = 1 - 10x^3 + 15x^4 - 6x^5, x = (r - ron)/(rc - ron),
+ * ron = taper_frac * rc, for r > ron. */
+#define OR_VDW_HAL 0
+#define OR_VDW_LJ 1
+
+static void or_vdw_pair(int form, double r, double ri, double rj, double ei, double ej,
+                        double dhal, double ghal, double* e, double* dedr) {
+  if (form == OR_VDW_HAL) {
+    double rv = (ri * ri * ri + rj * rj * rj) / (ri * ri + rj * rj);
+    double se = sqrt(ei) + sqrt(ej);
+    double eps = se > 0.0 ? 4.0 * ei * ej / (se * se) : 0.0;
+    double rv7 = pow(rv, 7.0);
+    double rik7 = pow(r, 7.0);
+    double invrho = 1.0 / (rik7 + ghal * rv7);
+    double invtmp = 1.0 / (r + dhal * rv);
+    double t7 = pow((1.0 + dhal) * rv * invtmp, 7.0);
+    double w = (1.0 + ghal) * rv7 * invrho;
+    *e = eps * t7 * (w - 2.0);
+    /* d t7/dr = -7 t7 invtmp ; d w/dr = -7 r^6 w invrho */
+    *dedr = eps * (-7.0 * t7 * invtmp * (w - 2.0) - t7 * 7.0 * pow(r, 6.0) * w * invrho);
+  } else {
+    double s = 0.5 * (ri + rj);
+    double eps = sqrt(ei * ej);
+    double sr6 = pow(s / r, 6.0);
+    *e = 4.0 * eps * (sr6 * sr6 - sr6);
+    *dedr = 4.0 * eps * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r;
+  }
+}
+
+int or_evdw(int n, const double* xyz, double box, const int32_t* molid, const int32_t* row_ptr,
+            const int32_t* col, int form, const double* rad, const double* eps, double rc,
+            double taper_frac, double dhal, double ghal, double* energy, double* force,
+            double* virial) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  if (form != OR_VDW_HAL && form != OR_VDW_LJ) return OR_E_ARG;
+  double rc2 = rc * rc, ron = taper_frac * rc;
+  *energy = 0.0;
+  for (int k = 0; k < 9; ++k) virial[k] = 0.0;
+  for (int k = 0; k < 3 * n; ++k) force[k] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int j = col[p];
+      if (molid[i] == molid[j]) continue;
+      double d[3], r2;
+      or_image(xyz + 3 * i, xyz + 3 * j, box, d, &r2);
+      if (!(r2 <= rc2)) continue;
+      double r = sqrt(r2), e, dedr;
+      or_vdw_pair(form, r, rad[i], rad[j], eps[i], eps[j], dhal, ghal, &e, &dedr);
+      if (r > ron) {
+        double w = rc - ron, x = (r - ron) / w;
+        double S = 1.0 - 10.0 * pow(x, 3) + 15.0 * pow(x, 4) - 6.0 * pow(x, 5);
+        double dS = (-30.0 * x * x + 60.0 * pow(x, 3) - 30.0 * pow(x, 4)) / w;
+        dedr = dedr * S + e * dS;
+        e *= S;
+      }
+      *energy += e;
+      for (int a = 0; a < 3; ++a) {
+        double de = dedr * d[a] / r;
+        force[3 * i + a] += de;
+        force[3 * j + a] -= de;
+        for (int b = 0; b < 3; ++b) virial[3 * a + b] += d[a] * dedr * d[b] / r;
+      }
+    }
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Validation-only Ewald pieces (not on the GPU path).
+ * Self energy: -C beta/sqrt(pi) sum_i [qi^2 + (2 beta^2/3)|mui|^2
+ *                                      + (8 beta^4/5) Thi:Thi].
+ * Reciprocal energy (tin-foil):
+ *   (C/2V) sum_{k != 0} (4 pi/k^2) exp(-k^2/(4 beta^2)) |S(k)|^2,
+ *   S(k) = sum_j (qj + i muj.k - Thj:kk) exp(i k.r_j), k = 2 pi m / L,
+ * over integer vectors m with |m_a| <= kmax. */
+double or_eself(int n, const double* mpole, double beta) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double q, u[3], t[3][3];
+    or_unpack(mpole + 10 * i, &q, u, t);
+    double tt = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) tt += t[a][b] * t[a][b];
+    s += q * q + (2.0 * beta * beta / 3.0) * or_dot(u, u) + (8.0 * pow(beta, 4) / 5.0) * tt;
+  }
+  return -OR_COULOMB * beta / OR_SQRTPI * s;
+}
+
+double or_erecip(int n, const double* xyz, double box, const double* mpole, double beta,
+                 int kmax) {
+  const double twopi = 6.283185307179586477;
+  double vol = box * box * box, sum = 0.0;
+  for (int mx = -kmax; mx <= kmax; ++mx)
+    for (int my = -kmax; my <= kmax; ++my)
+      for (int mz = -kmax; mz <= kmax; ++mz) {
+        if (!mx && !my && !mz) continue;
+        double k[3] = {twopi * mx / box, twopi * my / box, twopi * mz / box};
+        double k2 = or_dot(k, k);
+        double damp = exp(-k2 / (4.0 * beta * beta)) * 4.0 * M_PI / k2;
+        if (damp < 1e-300) continue;
+        double sr = 0.0, si = 0.0;
+        for (int j = 0; j < n; ++j) {
+          double q, u[3], t[3][3], tk[3];
+          or_unpack(mpole + 10 * j, &q, u, t);
+          or_matvec3(t, k, tk);
+          double re = q - or_dot(k, tk), im = or_dot(u, k);
+          double ph = or_dot(k, xyz + 3 * j);
+          double c = cos(ph), s = sin(ph);
+          sr += re * c - im * s;
+          si += re * s + im * c;
+        }
+        sum += damp * (sr * sr + si * si);
+      }
+  return OR_COULOMB * sum / (2.0 * vol);
+}
