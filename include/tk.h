@@ -1,0 +1,219 @@
+/*
+ * tk.h -- C-ABI of the MI355X real-space AMOEBA pair engine (libtk.so).
+ *
+ * What it computes (arXiv 1906.01211, section "Hotspots", Table of the Rel
+ * profile): the routines that dominate a polarizable AMOEBA step on the
+ * paper's CPUs -- the cell-list neighbour builders, the permanent-multipole
+ * real-space energy and forces, the permanent field (the right-hand side of
+ * the polarization equations), the induced-dipole field mat-vec used at every
+ * iteration of the polarization solver, the Halgren buffered 14-7 vdW term,
+ * and, for the non-polarizable path, point charges and Lennard-Jones 12-6.
+ * The paper names these terms (section "Polarizable AMOEBA force field") but
+ * does not write their formulas; the definitions implemented are the textbook
+ * Ewald real-space / Thole / Halgren ones and are stated at each entry point.
+ *
+ * Conventions shared by every call:
+ *  - Units: Angstrom, elementary charge e, e*A (dipoles), e*A^2 (quadrupoles),
+ *    A^3 (polarizabilities), kcal/mol, kcal/mol/A.  Dipole tolerances in Debye
+ *    (1 e*A = 4.80320 D).  Coulomb constant C = 332.0637 kcal*A/(mol*e^2).
+ *  - Periodic cubic box of edge `box`; pair vectors use the minimum image;
+ *    every cutoff must satisfy cutoff <= box/2 (else TK_E_CUTOFF).
+ *  - Pair vector r = r_j - r_i; forces are F = -dE/dx, written (not
+ *    accumulated) as [n][3]; virials W_ab = sum over pairs r_a dE/dr_b, [3][3].
+ *  - Array arguments are DEVICE pointers owned by the caller (unless a
+ *    parameter says "host"); nothing is retained after the call returns.
+ *    `stream` is a hipStream_t (NULL = default stream).  Calls are ordered on
+ *    that stream.  Entry points that return results through host memory
+ *    (tk_nblist_build, tk_polarize_pcg) synchronise the stream before
+ *    returning; the others are asynchronous.
+ *  - Errors: every call returns a tk_status; argument errors are detected on
+ *    the host before any work is queued; no exception crosses the ABI.
+ *  - Precision: prec = TK_FP64 (all pair arithmetic in FP64) or TK_MIXED (pair
+ *    geometry, screening, damping and contractions in FP32; energies, virial,
+ *    forces, fields and all solver reductions accumulated in FP64).
+ *  - A tk_ctx owns scratch device memory (grown on demand, never shrunk, never
+ *    freed between calls) and up to TK_MAX_PLANS neighbour-list plans.  A
+ *    context is not thread safe; use one per host thread.
+ */
+#ifndef TK_H
+#define TK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tk_ctx tk_ctx;
+typedef int32_t tk_status;
+
+enum {
+  TK_OK = 0,
+  TK_E_ARG = -1,       /* invalid argument (null pointer, n < 0, NaN, bad enum) */
+  TK_E_CUTOFF = -2,    /* cutoff > box/2 */
+  TK_E_CAPACITY = -3,  /* output capacity too small; the required size is reported */
+  TK_E_NOCONV = -4,    /* PCG did not reach the tolerance within maxiter */
+  TK_E_BREAKDOWN = -5, /* PCG found p.Ap <= 0 (operator not positive definite) */
+  TK_E_NOMEM = -6,     /* device allocation failed */
+  TK_E_HIP = -7,       /* a HIP runtime call failed */
+  TK_E_BUSY = -8,      /* serving: result not ready yet */
+  TK_E_PLAN = -9       /* the list's plan slot is empty or was built for another system */
+};
+
+enum { TK_FP64 = 0, TK_MIXED = 1 };
+enum { TK_VDW_HAL = 0, TK_VDW_LJ = 1 };
+#define TK_MAX_PLANS 8
+
+/* Atoms of one periodic system.  xyz: device [n][3] (A, any real values:
+ * they are wrapped), molid: device [n] molecule id (pairs with equal molid are
+ * "excluded": see each entry point). */
+typedef struct {
+  int32_t n;
+  const double* xyz;
+  double box;
+  const int32_t* molid;
+} tk_system;
+
+/* A neighbour list as returned by tk_nblist_build.
+ * row_ptr: device [n+1]; col: device [npairs]; row i holds every j > i with
+ * |r_ij| <= cutoff (integer test below), ascending.  `plan` names the context
+ * slot that holds the same pair set in the cell-pair order the kernels use. */
+typedef struct {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  int64_t npairs;
+  double cutoff;
+  int32_t plan;
+} tk_nblist;
+
+/* Outcome of a polarization solve (host memory). */
+typedef struct {
+  int32_t status;      /* TK_OK, TK_E_NOCONV or TK_E_BREAKDOWN */
+  int32_t iters;       /* PCG updates performed (mat-vecs after the initial residual) */
+  int32_t refinements; /* FP64 refinement rounds (TK_MIXED only) */
+  int32_t converged;   /* 1 if the stopping rule was met */
+  double rms_debye;      /* RMS preconditioned residual at exit (solver recurrence) */
+  double rms_true_debye; /* same, from a fresh FP64 residual b - A mu */
+  double epol;           /* -1/2 C sum_i mu_i . E_perm_i, kcal/mol */
+} tk_pcg_info;
+
+/* Context on HIP device `device`. */
+tk_status tk_create(int device, tk_ctx** out);
+void tk_destroy(tk_ctx* ctx);
+const char* tk_strerror(tk_status s);
+
+/*
+ * Neighbour list (the cell-list builders of the Rel profile; neighbour
+ * selection by cutoff, section "General Structure"; the selection mask and
+ * compress loop, section "Typical selection loop").
+ * Exact integer definition: u = floor(frac(x/box) * 2^32) per coordinate
+ * (x/box rounded as an IEEE division; a fraction that rounds to 1 wraps to 0),
+ * d = (int32)(u_j - u_i), and (i, j) is listed iff dx^2+dy^2+dz^2 <= rq^2 in
+ * exact 64-bit arithmetic with rq = floor((cutoff/box) * 2^32).  The list is
+ * purely geometric (same-molecule pairs are included).
+ * Writes the canonical half list (row_ptr [n+1], col [cap]) and fills plan
+ * slot `plan_slot` of the context.  *npairs (host) receives the number of
+ * pairs; if it exceeds `cap`, returns TK_E_CAPACITY, col is not written and
+ * the plan is left empty.  row_ptr/col may be NULL (with cap = 0) to build the
+ * plan only.  Synchronises `stream`.  Errors: TK_E_ARG (n < 0, NULL xyz,
+ * non-finite coordinate, plan_slot out of range), TK_E_CUTOFF.
+ */
+tk_status tk_nblist_build(tk_ctx* ctx, void* stream, const tk_system* sys, double cutoff,
+                          int32_t plan_slot, int32_t* row_ptr, int32_t* col, int64_t cap,
+                          int64_t* npairs);
+
+/*
+ * Real-space Ewald permanent-multipole energy, forces and virial (the
+ * multipolar permanent electrostatic routine of section "Hotspots").
+ * mpole: device [n][10] = q, mu_x, mu_y, mu_z, Theta_xx, Theta_xy, Theta_xz,
+ * Theta_yy, Theta_yz, Theta_zz with Theta traceless and the site potential
+ * [q - mu.grad + Theta:grad grad] 1/r.  For each listed pair with r <= cutoff
+ * the energy is C sum_n c_n g_n (n = 0..4; c_n the usual charge/dipole/
+ * quadrupole invariants), g_n = B_n (Ewald-screened radial functions,
+ * B_0 = erfc(beta r)/r) for pairs of different molecules and g_n = B_n - R_n
+ * (removal of the screened part, R_n bare) within a molecule.  No
+ * self or reciprocal-space term.  energy: device [3] = total, sum over
+ * non-excluded pairs, sum of intramolecular corrections.  force: [n][3];
+ * virial: [3][3].  A charge-only input (mu = Theta = 0) is accepted; see also
+ * tk_echarge_real.
+ */
+tk_status tk_empole_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                         const double* mpole, double ewald_beta, double cutoff, int prec,
+                         double* energy, double* force, double* virial);
+
+/*
+ * Point-charge Ewald real space (the charge-charge routine of the CHARMM
+ * profile): e = C q_i q_j g_0 with the same molecule rule as tk_empole_real.
+ * q: device [n].  energy: device [3] as above.
+ */
+tk_status tk_echarge_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                          const double* q, double ewald_beta, double cutoff, int prec,
+                          double* energy, double* force, double* virial);
+
+/*
+ * Permanent field at every site (the right-hand side of the polarization
+ * equations; efld0_direct in the Rel profile).  For each listed pair with
+ * r <= cutoff: E_i += q_j T1 + T2 mu_j + T3:Theta_j and
+ * E_j += -q_i T1 + T2 mu_i - T3:Theta_i, with T1 = -r g1, T2 = r r g2 - I g1,
+ * (T3:Theta)_a = -r_a (r.Theta.r) g3 + 2 (Theta r)_a g2,
+ * g_n = B_n - (1 - s l_(2n+1)) R_n, s = 0 within a molecule else 1, and the
+ * Thole factors l3 = 1 - e^-x, l5 = 1 - (1+x) e^-x, l7 = 1 - (1+x+0.6x^2) e^-x,
+ * x = min(a_i, a_j) r^3 / sqrt(alpha_i alpha_j) (l = 1 when alpha_i alpha_j = 0);
+ * plus the Ewald self field c mu_i, c = 4 beta^3 / (3 sqrt(pi)).
+ * polarity: device [n] (A^3, >= 0); thole: device [n]; field: device [n][3]
+ * in e/A^2 (no Coulomb constant).
+ */
+tk_status tk_efield_direct(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                           const double* mpole, const double* polarity, const double* thole,
+                           double ewald_beta, double cutoff, int prec, double* field);
+
+/*
+ * Induced-dipole field mat-vec (tmatxb in the Rel profile, the largest
+ * hotspot).  For every listed pair with r <= cutoff (same molecule included):
+ * out_i += T2 mu_j, out_j += T2 mu_i with g1 = B1 - (1 - l3) R1,
+ * g2 = B2 - (1 - l5) R2, plus the self field c mu_i.  include_diag = 0 returns
+ * this field (T + cI) mu; include_diag = 1 returns A mu = mu_i/alpha_i - field_i
+ * (rows of atoms with alpha = 0 are zero).  mu, out: device [n][3].
+ */
+tk_status tk_tmatvec(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                     const double* polarity, const double* thole, double ewald_beta,
+                     double cutoff, int include_diag, int prec, const double* mu, double* out);
+
+/*
+ * Induced dipoles: solve A mu = E_perm (A as in tk_tmatvec, E_perm as in
+ * tk_efield_direct) by preconditioned conjugate gradient, the polarization
+ * solver that calls the mat-vec up to 12 times per step (section
+ * "Hotspots").  Preconditioner diag(alpha); initial guess mu_guess (device
+ * [n][3], may be NULL: then alpha * E_perm).  Stopping rule, checked before
+ * each mat-vec: 4.80320 * sqrt(sum |alpha_i r_i|^2 / n_pol) <= tol_debye.
+ * After the loop a fresh FP64 residual is formed (info->rms_true_debye);
+ * with TK_MIXED, up to 3 FP64-residual refinement rounds are added while it
+ * exceeds the tolerance.  mu_out: device [n][3].  info: HOST memory.
+ * Returns info->status.  Synchronises `stream`.
+ */
+tk_status tk_polarize_pcg(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                          const double* mpole, const double* polarity, const double* thole,
+                          double ewald_beta, double cutoff, double tol_debye, int32_t maxiter,
+                          int prec, const double* mu_guess, double* mu_out, tk_pcg_info* info);
+
+/*
+ * van der Waals (ehal / elj in the Rel profile).  form = TK_VDW_HAL: Halgren
+ * buffered 14-7, e = eps_ij [(1+d) R_ij/(r + d R_ij)]^7
+ * [(1+g) R_ij^7/(r^7 + g R_ij^7) - 2], R_ij = (R_i^3+R_j^3)/(R_i^2+R_j^2),
+ * eps_ij = 4 e_i e_j/(sqrt(e_i)+sqrt(e_j))^2, d = hal_delta, g = hal_gamma.
+ * form = TK_VDW_LJ: e = 4 eps_ij [(s/r)^12 - (s/r)^6], s = (s_i+s_j)/2,
+ * eps_ij = sqrt(e_i e_j).  Same-molecule pairs are skipped; for
+ * r > taper_on_frac * cutoff the energy is multiplied by
+ * S(x) = 1 - 10x^3 + 15x^4 - 6x^5, x = (r - r_on)/(cutoff - r_on).
+ * radius_or_sigma, eps: device [n].  energy: device [1].
+ */
+tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                  int form, const double* radius_or_sigma, const double* eps, double cutoff,
+                  double taper_on_frac, double hal_delta, double hal_gamma, int prec,
+                  double* energy, double* force, double* virial);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TK_H */

@@ -1,0 +1,195 @@
+// Pair terms on the cell-pair tile skeleton: permanent multipoles (energy,
+// forces, virial), point charges, permanent field, induced-dipole field
+// mat-vec, Halgren 14-7 / LJ 12-6 van der Waals; their C-ABI entry points.
+#include <cmath>
+
+#include "pairs.hpp"
+#include "terms.hpp"
+
+namespace tk {
+
+namespace {
+
+__global__ void k_finish_energy3(const double* __restrict__ sums, double* energy, double* virial) {
+  energy[0] = sums[0] + sums[1];
+  energy[1] = sums[0];
+  energy[2] = sums[1];
+  for (int k = 0; k < 9; ++k) virial[k] = sums[2 + k];
+}
+
+__global__ void k_finish_energy1(const double* __restrict__ sums, double* energy, double* virial) {
+  energy[0] = sums[0];
+  for (int k = 0; k < 9; ++k) virial[k] = sums[1 + k];
+}
+
+tk_status common_args(tk_ctx* ctx, const tk_system* sys, const tk_nblist* list, double cutoff,
+                      int prec, const Plan** plan) {
+  if (!ctx) return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (prec != TK_FP64 && prec != TK_MIXED) return TK_E_ARG;
+  if (!std::isfinite(cutoff)) return TK_E_ARG;
+  return get_plan(ctx, sys, list, cutoff, plan);
+}
+
+}  // namespace
+
+template <class R>
+tk_status launch_tmat(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_system* sys,
+                      const double* polarity, const double* thole, double beta, double cutoff,
+                      int include_diag, const double* mu, double* out) {
+  TmatPh<R> ph;
+  ph.xyz = sys->xyz;
+  ph.mu = mu;
+  ph.mu_sorted = 0;
+  ph.polarity = polarity;
+  ph.thole = thole;
+  ph.g.set(sys->box, cutoff, beta);
+  ph.molid = sys->molid;
+  EpiMutual epi{out, mu, polarity, ph.g.cself, include_diag};
+  return run_term(ctx, st, P, ph, epi, nullptr);
+}
+
+
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+tk_status tk_empole_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                         const double* mpole, double ewald_beta, double cutoff, int prec,
+                         double* energy, double* force, double* virial) {
+  const Plan* P;
+  tk_status s = common_args(ctx, sys, list, cutoff, prec, &P);
+  if (s) return s;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !energy || !virial) return TK_E_ARG;
+  if (sys->n > 0 && (!mpole || !force)) return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  void* sums;
+  if ((s = scratch(ctx, "sums", sizeof(double) * 32, &sums))) return s;
+  if (sys->n == 0) {
+    TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
+    TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
+    return TK_OK;
+  }
+  if (prec == TK_FP64) {
+    EmpolePh<double> ph;
+    ph.xyz = sys->xyz; ph.mpole = mpole; ph.molid = sys->molid;
+    ph.g.set(sys->box, cutoff, ewald_beta);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+  } else {
+    EmpolePh<float> ph;
+    ph.xyz = sys->xyz; ph.mpole = mpole; ph.molid = sys->molid;
+    ph.g.set(sys->box, cutoff, ewald_beta);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+  }
+  if (s) return s;
+  k_finish_energy3<<<1, 1, 0, st>>>((double*)sums, energy, virial);
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+tk_status tk_echarge_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                          const double* q, double ewald_beta, double cutoff, int prec,
+                          double* energy, double* force, double* virial) {
+  const Plan* P;
+  tk_status s = common_args(ctx, sys, list, cutoff, prec, &P);
+  if (s) return s;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !energy || !virial) return TK_E_ARG;
+  if (sys->n > 0 && (!q || !force)) return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  void* sums;
+  if ((s = scratch(ctx, "sums", sizeof(double) * 32, &sums))) return s;
+  if (sys->n == 0) {
+    TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
+    TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
+    return TK_OK;
+  }
+  if (prec == TK_FP64) {
+    ChargePh<double> ph;
+    ph.xyz = sys->xyz; ph.q = q; ph.molid = sys->molid;
+    ph.g.set(sys->box, cutoff, ewald_beta);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+  } else {
+    ChargePh<float> ph;
+    ph.xyz = sys->xyz; ph.q = q; ph.molid = sys->molid;
+    ph.g.set(sys->box, cutoff, ewald_beta);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+  }
+  if (s) return s;
+  k_finish_energy3<<<1, 1, 0, st>>>((double*)sums, energy, virial);
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+tk_status tk_efield_direct(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                           const double* mpole, const double* polarity, const double* thole,
+                           double ewald_beta, double cutoff, int prec, double* field) {
+  const Plan* P;
+  tk_status s = common_args(ctx, sys, list, cutoff, prec, &P);
+  if (s) return s;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta)) return TK_E_ARG;
+  if (sys->n == 0) return TK_OK;
+  if (!mpole || !polarity || !thole || !field) return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  return prec == TK_FP64
+             ? launch_efield<double>(ctx, st, *P, sys, mpole, polarity, thole, ewald_beta, cutoff,
+                                     field, 0)
+             : launch_efield<float>(ctx, st, *P, sys, mpole, polarity, thole, ewald_beta, cutoff,
+                                    field, 0);
+}
+
+tk_status tk_tmatvec(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                     const double* polarity, const double* thole, double ewald_beta,
+                     double cutoff, int include_diag, int prec, const double* mu, double* out) {
+  const Plan* P;
+  tk_status s = common_args(ctx, sys, list, cutoff, prec, &P);
+  if (s) return s;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta)) return TK_E_ARG;
+  if (include_diag != 0 && include_diag != 1) return TK_E_ARG;
+  if (sys->n == 0) return TK_OK;
+  if (!polarity || !thole || !mu || !out) return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  return prec == TK_FP64 ? launch_tmat<double>(ctx, st, *P, sys, polarity, thole, ewald_beta,
+                                               cutoff, include_diag, mu, out)
+                         : launch_tmat<float>(ctx, st, *P, sys, polarity, thole, ewald_beta,
+                                              cutoff, include_diag, mu, out);
+}
+
+tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                  int form, const double* radius_or_sigma, const double* eps, double cutoff,
+                  double taper_on_frac, double hal_delta, double hal_gamma, int prec,
+                  double* energy, double* force, double* virial) {
+  const Plan* P;
+  tk_status s = common_args(ctx, sys, list, cutoff, prec, &P);
+  if (s) return s;
+  if (form != TK_VDW_HAL && form != TK_VDW_LJ) return TK_E_ARG;
+  if (!(taper_on_frac >= 0.0 && taper_on_frac <= 1.0) || !std::isfinite(hal_delta) ||
+      !std::isfinite(hal_gamma) || !energy || !virial)
+    return TK_E_ARG;
+  if (sys->n > 0 && (!radius_or_sigma || !eps || !force)) return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  void* sums;
+  if ((s = scratch(ctx, "sums", sizeof(double) * 32, &sums))) return s;
+  if (sys->n == 0) {
+    TK_HIP(hipMemsetAsync(energy, 0, sizeof(double), st));
+    TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
+    return TK_OK;
+  }
+  if (prec == TK_FP64) {
+    VdwPh<double> ph;
+    ph.set(sys, form, radius_or_sigma, eps, cutoff, taper_on_frac, hal_delta, hal_gamma);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+  } else {
+    VdwPh<float> ph;
+    ph.set(sys, form, radius_or_sigma, eps, cutoff, taper_on_frac, hal_delta, hal_gamma);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+  }
+  if (s) return s;
+  k_finish_energy1<<<1, 1, 0, st>>>((double*)sums, energy, virial);
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+}  // extern "C"

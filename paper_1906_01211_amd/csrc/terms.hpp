@@ -1,0 +1,542 @@
+// Pair physics for the tile skeleton (pairs.hpp).  Each functor stages the
+// per-atom fields it needs (field-major in LDS) and evaluates one listed pair,
+// adding both atoms' contributions to the LDS accumulators.
+//
+// R is the pair-arithmetic type: double (TK_FP64) or float (TK_MIXED).  With
+// float the pair vector is formed in FP64 from the FP64 coordinates, the
+// cutoff test stays in FP64 (identical pair decisions in both precisions),
+// radial functions of same-molecule pairs are evaluated in FP64 (their
+// screened-minus-bare differences cancel badly), and every accumulation
+// (LDS atomics, energies, virial) is FP64.
+#pragma once
+
+#include <type_traits>
+
+#include "pairs.hpp"
+
+namespace tk {
+
+template <class R> __device__ __forceinline__ R t_exp(R x);
+template <> __device__ __forceinline__ double t_exp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ float t_exp<float>(float x) { return __expf(x); }
+template <class R> __device__ __forceinline__ R t_erfc(R x);
+template <> __device__ __forceinline__ double t_erfc<double>(double x) { return erfc(x); }
+template <> __device__ __forceinline__ float t_erfc<float>(float x) { return erfcf(x); }
+template <class R> __device__ __forceinline__ R t_sqrt(R x);
+template <> __device__ __forceinline__ double t_sqrt<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float t_sqrt<float>(float x) { return sqrtf(x); }
+
+// Geometry and Ewald constants shared by the electrostatic terms.
+struct Geom {
+  double box, inv_box, rc2, beta, beta2, bsp_inv, cself;
+  int bare;   // beta == 0: no screening, B_n = R_n
+  void set(double b, double rc, double be) {
+    box = b;
+    inv_box = 1.0 / b;
+    rc2 = rc * rc;
+    beta = be;
+    beta2 = be * be;
+    bare = be == 0.0;
+    bsp_inv = bare ? 0.0 : 1.0 / (be * kSqrtPi);
+    cself = 4.0 * be * be * be / (3.0 * kSqrtPi);
+  }
+};
+
+// B_0..B_N (Ewald-screened) and, if wanted, R_0..R_N (bare) at distance r.
+//   B0 = erfc(beta r)/r,  Bn = [(2n-1) B(n-1) + (2 beta^2)^n exp(-beta^2 r^2)/(beta sqrt(pi))]/r^2
+template <class R, int N>
+__device__ __forceinline__ void radial(const Geom& g, R r, R rinv, R* B, R* Rb) {
+  const R rinv2 = rinv * rinv;
+  Rb[0] = rinv;
+#pragma unroll
+  for (int n = 1; n <= N; ++n) Rb[n] = R(2 * n - 1) * Rb[n - 1] * rinv2;
+  if (g.bare) {
+#pragma unroll
+    for (int n = 0; n <= N; ++n) B[n] = Rb[n];
+    return;
+  }
+  const R beta = R(g.beta), b2 = R(2.0 * g.beta2);
+  const R ex = t_exp<R>(-R(g.beta2) * r * r) * R(g.bsp_inv);
+  B[0] = t_erfc<R>(beta * r) * rinv;
+  R pw = b2;
+#pragma unroll
+  for (int n = 1; n <= N; ++n) {
+    B[n] = (R(2 * n - 1) * B[n - 1] + pw * ex) * rinv2;
+    pw *= b2;
+  }
+}
+
+// g_n = B_n - w_n R_n; for R = float and same-molecule pairs the radial
+// functions come from FP64.
+template <class R, int N>
+__device__ __forceinline__ void radial_pair(const Geom& g, double r2, bool same_mol, R* B, R* Rb) {
+  if (std::is_same<R, float>::value && same_mol) {
+    double r = sqrt(r2), ri = 1.0 / r, Bd[N + 1], Rd[N + 1];
+    radial<double, N>(g, r, ri, Bd, Rd);
+#pragma unroll
+    for (int n = 0; n <= N; ++n) {
+      B[n] = R(Bd[n] - Rd[n]);   // the FP64 difference, carried in B; Rb zero
+      Rb[n] = R(0);
+    }
+    return;
+  }
+  R r = t_sqrt<R>(R(r2));
+  R rinv = R(1) / r;
+  radial<R, N>(g, r, rinv, B, Rb);
+}
+
+// Thole factors l3, l5, l7 with x = a_ij r^3 isa_i isa_j, isa = 1/sqrt(alpha)
+// (0 when alpha = 0, which makes every factor 1).
+template <class R>
+__device__ __forceinline__ void thole_damp(R r, R isa_i, R isa_j, R ti, R tj, R& l3, R& l5, R& l7) {
+  const R pr = isa_i * isa_j;
+  if (pr == R(0)) {
+    l3 = l5 = l7 = R(1);
+    return;
+  }
+  const R a = ti < tj ? ti : tj;
+  const R x = a * r * r * r * pr;
+  const R e = t_exp<R>(-x);
+  l3 = R(1) - e;
+  l5 = R(1) - (R(1) + x) * e;
+  l7 = R(1) - (R(1) + x + R(0.6) * x * x) * e;
+}
+
+__device__ __forceinline__ double inv_sqrt_alpha(double a) { return a > 0.0 ? 1.0 / sqrt(a) : 0.0; }
+
+// --------------------------------------------------------------------------
+// Permanent multipoles: energy, forces, virial.
+// Fields: x y z | q mux muy muz Txx Txy Txz Tyy Tyz Tzz | molid
+template <class R>
+struct EmpolePh {
+  static constexpr int NF = 14, NA = 3, NS = 11;
+  __device__ bool skip() const { return false; }
+  const double* xyz;
+  const double* mpole;
+  const int32_t* molid;
+  Geom g;
+  __device__ void stage(double* L, int cap, int t, int s, const int32_t* perm) const {
+    const int i = perm[s];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) L[c * cap + t] = xyz[3 * i + c];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) L[(3 + k) * cap + t] = mpole[10 * i + k];
+    L[13 * cap + t] = (double)molid[i];
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double* sc) const {
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
+    if (!(r2 <= g.rc2)) return;
+    const bool excl = LH[13 * cap + a] == LK[13 * cap + b];
+    R B[6], Rb[6];
+    radial_pair<R, 5>(g, r2, excl, B, Rb);
+    R gg[6];
+#pragma unroll
+    for (int n = 0; n < 6; ++n) gg[n] = excl ? B[n] - Rb[n] : B[n];
+    const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
+    const R qi = R(LH[3 * cap + a]), qj = R(LK[3 * cap + b]);
+    const R ui[3] = {R(LH[4 * cap + a]), R(LH[5 * cap + a]), R(LH[6 * cap + a])};
+    const R uj[3] = {R(LK[4 * cap + b]), R(LK[5 * cap + b]), R(LK[6 * cap + b])};
+    // Theta as 6 unique components xx xy xz yy yz zz
+    const R ti[6] = {R(LH[7 * cap + a]), R(LH[8 * cap + a]), R(LH[9 * cap + a]),
+                     R(LH[10 * cap + a]), R(LH[11 * cap + a]), R(LH[12 * cap + a])};
+    const R tj[6] = {R(LK[7 * cap + b]), R(LK[8 * cap + b]), R(LK[9 * cap + b]),
+                     R(LK[10 * cap + b]), R(LK[11 * cap + b]), R(LK[12 * cap + b])};
+    auto tmul = [](const R* t, const R* x, R* y) {
+      y[0] = t[0] * x[0] + t[1] * x[1] + t[2] * x[2];
+      y[1] = t[1] * x[0] + t[3] * x[1] + t[4] * x[2];
+      y[2] = t[2] * x[0] + t[4] * x[1] + t[5] * x[2];
+    };
+    auto dot = [](const R* x, const R* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+    R vi[3], vj[3];
+    tmul(ti, d, vi);
+    tmul(tj, d, vj);
+    const R di = dot(ui, d), dj = dot(uj, d), Qi = dot(d, vi), Qj = dot(d, vj);
+    const R tt = ti[0] * tj[0] + ti[3] * tj[3] + ti[5] * tj[5] +
+                 R(2) * (ti[1] * tj[1] + ti[2] * tj[2] + ti[4] * tj[4]);
+    const R c0 = qi * qj;
+    const R c1 = qj * di - qi * dj + dot(ui, uj);
+    const R c2 = qi * Qj + qj * Qi - di * dj + R(2) * (dot(uj, vi) - dot(ui, vj) + tt);
+    const R c3 = di * Qj - dj * Qi - R(4) * dot(vi, vj);
+    const R c4 = Qi * Qj;
+    R tiuj[3], tjui[3], tivj[3], tjvi[3];
+    tmul(ti, uj, tiuj);
+    tmul(tj, ui, tjui);
+    tmul(ti, vj, tivj);
+    tmul(tj, vi, tjvi);
+    const R e = c0 * gg[0] + c1 * gg[1] + c2 * gg[2] + c3 * gg[3] + c4 * gg[4];
+    const R sr = c0 * gg[1] + c1 * gg[2] + c2 * gg[3] + c3 * gg[4] + c4 * gg[5];
+    double de[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const R dc1 = qj * ui[c] - qi * uj[c];
+      const R dc2 = R(2) * (qi * vj[c] + qj * vi[c]) - dj * ui[c] - di * uj[c] +
+                    R(2) * (tiuj[c] - tjui[c]);
+      const R dc3 = Qj * ui[c] + R(2) * di * vj[c] - Qi * uj[c] - R(2) * dj * vi[c] -
+                    R(4) * (tivj[c] + tjvi[c]);
+      const R dc4 = R(2) * (Qj * vi[c] + Qi * vj[c]);
+      de[c] = kCoulomb * (double)(dc1 * gg[1] + dc2 * gg[2] + dc3 * gg[3] + dc4 * gg[4] - sr * d[c]);
+    }
+    const double en = kCoulomb * (double)e;
+    sc[excl ? 1 : 0] += en;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lds_add(&AH[c * cap + a], de[c]);
+      lds_add(&AK[c * cap + b], -de[c]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) sc[2 + 3 * c + q] += dd[c] * de[q];
+    }
+  }
+};
+
+// Point charges: e = C qi qj g0, de/dr = -C qi qj g1 r.
+// Fields: x y z | q | molid
+template <class R>
+struct ChargePh {
+  static constexpr int NF = 5, NA = 3, NS = 11;
+  __device__ bool skip() const { return false; }
+  const double* xyz;
+  const double* q;
+  const int32_t* molid;
+  Geom g;
+  __device__ void stage(double* L, int cap, int t, int s, const int32_t* perm) const {
+    const int i = perm[s];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) L[c * cap + t] = xyz[3 * i + c];
+    L[3 * cap + t] = q[i];
+    L[4 * cap + t] = (double)molid[i];
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double* sc) const {
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
+    if (!(r2 <= g.rc2)) return;
+    const bool excl = LH[4 * cap + a] == LK[4 * cap + b];
+    R B[2], Rb[2];
+    radial_pair<R, 1>(g, r2, excl, B, Rb);
+    const R g0 = excl ? B[0] - Rb[0] : B[0];
+    const R g1 = excl ? B[1] - Rb[1] : B[1];
+    const double qq = kCoulomb * LH[3 * cap + a] * LK[3 * cap + b];
+    const double en = qq * (double)g0;
+    const double f = -qq * (double)g1;
+    sc[excl ? 1 : 0] += en;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double de = f * dd[c];
+      lds_add(&AH[c * cap + a], de);
+      lds_add(&AK[c * cap + b], -de);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sc[2 + 3 * c + k] += dd[c] * f * dd[k];
+    }
+  }
+};
+
+// Permanent field (right-hand side of the polarization equations).
+// Fields: x y z | q mu(3) Theta(6) | molid | isa | thole
+template <class R>
+struct EfieldPh {
+  static constexpr int NF = 16, NA = 3, NS = 0;
+  __device__ bool skip() const { return false; }
+  const double* xyz;
+  const double* mpole;
+  const int32_t* molid;
+  const double* polarity;
+  const double* thole;
+  Geom g;
+  __device__ void stage(double* L, int cap, int t, int s, const int32_t* perm) const {
+    const int i = perm[s];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) L[c * cap + t] = xyz[3 * i + c];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) L[(3 + k) * cap + t] = mpole[10 * i + k];
+    L[13 * cap + t] = (double)molid[i];
+    L[14 * cap + t] = inv_sqrt_alpha(polarity[i]);
+    L[15 * cap + t] = thole[i];
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double*) const {
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
+    if (!(r2 <= g.rc2)) return;
+    const bool excl = LH[13 * cap + a] == LK[13 * cap + b];
+    R B[4], Rb[4];
+    radial_pair<R, 3>(g, r2, excl, B, Rb);
+    R g1, g2, g3;
+    if (excl) {
+      g1 = B[1] - Rb[1];
+      g2 = B[2] - Rb[2];
+      g3 = B[3] - Rb[3];
+    } else {
+      R l3, l5, l7;
+      const R r = t_sqrt<R>(R(r2));
+      thole_damp<R>(r, R(LH[14 * cap + a]), R(LK[14 * cap + b]), R(LH[15 * cap + a]),
+               R(LK[15 * cap + b]), l3, l5, l7);
+      g1 = B[1] - (R(1) - l3) * Rb[1];
+      g2 = B[2] - (R(1) - l5) * Rb[2];
+      g3 = B[3] - (R(1) - l7) * Rb[3];
+    }
+    const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
+    const R qi = R(LH[3 * cap + a]), qj = R(LK[3 * cap + b]);
+    const R ui[3] = {R(LH[4 * cap + a]), R(LH[5 * cap + a]), R(LH[6 * cap + a])};
+    const R uj[3] = {R(LK[4 * cap + b]), R(LK[5 * cap + b]), R(LK[6 * cap + b])};
+    const R ti[6] = {R(LH[7 * cap + a]), R(LH[8 * cap + a]), R(LH[9 * cap + a]),
+                     R(LH[10 * cap + a]), R(LH[11 * cap + a]), R(LH[12 * cap + a])};
+    const R tj[6] = {R(LK[7 * cap + b]), R(LK[8 * cap + b]), R(LK[9 * cap + b]),
+                     R(LK[10 * cap + b]), R(LK[11 * cap + b]), R(LK[12 * cap + b])};
+    R vi[3], vj[3];
+    vi[0] = ti[0] * d[0] + ti[1] * d[1] + ti[2] * d[2];
+    vi[1] = ti[1] * d[0] + ti[3] * d[1] + ti[4] * d[2];
+    vi[2] = ti[2] * d[0] + ti[4] * d[1] + ti[5] * d[2];
+    vj[0] = tj[0] * d[0] + tj[1] * d[1] + tj[2] * d[2];
+    vj[1] = tj[1] * d[0] + tj[3] * d[1] + tj[4] * d[2];
+    vj[2] = tj[2] * d[0] + tj[4] * d[1] + tj[5] * d[2];
+    const R di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
+    const R dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
+    const R Qi = d[0] * vi[0] + d[1] * vi[1] + d[2] * vi[2];
+    const R Qj = d[0] * vj[0] + d[1] * vj[1] + d[2] * vj[2];
+    // field at i from j: d(-qj g1 + dj g2 - Qj g3) - uj g1 + 2 vj g2
+    // field at j from i: d( qi g1 + di g2 + Qi g3) - ui g1 - 2 vi g2
+    const R si = -qj * g1 + dj * g2 - Qj * g3;
+    const R sj = qi * g1 + di * g2 + Qi * g3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lds_add(&AH[c * cap + a], (double)(d[c] * si - uj[c] * g1 + R(2) * vj[c] * g2));
+      lds_add(&AK[c * cap + b], (double)(d[c] * sj - ui[c] * g1 - R(2) * vi[c] * g2));
+    }
+  }
+};
+
+// Mutual induced-dipole field: E_i += T2 mu_j, E_j += T2 mu_i (all pairs).
+// Fields: x y z | mu(3) | isa | thole | molid
+template <class R>
+struct TmatPh {
+  static constexpr int NF = 9, NA = 3, NS = 0;
+  const int* done = nullptr;   // solver flag: skip when set
+  __device__ bool skip() const { return done && *done; }
+  const double* xyz;
+  const double* mu;
+  int mu_sorted;   // mu indexed by sorted position (solver-internal vectors)
+  const double* polarity;
+  const double* thole;
+  const int32_t* molid;
+  Geom g;
+  __device__ void stage(double* L, int cap, int t, int s, const int32_t* perm) const {
+    const int i = perm[s];
+    const int m = mu_sorted ? s : i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      L[c * cap + t] = xyz[3 * i + c];
+      L[(3 + c) * cap + t] = mu[3 * m + c];
+    }
+    L[6 * cap + t] = inv_sqrt_alpha(polarity[i]);
+    L[7 * cap + t] = thole[i];
+    L[8 * cap + t] = molid ? (double)molid[i] : (double)i;
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double*) const {
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
+    if (!(r2 <= g.rc2)) return;
+    const bool same = LH[8 * cap + a] == LK[8 * cap + b];
+    R B[3], Rb[3];
+    radial_pair<R, 2>(g, r2, same, B, Rb);
+    R l3, l5, l7;
+    const R r = t_sqrt<R>(R(r2));
+    thole_damp<R>(r, R(LH[6 * cap + a]), R(LK[6 * cap + b]), R(LH[7 * cap + a]), R(LK[7 * cap + b]),
+             l3, l5, l7);
+    // g1 = B1 - (1 - l3) R1, g2 = B2 - (1 - l5) R2 (for FP32 same-molecule pairs
+    // B carries the FP64 difference B - R and the bare part is re-added with l)
+    R g1, g2;
+    if (std::is_same<R, float>::value && same) {
+      const double rd = sqrt(r2), ri = 1.0 / rd;
+      const double R1 = ri * ri * ri, R2 = 3.0 * R1 * ri * ri;
+      g1 = R((double)B[1] + (double)l3 * R1);
+      g2 = R((double)B[2] + (double)l5 * R2);
+    } else {
+      g1 = B[1] - (R(1) - l3) * Rb[1];
+      g2 = B[2] - (R(1) - l5) * Rb[2];
+    }
+    const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
+    const R ui[3] = {R(LH[3 * cap + a]), R(LH[4 * cap + a]), R(LH[5 * cap + a])};
+    const R uj[3] = {R(LK[3 * cap + b]), R(LK[4 * cap + b]), R(LK[5 * cap + b])};
+    const R di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
+    const R dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
+    const R si = dj * g2, sj = di * g2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lds_add(&AH[c * cap + a], (double)(d[c] * si - uj[c] * g1));
+      lds_add(&AK[c * cap + b], (double)(d[c] * sj - ui[c] * g1));
+    }
+  }
+};
+
+// Halgren 14-7 / LJ 12-6 with the quintic taper.
+// Fields: x y z | radius (HAL R or LJ sigma) | sqrt(eps) | molid
+template <class R>
+struct VdwPh {
+  static constexpr int NF = 6, NA = 3, NS = 10;
+  __device__ bool skip() const { return false; }
+  const double* xyz;
+  const double* rad;
+  const double* eps;
+  const int32_t* molid;
+  int form;
+  double box, inv_box, rc2, ron, rc, tw_inv, dhal, ghal;
+  void set(const tk_system* sys, int f, const double* r_, const double* e_, double cutoff,
+           double taper, double d, double gm) {
+    xyz = sys->xyz;
+    rad = r_;
+    eps = e_;
+    molid = sys->molid;
+    form = f;
+    box = sys->box;
+    inv_box = 1.0 / sys->box;
+    rc = cutoff;
+    rc2 = cutoff * cutoff;
+    ron = taper * cutoff;
+    tw_inv = cutoff > ron ? 1.0 / (cutoff - ron) : 0.0;
+    dhal = d;
+    ghal = gm;
+  }
+  __device__ void stage(double* L, int cap, int t, int s, const int32_t* perm) const {
+    const int i = perm[s];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) L[c * cap + t] = xyz[3 * i + c];
+    L[3 * cap + t] = rad[i];
+    L[4 * cap + t] = sqrt(eps[i]);
+    L[5 * cap + t] = (double)molid[i];
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double* sc) const {
+    if (LH[5 * cap + a] == LK[5 * cap + b]) return;
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, box, inv_box, dd);
+    if (!(r2 <= rc2)) return;
+    const R r = t_sqrt<R>(R(r2));
+    const R ri = R(LH[3 * cap + a]), rj = R(LK[3 * cap + b]);
+    const R si = R(LH[4 * cap + a]), sj = R(LK[4 * cap + b]);
+    R e, dedr;
+    if (form == TK_VDW_HAL) {
+      const R ri2 = ri * ri, rj2 = rj * rj;
+      const R rv = (ri2 * ri + rj2 * rj) / (ri2 + rj2);
+      const R se = si + sj;
+      const R ep = se > R(0) ? R(4) * (si * si) * (sj * sj) / (se * se) : R(0);
+      const R rv2 = rv * rv, rv7 = rv2 * rv2 * rv2 * rv;
+      const R r6 = R(r2) * R(r2) * R(r2), rik7 = r6 * r;
+      const R invrho = R(1) / (rik7 + R(ghal) * rv7);
+      const R invtmp = R(1) / (r + R(dhal) * rv);
+      const R tb = R(1.0 + dhal) * rv * invtmp;
+      const R tb2 = tb * tb, t7 = tb2 * tb2 * tb2 * tb;
+      const R w = R(1.0 + ghal) * rv7 * invrho;
+      e = ep * t7 * (w - R(2));
+      dedr = ep * (R(-7) * t7 * invtmp * (w - R(2)) - R(7) * t7 * r6 * w * invrho);
+    } else {
+      const R sg = R(0.5) * (ri + rj);
+      const R ep = si * sj;
+      const R q = sg * sg / R(r2);
+      const R sr6 = q * q * q;
+      e = R(4) * ep * (sr6 * sr6 - sr6);
+      dedr = R(4) * ep * (R(-12) * sr6 * sr6 + R(6) * sr6) / r;
+    }
+    if ((double)r > ron) {
+      const R x = (r - R(ron)) * R(tw_inv);
+      const R x2 = x * x, x3 = x2 * x;
+      const R S = R(1) - R(10) * x3 + R(15) * x3 * x - R(6) * x3 * x2;
+      const R dS = (R(-30) * x2 + R(60) * x3 - R(30) * x3 * x) * R(tw_inv);
+      dedr = dedr * S + e * dS;
+      e *= S;
+    }
+    const double f = (double)dedr / (double)r;
+    sc[0] += (double)e;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double de = f * dd[c];
+      lds_add(&AH[c * cap + a], de);
+      lds_add(&AK[c * cap + b], -de);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sc[1 + 3 * c + k] += dd[c] * f * dd[k];
+    }
+  }
+};
+
+// Epilogues of the per-atom reduction.
+struct EpiForce {   // the sums are the atom's force; caller order
+  double* force;
+  __device__ void operator()(int, int i, const double* a) const {
+    force[3 * i] = a[0];
+    force[3 * i + 1] = a[1];
+    force[3 * i + 2] = a[2];
+  }
+};
+
+struct EpiPermField {   // permanent field + Ewald self field c * mu_perm
+  double* out;
+  const double* mpole;
+  double cself;
+  int sorted_out;
+  __device__ void operator()(int s, int i, const double* a) const {
+    const int o = sorted_out ? s : i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[3 * o + c] = a[c] + cself * mpole[10 * i + 1 + c];
+  }
+};
+
+struct EpiMutual {   // mutual field (T + cI) mu, or A mu = mu/alpha - field
+  double* out;
+  const double* mu;
+  const double* alpha;
+  double cself;
+  int include_diag;
+  __device__ void operator()(int, int i, const double* a) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double m = mu[3 * i + c];
+      double f = a[c] + cself * m;
+      if (include_diag) {
+        const double al = alpha[i];
+        f = al > 0.0 ? m / al - f : 0.0;
+      }
+      out[3 * i + c] = f;
+    }
+  }
+};
+
+// Launch one pair term over a plan: units -> per-atom reduce (Epi) -> scalars.
+template <class Ph, class Epi>
+tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, const Epi& epi,
+                   double* sums_out) {
+  const long pstride = pad64(P.n);
+  void *partial, *uscal;
+  tk_status s;
+  if ((s = scratch(ctx, "partial", sizeof(double) * kMaxSlots * Ph::NA * pstride, &partial)) ||
+      (s = scratch(ctx, "uscal", sizeof(double) * (size_t)P.nunits * (Ph::NS > 0 ? Ph::NS : 1),
+                   &uscal)))
+    return s;
+  PlanView pv = P.view();
+  const size_t lds = unit_lds_bytes<Ph>(P);
+  if (lds > kMaxLds) return TK_E_CAPACITY;
+  k_units<Ph><<<P.nunits, 64, lds, st>>>(pv, ph, (double*)partial, pstride, (double*)uscal);
+  k_reduce<Ph::NA, Epi><<<ceil_div(P.n, 256), 256, 0, st>>>(pv, (double*)partial, pstride, epi);
+  if (Ph::NS > 0 && sums_out)
+    k_sum_units<(Ph::NS > 0 ? Ph::NS : 1)><<<1, 256, 0, st>>>((double*)uscal, P.nunits, sums_out);
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+template <class R>
+inline tk_status launch_efield(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_system* sys,
+                        const double* mpole, const double* polarity, const double* thole,
+                        double beta, double cutoff, double* out, int sorted_out) {
+  EfieldPh<R> ph;
+  ph.xyz = sys->xyz;
+  ph.mpole = mpole;
+  ph.molid = sys->molid;
+  ph.polarity = polarity;
+  ph.thole = thole;
+  ph.g.set(sys->box, cutoff, beta);
+  EpiPermField e2{out, mpole, ph.g.cself, sorted_out};
+  return run_term(ctx, st, P, ph, e2, nullptr);
+}
+
+}  // namespace tk

@@ -1,0 +1,118 @@
+// Internal declarations of libtk: context, plan slots, device-buffer arena,
+// launch helpers.  Host and device code include this header; it is not part of
+// the C-ABI (include/tk.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "tk.h"
+
+namespace tk {
+
+// Readings where the paper is silent (Coulomb constant, Debye factor).
+constexpr double kCoulomb = 332.0637;
+constexpr double kDebye = 4.80320;
+constexpr double kSqrtPi = 1.7724538509055160273;
+constexpr double kTwo32 = 4294967296.0;
+
+// Cell-pair work decomposition.  Cells are at least one list cutoff wide, so
+// every listed pair joins a cell to one of its (at most 27) neighbours.  A
+// work unit is an unordered neighbouring cell pair (H, K), H <= K; each cell
+// takes part in at most 28 unit roles (27 neighbours, the self pair twice),
+// and each role owns one partial-result slot for the cell's atoms.
+constexpr int kMaxSlots = 28;
+constexpr int kMaxCellAtoms = 512;   // LDS staging limit per cell
+constexpr int kWave = 64;
+constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
+
+struct Unit {
+  int32_t h, k, slot_h, slot_k;
+};
+
+// Device views of a plan (the pair set of one neighbour list, in cell-pair
+// order).  Sorted position s = rank of an atom by (cell, caller index).
+struct PlanView {
+  int32_t n, ncells, nunits, max_occ;
+  const int32_t* perm;        // [n] sorted position -> caller index
+  const int32_t* scell;       // [n] cell of sorted position
+  const int32_t* cell_start;  // [ncells+1]
+  const int32_t* cell_nslot;  // [ncells] number of unit roles of the cell
+  const Unit* units;          // [nunits]
+  const int32_t* unit_ptr;    // [nunits+1] offsets into codes
+  const uint32_t* codes;      // pair codes: a | b << 16 (local indices in H, K)
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Plan {
+  bool valid = false;
+  int32_t n = 0;
+  double box = 0.0, cutoff = 0.0;
+  int32_t nc = 0, ncells = 0, nunits = 0, max_occ = 0, max_row = 0;
+  int64_t npairs = 0;
+  DevBuf perm, scell, cell_start, cell_nslot, units, unit_ptr, codes, us, nbr;
+  PlanView view() const {
+    PlanView v;
+    v.n = n; v.ncells = ncells; v.nunits = nunits; v.max_occ = max_occ;
+    v.perm = (const int32_t*)perm.p; v.scell = (const int32_t*)scell.p;
+    v.cell_start = (const int32_t*)cell_start.p; v.cell_nslot = (const int32_t*)cell_nslot.p;
+    v.units = (const Unit*)units.p; v.unit_ptr = (const int32_t*)unit_ptr.p;
+    v.codes = (const uint32_t*)codes.p;
+    return v;
+  }
+};
+
+struct CellTables {   // host-built tables for one cells-per-edge value
+  int32_t nc = 0, ncells = 0, nunits = 0;
+  std::vector<Unit> units;
+  std::vector<int32_t> nslot;     // per cell
+  std::vector<int32_t> nbr;       // per cell: count, then up to 27 neighbour cells
+};
+
+}  // namespace tk
+
+struct tk_ctx {
+  int device = 0;
+  tk::Plan plans[TK_MAX_PLANS];
+  std::map<std::string, tk::DevBuf> scratch;   // grow-only named device buffers
+  std::map<int, tk::CellTables> tables;        // by cells per edge
+  void* pinned = nullptr;                      // host readback buffer
+  size_t pinned_bytes = 0;
+};
+
+namespace tk {
+
+tk_status hip_status(hipError_t e, const char* what);
+#define TK_HIP(call)                                     \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return tk::hip_status(e_, #call); \
+  } while (0)
+
+// Grow-only buffers: the first call with a given size allocates, later calls
+// reuse.  Never freed before tk_destroy.
+tk_status ensure(DevBuf& b, size_t bytes);
+tk_status scratch(tk_ctx* ctx, const char* name, size_t bytes, void** out);
+tk_status pinned(tk_ctx* ctx, size_t bytes, void** out);
+const CellTables& cell_tables(tk_ctx* ctx, int nc);
+
+// Exclusive scan of int32 counts: out[0..len] with out[len] = total.
+tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len);
+
+// Checks shared by the pair entry points.
+tk_status check_system(const tk_system* sys);
+tk_status get_plan(tk_ctx* ctx, const tk_system* sys, const tk_nblist* list, double cutoff,
+                   const Plan** out);
+
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace tk

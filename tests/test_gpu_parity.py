@@ -1,0 +1,226 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Tolerances (FP64 path): neighbour lists bit-exact; each energy component
+relative 1e-10; forces and fields max |diff| <= 1e-8 * RMS of the oracle's;
+solver iterates at a fixed iteration count relative 1e-10.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_01211_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+C, DEBYE = O.constants()
+S = synth.AMOEBA_SETTINGS
+
+
+@pytest.fixture(scope="module")
+def tk():
+    import torch
+    from paper_1906_01211_amd import tk as _tk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _tk.load()
+    return _tk
+
+
+@pytest.fixture(scope="module")
+def ctx(tk):
+    c = tk.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def fmax_rel(got, ref):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    return np.abs(got - ref).max() / np.sqrt(np.mean(ref ** 2))
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def assert_list_equal(lst, row_ptr, col):
+    assert lst.npairs == len(col)
+    assert np.array_equal(np_(lst.row_ptr), row_ptr)
+    assert np.array_equal(np_(lst.col), col)
+
+
+_cache = {}
+
+
+def water(name):
+    if name not in _cache:
+        _cache[name] = synth.make(name)
+    return _cache[name]
+
+
+def oracle_list(w, rc):
+    key = ("list", w.params.get("name", id(w)), w.n, rc)
+    if key not in _cache:
+        _cache[key] = O.nblist(w.xyz, w.box, rc)
+    return _cache[key]
+
+
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name,rc", [("water216", 7.001), ("water216", 9.001),
+                                     ("water7853", 7.001), ("water7853", 9.001)])
+def test_nblist_bit_exact(ctx, name, rc):
+    w = water(name)
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, rc, plan_slot=0)
+    rp, cp = oracle_list(w, rc)
+    assert_list_equal(lst, rp, cp)
+
+
+@pytest.mark.parametrize("n,box,rc,seed", [(1, 10.0, 3.0, 0), (2, 10.0, 5.0, 1), (37, 7.0, 3.4, 2),
+                                           (300, 12.0, 3.0, 3), (500, 20.0, 9.9, 4),
+                                           (1000, 17.0, 2.0, 5)])
+def test_nblist_random_boxes(ctx, n, box, rc, seed):
+    rng = np.random.default_rng(seed)
+    xyz = rng.uniform(-box, 2 * box, size=(n, 3))
+    sysr = ctx.system(xyz, box, np.arange(n) // 3)
+    lst = ctx.nblist(sysr, rc, plan_slot=1)
+    rp, cp = O.nblist(xyz, box, rc)
+    assert_list_equal(lst, rp, cp)
+
+
+def test_nblist_errors(ctx, tk):
+    xyz = np.random.default_rng(0).uniform(0, 10, size=(20, 3))
+    sysr = ctx.system(xyz, 10.0, np.arange(20))
+    with pytest.raises(tk.TkError) as e:
+        ctx.nblist(sysr, 5.5)
+    assert e.value.status == tk.E_CUTOFF
+    bad = xyz.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(tk.TkError) as e:
+        ctx.nblist(ctx.system(bad, 10.0, np.arange(20)), 4.0)
+    assert e.value.status == tk.E_ARG
+    # too small a capacity reports the required size (binding then retries)
+    lst = ctx.nblist(sysr, 4.0, cap=3)
+    rp, cp = O.nblist(xyz, 10.0, 4.0)
+    assert_list_equal(lst, rp, cp)
+
+
+# ----------------------------------------------------------------------------
+def setup_amoeba(ctx, name, rc_list, slot):
+    w = water(name)
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, rc_list, plan_slot=slot)
+    rp, cp = oracle_list(w, rc_list)
+    return w, sysr, lst, rp, cp
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+def test_empole_fp64(ctx, name):
+    w, sysr, lst, rp, cp = setup_amoeba(ctx, name, 7.001, 2)
+    e, f, vir = ctx.empole_real(sysr, lst, w.mpole, S["beta"], 7.0)
+    eo, fo, vo = O.empole_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, S["beta"], 7.0)
+    e = np_(e)
+    for k in range(3):
+        assert rel(e[k], eo[k]) < 1e-10, (k, e[k], eo[k])
+    assert fmax_rel(np_(f), fo) < 1e-8
+    assert np.abs(np_(vir) - vo).max() < 1e-10 * np.abs(vo).max()
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+def test_efield_and_tmatvec_fp64(ctx, name):
+    w, sysr, lst, rp, cp = setup_amoeba(ctx, name, 7.001, 2)
+    fld = ctx.efield_direct(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0)
+    fo = O.efield_direct(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, S["beta"],
+                         7.0)
+    assert fmax_rel(np_(fld), fo) < 1e-8
+    mu = np.random.default_rng(7).normal(0, 0.05, size=(w.n, 3))
+    for diag in (0, 1):
+        out = ctx.tmatvec(sysr, lst, w.polarity, w.thole, S["beta"], 7.0, mu, include_diag=diag)
+        oo = O.tmatvec(w.xyz, w.box, rp, cp, w.polarity, w.thole, S["beta"], 7.0, mu, diag)
+        assert fmax_rel(np_(out), oo) < 1e-8
+
+
+@pytest.mark.parametrize("k", [0, 1, 3, 6])
+def test_pcg_iterates_fp64(ctx, k):
+    w, sysr, lst, rp, cp = setup_amoeba(ctx, "water216", 7.001, 2)
+    mu, info = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
+                                tol_debye=0.0, maxiter=k)
+    mo, io = O.polarize_pcg(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                            S["beta"], 7.0, tol_debye=0.0, maxiter=k)
+    assert info["iters"] == io["iters"] == k
+    assert info["status"] == io["status"]
+    assert np.abs(np_(mu) - mo).max() <= 1e-10 * np.abs(mo).max()
+    assert rel(info["rms_debye"], io["rms_debye"]) < 1e-8
+    assert rel(info["epol"], io["epol"]) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+def test_pcg_converged_fp64(ctx, name):
+    w, sysr, lst, rp, cp = setup_amoeba(ctx, name, 7.001, 2)
+    mu, info = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
+                                tol_debye=S["tol_debye"])
+    mo, io = O.polarize_pcg(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                            S["beta"], 7.0, tol_debye=S["tol_debye"])
+    assert info["converged"] == io["converged"] == 1
+    assert info["iters"] == io["iters"]
+    assert np.abs(np_(mu) - mo).max() <= 1e-10 * np.abs(mo).max()
+    assert rel(info["epol"], io["epol"]) < 1e-10
+    assert rel(info["rms_true_debye"], io["rms_true_debye"]) < 1e-6
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+@pytest.mark.parametrize("form", [0, 1])
+def test_evdw_fp64(ctx, name, form):
+    w, sysr, lst, rp, cp = setup_amoeba(ctx, name, 9.001, 3)
+    rad = w.vdw_rad if form == 0 else np.where(np.arange(w.n) % 3 == 0, 3.15, 1.2)
+    e, f, vir = ctx.evdw(sysr, lst, form, rad, w.vdw_eps, 9.0)
+    eo, fo, vo = O.evdw(w.xyz, w.box, w.molid, rp, cp, form, rad, w.vdw_eps, 9.0)
+    assert rel(float(e), eo) < 1e-10
+    assert fmax_rel(np_(f), fo) < 1e-8
+    assert np.abs(np_(vir) - vo).max() < 1e-10 * np.abs(vo).max()
+
+
+def test_echarge_fp64_small(ctx):
+    w = synth.charge_lj_water_box(1000, 31.0, 77)
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, 12.001, plan_slot=4)
+    rp, cp = O.nblist(w.xyz, w.box, 12.001)
+    assert_list_equal(lst, rp, cp)
+    e, f, vir = ctx.echarge_real(sysr, lst, w.charges, 0.34, 12.0)
+    eo, fo, vo = O.echarge_real(w.xyz, w.box, w.molid, rp, cp, w.charges, 0.34, 12.0)
+    for k in range(3):
+        assert rel(np_(e)[k], eo[k]) < 1e-10
+    assert fmax_rel(np_(f), fo) < 1e-8
+    # the multipole kernel with mu = Theta = 0 gives the same result
+    e2, f2, _ = ctx.empole_real(sysr, lst, w.mpole, 0.34, 12.0)
+    assert rel(np_(e2)[0], eo[0]) < 1e-10
+    e3, f3, _ = ctx.evdw(sysr, lst, 1, w.vdw_rad, w.vdw_eps, 12.0)
+    eo3, fo3, _ = O.evdw(w.xyz, w.box, w.molid, rp, cp, 1, w.vdw_rad, w.vdw_eps, 12.0)
+    assert rel(float(e3), eo3) < 1e-10
+    assert fmax_rel(np_(f3), fo3) < 1e-8
+
+
+def test_deterministic_repeat(ctx):
+    w, sysr, lst, rp, cp = setup_amoeba(ctx, "water7853", 7.001, 2)
+    e1, f1, _ = ctx.empole_real(sysr, lst, w.mpole, S["beta"], 7.0)
+    e2, f2, _ = ctx.empole_real(sysr, lst, w.mpole, S["beta"], 7.0)
+    assert np.array_equal(np_(e1), np_(e2)) and np.array_equal(np_(f1), np_(f2))
+    m1, _ = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0)
+    m2, _ = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0)
+    assert np.array_equal(np_(m1), np_(m2))
+
+
+def test_plan_mismatch_is_rejected(ctx, tk):
+    w, sysr, lst, rp, cp = setup_amoeba(ctx, "water216", 7.001, 2)
+    other = ctx.system(w.xyz[:30], w.box, w.molid[:30])
+    with pytest.raises(tk.TkError) as e:
+        ctx.empole_real(other, lst, w.mpole[:30], S["beta"], 7.0)
+    assert e.value.status == tk.E_PLAN
+    with pytest.raises(tk.TkError) as e:
+        ctx.empole_real(sysr, lst, w.mpole, S["beta"], 7.5)   # kernel cutoff beyond the list
+    assert e.value.status == tk.E_ARG
