@@ -1,0 +1,222 @@
+"""Benchmark: one step = one pass of the real-space AMOEBA hot path on one GPU.
+
+Step (23,559-atom water box, FP64 unless --prec mixed):
+  neighbour list at 7 A (CSR + cell-pair plan), neighbour list at 9 A,
+  permanent-multipole energy/forces/virial (7 A), induced dipoles by PCG to
+  1e-5 D RMS (permanent field + mat-vecs + FP64 true residual), Halgren 14-7
+  energy/forces/virial (9 A).
+value = real-space pair interactions per second over the whole step (each
+listed pair with r <= rc counted once per kernel evaluation; the mat-vec once
+per call).  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line.  Extra keys: polarization solves/s, the mixed-precision
+step, the point-charge + LJ path (96,000 atoms, 12 A), the roofline of the
+dominant kernel (HIP events inside the library, on the launch stream) and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1906_01211_amd import synth  # noqa: E402
+
+# Per-pair algorithmic floating-point operations of each kernel's definition
+# (+, -, * count 1, fused multiply-add 2; sqrt, division, exp and erfc count 1
+# each).  Derivation in the design doc.
+FLOPS_PER_PAIR = {"tmatvec": 62, "efield": 163, "empole": 398, "hal": 72, "charge": 31, "lj": 40}
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def count_pairs(xyz, box, row_ptr, col, rc, molid=None, skip_same=False):
+    n = len(row_ptr) - 1
+    i = np.repeat(np.arange(n), np.diff(row_ptr))
+    d = xyz[col] - xyz[i]
+    d -= box * np.rint(d / box)
+    ok = np.einsum("ij,ij->i", d, d) <= rc * rc
+    if skip_same:
+        ok &= molid[i] != molid[col]
+    return int(ok.sum())
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    return ap.parse_args()
+
+
+class AmoebaStep:
+    def __init__(self, ctx, tk, w, prec):
+        import torch
+        self.ctx, self.tk, self.w, self.prec = ctx, tk, w, prec
+        s = synth.AMOEBA_SETTINGS
+        self.s = s
+        dev = ctx.device
+        self.sys = ctx.system(w.xyz, w.box, w.molid)
+        self.mpole = torch.as_tensor(w.mpole, device=dev)
+        self.pol = torch.as_tensor(w.polarity, device=dev)
+        self.thole = torch.as_tensor(w.thole, device=dev)
+        self.rad = torch.as_tensor(w.vdw_rad, device=dev)
+        self.eps = torch.as_tensor(w.vdw_eps, device=dev)
+        self.info = None
+
+    def __call__(self):
+        c, s, p = self.ctx, self.s, self.prec
+        l7 = c.nblist(self.sys, s["rc_ewald"] + s["skin"], plan_slot=0)
+        l9 = c.nblist(self.sys, s["rc_vdw"] + s["skin"], plan_slot=1)
+        c.empole_real(self.sys, l7, self.mpole, s["beta"], s["rc_ewald"], prec=p)
+        _, self.info = c.polarize_pcg(self.sys, l7, self.mpole, self.pol, self.thole, s["beta"],
+                                      s["rc_ewald"], tol_debye=s["tol_debye"],
+                                      maxiter=s["maxiter"], prec=p)
+        c.evdw(self.sys, l9, self.tk.VDW_HAL, self.rad, self.eps, s["rc_vdw"],
+               s["taper_frac"], s["dhal"], s["ghal"], prec=p)
+        return l7, l9
+
+    def pair_counts(self):
+        l7, l9 = self()
+        w, s = self.w, self.s
+        n7 = count_pairs(w.xyz, w.box, l7.row_ptr.cpu().numpy(), l7.col.cpu().numpy(),
+                         s["rc_ewald"])
+        n9 = count_pairs(w.xyz, w.box, l9.row_ptr.cpu().numpy(), l9.col.cpu().numpy(), s["rc_vdw"],
+                         w.molid, skip_same=True)
+        return n7, n9
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(w, n7, n9):
+    """The CPU oracle on the same step (bounded: one full step of this workload)."""
+    from oracle import oracle as O
+    s = synth.AMOEBA_SETTINGS
+    t0 = time.perf_counter()
+    rp7, cp7 = O.nblist(w.xyz, w.box, s["rc_ewald"] + s["skin"])
+    rp9, cp9 = O.nblist(w.xyz, w.box, s["rc_vdw"] + s["skin"])
+    O.empole_real(w.xyz, w.box, w.molid, rp7, cp7, w.mpole, s["beta"], s["rc_ewald"])
+    _, info = O.polarize_pcg(w.xyz, w.box, w.molid, rp7, cp7, w.mpole, w.polarity, w.thole,
+                             s["beta"], s["rc_ewald"], tol_debye=s["tol_debye"])
+    O.evdw(w.xyz, w.box, w.molid, rp9, cp9, 0, w.vdw_rad, w.vdw_eps, s["rc_vdw"])
+    dt = time.perf_counter() - t0
+    pairs = n7 * (2 + info["iters"] + 2) + n9
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full FP64 step of the 23,559-atom water box (serial C oracle, "
+                      f"{dt:.2f} s, {info['iters']} PCG iterations)", "seconds": dt}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
+              f"(the path is single-GPU; multi-GPU sharding is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1906_01211_amd import tk
+    tk.load()
+    ctx = tk.Context(0)
+    prec = tk.FP64 if a.prec == "fp64" else tk.MIXED
+    w = synth.make("water7853")
+    step = AmoebaStep(ctx, tk, w, prec)
+    n7, n9 = step.pair_counts()
+
+    # timed region: the dominant kernel (mutual-field mat-vec tiles) is timed
+    # by HIP events that the library records on its launch stream
+    dom = "units_tmat_fp64" if prec == tk.FP64 else "units_tmat_fp32"
+    ctx.profile(True, only=dom)
+    ms = timed(step, a.steps, a.warmup) * 1e3
+    dprof = ctx.profile_read()
+    # full kernel breakdown from a separate pass (not used for `value`)
+    ctx.profile(True)
+    timed(step, max(2, a.steps // 4), 0)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    iters = step.info["iters"]
+    mv_calls = iters + 2          # initial residual + iterations + final FP64 residual
+    pairs = n7 * (1 + 1 + mv_calls) + n9   # empole + efield + mat-vecs + HAL
+    value = pairs / (ms * 1e-3)
+
+    roof = None
+    if dom in dprof and dprof[dom]["launches"] > 0:
+        avg_ms = dprof[dom]["ms"] / dprof[dom]["launches"]
+        flops = FLOPS_PER_PAIR["tmatvec"] * n7
+        ach = flops / (avg_ms * 1e-3) / 1e12
+        peak = PEAK_FP64_TFLOPS if prec == tk.FP64 else PEAK_FP32_TFLOPS
+        roof = {"bound": "alu", "kernel": "k_units<TmatPh>", "achieved": round(ach, 3),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
+                "avg_launch_us": round(avg_ms * 1e3, 3),
+                "flops_per_launch": flops}
+    out = {
+        "metric": "real-space pair-interactions/s + polarization solves/s (mixed vs FP64); p99 lat",
+        "value": value, "unit": "pair-interactions/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == tk.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "water box, 7,853 waters (23,559 atoms), 62.23 A, AMOEBA-style "
+                               "multipoles + Thole polarization + HAL, rc 7/9 A",
+                   "atoms": w.n, "pairs_7A": n7, "pairs_9A_hal": n9,
+                   "pcg_iters": iters, "prec": a.prec},
+        "solves_per_s": 1e3 / ms,
+        "kernel_ms_per_step": {k: round(v["ms"] / max(2, a.steps // 4), 5) for k, v in prof.items()},
+        "roofline": roof,
+    }
+    if not a.no_extras:
+        out["extras"] = extras(ctx, tk, w, a, prec)
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, n7, n9)
+    ctx.close()
+    print(json.dumps(out))
+
+
+def extras(ctx, tk, w, a, prec):
+    """Mixed-vs-FP64 step and the charge + LJ path (not part of `value`)."""
+    import torch
+    res = {}
+    other = tk.MIXED if prec == tk.FP64 else tk.FP64
+    st = AmoebaStep(ctx, tk, w, other)
+    ms = timed(st, max(3, a.steps // 2), 2) * 1e3
+    res["amoeba_step_ms_" + ("mixed" if other == tk.MIXED else "fp64")] = ms
+    res["pcg_iters_other"] = st.info["iters"]
+    wc = synth.make("water32000_charge_lj")
+    s = synth.CHARGE_SETTINGS
+    sysr = ctx.system(wc.xyz, wc.box, wc.molid)
+    q = torch.as_tensor(wc.charges, device=ctx.device)
+    rad = torch.as_tensor(wc.vdw_rad, device=ctx.device)
+    eps = torch.as_tensor(wc.vdw_eps, device=ctx.device)
+    for name, pr in (("fp64", tk.FP64), ("mixed", tk.MIXED)):
+        def cstep():
+            l12 = ctx.nblist(sysr, s["rc_ewald"] + s["skin"], plan_slot=2)
+            ctx.echarge_real(sysr, l12, q, s["beta"], s["rc_ewald"], prec=pr)
+            ctx.evdw(sysr, l12, tk.VDW_LJ, rad, eps, s["rc_vdw"], s["taper_frac"], prec=pr)
+            return l12
+        l12 = cstep()
+        ms = timed(cstep, 3, 1) * 1e3
+        res[f"charge_lj_step_ms_{name}"] = ms
+        res["charge_lj_pairs_12A"] = int(l12.npairs)
+        res[f"charge_lj_pairs_per_s_{name}"] = 2 * l12.npairs / (ms * 1e-3)
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -213,6 +213,21 @@ tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nbli
                   double taper_on_frac, double hal_delta, double hal_gamma, int prec,
                   double* energy, double* force, double* virial);
 
+/*
+ * Kernel timing (tracing aid).  When enabled, the library brackets its kernel
+ * launches with HIP events on the launch stream; `only` (host string, may be
+ * NULL) restricts timing to the kernel of that name.  tk_profile_read returns
+ * the idx-th timed kernel (names like "units_tmat_fp64", "nblist_rows_fill"):
+ * name (host buffer of name_len bytes), number of timed launches and total
+ * milliseconds; it waits for the timed work to finish.  TK_E_ARG when idx is
+ * past the last kernel.  tk_profile_enable(ctx, 0, NULL) stops timing;
+ * tk_profile_reset clears the counters.
+ */
+tk_status tk_profile_enable(tk_ctx* ctx, int on, const char* only);
+tk_status tk_profile_read(tk_ctx* ctx, int32_t idx, char* name, int32_t name_len,
+                          int64_t* launches, double* total_ms);
+tk_status tk_profile_reset(tk_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

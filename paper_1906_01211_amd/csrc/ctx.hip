@@ -2,6 +2,7 @@
 // device exclusive scan, and argument checks shared by the entry points.
 #include <cmath>
 #include <cstring>
+#include <iterator>
 
 #include "tk_internal.hpp"
 
@@ -40,20 +41,23 @@ tk_status scratch(tk_ctx* ctx, const char* name, size_t bytes, void** out) {
   return s;
 }
 
-tk_status pinned(tk_ctx* ctx, size_t bytes, void** out) {
+tk_status pinned(tk_ctx* ctx, size_t bytes, void** out, void** dev) {
   if (ctx->pinned_bytes < bytes) {
     if (ctx->pinned) TK_HIP(hipHostFree(ctx->pinned));
     ctx->pinned = nullptr;
+    ctx->pinned_dev = nullptr;
     ctx->pinned_bytes = 0;
     size_t want = bytes < 4096 ? 4096 : bytes;
-    TK_HIP(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+    TK_HIP(hipHostMalloc(&ctx->pinned, want, hipHostMallocCoherent));   // fine-grained: kernels write it directly
+    TK_HIP(hipHostGetDevicePointer(&ctx->pinned_dev, ctx->pinned, 0));
     ctx->pinned_bytes = want;
   }
   *out = ctx->pinned;
+  if (dev) *dev = ctx->pinned_dev;
   return TK_OK;
 }
 
-const CellTables& cell_tables(tk_ctx* ctx, int nc) {
+CellTables& cell_tables(tk_ctx* ctx, int nc) {
   auto it = ctx->tables.find(nc);
   if (it != ctx->tables.end()) return it->second;
   CellTables t;
@@ -101,58 +105,62 @@ const CellTables& cell_tables(tk_ctx* ctx, int nc) {
 // Exclusive scan (three phases: block sums, scan of block sums, block scan).
 constexpr int kScanBlock = 256, kScanItems = 4, kScanTile = kScanBlock * kScanItems;
 
-__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
+template <class T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T* total) {
   int tid = threadIdx.x;
   sh[tid] = v;
   __syncthreads();
   for (int off = 1; off < kScanBlock; off <<= 1) {
-    int t = tid >= off ? sh[tid - off] : 0;
+    T t = tid >= off ? sh[tid - off] : T(0);
     __syncthreads();
     sh[tid] += t;
     __syncthreads();
   }
-  int incl = sh[tid];
+  T incl = sh[tid];
   *total = sh[kScanBlock - 1];
   __syncthreads();
   return incl - v;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_sums(const int32_t* in, int len, int32_t* bsum) {
-  __shared__ int sh[kScanBlock];
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(const T* in, long len, T* bsum) {
+  __shared__ T sh[kScanBlock];
   long base = (long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  int s = 0;
+  T s = 0;
   for (int q = 0; q < kScanItems; ++q)
     if (base + q < len) s += in[base + q];
-  int tot;
-  block_exclusive_scan(s, sh, &tot);
+  T tot;
+  block_exclusive_scan<T>(s, sh, &tot);
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_bsum(int32_t* bsum, int nb) {
-  __shared__ int sh[kScanBlock];
-  int carry = 0;
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_bsum(T* bsum, int nb) {
+  __shared__ T sh[kScanBlock];
+  T carry = 0;
   for (int b0 = 0; b0 < nb; b0 += kScanBlock) {
     int i = b0 + threadIdx.x;
-    int v = i < nb ? bsum[i] : 0;
-    int tot;
-    int ex = block_exclusive_scan(v, sh, &tot);
+    T v = i < nb ? bsum[i] : T(0);
+    T tot;
+    T ex = block_exclusive_scan<T>(v, sh, &tot);
     if (i < nb) bsum[i] = carry + ex;
     carry += tot;
   }
   if (threadIdx.x == 0) bsum[nb] = carry;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_final(const int32_t* in, int len,
-                                                           const int32_t* bsum, int32_t* out) {
-  __shared__ int sh[kScanBlock];
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_final(const T* in, long len, const T* bsum,
+                                                           T* out) {
+  __shared__ T sh[kScanBlock];
   long base = (long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  int v[kScanItems], s = 0;
+  T v[kScanItems], s = 0;
   for (int q = 0; q < kScanItems; ++q) {
-    v[q] = base + q < len ? in[base + q] : 0;
+    v[q] = base + q < len ? in[base + q] : T(0);
     s += v[q];
   }
-  int tot;
-  int ex = block_exclusive_scan(s, sh, &tot) + bsum[blockIdx.x];
+  T tot;
+  T ex = block_exclusive_scan<T>(s, sh, &tot) + bsum[blockIdx.x];
   for (int q = 0; q < kScanItems; ++q) {
     if (base + q < len) out[base + q] = ex;
     ex += v[q];
@@ -160,17 +168,70 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const int32_t* in, in
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[len] = bsum[gridDim.x];
 }
 
-tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len) {
+template <class T>
+static tk_status scan_t(tk_ctx* ctx, hipStream_t st, const T* in, T* out, long len,
+                        const char* name) {
   int nb = ceil_div(len, kScanTile);
   if (nb < 1) nb = 1;
   void* bs;
-  tk_status s = scratch(ctx, "scan_bsum", sizeof(int32_t) * (nb + 1), &bs);
+  tk_status s = scratch(ctx, name, sizeof(T) * (nb + 1), &bs);
   if (s) return s;
-  k_scan_sums<<<nb, kScanBlock, 0, st>>>(in, len, (int32_t*)bs);
-  k_scan_bsum<<<1, kScanBlock, 0, st>>>((int32_t*)bs, nb);
-  k_scan_final<<<nb, kScanBlock, 0, st>>>(in, len, (int32_t*)bs, out);
+  k_scan_sums<T><<<nb, kScanBlock, 0, st>>>(in, len, (T*)bs);
+  k_scan_bsum<T><<<1, kScanBlock, 0, st>>>((T*)bs, nb);
+  k_scan_final<T><<<nb, kScanBlock, 0, st>>>(in, len, (T*)bs, out);
   TK_HIP(hipGetLastError());
   return TK_OK;
+}
+
+tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len) {
+  return scan_t<int32_t>(ctx, st, in, out, len, "scan_bsum32");
+}
+
+tk_status scan_i64(tk_ctx* ctx, hipStream_t st, const int64_t* in, int64_t* out, long len) {
+  return scan_t<int64_t>(ctx, st, in, out, len, "scan_bsum64");
+}
+
+static hipEvent_t take_event(tk_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(tk_ctx* c, hipStream_t s, const std::string& name) : ctx(c), st(s) {
+  if (!ctx->prof_on || (!ctx->prof_only.empty() && ctx->prof_only != name)) return;
+  a = take_event(ctx);
+  if (!a) return;
+  e = &ctx->prof[name];
+  (void)hipEventRecord(a, st);
+}
+
+ProfScope::~ProfScope() {
+  if (!e) return;
+  hipEvent_t b = take_event(ctx);
+  if (!b) return;
+  (void)hipEventRecord(b, st);
+  e->pending.emplace_back(a, b);
+}
+
+static void prof_drain(tk_ctx* ctx) {
+  for (auto& kv : ctx->prof) {
+    for (auto& ev : kv.second.pending) {
+      float ms = 0.f;
+      if (hipEventSynchronize(ev.second) == hipSuccess &&
+          hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
+        kv.second.ms += ms;
+        kv.second.launches += 1;
+      }
+      ctx->event_pool.push_back(ev.first);
+      ctx->event_pool.push_back(ev.second);
+    }
+    kv.second.pending.clear();
+  }
 }
 
 tk_status check_system(const tk_system* sys) {
@@ -210,18 +271,54 @@ tk_status tk_create(int device, tk_ctx** out) {
   return TK_OK;
 }
 
+tk_status tk_profile_enable(tk_ctx* ctx, int on, const char* only) {
+  if (!ctx) return TK_E_ARG;
+  ctx->prof_on = on != 0;
+  ctx->prof_only = only ? only : "";
+  return TK_OK;
+}
+
+tk_status tk_profile_read(tk_ctx* ctx, int32_t idx, char* name, int32_t name_len,
+                          int64_t* launches, double* total_ms) {
+  if (!ctx || idx < 0) return TK_E_ARG;
+  tk::prof_drain(ctx);
+  if (idx >= (int32_t)ctx->prof.size()) return TK_E_ARG;
+  auto it = ctx->prof.begin();
+  std::advance(it, idx);
+  if (name && name_len > 0) {
+    std::strncpy(name, it->first.c_str(), (size_t)name_len - 1);
+    name[name_len - 1] = 0;
+  }
+  if (launches) *launches = it->second.launches;
+  if (total_ms) *total_ms = it->second.ms;
+  return TK_OK;
+}
+
+tk_status tk_profile_reset(tk_ctx* ctx) {
+  if (!ctx) return TK_E_ARG;
+  tk::prof_drain(ctx);
+  ctx->prof.clear();
+  return TK_OK;
+}
+
 void tk_destroy(tk_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  tk::prof_drain(ctx);
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   auto freeb = [](tk::DevBuf& b) {
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
   };
   for (auto& p : ctx->plans) {
-    freeb(p.perm); freeb(p.scell); freeb(p.cell_start); freeb(p.cell_nslot); freeb(p.units);
-    freeb(p.unit_ptr); freeb(p.codes); freeb(p.us); freeb(p.nbr);
+    freeb(p.perm); freeb(p.scell); freeb(p.cell_start); freeb(p.unit_off); freeb(p.unit_cnt);
+    freeb(p.codes); freeb(p.us); freeb(p.slots);
+  }
+  for (auto& kv : ctx->tables) {
+    freeb(kv.second.units_d);
+    freeb(kv.second.nslot_d);
   }
   for (auto& kv : ctx->scratch) freeb(kv.second);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);

@@ -2,11 +2,15 @@
 // paper's Rel profile, with the selection-mask + compress pattern of its
 // section "Typical selection loop" mapped to wavefront ballots).
 //
-// Steps:  quantize -> cell histogram -> scan -> scatter -> per-cell stable order
-//         -> cell-pair plan (count, scan, fill)
-//         -> canonical CSR rows (count, scan, fill with an in-LDS ordering by j).
-// Every pair decision is the same exact 64-bit integer test, so the plan and
-// the CSR hold the same pair set, bit for bit, whatever the launch order.
+// Pipeline:
+//   quantize -> cell histogram -> scan -> scatter -> per-cell stable order
+//   -> candidate windows (one per cell-pair unit) -> ONE enumeration that
+//      writes each unit's listed pairs into its window and counts, per
+//      (unit role, atom), the pairs whose CSR row is that atom's
+//   -> row lengths + role offsets -> scan  [one host synchronisation]
+//   -> canonical CSR written from the pair codes -> rows ordered by j.
+// Every pair decision is the same exact test, so the plan (what the pair
+// kernels read) and the CSR (what the caller reads) hold the same pair set.
 #include <cmath>
 
 #include "tk_internal.hpp"
@@ -22,16 +26,28 @@ __device__ __forceinline__ bool pair_in(const uint4& a, const uint4& b, uint64_t
   return d2 <= rq2;
 }
 
+// Fast form of the exact test: the FP64 sum of squares of the (exact) integer
+// differences is within 3 ulp of the true value, so outside a +-2^-50 band
+// around rq^2 it decides; inside the band the exact 64-bit test decides.
+struct PairTest {
+  uint64_t rq2;
+  double lo, hi;
+  __device__ __forceinline__ bool operator()(const uint4& a, const uint4& b) const {
+    const double dx = (double)(int32_t)(b.x - a.x), dy = (double)(int32_t)(b.y - a.y),
+                 dz = (double)(int32_t)(b.z - a.z);
+    const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    if (d2 < lo) return true;
+    if (d2 > hi) return false;
+    return pair_in(a, b, rq2);
+  }
+};
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
   return __popcll(mask & ((1ull << lane_id()) - 1ull));
 }
 
-__device__ __forceinline__ int wave_sum(int v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
 __device__ __forceinline__ int wave_min(int v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
   return v;
@@ -41,10 +57,12 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// info: [0] status, [1] max cell occupancy, [2] max CSR row, [3] listed pairs,
+//       [4] 1 if the candidate windows did not fit the plan buffer
 // u = floor(frac(x/L) * 2^32) per coordinate; cell = (u * nc) >> 32 per axis.
 __global__ void k_quantize(int n, const double* __restrict__ xyz, double box, int nc,
                            uint32_t* __restrict__ u, int32_t* __restrict__ cell,
-                           int32_t* __restrict__ cell_count, int32_t* __restrict__ status) {
+                           int32_t* __restrict__ cell_count, int32_t* __restrict__ info) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int c[3];
@@ -57,7 +75,7 @@ __global__ void k_quantize(int n, const double* __restrict__ xyz, double box, in
       if (f >= 1.0) f = 0.0;
       q = (uint32_t)(f * kTwo32);
     } else {
-      atomicMin(status, (int)TK_E_ARG);
+      atomicMin(&info[0], (int)TK_E_ARG);
     }
     u[3 * i + a] = q;
     c[a] = (int)(((uint64_t)q * (uint64_t)nc) >> 32);
@@ -100,123 +118,193 @@ __global__ __launch_bounds__(64) void k_cellsort(const int32_t* __restrict__ cst
   }
 }
 
-// One wave per cell-pair unit.  Candidates (a in H, b in K) are visited in
-// "diagonal" order b = (a + k) mod |K|, so consecutive listed pairs touch
-// distinct atoms on both sides (conflict-free LDS accumulation later).
-template <bool kFill>
-__global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict__ units,
-                                             const int32_t* __restrict__ cstart,
-                                             const uint4* __restrict__ us, uint64_t rq2,
-                                             int32_t* __restrict__ unit_cnt,
-                                             const int32_t* __restrict__ unit_ptr,
-                                             uint32_t* __restrict__ codes) {
-  int uidx = blockIdx.x;
-  if (uidx >= nunits) return;
-  Unit un = units[uidx];
-  int hs = cstart[un.h], nh = cstart[un.h + 1] - hs;
-  int ks = cstart[un.k], nk = cstart[un.k + 1] - ks;
-  if (nh > kMaxCellAtoms || nk > kMaxCellAtoms) return;
-  bool self = un.h == un.k;
-  int base = kFill ? unit_ptr[uidx] : 0, cnt = 0;
-  int lane = lane_id();
-  for (int kk = 0; kk < nk; ++kk) {
-    for (int a0 = 0; a0 < nh; a0 += 64) {
-      int a = a0 + lane;
-      bool pass = false;
-      int b = 0;
-      if (a < nh) {
-        b = (a + kk) % nk;
-        if (!self || a < b) pass = pair_in(us[hs + a], us[ks + b], rq2);
-      }
-      uint64_t mask = __ballot(pass);
-      if (kFill && pass) codes[base + lanes_below(mask)] = (uint32_t)a | ((uint32_t)b << 16);
-      int pc = __popcll(mask);
-      base += pc;
-      cnt += pc;
-    }
-  }
-  if (!kFill && lane == 0) unit_cnt[uidx] = cnt;
+// Candidate window of each unit: |H| * |K| slots.
+__global__ void k_cand(int nunits, const Unit* __restrict__ units, const int32_t* __restrict__ cstart,
+                       int64_t* __restrict__ cand) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nunits) return;
+  Unit un = units[u];
+  cand[u] = (int64_t)(cstart[un.h + 1] - cstart[un.h]) * (int64_t)(cstart[un.k + 1] - cstart[un.k]);
 }
 
-// One wave per caller row i: visit the atoms of the (unique) neighbour cells
-// of cell(i), keep j > i inside the cutoff.  Count mode writes the row length;
-// fill mode collects the row in LDS, orders it by j and writes it.
-template <bool kFill>
-__global__ __launch_bounds__(64) void k_rows(int n, const int32_t* __restrict__ cell,
-                                             const uint32_t* __restrict__ u,
-                                             const int32_t* __restrict__ nbr,
+// One wave per cell-pair unit (H, K), both cells staged in LDS.  Candidates
+// (a in H, b in K) are visited in "diagonal" order b = (a + k) mod |K|, so
+// consecutive listed pairs touch distinct atoms on both sides (conflict-free
+// LDS accumulation in the pair kernels).  Writes the unit's pair codes
+// a | b << 16 into its window, the unit's pair count, and per (unit role,
+// atom) the number of pairs whose CSR row is that atom's (the smaller caller
+// index owns the pair).
+__global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict__ units,
                                              const int32_t* __restrict__ cstart,
-                                             const uint4* __restrict__ us, uint64_t rq2,
-                                             int32_t* __restrict__ row_cnt,
-                                             const int32_t* __restrict__ row_ptr,
-                                             int32_t* __restrict__ col, int32_t* __restrict__ info) {
-  extern __shared__ int lds[];
-  int i = blockIdx.x;
-  if (i >= n) return;
-  int lane = lane_id();
-  uint4 ui = make_uint4(u[3 * i], u[3 * i + 1], u[3 * i + 2], (uint32_t)i);
-  int c = cell[i];
-  int nn = nbr[c * 28];
-  int m = 0;
-  int* A = lds;   // [max_row] row entries in visit order
-  for (int q = 0; q < nn; ++q) {
-    int cc = nbr[c * 28 + 1 + q];
-    int t0 = cstart[cc], t1 = cstart[cc + 1];
-    for (int t = t0; t < t1; t += 64) {
-      int tt = t + lane;
-      bool pass = false;
-      uint4 uj;
-      if (tt < t1) {
-        uj = us[tt];
-        pass = uj.w > (uint32_t)i && pair_in(ui, uj, rq2);
-      }
-      uint64_t mask = __ballot(pass);
-      if (kFill && pass) A[m + lanes_below(mask)] = (int)uj.w;
-      m += __popcll(mask);
-    }
-  }
-  if (!kFill) {
-    if (lane == 0) {
-      row_cnt[i] = m;
-      atomicMax(&info[2], m);
-    }
+                                             const uint4* __restrict__ us, PairTest test,
+                                             long pstride, const int64_t* __restrict__ unit_off,
+                                             long code_cap, uint32_t* __restrict__ codes,
+                                             int32_t* __restrict__ unit_cnt,
+                                             int32_t* __restrict__ slot_cnt,
+                                             int32_t* __restrict__ info) {
+  __shared__ uint4 sK[kMaxCellAtoms];
+  __shared__ int cH[kMaxCellAtoms], cK[kMaxCellAtoms];
+  const int uidx = blockIdx.x;
+  const int lane = lane_id();
+  if (unit_off[nunits] > code_cap) {   // windows do not fit: host grows the buffer, reruns
+    if (uidx == 0 && lane == 0) info[4] = 1;
     return;
   }
+  const Unit un = units[uidx];
+  const int hs = cstart[un.h], nh = cstart[un.h + 1] - hs;
+  const int ks = cstart[un.k], nk = cstart[un.k + 1] - ks;
+  if (nh > kMaxCellAtoms || nk > kMaxCellAtoms) return;
+  const bool self = un.h == un.k;
+  for (int t = lane; t < nh; t += 64) cH[t] = 0;
+  for (int t = lane; t < nk; t += 64) {
+    sK[t] = us[ks + t];
+    cK[t] = 0;
+  }
   __syncthreads();
-  int start = row_ptr[i];
-  if (m == 0) return;
-  // order the row by j: monotone buckets over [jmin, jmax], then rank inside a bucket
+  uint32_t* out = codes + unit_off[uidx];
+  int cnt = 0;
+  // visit order: (k, a) with a fastest; each lane keeps its own H atom in
+  // registers for a whole chunk of 64 a's.
+  for (int a0 = 0; a0 < nh; a0 += 64) {
+    const int a = a0 + lane;
+    const uint4 ua = a < nh ? us[hs + a] : make_uint4(0, 0, 0, 0);
+    int b = a;   // b = (a + kk) mod nk, advanced incrementally
+    while (b >= nk && nk > 0) b -= nk;
+    for (int kk = 0; kk < nk; ++kk) {
+      bool pass = false;
+      if (a < nh && (!self || a < b)) pass = test(ua, sK[b]);
+      const uint64_t mask = __ballot(pass);
+      if (pass) {
+        out[cnt + lanes_below(mask)] = (uint32_t)a | ((uint32_t)b << 16);
+        atomicAdd(ua.w < sK[b].w ? &cH[a] : &cK[b], 1);
+      }
+      cnt += __popcll(mask);
+      if (++b == nk) b = 0;
+    }
+  }
+  __syncthreads();
+  if (lane == 0) {
+    unit_cnt[uidx] = cnt;
+    atomicAdd(&info[3], cnt);
+  }
+  for (int t = lane; t < nh; t += 64) slot_cnt[(long)un.slot_h * pstride + hs + t] = cH[t];
+  for (int t = lane; t < nk; t += 64) slot_cnt[(long)un.slot_k * pstride + ks + t] = cK[t];
+}
+
+// Per sorted atom: the CSR row length (sum over its unit roles, written in
+// caller order) and, in place, the exclusive prefix of its per-role counts.
+__global__ void k_row_slots(int n, const int32_t* __restrict__ perm, const int32_t* __restrict__ scell,
+                            const int32_t* __restrict__ cell_nslot, long pstride,
+                            int32_t* __restrict__ slot_cnt, int32_t* __restrict__ row_cnt,
+                            int32_t* __restrict__ info) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int ns = cell_nslot[scell[s]];
+  int c[kMaxSlots];
+#pragma unroll
+  for (int k = 0; k < kMaxSlots; ++k) c[k] = k < ns ? slot_cnt[(long)k * pstride + s] : 0;
+  int run = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxSlots; ++k) {
+    if (k < ns) slot_cnt[(long)k * pstride + s] = run;
+    run += c[k];
+  }
+  row_cnt[perm[s]] = run;
+  atomicMax(&info[2], run);
+}
+
+// One wave per unit: each listed pair's j goes into its CSR row, at the
+// owner atom's role offset (order inside a role is fixed by the row sort).
+__global__ __launch_bounds__(64) void k_csr_fill(const Unit* __restrict__ units,
+                                                 const int32_t* __restrict__ cstart,
+                                                 const int32_t* __restrict__ perm, long pstride,
+                                                 const int64_t* __restrict__ unit_off,
+                                                 const int32_t* __restrict__ unit_cnt,
+                                                 const uint32_t* __restrict__ codes,
+                                                 const int32_t* __restrict__ slot_off,
+                                                 const int32_t* __restrict__ row_ptr,
+                                                 int32_t* __restrict__ col) {
+  __shared__ int pH[kMaxCellAtoms], pK[kMaxCellAtoms], cH[kMaxCellAtoms], cK[kMaxCellAtoms];
+  __shared__ int bH[kMaxCellAtoms], bK[kMaxCellAtoms];
+  const int uidx = blockIdx.x, lane = lane_id();
+  const Unit un = units[uidx];
+  const int hs = cstart[un.h], nh = cstart[un.h + 1] - hs;
+  const int ks = cstart[un.k], nk = cstart[un.k + 1] - ks;
+  if (nh > kMaxCellAtoms || nk > kMaxCellAtoms) return;
+  for (int t = lane; t < nh; t += 64) {
+    const int i = perm[hs + t];
+    pH[t] = i;
+    cH[t] = 0;
+    bH[t] = row_ptr[i] + slot_off[(long)un.slot_h * pstride + hs + t];
+  }
+  for (int t = lane; t < nk; t += 64) {
+    const int i = perm[ks + t];
+    pK[t] = i;
+    cK[t] = 0;
+    bK[t] = row_ptr[i] + slot_off[(long)un.slot_k * pstride + ks + t];
+  }
+  __syncthreads();
+  const uint32_t* src = codes + unit_off[uidx];
+  const int m = unit_cnt[uidx];
+  for (int p = lane; p < m; p += 64) {
+    const uint32_t code = src[p];
+    const int a = (int)(code & 0xffffu), b = (int)(code >> 16);
+    const int ia = pH[a], ib = pK[b];
+    if (ia < ib) col[bH[a] + atomicAdd(&cH[a], 1)] = ib;
+    else col[bK[b] + atomicAdd(&cK[b], 1)] = ia;
+  }
+}
+
+// Gathers the build's outcome into pinned host memory (one kernel instead of
+// several small copies).
+__global__ void k_readback(const int32_t* __restrict__ info, const int32_t* __restrict__ rp_end,
+                           const int64_t* __restrict__ off_end, int32_t* __restrict__ host) {
+  for (int k = 0; k < 5; ++k) host[k] = info[k];
+  host[5] = *rp_end;
+  *(int64_t*)(host + 8) = *off_end;
+}
+
+// One wave per CSR row: order the row by j (monotone buckets over [jmin, jmax],
+// then rank inside a bucket).  LDS: A[max_row], G[max_row], cnt, off.
+__global__ __launch_bounds__(64) void k_rowsort(int n, const int32_t* __restrict__ row_ptr,
+                                                int32_t* __restrict__ col, int max_row) {
+  extern __shared__ int lds[];
+  const int i = blockIdx.x;
+  const int lane = lane_id();
+  const int start = row_ptr[i], m = row_ptr[i + 1] - start;
+  if (m <= 1) return;
+  const int nbmax = max_row < kBuckets ? max_row : kBuckets;
+  int* A = lds;
+  int* G = A + max_row;
+  int* cnt = G + max_row;
+  int* off = cnt + nbmax;
   int jmin = 0x7fffffff, jmax = -1;
   for (int e = lane; e < m; e += 64) {
-    jmin = min(jmin, A[e]);
-    jmax = max(jmax, A[e]);
+    const int v = col[start + e];
+    A[e] = v;
+    jmin = min(jmin, v);
+    jmax = max(jmax, v);
   }
   jmin = wave_min(jmin);
   jmax = wave_max(jmax);
-  int nb = m < kBuckets ? m : kBuckets;
-  double scale = (double)nb / (double)(jmax - jmin + 1);
-  int* G = A + m;          // [m] entries grouped by bucket
-  int* cnt = G + m;        // [nb]
-  int* off = cnt + nb;     // [nb]
-  for (int b = lane; b < nb; b += 64) {
-    cnt[b] = 0;
-    off[b] = 0;
-  }
+  const int nb = m < kBuckets ? m : kBuckets;
+  const double scale = (double)nb / (double)(jmax - jmin + 1);
+  for (int b = lane; b < nb; b += 64) cnt[b] = 0;
   __syncthreads();
   for (int e = lane; e < m; e += 64) {
-    int b = min(nb - 1, (int)((double)(A[e] - jmin) * scale));
+    const int b = min(nb - 1, (int)((double)(A[e] - jmin) * scale));
     atomicAdd(&cnt[b], 1);
   }
   __syncthreads();
-  // exclusive scan of cnt (one wave: each lane scans a contiguous chunk)
-  int per = (nb + 63) / 64, b0 = lane * per, b1 = min(nb, b0 + per), s = 0;
-  for (int b = b0; b < b1; ++b) s += cnt[b];
-  int incl = s;
+  const int per = (nb + 63) / 64, b0 = lane * per, b1 = min(nb, b0 + per);
+  int sum = 0;
+  for (int b = b0; b < b1; ++b) sum += cnt[b];
+  int incl = sum;
   for (int o = 1; o < 64; o <<= 1) {
-    int t = __shfl_up(incl, o);
+    const int t = __shfl_up(incl, o);
     if (lane >= o) incl += t;
   }
-  int run = incl - s;
+  int run = incl - sum;
   for (int b = b0; b < b1; ++b) {
     off[b] = run;
     run += cnt[b];
@@ -225,14 +313,15 @@ __global__ __launch_bounds__(64) void k_rows(int n, const int32_t* __restrict__ 
   for (int b = lane; b < nb; b += 64) cnt[b] = 0;   // reuse as fill cursor
   __syncthreads();
   for (int e = lane; e < m; e += 64) {
-    int b = min(nb - 1, (int)((double)(A[e] - jmin) * scale));
+    const int b = min(nb - 1, (int)((double)(A[e] - jmin) * scale));
     G[off[b] + atomicAdd(&cnt[b], 1)] = A[e];
   }
   __syncthreads();
   for (int e = lane; e < m; e += 64) {
-    int j = A[e];
-    int b = min(nb - 1, (int)((double)(j - jmin) * scale));
-    int k0 = off[b], k1 = k0 + cnt[b], rank = k0;
+    const int j = A[e];
+    const int b = min(nb - 1, (int)((double)(j - jmin) * scale));
+    const int k0 = off[b], k1 = k0 + cnt[b];
+    int rank = k0;
     for (int k = k0; k < k1; ++k) rank += G[k] < j;
     col[start + rank] = j;
   }
@@ -250,38 +339,53 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
   if (!(cutoff > 0.0) || !std::isfinite(cutoff)) return TK_E_ARG;
   if (cutoff > 0.5 * sys->box) return TK_E_CUTOFF;
   if (slot < 0 || slot >= TK_MAX_PLANS || cap < 0) return TK_E_ARG;
-  if ((row_ptr == nullptr) != (col == nullptr) && !(row_ptr && cap == 0)) return TK_E_ARG;
+  if (col && !row_ptr) return TK_E_ARG;
   Plan& P = ctx->plans[slot];
   P.valid = false;
   const int n = sys->n;
   int nc = (int)std::floor(sys->box / cutoff);
   if (nc < 1) nc = 1;
-  const CellTables& T = cell_tables(ctx, nc);
+  CellTables& T = cell_tables(ctx, nc);
   const uint64_t rq = (uint64_t)std::floor((cutoff / sys->box) * kTwo32);
-  const uint64_t rq2 = rq * rq;
+  PairTest test;
+  test.rq2 = rq * rq;
+  test.lo = (double)test.rq2 * (1.0 - 0x1p-50);
+  test.hi = (double)test.rq2 * (1.0 + 0x1p-50);
   const int nn = n > 0 ? n : 1;
+  const long pstride = (nn + 63) / 64 * 64;
+  const bool want_csr = row_ptr != nullptr;
 
-  // plan buffers (device) and the host-built cell tables
+  // device copies of the cell tables (uploaded once per cells-per-edge value)
+  if (!T.uploaded) {
+    if ((s = ensure(T.units_d, sizeof(Unit) * T.nunits)) ||
+        (s = ensure(T.nslot_d, sizeof(int32_t) * T.ncells)))
+      return s;
+    TK_HIP(hipMemcpy(T.units_d.p, T.units.data(), sizeof(Unit) * T.nunits, hipMemcpyHostToDevice));
+    TK_HIP(hipMemcpy(T.nslot_d.p, T.nslot.data(), sizeof(int32_t) * T.ncells, hipMemcpyHostToDevice));
+    T.uploaded = true;
+  }
   if ((s = ensure(P.perm, sizeof(int32_t) * nn)) || (s = ensure(P.scell, sizeof(int32_t) * nn)) ||
       (s = ensure(P.cell_start, sizeof(int32_t) * (T.ncells + 1))) ||
-      (s = ensure(P.cell_nslot, sizeof(int32_t) * T.ncells)) ||
-      (s = ensure(P.units, sizeof(Unit) * T.nunits)) ||
-      (s = ensure(P.unit_ptr, sizeof(int32_t) * (T.nunits + 1))) ||
-      (s = ensure(P.us, sizeof(uint4) * nn)) || (s = ensure(P.nbr, sizeof(int32_t) * T.ncells * 28)))
+      (s = ensure(P.unit_off, sizeof(int64_t) * (T.nunits + 1))) ||
+      (s = ensure(P.unit_cnt, sizeof(int32_t) * T.nunits)) ||
+      (s = ensure(P.us, sizeof(uint4) * nn)) ||
+      (s = ensure(P.slots, sizeof(int32_t) * kMaxSlots * pstride)))
     return s;
-  TK_HIP(hipMemcpyAsync(P.units.p, T.units.data(), sizeof(Unit) * T.nunits, hipMemcpyHostToDevice, st));
-  TK_HIP(hipMemcpyAsync(P.cell_nslot.p, T.nslot.data(), sizeof(int32_t) * T.ncells,
-                        hipMemcpyHostToDevice, st));
-  TK_HIP(hipMemcpyAsync(P.nbr.p, T.nbr.data(), sizeof(int32_t) * T.ncells * 28,
-                        hipMemcpyHostToDevice, st));
-  void *u, *cell, *ccount, *cursor, *tmp, *info, *ucnt, *rcnt, *rptr;
+  // candidate windows: sum over units of |H||K|, estimated from the density
+  // (the buffer grows, and the enumeration reruns, if the estimate is short)
+  const double mean = (double)n / T.ncells;
+  const double est = 1.15 * (double)T.nunits * mean * mean + 16.0 * n + 65536.0;
+  if (P.codes.bytes < sizeof(uint32_t) * (size_t)est &&
+      (s = ensure(P.codes, sizeof(uint32_t) * (size_t)est)))
+    return s;
+  void *u, *cell, *ccount, *cursor, *tmp, *info, *cand, *rcnt, *rptr;
   if ((s = scratch(ctx, "nb_u", sizeof(uint32_t) * 3 * nn, &u)) ||
       (s = scratch(ctx, "nb_cell", sizeof(int32_t) * nn, &cell)) ||
       (s = scratch(ctx, "nb_ccount", sizeof(int32_t) * (T.ncells + 1), &ccount)) ||
       (s = scratch(ctx, "nb_cursor", sizeof(int32_t) * T.ncells, &cursor)) ||
       (s = scratch(ctx, "nb_tmp", sizeof(int32_t) * nn, &tmp)) ||
       (s = scratch(ctx, "nb_info", sizeof(int32_t) * 8, &info)) ||
-      (s = scratch(ctx, "nb_ucnt", sizeof(int32_t) * (T.nunits + 1), &ucnt)) ||
+      (s = scratch(ctx, "nb_cand", sizeof(int64_t) * (T.nunits + 1), &cand)) ||
       (s = scratch(ctx, "nb_rcnt", sizeof(int32_t) * (nn + 1), &rcnt)) ||
       (s = scratch(ctx, "nb_rptr", sizeof(int32_t) * (nn + 1), &rptr)))
     return s;
@@ -289,59 +393,81 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
   TK_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * T.ncells, st));
   TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
   const int32_t* cstart = (const int32_t*)P.cell_start.p;
+  const Unit* units = (const Unit*)T.units_d.p;
+  int32_t* rp = want_csr ? row_ptr : (int32_t*)rptr;
+  int32_t *h, *hd;
+  if ((s = pinned(ctx, 4096, (void**)&h, (void**)&hd))) return s;
   if (n > 0) {
-    k_quantize<<<ceil_div(n, 256), 256, 0, st>>>(n, sys->xyz, sys->box, nc, (uint32_t*)u,
-                                                  (int32_t*)cell, (int32_t*)ccount, (int32_t*)info);
-  }
-  if ((s = scan_i32(ctx, st, (int32_t*)ccount, (int32_t*)P.cell_start.p, T.ncells))) return s;
-  if (n > 0) {
+    {
+      ProfScope ps(ctx, st, "nblist_quantize");
+      k_quantize<<<ceil_div(n, 256), 256, 0, st>>>(n, sys->xyz, sys->box, nc, (uint32_t*)u,
+                                                    (int32_t*)cell, (int32_t*)ccount, (int32_t*)info);
+    }
+    if ((s = scan_i32(ctx, st, (int32_t*)ccount, (int32_t*)P.cell_start.p, T.ncells))) return s;
     k_scatter<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)cell, cstart, (int32_t*)cursor,
                                                  (int32_t*)tmp);
-    k_cellsort<<<T.ncells, 64, 0, st>>>(cstart, (int32_t*)tmp, (uint32_t*)u, (int32_t*)P.perm.p,
-                                        (int32_t*)P.scell.p, (uint4*)P.us.p, (int32_t*)info);
-    k_plan<false><<<T.nunits, 64, 0, st>>>(T.nunits, (Unit*)P.units.p, cstart, (uint4*)P.us.p, rq2,
-                                           (int32_t*)ucnt, nullptr, nullptr);
-    k_rows<false><<<n, 64, 0, st>>>(n, (int32_t*)cell, (uint32_t*)u, (int32_t*)P.nbr.p, cstart,
-                                    (uint4*)P.us.p, rq2, (int32_t*)rcnt, nullptr, nullptr,
-                                    (int32_t*)info);
-  } else {
-    TK_HIP(hipMemsetAsync(ucnt, 0, sizeof(int32_t) * (T.nunits + 1), st));
+    {
+      ProfScope ps(ctx, st, "nblist_cellsort");
+      k_cellsort<<<T.ncells, 64, 0, st>>>(cstart, (int32_t*)tmp, (uint32_t*)u, (int32_t*)P.perm.p,
+                                          (int32_t*)P.scell.p, (uint4*)P.us.p, (int32_t*)info);
+    }
+    k_cand<<<ceil_div(T.nunits, 256), 256, 0, st>>>(T.nunits, units, cstart, (int64_t*)cand);
+    if ((s = scan_i64(ctx, st, (int64_t*)cand, (int64_t*)P.unit_off.p, T.nunits))) return s;
   }
-  if ((s = scan_i32(ctx, st, (int32_t*)ucnt, (int32_t*)P.unit_ptr.p, T.nunits))) return s;
-  int32_t* rp = row_ptr ? row_ptr : (int32_t*)rptr;
-  if (n > 0) {
-    if ((s = scan_i32(ctx, st, (int32_t*)rcnt, rp, n))) return s;
-  } else {
-    TK_HIP(hipMemsetAsync(rp, 0, sizeof(int32_t), st));
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (n > 0) {
+      {
+        ProfScope ps(ctx, st, "nblist_plan");
+        k_plan<<<T.nunits, 64, 0, st>>>(T.nunits, units, cstart, (uint4*)P.us.p, test, pstride,
+                                        (int64_t*)P.unit_off.p, (long)(P.codes.bytes / 4),
+                                        (uint32_t*)P.codes.p, (int32_t*)P.unit_cnt.p,
+                                        (int32_t*)P.slots.p, (int32_t*)info);
+      }
+      k_row_slots<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)P.perm.p, (int32_t*)P.scell.p,
+                                                     (int32_t*)T.nslot_d.p, pstride,
+                                                     (int32_t*)P.slots.p, (int32_t*)rcnt,
+                                                     (int32_t*)info);
+      if ((s = scan_i32(ctx, st, (int32_t*)rcnt, rp, n))) return s;
+    } else {
+      TK_HIP(hipMemsetAsync(P.unit_cnt.p, 0, sizeof(int32_t) * T.nunits, st));
+      TK_HIP(hipMemsetAsync(P.unit_off.p, 0, sizeof(int64_t) * (T.nunits + 1), st));
+      TK_HIP(hipMemsetAsync(rp, 0, sizeof(int32_t), st));
+    }
+    // one readback: status, max occupancy, max row, pairs, window overflow, list total
+    k_readback<<<1, 1, 0, st>>>((int32_t*)info, rp + n, (int64_t*)P.unit_off.p + T.nunits, hd);
+    TK_HIP(hipGetLastError());
+    TK_HIP(hipStreamSynchronize(st));
+    if (h[0] != 0) return h[0];
+    if (h[4] == 0) break;
+    if (attempt == 1) return TK_E_HIP;
+    // windows did not fit: grow to the exact size and enumerate again
+    const int64_t need = *(int64_t*)(h + 8);
+    if ((s = ensure(P.codes, sizeof(uint32_t) * (size_t)need))) return s;
+    TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
   }
-  // one readback: status, max cell occupancy, max row, plan total, list total
-  int32_t* h;
-  if ((s = pinned(ctx, 64, (void**)&h))) return s;
-  TK_HIP(hipMemcpyAsync(h, info, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st));
-  TK_HIP(hipMemcpyAsync(h + 4, (int32_t*)P.unit_ptr.p + T.nunits, sizeof(int32_t),
-                        hipMemcpyDeviceToHost, st));
-  TK_HIP(hipMemcpyAsync(h + 5, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  TK_HIP(hipStreamSynchronize(st));
-  if (h[0] != 0) return h[0];
-  int64_t plan_pairs = h[4], list_pairs = h[5];
+  const int64_t list_pairs = h[5];
   *npairs_out = list_pairs;
-  if (plan_pairs != list_pairs) {
-    std::fprintf(stderr, "libtk: plan/list pair count mismatch %lld vs %lld\n",
-                 (long long)plan_pairs, (long long)list_pairs);
+  if (list_pairs != (int64_t)h[3]) {
+    std::fprintf(stderr, "libtk: plan/list pair count mismatch %d vs %d\n", h[3], h[5]);
     return TK_E_HIP;
   }
-  if (row_ptr && list_pairs > cap) return TK_E_CAPACITY;
-  if ((s = ensure(P.codes, sizeof(uint32_t) * (plan_pairs > 0 ? plan_pairs : 1)))) return s;
-  if (n > 0) {
-    k_plan<true><<<T.nunits, 64, 0, st>>>(T.nunits, (Unit*)P.units.p, cstart, (uint4*)P.us.p, rq2,
-                                          nullptr, (int32_t*)P.unit_ptr.p, (uint32_t*)P.codes.p);
-    if (row_ptr && list_pairs > 0) {
-      int max_row = h[2];
-      int nb = max_row < kBuckets ? max_row : kBuckets;
-      size_t lds = sizeof(int) * (2 * (size_t)max_row + 2 * (size_t)nb);
-      if (lds > 160 * 1024) return TK_E_CAPACITY;
-      k_rows<true><<<n, 64, lds, st>>>(n, (int32_t*)cell, (uint32_t*)u, (int32_t*)P.nbr.p, cstart,
-                                       (uint4*)P.us.p, rq2, nullptr, rp, col, (int32_t*)info);
+  const int max_row = h[2];
+  if (want_csr) {
+    if (list_pairs > cap) return TK_E_CAPACITY;
+    const int nb = max_row < kBuckets ? max_row : kBuckets;
+    const size_t lds = sizeof(int) * (2 * (size_t)max_row + 2 * (size_t)nb);
+    if (lds > kMaxLds) return TK_E_CAPACITY;
+    if (n > 0 && list_pairs > 0) {
+      {
+        ProfScope ps(ctx, st, "nblist_csr_fill");
+        k_csr_fill<<<T.nunits, 64, 0, st>>>(units, cstart, (int32_t*)P.perm.p, pstride,
+                                            (int64_t*)P.unit_off.p, (int32_t*)P.unit_cnt.p,
+                                            (uint32_t*)P.codes.p, (int32_t*)P.slots.p, rp, col);
+      }
+      {
+        ProfScope ps(ctx, st, "nblist_rowsort");
+        k_rowsort<<<n, 64, lds, st>>>(n, rp, col, max_row);
+      }
     }
   }
   TK_HIP(hipGetLastError());
@@ -353,8 +479,10 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
   P.ncells = T.ncells;
   P.nunits = T.nunits;
   P.max_occ = h[1];
-  P.max_row = h[2];
+  P.max_row = max_row;
   P.npairs = list_pairs;
+  P.units_p = units;
+  P.nslot_p = (const int32_t*)T.nslot_d.p;
   return TK_OK;
 }
 

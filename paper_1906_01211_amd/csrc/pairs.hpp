@@ -52,17 +52,22 @@ __global__ __launch_bounds__(64) void k_units(PlanView pv, Ph ph, double* __rest
   const int hs = pv.cell_start[un.h], nh = pv.cell_start[un.h + 1] - hs;
   const int ks = pv.cell_start[un.k], nk = pv.cell_start[un.k + 1] - ks;
   const int cap = pv.max_occ;
+  ph.prologue(lane);
   double* LH = lds;
   double* LK = LH + Ph::NF * cap;
   double* AH = LK + Ph::NF * cap;
   double* AK = AH + Ph::NA * cap;
   for (int t = lane; t < nh; t += 64) {
-    ph.stage(LH, cap, t, hs + t, pv.perm);
+#pragma unroll
+    for (int f = 0; f < Ph::NG; ++f) LH[f * cap + t] = ph.sorted[f * ph.gstride + hs + t];
+    ph.stage_dyn(LH, cap, t, hs + t);
 #pragma unroll
     for (int f = 0; f < Ph::NA; ++f) AH[f * cap + t] = 0.0;
   }
   for (int t = lane; t < nk; t += 64) {
-    ph.stage(LK, cap, t, ks + t, pv.perm);
+#pragma unroll
+    for (int f = 0; f < Ph::NG; ++f) LK[f * cap + t] = ph.sorted[f * ph.gstride + ks + t];
+    ph.stage_dyn(LK, cap, t, ks + t);
 #pragma unroll
     for (int f = 0; f < Ph::NA; ++f) AK[f * cap + t] = 0.0;
   }
@@ -70,8 +75,8 @@ __global__ __launch_bounds__(64) void k_units(PlanView pv, Ph ph, double* __rest
   double sc[Ph::NS > 0 ? Ph::NS : 1];
 #pragma unroll
   for (int k = 0; k < (Ph::NS > 0 ? Ph::NS : 1); ++k) sc[k] = 0.0;
-  const int p0 = pv.unit_ptr[u], p1 = pv.unit_ptr[u + 1];
-  for (int p = p0 + lane; p < p1; p += 64) {
+  const long p0 = pv.unit_off[u], p1 = p0 + pv.unit_cnt[u];
+  for (long p = p0 + lane; p < p1; p += 64) {
     const uint32_t code = pv.codes[p];
     ph.pair(LH, LK, cap, (int)(code & 0xffffu), (int)(code >> 16), AH, AK, sc);
   }
@@ -93,6 +98,19 @@ __global__ __launch_bounds__(64) void k_units(PlanView pv, Ph ph, double* __rest
   }
 }
 
+// Per-call gather of a functor's static per-atom fields into sorted SoA order
+// (so tile staging reads contiguous, coalesced rows).
+template <class Ph>
+__global__ __launch_bounds__(256) void k_gather(PlanView pv, Ph ph, double* __restrict__ out,
+                                                long gstride) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= pv.n) return;
+  double g[Ph::NG];
+  ph.gather(pv.perm[s], g);
+#pragma unroll
+  for (int f = 0; f < Ph::NG; ++f) out[f * gstride + s] = g[f];
+}
+
 // Sum each atom's partial slots (fixed order) and hand the NA sums to Epi.
 template <int NA, class Epi>
 __global__ __launch_bounds__(256) void k_reduce(PlanView pv, const double* __restrict__ partial,
@@ -103,29 +121,30 @@ __global__ __launch_bounds__(256) void k_reduce(PlanView pv, const double* __res
   double acc[NA];
 #pragma unroll
   for (int f = 0; f < NA; ++f) acc[f] = 0.0;
-  for (int k = 0; k < ns; ++k)
 #pragma unroll
-    for (int f = 0; f < NA; ++f) acc[f] += partial[((long)k * NA + f) * pstride + s];
+  for (int k = 0; k < kMaxSlots; ++k)   // unrolled: all slot loads in flight at once
+    if (k < ns)
+#pragma unroll
+      for (int f = 0; f < NA; ++f) acc[f] += partial[((long)k * NA + f) * pstride + s];
   epi(s, pv.perm[s], acc);
 }
 
-// Sum per-unit scalar records in a fixed order: out[k] = sum_u uscal[u][k].
+// Sum per-unit scalar records in a fixed order: out[k] = sum_u uscal[u][k];
+// one block per scalar.
 template <int NS>
 __global__ __launch_bounds__(256) void k_sum_units(const double* __restrict__ uscal, int nunits,
                                                    double* __restrict__ out) {
   __shared__ double sh[256];
-  for (int k = 0; k < NS; ++k) {
-    double v = 0.0;
-    for (int u = threadIdx.x; u < nunits; u += 256) v += uscal[(long)u * NS + k];
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = sh[0];
+  const int k = blockIdx.x;
+  double v = 0.0;
+  for (int u = threadIdx.x; u < nunits; u += 256) v += uscal[(long)u * NS + k];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
+  if (threadIdx.x == 0) out[k] = sh[0];
 }
 
 template <class Ph>

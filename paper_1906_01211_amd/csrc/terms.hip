@@ -46,6 +46,7 @@ tk_status launch_tmat(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_syste
   ph.thole = thole;
   ph.g.set(sys->box, cutoff, beta);
   ph.molid = sys->molid;
+  ph.perm_ = (const int32_t*)P.perm.p;
   EpiMutual epi{out, mu, polarity, ph.g.cself, include_diag};
   return run_term(ctx, st, P, ph, epi, nullptr);
 }

@@ -12,19 +12,13 @@
 
 #include <type_traits>
 
+#include "math.hpp"
 #include "pairs.hpp"
 
 namespace tk {
 
-template <class R> __device__ __forceinline__ R t_exp(R x);
-template <> __device__ __forceinline__ double t_exp<double>(double x) { return exp(x); }
-template <> __device__ __forceinline__ float t_exp<float>(float x) { return __expf(x); }
-template <class R> __device__ __forceinline__ R t_erfc(R x);
-template <> __device__ __forceinline__ double t_erfc<double>(double x) { return erfc(x); }
-template <> __device__ __forceinline__ float t_erfc<float>(float x) { return erfcf(x); }
-template <class R> __device__ __forceinline__ R t_sqrt(R x);
-template <> __device__ __forceinline__ double t_sqrt<double>(double x) { return sqrt(x); }
-template <> __device__ __forceinline__ float t_sqrt<float>(float x) { return sqrtf(x); }
+template <class R>
+inline const char* prec_tag() { return std::is_same<R, double>::value ? "_fp64" : "_fp32"; }
 
 // Geometry and Ewald constants shared by the electrostatic terms.
 struct Geom {
@@ -42,8 +36,9 @@ struct Geom {
   }
 };
 
-// B_0..B_N (Ewald-screened) and, if wanted, R_0..R_N (bare) at distance r.
+// B_0..B_N (Ewald-screened) and R_0..R_N (bare) at distance r:
 //   B0 = erfc(beta r)/r,  Bn = [(2n-1) B(n-1) + (2 beta^2)^n exp(-beta^2 r^2)/(beta sqrt(pi))]/r^2
+// erfc(beta r) = exp(-beta^2 r^2) erfcx(beta r): one exponential serves both.
 template <class R, int N>
 __device__ __forceinline__ void radial(const Geom& g, R r, R rinv, R* B, R* Rb) {
   const R rinv2 = rinv * rinv;
@@ -55,9 +50,11 @@ __device__ __forceinline__ void radial(const Geom& g, R r, R rinv, R* B, R* Rb) 
     for (int n = 0; n <= N; ++n) B[n] = Rb[n];
     return;
   }
-  const R beta = R(g.beta), b2 = R(2.0 * g.beta2);
-  const R ex = t_exp<R>(-R(g.beta2) * r * r) * R(g.bsp_inv);
-  B[0] = t_erfc<R>(beta * r) * rinv;
+  const R y = R(g.beta) * r;
+  const R e = exp_neg(-y * y);
+  const R b2 = R(2.0 * g.beta2);
+  const R ex = e * R(g.bsp_inv);
+  B[0] = e * erfcx(y) * rinv;
   R pw = b2;
 #pragma unroll
   for (int n = 1; n <= N; ++n) {
@@ -67,21 +64,22 @@ __device__ __forceinline__ void radial(const Geom& g, R r, R rinv, R* B, R* Rb) 
 }
 
 // g_n = B_n - w_n R_n; for R = float and same-molecule pairs the radial
-// functions come from FP64.
+// functions come from FP64 (B carries the FP64 difference B - R, Rb is zero).
 template <class R, int N>
 __device__ __forceinline__ void radial_pair(const Geom& g, double r2, bool same_mol, R* B, R* Rb) {
   if (std::is_same<R, float>::value && same_mol) {
-    double r = sqrt(r2), ri = 1.0 / r, Bd[N + 1], Rd[N + 1];
+    const double ri = rsqrt_r(r2), r = r2 * ri;
+    double Bd[N + 1], Rd[N + 1];
     radial<double, N>(g, r, ri, Bd, Rd);
 #pragma unroll
     for (int n = 0; n <= N; ++n) {
-      B[n] = R(Bd[n] - Rd[n]);   // the FP64 difference, carried in B; Rb zero
+      B[n] = R(Bd[n] - Rd[n]);
       Rb[n] = R(0);
     }
     return;
   }
-  R r = t_sqrt<R>(R(r2));
-  R rinv = R(1) / r;
+  const R rinv = rsqrt_r(R(r2));
+  const R r = R(r2) * rinv;
   radial<R, N>(g, r, rinv, B, Rb);
 }
 
@@ -96,7 +94,7 @@ __device__ __forceinline__ void thole_damp(R r, R isa_i, R isa_j, R ti, R tj, R&
   }
   const R a = ti < tj ? ti : tj;
   const R x = a * r * r * r * pr;
-  const R e = t_exp<R>(-x);
+  const R e = exp_neg(-x);
   l3 = R(1) - e;
   l5 = R(1) - (R(1) + x) * e;
   l7 = R(1) - (R(1) + x + R(0.6) * x * x) * e;
@@ -110,18 +108,24 @@ __device__ __forceinline__ double inv_sqrt_alpha(double a) { return a > 0.0 ? 1.
 template <class R>
 struct EmpolePh {
   static constexpr int NF = 14, NA = 3, NS = 11;
+  static constexpr const char* kName = "empole";
+  static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
+  __device__ void prologue(int lane) const { erfcx_stage<R>(lane, 64); }
   const double* xyz;
   const double* mpole;
   const int32_t* molid;
   Geom g;
-  __device__ void stage(double* L, int cap, int t, int s, const int32_t* perm) const {
-    const int i = perm[s];
+    static constexpr int NG = 14;   // fields gathered once per call (sorted SoA)
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void stage_dyn(double*, int, int, int) const {}
+  __device__ void gather(int i, double* g) const {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) L[c * cap + t] = xyz[3 * i + c];
+    for (int c = 0; c < 3; ++c) g[c] = xyz[3 * i + c];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) L[(3 + k) * cap + t] = mpole[10 * i + k];
-    L[13 * cap + t] = (double)molid[i];
+    for (int k = 0; k < 10; ++k) g[3 + k] = mpole[10 * i + k];
+    g[13] = (double)molid[i];
   }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
                        double* AK, double* sc) const {
@@ -195,17 +199,23 @@ struct EmpolePh {
 template <class R>
 struct ChargePh {
   static constexpr int NF = 5, NA = 3, NS = 11;
+  static constexpr const char* kName = "charge";
+  static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
+  __device__ void prologue(int lane) const { erfcx_stage<R>(lane, 64); }
   const double* xyz;
   const double* q;
   const int32_t* molid;
   Geom g;
-  __device__ void stage(double* L, int cap, int t, int s, const int32_t* perm) const {
-    const int i = perm[s];
+    static constexpr int NG = 5;   // fields gathered once per call (sorted SoA)
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void stage_dyn(double*, int, int, int) const {}
+  __device__ void gather(int i, double* g) const {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) L[c * cap + t] = xyz[3 * i + c];
-    L[3 * cap + t] = q[i];
-    L[4 * cap + t] = (double)molid[i];
+    for (int c = 0; c < 3; ++c) g[c] = xyz[3 * i + c];
+    g[3] = q[i];
+    g[4] = (double)molid[i];
   }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
                        double* AK, double* sc) const {
@@ -237,22 +247,28 @@ struct ChargePh {
 template <class R>
 struct EfieldPh {
   static constexpr int NF = 16, NA = 3, NS = 0;
+  static constexpr const char* kName = "efield";
+  static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
+  __device__ void prologue(int lane) const { erfcx_stage<R>(lane, 64); }
   const double* xyz;
   const double* mpole;
   const int32_t* molid;
   const double* polarity;
   const double* thole;
   Geom g;
-  __device__ void stage(double* L, int cap, int t, int s, const int32_t* perm) const {
-    const int i = perm[s];
+    static constexpr int NG = 16;   // fields gathered once per call (sorted SoA)
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void stage_dyn(double*, int, int, int) const {}
+  __device__ void gather(int i, double* g) const {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) L[c * cap + t] = xyz[3 * i + c];
+    for (int c = 0; c < 3; ++c) g[c] = xyz[3 * i + c];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) L[(3 + k) * cap + t] = mpole[10 * i + k];
-    L[13 * cap + t] = (double)molid[i];
-    L[14 * cap + t] = inv_sqrt_alpha(polarity[i]);
-    L[15 * cap + t] = thole[i];
+    for (int k = 0; k < 10; ++k) g[3 + k] = mpole[10 * i + k];
+    g[13] = (double)molid[i];
+    g[14] = inv_sqrt_alpha(polarity[i]);
+    g[15] = thole[i];
   }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
                        double* AK, double*) const {
@@ -269,7 +285,7 @@ struct EfieldPh {
       g3 = B[3] - Rb[3];
     } else {
       R l3, l5, l7;
-      const R r = t_sqrt<R>(R(r2));
+      const R r = R(r2) * rsqrt_r(R(r2));
       thole_damp<R>(r, R(LH[14 * cap + a]), R(LK[14 * cap + b]), R(LH[15 * cap + a]),
                R(LK[15 * cap + b]), l3, l5, l7);
       g1 = B[1] - (R(1) - l3) * Rb[1];
@@ -308,12 +324,15 @@ struct EfieldPh {
 };
 
 // Mutual induced-dipole field: E_i += T2 mu_j, E_j += T2 mu_i (all pairs).
-// Fields: x y z | mu(3) | isa | thole | molid
+// Fields: x y z | isa | thole | molid | mu(3)
 template <class R>
 struct TmatPh {
   static constexpr int NF = 9, NA = 3, NS = 0;
+  static constexpr const char* kName = "tmat";
+  static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   const int* done = nullptr;   // solver flag: skip when set
   __device__ bool skip() const { return done && *done; }
+  __device__ void prologue(int lane) const { erfcx_stage<R>(lane, 64); }
   const double* xyz;
   const double* mu;
   int mu_sorted;   // mu indexed by sorted position (solver-internal vectors)
@@ -321,35 +340,46 @@ struct TmatPh {
   const double* thole;
   const int32_t* molid;
   Geom g;
-  __device__ void stage(double* L, int cap, int t, int s, const int32_t* perm) const {
-    const int i = perm[s];
-    const int m = mu_sorted ? s : i;
+  const double* zdir = nullptr;      // solver: stage p = z + beta * p (search direction)
+  const double* beta_dir = nullptr;  // device scalar beta
+  static constexpr int NG = 6;       // x y z isa thole molid, gathered once per call
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void gather(int i, double* g) const {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      L[c * cap + t] = xyz[3 * i + c];
-      L[(3 + c) * cap + t] = mu[3 * m + c];
-    }
-    L[6 * cap + t] = inv_sqrt_alpha(polarity[i]);
-    L[7 * cap + t] = thole[i];
-    L[8 * cap + t] = molid ? (double)molid[i] : (double)i;
+    for (int c = 0; c < 3; ++c) g[c] = xyz[3 * i + c];
+    g[3] = inv_sqrt_alpha(polarity[i]);
+    g[4] = thole[i];
+    g[5] = molid ? (double)molid[i] : (double)i;
   }
+  // dipoles (or the solver's search direction) are read per call
+  __device__ void stage_dyn(double* L, int cap, int t, int s) const {
+    const int32_t* pm = perm_;
+    const int m = mu_sorted ? s : pm[s];
+    const double bd = zdir ? *beta_dir : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      L[(6 + c) * cap + t] = zdir ? fma(bd, mu[3 * m + c], zdir[3 * m + c]) : mu[3 * m + c];
+  }
+  const int32_t* perm_ = nullptr;
+
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
                        double* AK, double*) const {
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
     if (!(r2 <= g.rc2)) return;
-    const bool same = LH[8 * cap + a] == LK[8 * cap + b];
+    const bool same = LH[5 * cap + a] == LK[5 * cap + b];
     R B[3], Rb[3];
     radial_pair<R, 2>(g, r2, same, B, Rb);
     R l3, l5, l7;
-    const R r = t_sqrt<R>(R(r2));
-    thole_damp<R>(r, R(LH[6 * cap + a]), R(LK[6 * cap + b]), R(LH[7 * cap + a]), R(LK[7 * cap + b]),
+    const R r = R(r2) * rsqrt_r(R(r2));
+    thole_damp<R>(r, R(LH[3 * cap + a]), R(LK[3 * cap + b]), R(LH[4 * cap + a]), R(LK[4 * cap + b]),
              l3, l5, l7);
     // g1 = B1 - (1 - l3) R1, g2 = B2 - (1 - l5) R2 (for FP32 same-molecule pairs
     // B carries the FP64 difference B - R and the bare part is re-added with l)
     R g1, g2;
     if (std::is_same<R, float>::value && same) {
-      const double rd = sqrt(r2), ri = 1.0 / rd;
+      const double ri = rsqrt_r(r2);
       const double R1 = ri * ri * ri, R2 = 3.0 * R1 * ri * ri;
       g1 = R((double)B[1] + (double)l3 * R1);
       g2 = R((double)B[2] + (double)l5 * R2);
@@ -358,8 +388,8 @@ struct TmatPh {
       g2 = B[2] - (R(1) - l5) * Rb[2];
     }
     const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
-    const R ui[3] = {R(LH[3 * cap + a]), R(LH[4 * cap + a]), R(LH[5 * cap + a])};
-    const R uj[3] = {R(LK[3 * cap + b]), R(LK[4 * cap + b]), R(LK[5 * cap + b])};
+    const R ui[3] = {R(LH[6 * cap + a]), R(LH[7 * cap + a]), R(LH[8 * cap + a])};
+    const R uj[3] = {R(LK[6 * cap + b]), R(LK[7 * cap + b]), R(LK[8 * cap + b])};
     const R di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
     const R dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
     const R si = dj * g2, sj = di * g2;
@@ -376,7 +406,10 @@ struct TmatPh {
 template <class R>
 struct VdwPh {
   static constexpr int NF = 6, NA = 3, NS = 10;
+  static constexpr const char* kName = "vdw";
+  static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
+  __device__ void prologue(int) const {}
   const double* xyz;
   const double* rad;
   const double* eps;
@@ -399,13 +432,16 @@ struct VdwPh {
     dhal = d;
     ghal = gm;
   }
-  __device__ void stage(double* L, int cap, int t, int s, const int32_t* perm) const {
-    const int i = perm[s];
+    static constexpr int NG = 6;   // fields gathered once per call (sorted SoA)
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void stage_dyn(double*, int, int, int) const {}
+  __device__ void gather(int i, double* g) const {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) L[c * cap + t] = xyz[3 * i + c];
-    L[3 * cap + t] = rad[i];
-    L[4 * cap + t] = sqrt(eps[i]);
-    L[5 * cap + t] = (double)molid[i];
+    for (int c = 0; c < 3; ++c) g[c] = xyz[3 * i + c];
+    g[3] = rad[i];
+    g[4] = sqrt(eps[i]);
+    g[5] = (double)molid[i];
   }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
                        double* AK, double* sc) const {
@@ -413,7 +449,7 @@ struct VdwPh {
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, box, inv_box, dd);
     if (!(r2 <= rc2)) return;
-    const R r = t_sqrt<R>(R(r2));
+    const R r = sqrt_r(R(r2));
     const R ri = R(LH[3 * cap + a]), rj = R(LK[3 * cap + b]);
     const R si = R(LH[4 * cap + a]), sj = R(LK[4 * cap + b]);
     R e, dedr;
@@ -516,10 +552,22 @@ tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, con
   PlanView pv = P.view();
   const size_t lds = unit_lds_bytes<Ph>(P);
   if (lds > kMaxLds) return TK_E_CAPACITY;
-  k_units<Ph><<<P.nunits, 64, lds, st>>>(pv, ph, (double*)partial, pstride, (double*)uscal);
-  k_reduce<Ph::NA, Epi><<<ceil_div(P.n, 256), 256, 0, st>>>(pv, (double*)partial, pstride, epi);
+  void* gathered;
+  if ((s = scratch(ctx, "gathered", sizeof(double) * Ph::NG * pstride, &gathered))) return s;
+  Ph phg = ph;
+  phg.sorted = (const double*)gathered;
+  phg.gstride = pstride;
+  k_gather<Ph><<<ceil_div(P.n, 256), 256, 0, st>>>(pv, phg, (double*)gathered, pstride);
+  {
+    ProfScope ps(ctx, st, std::string("units_") + Ph::kName + Ph::kTag);
+    k_units<Ph><<<P.nunits, 64, lds, st>>>(pv, phg, (double*)partial, pstride, (double*)uscal);
+  }
+  {
+    ProfScope ps(ctx, st, "reduce_atoms");
+    k_reduce<Ph::NA, Epi><<<ceil_div(P.n, 256), 256, 0, st>>>(pv, (double*)partial, pstride, epi);
+  }
   if (Ph::NS > 0 && sums_out)
-    k_sum_units<(Ph::NS > 0 ? Ph::NS : 1)><<<1, 256, 0, st>>>((double*)uscal, P.nunits, sums_out);
+    k_sum_units<(Ph::NS > 0 ? Ph::NS : 1)><<<(Ph::NS > 0 ? Ph::NS : 1), 256, 0, st>>>((double*)uscal, P.nunits, sums_out);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }

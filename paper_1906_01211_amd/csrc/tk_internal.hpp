@@ -44,7 +44,8 @@ struct PlanView {
   const int32_t* cell_start;  // [ncells+1]
   const int32_t* cell_nslot;  // [ncells] number of unit roles of the cell
   const Unit* units;          // [nunits]
-  const int32_t* unit_ptr;    // [nunits+1] offsets into codes
+  const int64_t* unit_off;    // [nunits+1] start of each unit's window in codes
+  const int32_t* unit_cnt;    // [nunits] listed pairs of the unit (window prefix)
   const uint32_t* codes;      // pair codes: a | b << 16 (local indices in H, K)
 };
 
@@ -59,13 +60,16 @@ struct Plan {
   double box = 0.0, cutoff = 0.0;
   int32_t nc = 0, ncells = 0, nunits = 0, max_occ = 0, max_row = 0;
   int64_t npairs = 0;
-  DevBuf perm, scell, cell_start, cell_nslot, units, unit_ptr, codes, us, nbr;
+  DevBuf perm, scell, cell_start, unit_off, unit_cnt, codes, us, slots;
+  const Unit* units_p = nullptr;       // device cell tables shared by plans with the same nc
+  const int32_t* nslot_p = nullptr;
   PlanView view() const {
     PlanView v;
     v.n = n; v.ncells = ncells; v.nunits = nunits; v.max_occ = max_occ;
     v.perm = (const int32_t*)perm.p; v.scell = (const int32_t*)scell.p;
-    v.cell_start = (const int32_t*)cell_start.p; v.cell_nslot = (const int32_t*)cell_nslot.p;
-    v.units = (const Unit*)units.p; v.unit_ptr = (const int32_t*)unit_ptr.p;
+    v.cell_start = (const int32_t*)cell_start.p; v.cell_nslot = nslot_p;
+    v.units = units_p; v.unit_off = (const int64_t*)unit_off.p;
+    v.unit_cnt = (const int32_t*)unit_cnt.p;
     v.codes = (const uint32_t*)codes.p;
     return v;
   }
@@ -76,16 +80,31 @@ struct CellTables {   // host-built tables for one cells-per-edge value
   std::vector<Unit> units;
   std::vector<int32_t> nslot;     // per cell
   std::vector<int32_t> nbr;       // per cell: count, then up to 27 neighbour cells
+  bool uploaded = false;
+  DevBuf units_d, nslot_d;        // device copies
 };
 
 }  // namespace tk
 
+namespace tk {
+struct ProfEntry {
+  int64_t launches = 0;
+  double ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+}  // namespace tk
+
 struct tk_ctx {
   int device = 0;
+  bool prof_on = false;
+  std::string prof_only;
+  std::map<std::string, tk::ProfEntry> prof;
+  std::vector<hipEvent_t> event_pool;
   tk::Plan plans[TK_MAX_PLANS];
   std::map<std::string, tk::DevBuf> scratch;   // grow-only named device buffers
   std::map<int, tk::CellTables> tables;        // by cells per edge
-  void* pinned = nullptr;                      // host readback buffer
+  void* pinned = nullptr;                      // host readback buffer (device-writable)
+  void* pinned_dev = nullptr;                  // its device address
   size_t pinned_bytes = 0;
 };
 
@@ -102,11 +121,13 @@ tk_status hip_status(hipError_t e, const char* what);
 // reuse.  Never freed before tk_destroy.
 tk_status ensure(DevBuf& b, size_t bytes);
 tk_status scratch(tk_ctx* ctx, const char* name, size_t bytes, void** out);
-tk_status pinned(tk_ctx* ctx, size_t bytes, void** out);
-const CellTables& cell_tables(tk_ctx* ctx, int nc);
+// Pinned host memory that kernels write directly (zero-copy readback).
+tk_status pinned(tk_ctx* ctx, size_t bytes, void** out, void** dev = nullptr);
+CellTables& cell_tables(tk_ctx* ctx, int nc);
 
 // Exclusive scan of int32 counts: out[0..len] with out[len] = total.
 tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len);
+tk_status scan_i64(tk_ctx* ctx, hipStream_t st, const int64_t* in, int64_t* out, long len);
 
 // Checks shared by the pair entry points.
 tk_status check_system(const tk_system* sys);
@@ -114,5 +135,15 @@ tk_status get_plan(tk_ctx* ctx, const tk_system* sys, const tk_nblist* list, dou
                    const Plan** out);
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Brackets one kernel launch with events when kernel timing is on.
+struct ProfScope {
+  tk_ctx* ctx;
+  hipStream_t st;
+  ProfEntry* e = nullptr;
+  hipEvent_t a = nullptr;
+  ProfScope(tk_ctx* c, hipStream_t s, const std::string& name);
+  ~ProfScope();
+};
 
 }  // namespace tk

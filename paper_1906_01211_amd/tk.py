@@ -62,6 +62,9 @@ _SIGS = {
                         _i32, C.c_int, _vp, _vp, C.POINTER(PcgInfo)],
     "tk_evdw": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), C.c_int, _vp, _vp, _d, _d, _d, _d,
                 C.c_int, _vp, _vp, _vp],
+    "tk_profile_enable": [_vp, C.c_int, C.c_char_p],
+    "tk_profile_read": [_vp, _i32, C.c_char_p, _i32, C.POINTER(_i64), C.POINTER(_d)],
+    "tk_profile_reset": [_vp],
 }
 
 
@@ -124,6 +127,24 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # -- kernel timing -----------------------------------------------------------
+    def profile(self, on=True, only=None):
+        """Time kernel launches with HIP events on their stream (optionally one kernel)."""
+        if on:
+            _check(load().tk_profile_reset(self._h), "tk_profile_reset")
+        _check(load().tk_profile_enable(self._h, int(on), None if only is None else only.encode()),
+               "tk_profile_enable")
+
+    def profile_read(self):
+        out = {}
+        buf = C.create_string_buffer(128)
+        n, ms = C.c_int64(0), C.c_double(0.0)
+        k = 0
+        while load().tk_profile_read(self._h, k, buf, 128, C.byref(n), C.byref(ms)) == OK:
+            out[buf.value.decode()] = {"launches": int(n.value), "ms": float(ms.value)}
+            k += 1
+        return out
 
     # -- systems and lists ---------------------------------------------------
     def system(self, xyz, box, molid):
