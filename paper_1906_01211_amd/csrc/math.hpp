@@ -32,14 +32,25 @@ __device__ __forceinline__ float* erfcx_lds32() {
   return t;
 }
 
+// The LDS copy is coefficient-major (t[k * 32 + piece]): lanes on different
+// pieces read different banks.
+// The FP32 kernels also stage the FP64 table: their same-molecule pairs take
+// the FP64 path.
 template <class R>
 __device__ __forceinline__ void erfcx_stage(int lane, int nthreads) {
-  if (sizeof(R) == 8) {
+  {
     double* t = erfcx_lds64();
-    for (int k = lane; k < kErfcxPieces * (kErfcxTab64Deg + 1); k += nthreads) t[k] = kErfcxTab64[k];
-  } else {
+    for (int e = lane; e < kErfcxPieces * (kErfcxTab64Deg + 1); e += nthreads) {
+      const int j = e / (kErfcxTab64Deg + 1), k = e - j * (kErfcxTab64Deg + 1);
+      t[k * kErfcxPieces + j] = kErfcxTab64[e];
+    }
+  }
+  if (sizeof(R) == 4) {
     float* t = erfcx_lds32();
-    for (int k = lane; k < kErfcxPieces * (kErfcxTab32Deg + 1); k += nthreads) t[k] = kErfcxTab32[k];
+    for (int e = lane; e < kErfcxPieces * (kErfcxTab32Deg + 1); e += nthreads) {
+      const int j = e / (kErfcxTab32Deg + 1), k = e - j * (kErfcxTab32Deg + 1);
+      t[k * kErfcxPieces + j] = kErfcxTab32[e];
+    }
   }
 }
 
@@ -68,15 +79,25 @@ __device__ __forceinline__ double exp_neg(double x) {
 
 __device__ __forceinline__ float exp_neg(float x) { return __expf(x); }
 
+// FP32 exp of an FP64 argument x <= 0: the reduction x = k ln2 + r runs in
+// FP64 (so the rounding of a large argument is not amplified), 2^r in FP32.
+__device__ __forceinline__ float exp_neg_f32_of(double x) {
+  x = fmax(x, -87.0);
+  const double k = rint(x * 1.4426950408889634074);
+  double r = fma(-k, 0x1.62e42fee00000p-1, x);
+  r = fma(-k, 1.9082149292705877e-10, r);
+  return __expf((float)r) * __int_as_float(((int)k + 127) << 23);
+}
+
 __device__ __forceinline__ double erfcx(double y) {
   const double* t = erfcx_lds64();
   const double s = fmin(fmax(y, 0.0) * 4.0, 31.999999);
   const int j = (int)s;
   const double x = 2.0 * (s - (double)j) - 1.0;   // = 8 (y - y_mid)
-  const double* c = t + j * (kErfcxTab64Deg + 1);
-  double p = c[kErfcxTab64Deg];
+  const double* c = t + j;
+  double p = c[kErfcxTab64Deg * kErfcxPieces];
 #pragma unroll
-  for (int k = kErfcxTab64Deg - 1; k >= 0; --k) p = fma(p, x, c[k]);
+  for (int k = kErfcxTab64Deg - 1; k >= 0; --k) p = fma(p, x, c[k * kErfcxPieces]);
   return p;
 }
 
@@ -85,10 +106,10 @@ __device__ __forceinline__ float erfcx(float y) {
   const float s = fminf(fmaxf(y, 0.0f) * 4.0f, 31.99998f);
   const int j = (int)s;
   const float x = 2.0f * (s - (float)j) - 1.0f;
-  const float* c = t + j * (kErfcxTab32Deg + 1);
-  float p = c[kErfcxTab32Deg];
+  const float* c = t + j;
+  float p = c[kErfcxTab32Deg * kErfcxPieces];
 #pragma unroll
-  for (int k = kErfcxTab32Deg - 1; k >= 0; --k) p = fmaf(p, x, c[k]);
+  for (int k = kErfcxTab32Deg - 1; k >= 0; --k) p = fmaf(p, x, c[k * kErfcxPieces]);
   return p;
 }
 

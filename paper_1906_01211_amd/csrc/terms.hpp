@@ -40,7 +40,7 @@ struct Geom {
 //   B0 = erfc(beta r)/r,  Bn = [(2n-1) B(n-1) + (2 beta^2)^n exp(-beta^2 r^2)/(beta sqrt(pi))]/r^2
 // erfc(beta r) = exp(-beta^2 r^2) erfcx(beta r): one exponential serves both.
 template <class R, int N>
-__device__ __forceinline__ void radial(const Geom& g, R r, R rinv, R* B, R* Rb) {
+__device__ __forceinline__ void radial(const Geom& g, R r, R rinv, R* B, R* Rb, double r2d) {
   const R rinv2 = rinv * rinv;
   Rb[0] = rinv;
 #pragma unroll
@@ -51,7 +51,11 @@ __device__ __forceinline__ void radial(const Geom& g, R r, R rinv, R* B, R* Rb) 
     return;
   }
   const R y = R(g.beta) * r;
-  const R e = exp_neg(-y * y);
+  R e;
+  if (std::is_same<R, float>::value)
+    e = R(exp_neg_f32_of(-g.beta2 * r2d));   // argument -beta^2 r^2 kept in FP64
+  else
+    e = R(exp_neg((double)(-y * y)));
   const R b2 = R(2.0 * g.beta2);
   const R ex = e * R(g.bsp_inv);
   B[0] = e * erfcx(y) * rinv;
@@ -70,7 +74,7 @@ __device__ __forceinline__ void radial_pair(const Geom& g, double r2, bool same_
   if (std::is_same<R, float>::value && same_mol) {
     const double ri = rsqrt_r(r2), r = r2 * ri;
     double Bd[N + 1], Rd[N + 1];
-    radial<double, N>(g, r, ri, Bd, Rd);
+    radial<double, N>(g, r, ri, Bd, Rd, r2);
 #pragma unroll
     for (int n = 0; n <= N; ++n) {
       B[n] = R(Bd[n] - Rd[n]);
@@ -80,7 +84,7 @@ __device__ __forceinline__ void radial_pair(const Geom& g, double r2, bool same_
   }
   const R rinv = rsqrt_r(R(r2));
   const R r = R(r2) * rinv;
-  radial<R, N>(g, r, rinv, B, Rb);
+  radial<R, N>(g, r, rinv, B, Rb, r2);
 }
 
 // Thole factors l3, l5, l7 with x = a_ij r^3 isa_i isa_j, isa = 1/sqrt(alpha)
@@ -225,10 +229,20 @@ struct ChargePh {
     const bool excl = LH[4 * cap + a] == LK[4 * cap + b];
     R B[2], Rb[2];
     radial_pair<R, 1>(g, r2, excl, B, Rb);
-    const R g0 = excl ? B[0] - Rb[0] : B[0];
     const R g1 = excl ? B[1] - Rb[1] : B[1];
+    double g0;
+    if (std::is_same<R, float>::value && !excl) {
+      // the energy of a point-charge system is a large cancelling sum: its
+      // screened pair term is evaluated in FP64 even in the mixed form
+      double B0d[1], R0d[1];
+      const double ri = rsqrt_r(r2);
+      radial<double, 0>(g, r2 * ri, ri, B0d, R0d, r2);
+      g0 = B0d[0];
+    } else {
+      g0 = (double)(excl ? B[0] - Rb[0] : B[0]);
+    }
     const double qq = kCoulomb * LH[3 * cap + a] * LK[3 * cap + b];
-    const double en = qq * (double)g0;
+    const double en = qq * g0;
     const double f = -qq * (double)g1;
     sc[excl ? 1 : 0] += en;
 #pragma unroll
@@ -443,48 +457,63 @@ struct VdwPh {
     g[4] = sqrt(eps[i]);
     g[5] = (double)molid[i];
   }
+  // HAL / LJ pair energy and de/dr with the taper, in arithmetic type T
+  template <class T>
+  __device__ __forceinline__ void eval(double r2, T ri, T rj, T si, T sj, T& e, T& dedr,
+                                       T& rr) const {
+    const T r = sqrt_r(T(r2));
+    rr = r;
+    if (form == TK_VDW_HAL) {
+      const T ri2 = ri * ri, rj2 = rj * rj;
+      const T rv = (ri2 * ri + rj2 * rj) / (ri2 + rj2);
+      const T se = si + sj;
+      const T ep = se > T(0) ? T(4) * (si * si) * (sj * sj) / (se * se) : T(0);
+      const T rv2 = rv * rv, rv7 = rv2 * rv2 * rv2 * rv;
+      const T r6 = T(r2) * T(r2) * T(r2), rik7 = r6 * r;
+      const T invrho = T(1) / (rik7 + T(ghal) * rv7);
+      const T invtmp = T(1) / (r + T(dhal) * rv);
+      const T tb = T(1.0 + dhal) * rv * invtmp;
+      const T tb2 = tb * tb, t7 = tb2 * tb2 * tb2 * tb;
+      const T w = T(1.0 + ghal) * rv7 * invrho;
+      e = ep * t7 * (w - T(2));
+      dedr = ep * (T(-7) * t7 * invtmp * (w - T(2)) - T(7) * t7 * r6 * w * invrho);
+    } else {
+      const T sg = T(0.5) * (ri + rj);
+      const T ep = si * sj;
+      const T q = sg * sg / T(r2);
+      const T sr6 = q * q * q;
+      e = T(4) * ep * (sr6 * sr6 - sr6);
+      dedr = T(4) * ep * (T(-12) * sr6 * sr6 + T(6) * sr6) / r;
+    }
+    if ((double)r > ron) {
+      const T x = (r - T(ron)) * T(tw_inv);
+      const T x2 = x * x, x3 = x2 * x;
+      const T S = T(1) - T(10) * x3 + T(15) * x3 * x - T(6) * x3 * x2;
+      const T dS = (T(-30) * x2 + T(60) * x3 - T(30) * x3 * x) * T(tw_inv);
+      dedr = dedr * S + e * dS;
+      e *= S;
+    }
+  }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
                        double* AK, double* sc) const {
     if (LH[5 * cap + a] == LK[5 * cap + b]) return;
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, box, inv_box, dd);
     if (!(r2 <= rc2)) return;
-    const R r = sqrt_r(R(r2));
-    const R ri = R(LH[3 * cap + a]), rj = R(LK[3 * cap + b]);
-    const R si = R(LH[4 * cap + a]), sj = R(LK[4 * cap + b]);
-    R e, dedr;
-    if (form == TK_VDW_HAL) {
-      const R ri2 = ri * ri, rj2 = rj * rj;
-      const R rv = (ri2 * ri + rj2 * rj) / (ri2 + rj2);
-      const R se = si + sj;
-      const R ep = se > R(0) ? R(4) * (si * si) * (sj * sj) / (se * se) : R(0);
-      const R rv2 = rv * rv, rv7 = rv2 * rv2 * rv2 * rv;
-      const R r6 = R(r2) * R(r2) * R(r2), rik7 = r6 * r;
-      const R invrho = R(1) / (rik7 + R(ghal) * rv7);
-      const R invtmp = R(1) / (r + R(dhal) * rv);
-      const R tb = R(1.0 + dhal) * rv * invtmp;
-      const R tb2 = tb * tb, t7 = tb2 * tb2 * tb2 * tb;
-      const R w = R(1.0 + ghal) * rv7 * invrho;
-      e = ep * t7 * (w - R(2));
-      dedr = ep * (R(-7) * t7 * invtmp * (w - R(2)) - R(7) * t7 * r6 * w * invrho);
-    } else {
-      const R sg = R(0.5) * (ri + rj);
-      const R ep = si * sj;
-      const R q = sg * sg / R(r2);
-      const R sr6 = q * q * q;
-      e = R(4) * ep * (sr6 * sr6 - sr6);
-      dedr = R(4) * ep * (R(-12) * sr6 * sr6 + R(6) * sr6) / r;
-    }
-    if ((double)r > ron) {
-      const R x = (r - R(ron)) * R(tw_inv);
-      const R x2 = x * x, x3 = x2 * x;
-      const R S = R(1) - R(10) * x3 + R(15) * x3 * x - R(6) * x3 * x2;
-      const R dS = (R(-30) * x2 + R(60) * x3 - R(30) * x3 * x) * R(tw_inv);
-      dedr = dedr * S + e * dS;
-      e *= S;
+    R e, dedr, r;
+    eval<R>(r2, R(LH[3 * cap + a]), R(LK[3 * cap + b]), R(LH[4 * cap + a]), R(LK[4 * cap + b]), e,
+            dedr, r);
+    double en = (double)e;
+    if (std::is_same<R, float>::value) {
+      // the vdW energy is a sum of cancelling attractive and repulsive terms:
+      // in the mixed form it is evaluated in FP64 (forces stay FP32)
+      double ed, dd64, rd;
+      eval<double>(r2, LH[3 * cap + a], LK[3 * cap + b], LH[4 * cap + a], LK[4 * cap + b], ed, dd64,
+                   rd);
+      en = ed;
     }
     const double f = (double)dedr / (double)r;
-    sc[0] += (double)e;
+    sc[0] += en;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double de = f * dd[c];
