@@ -143,7 +143,7 @@ def main():
 
     # timed region: the dominant kernel (mutual-field mat-vec tiles) is timed
     # by HIP events that the library records on its launch stream
-    dom = "units_tmat_fp64" if prec == tk.FP64 else "units_tmat_fp32"
+    dom = "pcg_mv_fp64" if prec == tk.FP64 else "pcg_mv_fp32"
     ctx.profile(True, only=dom)
     ms = timed(step, a.steps, a.warmup) * 1e3
     dprof = ctx.profile_read()

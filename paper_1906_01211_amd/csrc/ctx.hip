@@ -98,6 +98,21 @@ CellTables& cell_tables(tk_ctx* ctx, int nc) {
   }
   t.nunits = (int32_t)t.units.size();
   t.nslot = cnt;
+  // per cell: the units it takes part in (each unique neighbour cell once),
+  // encoded unit * 4 + role (0: the cell is the unit's H, 1: its K, 2: both)
+  t.cu.assign((size_t)t.ncells * kCellUnitStride, 0);
+  for (int u = 0; u < t.nunits; ++u) {
+    const Unit& un = t.units[u];
+    if (un.h == un.k) {
+      int32_t* e = &t.cu[(size_t)un.h * kCellUnitStride];
+      e[1 + e[0]++] = u * 4 + 2;
+    } else {
+      int32_t* e = &t.cu[(size_t)un.h * kCellUnitStride];
+      e[1 + e[0]++] = u * 4 + 0;
+      e = &t.cu[(size_t)un.k * kCellUnitStride];
+      e[1 + e[0]++] = u * 4 + 1;
+    }
+  }
   return ctx->tables.emplace(nc, std::move(t)).first->second;
 }
 

@@ -58,7 +58,8 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // info: [0] status, [1] max cell occupancy, [2] max CSR row, [3] listed pairs,
-//       [4] 1 if the candidate windows did not fit the plan buffer
+//       [4] 1 if the candidate windows did not fit the plan buffer,
+//       [5] max atoms over a cell's neighbour cells
 // u = floor(frac(x/L) * 2^32) per coordinate; cell = (u * nc) >> 32 per axis.
 __global__ void k_quantize(int n, const double* __restrict__ xyz, double box, int nc,
                            uint32_t* __restrict__ u, int32_t* __restrict__ cell,
@@ -255,12 +256,28 @@ __global__ __launch_bounds__(64) void k_csr_fill(const Unit* __restrict__ units,
   }
 }
 
+// Per cell: atoms in its neighbour cells (itself included), maximum into
+// info[5] (the staging size of the per-cell mat-vec).
+__global__ void k_nbhd(int ncells, const int32_t* __restrict__ cu, const Unit* __restrict__ units,
+                       const int32_t* __restrict__ cstart, int32_t* __restrict__ info) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  const int32_t* e = cu + (long)c * kCellUnitStride;
+  int tot = 0;
+  for (int j = 0; j < e[0]; ++j) {
+    const int u = e[1 + j] >> 2, role = e[1 + j] & 3;
+    const int oc = role == 1 ? units[u].h : units[u].k;
+    tot += cstart[oc + 1] - cstart[oc];
+  }
+  atomicMax(&info[5], tot);
+}
+
 // Gathers the build's outcome into pinned host memory (one kernel instead of
 // several small copies).
 __global__ void k_readback(const int32_t* __restrict__ info, const int32_t* __restrict__ rp_end,
                            const int64_t* __restrict__ off_end, int32_t* __restrict__ host) {
-  for (int k = 0; k < 5; ++k) host[k] = info[k];
-  host[5] = *rp_end;
+  for (int k = 0; k < 6; ++k) host[k] = info[k];
+  host[6] = *rp_end;
   *(int64_t*)(host + 8) = *off_end;
 }
 
@@ -358,8 +375,10 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
   // device copies of the cell tables (uploaded once per cells-per-edge value)
   if (!T.uploaded) {
     if ((s = ensure(T.units_d, sizeof(Unit) * T.nunits)) ||
-        (s = ensure(T.nslot_d, sizeof(int32_t) * T.ncells)))
+        (s = ensure(T.nslot_d, sizeof(int32_t) * T.ncells)) ||
+        (s = ensure(T.cu_d, sizeof(int32_t) * T.cu.size())))
       return s;
+    TK_HIP(hipMemcpy(T.cu_d.p, T.cu.data(), sizeof(int32_t) * T.cu.size(), hipMemcpyHostToDevice));
     TK_HIP(hipMemcpy(T.units_d.p, T.units.data(), sizeof(Unit) * T.nunits, hipMemcpyHostToDevice));
     TK_HIP(hipMemcpy(T.nslot_d.p, T.nslot.data(), sizeof(int32_t) * T.ncells, hipMemcpyHostToDevice));
     T.uploaded = true;
@@ -416,6 +435,8 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
   }
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (n > 0) {
+      k_nbhd<<<ceil_div(T.ncells, 256), 256, 0, st>>>(T.ncells, (const int32_t*)T.cu_d.p, units,
+                                                      cstart, (int32_t*)info);
       {
         ProfScope ps(ctx, st, "nblist_plan");
         k_plan<<<T.nunits, 64, 0, st>>>(T.nunits, units, cstart, (uint4*)P.us.p, test, pstride,
@@ -433,7 +454,8 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
       TK_HIP(hipMemsetAsync(P.unit_off.p, 0, sizeof(int64_t) * (T.nunits + 1), st));
       TK_HIP(hipMemsetAsync(rp, 0, sizeof(int32_t), st));
     }
-    // one readback: status, max occupancy, max row, pairs, window overflow, list total
+    // one readback: status, max occupancy, max row, pairs, window overflow,
+    // max neighbourhood, list total
     k_readback<<<1, 1, 0, st>>>((int32_t*)info, rp + n, (int64_t*)P.unit_off.p + T.nunits, hd);
     TK_HIP(hipGetLastError());
     TK_HIP(hipStreamSynchronize(st));
@@ -445,10 +467,10 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
     if ((s = ensure(P.codes, sizeof(uint32_t) * (size_t)need))) return s;
     TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
   }
-  const int64_t list_pairs = h[5];
+  const int64_t list_pairs = h[6];
   *npairs_out = list_pairs;
   if (list_pairs != (int64_t)h[3]) {
-    std::fprintf(stderr, "libtk: plan/list pair count mismatch %d vs %d\n", h[3], h[5]);
+    std::fprintf(stderr, "libtk: plan/list pair count mismatch %d vs %d\n", h[3], h[6]);
     return TK_E_HIP;
   }
   const int max_row = h[2];
@@ -480,6 +502,8 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
   P.nunits = T.nunits;
   P.max_occ = h[1];
   P.max_row = max_row;
+  P.max_nbhd = h[5];
+  P.cu_p = (const int32_t*)T.cu_d.p;
   P.npairs = list_pairs;
   P.units_p = units;
   P.nslot_p = (const int32_t*)T.nslot_d.p;

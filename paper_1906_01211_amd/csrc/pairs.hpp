@@ -78,7 +78,7 @@ __global__ __launch_bounds__(64) void k_units(PlanView pv, Ph ph, double* __rest
   const long p0 = pv.unit_off[u], p1 = p0 + pv.unit_cnt[u];
   for (long p = p0 + lane; p < p1; p += 64) {
     const uint32_t code = pv.codes[p];
-    ph.pair(LH, LK, cap, (int)(code & 0xffffu), (int)(code >> 16), AH, AK, sc);
+    ph.pair(LH, LK, cap, (int)(code & 0xffffu), (int)(code >> 16), AH, AK, sc, p);
   }
   __syncthreads();
   for (int t = lane; t < nh; t += 64)

@@ -132,7 +132,7 @@ struct EmpolePh {
     g[13] = (double)molid[i];
   }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
-                       double* AK, double* sc) const {
+                       double* AK, double* sc, long) const {
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
     if (!(r2 <= g.rc2)) return;
@@ -222,7 +222,7 @@ struct ChargePh {
     g[4] = (double)molid[i];
   }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
-                       double* AK, double* sc) const {
+                       double* AK, double* sc, long) const {
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
     if (!(r2 <= g.rc2)) return;
@@ -284,27 +284,58 @@ struct EfieldPh {
     g[14] = inv_sqrt_alpha(polarity[i]);
     g[15] = thole[i];
   }
+  // Optional by-product for the solver: the mutual-field radial factors of
+  // the pair (same molecule included, Thole-damped), gc[p] = g1, gc[gcs + p]
+  // = g2, zero beyond the cutoff.  The permanent and mutual kernels differ
+  // only on same-molecule pairs (scale 0 vs 1), so one pass yields both.
+  using GC = R;
+  GC* gc = nullptr;
+  long gcs = 0;
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
-                       double* AK, double*) const {
+                       double* AK, double*, long p) const {
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
-    if (!(r2 <= g.rc2)) return;
+    if (!(r2 <= g.rc2)) {
+      if (gc) {
+        gc[p] = GC(0);
+        gc[gcs + p] = GC(0);
+      }
+      return;
+    }
     const bool excl = LH[13 * cap + a] == LK[13 * cap + b];
     R B[4], Rb[4];
     radial_pair<R, 3>(g, r2, excl, B, Rb);
     R g1, g2, g3;
+    R l3, l5, l7;
+    if (!excl || gc) {
+      const R r = R(r2) * rsqrt_r(R(r2));
+      thole_damp<R>(r, R(LH[14 * cap + a]), R(LK[14 * cap + b]), R(LH[15 * cap + a]),
+                    R(LK[15 * cap + b]), l3, l5, l7);
+    }
     if (excl) {
       g1 = B[1] - Rb[1];
       g2 = B[2] - Rb[2];
       g3 = B[3] - Rb[3];
+      if (gc) {
+        if (std::is_same<R, float>::value) {
+          // B carries the FP64 difference B - R; re-add the damped bare part in FP64
+          const double ri = rsqrt_r(r2);
+          const double R1 = ri * ri * ri, R2 = 3.0 * R1 * ri * ri;
+          gc[p] = GC((double)B[1] + (double)l3 * R1);
+          gc[gcs + p] = GC((double)B[2] + (double)l5 * R2);
+        } else {
+          gc[p] = B[1] - (R(1) - l3) * Rb[1];
+          gc[gcs + p] = B[2] - (R(1) - l5) * Rb[2];
+        }
+      }
     } else {
-      R l3, l5, l7;
-      const R r = R(r2) * rsqrt_r(R(r2));
-      thole_damp<R>(r, R(LH[14 * cap + a]), R(LK[14 * cap + b]), R(LH[15 * cap + a]),
-               R(LK[15 * cap + b]), l3, l5, l7);
       g1 = B[1] - (R(1) - l3) * Rb[1];
       g2 = B[2] - (R(1) - l5) * Rb[2];
       g3 = B[3] - (R(1) - l7) * Rb[3];
+      if (gc) {
+        gc[p] = g1;
+        gc[gcs + p] = g2;
+      }
     }
     const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
     const R qi = R(LH[3 * cap + a]), qj = R(LK[3 * cap + b]);
@@ -344,8 +375,9 @@ struct TmatPh {
   static constexpr int NF = 9, NA = 3, NS = 0;
   static constexpr const char* kName = "tmat";
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
-  const int* done = nullptr;   // solver flag: skip when set
-  __device__ bool skip() const { return done && *done; }
+  const int* done = nullptr;   // solver flag (status; 0 while iterating)
+  int run_when_done = 0;       // 0: skip once the solver has finished; 1: skip until it has
+  __device__ bool skip() const { return done && ((*done != 0) != (run_when_done != 0)); }
   __device__ void prologue(int lane) const { erfcx_stage<R>(lane, 64); }
   const double* xyz;
   const double* mu;
@@ -378,7 +410,7 @@ struct TmatPh {
   const int32_t* perm_ = nullptr;
 
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
-                       double* AK, double*) const {
+                       double* AK, double*, long) const {
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
     if (!(r2 <= g.rc2)) return;
@@ -404,6 +436,56 @@ struct TmatPh {
     const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
     const R ui[3] = {R(LH[6 * cap + a]), R(LH[7 * cap + a]), R(LH[8 * cap + a])};
     const R uj[3] = {R(LK[6 * cap + b]), R(LK[7 * cap + b]), R(LK[8 * cap + b])};
+    const R di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
+    const R dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
+    const R si = dj * g2, sj = di * g2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lds_add(&AH[c * cap + a], (double)(d[c] * si - uj[c] * g1));
+      lds_add(&AK[c * cap + b], (double)(d[c] * sj - ui[c] * g1));
+    }
+  }
+};
+
+// Mutual field from radial factors cached by the permanent-field pass
+// (EfieldPh::gc): per pair only the minimum-image vector is recomputed.
+// Fields: x y z | mu(3)
+template <class R>
+struct TmatCachedPh {
+  static constexpr int NF = 6, NA = 3, NS = 0, NG = 3;
+  static constexpr const char* kName = "tmatc";
+  static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
+  const int* done = nullptr;   // solver flag (status; 0 while iterating)
+  int run_when_done = 0;       // 0: skip once the solver has finished; 1: skip until it has
+  __device__ bool skip() const { return done && ((*done != 0) != (run_when_done != 0)); }
+  __device__ void prologue(int) const {}
+  const R* gc = nullptr;
+  long gcs = 0;
+  double box, inv_box;
+  const double* xyz = nullptr;
+  const double* mu = nullptr;        // sorted order
+  const double* zdir = nullptr;      // stage p = z + beta * p when set
+  const double* beta_dir = nullptr;
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void gather(int i, double* g) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] = xyz[3 * i + c];
+  }
+  __device__ void stage_dyn(double* L, int cap, int t, int s) const {
+    const double bd = zdir ? *beta_dir : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      L[(3 + c) * cap + t] = zdir ? fma(bd, mu[3 * s + c], zdir[3 * s + c]) : mu[3 * s + c];
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double*, long p) const {
+    const R g1 = gc[p], g2 = gc[gcs + p];
+    double dd[3];
+    image3(LH, LK, cap, a, b, box, inv_box, dd);
+    const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
+    const R ui[3] = {R(LH[3 * cap + a]), R(LH[4 * cap + a]), R(LH[5 * cap + a])};
+    const R uj[3] = {R(LK[3 * cap + b]), R(LK[4 * cap + b]), R(LK[5 * cap + b])};
     const R di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
     const R dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
     const R si = dj * g2, sj = di * g2;
@@ -495,7 +577,7 @@ struct VdwPh {
     }
   }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
-                       double* AK, double* sc) const {
+                       double* AK, double* sc, long) const {
     if (LH[5 * cap + a] == LK[5 * cap + b]) return;
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, box, inv_box, dd);
@@ -604,8 +686,11 @@ tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, con
 template <class R>
 inline tk_status launch_efield(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_system* sys,
                         const double* mpole, const double* polarity, const double* thole,
-                        double beta, double cutoff, double* out, int sorted_out) {
+                        double beta, double cutoff, double* out, int sorted_out,
+                        R* gc = nullptr, long gcs = 0) {
   EfieldPh<R> ph;
+  ph.gc = gc;
+  ph.gcs = gcs;
   ph.xyz = sys->xyz;
   ph.mpole = mpole;
   ph.molid = sys->molid;

@@ -27,6 +27,7 @@ constexpr double kTwo32 = 4294967296.0;
 // takes part in at most 28 unit roles (27 neighbours, the self pair twice),
 // and each role owns one partial-result slot for the cell's atoms.
 constexpr int kMaxSlots = 28;
+constexpr int kCellUnitStride = 28;  // per-cell unit list: count + up to 27 entries
 constexpr int kMaxCellAtoms = 512;   // LDS staging limit per cell
 constexpr int kWave = 64;
 constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
@@ -47,6 +48,7 @@ struct PlanView {
   const int64_t* unit_off;    // [nunits+1] start of each unit's window in codes
   const int32_t* unit_cnt;    // [nunits] listed pairs of the unit (window prefix)
   const uint32_t* codes;      // pair codes: a | b << 16 (local indices in H, K)
+  const int32_t* cell_units;  // [ncells][28]: count, then unit * 4 + role
 };
 
 struct DevBuf {
@@ -59,10 +61,12 @@ struct Plan {
   int32_t n = 0;
   double box = 0.0, cutoff = 0.0;
   int32_t nc = 0, ncells = 0, nunits = 0, max_occ = 0, max_row = 0;
+  int32_t max_nbhd = 0;   // max over cells of the atoms in the cell's neighbour cells (itself included)
   int64_t npairs = 0;
   DevBuf perm, scell, cell_start, unit_off, unit_cnt, codes, us, slots;
   const Unit* units_p = nullptr;       // device cell tables shared by plans with the same nc
   const int32_t* nslot_p = nullptr;
+  const int32_t* cu_p = nullptr;
   PlanView view() const {
     PlanView v;
     v.n = n; v.ncells = ncells; v.nunits = nunits; v.max_occ = max_occ;
@@ -71,6 +75,7 @@ struct Plan {
     v.units = units_p; v.unit_off = (const int64_t*)unit_off.p;
     v.unit_cnt = (const int32_t*)unit_cnt.p;
     v.codes = (const uint32_t*)codes.p;
+    v.cell_units = cu_p;
     return v;
   }
 };
@@ -80,8 +85,9 @@ struct CellTables {   // host-built tables for one cells-per-edge value
   std::vector<Unit> units;
   std::vector<int32_t> nslot;     // per cell
   std::vector<int32_t> nbr;       // per cell: count, then up to 27 neighbour cells
+  std::vector<int32_t> cu;        // per cell: count, then unit * 4 + role (kCellUnitStride)
   bool uploaded = false;
-  DevBuf units_d, nslot_d;        // device copies
+  DevBuf units_d, nslot_d, cu_d;  // device copies
 };
 
 }  // namespace tk
@@ -106,6 +112,7 @@ struct tk_ctx {
   void* pinned = nullptr;                      // host readback buffer (device-writable)
   void* pinned_dev = nullptr;                  // its device address
   size_t pinned_bytes = 0;
+  int pcg_hint[TK_MAX_PLANS][2] = {};          // last solve's iteration count per plan slot, precision
 };
 
 namespace tk {
