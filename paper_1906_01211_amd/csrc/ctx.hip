@@ -183,14 +183,84 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const T* in, long len
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[len] = bsum[gridDim.x];
 }
 
+// One workgroup for short arrays (one launch instead of three): thread t
+// sums a contiguous chunk, the chunk sums are scanned across the workgroup,
+// then each thread writes its chunk.
+constexpr int kScan1Threads = 1024;
+constexpr long kScan1Max = 4096;
+constexpr int kScan2MaxBlocks = 4096;
+
+template <class T>
+__global__ __launch_bounds__(kScan1Threads) void k_scan1(const T* __restrict__ in, long len,
+                                                         T* __restrict__ out) {
+  __shared__ T wsum[kScan1Threads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const long chunk = (len + kScan1Threads - 1) / kScan1Threads;
+  const long b0 = tid * chunk, b1 = b0 + chunk < len ? b0 + chunk : len;
+  T s = 0;
+  for (long i = b0; i < b1; ++i) s += in[i];
+  T incl = s;   // inclusive scan inside the wave
+  for (int o = 1; o < 64; o <<= 1) {
+    const T t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  T base = 0;
+  for (int k = 0; k < w; ++k) base += wsum[k];
+  T run = base + incl - s;
+  for (long i = b0; i < b1; ++i) {
+    const T v = in[i];
+    out[i] = run;
+    run += v;
+  }
+  if (tid == kScan1Threads - 1) out[len] = base + incl;
+}
+
+// Final pass that finds its own carry: block b sums the tile totals of the
+// blocks before it (fixed order), so no separate pass over the totals.
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_final_carry(const T* in, long len,
+                                                                 const T* bsum, T* out) {
+  __shared__ T sh[kScanBlock];
+  T c = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanBlock) c += bsum[b];
+  T ctot;
+  block_exclusive_scan<T>(c, sh, &ctot);
+  long base = (long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  T v[kScanItems], s = 0;
+  for (int q = 0; q < kScanItems; ++q) {
+    v[q] = base + q < len ? in[base + q] : T(0);
+    s += v[q];
+  }
+  T tot;
+  T ex = block_exclusive_scan<T>(s, sh, &tot) + ctot;
+  for (int q = 0; q < kScanItems; ++q) {
+    if (base + q < len) out[base + q] = ex;
+    ex += v[q];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[len] = ctot + tot;
+}
+
 template <class T>
 static tk_status scan_t(tk_ctx* ctx, hipStream_t st, const T* in, T* out, long len,
                         const char* name) {
+  if (len <= kScan1Max) {
+    k_scan1<T><<<1, kScan1Threads, 0, st>>>(in, len, out);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+  }
   int nb = ceil_div(len, kScanTile);
   if (nb < 1) nb = 1;
   void* bs;
   tk_status s = scratch(ctx, name, sizeof(T) * (nb + 1), &bs);
   if (s) return s;
+  if (nb <= kScan2MaxBlocks) {
+    k_scan_sums<T><<<nb, kScanBlock, 0, st>>>(in, len, (T*)bs);
+    k_scan_final_carry<T><<<nb, kScanBlock, 0, st>>>(in, len, (T*)bs, out);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+  }
   k_scan_sums<T><<<nb, kScanBlock, 0, st>>>(in, len, (T*)bs);
   k_scan_bsum<T><<<1, kScanBlock, 0, st>>>((T*)bs, nb);
   k_scan_final<T><<<nb, kScanBlock, 0, st>>>(in, len, (T*)bs, out);

@@ -86,6 +86,81 @@ __global__ void k_quantize(int n, const double* __restrict__ xyz, double box, in
   atomicAdd(&cell_count[cc], 1);
 }
 
+// Stable counting sort by cell without global atomics (boxes with at most
+// kMaxHistCells cells): per-block LDS histograms H[c][b], one exclusive scan
+// over H in cell-major order, then each atom's slot is its (cell, block)
+// offset plus its rank among the block's earlier atoms of the same cell.
+// Slots come out ordered by (cell, caller index).
+constexpr int kHistBlock = 256;
+constexpr int kMaxHistCells = 4096;
+
+__global__ __launch_bounds__(kHistBlock) void k_quantize_hist(int n, const double* __restrict__ xyz,
+                                                              double box, int nc, int ncells,
+                                                              uint32_t* __restrict__ u,
+                                                              int32_t* __restrict__ cell,
+                                                              int32_t* __restrict__ H,
+                                                              int32_t* __restrict__ info) {
+  __shared__ int hist[kMaxHistCells];
+  for (int c = threadIdx.x; c < ncells; c += kHistBlock) hist[c] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * kHistBlock + threadIdx.x;
+  if (i < n) {
+    int c[3];
+    for (int a = 0; a < 3; ++a) {
+      const double x = xyz[3 * i + a];
+      uint32_t q = 0;
+      if (isfinite(x)) {
+        const double t = x / box;
+        double f = t - floor(t);
+        if (f >= 1.0) f = 0.0;
+        q = (uint32_t)(f * kTwo32);
+      } else {
+        atomicMin(&info[0], (int)TK_E_ARG);
+      }
+      u[3 * i + a] = q;
+      c[a] = (int)(((uint64_t)q * (uint64_t)nc) >> 32);
+    }
+    const int cc = (c[0] * nc + c[1]) * nc + c[2];
+    cell[i] = cc;
+    atomicAdd(&hist[cc], 1);
+  }
+  __syncthreads();
+  const int nblk = gridDim.x;
+  for (int c = threadIdx.x; c < ncells; c += kHistBlock) H[(long)c * nblk + blockIdx.x] = hist[c];
+}
+
+// off = exclusive scan of H (cell-major).  Block 0 also writes cell_start,
+// the largest occupancy and the capacity check.
+__global__ __launch_bounds__(kHistBlock) void k_scatter_stable(
+    int n, int ncells, const int32_t* __restrict__ cell, const int32_t* __restrict__ off,
+    const uint32_t* __restrict__ u, int32_t* __restrict__ perm, int32_t* __restrict__ scell,
+    uint4* __restrict__ us, int32_t* __restrict__ cstart, int32_t* __restrict__ info) {
+  __shared__ int cl[kHistBlock];
+  const int nblk = gridDim.x;
+  const int i = blockIdx.x * kHistBlock + threadIdx.x;
+  const int c = i < n ? cell[i] : -1;
+  cl[threadIdx.x] = c;
+  __syncthreads();
+  if (i < n) {
+    int rank = 0;
+    for (int t = 0; t < (int)threadIdx.x; ++t) rank += cl[t] == c;
+    const int slot = off[(long)c * nblk + blockIdx.x] + rank;
+    perm[slot] = i;
+    scell[slot] = c;
+    us[slot] = make_uint4(u[3 * i], u[3 * i + 1], u[3 * i + 2], (uint32_t)i);
+  }
+  if (blockIdx.x == 0) {
+    for (int cc = threadIdx.x; cc < ncells; cc += kHistBlock) {
+      const int s0 = off[(long)cc * nblk];
+      const int s1 = cc + 1 < ncells ? off[(long)(cc + 1) * nblk] : n;
+      cstart[cc] = s0;
+      atomicMax(&info[1], s1 - s0);
+      if (s1 - s0 > kMaxCellAtoms) atomicMin(&info[0], (int)TK_E_CAPACITY);
+    }
+    if (threadIdx.x == 0) cstart[ncells] = n;
+  }
+}
+
 __global__ void k_scatter(int n, const int32_t* __restrict__ cell, const int32_t* __restrict__ cstart,
                           int32_t* __restrict__ cursor, int32_t* __restrict__ tmp) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,20 +331,22 @@ __global__ __launch_bounds__(64) void k_csr_fill(const Unit* __restrict__ units,
   }
 }
 
-// Per cell: atoms in its neighbour cells (itself included), maximum into
-// info[5] (the staging size of the per-cell mat-vec).
-__global__ void k_nbhd(int ncells, const int32_t* __restrict__ cu, const Unit* __restrict__ units,
-                       const int32_t* __restrict__ cstart, int32_t* __restrict__ info) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells) return;
-  const int32_t* e = cu + (long)c * kCellUnitStride;
-  int tot = 0;
-  for (int j = 0; j < e[0]; ++j) {
-    const int u = e[1 + j] >> 2, role = e[1 + j] & 3;
+// One wave per cell: atoms in its neighbour cells (itself included); the
+// maximum goes to info[5] (staging size of the per-cell mat-vec).
+__global__ __launch_bounds__(64) void k_nbhd(const int32_t* __restrict__ cu,
+                                             const Unit* __restrict__ units,
+                                             const int32_t* __restrict__ cstart,
+                                             int32_t* __restrict__ info) {
+  const int32_t* e = cu + (long)blockIdx.x * kCellUnitStride;
+  const int lane = lane_id();
+  int cnt = 0;
+  if (lane < e[0]) {
+    const int u = e[1 + lane] >> 2, role = e[1 + lane] & 3;
     const int oc = role == 1 ? units[u].h : units[u].k;
-    tot += cstart[oc + 1] - cstart[oc];
+    cnt = cstart[oc + 1] - cstart[oc];
   }
-  atomicMax(&info[5], tot);
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+  if (lane == 0) atomicMax(&info[5], cnt);
 }
 
 // Gathers the build's outcome into pinned host memory (one kernel instead of
@@ -408,15 +485,36 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
       (s = scratch(ctx, "nb_rcnt", sizeof(int32_t) * (nn + 1), &rcnt)) ||
       (s = scratch(ctx, "nb_rptr", sizeof(int32_t) * (nn + 1), &rptr)))
     return s;
-  TK_HIP(hipMemsetAsync(ccount, 0, sizeof(int32_t) * (T.ncells + 1), st));
-  TK_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * T.ncells, st));
   TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
   const int32_t* cstart = (const int32_t*)P.cell_start.p;
   const Unit* units = (const Unit*)T.units_d.p;
   int32_t* rp = want_csr ? row_ptr : (int32_t*)rptr;
   int32_t *h, *hd;
   if ((s = pinned(ctx, 4096, (void**)&h, (void**)&hd))) return s;
-  if (n > 0) {
+  if (n > 0 && T.ncells <= kMaxHistCells) {
+    const int nblk = ceil_div(n, kHistBlock);
+    const long hl = (long)T.ncells * nblk;
+    void *H, *Hoff;
+    if ((s = scratch(ctx, "nb_hist", sizeof(int32_t) * hl, &H)) ||
+        (s = scratch(ctx, "nb_hist_off", sizeof(int32_t) * (hl + 1), &Hoff)))
+      return s;
+    {
+      ProfScope ps(ctx, st, "nblist_quantize");
+      k_quantize_hist<<<nblk, kHistBlock, 0, st>>>(n, sys->xyz, sys->box, nc, T.ncells,
+                                                    (uint32_t*)u, (int32_t*)cell, (int32_t*)H,
+                                                    (int32_t*)info);
+    }
+    if ((s = scan_i32(ctx, st, (int32_t*)H, (int32_t*)Hoff, (int)hl))) return s;
+    {
+      ProfScope ps(ctx, st, "nblist_cellsort");
+      k_scatter_stable<<<nblk, kHistBlock, 0, st>>>(n, T.ncells, (int32_t*)cell, (int32_t*)Hoff,
+                                                     (uint32_t*)u, (int32_t*)P.perm.p,
+                                                     (int32_t*)P.scell.p, (uint4*)P.us.p,
+                                                     (int32_t*)P.cell_start.p, (int32_t*)info);
+    }
+  } else if (n > 0) {
+    TK_HIP(hipMemsetAsync(ccount, 0, sizeof(int32_t) * (T.ncells + 1), st));
+    TK_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * T.ncells, st));
     {
       ProfScope ps(ctx, st, "nblist_quantize");
       k_quantize<<<ceil_div(n, 256), 256, 0, st>>>(n, sys->xyz, sys->box, nc, (uint32_t*)u,
@@ -430,13 +528,16 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
       k_cellsort<<<T.ncells, 64, 0, st>>>(cstart, (int32_t*)tmp, (uint32_t*)u, (int32_t*)P.perm.p,
                                           (int32_t*)P.scell.p, (uint4*)P.us.p, (int32_t*)info);
     }
+  } else {
+    TK_HIP(hipMemsetAsync(P.cell_start.p, 0, sizeof(int32_t) * (T.ncells + 1), st));
+  }
+  if (n > 0) {
     k_cand<<<ceil_div(T.nunits, 256), 256, 0, st>>>(T.nunits, units, cstart, (int64_t*)cand);
     if ((s = scan_i64(ctx, st, (int64_t*)cand, (int64_t*)P.unit_off.p, T.nunits))) return s;
   }
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (n > 0) {
-      k_nbhd<<<ceil_div(T.ncells, 256), 256, 0, st>>>(T.ncells, (const int32_t*)T.cu_d.p, units,
-                                                      cstart, (int32_t*)info);
+      k_nbhd<<<T.ncells, 64, 0, st>>>((const int32_t*)T.cu_d.p, units, cstart, (int32_t*)info);
       {
         ProfScope ps(ctx, st, "nblist_plan");
         k_plan<<<T.nunits, 64, 0, st>>>(T.nunits, units, cstart, (uint4*)P.us.p, test, pstride,
@@ -454,8 +555,7 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
       TK_HIP(hipMemsetAsync(P.unit_off.p, 0, sizeof(int64_t) * (T.nunits + 1), st));
       TK_HIP(hipMemsetAsync(rp, 0, sizeof(int32_t), st));
     }
-    // one readback: status, max occupancy, max row, pairs, window overflow,
-    // max neighbourhood, list total
+    // one readback: status, max occupancy, max row, pairs, window overflow, list total
     k_readback<<<1, 1, 0, st>>>((int32_t*)info, rp + n, (int64_t*)P.unit_off.p + T.nunits, hd);
     TK_HIP(hipGetLastError());
     TK_HIP(hipStreamSynchronize(st));

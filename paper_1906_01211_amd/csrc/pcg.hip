@@ -408,7 +408,8 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   double* ACC = L + 6 * SC;        // [wave][3][OC]
   const int total = e_off[ne];
   const long ps = A.pstride;
-  const bool dir = kMode == 1 && A.k >= 1;
+  // operand v + beta * pold: for k = 0 (and modes 0, 2) beta = 0 and pold = v
+  const double* pold = (kMode == 1 && A.k >= 1) ? A.pold : A.v;
   for (int i0 = tid; i0 < total; i0 += kMvThreads * kMvStageBatch) {
     int src[kMvStageBatch];
 #pragma unroll
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
       f[m][2] = A.pos[2 * ps + s];
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        f[m][3 + d] = dir ? fma(beta, A.pold[3 * s + d], A.v[3 * s + d]) : A.v[3 * s + d];
+        f[m][3 + d] = fma(beta, pold[3 * s + d], A.v[3 * s + d]);
     }
 #pragma unroll
     for (int m = 0; m < kMvStageBatch; ++m) {
@@ -457,14 +458,15 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
     // issue the batch's code and factor loads together
     uint32_t codes[kMvBatch];
     R g1s[kMvBatch], g2s[kMvBatch];
-    int js[kMvBatch];
+    int roles[kMvBatch], offs[kMvBatch];   // kept in registers: no LDS reads after the atomics
 #pragma unroll
     for (int m = 0; m < kMvBatch; ++m) {
       const int vix = v0 + m * kMvThreads;
-      js[m] = -1;
+      roles[m] = -1;
       if (vix < T) {
         while (vix >= e_pre[j + 1]) ++j;
-        js[m] = j;
+        roles[m] = e_role[j];
+        offs[m] = e_off[j];
         const long p = e_uoff[j] + (vix - e_pre[j]);
         codes[m] = pv.codes[p];
         g1s[m] = A.gc[p];
@@ -473,13 +475,12 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
     }
 #pragma unroll
     for (int m = 0; m < kMvBatch; ++m) {
-    if (js[m] < 0) continue;
-    const int jm = js[m];
-    const int role = e_role[jm];
+    if (roles[m] < 0) continue;
+    const int role = roles[m];
     const uint32_t code = codes[m];
     const int a = (int)(code & 0xffffu), b = (int)(code >> 16);
     const int own = role == 1 ? b : a;
-    const int oth = e_off[jm] + (role == 1 ? a : b);
+    const int oth = offs[m] + (role == 1 ? a : b);
     const int ownL = own0 + own;
     const R g1 = g1s[m], g2 = g2s[m];
     R dv[3];
