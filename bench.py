@@ -27,13 +27,37 @@ sys.path.insert(0, ROOT)
 
 from paper_1906_01211_amd import synth  # noqa: E402
 
-# Per-pair algorithmic floating-point operations of each kernel's definition
-# (+, -, * count 1, fused multiply-add 2; sqrt, division, exp and erfc count 1
-# each).  Derivation in the design doc.
-FLOPS_PER_PAIR = {"tmatvec": 62, "efield": 163, "empole": 398, "hal": 72, "charge": 31, "lj": 40}
+# Compulsory HBM bytes of one solver mat-vec launch (iteration k): per listed
+# pair its 4-byte pair code and its two cached radial factors (8 bytes each in
+# FP64, 4 in the mixed form); per atom the coordinates (24), z (24), the
+# previous direction (24) and alpha (8) read, p (24) and q (24) written.
+MV_BYTES_PER_PAIR = {"fp64": 4 + 16, "mixed": 4 + 8}
+MV_BYTES_PER_ATOM = 24 + 24 + 24 + 8 + 24 + 24
+# Floating-point operations per listed pair of the same launch (both atoms'
+# fields: pair vector 9, two dot products 10, two field updates 12, scale 2).
+MV_FLOPS_PER_PAIR = 33
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+
+
+def committed_traffic(prec):
+    """HBM bytes per launch of the FP64 solver mat-vec from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    if prec != "fp64":
+        return None
+    path = os.path.join(ROOT, "profiles", "pcg_mv_water7853_fp64_traffic.txt")
+    src = os.path.join(ROOT, "paper_1906_01211_amd", "csrc", "pcg.hip")
+    try:
+        kv = dict(line.split(": ", 1) for line in open(path).read().splitlines()
+                  if line.startswith(("kernel_source_sha256", "fetch_bytes", "write_bytes")))
+        if kv["kernel_source_sha256"].strip() != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+        return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def count_pairs(xyz, box, row_ptr, col, rc, molid=None, skip_same=False):
@@ -55,6 +79,9 @@ def parse():
     ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run device-to-device copies of this many MiB (a kernel of known "
+                         "traffic for scaling HBM counters)")
     return ap.parse_args()
 
 
@@ -87,6 +114,7 @@ class AmoebaStep:
 
     def pair_counts(self):
         l7, l9 = self()
+        self.l7_pairs = l7.npairs
         w, s = self.w, self.s
         n7 = count_pairs(w.xyz, w.box, l7.row_ptr.cpu().numpy(), l7.col.cpu().numpy(),
                          s["rc_ewald"])
@@ -136,13 +164,20 @@ def main():
     from paper_1906_01211_amd import tk
     tk.load()
     ctx = tk.Context(0)
+    if a.calibrate_copy > 0:
+        src = torch.ones(a.calibrate_copy << 17, dtype=torch.float64, device=ctx.device)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prec = tk.FP64 if a.prec == "fp64" else tk.MIXED
     w = synth.make("water7853")
     step = AmoebaStep(ctx, tk, w, prec)
     n7, n9 = step.pair_counts()
 
-    # timed region: the dominant kernel (mutual-field mat-vec tiles) is timed
-    # by HIP events that the library records on its launch stream
+    # timed region: the dominant kernel (the solver's per-cell mat-vec) is
+    # timed by HIP events that the library records on its launch stream
     dom = "pcg_mv_fp64" if prec == tk.FP64 else "pcg_mv_fp32"
     ctx.profile(True, only=dom)
     ms = timed(step, a.steps, a.warmup) * 1e3
@@ -159,14 +194,23 @@ def main():
 
     roof = None
     if dom in dprof and dprof[dom]["launches"] > 0:
-        avg_ms = dprof[dom]["ms"] / dprof[dom]["launches"]
-        flops = FLOPS_PER_PAIR["tmatvec"] * n7
-        ach = flops / (avg_ms * 1e-3) / 1e12
-        peak = PEAK_FP64_TFLOPS if prec == tk.FP64 else PEAK_FP32_TFLOPS
-        roof = {"bound": "alu", "kernel": "k_units<TmatPh>", "achieved": round(ach, 3),
-                "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
+        launches = dprof[dom]["launches"]
+        avg_ms = dprof[dom]["ms"] / launches
+        # launches per solve: iterations 0..iters-1 do the mat-vec, the last
+        # one only finds convergence and returns
+        solves = a.steps + a.warmup
+        working = iters * solves
+        nl7 = int(step.l7_pairs)
+        bpl = MV_BYTES_PER_PAIR[a.prec] * nl7 + MV_BYTES_PER_ATOM * w.n
+        ach = bpl * working / (dprof[dom]["ms"] * 1e-3) / 1e9
+        fl = MV_FLOPS_PER_PAIR * n7 * working / (dprof[dom]["ms"] * 1e-3) / 1e12
+        peak_fl = PEAK_FP64_TFLOPS if prec == tk.FP64 else PEAK_FP32_TFLOPS
+        roof = {"bound": "hbm", "kernel": "k_pcg_mv (solver mat-vec, iteration form)",
+                "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": committed_traffic(a.prec),
+                "bytes_per_launch": bpl, "launches": launches, "working_launches": working,
                 "avg_launch_us": round(avg_ms * 1e3, 3),
-                "flops_per_launch": flops}
+                "alu_tflops": round(fl, 3), "alu_frac": round(fl / peak_fl, 4)}
     out = {
         "metric": "real-space pair-interactions/s + polarization solves/s (mixed vs FP64); p99 lat",
         "value": value, "unit": "pair-interactions/s", "n_gpus": 1, "steps": a.steps,
