@@ -213,6 +213,119 @@ tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nbli
                   double taper_on_frac, double hal_delta, double hal_gamma, int prec,
                   double* energy, double* force, double* virial);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent systems (the serving form; the paper has no serving
+ * path, so this is an engine feature around the terms of section "Hotspots").
+ *
+ * A batch holds nsys systems, each with its own periodic cubic box; every
+ * launch of a batch step covers all of them (multi-system kernels: each cell
+ * and each unit knows its system), and each system's results are bitwise
+ * identical to those of the same system stepped alone.
+ */
+typedef struct {
+  int32_t nsys;              /* number of systems, >= 1 */
+  const int32_t* atom_off;   /* host [nsys+1]: system k owns atoms atom_off[k] .. atom_off[k+1]-1,
+                                atom_off[0] = 0, non-decreasing */
+  const double* box;         /* host [nsys]: cubic edge of each system (A) */
+  const double* xyz;         /* device [atom_off[nsys]][3], each system in its own frame */
+  const int32_t* molid;      /* device [atom_off[nsys]]: molecule ids (compared within a system) */
+} tk_batch;
+
+typedef struct {             /* host; one AMOEBA step for every system of a batch */
+  double rc_ewald;           /* real-space Ewald cutoff (A); rc_ewald + skin <= box/2 is required */
+  double rc_vdw;             /* vdW cutoff; per system clamped to box/2 - skin (small boxes) */
+  double skin;               /* list skin added to both cutoffs (>= 0) */
+  double ewald_beta;         /* Ewald screening parameter (1/A) */
+  double tol_debye;          /* PCG tolerance, RMS of the preconditioned residual (D) */
+  double taper_on_frac;      /* vdW taper start as a fraction of the vdW cutoff */
+  double hal_delta, hal_gamma;
+  int32_t maxiter;           /* PCG iteration limit */
+  int32_t prec;              /* TK_FP64 or TK_MIXED */
+} tk_step_params;
+
+typedef struct {             /* host; per system */
+  double e_mpole[3];         /* permanent multipoles: total, non-excluded, exclusion correction */
+  double w_mpole[9];
+  double e_vdw;              /* Halgren 14-7 */
+  double w_vdw[9];
+  double rc_vdw;             /* the vdW cutoff used for this system */
+  tk_pcg_info pcg;           /* the induced-dipole solve (epol = -C/2 mu.E_perm) */
+} tk_step_result;
+
+/*
+ * One step for every system of the batch: neighbour lists at rc_ewald + skin
+ * and rc_vdw(k) + skin, tk_empole_real, tk_polarize_pcg and tk_evdw (HAL)
+ * with the definitions stated at those entry points.
+ * mpole [n][10], polarity, thole, vdw_rad, vdw_eps [n]: device, caller order.
+ * mu_guess: device [n][3] or NULL; use_guess: host [nsys] or NULL.  System k
+ * starts its dipole solve from mu_guess when mu_guess is given and
+ * (use_guess is NULL or use_guess[k] != 0), else from alpha * E_perm.
+ * Outputs (device, [n][3], overwritten): force_mpole, mu, force_vdw.
+ * results: host [nsys].
+ * Synchronises the stream.  Returns TK_OK even when some system's solve did
+ * not converge (see results[k].pcg.status); TK_E_CUTOFF when rc_ewald + skin
+ * exceeds some box/2; TK_E_CAPACITY when a cell holds more atoms than the
+ * kernels stage.  Uses two context plan slots of its own (not the caller's).
+ */
+tk_status tk_batch_step(tk_ctx* ctx, void* stream, const tk_batch* batch,
+                        const tk_step_params* params, const double* mpole,
+                        const double* polarity, const double* thole, const double* vdw_rad,
+                        const double* vdw_eps, const double* mu_guess,
+                        const int32_t* use_guess, double* force_mpole, double* mu,
+                        double* force_vdw, tk_step_result* results);
+
+/*
+ * Serving runtime: continuous batching of step requests.  A server owns its
+ * own context and HIP stream on `device` and a worker thread.  Requests are
+ * queued by tk_server_submit (host arrays, copied at once); the worker forms
+ * each batch from the queue in arrival order while the estimated device
+ * footprint of the batch stays within hbm_budget bytes (and at most
+ * max_batch systems), runs one tk_batch_step on it, and publishes every
+ * result; requests that arrive meanwhile join the next batch.  A request
+ * whose own footprint exceeds the budget is rejected (TK_E_CAPACITY).
+ * Sessions: a request with a nonzero session id starts its dipole solve from
+ * the dipoles of the previous completed request of the same session when
+ * the atom count matches (resident guesses; otherwise from alpha * E_perm).
+ * The server's functions may be called from any host thread.
+ */
+typedef struct tk_server tk_server;
+
+typedef struct {             /* host arrays, copied by tk_server_submit */
+  int32_t n;
+  double box;
+  const double* xyz;         /* [n][3] */
+  const int32_t* molid;      /* [n] */
+  const double* mpole;       /* [n][10] */
+  const double* polarity;    /* [n] */
+  const double* thole;       /* [n] */
+  const double* vdw_rad;     /* [n] */
+  const double* vdw_eps;     /* [n] */
+  uint64_t session;          /* 0: none */
+} tk_request;
+
+typedef struct {             /* host timestamps (ns, monotonic clock) and the batch it ran in */
+  int64_t t_submit, t_start, t_done;
+  int32_t batch_size;        /* systems in that batch */
+  int32_t batch_index;       /* sequence number of the batch */
+} tk_timing;
+
+tk_status tk_server_create(int device, const tk_step_params* params, size_t hbm_budget,
+                           int32_t max_batch, tk_server** out);
+/* Estimated device bytes of one request of n atoms (the admission measure). */
+size_t tk_server_footprint(int32_t n);
+tk_status tk_server_submit(tk_server* srv, const tk_request* req, uint64_t* id);
+/*
+ * TK_E_BUSY while request `id` is queued or running; then copies its results
+ * (any output pointer may be NULL: host [n][3] arrays force_mpole, mu,
+ * force_vdw) and returns the step status (TK_OK, or the batch's error).
+ * A request's results can be polled until tk_server_release(id).
+ */
+tk_status tk_server_poll(tk_server* srv, uint64_t id, tk_step_result* result, tk_timing* timing,
+                         double* force_mpole, double* mu, double* force_vdw);
+tk_status tk_server_release(tk_server* srv, uint64_t id);
+/* Waits for every submitted request, then stops the worker and frees all. */
+void tk_server_destroy(tk_server* srv);
+
 /*
  * Kernel timing (tracing aid).  When enabled, the library brackets its kernel
  * launches with HIP events on the launch stream; `only` (host string, may be

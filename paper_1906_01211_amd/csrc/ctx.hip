@@ -331,7 +331,7 @@ tk_status get_plan(tk_ctx* ctx, const tk_system* sys, const tk_nblist* list, dou
   if (cutoff > 0.5 * sys->box) return TK_E_CUTOFF;
   if (list->plan < 0 || list->plan >= TK_MAX_PLANS) return TK_E_PLAN;
   const Plan& p = ctx->plans[list->plan];
-  if (!p.valid || p.n != sys->n || p.box != sys->box || p.cutoff != list->cutoff ||
+  if (!p.valid || p.nsys != 1 || p.n != sys->n || p.box != sys->box || p.cutoff != list->cutoff ||
       p.npairs != list->npairs)
     return TK_E_PLAN;
   if (cutoff > p.cutoff) return TK_E_ARG;   // the list must cover the kernel cutoff

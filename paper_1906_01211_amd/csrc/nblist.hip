@@ -12,6 +12,7 @@
 // Every pair decision is the same exact test, so the plan (what the pair
 // kernels read) and the CSR (what the caller reads) hold the same pair set.
 #include <cmath>
+#include <cstring>
 
 #include "tk_internal.hpp"
 
@@ -32,6 +33,7 @@ __device__ __forceinline__ bool pair_in(const uint4& a, const uint4& b, uint64_t
 struct PairTest {
   uint64_t rq2;
   double lo, hi;
+  __device__ __forceinline__ PairTest(const SysDev& d) : rq2(d.rq2), lo(d.lo), hi(d.hi) {}
   __device__ __forceinline__ bool operator()(const uint4& a, const uint4& b) const {
     const double dx = (double)(int32_t)(b.x - a.x), dy = (double)(int32_t)(b.y - a.y),
                  dz = (double)(int32_t)(b.z - a.z);
@@ -60,18 +62,28 @@ __device__ __forceinline__ int wave_max(int v) {
 // info: [0] status, [1] max cell occupancy, [2] max CSR row, [3] listed pairs,
 //       [4] 1 if the candidate windows did not fit the plan buffer,
 //       [5] max atoms over a cell's neighbour cells
-// u = floor(frac(x/L) * 2^32) per coordinate; cell = (u * nc) >> 32 per axis.
-__global__ void k_quantize(int n, const double* __restrict__ xyz, double box, int nc,
-                           uint32_t* __restrict__ u, int32_t* __restrict__ cell,
-                           int32_t* __restrict__ cell_count, int32_t* __restrict__ info) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// System of atom i: the last system whose first atom is <= i.
+__device__ __forceinline__ int atom_system(const SysDev* sys, int nsys, int i) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sys[mid].atom0 <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// u = floor(frac(x/L) * 2^32) per coordinate; cell = (u * nc) >> 32 per axis,
+// offset by the system's first cell.
+__device__ __forceinline__ int quantize_atom(const double* __restrict__ xyz, int i,
+                                             const SysDev& sd, uint32_t* __restrict__ u,
+                                             int32_t* __restrict__ info) {
   int c[3];
   for (int a = 0; a < 3; ++a) {
-    double x = xyz[3 * i + a];
+    const double x = xyz[3 * i + a];
     uint32_t q = 0;
     if (isfinite(x)) {
-      double t = x / box;
+      const double t = x / sd.box;
       double f = t - floor(t);
       if (f >= 1.0) f = 0.0;
       q = (uint32_t)(f * kTwo32);
@@ -79,14 +91,22 @@ __global__ void k_quantize(int n, const double* __restrict__ xyz, double box, in
       atomicMin(&info[0], (int)TK_E_ARG);
     }
     u[3 * i + a] = q;
-    c[a] = (int)(((uint64_t)q * (uint64_t)nc) >> 32);
+    c[a] = (int)(((uint64_t)q * (uint64_t)sd.nc) >> 32);
   }
-  int cc = (c[0] * nc + c[1]) * nc + c[2];
+  return sd.cell0 + (c[0] * sd.nc + c[1]) * sd.nc + c[2];
+}
+
+__global__ void k_quantize(int n, const double* __restrict__ xyz, const SysDev* __restrict__ sys,
+                           int nsys, uint32_t* __restrict__ u, int32_t* __restrict__ cell,
+                           int32_t* __restrict__ cell_count, int32_t* __restrict__ info) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int cc = quantize_atom(xyz, i, sys[atom_system(sys, nsys, i)], u, info);
   cell[i] = cc;
   atomicAdd(&cell_count[cc], 1);
 }
 
-// Stable counting sort by cell without global atomics (boxes with at most
+// Stable counting sort by cell without global atomics (plans with at most
 // kMaxHistCells cells): per-block LDS histograms H[c][b], one exclusive scan
 // over H in cell-major order, then each atom's slot is its (cell, block)
 // offset plus its rank among the block's earlier atoms of the same cell.
@@ -95,7 +115,8 @@ constexpr int kHistBlock = 256;
 constexpr int kMaxHistCells = 4096;
 
 __global__ __launch_bounds__(kHistBlock) void k_quantize_hist(int n, const double* __restrict__ xyz,
-                                                              double box, int nc, int ncells,
+                                                              const SysDev* __restrict__ sys,
+                                                              int nsys, int ncells,
                                                               uint32_t* __restrict__ u,
                                                               int32_t* __restrict__ cell,
                                                               int32_t* __restrict__ H,
@@ -105,22 +126,7 @@ __global__ __launch_bounds__(kHistBlock) void k_quantize_hist(int n, const doubl
   __syncthreads();
   const int i = blockIdx.x * kHistBlock + threadIdx.x;
   if (i < n) {
-    int c[3];
-    for (int a = 0; a < 3; ++a) {
-      const double x = xyz[3 * i + a];
-      uint32_t q = 0;
-      if (isfinite(x)) {
-        const double t = x / box;
-        double f = t - floor(t);
-        if (f >= 1.0) f = 0.0;
-        q = (uint32_t)(f * kTwo32);
-      } else {
-        atomicMin(&info[0], (int)TK_E_ARG);
-      }
-      u[3 * i + a] = q;
-      c[a] = (int)(((uint64_t)q * (uint64_t)nc) >> 32);
-    }
-    const int cc = (c[0] * nc + c[1]) * nc + c[2];
+    const int cc = quantize_atom(xyz, i, sys[atom_system(sys, nsys, i)], u, info);
     cell[i] = cc;
     atomicAdd(&hist[cc], 1);
   }
@@ -212,7 +218,9 @@ __global__ void k_cand(int nunits, const Unit* __restrict__ units, const int32_t
 // index owns the pair).
 __global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict__ units,
                                              const int32_t* __restrict__ cstart,
-                                             const uint4* __restrict__ us, PairTest test,
+                                             const uint4* __restrict__ us,
+                                             const SysDev* __restrict__ sys,
+                                             const int32_t* __restrict__ cell_sys,
                                              long pstride, const int64_t* __restrict__ unit_off,
                                              long code_cap, uint32_t* __restrict__ codes,
                                              int32_t* __restrict__ unit_cnt,
@@ -230,6 +238,7 @@ __global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict_
   const int hs = cstart[un.h], nh = cstart[un.h + 1] - hs;
   const int ks = cstart[un.k], nk = cstart[un.k + 1] - ks;
   if (nh > kMaxCellAtoms || nk > kMaxCellAtoms) return;
+  const PairTest test(sys[cell_sys ? cell_sys[un.h] : 0]);
   const bool self = un.h == un.k;
   for (int t = lane; t < nh; t += 64) cH[t] = 0;
   for (int t = lane; t < nk; t += 64) {
@@ -331,6 +340,50 @@ __global__ __launch_bounds__(64) void k_csr_fill(const Unit* __restrict__ units,
   }
 }
 
+// Batch plans: the unit and cell tables of every system, from the per-nc
+// templates, with cell and unit indices offset by the system's first ones.
+struct TplPtrs {
+  const Unit* units;
+  const int32_t* nslot;
+  const int32_t* cu;
+};
+
+__global__ void k_batch_units(int nunits, int nsys, const SysDev* __restrict__ sys,
+                              const TplPtrs* __restrict__ tpl, Unit* __restrict__ out) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nunits) return;
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sys[mid].unit0 <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  const SysDev& d = sys[lo];
+  const Unit t = tpl[lo].units[u - d.unit0];
+  out[u] = Unit{t.h + d.cell0, t.k + d.cell0, t.slot_h, t.slot_k};
+}
+
+__global__ void k_batch_cells(int ncells, int nsys, const SysDev* __restrict__ sys,
+                              const TplPtrs* __restrict__ tpl, int32_t* __restrict__ nslot,
+                              int32_t* __restrict__ cu, int32_t* __restrict__ cell_sys) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sys[mid].cell0 <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const SysDev& d = sys[lo];
+  const int lc = c - d.cell0;
+  nslot[c] = tpl[lo].nslot[lc];
+  cell_sys[c] = lo;
+  const int32_t* e = tpl[lo].cu + (long)lc * kCellUnitStride;
+  int32_t* o = cu + (long)c * kCellUnitStride;
+  o[0] = e[0];
+  for (int j = 0; j < e[0]; ++j) o[1 + j] = ((e[1 + j] >> 2) + d.unit0) * 4 + (e[1 + j] & 3);
+}
+
 // One wave per cell: atoms in its neighbour cells (itself included); the
 // maximum goes to info[5] (staging size of the per-cell mat-vec).
 __global__ __launch_bounds__(64) void k_nbhd(const int32_t* __restrict__ cu,
@@ -423,140 +476,210 @@ __global__ __launch_bounds__(64) void k_rowsort(int n, const int32_t* __restrict
 
 }  // namespace
 
-static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
-                                   double cutoff, int slot, int32_t* row_ptr, int32_t* col,
-                                   int64_t cap, int64_t* npairs_out) {
+// Upload a cells-per-edge template table once.
+static tk_status upload_tables(CellTables& T) {
+  if (T.uploaded) return TK_OK;
+  tk_status s;
+  if ((s = ensure(T.units_d, sizeof(Unit) * T.nunits)) ||
+      (s = ensure(T.nslot_d, sizeof(int32_t) * T.ncells)) ||
+      (s = ensure(T.cu_d, sizeof(int32_t) * T.cu.size())))
+    return s;
+  TK_HIP(hipMemcpy(T.cu_d.p, T.cu.data(), sizeof(int32_t) * T.cu.size(), hipMemcpyHostToDevice));
+  TK_HIP(hipMemcpy(T.units_d.p, T.units.data(), sizeof(Unit) * T.nunits, hipMemcpyHostToDevice));
+  TK_HIP(hipMemcpy(T.nslot_d.p, T.nslot.data(), sizeof(int32_t) * T.ncells, hipMemcpyHostToDevice));
+  T.uploaded = true;
+  return TK_OK;
+}
+
+tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double* xyz,
+                     const PlanSpec& spec, int32_t* row_ptr, int32_t* col, int64_t cap,
+                     int64_t* npairs_out) {
   if (!npairs_out) return TK_E_ARG;
   *npairs_out = 0;
-  tk_status s = check_system(sys);
-  if (s) return s;
-  if (!(cutoff > 0.0) || !std::isfinite(cutoff)) return TK_E_ARG;
-  if (cutoff > 0.5 * sys->box) return TK_E_CUTOFF;
-  if (slot < 0 || slot >= TK_MAX_PLANS || cap < 0) return TK_E_ARG;
+  const int nsys = spec.nsys;
+  if (nsys < 1 || slot < 0 || slot >= kNumPlans || cap < 0 || n < 0) return TK_E_ARG;
   if (col && !row_ptr) return TK_E_ARG;
+  if (n > 0 && !xyz) return TK_E_ARG;
   Plan& P = ctx->plans[slot];
   P.valid = false;
-  const int n = sys->n;
-  int nc = (int)std::floor(sys->box / cutoff);
-  if (nc < 1) nc = 1;
-  CellTables& T = cell_tables(ctx, nc);
-  const uint64_t rq = (uint64_t)std::floor((cutoff / sys->box) * kTwo32);
-  PairTest test;
-  test.rq2 = rq * rq;
-  test.lo = (double)test.rq2 * (1.0 - 0x1p-50);
-  test.hi = (double)test.rq2 * (1.0 + 0x1p-50);
+  // per-system cell grids and exact list tests
+  std::vector<SysDev> sd(nsys + 1);
+  std::vector<CellTables*> tabs(nsys);
+  int ncells = 0, nunits = 0;
+  double est = 16.0 * n + 65536.0;
+  tk_status s;
+  for (int k = 0; k < nsys; ++k) {
+    const double box = spec.box[k], cut = spec.cutoff[k];
+    const int na = spec.atom0[k + 1] - spec.atom0[k];
+    if (!(box > 0.0) || !std::isfinite(box) || !(cut > 0.0) || !std::isfinite(cut) || na < 0)
+      return TK_E_ARG;
+    if (cut > 0.5 * box) return TK_E_CUTOFF;
+    int nc = (int)std::floor(box / cut);
+    if (nc < 1) nc = 1;
+    CellTables& T = cell_tables(ctx, nc);
+    if ((s = upload_tables(T))) return s;
+    tabs[k] = &T;
+    const uint64_t rq = (uint64_t)std::floor((cut / box) * kTwo32);
+    SysDev& d = sd[k];
+    d.box = box;
+    d.inv_box = 1.0 / box;
+    d.rq2 = rq * rq;
+    d.lo = (double)d.rq2 * (1.0 - 0x1p-50);
+    d.hi = (double)d.rq2 * (1.0 + 0x1p-50);
+    d.nc = nc;
+    d.cell0 = ncells;
+    d.unit0 = nunits;
+    d.atom0 = spec.atom0[k];
+    ncells += T.ncells;
+    nunits += T.nunits;
+    // candidate windows: sum over units of |H||K|, estimated from the density
+    // (the buffer grows, and the enumeration reruns, if the estimate is short)
+    const double mean = (double)na / T.ncells;
+    est += 1.15 * (double)T.nunits * mean * mean;
+  }
+  if (spec.atom0[0] != 0 || spec.atom0[nsys] != n) return TK_E_ARG;
+  sd[nsys] = SysDev{};
+  sd[nsys].cell0 = ncells;
+  sd[nsys].unit0 = nunits;
+  sd[nsys].atom0 = n;
   const int nn = n > 0 ? n : 1;
   const long pstride = (nn + 63) / 64 * 64;
   const bool want_csr = row_ptr != nullptr;
-
-  // device copies of the cell tables (uploaded once per cells-per-edge value)
-  if (!T.uploaded) {
-    if ((s = ensure(T.units_d, sizeof(Unit) * T.nunits)) ||
-        (s = ensure(T.nslot_d, sizeof(int32_t) * T.ncells)) ||
-        (s = ensure(T.cu_d, sizeof(int32_t) * T.cu.size())))
-      return s;
-    TK_HIP(hipMemcpy(T.cu_d.p, T.cu.data(), sizeof(int32_t) * T.cu.size(), hipMemcpyHostToDevice));
-    TK_HIP(hipMemcpy(T.units_d.p, T.units.data(), sizeof(Unit) * T.nunits, hipMemcpyHostToDevice));
-    TK_HIP(hipMemcpy(T.nslot_d.p, T.nslot.data(), sizeof(int32_t) * T.ncells, hipMemcpyHostToDevice));
-    T.uploaded = true;
-  }
   if ((s = ensure(P.perm, sizeof(int32_t) * nn)) || (s = ensure(P.scell, sizeof(int32_t) * nn)) ||
-      (s = ensure(P.cell_start, sizeof(int32_t) * (T.ncells + 1))) ||
-      (s = ensure(P.unit_off, sizeof(int64_t) * (T.nunits + 1))) ||
-      (s = ensure(P.unit_cnt, sizeof(int32_t) * T.nunits)) ||
+      (s = ensure(P.cell_start, sizeof(int32_t) * (ncells + 1))) ||
+      (s = ensure(P.unit_off, sizeof(int64_t) * (nunits + 1))) ||
+      (s = ensure(P.unit_cnt, sizeof(int32_t) * nunits)) ||
       (s = ensure(P.us, sizeof(uint4) * nn)) ||
-      (s = ensure(P.slots, sizeof(int32_t) * kMaxSlots * pstride)))
+      (s = ensure(P.slots, sizeof(int32_t) * kMaxSlots * pstride)) ||
+      (s = ensure(P.sysd, sizeof(SysDev) * (nsys + 1))))
     return s;
-  // candidate windows: sum over units of |H||K|, estimated from the density
-  // (the buffer grows, and the enumeration reruns, if the estimate is short)
-  const double mean = (double)n / T.ncells;
-  const double est = 1.15 * (double)T.nunits * mean * mean + 16.0 * n + 65536.0;
   if (P.codes.bytes < sizeof(uint32_t) * (size_t)est &&
       (s = ensure(P.codes, sizeof(uint32_t) * (size_t)est)))
     return s;
   void *u, *cell, *ccount, *cursor, *tmp, *info, *cand, *rcnt, *rptr;
   if ((s = scratch(ctx, "nb_u", sizeof(uint32_t) * 3 * nn, &u)) ||
       (s = scratch(ctx, "nb_cell", sizeof(int32_t) * nn, &cell)) ||
-      (s = scratch(ctx, "nb_ccount", sizeof(int32_t) * (T.ncells + 1), &ccount)) ||
-      (s = scratch(ctx, "nb_cursor", sizeof(int32_t) * T.ncells, &cursor)) ||
+      (s = scratch(ctx, "nb_ccount", sizeof(int32_t) * (ncells + 1), &ccount)) ||
+      (s = scratch(ctx, "nb_cursor", sizeof(int32_t) * ncells, &cursor)) ||
       (s = scratch(ctx, "nb_tmp", sizeof(int32_t) * nn, &tmp)) ||
       (s = scratch(ctx, "nb_info", sizeof(int32_t) * 8, &info)) ||
-      (s = scratch(ctx, "nb_cand", sizeof(int64_t) * (T.nunits + 1), &cand)) ||
+      (s = scratch(ctx, "nb_cand", sizeof(int64_t) * (nunits + 1), &cand)) ||
       (s = scratch(ctx, "nb_rcnt", sizeof(int32_t) * (nn + 1), &rcnt)) ||
       (s = scratch(ctx, "nb_rptr", sizeof(int32_t) * (nn + 1), &rptr)))
     return s;
+  // pinned staging: [0, 4096) readback; then the system table
+  const size_t sys_bytes = sizeof(SysDev) * (nsys + 1);
+  const size_t tpl_off = 4096 + sys_bytes;
+  const size_t stage_bytes = tpl_off + sizeof(TplPtrs) * nsys;
+  char *hb, *hdb;
+  if ((s = pinned(ctx, stage_bytes, (void**)&hb, (void**)&hdb))) return s;
+  int32_t* h = (int32_t*)hb;
+  int32_t* hd = (int32_t*)hdb;
+  // the previous build's readback of this context has been consumed (every
+  // build synchronises before returning), so the staging area is free
+  std::memcpy(hb + 4096, sd.data(), sys_bytes);
+  TK_HIP(hipMemcpyAsync(P.sysd.p, hb + 4096, sys_bytes, hipMemcpyHostToDevice, st));
+  const SysDev* sysd = (const SysDev*)P.sysd.p;
+  const Unit* units;
+  const int32_t *nslot, *cu, *cell_sys = nullptr;
+  if (nsys == 1) {
+    units = (const Unit*)tabs[0]->units_d.p;
+    nslot = (const int32_t*)tabs[0]->nslot_d.p;
+    cu = (const int32_t*)tabs[0]->cu_d.p;
+  } else {
+    TplPtrs* tp = (TplPtrs*)(hb + tpl_off);
+    for (int k = 0; k < nsys; ++k)
+      tp[k] = TplPtrs{(const Unit*)tabs[k]->units_d.p, (const int32_t*)tabs[k]->nslot_d.p,
+                      (const int32_t*)tabs[k]->cu_d.p};
+    if ((s = ensure(P.tplp, sizeof(TplPtrs) * nsys)) ||
+        (s = ensure(P.bunits, sizeof(Unit) * nunits)) ||
+        (s = ensure(P.bnslot, sizeof(int32_t) * ncells)) ||
+        (s = ensure(P.bcu, sizeof(int32_t) * kCellUnitStride * (size_t)ncells)) ||
+        (s = ensure(P.cell_sys, sizeof(int32_t) * ncells)))
+      return s;
+    TK_HIP(hipMemcpyAsync(P.tplp.p, tp, sizeof(TplPtrs) * nsys, hipMemcpyHostToDevice, st));
+    k_batch_units<<<ceil_div(nunits, 256), 256, 0, st>>>(nunits, nsys, sysd,
+                                                         (const TplPtrs*)P.tplp.p,
+                                                         (Unit*)P.bunits.p);
+    k_batch_cells<<<ceil_div(ncells, 256), 256, 0, st>>>(ncells, nsys, sysd,
+                                                         (const TplPtrs*)P.tplp.p,
+                                                         (int32_t*)P.bnslot.p, (int32_t*)P.bcu.p,
+                                                         (int32_t*)P.cell_sys.p);
+    units = (const Unit*)P.bunits.p;
+    nslot = (const int32_t*)P.bnslot.p;
+    cu = (const int32_t*)P.bcu.p;
+    cell_sys = (const int32_t*)P.cell_sys.p;
+  }
   TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
   const int32_t* cstart = (const int32_t*)P.cell_start.p;
-  const Unit* units = (const Unit*)T.units_d.p;
   int32_t* rp = want_csr ? row_ptr : (int32_t*)rptr;
-  int32_t *h, *hd;
-  if ((s = pinned(ctx, 4096, (void**)&h, (void**)&hd))) return s;
-  if (n > 0 && T.ncells <= kMaxHistCells) {
+  if (n > 0 && ncells <= kMaxHistCells) {
     const int nblk = ceil_div(n, kHistBlock);
-    const long hl = (long)T.ncells * nblk;
+    const long hl = (long)ncells * nblk;
     void *H, *Hoff;
     if ((s = scratch(ctx, "nb_hist", sizeof(int32_t) * hl, &H)) ||
         (s = scratch(ctx, "nb_hist_off", sizeof(int32_t) * (hl + 1), &Hoff)))
       return s;
     {
       ProfScope ps(ctx, st, "nblist_quantize");
-      k_quantize_hist<<<nblk, kHistBlock, 0, st>>>(n, sys->xyz, sys->box, nc, T.ncells,
-                                                    (uint32_t*)u, (int32_t*)cell, (int32_t*)H,
-                                                    (int32_t*)info);
+      k_quantize_hist<<<nblk, kHistBlock, 0, st>>>(n, xyz, sysd, nsys, ncells, (uint32_t*)u,
+                                                    (int32_t*)cell, (int32_t*)H, (int32_t*)info);
     }
     if ((s = scan_i32(ctx, st, (int32_t*)H, (int32_t*)Hoff, (int)hl))) return s;
     {
       ProfScope ps(ctx, st, "nblist_cellsort");
-      k_scatter_stable<<<nblk, kHistBlock, 0, st>>>(n, T.ncells, (int32_t*)cell, (int32_t*)Hoff,
+      k_scatter_stable<<<nblk, kHistBlock, 0, st>>>(n, ncells, (int32_t*)cell, (int32_t*)Hoff,
                                                      (uint32_t*)u, (int32_t*)P.perm.p,
                                                      (int32_t*)P.scell.p, (uint4*)P.us.p,
                                                      (int32_t*)P.cell_start.p, (int32_t*)info);
     }
   } else if (n > 0) {
-    TK_HIP(hipMemsetAsync(ccount, 0, sizeof(int32_t) * (T.ncells + 1), st));
-    TK_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * T.ncells, st));
+    TK_HIP(hipMemsetAsync(ccount, 0, sizeof(int32_t) * (ncells + 1), st));
+    TK_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * ncells, st));
     {
       ProfScope ps(ctx, st, "nblist_quantize");
-      k_quantize<<<ceil_div(n, 256), 256, 0, st>>>(n, sys->xyz, sys->box, nc, (uint32_t*)u,
-                                                    (int32_t*)cell, (int32_t*)ccount, (int32_t*)info);
+      k_quantize<<<ceil_div(n, 256), 256, 0, st>>>(n, xyz, sysd, nsys, (uint32_t*)u,
+                                                    (int32_t*)cell, (int32_t*)ccount,
+                                                    (int32_t*)info);
     }
-    if ((s = scan_i32(ctx, st, (int32_t*)ccount, (int32_t*)P.cell_start.p, T.ncells))) return s;
+    if ((s = scan_i32(ctx, st, (int32_t*)ccount, (int32_t*)P.cell_start.p, ncells))) return s;
     k_scatter<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)cell, cstart, (int32_t*)cursor,
                                                  (int32_t*)tmp);
     {
       ProfScope ps(ctx, st, "nblist_cellsort");
-      k_cellsort<<<T.ncells, 64, 0, st>>>(cstart, (int32_t*)tmp, (uint32_t*)u, (int32_t*)P.perm.p,
-                                          (int32_t*)P.scell.p, (uint4*)P.us.p, (int32_t*)info);
+      k_cellsort<<<ncells, 64, 0, st>>>(cstart, (int32_t*)tmp, (uint32_t*)u, (int32_t*)P.perm.p,
+                                        (int32_t*)P.scell.p, (uint4*)P.us.p, (int32_t*)info);
     }
   } else {
-    TK_HIP(hipMemsetAsync(P.cell_start.p, 0, sizeof(int32_t) * (T.ncells + 1), st));
+    TK_HIP(hipMemsetAsync(P.cell_start.p, 0, sizeof(int32_t) * (ncells + 1), st));
   }
   if (n > 0) {
-    k_cand<<<ceil_div(T.nunits, 256), 256, 0, st>>>(T.nunits, units, cstart, (int64_t*)cand);
-    if ((s = scan_i64(ctx, st, (int64_t*)cand, (int64_t*)P.unit_off.p, T.nunits))) return s;
+    k_cand<<<ceil_div(nunits, 256), 256, 0, st>>>(nunits, units, cstart, (int64_t*)cand);
+    if ((s = scan_i64(ctx, st, (int64_t*)cand, (int64_t*)P.unit_off.p, nunits))) return s;
   }
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (n > 0) {
-      k_nbhd<<<T.ncells, 64, 0, st>>>((const int32_t*)T.cu_d.p, units, cstart, (int32_t*)info);
+      k_nbhd<<<ncells, 64, 0, st>>>(cu, units, cstart, (int32_t*)info);
       {
         ProfScope ps(ctx, st, "nblist_plan");
-        k_plan<<<T.nunits, 64, 0, st>>>(T.nunits, units, cstart, (uint4*)P.us.p, test, pstride,
-                                        (int64_t*)P.unit_off.p, (long)(P.codes.bytes / 4),
-                                        (uint32_t*)P.codes.p, (int32_t*)P.unit_cnt.p,
-                                        (int32_t*)P.slots.p, (int32_t*)info);
+        k_plan<<<nunits, 64, 0, st>>>(nunits, units, cstart, (uint4*)P.us.p, sysd, cell_sys,
+                                      pstride, (int64_t*)P.unit_off.p,
+                                      (long)(P.codes.bytes / 4), (uint32_t*)P.codes.p,
+                                      (int32_t*)P.unit_cnt.p, (int32_t*)P.slots.p,
+                                      (int32_t*)info);
       }
       k_row_slots<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)P.perm.p, (int32_t*)P.scell.p,
-                                                     (int32_t*)T.nslot_d.p, pstride,
-                                                     (int32_t*)P.slots.p, (int32_t*)rcnt,
-                                                     (int32_t*)info);
+                                                     nslot, pstride, (int32_t*)P.slots.p,
+                                                     (int32_t*)rcnt, (int32_t*)info);
       if ((s = scan_i32(ctx, st, (int32_t*)rcnt, rp, n))) return s;
     } else {
-      TK_HIP(hipMemsetAsync(P.unit_cnt.p, 0, sizeof(int32_t) * T.nunits, st));
-      TK_HIP(hipMemsetAsync(P.unit_off.p, 0, sizeof(int64_t) * (T.nunits + 1), st));
+      TK_HIP(hipMemsetAsync(P.unit_cnt.p, 0, sizeof(int32_t) * nunits, st));
+      TK_HIP(hipMemsetAsync(P.unit_off.p, 0, sizeof(int64_t) * (nunits + 1), st));
       TK_HIP(hipMemsetAsync(rp, 0, sizeof(int32_t), st));
     }
-    // one readback: status, max occupancy, max row, pairs, window overflow, list total
-    k_readback<<<1, 1, 0, st>>>((int32_t*)info, rp + n, (int64_t*)P.unit_off.p + T.nunits, hd);
+    // one readback: status, max occupancy, max row, pairs, window overflow,
+    // max neighbourhood, list total
+    k_readback<<<1, 1, 0, st>>>((int32_t*)info, rp + n, (int64_t*)P.unit_off.p + nunits, hd);
     TK_HIP(hipGetLastError());
     TK_HIP(hipStreamSynchronize(st));
     if (h[0] != 0) return h[0];
@@ -582,9 +705,9 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
     if (n > 0 && list_pairs > 0) {
       {
         ProfScope ps(ctx, st, "nblist_csr_fill");
-        k_csr_fill<<<T.nunits, 64, 0, st>>>(units, cstart, (int32_t*)P.perm.p, pstride,
-                                            (int64_t*)P.unit_off.p, (int32_t*)P.unit_cnt.p,
-                                            (uint32_t*)P.codes.p, (int32_t*)P.slots.p, rp, col);
+        k_csr_fill<<<nunits, 64, 0, st>>>(units, cstart, (int32_t*)P.perm.p, pstride,
+                                          (int64_t*)P.unit_off.p, (int32_t*)P.unit_cnt.p,
+                                          (uint32_t*)P.codes.p, (int32_t*)P.slots.p, rp, col);
       }
       {
         ProfScope ps(ctx, st, "nblist_rowsort");
@@ -595,19 +718,35 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
   TK_HIP(hipGetLastError());
   P.valid = true;
   P.n = n;
-  P.box = sys->box;
-  P.cutoff = cutoff;
-  P.nc = nc;
-  P.ncells = T.ncells;
-  P.nunits = T.nunits;
+  P.nsys = nsys;
+  P.h_sys = sd;
+  P.box = spec.box[0];
+  P.cutoff = spec.cutoff[0];
+  P.nc = sd[0].nc;
+  P.ncells = ncells;
+  P.nunits = nunits;
   P.max_occ = h[1];
   P.max_row = max_row;
   P.max_nbhd = h[5];
-  P.cu_p = (const int32_t*)T.cu_d.p;
   P.npairs = list_pairs;
   P.units_p = units;
-  P.nslot_p = (const int32_t*)T.nslot_d.p;
+  P.nslot_p = nslot;
+  P.cu_p = cu;
   return TK_OK;
+}
+
+static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
+                                   double cutoff, int slot, int32_t* row_ptr, int32_t* col,
+                                   int64_t cap, int64_t* npairs_out) {
+  if (!npairs_out) return TK_E_ARG;
+  *npairs_out = 0;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (!(cutoff > 0.0) || !std::isfinite(cutoff)) return TK_E_ARG;
+  if (slot < 0 || slot >= TK_MAX_PLANS) return TK_E_ARG;
+  const int32_t atom0[2] = {0, sys->n};
+  PlanSpec spec{1, atom0, &sys->box, &cutoff};
+  return build_plan(ctx, st, slot, sys->n, sys->xyz, spec, row_ptr, col, cap, npairs_out);
 }
 
 }  // namespace tk

@@ -49,6 +49,10 @@ __global__ __launch_bounds__(64) void k_units(PlanView pv, Ph ph, double* __rest
   const int u = blockIdx.x;
   const int lane = threadIdx.x;
   const Unit un = pv.units[u];
+  if (pv.nsys > 1) {   // batch: this unit's system geometry
+    const int sy = pv.cell_sys[un.h];
+    ph.set_sys(pv.sys[sy], sy);
+  }
   const int hs = pv.cell_start[un.h], nh = pv.cell_start[un.h + 1] - hs;
   const int ks = pv.cell_start[un.k], nk = pv.cell_start[un.k + 1] - ks;
   const int cap = pv.max_occ;
@@ -129,22 +133,25 @@ __global__ __launch_bounds__(256) void k_reduce(PlanView pv, const double* __res
   epi(s, pv.perm[s], acc);
 }
 
-// Sum per-unit scalar records in a fixed order: out[k] = sum_u uscal[u][k];
-// one block per scalar.
+// Sum per-unit scalar records in a fixed order, per system:
+// out[s][k] = sum over the units u of system s of uscal[u][k]; one block per
+// (scalar, system).
 template <int NS>
-__global__ __launch_bounds__(256) void k_sum_units(const double* __restrict__ uscal, int nunits,
+__global__ __launch_bounds__(256) void k_sum_units(const double* __restrict__ uscal,
+                                                   const SysDev* __restrict__ sys,
                                                    double* __restrict__ out) {
   __shared__ double sh[256];
-  const int k = blockIdx.x;
+  const int k = blockIdx.x, sy = blockIdx.y;
+  const int u0 = sys[sy].unit0, u1 = sys[sy + 1].unit0;
   double v = 0.0;
-  for (int u = threadIdx.x; u < nunits; u += 256) v += uscal[(long)u * NS + k];
+  for (int u = u0 + threadIdx.x; u < u1; u += 256) v += uscal[(long)u * NS + k];
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[k] = sh[0];
+  if (threadIdx.x == 0) out[(long)sy * NS + k] = sh[0];
 }
 
 template <class Ph>

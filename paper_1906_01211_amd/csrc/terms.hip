@@ -10,17 +10,32 @@ namespace tk {
 
 namespace {
 
-__global__ void k_finish_energy3(const double* __restrict__ sums, double* energy, double* virial) {
-  energy[0] = sums[0] + sums[1];
-  energy[1] = sums[0];
-  energy[2] = sums[1];
-  for (int k = 0; k < 9; ++k) virial[k] = sums[2 + k];
+}  // namespace
+
+// Per system: energy[3] = (total, non-excluded, exclusion correction) and the
+// virial from the 11 unit sums.
+__global__ void k_finish_energy3(int nsys, const double* __restrict__ sums, double* energy,
+                                 double* virial) {
+  const int sy = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sy >= nsys) return;
+  const double* sm = sums + 11 * sy;
+  energy[3 * sy] = sm[0] + sm[1];
+  energy[3 * sy + 1] = sm[0];
+  energy[3 * sy + 2] = sm[1];
+  for (int k = 0; k < 9; ++k) virial[9 * sy + k] = sm[2 + k];
 }
 
-__global__ void k_finish_energy1(const double* __restrict__ sums, double* energy, double* virial) {
-  energy[0] = sums[0];
-  for (int k = 0; k < 9; ++k) virial[k] = sums[1 + k];
+// Per system: energy and virial from the 10 unit sums.
+__global__ void k_finish_energy1(int nsys, const double* __restrict__ sums, double* energy,
+                                 double* virial) {
+  const int sy = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sy >= nsys) return;
+  const double* sm = sums + 10 * sy;
+  energy[sy] = sm[0];
+  for (int k = 0; k < 9; ++k) virial[9 * sy + k] = sm[1 + k];
 }
+
+namespace {
 
 tk_status common_args(tk_ctx* ctx, const tk_system* sys, const tk_nblist* list, double cutoff,
                       int prec, const Plan** plan) {
@@ -86,7 +101,7 @@ tk_status tk_empole_real(tk_ctx* ctx, void* stream, const tk_system* sys, const 
     s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
   }
   if (s) return s;
-  k_finish_energy3<<<1, 1, 0, st>>>((double*)sums, energy, virial);
+  k_finish_energy3<<<1, 64, 0, st>>>(1, (double*)sums, energy, virial);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }
@@ -119,7 +134,7 @@ tk_status tk_echarge_real(tk_ctx* ctx, void* stream, const tk_system* sys, const
     s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
   }
   if (s) return s;
-  k_finish_energy3<<<1, 1, 0, st>>>((double*)sums, energy, virial);
+  k_finish_energy3<<<1, 64, 0, st>>>(1, (double*)sums, energy, virial);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }
@@ -188,7 +203,7 @@ tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nbli
     s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
   }
   if (s) return s;
-  k_finish_energy1<<<1, 1, 0, st>>>((double*)sums, energy, virial);
+  k_finish_energy1<<<1, 64, 0, st>>>(1, (double*)sums, energy, virial);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }

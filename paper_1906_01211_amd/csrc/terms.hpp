@@ -6,8 +6,10 @@
 // float the pair vector is formed in FP64 from the FP64 coordinates, the
 // cutoff test stays in FP64 (identical pair decisions in both precisions),
 // radial functions of same-molecule pairs are evaluated in FP64 (their
-// screened-minus-bare differences cancel badly), and every accumulation
-// (LDS atomics, energies, virial) is FP64.
+// screened-minus-bare differences cancel badly), pairs closer than 2 A are
+// evaluated entirely in FP64 (their large forces would carry FP32 rounding of
+// the same relative size), and every accumulation (LDS atomics, energies,
+// virial) is FP64.
 #pragma once
 
 #include <type_traits>
@@ -16,6 +18,10 @@
 #include "pairs.hpp"
 
 namespace tk {
+
+// Mixed form: pairs closer than 2 A (contacts; their forces are large, and
+// FP32 rounding scales with them) are evaluated entirely in FP64.
+constexpr double kMixedCloseR2 = 4.0;
 
 template <class R>
 inline const char* prec_tag() { return std::is_same<R, double>::value ? "_fp64" : "_fp32"; }
@@ -120,6 +126,10 @@ struct EmpolePh {
   const double* mpole;
   const int32_t* molid;
   Geom g;
+  __device__ void set_sys(const SysDev& d, int) {
+    g.box = d.box;
+    g.inv_box = d.inv_box;
+  }
     static constexpr int NG = 14;   // fields gathered once per call (sorted SoA)
   const double* sorted = nullptr;
   long gstride = 0;
@@ -131,62 +141,72 @@ struct EmpolePh {
     for (int k = 0; k < 10; ++k) g[3 + k] = mpole[10 * i + k];
     g[13] = (double)molid[i];
   }
+  // pair energy and de/dr in arithmetic type T
+  template <class T>
+  __device__ __forceinline__ void eval(const double* LH, const double* LK, int cap, int a, int b,
+                                       const double* dd, double r2, bool excl, double* de,
+                                       double& en) const {
+    T B[6], Rb[6];
+    radial_pair<T, 5>(g, r2, excl, B, Rb);
+    T gg[6];
+#pragma unroll
+    for (int n = 0; n < 6; ++n) gg[n] = excl ? B[n] - Rb[n] : B[n];
+    const T d[3] = {T(dd[0]), T(dd[1]), T(dd[2])};
+    const T qi = T(LH[3 * cap + a]), qj = T(LK[3 * cap + b]);
+    const T ui[3] = {T(LH[4 * cap + a]), T(LH[5 * cap + a]), T(LH[6 * cap + a])};
+    const T uj[3] = {T(LK[4 * cap + b]), T(LK[5 * cap + b]), T(LK[6 * cap + b])};
+    // Theta as 6 unique components xx xy xz yy yz zz
+    const T ti[6] = {T(LH[7 * cap + a]), T(LH[8 * cap + a]), T(LH[9 * cap + a]),
+                     T(LH[10 * cap + a]), T(LH[11 * cap + a]), T(LH[12 * cap + a])};
+    const T tj[6] = {T(LK[7 * cap + b]), T(LK[8 * cap + b]), T(LK[9 * cap + b]),
+                     T(LK[10 * cap + b]), T(LK[11 * cap + b]), T(LK[12 * cap + b])};
+    auto tmul = [](const T* t, const T* x, T* y) {
+      y[0] = t[0] * x[0] + t[1] * x[1] + t[2] * x[2];
+      y[1] = t[1] * x[0] + t[3] * x[1] + t[4] * x[2];
+      y[2] = t[2] * x[0] + t[4] * x[1] + t[5] * x[2];
+    };
+    auto dot = [](const T* x, const T* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+    T vi[3], vj[3];
+    tmul(ti, d, vi);
+    tmul(tj, d, vj);
+    const T di = dot(ui, d), dj = dot(uj, d), Qi = dot(d, vi), Qj = dot(d, vj);
+    const T tt = ti[0] * tj[0] + ti[3] * tj[3] + ti[5] * tj[5] +
+                 T(2) * (ti[1] * tj[1] + ti[2] * tj[2] + ti[4] * tj[4]);
+    const T c0 = qi * qj;
+    const T c1 = qj * di - qi * dj + dot(ui, uj);
+    const T c2 = qi * Qj + qj * Qi - di * dj + T(2) * (dot(uj, vi) - dot(ui, vj) + tt);
+    const T c3 = di * Qj - dj * Qi - T(4) * dot(vi, vj);
+    const T c4 = Qi * Qj;
+    T tiuj[3], tjui[3], tivj[3], tjvi[3];
+    tmul(ti, uj, tiuj);
+    tmul(tj, ui, tjui);
+    tmul(ti, vj, tivj);
+    tmul(tj, vi, tjvi);
+    const T e = c0 * gg[0] + c1 * gg[1] + c2 * gg[2] + c3 * gg[3] + c4 * gg[4];
+    const T sr = c0 * gg[1] + c1 * gg[2] + c2 * gg[3] + c3 * gg[4] + c4 * gg[5];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T dc1 = qj * ui[c] - qi * uj[c];
+      const T dc2 = T(2) * (qi * vj[c] + qj * vi[c]) - dj * ui[c] - di * uj[c] +
+                    T(2) * (tiuj[c] - tjui[c]);
+      const T dc3 = Qj * ui[c] + T(2) * di * vj[c] - Qi * uj[c] - T(2) * dj * vi[c] -
+                    T(4) * (tivj[c] + tjvi[c]);
+      const T dc4 = T(2) * (Qj * vi[c] + Qi * vj[c]);
+      de[c] = kCoulomb * (double)(dc1 * gg[1] + dc2 * gg[2] + dc3 * gg[3] + dc4 * gg[4] - sr * d[c]);
+    }
+    en = kCoulomb * (double)e;
+  }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
                        double* AK, double* sc, long) const {
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
     if (!(r2 <= g.rc2)) return;
     const bool excl = LH[13 * cap + a] == LK[13 * cap + b];
-    R B[6], Rb[6];
-    radial_pair<R, 5>(g, r2, excl, B, Rb);
-    R gg[6];
-#pragma unroll
-    for (int n = 0; n < 6; ++n) gg[n] = excl ? B[n] - Rb[n] : B[n];
-    const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
-    const R qi = R(LH[3 * cap + a]), qj = R(LK[3 * cap + b]);
-    const R ui[3] = {R(LH[4 * cap + a]), R(LH[5 * cap + a]), R(LH[6 * cap + a])};
-    const R uj[3] = {R(LK[4 * cap + b]), R(LK[5 * cap + b]), R(LK[6 * cap + b])};
-    // Theta as 6 unique components xx xy xz yy yz zz
-    const R ti[6] = {R(LH[7 * cap + a]), R(LH[8 * cap + a]), R(LH[9 * cap + a]),
-                     R(LH[10 * cap + a]), R(LH[11 * cap + a]), R(LH[12 * cap + a])};
-    const R tj[6] = {R(LK[7 * cap + b]), R(LK[8 * cap + b]), R(LK[9 * cap + b]),
-                     R(LK[10 * cap + b]), R(LK[11 * cap + b]), R(LK[12 * cap + b])};
-    auto tmul = [](const R* t, const R* x, R* y) {
-      y[0] = t[0] * x[0] + t[1] * x[1] + t[2] * x[2];
-      y[1] = t[1] * x[0] + t[3] * x[1] + t[4] * x[2];
-      y[2] = t[2] * x[0] + t[4] * x[1] + t[5] * x[2];
-    };
-    auto dot = [](const R* x, const R* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
-    R vi[3], vj[3];
-    tmul(ti, d, vi);
-    tmul(tj, d, vj);
-    const R di = dot(ui, d), dj = dot(uj, d), Qi = dot(d, vi), Qj = dot(d, vj);
-    const R tt = ti[0] * tj[0] + ti[3] * tj[3] + ti[5] * tj[5] +
-                 R(2) * (ti[1] * tj[1] + ti[2] * tj[2] + ti[4] * tj[4]);
-    const R c0 = qi * qj;
-    const R c1 = qj * di - qi * dj + dot(ui, uj);
-    const R c2 = qi * Qj + qj * Qi - di * dj + R(2) * (dot(uj, vi) - dot(ui, vj) + tt);
-    const R c3 = di * Qj - dj * Qi - R(4) * dot(vi, vj);
-    const R c4 = Qi * Qj;
-    R tiuj[3], tjui[3], tivj[3], tjvi[3];
-    tmul(ti, uj, tiuj);
-    tmul(tj, ui, tjui);
-    tmul(ti, vj, tivj);
-    tmul(tj, vi, tjvi);
-    const R e = c0 * gg[0] + c1 * gg[1] + c2 * gg[2] + c3 * gg[3] + c4 * gg[4];
-    const R sr = c0 * gg[1] + c1 * gg[2] + c2 * gg[3] + c3 * gg[4] + c4 * gg[5];
-    double de[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const R dc1 = qj * ui[c] - qi * uj[c];
-      const R dc2 = R(2) * (qi * vj[c] + qj * vi[c]) - dj * ui[c] - di * uj[c] +
-                    R(2) * (tiuj[c] - tjui[c]);
-      const R dc3 = Qj * ui[c] + R(2) * di * vj[c] - Qi * uj[c] - R(2) * dj * vi[c] -
-                    R(4) * (tivj[c] + tjvi[c]);
-      const R dc4 = R(2) * (Qj * vi[c] + Qi * vj[c]);
-      de[c] = kCoulomb * (double)(dc1 * gg[1] + dc2 * gg[2] + dc3 * gg[3] + dc4 * gg[4] - sr * d[c]);
-    }
-    const double en = kCoulomb * (double)e;
+    double de[3], en;
+    if (std::is_same<R, float>::value && r2 < kMixedCloseR2)
+      eval<double>(LH, LK, cap, a, b, dd, r2, excl, de, en);
+    else
+      eval<R>(LH, LK, cap, a, b, dd, r2, excl, de, en);
     sc[excl ? 1 : 0] += en;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -211,6 +231,10 @@ struct ChargePh {
   const double* q;
   const int32_t* molid;
   Geom g;
+  __device__ void set_sys(const SysDev& d, int) {
+    g.box = d.box;
+    g.inv_box = d.inv_box;
+  }
     static constexpr int NG = 5;   // fields gathered once per call (sorted SoA)
   const double* sorted = nullptr;
   long gstride = 0;
@@ -227,23 +251,26 @@ struct ChargePh {
     const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
     if (!(r2 <= g.rc2)) return;
     const bool excl = LH[4 * cap + a] == LK[4 * cap + b];
-    R B[2], Rb[2];
-    radial_pair<R, 1>(g, r2, excl, B, Rb);
-    const R g1 = excl ? B[1] - Rb[1] : B[1];
-    double g0;
-    if (std::is_same<R, float>::value && !excl) {
+    double g0, g1;
+    if (std::is_same<R, float>::value && !excl && !(r2 < kMixedCloseR2)) {
+      R B[2], Rb[2];
+      radial_pair<R, 1>(g, r2, false, B, Rb);
+      g1 = (double)B[1];
       // the energy of a point-charge system is a large cancelling sum: its
       // screened pair term is evaluated in FP64 even in the mixed form
       double B0d[1], R0d[1];
       const double ri = rsqrt_r(r2);
       radial<double, 0>(g, r2 * ri, ri, B0d, R0d, r2);
       g0 = B0d[0];
-    } else {
-      g0 = (double)(excl ? B[0] - Rb[0] : B[0]);
+    } else {   // FP64 form; in the mixed form also excluded and close pairs
+      double B[2], Rb[2];
+      radial_pair<double, 1>(g, r2, excl, B, Rb);
+      g0 = excl ? B[0] - Rb[0] : B[0];
+      g1 = excl ? B[1] - Rb[1] : B[1];
     }
     const double qq = kCoulomb * LH[3 * cap + a] * LK[3 * cap + b];
     const double en = qq * g0;
-    const double f = -qq * (double)g1;
+    const double f = -qq * g1;
     sc[excl ? 1 : 0] += en;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -271,6 +298,10 @@ struct EfieldPh {
   const double* polarity;
   const double* thole;
   Geom g;
+  __device__ void set_sys(const SysDev& d, int) {
+    g.box = d.box;
+    g.inv_box = d.inv_box;
+  }
     static constexpr int NG = 16;   // fields gathered once per call (sorted SoA)
   const double* sorted = nullptr;
   long gstride = 0;
@@ -291,6 +322,74 @@ struct EfieldPh {
   using GC = R;
   GC* gc = nullptr;
   long gcs = 0;
+  // field contributions at both atoms (fi at H's atom, fj at K's) in type T
+  template <class T>
+  __device__ __forceinline__ void eval(const double* LH, const double* LK, int cap, int a, int b,
+                                       const double* dd, double r2, bool excl, double* fi,
+                                       double* fj, long p) const {
+    T B[4], Rb[4];
+    radial_pair<T, 3>(g, r2, excl, B, Rb);
+    T g1, g2, g3;
+    T l3, l5, l7;
+    if (!excl || gc) {
+      const T r = T(r2) * rsqrt_r(T(r2));
+      thole_damp<T>(r, T(LH[14 * cap + a]), T(LK[14 * cap + b]), T(LH[15 * cap + a]),
+                    T(LK[15 * cap + b]), l3, l5, l7);
+    }
+    if (excl) {
+      g1 = B[1] - Rb[1];
+      g2 = B[2] - Rb[2];
+      g3 = B[3] - Rb[3];
+      if (gc) {
+        if (std::is_same<T, float>::value) {
+          // B carries the FP64 difference B - R; re-add the damped bare part in FP64
+          const double ri = rsqrt_r(r2);
+          const double R1 = ri * ri * ri, R2 = 3.0 * R1 * ri * ri;
+          gc[p] = GC((double)B[1] + (double)l3 * R1);
+          gc[gcs + p] = GC((double)B[2] + (double)l5 * R2);
+        } else {
+          gc[p] = GC(B[1] - (T(1) - l3) * Rb[1]);
+          gc[gcs + p] = GC(B[2] - (T(1) - l5) * Rb[2]);
+        }
+      }
+    } else {
+      g1 = B[1] - (T(1) - l3) * Rb[1];
+      g2 = B[2] - (T(1) - l5) * Rb[2];
+      g3 = B[3] - (T(1) - l7) * Rb[3];
+      if (gc) {
+        gc[p] = GC(g1);
+        gc[gcs + p] = GC(g2);
+      }
+    }
+    const T d[3] = {T(dd[0]), T(dd[1]), T(dd[2])};
+    const T qi = T(LH[3 * cap + a]), qj = T(LK[3 * cap + b]);
+    const T ui[3] = {T(LH[4 * cap + a]), T(LH[5 * cap + a]), T(LH[6 * cap + a])};
+    const T uj[3] = {T(LK[4 * cap + b]), T(LK[5 * cap + b]), T(LK[6 * cap + b])};
+    const T ti[6] = {T(LH[7 * cap + a]), T(LH[8 * cap + a]), T(LH[9 * cap + a]),
+                     T(LH[10 * cap + a]), T(LH[11 * cap + a]), T(LH[12 * cap + a])};
+    const T tj[6] = {T(LK[7 * cap + b]), T(LK[8 * cap + b]), T(LK[9 * cap + b]),
+                     T(LK[10 * cap + b]), T(LK[11 * cap + b]), T(LK[12 * cap + b])};
+    T vi[3], vj[3];
+    vi[0] = ti[0] * d[0] + ti[1] * d[1] + ti[2] * d[2];
+    vi[1] = ti[1] * d[0] + ti[3] * d[1] + ti[4] * d[2];
+    vi[2] = ti[2] * d[0] + ti[4] * d[1] + ti[5] * d[2];
+    vj[0] = tj[0] * d[0] + tj[1] * d[1] + tj[2] * d[2];
+    vj[1] = tj[1] * d[0] + tj[3] * d[1] + tj[4] * d[2];
+    vj[2] = tj[2] * d[0] + tj[4] * d[1] + tj[5] * d[2];
+    const T di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
+    const T dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
+    const T Qi = d[0] * vi[0] + d[1] * vi[1] + d[2] * vi[2];
+    const T Qj = d[0] * vj[0] + d[1] * vj[1] + d[2] * vj[2];
+    // field at i from j: d(-qj g1 + dj g2 - Qj g3) - uj g1 + 2 vj g2
+    // field at j from i: d( qi g1 + di g2 + Qi g3) - ui g1 - 2 vi g2
+    const T si = -qj * g1 + dj * g2 - Qj * g3;
+    const T sj = qi * g1 + di * g2 + Qi * g3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      fi[c] = (double)(d[c] * si - uj[c] * g1 + T(2) * vj[c] * g2);
+      fj[c] = (double)(d[c] * sj - ui[c] * g1 - T(2) * vi[c] * g2);
+    }
+  }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
                        double* AK, double*, long p) const {
     double dd[3];
@@ -303,67 +402,15 @@ struct EfieldPh {
       return;
     }
     const bool excl = LH[13 * cap + a] == LK[13 * cap + b];
-    R B[4], Rb[4];
-    radial_pair<R, 3>(g, r2, excl, B, Rb);
-    R g1, g2, g3;
-    R l3, l5, l7;
-    if (!excl || gc) {
-      const R r = R(r2) * rsqrt_r(R(r2));
-      thole_damp<R>(r, R(LH[14 * cap + a]), R(LK[14 * cap + b]), R(LH[15 * cap + a]),
-                    R(LK[15 * cap + b]), l3, l5, l7);
-    }
-    if (excl) {
-      g1 = B[1] - Rb[1];
-      g2 = B[2] - Rb[2];
-      g3 = B[3] - Rb[3];
-      if (gc) {
-        if (std::is_same<R, float>::value) {
-          // B carries the FP64 difference B - R; re-add the damped bare part in FP64
-          const double ri = rsqrt_r(r2);
-          const double R1 = ri * ri * ri, R2 = 3.0 * R1 * ri * ri;
-          gc[p] = GC((double)B[1] + (double)l3 * R1);
-          gc[gcs + p] = GC((double)B[2] + (double)l5 * R2);
-        } else {
-          gc[p] = B[1] - (R(1) - l3) * Rb[1];
-          gc[gcs + p] = B[2] - (R(1) - l5) * Rb[2];
-        }
-      }
-    } else {
-      g1 = B[1] - (R(1) - l3) * Rb[1];
-      g2 = B[2] - (R(1) - l5) * Rb[2];
-      g3 = B[3] - (R(1) - l7) * Rb[3];
-      if (gc) {
-        gc[p] = g1;
-        gc[gcs + p] = g2;
-      }
-    }
-    const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
-    const R qi = R(LH[3 * cap + a]), qj = R(LK[3 * cap + b]);
-    const R ui[3] = {R(LH[4 * cap + a]), R(LH[5 * cap + a]), R(LH[6 * cap + a])};
-    const R uj[3] = {R(LK[4 * cap + b]), R(LK[5 * cap + b]), R(LK[6 * cap + b])};
-    const R ti[6] = {R(LH[7 * cap + a]), R(LH[8 * cap + a]), R(LH[9 * cap + a]),
-                     R(LH[10 * cap + a]), R(LH[11 * cap + a]), R(LH[12 * cap + a])};
-    const R tj[6] = {R(LK[7 * cap + b]), R(LK[8 * cap + b]), R(LK[9 * cap + b]),
-                     R(LK[10 * cap + b]), R(LK[11 * cap + b]), R(LK[12 * cap + b])};
-    R vi[3], vj[3];
-    vi[0] = ti[0] * d[0] + ti[1] * d[1] + ti[2] * d[2];
-    vi[1] = ti[1] * d[0] + ti[3] * d[1] + ti[4] * d[2];
-    vi[2] = ti[2] * d[0] + ti[4] * d[1] + ti[5] * d[2];
-    vj[0] = tj[0] * d[0] + tj[1] * d[1] + tj[2] * d[2];
-    vj[1] = tj[1] * d[0] + tj[3] * d[1] + tj[4] * d[2];
-    vj[2] = tj[2] * d[0] + tj[4] * d[1] + tj[5] * d[2];
-    const R di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
-    const R dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
-    const R Qi = d[0] * vi[0] + d[1] * vi[1] + d[2] * vi[2];
-    const R Qj = d[0] * vj[0] + d[1] * vj[1] + d[2] * vj[2];
-    // field at i from j: d(-qj g1 + dj g2 - Qj g3) - uj g1 + 2 vj g2
-    // field at j from i: d( qi g1 + di g2 + Qi g3) - ui g1 - 2 vi g2
-    const R si = -qj * g1 + dj * g2 - Qj * g3;
-    const R sj = qi * g1 + di * g2 + Qi * g3;
+    double fi[3], fj[3];
+    if (std::is_same<R, float>::value && r2 < kMixedCloseR2)
+      eval<double>(LH, LK, cap, a, b, dd, r2, excl, fi, fj, p);
+    else
+      eval<R>(LH, LK, cap, a, b, dd, r2, excl, fi, fj, p);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      lds_add(&AH[c * cap + a], (double)(d[c] * si - uj[c] * g1 + R(2) * vj[c] * g2));
-      lds_add(&AK[c * cap + b], (double)(d[c] * sj - ui[c] * g1 - R(2) * vi[c] * g2));
+      lds_add(&AH[c * cap + a], fi[c]);
+      lds_add(&AK[c * cap + b], fj[c]);
     }
   }
 };
@@ -386,6 +433,10 @@ struct TmatPh {
   const double* thole;
   const int32_t* molid;
   Geom g;
+  __device__ void set_sys(const SysDev& d, int) {
+    g.box = d.box;
+    g.inv_box = d.inv_box;
+  }
   const double* zdir = nullptr;      // solver: stage p = z + beta * p (search direction)
   const double* beta_dir = nullptr;  // device scalar beta
   static constexpr int NG = 6;       // x y z isa thole molid, gathered once per call
@@ -409,40 +460,56 @@ struct TmatPh {
   }
   const int32_t* perm_ = nullptr;
 
+  // field contributions at both atoms in type T
+  template <class T>
+  __device__ __forceinline__ void eval(const double* LH, const double* LK, int cap, int a, int b,
+                                       const double* dd, double r2, bool same, double* fi,
+                                       double* fj) const {
+    T B[3], Rb[3];
+    radial_pair<T, 2>(g, r2, same, B, Rb);
+    T l3, l5, l7;
+    const T r = T(r2) * rsqrt_r(T(r2));
+    thole_damp<T>(r, T(LH[3 * cap + a]), T(LK[3 * cap + b]), T(LH[4 * cap + a]),
+                  T(LK[4 * cap + b]), l3, l5, l7);
+    // g1 = B1 - (1 - l3) R1, g2 = B2 - (1 - l5) R2 (for FP32 same-molecule pairs
+    // B carries the FP64 difference B - R and the bare part is re-added with l)
+    T g1, g2;
+    if (std::is_same<T, float>::value && same) {
+      const double ri = rsqrt_r(r2);
+      const double R1 = ri * ri * ri, R2 = 3.0 * R1 * ri * ri;
+      g1 = T((double)B[1] + (double)l3 * R1);
+      g2 = T((double)B[2] + (double)l5 * R2);
+    } else {
+      g1 = B[1] - (T(1) - l3) * Rb[1];
+      g2 = B[2] - (T(1) - l5) * Rb[2];
+    }
+    const T d[3] = {T(dd[0]), T(dd[1]), T(dd[2])};
+    const T ui[3] = {T(LH[6 * cap + a]), T(LH[7 * cap + a]), T(LH[8 * cap + a])};
+    const T uj[3] = {T(LK[6 * cap + b]), T(LK[7 * cap + b]), T(LK[8 * cap + b])};
+    const T di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
+    const T dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
+    const T si = dj * g2, sj = di * g2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      fi[c] = (double)(d[c] * si - uj[c] * g1);
+      fj[c] = (double)(d[c] * sj - ui[c] * g1);
+    }
+  }
   __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
                        double* AK, double*, long) const {
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
     if (!(r2 <= g.rc2)) return;
     const bool same = LH[5 * cap + a] == LK[5 * cap + b];
-    R B[3], Rb[3];
-    radial_pair<R, 2>(g, r2, same, B, Rb);
-    R l3, l5, l7;
-    const R r = R(r2) * rsqrt_r(R(r2));
-    thole_damp<R>(r, R(LH[3 * cap + a]), R(LK[3 * cap + b]), R(LH[4 * cap + a]), R(LK[4 * cap + b]),
-             l3, l5, l7);
-    // g1 = B1 - (1 - l3) R1, g2 = B2 - (1 - l5) R2 (for FP32 same-molecule pairs
-    // B carries the FP64 difference B - R and the bare part is re-added with l)
-    R g1, g2;
-    if (std::is_same<R, float>::value && same) {
-      const double ri = rsqrt_r(r2);
-      const double R1 = ri * ri * ri, R2 = 3.0 * R1 * ri * ri;
-      g1 = R((double)B[1] + (double)l3 * R1);
-      g2 = R((double)B[2] + (double)l5 * R2);
-    } else {
-      g1 = B[1] - (R(1) - l3) * Rb[1];
-      g2 = B[2] - (R(1) - l5) * Rb[2];
-    }
-    const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
-    const R ui[3] = {R(LH[6 * cap + a]), R(LH[7 * cap + a]), R(LH[8 * cap + a])};
-    const R uj[3] = {R(LK[6 * cap + b]), R(LK[7 * cap + b]), R(LK[8 * cap + b])};
-    const R di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
-    const R dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
-    const R si = dj * g2, sj = di * g2;
+    double fi[3], fj[3];
+    if (std::is_same<R, float>::value && r2 < kMixedCloseR2)
+      eval<double>(LH, LK, cap, a, b, dd, r2, same, fi, fj);
+    else
+      eval<R>(LH, LK, cap, a, b, dd, r2, same, fi, fj);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      lds_add(&AH[c * cap + a], (double)(d[c] * si - uj[c] * g1));
-      lds_add(&AK[c * cap + b], (double)(d[c] * sj - ui[c] * g1));
+      lds_add(&AH[c * cap + a], fi[c]);
+      lds_add(&AK[c * cap + b], fj[c]);
     }
   }
 };
@@ -462,6 +529,10 @@ struct TmatCachedPh {
   const R* gc = nullptr;
   long gcs = 0;
   double box, inv_box;
+  __device__ void set_sys(const SysDev& d, int) {
+    box = d.box;
+    inv_box = d.inv_box;
+  }
   const double* xyz = nullptr;
   const double* mu = nullptr;        // sorted order
   const double* zdir = nullptr;      // stage p = z + beta * p when set
@@ -511,9 +582,16 @@ struct VdwPh {
   const double* eps;
   const int32_t* molid;
   int form;
-  double box, inv_box, rc2, ron, rc, tw_inv, dhal, ghal;
+  double box, inv_box, rc2, ron, rc, tw_inv, dhal, ghal, taper;
+  const double* sys_cut = nullptr;   // batch: per-system cutoff (nullptr: rc for all)
+  __host__ __device__ void set_cut(double cutoff) {
+    rc = cutoff;
+    rc2 = cutoff * cutoff;
+    ron = taper * cutoff;
+    tw_inv = cutoff > ron ? 1.0 / (cutoff - ron) : 0.0;
+  }
   void set(const tk_system* sys, int f, const double* r_, const double* e_, double cutoff,
-           double taper, double d, double gm) {
+           double tp, double d, double gm) {
     xyz = sys->xyz;
     rad = r_;
     eps = e_;
@@ -521,12 +599,15 @@ struct VdwPh {
     form = f;
     box = sys->box;
     inv_box = 1.0 / sys->box;
-    rc = cutoff;
-    rc2 = cutoff * cutoff;
-    ron = taper * cutoff;
-    tw_inv = cutoff > ron ? 1.0 / (cutoff - ron) : 0.0;
+    taper = tp;
+    set_cut(cutoff);
     dhal = d;
     ghal = gm;
+  }
+  __device__ void set_sys(const SysDev& d, int sy) {
+    box = d.box;
+    inv_box = d.inv_box;
+    if (sys_cut) set_cut(sys_cut[sy]);
   }
     static constexpr int NG = 6;   // fields gathered once per call (sorted SoA)
   const double* sorted = nullptr;
@@ -582,19 +663,25 @@ struct VdwPh {
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, box, inv_box, dd);
     if (!(r2 <= rc2)) return;
-    R e, dedr, r;
-    eval<R>(r2, R(LH[3 * cap + a]), R(LK[3 * cap + b]), R(LH[4 * cap + a]), R(LK[4 * cap + b]), e,
-            dedr, r);
-    double en = (double)e;
-    if (std::is_same<R, float>::value) {
+    double en, f;
+    if (std::is_same<R, float>::value && !(r2 < kMixedCloseR2)) {
+      R e, dedr, r;
+      eval<R>(r2, R(LH[3 * cap + a]), R(LK[3 * cap + b]), R(LH[4 * cap + a]), R(LK[4 * cap + b]),
+              e, dedr, r);
+      f = (double)dedr / (double)r;
       // the vdW energy is a sum of cancelling attractive and repulsive terms:
       // in the mixed form it is evaluated in FP64 (forces stay FP32)
       double ed, dd64, rd;
       eval<double>(r2, LH[3 * cap + a], LK[3 * cap + b], LH[4 * cap + a], LK[4 * cap + b], ed, dd64,
                    rd);
       en = ed;
+    } else {   // FP64 form; in the mixed form also close pairs
+      double e, dedr, r;
+      eval<double>(r2, LH[3 * cap + a], LK[3 * cap + b], LH[4 * cap + a], LK[4 * cap + b], e, dedr,
+                   r);
+      en = e;
+      f = dedr / r;
     }
-    const double f = (double)dedr / (double)r;
     sc[0] += en;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -678,7 +765,8 @@ tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, con
     k_reduce<Ph::NA, Epi><<<ceil_div(P.n, 256), 256, 0, st>>>(pv, (double*)partial, pstride, epi);
   }
   if (Ph::NS > 0 && sums_out)
-    k_sum_units<(Ph::NS > 0 ? Ph::NS : 1)><<<(Ph::NS > 0 ? Ph::NS : 1), 256, 0, st>>>((double*)uscal, P.nunits, sums_out);
+    k_sum_units<(Ph::NS > 0 ? Ph::NS : 1)><<<dim3(Ph::NS > 0 ? Ph::NS : 1, P.nsys), 256, 0, st>>>(
+        (double*)uscal, pv.sys, sums_out);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }

@@ -27,6 +27,9 @@ constexpr double kTwo32 = 4294967296.0;
 // takes part in at most 28 unit roles (27 neighbours, the self pair twice),
 // and each role owns one partial-result slot for the cell's atoms.
 constexpr int kMaxSlots = 28;
+// Plan slots beyond the caller's TK_MAX_PLANS, used by the batch step.
+constexpr int kBatchPlan7 = TK_MAX_PLANS, kBatchPlan9 = TK_MAX_PLANS + 1;
+constexpr int kNumPlans = TK_MAX_PLANS + 2;
 constexpr int kCellUnitStride = 28;  // per-cell unit list: count + up to 27 entries
 constexpr int kMaxCellAtoms = 512;   // LDS staging limit per cell
 constexpr int kWave = 64;
@@ -34,6 +37,17 @@ constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
 
 struct Unit {
   int32_t h, k, slot_h, slot_k;
+};
+
+// One system of a plan.  A plan holds one system (the single-system entry
+// points) or a batch of independent systems (the serving path): each system
+// has its own box, cell grid and list cutoff; its cells, units and atoms are
+// contiguous ranges of the plan's.
+struct SysDev {
+  double box, inv_box;
+  uint64_t rq2;            // quantised list cutoff squared (exact test)
+  double lo, hi;           // band of the FP64 pre-test around rq2
+  int32_t nc, cell0, unit0, atom0;
 };
 
 // Device views of a plan (the pair set of one neighbour list, in cell-pair
@@ -49,7 +63,15 @@ struct PlanView {
   const int32_t* unit_cnt;    // [nunits] listed pairs of the unit (window prefix)
   const uint32_t* codes;      // pair codes: a | b << 16 (local indices in H, K)
   const int32_t* cell_units;  // [ncells][28]: count, then unit * 4 + role
+  int32_t nsys;
+  const SysDev* sys;          // [nsys]
+  const int32_t* cell_sys;    // [ncells] system of each cell; nullptr when nsys == 1
 };
+
+// System of a cell (0 for single-system plans).
+__device__ __forceinline__ int cell_system(const PlanView& pv, int c) {
+  return pv.cell_sys ? pv.cell_sys[c] : 0;
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -64,11 +86,17 @@ struct Plan {
   int32_t max_nbhd = 0;   // max over cells of the atoms in the cell's neighbour cells (itself included)
   int64_t npairs = 0;
   DevBuf perm, scell, cell_start, unit_off, unit_cnt, codes, us, slots;
-  const Unit* units_p = nullptr;       // device cell tables shared by plans with the same nc
-  const int32_t* nslot_p = nullptr;
+  const Unit* units_p = nullptr;       // device cell tables (shared by plans with the same
+  const int32_t* nslot_p = nullptr;    // nc for one system; built per batch otherwise)
   const int32_t* cu_p = nullptr;
+  int32_t nsys = 1;
+  std::vector<SysDev> h_sys;           // host copy, with a final entry holding the totals
+  DevBuf sysd, cell_sys, bunits, bnslot, bcu, tplp;
   PlanView view() const {
     PlanView v;
+    v.nsys = nsys;
+    v.sys = (const SysDev*)sysd.p;
+    v.cell_sys = nsys > 1 ? (const int32_t*)cell_sys.p : nullptr;
     v.n = n; v.ncells = ncells; v.nunits = nunits; v.max_occ = max_occ;
     v.perm = (const int32_t*)perm.p; v.scell = (const int32_t*)scell.p;
     v.cell_start = (const int32_t*)cell_start.p; v.cell_nslot = nslot_p;
@@ -106,13 +134,13 @@ struct tk_ctx {
   std::string prof_only;
   std::map<std::string, tk::ProfEntry> prof;
   std::vector<hipEvent_t> event_pool;
-  tk::Plan plans[TK_MAX_PLANS];
+  tk::Plan plans[tk::kNumPlans];
   std::map<std::string, tk::DevBuf> scratch;   // grow-only named device buffers
   std::map<int, tk::CellTables> tables;        // by cells per edge
   void* pinned = nullptr;                      // host readback buffer (device-writable)
   void* pinned_dev = nullptr;                  // its device address
   size_t pinned_bytes = 0;
-  int pcg_hint[TK_MAX_PLANS][2] = {};          // last solve's iteration count per plan slot, precision
+  int pcg_hint[tk::kNumPlans][2] = {};         // last solve's iteration count per plan slot, precision
 };
 
 namespace tk {
@@ -135,6 +163,31 @@ CellTables& cell_tables(tk_ctx* ctx, int nc);
 // Exclusive scan of int32 counts: out[0..len] with out[len] = total.
 tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len);
 tk_status scan_i64(tk_ctx* ctx, hipStream_t st, const int64_t* in, int64_t* out, long len);
+
+// Systems of a plan (host arrays): atom0[nsys+1] offsets, box[nsys],
+// list cutoff[nsys].
+struct PlanSpec {
+  int nsys;
+  const int32_t* atom0;
+  const double* box;
+  const double* cutoff;
+};
+// Builds plan slot `slot` for the atoms xyz[n][3] (and the caller's CSR when
+// row_ptr is given); synchronises the stream once.
+tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double* xyz,
+                     const PlanSpec& spec, int32_t* row_ptr, int32_t* col, int64_t cap,
+                     int64_t* npairs_out);
+
+// Induced dipoles of every system of plan P (right-hand side, PCG, FP64 true
+// residual and, in the mixed form, refinement).  xyz, molid and the
+// parameters are in caller order for the plan's atoms; mu_guess is used for
+// the systems whose guess_on entry (device [nsys], nullable: all) is nonzero;
+// info[P->nsys] is host memory.  Synchronises the stream.
+tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double* xyz,
+                        const int32_t* molid, const double* mpole, const double* polarity,
+                        const double* thole, double ewald_beta, double cutoff, double tol_debye,
+                        int32_t maxiter, int prec, const double* mu_guess,
+                        const int32_t* guess_on, double* mu_out, tk_pcg_info* info);
 
 // Checks shared by the pair entry points.
 tk_status check_system(const tk_system* sys);

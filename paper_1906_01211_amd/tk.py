@@ -36,6 +36,45 @@ class PcgInfo(C.Structure):
                 ("rms_true_debye", C.c_double), ("epol", C.c_double)]
 
 
+class StepParams(C.Structure):
+    _fields_ = [("rc_ewald", C.c_double), ("rc_vdw", C.c_double), ("skin", C.c_double),
+                ("ewald_beta", C.c_double), ("tol_debye", C.c_double),
+                ("taper_on_frac", C.c_double), ("hal_delta", C.c_double),
+                ("hal_gamma", C.c_double), ("maxiter", C.c_int32), ("prec", C.c_int32)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("nsys", C.c_int32), ("atom_off", C.c_void_p), ("box", C.c_void_p),
+                ("xyz", C.c_void_p), ("molid", C.c_void_p)]
+
+
+class StepResult(C.Structure):
+    _fields_ = [("e_mpole", C.c_double * 3), ("w_mpole", C.c_double * 9), ("e_vdw", C.c_double),
+                ("w_vdw", C.c_double * 9), ("rc_vdw", C.c_double), ("pcg", PcgInfo)]
+
+    def as_dict(self):
+        return {"e_mpole": list(self.e_mpole), "w_mpole": list(self.w_mpole),
+                "e_vdw": self.e_vdw, "w_vdw": list(self.w_vdw), "rc_vdw": self.rc_vdw,
+                "pcg": {k: getattr(self.pcg, k) for k, _ in PcgInfo._fields_}}
+
+
+class Request(C.Structure):
+    _fields_ = [("n", C.c_int32), ("box", C.c_double), ("xyz", C.c_void_p), ("molid", C.c_void_p),
+                ("mpole", C.c_void_p), ("polarity", C.c_void_p), ("thole", C.c_void_p),
+                ("vdw_rad", C.c_void_p), ("vdw_eps", C.c_void_p), ("session", C.c_uint64)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("t_submit", C.c_int64), ("t_start", C.c_int64), ("t_done", C.c_int64),
+                ("batch_size", C.c_int32), ("batch_index", C.c_int32)]
+
+
+def step_params(s, prec=FP64):
+    """StepParams from a settings dict (synth.AMOEBA_SETTINGS keys)."""
+    return StepParams(s["rc_ewald"], s["rc_vdw"], s["skin"], s["beta"], s["tol_debye"],
+                      s["taper_frac"], s["dhal"], s["ghal"], int(s["maxiter"]), int(prec))
+
+
 class TkError(RuntimeError):
     def __init__(self, status, where=""):
         msg = load().tk_strerror(status).decode() if _lib is not None else str(status)
@@ -62,6 +101,14 @@ _SIGS = {
                         _i32, C.c_int, _vp, _vp, C.POINTER(PcgInfo)],
     "tk_evdw": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), C.c_int, _vp, _vp, _d, _d, _d, _d,
                 C.c_int, _vp, _vp, _vp],
+    "tk_batch_step": [_vp, _vp, C.POINTER(Batch), C.POINTER(StepParams), _vp, _vp, _vp, _vp, _vp,
+                      _vp, _vp, _vp, _vp, _vp, _vp],
+    "tk_server_create": [C.c_int, C.POINTER(StepParams), C.c_size_t, _i32, C.POINTER(_vp)],
+    "tk_server_footprint": [_i32],
+    "tk_server_submit": [_vp, C.POINTER(Request), C.POINTER(C.c_uint64)],
+    "tk_server_poll": [_vp, C.c_uint64, C.POINTER(StepResult), C.POINTER(Timing), _vp, _vp, _vp],
+    "tk_server_release": [_vp, C.c_uint64],
+    "tk_server_destroy": [_vp],
     "tk_profile_enable": [_vp, C.c_int, C.c_char_p],
     "tk_profile_read": [_vp, _i32, C.c_char_p, _i32, C.POINTER(_i64), C.POINTER(_d)],
     "tk_profile_reset": [_vp],
@@ -82,8 +129,10 @@ def load(path: str = LIB_PATH):
         for name, args in _SIGS.items():
             f = getattr(L, name)
             f.argtypes = args
-            f.restype = C.c_int32 if name not in ("tk_destroy", "tk_strerror") else None
+            f.restype = C.c_int32 if name not in ("tk_destroy", "tk_strerror",
+                                                  "tk_server_destroy") else None
         L.tk_strerror.restype = C.c_char_p
+        L.tk_server_footprint.restype = C.c_size_t
         _lib = L
     return _lib
 
@@ -238,6 +287,99 @@ class Context:
                               int(form), _ptr(r), _ptr(ep), cutoff, taper_frac, dhal, ghal, prec,
                               _ptr(e), _ptr(f), _ptr(w)), "tk_evdw")
         return e[0], f, w
+
+
+    # -- batches of systems ----------------------------------------------------
+    def batch_step(self, systems, params, mu_guess=None, use_guess=None):
+        """One step (lists, multipoles, dipoles, HAL) for a list of systems in
+        one batch.  systems: objects with xyz, box, molid, mpole, polarity,
+        thole, vdw_rad, vdw_eps (host arrays).  Returns (results, forces_mpole,
+        mu, forces_vdw) with per-system dicts and per-system [n][3] tensors."""
+        import numpy as np
+        off = np.zeros(len(systems) + 1, dtype=np.int32)
+        off[1:] = np.cumsum([len(w.xyz) for w in systems])
+        box = np.array([w.box for w in systems], dtype=np.float64)
+        cat = lambda f, dt: _dev(np.concatenate([np.asarray(getattr(w, f)) for w in systems]),
+                                 dt, self.device)
+        xyz, molid = cat("xyz", torch.float64), cat("molid", torch.int32)
+        mp, pol, th = cat("mpole", torch.float64), cat("polarity", torch.float64), cat(
+            "thole", torch.float64)
+        rad, eps = cat("vdw_rad", torch.float64), cat("vdw_eps", torch.float64)
+        n = int(off[-1])
+        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device)
+        ug = None if use_guess is None else np.ascontiguousarray(use_guess, dtype=np.int32)
+        fm = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        mu = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        fv = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        res = (StepResult * len(systems))()
+        b = Batch(len(systems), off.ctypes.data, box.ctypes.data, xyz.data_ptr(), molid.data_ptr())
+        _check(load().tk_batch_step(self._h, _stream(self.device), C.byref(b), C.byref(params),
+                                    _ptr(mp), _ptr(pol), _ptr(th), _ptr(rad), _ptr(eps), _ptr(g),
+                                    None if ug is None else C.c_void_p(ug.ctypes.data), _ptr(fm),
+                                    _ptr(mu), _ptr(fv), res), "tk_batch_step")
+        split = lambda t: [t[off[k]:off[k + 1]] for k in range(len(systems))]
+        return [r.as_dict() for r in res], split(fm), split(mu), split(fv)
+
+
+class Server:
+    """Continuous-batching server (its own context, stream and worker thread)."""
+
+    def __init__(self, params, hbm_budget, max_batch=256, device=0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libtk needs a ROCm GPU; none is visible")
+        self._h = C.c_void_p()
+        self._keep = {}
+        _check(load().tk_server_create(device, C.byref(params), int(hbm_budget), int(max_batch),
+                                       C.byref(self._h)), "tk_server_create")
+
+    @staticmethod
+    def footprint(n):
+        return int(load().tk_server_footprint(int(n)))
+
+    def submit(self, w, session=0):
+        """Queue one system (host arrays); returns the request id."""
+        import numpy as np
+        arr = [np.ascontiguousarray(w.xyz, dtype=np.float64),
+               np.ascontiguousarray(w.molid, dtype=np.int32),
+               np.ascontiguousarray(w.mpole, dtype=np.float64),
+               np.ascontiguousarray(w.polarity, dtype=np.float64),
+               np.ascontiguousarray(w.thole, dtype=np.float64),
+               np.ascontiguousarray(w.vdw_rad, dtype=np.float64),
+               np.ascontiguousarray(w.vdw_eps, dtype=np.float64)]
+        q = Request(len(arr[0]), float(w.box), *[a.ctypes.data for a in arr], int(session))
+        rid = C.c_uint64(0)
+        _check(load().tk_server_submit(self._h, C.byref(q), C.byref(rid)), "tk_server_submit")
+        self._keep[rid.value] = len(arr[0])
+        return rid.value
+
+    def poll(self, rid, arrays=True):
+        """None while running; else (result dict, timing dict, f_mpole, mu, f_vdw)."""
+        import numpy as np
+        n = self._keep[rid]
+        res, tim = StepResult(), Timing()
+        outs = [np.empty((n, 3)) for _ in range(3)] if arrays else [None] * 3
+        st = load().tk_server_poll(self._h, rid, C.byref(res), C.byref(tim),
+                                   *[None if a is None else C.c_void_p(a.ctypes.data) for a in outs])
+        if st == E_BUSY:
+            return None
+        _check(st, "tk_server_poll")
+        t = {k: getattr(tim, k) for k, _ in Timing._fields_}
+        return (res.as_dict(), t, *outs)
+
+    def release(self, rid):
+        _check(load().tk_server_release(self._h, rid), "tk_server_release")
+        self._keep.pop(rid, None)
+
+    def close(self):
+        if self._h:
+            load().tk_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 @dataclass

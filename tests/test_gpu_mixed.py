@@ -80,10 +80,11 @@ def test_pcg_mixed_dipoles(ctx, tk, name):
 
 
 def test_pcg_mixed_refinement_triggers(ctx, tk):
-    # a tolerance below what FP32 pair arithmetic resolves forces FP64 refinement
+    # a tolerance below what FP32 pair arithmetic resolves (the FP32 operator
+    # differs from the FP64 one by ~1e-8 D in the residual) forces FP64 refinement
     w, sysr, lst, rp, cp = setup(ctx, "water216", 7.001, 2)
     mu, info = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
-                                tol_debye=1e-8, maxiter=100, prec=tk.MIXED)
+                                tol_debye=1e-10, maxiter=100, prec=tk.MIXED)
     assert info["refinements"] >= 1
     tight, _ = O.polarize_pcg(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
                               S["beta"], 7.0, tol_debye=1e-11, maxiter=300)
