@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run device-to-device copies of this many MiB (a kernel of known "
                          "traffic for scaling HBM counters)")
@@ -227,6 +229,8 @@ def main():
     }
     if not a.no_extras:
         out["extras"] = extras(ctx, tk, w, a, prec)
+    if not a.no_serving:
+        out["serving"] = serving(tk, a.serving_requests)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, n7, n9)
     ctx.close()
@@ -260,6 +264,100 @@ def extras(ctx, tk, w, a, prec):
         res["charge_lj_pairs_12A"] = int(l12.npairs)
         res[f"charge_lj_pairs_per_s_{name}"] = 2 * l12.npairs / (ms * 1e-3)
     return res
+
+
+_serving_systems = {}
+
+
+def serving_systems(count):
+    """The request stream's systems (log-uniform 300-30,000 atoms, water density)."""
+    if count not in _serving_systems:
+        reqs = synth.serving_requests(count)
+        _serving_systems[count] = [synth.amoeba_water_box(r["n_w"], r["box"], r["seed"])
+                                   for r in reqs]
+    return _serving_systems[count]
+
+
+def run_stream(srv, systems, arrivals=None):
+    """Submit every system (all at once, or at the given offsets in seconds)
+    and wait for all; returns latencies (ms), wall time (s) and batch count."""
+    import threading
+    ids = [None] * len(systems)
+
+    def feed():
+        t0 = time.perf_counter()
+        for k, w in enumerate(systems):
+            if arrivals is not None:
+                dt = arrivals[k] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            ids[k] = srv.submit(w)
+
+    th = threading.Thread(target=feed)
+    th.start()
+    th.join()
+    lat, first, last, batches = [], None, None, {}
+    for rid in ids:
+        while True:
+            out = srv.poll(rid, arrays=False)
+            if out is not None:
+                break
+            time.sleep(2e-4)
+        t = out[1]
+        lat.append((t["t_done"] - t["t_submit"]) * 1e-6)
+        first = t["t_submit"] if first is None else min(first, t["t_submit"])
+        last = t["t_done"] if last is None else max(last, t["t_done"])
+        batches[t["batch_index"]] = (t["t_done"] - t["t_start"]) * 1e-9
+        srv.release(rid)
+    return np.array(lat), (last - first) * 1e-9, len(batches), sum(batches.values())
+
+
+def serving(tk, count):
+    """Serving form on the request stream: capacity (all requests queued at
+    once) and p50/p99 latency under Poisson arrivals at 0.5, 0.8, 1.0 and 1.2
+    times that capacity, for FP64 and mixed; a 512 MiB device budget; and the
+    baseline of one request at a time (FP64) under the same arrivals."""
+    systems = serving_systems(count)
+    atoms = sum(w.n for w in systems)
+    loads = (0.5, 0.8, 1.0, 1.2)
+    out = {"requests": count, "atoms": atoms,
+           "sizes": "log-uniform 300-30,000 atoms, water-box density, seeds 20000+k; Poisson "
+                    "arrivals seed 1004"}
+
+    def arrivals(rate):
+        return [r["arrival"] for r in synth.serving_requests(count, rate=rate)]
+
+    def one(prec, budget, max_batch, fracs, base=None):
+        """fracs: offered loads as fractions of `base` req/s (default: this
+        configuration's own capacity)."""
+        srv = tk.Server(tk.step_params(synth.AMOEBA_SETTINGS, prec), budget, max_batch)
+        try:
+            for _ in range(2):                          # warm-up: grows the device arena
+                run_stream(srv, systems)
+            lat, wall, nb, busy = run_stream(srv, systems)   # capacity: all queued at once
+            res = {"capacity_req_s": count / wall, "atoms_per_s": atoms / wall, "batches": nb,
+                   "busy_atoms_per_s": atoms / busy,
+                   "closed_p50_ms": float(np.percentile(lat, 50)),
+                   "closed_p99_ms": float(np.percentile(lat, 99))}
+            ref = res["capacity_req_s"] if base is None else base
+            for f in fracs:
+                rate = f * ref
+                lat, wall, nb, busy = run_stream(srv, systems, arrivals(rate))
+                res[f"load_{f}"] = {"rate_req_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+                                    "p99_ms": float(np.percentile(lat, 99)),
+                                    "throughput_req_s": count / wall, "batches": nb}
+            return res
+        finally:
+            srv.close()
+
+    big = 64 << 30
+    out["fp64"] = one(tk.FP64, big, 4096, loads)
+    out["mixed"] = one(tk.MIXED, big, 4096, loads)
+    cap = out["fp64"]["capacity_req_s"]
+    # loads below are fractions of the unconstrained FP64 capacity
+    out["fp64_budget_512MiB"] = one(tk.FP64, 512 << 20, 4096, (0.5, 0.8), base=cap)
+    out["fp64_one_at_a_time"] = one(tk.FP64, big, 1, (0.5, 1.0), base=cap)
+    return out
 
 
 if __name__ == "__main__":

@@ -224,6 +224,7 @@ __global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict_
                                              long pstride, const int64_t* __restrict__ unit_off,
                                              long code_cap, uint32_t* __restrict__ codes,
                                              int32_t* __restrict__ unit_cnt,
+                                             int64_t* __restrict__ cnt64,
                                              int32_t* __restrict__ slot_cnt,
                                              int32_t* __restrict__ info) {
   __shared__ uint4 sK[kMaxCellAtoms];
@@ -270,10 +271,25 @@ __global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict_
   __syncthreads();
   if (lane == 0) {
     unit_cnt[uidx] = cnt;
+    cnt64[uidx] = cnt;
     atomicAdd(&info[3], cnt);
   }
   for (int t = lane; t < nh; t += 64) slot_cnt[(long)un.slot_h * pstride + hs + t] = cH[t];
   for (int t = lane; t < nk; t += 64) slot_cnt[(long)un.slot_k * pstride + ks + t] = cK[t];
+}
+
+// One wave per unit: move the unit's pair codes from its candidate window
+// to its place in the dense code array (windows are sized by candidates,
+// the dense array by listed pairs).
+__global__ __launch_bounds__(64) void k_compact(const int64_t* __restrict__ woff,
+                                                const uint32_t* __restrict__ windows,
+                                                const int64_t* __restrict__ doff,
+                                                const int32_t* __restrict__ unit_cnt,
+                                                uint32_t* __restrict__ codes) {
+  const int u = blockIdx.x;
+  const uint32_t* src = windows + woff[u];
+  uint32_t* dst = codes + doff[u];
+  for (int t = threadIdx.x; t < unit_cnt[u]; t += 64) dst[t] = src[t];
 }
 
 // Per sorted atom: the CSR row length (sum over its unit roles, written in
@@ -553,10 +569,13 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
       (s = ensure(P.slots, sizeof(int32_t) * kMaxSlots * pstride)) ||
       (s = ensure(P.sysd, sizeof(SysDev) * (nsys + 1))))
     return s;
-  if (P.codes.bytes < sizeof(uint32_t) * (size_t)est &&
-      (s = ensure(P.codes, sizeof(uint32_t) * (size_t)est)))
+  // candidate windows: scratch shared by every build (the plan keeps the
+  // dense codes); grown to the exact size and rerun if the estimate is short
+  void* windows = nullptr;
+  DevBuf& wb = ctx->scratch["nb_windows"];
+  if (wb.bytes < sizeof(uint32_t) * (size_t)est && (s = ensure(wb, sizeof(uint32_t) * (size_t)est)))
     return s;
-  void *u, *cell, *ccount, *cursor, *tmp, *info, *cand, *rcnt, *rptr;
+  void *u, *cell, *ccount, *cursor, *tmp, *info, *cand, *rcnt, *rptr, *woff, *cnt64;
   if ((s = scratch(ctx, "nb_u", sizeof(uint32_t) * 3 * nn, &u)) ||
       (s = scratch(ctx, "nb_cell", sizeof(int32_t) * nn, &cell)) ||
       (s = scratch(ctx, "nb_ccount", sizeof(int32_t) * (ncells + 1), &ccount)) ||
@@ -564,6 +583,8 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
       (s = scratch(ctx, "nb_tmp", sizeof(int32_t) * nn, &tmp)) ||
       (s = scratch(ctx, "nb_info", sizeof(int32_t) * 8, &info)) ||
       (s = scratch(ctx, "nb_cand", sizeof(int64_t) * (nunits + 1), &cand)) ||
+      (s = scratch(ctx, "nb_woff", sizeof(int64_t) * (nunits + 1), &woff)) ||
+      (s = scratch(ctx, "nb_cnt64", sizeof(int64_t) * (nunits + 1), &cnt64)) ||
       (s = scratch(ctx, "nb_rcnt", sizeof(int32_t) * (nn + 1), &rcnt)) ||
       (s = scratch(ctx, "nb_rptr", sizeof(int32_t) * (nn + 1), &rptr)))
     return s;
@@ -655,18 +676,18 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   }
   if (n > 0) {
     k_cand<<<ceil_div(nunits, 256), 256, 0, st>>>(nunits, units, cstart, (int64_t*)cand);
-    if ((s = scan_i64(ctx, st, (int64_t*)cand, (int64_t*)P.unit_off.p, nunits))) return s;
+    if ((s = scan_i64(ctx, st, (int64_t*)cand, (int64_t*)woff, nunits))) return s;
   }
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (n > 0) {
       k_nbhd<<<ncells, 64, 0, st>>>(cu, units, cstart, (int32_t*)info);
       {
         ProfScope ps(ctx, st, "nblist_plan");
+        windows = wb.p;
         k_plan<<<nunits, 64, 0, st>>>(nunits, units, cstart, (uint4*)P.us.p, sysd, cell_sys,
-                                      pstride, (int64_t*)P.unit_off.p,
-                                      (long)(P.codes.bytes / 4), (uint32_t*)P.codes.p,
-                                      (int32_t*)P.unit_cnt.p, (int32_t*)P.slots.p,
-                                      (int32_t*)info);
+                                      pstride, (int64_t*)woff, (long)(wb.bytes / 4),
+                                      (uint32_t*)windows, (int32_t*)P.unit_cnt.p,
+                                      (int64_t*)cnt64, (int32_t*)P.slots.p, (int32_t*)info);
       }
       k_row_slots<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)P.perm.p, (int32_t*)P.scell.p,
                                                      nslot, pstride, (int32_t*)P.slots.p,
@@ -675,11 +696,12 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     } else {
       TK_HIP(hipMemsetAsync(P.unit_cnt.p, 0, sizeof(int32_t) * nunits, st));
       TK_HIP(hipMemsetAsync(P.unit_off.p, 0, sizeof(int64_t) * (nunits + 1), st));
+      TK_HIP(hipMemsetAsync(woff, 0, sizeof(int64_t) * (nunits + 1), st));
       TK_HIP(hipMemsetAsync(rp, 0, sizeof(int32_t), st));
     }
     // one readback: status, max occupancy, max row, pairs, window overflow,
     // max neighbourhood, list total
-    k_readback<<<1, 1, 0, st>>>((int32_t*)info, rp + n, (int64_t*)P.unit_off.p + nunits, hd);
+    k_readback<<<1, 1, 0, st>>>((int32_t*)info, rp + n, (int64_t*)woff + nunits, hd);
     TK_HIP(hipGetLastError());
     TK_HIP(hipStreamSynchronize(st));
     if (h[0] != 0) return h[0];
@@ -687,7 +709,7 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     if (attempt == 1) return TK_E_HIP;
     // windows did not fit: grow to the exact size and enumerate again
     const int64_t need = *(int64_t*)(h + 8);
-    if ((s = ensure(P.codes, sizeof(uint32_t) * (size_t)need))) return s;
+    if ((s = ensure(wb, sizeof(uint32_t) * (size_t)need))) return s;
     TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
   }
   const int64_t list_pairs = h[6];
@@ -697,6 +719,15 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     return TK_E_HIP;
   }
   const int max_row = h[2];
+  // dense codes: unit_off = exclusive scan of the unit counts
+  if ((s = ensure(P.codes, sizeof(uint32_t) * (size_t)(list_pairs > 0 ? list_pairs : 1)))) return s;
+  if (n > 0) {
+    if ((s = scan_i64(ctx, st, (int64_t*)cnt64, (int64_t*)P.unit_off.p, nunits))) return s;
+    ProfScope ps(ctx, st, "nblist_compact");
+    k_compact<<<nunits, 64, 0, st>>>((const int64_t*)woff, (const uint32_t*)windows,
+                                     (const int64_t*)P.unit_off.p, (const int32_t*)P.unit_cnt.p,
+                                     (uint32_t*)P.codes.p);
+  }
   if (want_csr) {
     if (list_pairs > cap) return TK_E_CAPACITY;
     const int nb = max_row < kBuckets ? max_row : kBuckets;

@@ -107,10 +107,13 @@ struct tk_server {
 };
 
 extern "C" size_t tk_server_footprint(int32_t n) {
-  // inputs 164 B/atom (coordinates, molecule id, multipoles, four parameters,
-  // guess), outputs 72 B/atom, list plans and solver scratch ~2.8 KB/atom,
-  // plus fixed per-system tables
-  return (size_t)(n > 0 ? n : 0) * 3072 + 256 * 1024;
+  // per atom: inputs 164 B (coordinates, molecule id, multipoles, four
+  // parameters, guess) and outputs 72 B; candidate windows of the 9 A list
+  // build ~7.2 KB (transient, shared by both builds); pair codes of both
+  // lists ~1.1 KB; cached mat-vec factors ~1.4 KB; partial-result slots
+  // 0.7 KB; sorted fields and solver vectors ~0.5 KB.  Plus fixed per-system
+  // tables.
+  return (size_t)(n > 0 ? n : 0) * 11264 + 256 * 1024;
 }
 
 tk_status tk_server::run(std::vector<std::shared_ptr<Req>>& batch,
