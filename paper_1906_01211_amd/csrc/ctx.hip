@@ -113,6 +113,15 @@ CellTables& cell_tables(tk_ctx* ctx, int nc) {
       e[1 + e[0]++] = u * 4 + 1;
     }
   }
+  // cells grouped by octant (each axis split at ceil(nc/2)), lexicographic inside
+  const int half = (nc + 1) / 2;
+  for (int oct = 0; oct < 8; ++oct)
+    for (int x = 0; x < nc; ++x)
+      for (int y = 0; y < nc; ++y)
+        for (int z = 0; z < nc; ++z) {
+          const int o = (x >= half) * 4 + (y >= half) * 2 + (z >= half);
+          if (o == oct) t.order.push_back((x * nc + y) * nc + z);
+        }
   return ctx->tables.emplace(nc, std::move(t)).first->second;
 }
 

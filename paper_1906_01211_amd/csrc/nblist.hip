@@ -38,9 +38,9 @@ struct PairTest {
     const double dx = (double)(int32_t)(b.x - a.x), dy = (double)(int32_t)(b.y - a.y),
                  dz = (double)(int32_t)(b.z - a.z);
     const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    if (d2 < lo) return true;
-    if (d2 > hi) return false;
-    return pair_in(a, b, rq2);
+    bool in = d2 < lo;
+    if (!in && d2 <= hi) in = pair_in(a, b, rq2);   // rare: inside the rounding band
+    return in;
   }
 };
 
@@ -60,7 +60,7 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // info: [0] status, [1] max cell occupancy, [2] max CSR row, [3] listed pairs,
-//       [4] 1 if the candidate windows did not fit the plan buffer,
+//       [4] 1 if the candidate windows (or k_plan's staging bound) did not fit,
 //       [5] max atoms over a cell's neighbour cells
 // System of atom i: the last system whose first atom is <= i.
 __device__ __forceinline__ int atom_system(const SysDev* sys, int nsys, int i) {
@@ -226,9 +226,13 @@ __global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict_
                                              int32_t* __restrict__ unit_cnt,
                                              int64_t* __restrict__ cnt64,
                                              int32_t* __restrict__ slot_cnt,
-                                             int32_t* __restrict__ info) {
-  __shared__ uint4 sK[kMaxCellAtoms];
-  __shared__ int cH[kMaxCellAtoms], cK[kMaxCellAtoms];
+                                             int32_t* __restrict__ info, int occ_cap) {
+  // dynamic LDS: sK[occ_cap] (uint4) then cK[occ_cap]; occ_cap is the host's
+  // bound on the cell occupancy (a larger cell makes the host rerun with the
+  // full bound)
+  extern __shared__ uint4 plan_lds[];
+  uint4* sK = plan_lds;
+  int* cK = (int*)(plan_lds + occ_cap);
   const int uidx = blockIdx.x;
   const int lane = lane_id();
   if (unit_off[nunits] > code_cap) {   // windows do not fit: host grows the buffer, reruns
@@ -239,9 +243,12 @@ __global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict_
   const int hs = cstart[un.h], nh = cstart[un.h + 1] - hs;
   const int ks = cstart[un.k], nk = cstart[un.k + 1] - ks;
   if (nh > kMaxCellAtoms || nk > kMaxCellAtoms) return;
+  if (nk > occ_cap) {   // staging bound too small: host reruns with kMaxCellAtoms
+    if (lane == 0) info[4] = 1;
+    return;
+  }
   const PairTest test(sys[cell_sys ? cell_sys[un.h] : 0]);
   const bool self = un.h == un.k;
-  for (int t = lane; t < nh; t += 64) cH[t] = 0;
   for (int t = lane; t < nk; t += 64) {
     sK[t] = us[ks + t];
     cK[t] = 0;
@@ -250,23 +257,45 @@ __global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict_
   uint32_t* out = codes + unit_off[uidx];
   int cnt = 0;
   // visit order: (k, a) with a fastest; each lane keeps its own H atom in
-  // registers for a whole chunk of 64 a's.
+  // registers for a whole chunk of 64 a's, and kPlanUnroll steps of k are
+  // tested together (independent LDS reads and tests in flight) before their
+  // codes are written in order.
+  constexpr int kPlanUnroll = 4;
   for (int a0 = 0; a0 < nh; a0 += 64) {
     const int a = a0 + lane;
-    const uint4 ua = a < nh ? us[hs + a] : make_uint4(0, 0, 0, 0);
+    const bool av = a < nh;
+    const uint4 ua = av ? us[hs + a] : make_uint4(0, 0, 0, 0);
     int b = a;   // b = (a + kk) mod nk, advanced incrementally
     while (b >= nk && nk > 0) b -= nk;
-    for (int kk = 0; kk < nk; ++kk) {
-      bool pass = false;
-      if (a < nh && (!self || a < b)) pass = test(ua, sK[b]);
-      const uint64_t mask = __ballot(pass);
-      if (pass) {
-        out[cnt + lanes_below(mask)] = (uint32_t)a | ((uint32_t)b << 16);
-        atomicAdd(ua.w < sK[b].w ? &cH[a] : &cK[b], 1);
+    int own = 0;   // pairs whose CSR row is a's (a has the smaller caller index)
+    for (int kk0 = 0; kk0 < nk; kk0 += kPlanUnroll) {
+      int bj[kPlanUnroll];
+      uint4 kj[kPlanUnroll];
+      bool pj[kPlanUnroll];
+#pragma unroll
+      for (int j = 0; j < kPlanUnroll; ++j) {
+        bj[j] = b;
+        if (++b == nk) b = 0;
       }
-      cnt += __popcll(mask);
-      if (++b == nk) b = 0;
+#pragma unroll
+      for (int j = 0; j < kPlanUnroll; ++j) kj[j] = sK[bj[j]];
+#pragma unroll
+      for (int j = 0; j < kPlanUnroll; ++j) {   // branch-free except the rare band test
+        const bool ok = av & (kk0 + j < nk) & (!self | (a < bj[j]));
+        pj[j] = ok & test(ua, kj[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < kPlanUnroll; ++j) {
+        const uint64_t mask = __ballot(pj[j]);
+        if (pj[j]) {
+          out[cnt + lanes_below(mask)] = (uint32_t)a | ((uint32_t)bj[j] << 16);
+          if (ua.w < kj[j].w) ++own;
+          else atomicAdd(&cK[bj[j]], 1);
+        }
+        cnt += __popcll(mask);
+      }
     }
+    if (av) slot_cnt[(long)un.slot_h * pstride + hs + a] = own;
   }
   __syncthreads();
   if (lane == 0) {
@@ -274,7 +303,6 @@ __global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict_
     cnt64[uidx] = cnt;
     atomicAdd(&info[3], cnt);
   }
-  for (int t = lane; t < nh; t += 64) slot_cnt[(long)un.slot_h * pstride + hs + t] = cH[t];
   for (int t = lane; t < nk; t += 64) slot_cnt[(long)un.slot_k * pstride + ks + t] = cK[t];
 }
 
@@ -362,6 +390,7 @@ struct TplPtrs {
   const Unit* units;
   const int32_t* nslot;
   const int32_t* cu;
+  const int32_t* order;
 };
 
 __global__ void k_batch_units(int nunits, int nsys, const SysDev* __restrict__ sys,
@@ -381,7 +410,8 @@ __global__ void k_batch_units(int nunits, int nsys, const SysDev* __restrict__ s
 
 __global__ void k_batch_cells(int ncells, int nsys, const SysDev* __restrict__ sys,
                               const TplPtrs* __restrict__ tpl, int32_t* __restrict__ nslot,
-                              int32_t* __restrict__ cu, int32_t* __restrict__ cell_sys) {
+                              int32_t* __restrict__ cu, int32_t* __restrict__ cell_sys,
+                              int32_t* __restrict__ order) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
   int lo = 0, hi = nsys - 1;
@@ -394,6 +424,7 @@ __global__ void k_batch_cells(int ncells, int nsys, const SysDev* __restrict__ s
   const int lc = c - d.cell0;
   nslot[c] = tpl[lo].nslot[lc];
   cell_sys[c] = lo;
+  order[c] = d.cell0 + tpl[lo].order[lc];   // systems in turn, each octant-grouped
   const int32_t* e = tpl[lo].cu + (long)lc * kCellUnitStride;
   int32_t* o = cu + (long)c * kCellUnitStride;
   o[0] = e[0];
@@ -498,9 +529,12 @@ static tk_status upload_tables(CellTables& T) {
   tk_status s;
   if ((s = ensure(T.units_d, sizeof(Unit) * T.nunits)) ||
       (s = ensure(T.nslot_d, sizeof(int32_t) * T.ncells)) ||
-      (s = ensure(T.cu_d, sizeof(int32_t) * T.cu.size())))
+      (s = ensure(T.cu_d, sizeof(int32_t) * T.cu.size())) ||
+      (s = ensure(T.order_d, sizeof(int32_t) * T.order.size())))
     return s;
   TK_HIP(hipMemcpy(T.cu_d.p, T.cu.data(), sizeof(int32_t) * T.cu.size(), hipMemcpyHostToDevice));
+  TK_HIP(hipMemcpy(T.order_d.p, T.order.data(), sizeof(int32_t) * T.order.size(),
+                   hipMemcpyHostToDevice));
   TK_HIP(hipMemcpy(T.units_d.p, T.units.data(), sizeof(Unit) * T.nunits, hipMemcpyHostToDevice));
   TK_HIP(hipMemcpy(T.nslot_d.p, T.nslot.data(), sizeof(int32_t) * T.ncells, hipMemcpyHostToDevice));
   T.uploaded = true;
@@ -602,21 +636,23 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   TK_HIP(hipMemcpyAsync(P.sysd.p, hb + 4096, sys_bytes, hipMemcpyHostToDevice, st));
   const SysDev* sysd = (const SysDev*)P.sysd.p;
   const Unit* units;
-  const int32_t *nslot, *cu, *cell_sys = nullptr;
+  const int32_t *nslot, *cu, *order, *cell_sys = nullptr;
   if (nsys == 1) {
     units = (const Unit*)tabs[0]->units_d.p;
     nslot = (const int32_t*)tabs[0]->nslot_d.p;
     cu = (const int32_t*)tabs[0]->cu_d.p;
+    order = (const int32_t*)tabs[0]->order_d.p;
   } else {
     TplPtrs* tp = (TplPtrs*)(hb + tpl_off);
     for (int k = 0; k < nsys; ++k)
       tp[k] = TplPtrs{(const Unit*)tabs[k]->units_d.p, (const int32_t*)tabs[k]->nslot_d.p,
-                      (const int32_t*)tabs[k]->cu_d.p};
+                      (const int32_t*)tabs[k]->cu_d.p, (const int32_t*)tabs[k]->order_d.p};
     if ((s = ensure(P.tplp, sizeof(TplPtrs) * nsys)) ||
         (s = ensure(P.bunits, sizeof(Unit) * nunits)) ||
         (s = ensure(P.bnslot, sizeof(int32_t) * ncells)) ||
         (s = ensure(P.bcu, sizeof(int32_t) * kCellUnitStride * (size_t)ncells)) ||
-        (s = ensure(P.cell_sys, sizeof(int32_t) * ncells)))
+        (s = ensure(P.cell_sys, sizeof(int32_t) * ncells)) ||
+        (s = ensure(P.border, sizeof(int32_t) * ncells)))
       return s;
     TK_HIP(hipMemcpyAsync(P.tplp.p, tp, sizeof(TplPtrs) * nsys, hipMemcpyHostToDevice, st));
     k_batch_units<<<ceil_div(nunits, 256), 256, 0, st>>>(nunits, nsys, sysd,
@@ -625,10 +661,12 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     k_batch_cells<<<ceil_div(ncells, 256), 256, 0, st>>>(ncells, nsys, sysd,
                                                          (const TplPtrs*)P.tplp.p,
                                                          (int32_t*)P.bnslot.p, (int32_t*)P.bcu.p,
-                                                         (int32_t*)P.cell_sys.p);
+                                                         (int32_t*)P.cell_sys.p,
+                                                         (int32_t*)P.border.p);
     units = (const Unit*)P.bunits.p;
     nslot = (const int32_t*)P.bnslot.p;
     cu = (const int32_t*)P.bcu.p;
+    order = (const int32_t*)P.border.p;
     cell_sys = (const int32_t*)P.cell_sys.p;
   }
   TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
@@ -678,16 +716,27 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     k_cand<<<ceil_div(nunits, 256), 256, 0, st>>>(nunits, units, cstart, (int64_t*)cand);
     if ((s = scan_i64(ctx, st, (int64_t*)cand, (int64_t*)woff, nunits))) return s;
   }
+  // staging bound of k_plan: three times the largest mean cell occupancy
+  // (at least 64); a denser cell makes the build rerun with kMaxCellAtoms
+  double max_mean = 0.0;
+  for (int k = 0; k < nsys; ++k) {
+    const int cells = sd[k + 1].cell0 - sd[k].cell0;
+    max_mean = std::fmax(max_mean, (double)(spec.atom0[k + 1] - spec.atom0[k]) / cells);
+  }
+  int occ_cap = (int)std::ceil(3.0 * max_mean);
+  occ_cap = occ_cap < 64 ? 64 : occ_cap > kMaxCellAtoms ? kMaxCellAtoms : occ_cap;
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (n > 0) {
       k_nbhd<<<ncells, 64, 0, st>>>(cu, units, cstart, (int32_t*)info);
       {
         ProfScope ps(ctx, st, "nblist_plan");
         windows = wb.p;
-        k_plan<<<nunits, 64, 0, st>>>(nunits, units, cstart, (uint4*)P.us.p, sysd, cell_sys,
-                                      pstride, (int64_t*)woff, (long)(wb.bytes / 4),
-                                      (uint32_t*)windows, (int32_t*)P.unit_cnt.p,
-                                      (int64_t*)cnt64, (int32_t*)P.slots.p, (int32_t*)info);
+        const size_t plds = (sizeof(uint4) + sizeof(int)) * (size_t)occ_cap;
+        k_plan<<<nunits, 64, plds, st>>>(nunits, units, cstart, (uint4*)P.us.p, sysd, cell_sys,
+                                         pstride, (int64_t*)woff, (long)(wb.bytes / 4),
+                                         (uint32_t*)windows, (int32_t*)P.unit_cnt.p,
+                                         (int64_t*)cnt64, (int32_t*)P.slots.p, (int32_t*)info,
+                                         occ_cap);
       }
       k_row_slots<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)P.perm.p, (int32_t*)P.scell.p,
                                                      nslot, pstride, (int32_t*)P.slots.p,
@@ -707,9 +756,10 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     if (h[0] != 0) return h[0];
     if (h[4] == 0) break;
     if (attempt == 1) return TK_E_HIP;
-    // windows did not fit: grow to the exact size and enumerate again
+    // windows or staging bound did not fit: exact sizes, enumerate again
     const int64_t need = *(int64_t*)(h + 8);
     if ((s = ensure(wb, sizeof(uint32_t) * (size_t)need))) return s;
+    occ_cap = kMaxCellAtoms;
     TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
   }
   const int64_t list_pairs = h[6];
@@ -763,6 +813,7 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   P.units_p = units;
   P.nslot_p = nslot;
   P.cu_p = cu;
+  P.order_p = order;
   return TK_OK;
 }
 

@@ -99,16 +99,19 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_setup(PlanView pv, const do
   if (threadIdx.x == 0) npart[c] = cnt[0];
 }
 
-// One thread per system: fresh state.  active (device, nullable): systems
+// One block per system: fresh state.  active (device, nullable): systems
 // outside the solve start as done.
-__global__ void k_cs_init(PlanView pv, const double* __restrict__ npart, PcgState* st, double tol,
-                          int maxiter, const int32_t* __restrict__ active) {
-  const int sy = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sy >= pv.nsys) return;
-  double np = 0.0;
-  for (int c = pv.sys[sy].cell0; c < pv.sys[sy + 1].cell0; ++c) np += npart[c];
+__global__ __launch_bounds__(64) void k_cs_init(PlanView pv, const double* __restrict__ npart,
+                                                PcgState* st, double tol, int maxiter,
+                                                const int32_t* __restrict__ active) {
+  __shared__ double sh[16];
+  const int sy = blockIdx.x;
+  double np[1] = {0.0};
+  for (int c = pv.sys[sy].cell0 + threadIdx.x; c < pv.sys[sy + 1].cell0; c += 64) np[0] += npart[c];
+  wg_sum<1>(np, sh);
+  if (threadIdx.x != 0) return;
   PcgState s0 = {};
-  s0.npol = (int)np;
+  s0.npol = (int)np[0];
   s0.tol = tol;
   s0.maxiter = maxiter;
   s0.done = active && !active[sy] ? 1 : 0;
@@ -118,9 +121,10 @@ __global__ void k_cs_init(PlanView pv, const double* __restrict__ npart, PcgStat
 // ---------------------------------------------------------------------------
 // Per-cell mat-vec with the iteration's bookkeeping folded in.
 //
-// One workgroup per cell C owns C's atoms.  It walks the pair codes of all
-// units C takes part in (each unordered pair is therefore visited from both
-// of its cells) and accumulates only C's side.  With kStage the coordinates
+// One workgroup per cell C owns C's atoms (cells in the XCD-local order of
+// xcd_cell).  It walks the pair codes of all units C takes part in (each
+// unordered pair is therefore visited from both of its cells) and
+// accumulates only C's side.  With kStage the coordinates
 // and operand of all of C's neighbour cells are staged in LDS first;
 // otherwise (neighbourhoods too large for LDS) they are read from the sorted
 // arrays.  Each wave keeps its own accumulator copy in LDS, summed in wave
@@ -170,15 +174,17 @@ __global__ __launch_bounds__(kCellThreads) void k_pcg_mv(MvArgs<R> A) {
   __shared__ int e_off[kCellUnitStride + 1], e_pre[kCellUnitStride + 1];
   __shared__ long e_uoff[kCellUnitStride];
   __shared__ int self_j, s_done;
-  const int c = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const PlanView& pv = A.pv;
+  const int c = xcd_cell(pv, blockIdx.x);
+  if (c < 0) return;
   const CellSys cs = cell_sys_of(pv, c);
   PcgState* st = A.st + cs.sy;
   if (tid == 0) s_done = st->done;   // one read per workgroup: all its waves agree
   __syncthreads();
   if (kMode != 2 && s_done) return;
   if (kMode == 2 && !s_done) return;
-  const int ncells = gridDim.x;
+  const int ncells = pv.ncells;
   double beta = 0.0;
   if (kMode == 1) {
     double v3[3] = {0.0, 0.0, 0.0};
@@ -411,7 +417,8 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_update(
     double* __restrict__ pz_next, int k, PcgState* states, PcgState* host) {
   __shared__ double sh[2 * 16];
   __shared__ int s_done;
-  const int c = blockIdx.x, ncells = gridDim.x;
+  const int c = xcd_cell(pv, blockIdx.x), ncells = pv.ncells;
+  if (c < 0) return;
   const CellSys cs = cell_sys_of(pv, c);
   PcgState* st = states + cs.sy;
   if (threadIdx.x == 0) s_done = st->done;   // one read per workgroup: all its waves agree
@@ -647,9 +654,9 @@ struct Solver {
   void launch_mv(const MvArgs<R>& a, const char* name) {
     ProfScope ps(ctx, st, std::string(name) + prec_tag<R>());
     if (stage)
-      k_pcg_mv<R, kMode, true><<<ncells, kCellThreads, mv_lds, st>>>(a);
+      k_pcg_mv<R, kMode, true><<<xcd_grid(ncells), kCellThreads, mv_lds, st>>>(a);
     else
-      k_pcg_mv<R, kMode, false><<<ncells, kCellThreads, mv_lds, st>>>(a);
+      k_pcg_mv<R, kMode, false><<<xcd_grid(ncells), kCellThreads, mv_lds, st>>>(a);
   }
 
   // iteration k, first half: convergence test, p_k, q = A p_k
@@ -670,7 +677,7 @@ struct Solver {
   // iteration k, second half: update x, r, z
   void queue_update(int k) {
     ProfScope ps(ctx, st, "pcg_update");
-    k_cs_update<<<ncells, kCellThreads, 0, st>>>(pv, alpha_s, pbuf[k & 1], q, x, r, z, pg,
+    k_cs_update<<<xcd_grid(ncells), kCellThreads, 0, st>>>(pv, alpha_s, pbuf[k & 1], q, x, r, z, pg,
                                                  pz[k & 1], pz[(k + 1) & 1], k, state, host_dev);
   }
 
@@ -770,7 +777,7 @@ struct Solver {
   template <class R>
   tk_status run(const double* rhs, double tol, int maxiter, int first_chunk, bool residual,
                 const int32_t* act) {
-    k_cs_init<<<ceil_div(nsys, 64), 64, 0, st>>>(pv, npart, state, tol, maxiter, act);
+    k_cs_init<<<nsys, 64, 0, st>>>(pv, npart, state, tol, maxiter, act);
     {
       MvArgs<R> a = mv_args<R>();
       a.v = x;

@@ -63,10 +63,24 @@ struct PlanView {
   const int32_t* unit_cnt;    // [nunits] listed pairs of the unit (window prefix)
   const uint32_t* codes;      // pair codes: a | b << 16 (local indices in H, K)
   const int32_t* cell_units;  // [ncells][28]: count, then unit * 4 + role
+  const int32_t* cell_order;  // [ncells] cells grouped by octant of their system's box
   int32_t nsys;
   const SysDev* sys;          // [nsys]
   const int32_t* cell_sys;    // [ncells] system of each cell; nullptr when nsys == 1
 };
+
+// Workgroups are dispatched to the 8 XCDs round-robin.  Per-cell kernels
+// launch 8 * ceil(ncells / 8) workgroups and map workgroup i to position
+// (i % 8) * ceil(ncells / 8) + i / 8 of the octant-grouped cell order, so
+// each XCD (with its own L2) works on one spatially compact block of cells
+// and most neighbour cells share an L2.  Returns -1 for the padding.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_cell(const PlanView& pv, int wg) {
+  const int per = (pv.ncells + kXcds - 1) / kXcds;
+  const int pos = (wg % kXcds) * per + wg / kXcds;
+  return pos < pv.ncells ? pv.cell_order[pos] : -1;
+}
+inline int xcd_grid(int ncells) { return (ncells + kXcds - 1) / kXcds * kXcds; }
 
 // System of a cell (0 for single-system plans).
 __device__ __forceinline__ int cell_system(const PlanView& pv, int c) {
@@ -89,9 +103,10 @@ struct Plan {
   const Unit* units_p = nullptr;       // device cell tables (shared by plans with the same
   const int32_t* nslot_p = nullptr;    // nc for one system; built per batch otherwise)
   const int32_t* cu_p = nullptr;
+  const int32_t* order_p = nullptr;
   int32_t nsys = 1;
   std::vector<SysDev> h_sys;           // host copy, with a final entry holding the totals
-  DevBuf sysd, cell_sys, bunits, bnslot, bcu, tplp;
+  DevBuf sysd, cell_sys, bunits, bnslot, bcu, border, tplp;
   PlanView view() const {
     PlanView v;
     v.nsys = nsys;
@@ -104,6 +119,7 @@ struct Plan {
     v.unit_cnt = (const int32_t*)unit_cnt.p;
     v.codes = (const uint32_t*)codes.p;
     v.cell_units = cu_p;
+    v.cell_order = order_p;
     return v;
   }
 };
@@ -114,8 +130,9 @@ struct CellTables {   // host-built tables for one cells-per-edge value
   std::vector<int32_t> nslot;     // per cell
   std::vector<int32_t> nbr;       // per cell: count, then up to 27 neighbour cells
   std::vector<int32_t> cu;        // per cell: count, then unit * 4 + role (kCellUnitStride)
+  std::vector<int32_t> order;     // cells grouped by octant of the box (XCD-local workgroups)
   bool uploaded = false;
-  DevBuf units_d, nslot_d, cu_d;  // device copies
+  DevBuf units_d, nslot_d, cu_d, order_d;  // device copies
 };
 
 }  // namespace tk

@@ -93,6 +93,20 @@ def test_nblist_random_boxes(ctx, n, box, rc, seed):
     assert_list_equal(lst, rp, cp)
 
 
+@pytest.mark.parametrize("seed", [5, 6])
+def test_nblist_clustered(ctx, seed):
+    # most atoms in one small region: cells far denser than the mean, which
+    # exceeds the enumeration's first staging bound and makes the build rerun
+    rng = np.random.default_rng(seed)
+    box = 30.0
+    xyz = np.concatenate([rng.uniform(11.0, 16.0, size=(300, 3)),
+                          rng.uniform(0.0, box, size=(60, 3))])
+    sysr = ctx.system(xyz, box, np.arange(len(xyz)) // 3)
+    lst = ctx.nblist(sysr, 7.001, plan_slot=1)
+    rp, cp = O.nblist(xyz, box, 7.001)
+    assert_list_equal(lst, rp, cp)
+
+
 def test_nblist_errors(ctx, tk):
     xyz = np.random.default_rng(0).uniform(0, 10, size=(20, 3))
     sysr = ctx.system(xyz, 10.0, np.arange(20))
