@@ -59,7 +59,7 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// info: [0] status, [1] max cell occupancy, [2] max CSR row, [3] listed pairs,
+// info: [0] status, [1] max cell occupancy, [2] max CSR row, [3] unused,
 //       [4] 1 if the candidate windows (or k_plan's staging bound) did not fit,
 //       [5] max atoms over a cell's neighbour cells
 // System of atom i: the last system whose first atom is <= i.
@@ -301,7 +301,6 @@ __global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict_
   if (lane == 0) {
     unit_cnt[uidx] = cnt;
     cnt64[uidx] = cnt;
-    atomicAdd(&info[3], cnt);
   }
   for (int t = lane; t < nk; t += 64) slot_cnt[(long)un.slot_k * pstride + ks + t] = cK[t];
 }
@@ -326,8 +325,9 @@ __global__ void k_row_slots(int n, const int32_t* __restrict__ perm, const int32
                             const int32_t* __restrict__ cell_nslot, long pstride,
                             int32_t* __restrict__ slot_cnt, int32_t* __restrict__ row_cnt,
                             int32_t* __restrict__ info) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+  const int s0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = s0 < n;
+  const int s = valid ? s0 : n - 1;   // lanes past the end repeat the last atom, write nothing
   const int ns = cell_nslot[scell[s]];
   int c[kMaxSlots];
 #pragma unroll
@@ -335,11 +335,14 @@ __global__ void k_row_slots(int n, const int32_t* __restrict__ perm, const int32
   int run = 0;
 #pragma unroll
   for (int k = 0; k < kMaxSlots; ++k) {
-    if (k < ns) slot_cnt[(long)k * pstride + s] = run;
+    if (valid && k < ns) slot_cnt[(long)k * pstride + s] = run;
     run += c[k];
   }
-  row_cnt[perm[s]] = run;
-  atomicMax(&info[2], run);
+  if (valid) row_cnt[perm[s]] = run;
+  // longest row: wave maximum, then one atomic per wave (not per atom)
+  int m = run;
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(&info[2], m);
 }
 
 // One wave per unit: each listed pair's j goes into its CSR row, at the
@@ -433,27 +436,36 @@ __global__ void k_batch_cells(int ncells, int nsys, const SysDev* __restrict__ s
 
 // One wave per cell: atoms in its neighbour cells (itself included); the
 // maximum goes to info[5] (staging size of the per-cell mat-vec).
-__global__ __launch_bounds__(64) void k_nbhd(const int32_t* __restrict__ cu,
-                                             const Unit* __restrict__ units,
-                                             const int32_t* __restrict__ cstart,
-                                             int32_t* __restrict__ info) {
-  const int32_t* e = cu + (long)blockIdx.x * kCellUnitStride;
+__global__ __launch_bounds__(256) void k_nbhd(int ncells, const int32_t* __restrict__ cu,
+                                              const Unit* __restrict__ units,
+                                              const int32_t* __restrict__ cstart,
+                                              int32_t* __restrict__ info) {
+  __shared__ int wmax[4];
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per cell
   const int lane = lane_id();
   int cnt = 0;
-  if (lane < e[0]) {
-    const int u = e[1 + lane] >> 2, role = e[1 + lane] & 3;
-    const int oc = role == 1 ? units[u].h : units[u].k;
-    cnt = cstart[oc + 1] - cstart[oc];
+  if (c < ncells) {
+    const int32_t* e = cu + (long)c * kCellUnitStride;
+    if (lane < e[0]) {
+      const int u = e[1 + lane] >> 2, role = e[1 + lane] & 3;
+      const int oc = role == 1 ? units[u].h : units[u].k;
+      cnt = cstart[oc + 1] - cstart[oc];
+    }
   }
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-  if (lane == 0) atomicMax(&info[5], cnt);
+  if (lane == 0) wmax[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(&info[5], max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3])));
 }
 
 // Gathers the build's outcome into pinned host memory (one kernel instead of
 // several small copies).
 __global__ void k_readback(const int32_t* __restrict__ info, const int32_t* __restrict__ rp_end,
-                           const int64_t* __restrict__ off_end, int32_t* __restrict__ host) {
+                           const int64_t* __restrict__ off_end, const int64_t* __restrict__ pairs,
+                           int32_t* __restrict__ host) {
   for (int k = 0; k < 6; ++k) host[k] = info[k];
+  host[3] = (int32_t)*pairs;   // listed pairs, summed over the units
   host[6] = *rp_end;
   *(int64_t*)(host + 8) = *off_end;
 }
@@ -727,7 +739,7 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   occ_cap = occ_cap < 64 ? 64 : occ_cap > kMaxCellAtoms ? kMaxCellAtoms : occ_cap;
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (n > 0) {
-      k_nbhd<<<ncells, 64, 0, st>>>(cu, units, cstart, (int32_t*)info);
+      k_nbhd<<<ceil_div(ncells, 4), 256, 0, st>>>(ncells, cu, units, cstart, (int32_t*)info);
       {
         ProfScope ps(ctx, st, "nblist_plan");
         windows = wb.p;
@@ -742,6 +754,8 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
                                                      nslot, pstride, (int32_t*)P.slots.p,
                                                      (int32_t*)rcnt, (int32_t*)info);
       if ((s = scan_i32(ctx, st, (int32_t*)rcnt, rp, n))) return s;
+      // dense code offsets (and the unit-based pair total for the readback)
+      if ((s = scan_i64(ctx, st, (int64_t*)cnt64, (int64_t*)P.unit_off.p, nunits))) return s;
     } else {
       TK_HIP(hipMemsetAsync(P.unit_cnt.p, 0, sizeof(int32_t) * nunits, st));
       TK_HIP(hipMemsetAsync(P.unit_off.p, 0, sizeof(int64_t) * (nunits + 1), st));
@@ -750,7 +764,8 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     }
     // one readback: status, max occupancy, max row, pairs, window overflow,
     // max neighbourhood, list total
-    k_readback<<<1, 1, 0, st>>>((int32_t*)info, rp + n, (int64_t*)woff + nunits, hd);
+    k_readback<<<1, 1, 0, st>>>((int32_t*)info, rp + n, (int64_t*)woff + nunits,
+                                (int64_t*)P.unit_off.p + nunits, hd);
     TK_HIP(hipGetLastError());
     TK_HIP(hipStreamSynchronize(st));
     if (h[0] != 0) return h[0];
@@ -769,10 +784,9 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     return TK_E_HIP;
   }
   const int max_row = h[2];
-  // dense codes: unit_off = exclusive scan of the unit counts
+  // dense codes at unit_off (the exclusive scan of the unit counts)
   if ((s = ensure(P.codes, sizeof(uint32_t) * (size_t)(list_pairs > 0 ? list_pairs : 1)))) return s;
   if (n > 0) {
-    if ((s = scan_i64(ctx, st, (int64_t*)cnt64, (int64_t*)P.unit_off.p, nunits))) return s;
     ProfScope ps(ctx, st, "nblist_compact");
     k_compact<<<nunits, 64, 0, st>>>((const int64_t*)woff, (const uint32_t*)windows,
                                      (const int64_t*)P.unit_off.p, (const int32_t*)P.unit_cnt.p,

@@ -138,6 +138,8 @@ __global__ __launch_bounds__(64) void k_cs_init(PlanView pv, const double* __res
 //          cell of each system records its state and mirrors it to the host.
 // kMode 2: v = x (only once the system has stopped): partials of
 //          |alpha (b - A x)|^2 and x.b.
+constexpr int kMvThreads = 512;    // mat-vec workgroups: 8 waves per cell
+constexpr int kMvWaves = kMvThreads / 64;
 constexpr int kMvBatch = 4;        // pairs per thread whose loads are issued together
 constexpr int kMvStageBatch = 4;   // staged atoms per thread whose loads are issued together
 
@@ -167,7 +169,7 @@ struct MvArgs {
 };
 
 template <class R, int kMode, bool kStage>
-__global__ __launch_bounds__(kCellThreads) void k_pcg_mv(MvArgs<R> A) {
+__global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   extern __shared__ double lds[];
   __shared__ double red[3 * 16];
   __shared__ int e_role[kCellUnitStride], e_cs[kCellUnitStride];
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(kCellThreads) void k_pcg_mv(MvArgs<R> A) {
   double beta = 0.0;
   if (kMode == 1) {
     double v3[3] = {0.0, 0.0, 0.0};
-    for (int cc = cs.c0 + tid; cc < cs.c1; cc += kCellThreads) {
+    for (int cc = cs.c0 + tid; cc < cs.c1; cc += kMvThreads) {
       v3[0] += A.pz_cur[cc];
       v3[1] += A.pz_cur[ncells + cc];
       if (A.k >= 1) v3[2] += A.pz_prev[cc];
@@ -259,11 +261,11 @@ __global__ __launch_bounds__(kCellThreads) void k_pcg_mv(MvArgs<R> A) {
   double* ACC = L + 6 * SC;
   const int own0 = kStage ? e_off[self_j] : 0;
   const int total = kStage ? e_off[ne] : nown;
-  for (int i0 = tid; i0 < total; i0 += kCellThreads * kMvStageBatch) {
+  for (int i0 = tid; i0 < total; i0 += kMvThreads * kMvStageBatch) {
     int src[kMvStageBatch];
 #pragma unroll
     for (int m = 0; m < kMvStageBatch; ++m) {
-      const int i = i0 + m * kCellThreads;
+      const int i = i0 + m * kMvThreads;
       int sidx = -1;
       if (i < total) {
         if (kStage) {
@@ -294,12 +296,12 @@ __global__ __launch_bounds__(kCellThreads) void k_pcg_mv(MvArgs<R> A) {
 #pragma unroll
     for (int m = 0; m < kMvStageBatch; ++m) {
       if (src[m] < 0) continue;
-      const int i = i0 + m * kCellThreads;
+      const int i = i0 + m * kMvThreads;
 #pragma unroll
       for (int d = 0; d < 6; ++d) L[d * SC + i] = f[m][d];
     }
   }
-  for (int i = tid; i < kCellWaves * 3 * nown; i += kCellThreads) {
+  for (int i = tid; i < kMvWaves * 3 * nown; i += kMvThreads) {
     const int ww = i / (3 * nown), rem = i - ww * 3 * nown;
     ACC[ww * 3 * OC + rem] = 0.0;   // [ww][d][t] with rem = d * nown + t
   }
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(kCellThreads) void k_pcg_mv(MvArgs<R> A) {
   double* MY = ACC + w * 3 * OC;   // this wave's copy: MY[d * nown + t]
   const int T = e_pre[ne];
   int j = 0;
-  for (int v0 = tid; v0 < T; v0 += kCellThreads * kMvBatch) {
+  for (int v0 = tid; v0 < T; v0 += kMvThreads * kMvBatch) {
     // the batch's code and factor loads are issued together; unit data is
     // kept in registers (no LDS reads after the atomics)
     uint32_t codes[kMvBatch];
@@ -315,7 +317,7 @@ __global__ __launch_bounds__(kCellThreads) void k_pcg_mv(MvArgs<R> A) {
     int roles[kMvBatch], offs[kMvBatch];
 #pragma unroll
     for (int m = 0; m < kMvBatch; ++m) {
-      const int vix = v0 + m * kCellThreads;
+      const int vix = v0 + m * kMvThreads;
       roles[m] = -1;
       if (vix < T) {
         while (vix >= e_pre[j + 1]) ++j;
@@ -370,14 +372,14 @@ __global__ __launch_bounds__(kCellThreads) void k_pcg_mv(MvArgs<R> A) {
   }
   __syncthreads();
   double sv[2] = {0.0, 0.0};
-  for (int t = tid; t < nown; t += kCellThreads) {
+  for (int t = tid; t < nown; t += kMvThreads) {
     const int s = hs + t;
     const double al = A.alpha_s[s];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       double f = 0.0;
 #pragma unroll
-      for (int ww = 0; ww < kCellWaves; ++ww) f += ACC[ww * 3 * OC + d * nown + t];
+      for (int ww = 0; ww < kMvWaves; ++ww) f += ACC[ww * 3 * OC + d * nown + t];
       const double vv = L[(3 + d) * SC + own0 + t];
       const double av = al > 0.0 ? vv / al - (f + A.cself * vv) : 0.0;   // (A v)_s
       if (kMode == 1) {
@@ -654,9 +656,9 @@ struct Solver {
   void launch_mv(const MvArgs<R>& a, const char* name) {
     ProfScope ps(ctx, st, std::string(name) + prec_tag<R>());
     if (stage)
-      k_pcg_mv<R, kMode, true><<<xcd_grid(ncells), kCellThreads, mv_lds, st>>>(a);
+      k_pcg_mv<R, kMode, true><<<xcd_grid(ncells), kMvThreads, mv_lds, st>>>(a);
     else
-      k_pcg_mv<R, kMode, false><<<xcd_grid(ncells), kCellThreads, mv_lds, st>>>(a);
+      k_pcg_mv<R, kMode, false><<<xcd_grid(ncells), kMvThreads, mv_lds, st>>>(a);
   }
 
   // iteration k, first half: convergence test, p_k, q = A p_k
@@ -839,7 +841,7 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   S.pstride = pad64(n);
   S.gcs = (long)(P->codes.bytes / sizeof(uint32_t));
   // stage whole neighbourhoods in LDS when they fit, else only the own cell
-  const size_t acc = (size_t)kCellWaves * 3 * P->max_occ;
+  const size_t acc = (size_t)kMvWaves * 3 * P->max_occ;
   S.stage = sizeof(double) * (6 * (size_t)P->max_nbhd + acc) + 4096 <= kMaxLds;
   S.mv_lds = sizeof(double) * (6 * (size_t)(S.stage ? P->max_nbhd : P->max_occ) + acc);
   if (S.mv_lds + 4096 > kMaxLds) return TK_E_CAPACITY;   // a cell beyond the LDS limit
