@@ -112,8 +112,8 @@ extern "C" tk_status tk_batch_step(tk_ctx* ctx, void* stream, const tk_batch* b,
   double* w1 = e1 + nsys;
   TK_HIP(hipMemcpyAsync(cutd, r9.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, st));
   if (n > 0) {
-    if (unit_lds_bytes<EmpolePh<double>>(P7) > kMaxLds ||
-        unit_lds_bytes<VdwPh<double>>(P9) > kMaxLds)
+    if (unit_lds_bytes<EmpolePh<double>>(P7, 1) > kMaxLds ||
+        unit_lds_bytes<VdwPh<double>>(P9, 1) > kMaxLds)
       return TK_E_CAPACITY;
     s = p->prec == TK_FP64
             ? run_mpole<double>(ctx, st, P7, b, mpole, p, force_mpole, (double*)sums3)

@@ -156,12 +156,17 @@ __global__ __launch_bounds__(kHistBlock) void k_scatter_stable(
     us[slot] = make_uint4(u[3 * i], u[3 * i + 1], u[3 * i + 2], (uint32_t)i);
   }
   if (blockIdx.x == 0) {
+    int occ = 0;
     for (int cc = threadIdx.x; cc < ncells; cc += kHistBlock) {
       const int s0 = off[(long)cc * nblk];
       const int s1 = cc + 1 < ncells ? off[(long)(cc + 1) * nblk] : n;
       cstart[cc] = s0;
-      atomicMax(&info[1], s1 - s0);
-      if (s1 - s0 > kMaxCellAtoms) atomicMin(&info[0], (int)TK_E_CAPACITY);
+      occ = max(occ, s1 - s0);
+    }
+    for (int o = 32; o > 0; o >>= 1) occ = max(occ, __shfl_xor(occ, o));
+    if ((threadIdx.x & 63) == 0) {   // one atomic per wave
+      atomicMax(&info[1], occ);
+      if (occ > kMaxCellAtoms) atomicMin(&info[0], (int)TK_E_CAPACITY);
     }
     if (threadIdx.x == 0) cstart[ncells] = n;
   }
@@ -308,15 +313,23 @@ __global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict_
 // One wave per unit: move the unit's pair codes from its candidate window
 // to its place in the dense code array (windows are sized by candidates,
 // the dense array by listed pairs).
-__global__ __launch_bounds__(64) void k_compact(const int64_t* __restrict__ woff,
-                                                const uint32_t* __restrict__ windows,
-                                                const int64_t* __restrict__ doff,
-                                                const int32_t* __restrict__ unit_cnt,
-                                                uint32_t* __restrict__ codes) {
+__global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ woff,
+                                                 const uint32_t* __restrict__ windows,
+                                                 const int64_t* __restrict__ doff,
+                                                 const int32_t* __restrict__ unit_cnt,
+                                                 uint32_t* __restrict__ codes) {
   const int u = blockIdx.x;
   const uint32_t* src = windows + woff[u];
   uint32_t* dst = codes + doff[u];
-  for (int t = threadIdx.x; t < unit_cnt[u]; t += 64) dst[t] = src[t];
+  const int m = unit_cnt[u];
+  for (int t0 = threadIdx.x; t0 < m; t0 += 4 * 256) {   // four loads in flight per thread
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = t0 + k * 256 < m ? src[t0 + k * 256] : 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (t0 + k * 256 < m) dst[t0 + k * 256] = v[k];
+  }
 }
 
 // Per sorted atom: the CSR row length (sum over its unit roles, written in
@@ -347,43 +360,57 @@ __global__ void k_row_slots(int n, const int32_t* __restrict__ perm, const int32
 
 // One wave per unit: each listed pair's j goes into its CSR row, at the
 // owner atom's role offset (order inside a role is fixed by the row sort).
-__global__ __launch_bounds__(64) void k_csr_fill(const Unit* __restrict__ units,
-                                                 const int32_t* __restrict__ cstart,
-                                                 const int32_t* __restrict__ perm, long pstride,
-                                                 const int64_t* __restrict__ unit_off,
-                                                 const int32_t* __restrict__ unit_cnt,
-                                                 const uint32_t* __restrict__ codes,
-                                                 const int32_t* __restrict__ slot_off,
-                                                 const int32_t* __restrict__ row_ptr,
-                                                 int32_t* __restrict__ col) {
-  __shared__ int pH[kMaxCellAtoms], pK[kMaxCellAtoms], cH[kMaxCellAtoms], cK[kMaxCellAtoms];
-  __shared__ int bH[kMaxCellAtoms], bK[kMaxCellAtoms];
-  const int uidx = blockIdx.x, lane = lane_id();
+__global__ __launch_bounds__(256) void k_csr_fill(const Unit* __restrict__ units,
+                                                  const int32_t* __restrict__ cstart,
+                                                  const int32_t* __restrict__ perm, long pstride,
+                                                  const int64_t* __restrict__ unit_off,
+                                                  const int32_t* __restrict__ unit_cnt,
+                                                  const uint32_t* __restrict__ codes,
+                                                  const int32_t* __restrict__ slot_off,
+                                                  const int32_t* __restrict__ row_ptr,
+                                                  int32_t* __restrict__ col, int occ) {
+  // dynamic LDS, occ entries each: pH pK cH cK bH bK
+  extern __shared__ int fill_lds[];
+  int* pH = fill_lds;
+  int* pK = pH + occ;
+  int* cH = pK + occ;
+  int* cK = cH + occ;
+  int* bH = cK + occ;
+  int* bK = bH + occ;
+  const int uidx = blockIdx.x, tid = threadIdx.x;
   const Unit un = units[uidx];
   const int hs = cstart[un.h], nh = cstart[un.h + 1] - hs;
   const int ks = cstart[un.k], nk = cstart[un.k + 1] - ks;
-  if (nh > kMaxCellAtoms || nk > kMaxCellAtoms) return;
-  for (int t = lane; t < nh; t += 64) {
+  if (nh > occ || nk > occ) return;
+  for (int t = tid; t < nh; t += 256) {
     const int i = perm[hs + t];
     pH[t] = i;
     cH[t] = 0;
     bH[t] = row_ptr[i] + slot_off[(long)un.slot_h * pstride + hs + t];
   }
-  for (int t = lane; t < nk; t += 64) {
+  for (int t = tid; t < nk; t += 256) {
     const int i = perm[ks + t];
     pK[t] = i;
     cK[t] = 0;
     bK[t] = row_ptr[i] + slot_off[(long)un.slot_k * pstride + ks + t];
   }
   __syncthreads();
+  // positions inside a row segment depend on the atomics' order; the row
+  // sort that follows makes every row canonical
   const uint32_t* src = codes + unit_off[uidx];
   const int m = unit_cnt[uidx];
-  for (int p = lane; p < m; p += 64) {
-    const uint32_t code = src[p];
-    const int a = (int)(code & 0xffffu), b = (int)(code >> 16);
-    const int ia = pH[a], ib = pK[b];
-    if (ia < ib) col[bH[a] + atomicAdd(&cH[a], 1)] = ib;
-    else col[bK[b] + atomicAdd(&cK[b], 1)] = ia;
+  for (int p0 = tid; p0 < m; p0 += 4 * 256) {
+    uint32_t cd[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cd[k] = p0 + k * 256 < m ? src[p0 + k * 256] : 0xffffffffu;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (cd[k] == 0xffffffffu) continue;
+      const int a = (int)(cd[k] & 0xffffu), b = (int)(cd[k] >> 16);
+      const int ia = pH[a], ib = pK[b];
+      if (ia < ib) col[bH[a] + atomicAdd(&cH[a], 1)] = ib;
+      else col[bK[b] + atomicAdd(&cK[b], 1)] = ia;
+    }
   }
 }
 
@@ -775,7 +802,9 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     const int64_t need = *(int64_t*)(h + 8);
     if ((s = ensure(wb, sizeof(uint32_t) * (size_t)need))) return s;
     occ_cap = kMaxCellAtoms;
-    TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
+    // clear only the overflow flag: the occupancy (from the cell sort, not
+    // rerun) and the maxima (rerun, idempotent) stay
+    TK_HIP(hipMemsetAsync((int32_t*)info + 4, 0, sizeof(int32_t), st));
   }
   const int64_t list_pairs = h[6];
   *npairs_out = list_pairs;
@@ -788,7 +817,7 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   if ((s = ensure(P.codes, sizeof(uint32_t) * (size_t)(list_pairs > 0 ? list_pairs : 1)))) return s;
   if (n > 0) {
     ProfScope ps(ctx, st, "nblist_compact");
-    k_compact<<<nunits, 64, 0, st>>>((const int64_t*)woff, (const uint32_t*)windows,
+    k_compact<<<nunits, 256, 0, st>>>((const int64_t*)woff, (const uint32_t*)windows,
                                      (const int64_t*)P.unit_off.p, (const int32_t*)P.unit_cnt.p,
                                      (uint32_t*)P.codes.p);
   }
@@ -800,9 +829,10 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     if (n > 0 && list_pairs > 0) {
       {
         ProfScope ps(ctx, st, "nblist_csr_fill");
-        k_csr_fill<<<nunits, 64, 0, st>>>(units, cstart, (int32_t*)P.perm.p, pstride,
-                                          (int64_t*)P.unit_off.p, (int32_t*)P.unit_cnt.p,
-                                          (uint32_t*)P.codes.p, (int32_t*)P.slots.p, rp, col);
+        const int occ = h[1] > 0 ? h[1] : 1;
+        k_csr_fill<<<nunits, 256, sizeof(int) * 6 * (size_t)occ, st>>>(
+            units, cstart, (int32_t*)P.perm.p, pstride, (int64_t*)P.unit_off.p,
+            (int32_t*)P.unit_cnt.p, (uint32_t*)P.codes.p, (int32_t*)P.slots.p, rp, col, occ);
       }
       {
         ProfScope ps(ctx, st, "nblist_rowsort");

@@ -1,16 +1,18 @@
 // Cell-pair tile skeleton shared by every pair kernel.
 //
-// One wavefront per work unit (an unordered pair of neighbouring cells H, K):
+// One workgroup of W waves per work unit (an unordered pair of neighbouring
+// cells H, K):
 //   1. stage the current data of H's and K's atoms into LDS (field-major, so
 //      consecutive atoms sit in consecutive banks);
-//   2. walk the unit's listed pairs (64 per step, one per lane); each lane
-//      evaluates its pair and adds both atoms' contributions to LDS
-//      accumulators with LDS atomics (the plan orders pairs so that lanes of a
-//      step touch distinct atoms);
-//   3. write the accumulators to the partial-result slots the unit owns for
-//      H and for K (no global atomics; each (slot, atom) has one writer);
-//   4. reduce per-lane scalars (energies, virial) across the wave and write one
-//      record per unit.
+//   2. walk the unit's listed pairs (64 W per step, one per lane); each lane
+//      evaluates its pair and adds both atoms' contributions to its wave's
+//      own LDS accumulators with LDS atomics (the plan orders pairs so that
+//      lanes of a step mostly touch distinct atoms);
+//   3. sum the wave copies in wave order and write them to the partial-result
+//      slots the unit owns for H and for K (no global atomics; each (slot,
+//      atom) has one writer);
+//   4. reduce per-lane scalars (energies, virial) across each wave, then the
+//      waves in order, and write one record per unit.
 // A second kernel sums each atom's slots in a fixed order, so results are
 // bitwise reproducible run to run.
 #pragma once
@@ -41,13 +43,16 @@ __device__ __forceinline__ double image3(const double* LH, const double* LK, int
   return fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]));
 }
 
-template <class Ph>
-__global__ __launch_bounds__(64) void k_units(PlanView pv, Ph ph, double* __restrict__ partial,
-                                              long pstride, double* __restrict__ uscal) {
+template <class Ph, int W>
+__global__ __launch_bounds__(64 * W) void k_units(PlanView pv, Ph ph, double* __restrict__ partial,
+                                                  long pstride, double* __restrict__ uscal) {
+  constexpr int NS1 = Ph::NS > 0 ? Ph::NS : 1;
+  constexpr int NT = 64 * W;
   extern __shared__ double lds[];
+  __shared__ double red[W * NS1];
   if (ph.skip()) return;   // solver finished: nothing to do
   const int u = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const Unit un = pv.units[u];
   if (pv.nsys > 1) {   // batch: this unit's system geometry
     const int sy = pv.cell_sys[un.h];
@@ -56,48 +61,66 @@ __global__ __launch_bounds__(64) void k_units(PlanView pv, Ph ph, double* __rest
   const int hs = pv.cell_start[un.h], nh = pv.cell_start[un.h + 1] - hs;
   const int ks = pv.cell_start[un.k], nk = pv.cell_start[un.k + 1] - ks;
   const int cap = pv.max_occ;
-  ph.prologue(lane);
+  ph.prologue(tid, NT);
   double* LH = lds;
   double* LK = LH + Ph::NF * cap;
-  double* AH = LK + Ph::NF * cap;
-  double* AK = AH + Ph::NA * cap;
-  for (int t = lane; t < nh; t += 64) {
+  double* AH = LK + Ph::NF * cap;        // [W][NA][cap]: one copy per wave
+  double* AK = AH + W * Ph::NA * cap;
+  for (int t = tid; t < nh; t += NT) {
 #pragma unroll
     for (int f = 0; f < Ph::NG; ++f) LH[f * cap + t] = ph.sorted[f * ph.gstride + hs + t];
     ph.stage_dyn(LH, cap, t, hs + t);
-#pragma unroll
-    for (int f = 0; f < Ph::NA; ++f) AH[f * cap + t] = 0.0;
   }
-  for (int t = lane; t < nk; t += 64) {
+  for (int t = tid; t < nk; t += NT) {
 #pragma unroll
     for (int f = 0; f < Ph::NG; ++f) LK[f * cap + t] = ph.sorted[f * ph.gstride + ks + t];
     ph.stage_dyn(LK, cap, t, ks + t);
-#pragma unroll
-    for (int f = 0; f < Ph::NA; ++f) AK[f * cap + t] = 0.0;
+  }
+  for (int t = tid; t < W * Ph::NA * cap; t += NT) {
+    AH[t] = 0.0;
+    AK[t] = 0.0;
   }
   __syncthreads();
-  double sc[Ph::NS > 0 ? Ph::NS : 1];
+  double sc[NS1];
 #pragma unroll
-  for (int k = 0; k < (Ph::NS > 0 ? Ph::NS : 1); ++k) sc[k] = 0.0;
+  for (int k = 0; k < NS1; ++k) sc[k] = 0.0;
+  double* MH = AH + w * Ph::NA * cap;
+  double* MK = AK + w * Ph::NA * cap;
   const long p0 = pv.unit_off[u], p1 = p0 + pv.unit_cnt[u];
-  for (long p = p0 + lane; p < p1; p += 64) {
+  for (long p = p0 + tid; p < p1; p += NT) {
     const uint32_t code = pv.codes[p];
-    ph.pair(LH, LK, cap, (int)(code & 0xffffu), (int)(code >> 16), AH, AK, sc, p);
+    ph.pair(LH, LK, cap, (int)(code & 0xffffu), (int)(code >> 16), MH, MK, sc, p);
   }
   __syncthreads();
-  for (int t = lane; t < nh; t += 64)
+  // the wave copies summed in wave order
+  for (int t = tid; t < nh; t += NT)
 #pragma unroll
-    for (int f = 0; f < Ph::NA; ++f)
-      partial[((long)un.slot_h * Ph::NA + f) * pstride + hs + t] = AH[f * cap + t];
-  for (int t = lane; t < nk; t += 64)
+    for (int f = 0; f < Ph::NA; ++f) {
+      double v = 0.0;
 #pragma unroll
-    for (int f = 0; f < Ph::NA; ++f)
-      partial[((long)un.slot_k * Ph::NA + f) * pstride + ks + t] = AK[f * cap + t];
+      for (int ww = 0; ww < W; ++ww) v += AH[(ww * Ph::NA + f) * cap + t];
+      partial[((long)un.slot_h * Ph::NA + f) * pstride + hs + t] = v;
+    }
+  for (int t = tid; t < nk; t += NT)
+#pragma unroll
+    for (int f = 0; f < Ph::NA; ++f) {
+      double v = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < W; ++ww) v += AK[(ww * Ph::NA + f) * cap + t];
+      partial[((long)un.slot_k * Ph::NA + f) * pstride + ks + t] = v;
+    }
   if (Ph::NS > 0) {
 #pragma unroll
-    for (int k = 0; k < Ph::NS; ++k) {
-      double v = wave_sum_d(sc[k]);
-      if (lane == 0) uscal[(long)u * Ph::NS + k] = v;
+    for (int k = 0; k < NS1; ++k) {
+      const double v = wave_sum_d(sc[k]);
+      if (lane == 0) red[w * NS1 + k] = v;
+    }
+    __syncthreads();
+    if (tid < NS1) {
+      double v = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < W; ++ww) v += red[ww * NS1 + tid];
+      uscal[(long)u * NS1 + tid] = v;
     }
   }
 }
@@ -154,9 +177,27 @@ __global__ __launch_bounds__(256) void k_sum_units(const double* __restrict__ us
   if (threadIdx.x == 0) out[(long)sy * NS + k] = sh[0];
 }
 
+// LDS of k_units<Ph, W>: both cells' fields and W accumulator copies each.
 template <class Ph>
-inline size_t unit_lds_bytes(const Plan& p) {
-  return sizeof(double) * (size_t)(2 * (Ph::NF + Ph::NA)) * (size_t)(p.max_occ > 0 ? p.max_occ : 1);
+inline size_t unit_lds_bytes(const Plan& p, int W) {
+  return sizeof(double) * (size_t)(2 * (Ph::NF + W * Ph::NA)) *
+         (size_t)(p.max_occ > 0 ? p.max_occ : 1);
+}
+
+// Ph::kWaves waves per unit when their LDS fits (two workgroups per CU at
+// least), else one.  Several waves per unit pay where the pair loop is long
+// next to the staging (many pairs per unit, few fields per atom); a term with
+// heavy staging and a short loop keeps more units in flight with one wave.
+template <class Ph>
+inline void launch_units(const Plan& P, const Ph& ph, double* partial, long pstride,
+                         double* uscal, hipStream_t st) {
+  constexpr int W = Ph::kWaves;
+  const size_t lw = unit_lds_bytes<Ph>(P, W);
+  if (W > 1 && 2 * (lw + 4096) <= kMaxLds)
+    k_units<Ph, W><<<P.nunits, 64 * W, lw, st>>>(P.view(), ph, partial, pstride, uscal);
+  else
+    k_units<Ph, 1><<<P.nunits, 64, unit_lds_bytes<Ph>(P, 1), st>>>(P.view(), ph, partial, pstride,
+                                                                   uscal);
 }
 
 inline long pad64(long n) { return (n + 63) / 64 * 64; }

@@ -718,8 +718,7 @@ struct Solver {
   void matvec64_tiles(const double* v) {
     TmatPh<double> ph = tmat64(v);
     ProfScope ps(ctx, st, "units_tmat_fp64");
-    k_units<TmatPh<double>><<<P->nunits, 64, unit_lds_bytes<TmatPh<double>>(*P), st>>>(
-        pv, ph, partial, pstride, nullptr);
+    launch_units(*P, ph, partial, pstride, nullptr, st);
   }
 
   // FP64 residual of x against rhs (rms_true, and epol from x.rhs), queued
@@ -876,7 +875,7 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   S.pz[0] = (double*)pz0; S.pz[1] = (double*)pz1; S.pg = (double*)pg;
   S.state = (PcgState*)state;
   S.active = (int32_t*)act;
-  if (unit_lds_bytes<EfieldPh<double>>(*P) > kMaxLds) return TK_E_CAPACITY;
+  if (unit_lds_bytes<EfieldPh<double>>(*P, 1) > kMaxLds) return TK_E_CAPACITY;
   if ((s = mv_attributes(S.mv_lds))) return s;
   // pinned: [1024, ...) host state mirrors, then the refinement mask
   void *hbase, *hdev;

@@ -119,9 +119,10 @@ template <class R>
 struct EmpolePh {
   static constexpr int NF = 14, NA = 3, NS = 11;
   static constexpr const char* kName = "empole";
+  static constexpr int kWaves = 1;   // waves per unit (pairs.hpp launch_units)
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
-  __device__ void prologue(int lane) const { erfcx_stage<R>(lane, 64); }
+  __device__ void prologue(int tid, int nt) const { erfcx_stage<R>(tid, nt); }
   const double* xyz;
   const double* mpole;
   const int32_t* molid;
@@ -224,9 +225,10 @@ template <class R>
 struct ChargePh {
   static constexpr int NF = 5, NA = 3, NS = 11;
   static constexpr const char* kName = "charge";
+  static constexpr int kWaves = 4;   // waves per unit (pairs.hpp launch_units)
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
-  __device__ void prologue(int lane) const { erfcx_stage<R>(lane, 64); }
+  __device__ void prologue(int tid, int nt) const { erfcx_stage<R>(tid, nt); }
   const double* xyz;
   const double* q;
   const int32_t* molid;
@@ -289,9 +291,10 @@ template <class R>
 struct EfieldPh {
   static constexpr int NF = 16, NA = 3, NS = 0;
   static constexpr const char* kName = "efield";
+  static constexpr int kWaves = 4;   // waves per unit (pairs.hpp launch_units)
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
-  __device__ void prologue(int lane) const { erfcx_stage<R>(lane, 64); }
+  __device__ void prologue(int tid, int nt) const { erfcx_stage<R>(tid, nt); }
   const double* xyz;
   const double* mpole;
   const int32_t* molid;
@@ -421,11 +424,12 @@ template <class R>
 struct TmatPh {
   static constexpr int NF = 9, NA = 3, NS = 0;
   static constexpr const char* kName = "tmat";
+  static constexpr int kWaves = 4;   // waves per unit (pairs.hpp launch_units)
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   const int* done = nullptr;   // solver flag (status; 0 while iterating)
   int run_when_done = 0;       // 0: skip once the solver has finished; 1: skip until it has
   __device__ bool skip() const { return done && ((*done != 0) != (run_when_done != 0)); }
-  __device__ void prologue(int lane) const { erfcx_stage<R>(lane, 64); }
+  __device__ void prologue(int tid, int nt) const { erfcx_stage<R>(tid, nt); }
   const double* xyz;
   const double* mu;
   int mu_sorted;   // mu indexed by sorted position (solver-internal vectors)
@@ -521,11 +525,12 @@ template <class R>
 struct TmatCachedPh {
   static constexpr int NF = 6, NA = 3, NS = 0, NG = 3;
   static constexpr const char* kName = "tmatc";
+  static constexpr int kWaves = 4;   // waves per unit (pairs.hpp launch_units)
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   const int* done = nullptr;   // solver flag (status; 0 while iterating)
   int run_when_done = 0;       // 0: skip once the solver has finished; 1: skip until it has
   __device__ bool skip() const { return done && ((*done != 0) != (run_when_done != 0)); }
-  __device__ void prologue(int) const {}
+  __device__ void prologue(int, int) const {}
   const R* gc = nullptr;
   long gcs = 0;
   double box, inv_box;
@@ -574,9 +579,10 @@ template <class R>
 struct VdwPh {
   static constexpr int NF = 6, NA = 3, NS = 10;
   static constexpr const char* kName = "vdw";
+  static constexpr int kWaves = 4;   // waves per unit (pairs.hpp launch_units)
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
-  __device__ void prologue(int) const {}
+  __device__ void prologue(int, int) const {}
   const double* xyz;
   const double* rad;
   const double* eps;
@@ -748,8 +754,7 @@ tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, con
                    &uscal)))
     return s;
   PlanView pv = P.view();
-  const size_t lds = unit_lds_bytes<Ph>(P);
-  if (lds > kMaxLds) return TK_E_CAPACITY;
+  if (unit_lds_bytes<Ph>(P, 1) > kMaxLds) return TK_E_CAPACITY;
   void* gathered;
   if ((s = scratch(ctx, "gathered", sizeof(double) * Ph::NG * pstride, &gathered))) return s;
   Ph phg = ph;
@@ -758,7 +763,7 @@ tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, con
   k_gather<Ph><<<ceil_div(P.n, 256), 256, 0, st>>>(pv, phg, (double*)gathered, pstride);
   {
     ProfScope ps(ctx, st, std::string("units_") + Ph::kName + Ph::kTag);
-    k_units<Ph><<<P.nunits, 64, lds, st>>>(pv, phg, (double*)partial, pstride, (double*)uscal);
+    launch_units(P, phg, (double*)partial, pstride, (double*)uscal, st);
   }
   {
     ProfScope ps(ctx, st, "reduce_atoms");

@@ -207,7 +207,7 @@ class Context:
         if cap is None:
             rho = n / sysref.box ** 3
             cap = int(n * (2.0 * 3.141592653589793 / 3.0) * cutoff ** 3 * rho * 1.3 + 4096)
-        row_ptr = torch.zeros(n + 1, dtype=torch.int32, device=self.device) if want_csr else None
+        row_ptr = torch.empty(n + 1, dtype=torch.int32, device=self.device) if want_csr else None
         col = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device) if want_csr else None
         npairs = C.c_int64(0)
         st = load().tk_nblist_build(self._h, _stream(self.device), C.byref(sysref.c), cutoff,
@@ -222,9 +222,9 @@ class Context:
     # -- pair terms ------------------------------------------------------------
     def empole_real(self, sysref, lst, mpole, beta, cutoff, prec=FP64):
         mp = _dev(mpole, torch.float64, self.device)
-        e = torch.zeros(3, dtype=torch.float64, device=self.device)
+        e = torch.empty(3, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
-        w = torch.zeros((3, 3), dtype=torch.float64, device=self.device)
+        w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
         _check(load().tk_empole_real(self._h, _stream(self.device), C.byref(sysref.c),
                                      C.byref(lst.c), _ptr(mp), beta, cutoff, prec, _ptr(e), _ptr(f),
                                      _ptr(w)), "tk_empole_real")
@@ -232,9 +232,9 @@ class Context:
 
     def echarge_real(self, sysref, lst, q, beta, cutoff, prec=FP64):
         qq = _dev(q, torch.float64, self.device)
-        e = torch.zeros(3, dtype=torch.float64, device=self.device)
+        e = torch.empty(3, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
-        w = torch.zeros((3, 3), dtype=torch.float64, device=self.device)
+        w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
         _check(load().tk_echarge_real(self._h, _stream(self.device), C.byref(sysref.c),
                                       C.byref(lst.c), _ptr(qq), beta, cutoff, prec, _ptr(e),
                                       _ptr(f), _ptr(w)), "tk_echarge_real")
@@ -280,9 +280,9 @@ class Context:
              prec=FP64):
         r = _dev(rad, torch.float64, self.device)
         ep = _dev(eps, torch.float64, self.device)
-        e = torch.zeros(1, dtype=torch.float64, device=self.device)
+        e = torch.empty(1, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
-        w = torch.zeros((3, 3), dtype=torch.float64, device=self.device)
+        w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
         _check(load().tk_evdw(self._h, _stream(self.device), C.byref(sysref.c), C.byref(lst.c),
                               int(form), _ptr(r), _ptr(ep), cutoff, taper_frac, dhal, ghal, prec,
                               _ptr(e), _ptr(f), _ptr(w)), "tk_evdw")

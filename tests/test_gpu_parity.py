@@ -105,6 +105,14 @@ def test_nblist_clustered(ctx, seed):
     lst = ctx.nblist(sysr, 7.001, plan_slot=1)
     rp, cp = O.nblist(xyz, box, 7.001)
     assert_list_equal(lst, rp, cp)
+    # the plan left by the rerun drives the pair kernels correctly
+    mp = np.zeros((len(xyz), 10))
+    mp[:, 0] = rng.normal(0.0, 0.3, len(xyz))
+    mp[:, 1:4] = rng.normal(0.0, 0.05, (len(xyz), 3))
+    e, f, _ = ctx.empole_real(sysr, lst, mp, S["beta"], 7.0)
+    eo, fo, _ = O.empole_real(xyz, box, np.arange(len(xyz)) // 3, rp, cp, mp, S["beta"], 7.0)
+    assert rel(np_(e)[0], eo[0]) < 1e-10
+    assert fmax_rel(np_(f), fo) < 1e-8
 
 
 def test_nblist_errors(ctx, tk):
