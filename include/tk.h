@@ -24,8 +24,9 @@
  *    parameter says "host"); nothing is retained after the call returns.
  *    `stream` is a hipStream_t (NULL = default stream).  Calls are ordered on
  *    that stream.  Entry points that return results through host memory
- *    (tk_nblist_build, tk_polarize_pcg) synchronise the stream before
- *    returning; the others are asynchronous.
+ *    (tk_nblist_build, tk_polarize_pcg, tk_batch_step) synchronise the
+ *    stream to produce them; device outputs are always written in stream
+ *    order.
  *  - Errors: every call returns a tk_status; argument errors are detected on
  *    the host before any work is queued; no exception crosses the ABI.
  *  - Precision: prec = TK_FP64 (all pair arithmetic in FP64) or TK_MIXED (pair
@@ -189,8 +190,9 @@ tk_status tk_tmatvec(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_n
  * each mat-vec: 4.80320 * sqrt(sum |alpha_i r_i|^2 / n_pol) <= tol_debye.
  * After the loop a fresh FP64 residual is formed (info->rms_true_debye);
  * with TK_MIXED, up to 3 FP64-residual refinement rounds are added while it
- * exceeds the tolerance.  mu_out: device [n][3].  info: HOST memory.
- * Returns info->status.  Synchronises `stream`.
+ * exceeds the tolerance.  mu_out: device [n][3], written in stream order
+ * (later work on `stream` sees it).  info: HOST memory, complete on return.
+ * Returns info->status.  Synchronises `stream` while solving.
  */
 tk_status tk_polarize_pcg(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
                           const double* mpole, const double* polarity, const double* thole,

@@ -214,118 +214,257 @@ __global__ void k_cand(int nunits, const Unit* __restrict__ units, const int32_t
   cand[u] = (int64_t)(cstart[un.h + 1] - cstart[un.h]) * (int64_t)(cstart[un.k + 1] - cstart[un.k]);
 }
 
-// One wave per cell-pair unit (H, K), both cells staged in LDS.  Candidates
-// (a in H, b in K) are visited in "diagonal" order b = (a + k) mod |K|, so
-// consecutive listed pairs touch distinct atoms on both sides (conflict-free
-// LDS accumulation in the pair kernels).  Writes the unit's pair codes
-// a | b << 16 into its window, the unit's pair count, and per (unit role,
-// atom) the number of pairs whose CSR row is that atom's (the smaller caller
-// index owns the pair).
-__global__ __launch_bounds__(64) void k_plan(int nunits, const Unit* __restrict__ units,
-                                             const int32_t* __restrict__ cstart,
-                                             const uint4* __restrict__ us,
-                                             const SysDev* __restrict__ sys,
-                                             const int32_t* __restrict__ cell_sys,
-                                             long pstride, const int64_t* __restrict__ unit_off,
-                                             long code_cap, uint32_t* __restrict__ codes,
-                                             int32_t* __restrict__ unit_cnt,
-                                             int64_t* __restrict__ cnt64,
-                                             int32_t* __restrict__ slot_cnt,
-                                             int32_t* __restrict__ info, int occ_cap) {
-  // dynamic LDS: sK[occ_cap] (uint4) then cK[occ_cap]; occ_cap is the host's
-  // bound on the cell occupancy (a larger cell makes the host rerun with the
-  // full bound)
+// Fixed-point span [lo, hi] of cell index ci along one axis: the u with
+// (u * nc) >> 32 == ci, i.e. lo = ceil(ci 2^32 / nc), hi = ceil((ci + 1)
+// 2^32 / nc) - 1.  In FP64 the quotient (below 2^33) is within 2^-21 of the
+// exact one while a non-integer quotient is at least 1/nc from an integer,
+// so the ceilings are exact.
+__device__ __forceinline__ void cell_span(int ci, int nc, uint32_t& lo, uint32_t& hi) {
+  lo = (uint32_t)ceil((double)ci * 4294967296.0 / (double)nc);
+  hi = (uint32_t)((uint64_t)ceil((double)(ci + 1) * 4294967296.0 / (double)nc) - 1u);
+}
+
+// Square of the periodic fixed-point distance from u to the span [lo, hi]:
+// 0 inside; else the shorter of the wrapping steps forward to lo and back
+// to hi (at most 2^31, so three squares fit in 64 bits).
+__device__ __forceinline__ uint64_t span_d2(uint32_t u, uint32_t lo, uint32_t hi) {
+  if (u >= lo && u <= hi) return 0;
+  const uint32_t d1 = lo - u, d2 = u - hi;
+  const uint64_t d = d1 < d2 ? d1 : d2;
+  return d * d;
+}
+
+// Reach filter: an atom whose squared distance to a cell's box exceeds rq^2
+// has no partner in that cell.  Every b in the cell lies in the box, and the
+// per-axis distance to the box is at most |int32(u_b - u_a)|, so the box
+// distance never exceeds the exact pair distance: the filter drops no pair.
+struct CellBox {
+  uint32_t lo[3], hi[3];
+  __device__ __forceinline__ CellBox(int local, int nc) {
+    const int ci[3] = {local / (nc * nc), (local / nc) % nc, local % nc};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) cell_span(ci[a], nc, lo[a], hi[a]);
+  }
+  __device__ __forceinline__ bool reach(const uint4& v, uint64_t rq2) const {
+    return span_d2(v.x, lo[0], hi[0]) + span_d2(v.y, lo[1], hi[1]) + span_d2(v.z, lo[2], hi[2]) <=
+           rq2;
+  }
+};
+
+constexpr int kPlanMaxWaves = 4;   // waves per unit: 1, 2 or 4 (host's choice by cell size)
+constexpr int kPlanRegions = (kMaxCellAtoms / 64) * kPlanMaxWaves;   // (H chunk, wave) regions
+
+// One workgroup of W = blockDim.x / 64 waves per cell-pair unit (H, K).
+//  1. Reach filter: the atoms of H that can reach K's box and those of K
+//     that can reach H's box are staged in LDS, in cell order (a self unit
+//     keeps all).  Corner and edge neighbours lose most of their atoms.
+//  2. Candidates (a, b) of the survivors are visited in "diagonal" order
+//     b = (m + k) mod |K'| for the survivor m of H on each lane (chunks of
+//     64), so consecutive listed pairs touch distinct atoms on both sides
+//     (conflict-free LDS accumulation in the pair kernels).  Wave w takes
+//     its part of the k range; each (chunk, wave) region of the unit's window
+//     receives its passing codes a | b << 16 (cell-local indices) in visit
+//     order and its count goes to rcnt; the compaction concatenates regions
+//     in (chunk, wave) order.
+//  3. Per (unit role, atom): the number of pairs whose CSR row is that
+//     atom's (the smaller caller index owns the pair).
+__global__ __launch_bounds__(64 * kPlanMaxWaves) void k_plan(
+    int nunits, const Unit* __restrict__ units, const int32_t* __restrict__ cstart,
+    const uint4* __restrict__ us, const SysDev* __restrict__ sys,
+    const int32_t* __restrict__ cell_sys, long pstride, const int64_t* __restrict__ unit_off,
+    long code_cap, uint32_t* __restrict__ codes, int32_t* __restrict__ unit_cnt,
+    int64_t* __restrict__ cnt64, int32_t* __restrict__ rcnt, int2* __restrict__ nfilt,
+    int32_t* __restrict__ slot_cnt, int32_t* __restrict__ info, int occ_cap) {
+  // dynamic LDS: sH sK (uint4), then iH iK cH cK (int), occ_cap entries each;
+  // occ_cap is the host's bound on the cell occupancy (a larger cell makes
+  // the host rerun with kMaxCellAtoms)
   extern __shared__ uint4 plan_lds[];
-  uint4* sK = plan_lds;
-  int* cK = (int*)(plan_lds + occ_cap);
-  const int uidx = blockIdx.x;
-  const int lane = lane_id();
+  uint4* sH = plan_lds;
+  uint4* sK = sH + occ_cap;
+  int* iH = (int*)(sK + occ_cap);
+  int* iK = iH + occ_cap;
+  int* cH = iK + occ_cap;
+  int* cK = cH + occ_cap;
+  __shared__ int wc[2][2][kPlanMaxWaves];
+  __shared__ int rc[kPlanRegions];
+  const int uidx = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int NT = blockDim.x, W = NT >> 6;
   if (unit_off[nunits] > code_cap) {   // windows do not fit: host grows the buffer, reruns
-    if (uidx == 0 && lane == 0) info[4] = 1;
+    if (uidx == 0 && tid == 0) info[4] = 1;
     return;
   }
   const Unit un = units[uidx];
   const int hs = cstart[un.h], nh = cstart[un.h + 1] - hs;
   const int ks = cstart[un.k], nk = cstart[un.k + 1] - ks;
   if (nh > kMaxCellAtoms || nk > kMaxCellAtoms) return;
-  if (nk > occ_cap) {   // staging bound too small: host reruns with kMaxCellAtoms
-    if (lane == 0) info[4] = 1;
+  if (nh > occ_cap || nk > occ_cap) {   // staging bound too small: host reruns with kMaxCellAtoms
+    if (tid == 0) info[4] = 1;
     return;
   }
-  const PairTest test(sys[cell_sys ? cell_sys[un.h] : 0]);
+  const SysDev sd = sys[cell_sys ? cell_sys[un.h] : 0];
+  const PairTest test(sd);
   const bool self = un.h == un.k;
-  for (int t = lane; t < nk; t += 64) {
-    sK[t] = us[ks + t];
-    cK[t] = 0;
+  const uint4 z4 = make_uint4(0, 0, 0, 0);
+  const CellBox bh(un.h - sd.cell0, sd.nc), bk(un.k - sd.cell0, sd.nc);
+  for (int t = tid; t < nh; t += NT) cH[t] = 0;
+  for (int t = tid; t < nk; t += NT) cK[t] = 0;
+  // 1. stable compaction of the survivors of both cells, one pass per NT
+  //    atoms (wave counts double-buffered: one barrier per pass)
+  int nhf = 0, nkf = 0;
+  const int nmax = nh > nk ? nh : nk;
+  for (int r0 = 0, par = 0; r0 < nmax; r0 += NT, par ^= 1) {
+    const int t = r0 + tid;
+    uint4 vh = z4, vk = z4;
+    bool kh = false, kk = false;
+    if (t < nh) {
+      vh = us[hs + t];
+      kh = self || bk.reach(vh, sd.rq2);
+    }
+    if (t < nk) {
+      vk = us[ks + t];
+      kk = self || bh.reach(vk, sd.rq2);
+    }
+    const uint64_t mh = __ballot(kh), mk = __ballot(kk);
+    if (lane == 0) {
+      wc[par][0][w] = __popcll(mh);
+      wc[par][1][w] = __popcll(mk);
+    }
+    __syncthreads();
+    int ph = nhf, pk = nkf;
+    for (int ww = 0; ww < W; ++ww) {
+      const int ch = wc[par][0][ww], ck = wc[par][1][ww];
+      ph += ww < w ? ch : 0;
+      pk += ww < w ? ck : 0;
+      nhf += ch;
+      nkf += ck;
+    }
+    if (kh) {
+      const int p = ph + lanes_below(mh);
+      sH[p] = vh;
+      iH[p] = t;
+    }
+    if (kk) {
+      const int p = pk + lanes_below(mk);
+      sK[p] = vk;
+      iK[p] = t;
+    }
   }
   __syncthreads();
-  uint32_t* out = codes + unit_off[uidx];
-  int cnt = 0;
-  // visit order: (k, a) with a fastest; each lane keeps its own H atom in
-  // registers for a whole chunk of 64 a's, and kPlanUnroll steps of k are
-  // tested together (independent LDS reads and tests in flight) before their
-  // codes are written in order.
+  // 2. enumeration
+  const int nch = (nhf + 63) >> 6;
+  const int kp = (nkf + W - 1) / W;
+  const int kk0 = min(w * kp, nkf), kk1 = min(kk0 + kp, nkf);
+  uint32_t* win = codes + unit_off[uidx];
   constexpr int kPlanUnroll = 4;
-  for (int a0 = 0; a0 < nh; a0 += 64) {
-    const int a = a0 + lane;
-    const bool av = a < nh;
-    const uint4 ua = av ? us[hs + a] : make_uint4(0, 0, 0, 0);
-    int b = a;   // b = (a + kk) mod nk, advanced incrementally
-    while (b >= nk && nk > 0) b -= nk;
-    int own = 0;   // pairs whose CSR row is a's (a has the smaller caller index)
-    for (int kk0 = 0; kk0 < nk; kk0 += kPlanUnroll) {
+  for (int ch = 0; ch < nch; ++ch) {
+    const int m = ch * 64 + lane;
+    const int la = min(64, nhf - ch * 64);
+    const bool av = m < nhf;
+    const uint4 ua = av ? sH[m] : z4;
+    const int a = av ? iH[m] : 0;
+    uint32_t* out = win + (long)64 * ch * nkf + (long)la * kk0;   // region (ch, w)
+    int bp = nkf > 0 ? (m + kk0) % nkf : 0;   // b position, advanced incrementally
+    int cnt = 0, own = 0;
+    for (int kq = kk0; kq < kk1; kq += kPlanUnroll) {
       int bj[kPlanUnroll];
       uint4 kj[kPlanUnroll];
       bool pj[kPlanUnroll];
 #pragma unroll
       for (int j = 0; j < kPlanUnroll; ++j) {
-        bj[j] = b;
-        if (++b == nk) b = 0;
+        bj[j] = bp;
+        if (++bp == nkf) bp = 0;
       }
 #pragma unroll
       for (int j = 0; j < kPlanUnroll; ++j) kj[j] = sK[bj[j]];
 #pragma unroll
       for (int j = 0; j < kPlanUnroll; ++j) {   // branch-free except the rare band test
-        const bool ok = av & (kk0 + j < nk) & (!self | (a < bj[j]));
+        // a self unit keeps every atom, so positions are cell indices there
+        const bool ok = av & (kq + j < kk1) & (!self | (m < bj[j]));
         pj[j] = ok & test(ua, kj[j]);
       }
 #pragma unroll
       for (int j = 0; j < kPlanUnroll; ++j) {
         const uint64_t mask = __ballot(pj[j]);
         if (pj[j]) {
-          out[cnt + lanes_below(mask)] = (uint32_t)a | ((uint32_t)bj[j] << 16);
+          const int b = iK[bj[j]];
+          out[cnt + lanes_below(mask)] = (uint32_t)a | ((uint32_t)b << 16);
           if (ua.w < kj[j].w) ++own;
-          else atomicAdd(&cK[bj[j]], 1);
+          else atomicAdd(&cK[b], 1);
         }
         cnt += __popcll(mask);
       }
     }
-    if (av) slot_cnt[(long)un.slot_h * pstride + hs + a] = own;
+    if (av && own) atomicAdd(&cH[a], own);
+    if (lane == 0) rc[ch * W + w] = cnt;
   }
   __syncthreads();
-  if (lane == 0) {
-    unit_cnt[uidx] = cnt;
-    cnt64[uidx] = cnt;
+  // 3. counts
+  const int nr = nch * W;
+  if (tid < nr) rcnt[(long)uidx * kPlanRegions + tid] = rc[tid];
+  if (tid == 0) {
+    int tot = 0;
+    for (int r = 0; r < nr; ++r) tot += rc[r];
+    unit_cnt[uidx] = tot;
+    cnt64[uidx] = tot;
+    nfilt[uidx] = make_int2(nhf, nkf);
   }
-  for (int t = lane; t < nk; t += 64) slot_cnt[(long)un.slot_k * pstride + ks + t] = cK[t];
+  for (int t = tid; t < nh; t += NT) slot_cnt[(long)un.slot_h * pstride + hs + t] = cH[t];
+  for (int t = tid; t < nk; t += NT) slot_cnt[(long)un.slot_k * pstride + ks + t] = cK[t];
 }
 
-// One wave per unit: move the unit's pair codes from its candidate window
-// to its place in the dense code array (windows are sized by candidates,
-// the dense array by listed pairs).
+// Per unit: move the unit's pair codes from the regions of its candidate
+// window to its place in the dense code array (windows are sized by
+// candidates, the dense array by listed pairs), regions in (chunk, wave)
+// order.
 __global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ woff,
                                                  const uint32_t* __restrict__ windows,
                                                  const int64_t* __restrict__ doff,
-                                                 const int32_t* __restrict__ unit_cnt,
+                                                 const int32_t* __restrict__ rcnt,
+                                                 const int2* __restrict__ nfilt, int W,
                                                  uint32_t* __restrict__ codes) {
-  const int u = blockIdx.x;
+  __shared__ int rs[kPlanRegions], rd[kPlanRegions + 1];
+  const int u = blockIdx.x, tid = threadIdx.x;
+  const int2 nf = nfilt[u];
+  const int nhf = nf.x, nkf = nf.y;
+  const int nr = ((nhf + 63) >> 6) * W;
+  const int kp = (nkf + W - 1) / W;
+  if (tid < 64) {   // wave 0: region starts (window) and dense prefix
+    int c = 0;
+    if (tid < nr) {
+      const int ch = tid / W, w = tid % W;
+      const int la = min(64, nhf - ch * 64);
+      rs[tid] = 64 * ch * nkf + la * min(w * kp, nkf);
+      c = rcnt[(long)u * kPlanRegions + tid];
+    }
+    int incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (tid >= o) incl += t;
+    }
+    if (tid < nr) rd[tid] = incl - c;
+    if (tid == nr - 1) rd[nr] = incl;
+    if (nr == 0 && tid == 0) rd[0] = 0;
+  }
+  __syncthreads();
   const uint32_t* src = windows + woff[u];
   uint32_t* dst = codes + doff[u];
-  const int m = unit_cnt[u];
-  for (int t0 = threadIdx.x; t0 < m; t0 += 4 * 256) {   // four loads in flight per thread
+  const int m = rd[nr];
+  for (int t0 = tid; t0 < m; t0 += 4 * 256) {   // four loads in flight per thread
     uint32_t v[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = t0 + k * 256 < m ? src[t0 + k * 256] : 0u;
+    for (int k = 0; k < 4; ++k) {
+      const int t = t0 + k * 256;
+      v[k] = 0u;
+      if (t < m) {
+        int lo = 0, hi = nr - 1;   // last region starting at or before t
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (rd[mid] <= t) lo = mid;
+          else hi = mid - 1;
+        }
+        v[k] = src[rs[lo] + (t - rd[lo])];
+      }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if (t0 + k * 256 < m) dst[t0 + k * 256] = v[k];
@@ -648,7 +787,7 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   DevBuf& wb = ctx->scratch["nb_windows"];
   if (wb.bytes < sizeof(uint32_t) * (size_t)est && (s = ensure(wb, sizeof(uint32_t) * (size_t)est)))
     return s;
-  void *u, *cell, *ccount, *cursor, *tmp, *info, *cand, *rcnt, *rptr, *woff, *cnt64;
+  void *u, *cell, *ccount, *cursor, *tmp, *info, *cand, *rcnt, *rptr, *woff, *cnt64, *regcnt, *nfilt;
   if ((s = scratch(ctx, "nb_u", sizeof(uint32_t) * 3 * nn, &u)) ||
       (s = scratch(ctx, "nb_cell", sizeof(int32_t) * nn, &cell)) ||
       (s = scratch(ctx, "nb_ccount", sizeof(int32_t) * (ncells + 1), &ccount)) ||
@@ -659,7 +798,9 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
       (s = scratch(ctx, "nb_woff", sizeof(int64_t) * (nunits + 1), &woff)) ||
       (s = scratch(ctx, "nb_cnt64", sizeof(int64_t) * (nunits + 1), &cnt64)) ||
       (s = scratch(ctx, "nb_rcnt", sizeof(int32_t) * (nn + 1), &rcnt)) ||
-      (s = scratch(ctx, "nb_rptr", sizeof(int32_t) * (nn + 1), &rptr)))
+      (s = scratch(ctx, "nb_rptr", sizeof(int32_t) * (nn + 1), &rptr)) ||
+      (s = scratch(ctx, "nb_regcnt", sizeof(int32_t) * kPlanRegions * (size_t)nunits, &regcnt)) ||
+      (s = scratch(ctx, "nb_nfilt", sizeof(int2) * (size_t)nunits, &nfilt)))
     return s;
   // pinned staging: [0, 4096) readback; then the system table
   const size_t sys_bytes = sizeof(SysDev) * (nsys + 1);
@@ -763,6 +904,8 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     max_mean = std::fmax(max_mean, (double)(spec.atom0[k + 1] - spec.atom0[k]) / cells);
   }
   int occ_cap = (int)std::ceil(3.0 * max_mean);
+  // waves per unit of the enumeration: more for larger cells
+  const int plan_waves = max_mean > 96.0 ? 4 : max_mean > 48.0 ? 2 : 1;
   occ_cap = occ_cap < 64 ? 64 : occ_cap > kMaxCellAtoms ? kMaxCellAtoms : occ_cap;
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (n > 0) {
@@ -770,12 +913,11 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
       {
         ProfScope ps(ctx, st, "nblist_plan");
         windows = wb.p;
-        const size_t plds = (sizeof(uint4) + sizeof(int)) * (size_t)occ_cap;
-        k_plan<<<nunits, 64, plds, st>>>(nunits, units, cstart, (uint4*)P.us.p, sysd, cell_sys,
-                                         pstride, (int64_t*)woff, (long)(wb.bytes / 4),
-                                         (uint32_t*)windows, (int32_t*)P.unit_cnt.p,
-                                         (int64_t*)cnt64, (int32_t*)P.slots.p, (int32_t*)info,
-                                         occ_cap);
+        const size_t plds = (2 * sizeof(uint4) + 4 * sizeof(int)) * (size_t)occ_cap;
+        k_plan<<<nunits, 64 * plan_waves, plds, st>>>(
+            nunits, units, cstart, (uint4*)P.us.p, sysd, cell_sys, pstride, (int64_t*)woff,
+            (long)(wb.bytes / 4), (uint32_t*)windows, (int32_t*)P.unit_cnt.p, (int64_t*)cnt64,
+            (int32_t*)regcnt, (int2*)nfilt, (int32_t*)P.slots.p, (int32_t*)info, occ_cap);
       }
       k_row_slots<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)P.perm.p, (int32_t*)P.scell.p,
                                                      nslot, pstride, (int32_t*)P.slots.p,
@@ -818,8 +960,8 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   if (n > 0) {
     ProfScope ps(ctx, st, "nblist_compact");
     k_compact<<<nunits, 256, 0, st>>>((const int64_t*)woff, (const uint32_t*)windows,
-                                     (const int64_t*)P.unit_off.p, (const int32_t*)P.unit_cnt.p,
-                                     (uint32_t*)P.codes.p);
+                                     (const int64_t*)P.unit_off.p, (const int32_t*)regcnt,
+                                     (const int2*)nfilt, plan_waves, (uint32_t*)P.codes.p);
   }
   if (want_csr) {
     if (list_pairs > cap) return TK_E_CAPACITY;

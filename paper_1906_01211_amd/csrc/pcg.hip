@@ -72,19 +72,43 @@ __device__ __forceinline__ CellSys cell_sys_of(const PlanView& pv, int c) {
   return CellSys{sy, pv.sys[sy].cell0, pv.sys[sy + 1].cell0};
 }
 
+// Per-cell tables of the iteration kernels, indexed by XCD position (the
+// workgroup's slot in xcd_pos order), so that a workgroup starts with one
+// round of independent loads instead of a chain of dependent ones.
+constexpr int kEntRow = 32;   // entries per cell row: up to 27 units plus the terminator
+static_assert(kCellUnitStride <= kEntRow, "cell entry rows hold every unit and the terminator");
+struct MvHdr {                // 48 bytes
+  int32_t c, ne, self_j, hs, nown, sy, c0, c1;   // cell, units, self entry, atoms, system range
+  double box, inv_box;
+};
+// A cell's part in one unit: role (0 H side, 1 K side, 2 self), first sorted
+// atom of the other cell, that cell's offset in the staged neighbourhood,
+// codes before this unit (among the cell's units) and the unit's first code.
+// Entry ne is the terminator: off = staged atoms, pre = the cell's codes.
+struct MvEnt {
+  int32_t role, src, off, pre;
+  int64_t uoff;
+};
+
 // Per cell: alpha and the initial guess (caller's, or alpha * b) in sorted
-// order; count of polarizable atoms into npart[c].
+// order; count of polarizable atoms into npart[c]; the cell's header and
+// unit entries.
 __global__ __launch_bounds__(kCellThreads) void k_cs_setup(PlanView pv, const double* __restrict__ pol,
                                                            const double* __restrict__ guess,
                                                            const int32_t* __restrict__ guess_on,
                                                            const double* __restrict__ b,
                                                            double* __restrict__ alpha_s,
                                                            double* __restrict__ x,
-                                                           double* __restrict__ npart) {
+                                                           double* __restrict__ npart,
+                                                           MvHdr* __restrict__ hdr,
+                                                           MvEnt* __restrict__ ent) {
   __shared__ double sh[16];
-  const int c = blockIdx.x;
+  const int pos = xcd_pos(pv.ncells, blockIdx.x);
+  if (pos < 0) return;
+  const int c = pv.cell_order[pos];
   const int hs = pv.cell_start[c], he = pv.cell_start[c + 1];
-  const bool use = guess && (!guess_on || guess_on[cell_system(pv, c)]);
+  const int sy = cell_system(pv, c);
+  const bool use = guess && (!guess_on || guess_on[sy]);
   double cnt[1] = {0.0};
   for (int s = hs + threadIdx.x; s < he; s += kCellThreads) {
     const int i = pv.perm[s];
@@ -94,6 +118,39 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_setup(PlanView pv, const do
 #pragma unroll
     for (int k = 0; k < 3; ++k)
       x[3 * s + k] = use ? (a > 0.0 ? guess[3 * i + k] : 0.0) : a * b[3 * s + k];
+  }
+  if (threadIdx.x < 64) {   // wave 0: the unit entries (exclusive prefixes over the cell's units)
+    const int lane = threadIdx.x;
+    const int32_t* cu = pv.cell_units + (long)c * kCellUnitStride;
+    const int ne = cu[0];
+    int no = 0, cn = 0, role = -1, ocs = 0;
+    long uoff = 0;
+    if (lane < ne) {
+      const int e = cu[1 + lane];
+      const int u = e >> 2;
+      role = e & 3;
+      const Unit un = pv.units[u];
+      const int oc = role == 1 ? un.h : un.k;
+      ocs = pv.cell_start[oc];
+      no = pv.cell_start[oc + 1] - ocs;
+      cn = pv.unit_cnt[u];
+      uoff = pv.unit_off[u];
+    }
+    int io = no, ic = cn;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t1 = __shfl_up(io, o), t2 = __shfl_up(ic, o);
+      if (lane >= o) {
+        io += t1;
+        ic += t2;
+      }
+    }
+    if (lane < kEntRow) ent[(long)pos * kEntRow + lane] = MvEnt{role, ocs, io - no, ic - cn, uoff};
+    const uint64_t sm = __ballot(lane < ne && role == 2);
+    if (lane == 0) {
+      const SysDev& sd = pv.sys[sy];
+      hdr[pos] = MvHdr{c, ne, sm ? __ffsll((long long)sm) - 1 : 0, hs, he - hs, sy,
+                       sd.cell0, pv.sys[sy + 1].cell0, sd.box, sd.inv_box};
+    }
   }
   wg_sum<1>(cnt, sh);
   if (threadIdx.x == 0) npart[c] = cnt[0];
@@ -122,7 +179,7 @@ __global__ __launch_bounds__(64) void k_cs_init(PlanView pv, const double* __res
 // Per-cell mat-vec with the iteration's bookkeeping folded in.
 //
 // One workgroup per cell C owns C's atoms (cells in the XCD-local order of
-// xcd_cell).  It walks the pair codes of all units C takes part in (each
+// xcd_pos).  It walks the pair codes of all units C takes part in (each
 // unordered pair is therefore visited from both of its cells) and
 // accumulates only C's side.  With kStage the coordinates
 // and operand of all of C's neighbour cells are staged in LDS first;
@@ -130,6 +187,14 @@ __global__ __launch_bounds__(64) void k_cs_init(PlanView pv, const double* __res
 // arrays.  Each wave keeps its own accumulator copy in LDS, summed in wave
 // order, so sums are reproducible.  The epilogue applies A to C's atoms
 // directly: no partial slots, no separate per-atom pass.
+//
+// Latency: the workgroup's global reads come in three rounds: (1) the cell
+// table, the system state and the partial sums; (2) the staged
+// neighbourhood, the first batch of pair codes and factors and the cell's
+// own alpha and right-hand side, all issued before any of them is waited
+// for; (3) the remaining pair batches.  kMulti: plans holding several
+// systems (the system's state and cell range come from the cell table; with
+// one system they are known without a read).
 //
 // kMode 0: v = x:  r = b - A x, z = alpha r; partials r.z, z.z.
 // kMode 1: iteration k: convergence test on the partials of r.z and z.z
@@ -141,11 +206,14 @@ __global__ __launch_bounds__(64) void k_cs_init(PlanView pv, const double* __res
 constexpr int kMvThreads = 512;    // mat-vec workgroups: 8 waves per cell
 constexpr int kMvWaves = kMvThreads / 64;
 constexpr int kMvBatch = 4;        // pairs per thread whose loads are issued together
-constexpr int kMvStageBatch = 4;   // staged atoms per thread whose loads are issued together
+constexpr int kMvStageBatch = 3;   // staged atoms per thread whose loads are issued together
+constexpr int kMvSub = 4;          // pairs per thread whose LDS reads are issued together
 
 template <class R>
 struct MvArgs {
   PlanView pv;
+  const MvHdr* hdr;    // [ncells] by XCD position
+  const MvEnt* ent;    // [ncells][kEntRow] by XCD position
   const R* gc;
   long gcs;
   double cself;
@@ -168,40 +236,50 @@ struct MvArgs {
   PcgState* host;
 };
 
-template <class R, int kMode, bool kStage>
+template <class R, int kMode, bool kStage, bool kMulti>
 __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   extern __shared__ double lds[];
   __shared__ double red[3 * 16];
-  __shared__ int e_role[kCellUnitStride], e_cs[kCellUnitStride];
-  __shared__ int e_off[kCellUnitStride + 1], e_pre[kCellUnitStride + 1];
-  __shared__ long e_uoff[kCellUnitStride];
-  __shared__ int self_j, s_done;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  __shared__ int e_role[kEntRow], e_src[kEntRow], e_off[kEntRow], e_pre[kEntRow];
+  __shared__ long e_uoff[kEntRow];
+  __shared__ int s_done;
+  const int tid = threadIdx.x, w = tid >> 6;
   const PlanView& pv = A.pv;
-  const int c = xcd_cell(pv, blockIdx.x);
-  if (c < 0) return;
-  const CellSys cs = cell_sys_of(pv, c);
-  PcgState* st = A.st + cs.sy;
-  if (tid == 0) s_done = st->done;   // one read per workgroup: all its waves agree
-  __syncthreads();
-  if (kMode != 2 && s_done) return;
-  if (kMode == 2 && !s_done) return;
   const int ncells = pv.ncells;
+  const int pos = xcd_pos(ncells, blockIdx.x);
+  if (pos < 0) return;
+  // round 1: cell table, state, partials
+  const MvHdr hd = A.hdr[pos];
+  if (tid < kEntRow) {
+    const MvEnt e = A.ent[(long)pos * kEntRow + tid];
+    e_role[tid] = e.role;
+    e_src[tid] = e.src;
+    e_off[tid] = e.off;
+    e_pre[tid] = e.pre;
+    e_uoff[tid] = e.uoff;
+  }
+  const int sy = kMulti ? hd.sy : 0;
+  const int c0 = kMulti ? hd.c0 : 0, c1 = kMulti ? hd.c1 : ncells;
+  PcgState* st = A.st + sy;
+  if (tid == 0) s_done = st->done;   // one read per workgroup: all its waves agree
   double beta = 0.0;
   if (kMode == 1) {
+    const int npol_i = st->npol, maxiter = st->maxiter;
+    const double tol = st->tol;
     double v3[3] = {0.0, 0.0, 0.0};
-    for (int cc = cs.c0 + tid; cc < cs.c1; cc += kMvThreads) {
+    for (int cc = c0 + tid; cc < c1; cc += kMvThreads) {
       v3[0] += A.pz_cur[cc];
       v3[1] += A.pz_cur[ncells + cc];
       if (A.k >= 1) v3[2] += A.pz_prev[cc];
     }
-    wg_sum<3>(v3, red);
+    wg_sum<3>(v3, red);   // its barriers also publish the entries and s_done
+    if (s_done) return;
     const double rz = v3[0], zz = v3[1], rzp = v3[2];
-    const double npol = st->npol > 0 ? (double)st->npol : 1.0;
+    const double npol = npol_i > 0 ? (double)npol_i : 1.0;
     const double rms = kDebye * sqrt(zz / npol);
-    const int stop = rms <= st->tol ? 1 : A.k >= st->maxiter ? 2 : 0;
+    const int stop = rms <= tol ? 1 : A.k >= maxiter ? 2 : 0;
     if (A.k >= 1) beta = rz / rzp;
-    if (c == cs.c0 && tid == 0) {
+    if (hd.c == c0 && tid == 0) {
       st->rho = rz;
       st->zz = zz;
       st->rms = rms;
@@ -209,49 +287,16 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
       st->beta = beta;
       st->iters = A.k;
       if (stop) st->done = stop;
-      A.host[cs.sy] = *st;
+      A.host[sy] = *st;
     }
     if (stop) return;
+  } else {
+    __syncthreads();
+    if (kMode != 2 && s_done) return;
+    if (kMode == 2 && !s_done) return;
   }
-  const SysDev sd = pv.sys[cs.sy];
-  // the cell's units: role, other cell, staging offset, pair-code prefix
-  const int32_t* cu = pv.cell_units + (long)c * kCellUnitStride;
-  const int ne = cu[0];
-  if (w == 0) {
-    int no = 0, cnt = 0, role = 0, ocs = 0;
-    if (lane < ne) {
-      const int e = cu[1 + lane];
-      const int u = e >> 2;
-      role = e & 3;
-      const Unit un = pv.units[u];
-      const int oc = role == 1 ? un.h : un.k;
-      ocs = pv.cell_start[oc];
-      no = pv.cell_start[oc + 1] - ocs;
-      cnt = pv.unit_cnt[u];
-      e_uoff[lane] = pv.unit_off[u];
-    }
-    int io = no, ic = cnt;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t1 = __shfl_up(io, o), t2 = __shfl_up(ic, o);
-      if (lane >= o) {
-        io += t1;
-        ic += t2;
-      }
-    }
-    if (lane < ne) {
-      e_role[lane] = role;
-      e_cs[lane] = ocs;
-      e_off[lane] = io - no;
-      e_pre[lane] = ic - cnt;
-      if (role == 2) self_j = lane;
-    }
-    if (lane == ne - 1) {
-      e_off[ne] = io;
-      e_pre[ne] = ic;
-    }
-  }
-  __syncthreads();
-  const int hs = pv.cell_start[c], nown = pv.cell_start[c + 1] - hs;
+  const int ne = hd.ne, hs = hd.hs, nown = hd.nown;
+  const double box = hd.box, inv_box = hd.inv_box;
   const long ps = A.pstride;
   // operand v + beta * pold: for k = 0 (and modes 0, 2) beta = 0 and pold = v
   const double* pold = (kMode == 1 && A.k >= 1) ? A.pold : A.v;
@@ -259,10 +304,13 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   const int SC = kStage ? A.stage_cap : A.own_cap, OC = A.own_cap;
   double* L = lds;
   double* ACC = L + 6 * SC;
-  const int own0 = kStage ? e_off[self_j] : 0;
+  const int own0 = kStage ? e_off[hd.self_j] : 0;
   const int total = kStage ? e_off[ne] : nown;
-  for (int i0 = tid; i0 < total; i0 += kMvThreads * kMvStageBatch) {
-    int src[kMvStageBatch];
+  const int T = e_pre[ne];
+  // round 2: staging loads, the first pair batch, own alpha and rhs
+  int src[kMvStageBatch];
+  double f[kMvStageBatch][6];
+  const auto stage_load = [&](int i0) {
 #pragma unroll
     for (int m = 0; m < kMvStageBatch; ++m) {
       const int i = i0 + m * kMvThreads;
@@ -275,24 +323,21 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
             if (e_off[mid] <= i) lo = mid;
             else hi = mid - 1;
           }
-          sidx = e_cs[lo] + (i - e_off[lo]);
+          sidx = e_src[lo] + (i - e_off[lo]);
         } else {
           sidx = hs + i;
         }
       }
       src[m] = sidx;
-    }
-    double f[kMvStageBatch][6];
+      if (sidx < 0) continue;
+      f[m][0] = A.pos[sidx];
+      f[m][1] = A.pos[ps + sidx];
+      f[m][2] = A.pos[2 * ps + sidx];
 #pragma unroll
-    for (int m = 0; m < kMvStageBatch; ++m) {
-      const int s = src[m];
-      if (s < 0) continue;
-      f[m][0] = A.pos[s];
-      f[m][1] = A.pos[ps + s];
-      f[m][2] = A.pos[2 * ps + s];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) f[m][3 + d] = fma(beta, pold[3 * s + d], A.v[3 * s + d]);
+      for (int d = 0; d < 3; ++d) f[m][3 + d] = fma(beta, pold[3 * sidx + d], A.v[3 * sidx + d]);
     }
+  };
+  const auto stage_store = [&](int i0) {
 #pragma unroll
     for (int m = 0; m < kMvStageBatch; ++m) {
       if (src[m] < 0) continue;
@@ -300,6 +345,40 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
 #pragma unroll
       for (int d = 0; d < 6; ++d) L[d * SC + i] = f[m][d];
     }
+  };
+  // pair batches: entry index, code and factors of kMvBatch pairs per thread
+  int ej[kMvBatch];
+  uint32_t cd[kMvBatch];
+  R g1s[kMvBatch], g2s[kMvBatch];
+  int j = 0;   // entry of the thread's current pair (pairs are visited in increasing order)
+  const auto batch_load = [&](int v0) {
+#pragma unroll
+    for (int m = 0; m < kMvBatch; ++m) {
+      const int vix = v0 + m * kMvThreads;
+      ej[m] = -1;
+      if (vix < T) {
+        while (vix >= e_pre[j + 1]) ++j;
+        ej[m] = j;
+        const long p = e_uoff[j] + (vix - e_pre[j]);
+        cd[m] = pv.codes[p];
+        g1s[m] = A.gc[p];
+        g2s[m] = A.gc[A.gcs + p];
+      }
+    }
+  };
+  stage_load(tid);
+  batch_load(tid);
+  double al0 = 0.0, rhs0[3] = {0.0, 0.0, 0.0};
+  if (tid < nown) {
+    al0 = A.alpha_s[hs + tid];
+    if (kMode != 1)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) rhs0[d] = A.rhs[3 * (hs + tid) + d];
+  }
+  stage_store(tid);
+  for (int i0 = tid + kMvThreads * kMvStageBatch; i0 < total; i0 += kMvThreads * kMvStageBatch) {
+    stage_load(i0);
+    stage_store(i0);
   }
   for (int i = tid; i < kMvWaves * 3 * nown; i += kMvThreads) {
     const int ww = i / (3 * nown), rem = i - ww * 3 * nown;
@@ -307,66 +386,69 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   }
   __syncthreads();
   double* MY = ACC + w * 3 * OC;   // this wave's copy: MY[d * nown + t]
-  const int T = e_pre[ne];
-  int j = 0;
   for (int v0 = tid; v0 < T; v0 += kMvThreads * kMvBatch) {
-    // the batch's code and factor loads are issued together; unit data is
-    // kept in registers (no LDS reads after the atomics)
-    uint32_t codes[kMvBatch];
-    R g1s[kMvBatch], g2s[kMvBatch];
-    int roles[kMvBatch], offs[kMvBatch];
+    if (v0 != tid) batch_load(v0);   // round 3 onwards
+    // sub-batches of kMvSub pairs: every LDS read of the sub-batch is issued
+    // before its accumulations (the compiler cannot move reads of L past the
+    // LDS atomics on MY, which it must assume may alias)
 #pragma unroll
-    for (int m = 0; m < kMvBatch; ++m) {
-      const int vix = v0 + m * kMvThreads;
-      roles[m] = -1;
-      if (vix < T) {
-        while (vix >= e_pre[j + 1]) ++j;
-        roles[m] = e_role[j];
-        offs[m] = kStage ? e_off[j] : e_cs[j];
-        const long p = e_uoff[j] + (vix - e_pre[j]);
-        codes[m] = pv.codes[p];
-        g1s[m] = A.gc[p];
-        g2s[m] = A.gc[A.gcs + p];
-      }
-    }
+    for (int m0 = 0; m0 < kMvBatch; m0 += kMvSub) {
+      double co[kMvSub][3], cb[kMvSub][3];
+      int io[kMvSub], ib[kMvSub];
 #pragma unroll
-    for (int m = 0; m < kMvBatch; ++m) {
-      if (roles[m] < 0) continue;
-      const int role = roles[m];
-      const int a = (int)(codes[m] & 0xffffu), b = (int)(codes[m] >> 16);
-      const int own = role == 1 ? b : a;
-      const int oth = offs[m] + (role == 1 ? a : b);   // LDS index, or sorted index
-      const int ownL = own0 + own;
-      const R g1 = g1s[m], g2 = g2s[m];
-      double xo[3], vo64[3];
-      if (kStage) {
+      for (int mm = 0; mm < kMvSub; ++mm) {
+        const int m = m0 + mm;
+        io[mm] = -1;
+        ib[mm] = -1;
+        if (ej[m] < 0) continue;
+        const int role = e_role[ej[m]];
+        const int offs = kStage ? e_off[ej[m]] : e_src[ej[m]];
+        const int a = (int)(cd[m] & 0xffffu), b = (int)(cd[m] >> 16);
+        const int own = role == 1 ? b : a;
+        const int oth = offs + (role == 1 ? a : b);   // LDS index, or sorted index
+        const int ownL = own0 + own;
+        const R g1 = g1s[m], g2 = g2s[m];
+        double xo[3], vo64[3];
+        if (kStage) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            xo[d] = L[d * SC + oth];
+            vo64[d] = L[(3 + d) * SC + oth];
+          }
+        } else {
+          xo[0] = A.pos[oth];
+          xo[1] = A.pos[ps + oth];
+          xo[2] = A.pos[2 * ps + oth];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) vo64[d] = fma(beta, pold[3 * oth + d], A.v[3 * oth + d]);
+        }
+        R dv[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          xo[d] = L[d * SC + oth];
-          vo64[d] = L[(3 + d) * SC + oth];
+          const double t = xo[d] - L[d * SC + ownL];
+          dv[d] = R(fma(-box, rint(t * inv_box), t));
         }
-      } else {
-        xo[0] = A.pos[oth];
-        xo[1] = A.pos[ps + oth];
-        xo[2] = A.pos[2 * ps + oth];
+        const R vo[3] = {R(vo64[0]), R(vo64[1]), R(vo64[2])};
+        const R so = (vo[0] * dv[0] + vo[1] * dv[1] + vo[2] * dv[2]) * g2;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) vo64[d] = fma(beta, pold[3 * oth + d], A.v[3 * oth + d]);
+        for (int d = 0; d < 3; ++d) co[mm][d] = (double)(dv[d] * so - vo[d] * g1);
+        io[mm] = own;
+        if (role == 2) {   // self unit: the other atom is also this cell's
+          const R va[3] = {R(L[3 * SC + ownL]), R(L[4 * SC + ownL]), R(L[5 * SC + ownL])};
+          const R sa = (va[0] * dv[0] + va[1] * dv[1] + va[2] * dv[2]) * g2;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) cb[mm][d] = (double)(dv[d] * sa - va[d] * g1);
+          ib[mm] = b;
+        }
       }
-      R dv[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double t = xo[d] - L[d * SC + ownL];
-        dv[d] = R(fma(-sd.box, rint(t * sd.inv_box), t));
-      }
-      const R vo[3] = {R(vo64[0]), R(vo64[1]), R(vo64[2])};
-      const R so = (vo[0] * dv[0] + vo[1] * dv[1] + vo[2] * dv[2]) * g2;
+      for (int mm = 0; mm < kMvSub; ++mm) {
+        if (io[mm] >= 0)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) lds_add(&MY[d * nown + own], (double)(dv[d] * so - vo[d] * g1));
-      if (role == 2) {   // self unit: the other atom is also this cell's
-        const R va[3] = {R(L[3 * SC + ownL]), R(L[4 * SC + ownL]), R(L[5 * SC + ownL])};
-        const R sa = (va[0] * dv[0] + va[1] * dv[1] + va[2] * dv[2]) * g2;
+          for (int d = 0; d < 3; ++d) lds_add(&MY[d * nown + io[mm]], co[mm][d]);
+        if (ib[mm] >= 0)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) lds_add(&MY[d * nown + b], (double)(dv[d] * sa - va[d] * g1));
+          for (int d = 0; d < 3; ++d) lds_add(&MY[d * nown + ib[mm]], cb[mm][d]);
       }
     }
   }
@@ -374,20 +456,22 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   double sv[2] = {0.0, 0.0};
   for (int t = tid; t < nown; t += kMvThreads) {
     const int s = hs + t;
-    const double al = A.alpha_s[s];
+    const bool first = t == tid;   // alpha and rhs already loaded in round 2
+    const double al = first ? al0 : A.alpha_s[s];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      double f = 0.0;
+      double fs = 0.0;
 #pragma unroll
-      for (int ww = 0; ww < kMvWaves; ++ww) f += ACC[ww * 3 * OC + d * nown + t];
+      for (int ww = 0; ww < kMvWaves; ++ww) fs += ACC[ww * 3 * OC + d * nown + t];
       const double vv = L[(3 + d) * SC + own0 + t];
-      const double av = al > 0.0 ? vv / al - (f + A.cself * vv) : 0.0;   // (A v)_s
+      const double av = al > 0.0 ? vv / al - (fs + A.cself * vv) : 0.0;   // (A v)_s
       if (kMode == 1) {
         A.pnew[3 * s + d] = vv;
         A.q[3 * s + d] = av;
         sv[0] += vv * av;
       } else {
-        const double rr = al > 0.0 ? A.rhs[3 * s + d] - av : 0.0;
+        const double bb = first ? rhs0[d] : A.rhs[3 * s + d];
+        const double rr = al > 0.0 ? bb - av : 0.0;
         const double zz = al * rr;
         if (kMode == 0) {
           A.r[3 * s + d] = rr;
@@ -396,50 +480,69 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
           sv[1] += zz * zz;
         } else {
           sv[0] += zz * zz;
-          sv[1] += vv * A.rhs[3 * s + d];
+          sv[1] += vv * bb;
         }
       }
     }
   }
   wg_sum<2>(sv, red);
   if (tid == 0) {
-    A.part[c] = sv[0];
-    if (kMode != 1) A.part[ncells + c] = sv[1];
+    A.part[hd.c] = sv[0];
+    if (kMode != 1) A.part[ncells + hd.c] = sv[1];
   }
 }
 
 // Iteration k, second half, per cell: gamma = p.q and rho_k from the
 // system's partials (fixed order, in every workgroup), alpha = rho/gamma,
 // x += alpha p, r -= alpha q, z = alpha_i r; partials of r.z and z.z for
-// iteration k + 1.
+// iteration k + 1.  The cell's atoms are read in the same round as the
+// partials (before alpha is known).
+template <bool kMulti>
 __global__ __launch_bounds__(kCellThreads) void k_cs_update(
-    PlanView pv, const double* __restrict__ alpha_s, const double* __restrict__ p,
-    const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
-    double* __restrict__ z, const double* __restrict__ pg, const double* __restrict__ pz_cur,
-    double* __restrict__ pz_next, int k, PcgState* states, PcgState* host) {
+    PlanView pv, const MvHdr* __restrict__ hdr, const double* __restrict__ alpha_s,
+    const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
+    double* __restrict__ r, double* __restrict__ z, const double* __restrict__ pg,
+    const double* __restrict__ pz_cur, double* __restrict__ pz_next, int k, PcgState* states,
+    PcgState* host) {
   __shared__ double sh[2 * 16];
   __shared__ int s_done;
-  const int c = xcd_cell(pv, blockIdx.x), ncells = pv.ncells;
-  if (c < 0) return;
-  const CellSys cs = cell_sys_of(pv, c);
-  PcgState* st = states + cs.sy;
+  const int ncells = pv.ncells;
+  const int pos = xcd_pos(ncells, blockIdx.x);
+  if (pos < 0) return;
+  const MvHdr hd = hdr[pos];
+  const int sy = kMulti ? hd.sy : 0;
+  const int c0 = kMulti ? hd.c0 : 0, c1 = kMulti ? hd.c1 : ncells;
+  PcgState* st = states + sy;
   if (threadIdx.x == 0) s_done = st->done;   // one read per workgroup: all its waves agree
-  __syncthreads();
-  if (s_done) return;
   double g2[2] = {0.0, 0.0};
-  for (int cc = cs.c0 + threadIdx.x; cc < cs.c1; cc += kCellThreads) {
+  for (int cc = c0 + threadIdx.x; cc < c1; cc += kCellThreads) {
     g2[0] += pg[cc];
     g2[1] += pz_cur[cc];
   }
+  const int hs = hd.hs, nown = hd.nown;
+  const int t0 = threadIdx.x;
+  double a0 = 0.0, p0[3] = {}, q0[3] = {}, x0[3] = {}, r0[3] = {};
+  if (t0 < nown) {
+    const int s = hs + t0;
+    a0 = alpha_s[s];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      p0[d] = p[3 * s + d];
+      q0[d] = q[3 * s + d];
+      x0[d] = x[3 * s + d];
+      r0[d] = r[3 * s + d];
+    }
+  }
   wg_sum<2>(g2, sh);
+  if (s_done) return;
   const double gam = g2[0], rho = g2[1];
-  const bool lead = c == cs.c0 && threadIdx.x == 0;
+  const bool lead = hd.c == c0 && threadIdx.x == 0;
   if (!(gam > 0.0)) {   // p.Ap <= 0: not positive definite
     if (lead) {
       st->gamma = gam;
       st->iters = k;
       st->done = 3;
-      host[cs.sy] = *st;
+      host[sy] = *st;
     }
     return;
   }
@@ -448,15 +551,16 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_update(
     st->gamma = gam;
     st->alpha = al;
   }
-  const int hs = pv.cell_start[c], he = pv.cell_start[c + 1];
   double sv[2] = {0.0, 0.0};
-  for (int s = hs + threadIdx.x; s < he; s += kCellThreads) {
-    const double a = alpha_s[s];
+  for (int t = t0; t < nown; t += kCellThreads) {
+    const int s = hs + t;
+    const bool first = t == t0;
+    const double a = first ? a0 : alpha_s[s];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int e = 3 * s + d;
-      x[e] += al * p[e];
-      const double rr = r[e] - al * q[e];
+      x[e] = (first ? x0[d] : x[e]) + al * (first ? p0[d] : p[e]);
+      const double rr = (first ? r0[d] : r[e]) - al * (first ? q0[d] : q[e]);
       r[e] = rr;
       const double zz = a * rr;
       z[e] = zz;
@@ -466,8 +570,8 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_update(
   }
   wg_sum<2>(sv, sh);
   if (threadIdx.x == 0) {
-    pz_next[c] = sv[0];
-    pz_next[ncells + c] = sv[1];
+    pz_next[hd.c] = sv[0];
+    pz_next[ncells + hd.c] = sv[1];
   }
 }
 
@@ -589,7 +693,9 @@ __global__ void k_scatter_out(int n, const int32_t* __restrict__ perm, const dou
 
 template <class R, int kMode, bool kStage>
 tk_status set_lds_attr(size_t lds) {
-  TK_HIP(hipFuncSetAttribute((const void*)k_pcg_mv<R, kMode, kStage>,
+  TK_HIP(hipFuncSetAttribute((const void*)k_pcg_mv<R, kMode, kStage, false>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  TK_HIP(hipFuncSetAttribute((const void*)k_pcg_mv<R, kMode, kStage, true>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   return TK_OK;
 }
@@ -625,6 +731,8 @@ struct Solver {
   double* pbuf[2];   // search directions p_k (k even, odd)
   double* pz[2];     // partials of r.z | z.z (k even, odd)
   double* pg;        // partials of p.q
+  MvHdr* hdr;        // per-cell tables of the iteration kernels
+  MvEnt* ent;
   void* gc;          // cached radial factors g1 | g2 per pair code (solver precision)
   long gcs;
   bool stage;
@@ -639,6 +747,8 @@ struct Solver {
   MvArgs<R> mv_args() const {
     MvArgs<R> a = {};
     a.pv = pv;
+    a.hdr = hdr;
+    a.ent = ent;
     a.gc = (const R*)gc;
     a.gcs = gcs;
     a.cself = cself;
@@ -655,10 +765,14 @@ struct Solver {
   template <class R, int kMode>
   void launch_mv(const MvArgs<R>& a, const char* name) {
     ProfScope ps(ctx, st, std::string(name) + prec_tag<R>());
-    if (stage)
-      k_pcg_mv<R, kMode, true><<<xcd_grid(ncells), kMvThreads, mv_lds, st>>>(a);
-    else
-      k_pcg_mv<R, kMode, false><<<xcd_grid(ncells), kMvThreads, mv_lds, st>>>(a);
+    const int g = xcd_grid(ncells);
+    if (nsys > 1) {
+      if (stage) k_pcg_mv<R, kMode, true, true><<<g, kMvThreads, mv_lds, st>>>(a);
+      else k_pcg_mv<R, kMode, false, true><<<g, kMvThreads, mv_lds, st>>>(a);
+    } else {
+      if (stage) k_pcg_mv<R, kMode, true, false><<<g, kMvThreads, mv_lds, st>>>(a);
+      else k_pcg_mv<R, kMode, false, false><<<g, kMvThreads, mv_lds, st>>>(a);
+    }
   }
 
   // iteration k, first half: convergence test, p_k, q = A p_k
@@ -679,8 +793,13 @@ struct Solver {
   // iteration k, second half: update x, r, z
   void queue_update(int k) {
     ProfScope ps(ctx, st, "pcg_update");
-    k_cs_update<<<xcd_grid(ncells), kCellThreads, 0, st>>>(pv, alpha_s, pbuf[k & 1], q, x, r, z, pg,
-                                                 pz[k & 1], pz[(k + 1) & 1], k, state, host_dev);
+    const int g = xcd_grid(ncells);
+    if (nsys > 1)
+      k_cs_update<true><<<g, kCellThreads, 0, st>>>(pv, hdr, alpha_s, pbuf[k & 1], q, x, r, z, pg,
+                                                    pz[k & 1], pz[(k + 1) & 1], k, state, host_dev);
+    else
+      k_cs_update<false><<<g, kCellThreads, 0, st>>>(pv, hdr, alpha_s, pbuf[k & 1], q, x, r, z, pg,
+                                                     pz[k & 1], pz[(k + 1) & 1], k, state, host_dev);
   }
 
   // TmatPh for the on-the-fly FP64 mat-vec of the mixed form
@@ -848,7 +967,7 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   const size_t npc = sizeof(double) * 2 * (size_t)S.ncells;
   tk_status s;
   void *alpha_s, *b, *x, *r, *z, *q, *partial = nullptr, *gath, *npart, *part, *dx, *rt, *pb0,
-       *pb1, *pz0, *pz1, *pg, *state, *act;
+       *pb1, *pz0, *pz1, *pg, *state, *act, *hdr, *ent;
   if ((s = scratch(ctx, "pcg_alpha", sizeof(double) * n, &alpha_s)) ||
       (s = scratch(ctx, "pcg_b", v3, &b)) || (s = scratch(ctx, "pcg_x", v3, &x)) ||
       (s = scratch(ctx, "pcg_r", v3, &r)) || (s = scratch(ctx, "pcg_z", v3, &z)) ||
@@ -860,6 +979,8 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
       (s = scratch(ctx, "pcg_pz1", npc, &pz1)) || (s = scratch(ctx, "pcg_pg", npc, &pg)) ||
       (s = scratch(ctx, "pcg_gathered", sizeof(double) * TmatPh<double>::NG * S.pstride, &gath)) ||
       (s = scratch(ctx, "pcg_state", sizeof(PcgState) * nsys, &state)) ||
+      (s = scratch(ctx, "pcg_hdr", sizeof(MvHdr) * S.ncells, &hdr)) ||
+      (s = scratch(ctx, "pcg_ent", sizeof(MvEnt) * kEntRow * S.ncells, &ent)) ||
       (s = scratch(ctx, "pcg_active", sizeof(int32_t) * nsys, &act)) ||
       (s = scratch(ctx, "pcg_gc", (prec == TK_FP64 ? sizeof(double) : sizeof(float)) * 2 * S.gcs,
                    &S.gc)))
@@ -875,6 +996,8 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   S.pz[0] = (double*)pz0; S.pz[1] = (double*)pz1; S.pg = (double*)pg;
   S.state = (PcgState*)state;
   S.active = (int32_t*)act;
+  S.hdr = (MvHdr*)hdr;
+  S.ent = (MvEnt*)ent;
   if (unit_lds_bytes<EfieldPh<double>>(*P, 1) > kMaxLds) return TK_E_CAPACITY;
   if ((s = mv_attributes(S.mv_lds))) return s;
   // pinned: [1024, ...) host state mirrors, then the refinement mask
@@ -894,8 +1017,8 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                                              ewald_beta, cutoff, S.b, 1, (float*)S.gc, S.gcs);
   if (s) return s;
   S.gather_geometry();
-  k_cs_setup<<<S.ncells, kCellThreads, 0, st>>>(S.pv, polarity, mu_guess, guess_on, S.b,
-                                                S.alpha_s, S.x, S.npart);
+  k_cs_setup<<<xcd_grid(S.ncells), kCellThreads, 0, st>>>(S.pv, polarity, mu_guess, guess_on, S.b,
+                                                          S.alpha_s, S.x, S.npart, S.hdr, S.ent);
   const int slot = (int)(P - ctx->plans);
   int& hint = ctx->pcg_hint[slot][prec == TK_FP64 ? 0 : 1];
   s = prec == TK_FP64 ? S.run<double>(S.b, tol_debye, maxiter, hint, true, nullptr)
@@ -952,9 +1075,10 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
       }
     }
   }
+  // the dipoles reach mu_out in stream order; the host already has the
+  // solve's outcome, so no further synchronisation
   k_scatter_out<<<ceil_div(n, 256), 256, 0, st>>>(n, (const int32_t*)P->perm.p, S.x, mu_out);
   TK_HIP(hipGetLastError());
-  TK_HIP(hipStreamSynchronize(st));
   return TK_OK;
 }
 

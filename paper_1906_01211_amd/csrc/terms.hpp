@@ -119,7 +119,7 @@ template <class R>
 struct EmpolePh {
   static constexpr int NF = 14, NA = 3, NS = 11;
   static constexpr const char* kName = "empole";
-  static constexpr int kWaves = 1;   // waves per unit (pairs.hpp launch_units)
+  static constexpr int kWaves = 2;   // waves per unit (pairs.hpp launch_units)
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
   __device__ void prologue(int tid, int nt) const { erfcx_stage<R>(tid, nt); }
@@ -291,7 +291,7 @@ template <class R>
 struct EfieldPh {
   static constexpr int NF = 16, NA = 3, NS = 0;
   static constexpr const char* kName = "efield";
-  static constexpr int kWaves = 4;   // waves per unit (pairs.hpp launch_units)
+  static constexpr int kWaves = 2;   // waves per unit (pairs.hpp launch_units)
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
   __device__ void prologue(int tid, int nt) const { erfcx_stage<R>(tid, nt); }

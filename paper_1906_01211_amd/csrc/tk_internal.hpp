@@ -73,12 +73,16 @@ struct PlanView {
 // launch 8 * ceil(ncells / 8) workgroups and map workgroup i to position
 // (i % 8) * ceil(ncells / 8) + i / 8 of the octant-grouped cell order, so
 // each XCD (with its own L2) works on one spatially compact block of cells
-// and most neighbour cells share an L2.  Returns -1 for the padding.
+// and most neighbour cells share an L2.  Both return -1 for the padding.
 constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_cell(const PlanView& pv, int wg) {
-  const int per = (pv.ncells + kXcds - 1) / kXcds;
+__device__ __forceinline__ int xcd_pos(int ncells, int wg) {
+  const int per = (ncells + kXcds - 1) / kXcds;
   const int pos = (wg % kXcds) * per + wg / kXcds;
-  return pos < pv.ncells ? pv.cell_order[pos] : -1;
+  return pos < ncells ? pos : -1;
+}
+__device__ __forceinline__ int xcd_cell(const PlanView& pv, int wg) {
+  const int pos = xcd_pos(pv.ncells, wg);
+  return pos >= 0 ? pv.cell_order[pos] : -1;
 }
 inline int xcd_grid(int ncells) { return (ncells + kXcds - 1) / kXcds * kXcds; }
 
@@ -199,7 +203,8 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
 // residual and, in the mixed form, refinement).  xyz, molid and the
 // parameters are in caller order for the plan's atoms; mu_guess is used for
 // the systems whose guess_on entry (device [nsys], nullable: all) is nonzero;
-// info[P->nsys] is host memory.  Synchronises the stream.
+// info[P->nsys] is host memory.  Synchronises the stream while solving;
+// mu_out is written in stream order after the return.
 tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double* xyz,
                         const int32_t* molid, const double* mpole, const double* polarity,
                         const double* thole, double ewald_beta, double cutoff, double tol_debye,
