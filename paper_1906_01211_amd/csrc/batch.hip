@@ -7,13 +7,6 @@
 
 #include "terms.hpp"
 
-namespace tk {
-__global__ void k_finish_energy3(int nsys, const double* __restrict__ sums, double* energy,
-                                 double* virial);
-__global__ void k_finish_energy1(int nsys, const double* __restrict__ sums, double* energy,
-                                 double* virial);
-}  // namespace tk
-
 using namespace tk;
 
 namespace {
@@ -33,13 +26,14 @@ tk_status check_params(const tk_step_params* p) {
 
 template <class R>
 tk_status run_mpole(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_batch* b,
-                    const double* mpole, const tk_step_params* p, double* force, double* sums) {
+                    const double* mpole, const tk_step_params* p, double* force, double* energy,
+                    double* virial) {
   EmpolePh<R> ph;
   ph.xyz = b->xyz;
   ph.mpole = mpole;
   ph.molid = b->molid;
   ph.g.set(b->box[0], p->rc_ewald, p->ewald_beta);
-  return run_term(ctx, st, P, ph, EpiForce{force}, sums);
+  return run_term(ctx, st, P, ph, EpiForce{force}, energy, virial);
 }
 
 // rc0: the first system's vdW cutoff (the functor's own geometry, used as
@@ -47,12 +41,12 @@ tk_status run_mpole(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_batch* 
 template <class R>
 tk_status run_vdw(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_batch* b,
                   const double* rad, const double* eps, const tk_step_params* p, double rc0,
-                  const double* sys_cut, double* force, double* sums) {
+                  const double* sys_cut, double* force, double* energy, double* virial) {
   VdwPh<R> ph;
   const tk_system s1{P.n, b->xyz, b->box[0], b->molid};
   ph.set(&s1, TK_VDW_HAL, rad, eps, rc0, p->taper_on_frac, p->hal_delta, p->hal_gamma);
   ph.sys_cut = sys_cut;
-  return run_term(ctx, st, P, ph, EpiForce{force}, sums);
+  return run_term(ctx, st, P, ph, EpiForce{force}, energy, virial);
 }
 
 }  // namespace
@@ -96,14 +90,12 @@ extern "C" tk_status tk_batch_step(tk_ctx* ctx, void* stream, const tk_batch* b,
   const Plan& P9 = ctx->plans[kBatchPlan9];
   // device outputs of the per-system scalars: e3 | w3 | e1 | w1, then vdW cutoffs
   const size_t nout = (size_t)nsys * (3 + 9 + 1 + 9);
-  void *sums3, *sums1, *outd, *cutd, *gon = nullptr;
+  void *outd, *cutd, *gon = nullptr;
   if (mu_guess && use_guess) {
     if ((s = scratch(ctx, "batch_guess_on", sizeof(int32_t) * nsys, &gon))) return s;
     TK_HIP(hipMemcpyAsync(gon, use_guess, sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
   }
-  if ((s = scratch(ctx, "batch_sums3", sizeof(double) * 11 * nsys, &sums3)) ||
-      (s = scratch(ctx, "batch_sums1", sizeof(double) * 10 * nsys, &sums1)) ||
-      (s = scratch(ctx, "batch_out", sizeof(double) * nout, &outd)) ||
+  if ((s = scratch(ctx, "batch_out", sizeof(double) * nout, &outd)) ||
       (s = scratch(ctx, "batch_cut", sizeof(double) * nsys, &cutd)))
     return s;
   double* e3 = (double*)outd;
@@ -116,17 +108,14 @@ extern "C" tk_status tk_batch_step(tk_ctx* ctx, void* stream, const tk_batch* b,
         unit_lds_bytes<VdwPh<double>>(P9, 1) > kMaxLds)
       return TK_E_CAPACITY;
     s = p->prec == TK_FP64
-            ? run_mpole<double>(ctx, st, P7, b, mpole, p, force_mpole, (double*)sums3)
-            : run_mpole<float>(ctx, st, P7, b, mpole, p, force_mpole, (double*)sums3);
+            ? run_mpole<double>(ctx, st, P7, b, mpole, p, force_mpole, e3, w3)
+            : run_mpole<float>(ctx, st, P7, b, mpole, p, force_mpole, e3, w3);
     if (s) return s;
     s = p->prec == TK_FP64 ? run_vdw<double>(ctx, st, P9, b, vdw_rad, vdw_eps, p, r9[0],
-                                             (const double*)cutd, force_vdw, (double*)sums1)
+                                             (const double*)cutd, force_vdw, e1, w1)
                            : run_vdw<float>(ctx, st, P9, b, vdw_rad, vdw_eps, p, r9[0],
-                                            (const double*)cutd, force_vdw, (double*)sums1);
+                                            (const double*)cutd, force_vdw, e1, w1);
     if (s) return s;
-    k_finish_energy3<<<ceil_div(nsys, 64), 64, 0, st>>>(nsys, (double*)sums3, e3, w3);
-    k_finish_energy1<<<ceil_div(nsys, 64), 64, 0, st>>>(nsys, (double*)sums1, e1, w1);
-    TK_HIP(hipGetLastError());
   } else {
     TK_HIP(hipMemsetAsync(outd, 0, sizeof(double) * nout, st));
   }

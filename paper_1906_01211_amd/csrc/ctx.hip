@@ -192,38 +192,73 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const T* in, long len
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[len] = bsum[gridDim.x];
 }
 
-// One workgroup for short arrays (one launch instead of three): thread t
-// sums a contiguous chunk, the chunk sums are scanned across the workgroup,
-// then each thread writes its chunk.
+// One workgroup for arrays up to kScan1Max (one launch instead of two or
+// three).  The array is read as kItems tiles of kScan1Threads values, thread
+// t holding value t of every tile (coalesced loads, all in flight together);
+// the tiles are scanned inside the waves level by level (the kItems shuffles
+// of a level are independent); wave 0 scans the (tile, wave) totals in
+// tile-major order, which gives every wave of every tile its offset; each
+// thread adds its wave's offset.
 constexpr int kScan1Threads = 1024;
-constexpr long kScan1Max = 4096;
+constexpr long kScan1Max = (long)kScan1Threads * 4;
 constexpr int kScan2MaxBlocks = 4096;
 
-template <class T>
+template <class T, int kItems>
 __global__ __launch_bounds__(kScan1Threads) void k_scan1(const T* __restrict__ in, long len,
                                                          T* __restrict__ out) {
-  __shared__ T wsum[kScan1Threads / 64];
+  constexpr int kW = kScan1Threads / 64;
+  constexpr int kTot = kItems * kW;      // (tile, wave) totals
+  constexpr int kPer = (kTot + 63) / 64;  // per lane of wave 0
+  __shared__ T wsum[kTot];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const long chunk = (len + kScan1Threads - 1) / kScan1Threads;
-  const long b0 = tid * chunk, b1 = b0 + chunk < len ? b0 + chunk : len;
-  T s = 0;
-  for (long i = b0; i < b1; ++i) s += in[i];
-  T incl = s;   // inclusive scan inside the wave
-  for (int o = 1; o < 64; o <<= 1) {
-    const T t = __shfl_up(incl, o);
-    if (lane >= o) incl += t;
+  T v[kItems], incl[kItems];
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    const long e = (long)q * kScan1Threads + tid;
+    v[q] = e < len ? in[e] : T(0);
+    incl[q] = v[q];
   }
-  if (lane == 63) wsum[w] = incl;
+  for (int o = 1; o < 64; o <<= 1) {   // inclusive scans inside the wave, all tiles per level
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+      const T t = __shfl_up(incl[q], o);
+      if (lane >= o) incl[q] += t;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    if (lane == 63) wsum[q * kW + w] = incl[q];
+    v[q] = incl[q] - v[q];   // exclusive, inside the wave
+  }
   __syncthreads();
-  T base = 0;
-  for (int k = 0; k < w; ++k) base += wsum[k];
-  T run = base + incl - s;
-  for (long i = b0; i < b1; ++i) {
-    const T v = in[i];
-    out[i] = run;
-    run += v;
+  if (w == 0) {   // exclusive scan of the totals, tile-major; each lane holds kPer of them
+    T x[kPer], s = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = lane * kPer + k;
+      x[k] = i < kTot ? wsum[i] : T(0);
+      s += x[k];
+    }
+    T inc = s;
+    for (int o = 1; o < 64; o <<= 1) {
+      const T t = __shfl_up(inc, o);
+      if (lane >= o) inc += t;
+    }
+    T run = inc - s;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = lane * kPer + k;
+      if (i < kTot) wsum[i] = run;
+      run += x[k];
+    }
+    if (lane == 63) out[len] = inc;   // the total
   }
-  if (tid == kScan1Threads - 1) out[len] = base + incl;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    const long e = (long)q * kScan1Threads + tid;
+    if (e < len) out[e] = wsum[q * kW + w] + v[q];
+  }
 }
 
 // Final pass that finds its own carry: block b sums the tile totals of the
@@ -254,8 +289,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final_carry(const T* in, lo
 template <class T>
 static tk_status scan_t(tk_ctx* ctx, hipStream_t st, const T* in, T* out, long len,
                         const char* name) {
+  // one workgroup up to four tiles (measured: beyond that the two-launch
+  // scan over many workgroups is as fast or faster)
   if (len <= kScan1Max) {
-    k_scan1<T><<<1, kScan1Threads, 0, st>>>(in, len, out);
+    k_scan1<T, 4><<<1, kScan1Threads, 0, st>>>(in, len, out);
     TK_HIP(hipGetLastError());
     return TK_OK;
   }

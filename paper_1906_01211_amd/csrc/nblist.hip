@@ -205,15 +205,6 @@ __global__ __launch_bounds__(64) void k_cellsort(const int32_t* __restrict__ cst
   }
 }
 
-// Candidate window of each unit: |H| * |K| slots.
-__global__ void k_cand(int nunits, const Unit* __restrict__ units, const int32_t* __restrict__ cstart,
-                       int64_t* __restrict__ cand) {
-  int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= nunits) return;
-  Unit un = units[u];
-  cand[u] = (int64_t)(cstart[un.h + 1] - cstart[un.h]) * (int64_t)(cstart[un.k + 1] - cstart[un.k]);
-}
-
 // Fixed-point span [lo, hi] of cell index ci along one axis: the u with
 // (u * nc) >> 32 == ci, i.e. lo = ceil(ci 2^32 / nc), hi = ceil((ci + 1)
 // 2^32 / nc) - 1.  In FP64 the quotient (below 2^33) is within 2^-21 of the
@@ -600,14 +591,27 @@ __global__ void k_batch_cells(int ncells, int nsys, const SysDev* __restrict__ s
   for (int j = 0; j < e[0]; ++j) o[1 + j] = ((e[1 + j] >> 2) + d.unit0) * 4 + (e[1 + j] & 3);
 }
 
-// One wave per cell: atoms in its neighbour cells (itself included); the
-// maximum goes to info[5] (staging size of the per-cell mat-vec).
-__global__ __launch_bounds__(256) void k_nbhd(int ncells, const int32_t* __restrict__ cu,
-                                              const Unit* __restrict__ units,
-                                              const int32_t* __restrict__ cstart,
-                                              int32_t* __restrict__ info) {
+// One launch, two jobs (both need only the cell starts):
+//  - blocks [0, nbu): candidate window of each unit, |H| * |K| slots;
+//  - the rest: one wave per cell, atoms in its neighbour cells (itself
+//    included); the maximum goes to info[5] (staging size of the per-cell
+//    mat-vec).
+__global__ __launch_bounds__(256) void k_cand_nbhd(int nunits, int ncells, int nbu,
+                                                   const int32_t* __restrict__ cu,
+                                                   const Unit* __restrict__ units,
+                                                   const int32_t* __restrict__ cstart,
+                                                   int64_t* __restrict__ cand,
+                                                   int32_t* __restrict__ info) {
   __shared__ int wmax[4];
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per cell
+  if ((int)blockIdx.x < nbu) {
+    const int u = blockIdx.x * 256 + threadIdx.x;
+    if (u >= nunits) return;
+    const Unit un = units[u];
+    cand[u] =
+        (int64_t)(cstart[un.h + 1] - cstart[un.h]) * (int64_t)(cstart[un.k + 1] - cstart[un.k]);
+    return;
+  }
+  const int c = ((int)blockIdx.x - nbu) * 4 + (threadIdx.x >> 6);   // one wave per cell
   const int lane = lane_id();
   int cnt = 0;
   if (c < ncells) {
@@ -627,29 +631,42 @@ __global__ __launch_bounds__(256) void k_nbhd(int ncells, const int32_t* __restr
 
 // Gathers the build's outcome into pinned host memory (one kernel instead of
 // several small copies).
-__global__ void k_readback(const int32_t* __restrict__ info, const int32_t* __restrict__ rp_end,
+// info is left zeroed for the next build.
+__global__ void k_readback(int32_t* __restrict__ info, const int32_t* __restrict__ rp_end,
                            const int64_t* __restrict__ off_end, const int64_t* __restrict__ pairs,
                            int32_t* __restrict__ host) {
   for (int k = 0; k < 6; ++k) host[k] = info[k];
+  for (int k = 0; k < 8; ++k) info[k] = 0;
   host[3] = (int32_t)*pairs;   // listed pairs, summed over the units
   host[6] = *rp_end;
   *(int64_t*)(host + 8) = *off_end;
 }
 
-// One wave per CSR row: order the row by j (monotone buckets over [jmin, jmax],
-// then rank inside a bucket).  LDS: A[max_row], G[max_row], cnt, off.
-__global__ __launch_bounds__(64) void k_rowsort(int n, const int32_t* __restrict__ row_ptr,
-                                                int32_t* __restrict__ col, int max_row) {
+// One wave per CSR row, blockDim.x / 64 rows per workgroup (up to
+// kRowsPerBlock: tiny one-wave workgroups are dispatch-bound): order the row
+// by j (monotone buckets over [jmin, jmax], then rank inside a bucket).  LDS
+// per wave: A[max_row], G[max_row], cnt, off.
+constexpr int kRowsPerBlock = 4;
+__global__ __launch_bounds__(64 * kRowsPerBlock) void k_rowsort(int n,
+                                                                const int32_t* __restrict__ row_ptr,
+                                                                int32_t* __restrict__ col,
+                                                                int max_row) {
   extern __shared__ int lds[];
-  const int i = blockIdx.x;
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * (blockDim.x >> 6) + w;
   const int lane = lane_id();
-  const int start = row_ptr[i], m = row_ptr[i + 1] - start;
-  if (m <= 1) return;
   const int nbmax = max_row < kBuckets ? max_row : kBuckets;
-  int* A = lds;
+  int* A = lds + (size_t)w * (2 * max_row + 2 * nbmax);
   int* G = A + max_row;
   int* cnt = G + max_row;
   int* off = cnt + nbmax;
+  int start = 0, m = 0;
+  if (i < n) {
+    start = row_ptr[i];
+    m = row_ptr[i + 1] - start;
+  }
+  // every wave takes part in the barriers; rows of 0 or 1 entries do no work
+  if (m <= 1) m = 0;
   int jmin = 0x7fffffff, jmax = -1;
   for (int e = lane; e < m; e += 64) {
     const int v = col[start + e];
@@ -660,7 +677,7 @@ __global__ __launch_bounds__(64) void k_rowsort(int n, const int32_t* __restrict
   jmin = wave_min(jmin);
   jmax = wave_max(jmax);
   const int nb = m < kBuckets ? m : kBuckets;
-  const double scale = (double)nb / (double)(jmax - jmin + 1);
+  const double scale = m > 0 ? (double)nb / (double)(jmax - jmin + 1) : 0.0;
   for (int b = lane; b < nb; b += 64) cnt[b] = 0;
   __syncthreads();
   for (int e = lane; e < m; e += 64) {
@@ -697,6 +714,16 @@ __global__ __launch_bounds__(64) void k_rowsort(int n, const int32_t* __restrict
     for (int k = k0; k < k1; ++k) rank += G[k] < j;
     col[start + rank] = j;
   }
+}
+
+// Dynamic LDS above the default limit must be allowed per kernel.
+tk_status rowsort_attribute(size_t lds) {
+  static size_t done = 0;
+  if (lds <= done) return TK_OK;
+  TK_HIP(hipFuncSetAttribute((const void*)k_rowsort, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  done = lds;
+  return TK_OK;
 }
 
 }  // namespace
@@ -778,9 +805,10 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
       (s = ensure(P.unit_off, sizeof(int64_t) * (nunits + 1))) ||
       (s = ensure(P.unit_cnt, sizeof(int32_t) * nunits)) ||
       (s = ensure(P.us, sizeof(uint4) * nn)) ||
-      (s = ensure(P.slots, sizeof(int32_t) * kMaxSlots * pstride)) ||
-      (s = ensure(P.sysd, sizeof(SysDev) * (nsys + 1))))
+      (s = ensure(P.slots, sizeof(int32_t) * kMaxSlots * pstride)))
     return s;
+  const void* sysd_was = P.sysd.p;
+  if ((s = ensure(P.sysd, sizeof(SysDev) * (nsys + 1)))) return s;
   // candidate windows: scratch shared by every build (the plan keeps the
   // dense codes); grown to the exact size and rerun if the estimate is short
   void* windows = nullptr;
@@ -811,9 +839,14 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   int32_t* h = (int32_t*)hb;
   int32_t* hd = (int32_t*)hdb;
   // the previous build's readback of this context has been consumed (every
-  // build synchronises before returning), so the staging area is free
-  std::memcpy(hb + 4096, sd.data(), sys_bytes);
-  TK_HIP(hipMemcpyAsync(P.sysd.p, hb + 4096, sys_bytes, hipMemcpyHostToDevice, st));
+  // build synchronises before returning), so the staging area is free.  The
+  // system table is uploaded only when it differs from the plan's copy.
+  if (P.sysd.p != sysd_was || P.h_sys.size() != sd.size() ||
+      std::memcmp(P.h_sys.data(), sd.data(), sys_bytes) != 0) {
+    std::memcpy(hb + 4096, sd.data(), sys_bytes);
+    TK_HIP(hipMemcpyAsync(P.sysd.p, hb + 4096, sys_bytes, hipMemcpyHostToDevice, st));
+    P.h_sys = sd;
+  }
   const SysDev* sysd = (const SysDev*)P.sysd.p;
   const Unit* units;
   const int32_t *nslot, *cu, *order, *cell_sys = nullptr;
@@ -849,7 +882,9 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     order = (const int32_t*)P.border.p;
     cell_sys = (const int32_t*)P.cell_sys.p;
   }
-  TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
+  // status words: zero after every completed build (the readback clears them)
+  if (!ctx->nb_info_zero) TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
+  ctx->nb_info_zero = false;
   const int32_t* cstart = (const int32_t*)P.cell_start.p;
   int32_t* rp = want_csr ? row_ptr : (int32_t*)rptr;
   if (n > 0 && ncells <= kMaxHistCells) {
@@ -893,7 +928,9 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     TK_HIP(hipMemsetAsync(P.cell_start.p, 0, sizeof(int32_t) * (ncells + 1), st));
   }
   if (n > 0) {
-    k_cand<<<ceil_div(nunits, 256), 256, 0, st>>>(nunits, units, cstart, (int64_t*)cand);
+    const int nbu = ceil_div(nunits, 256);
+    k_cand_nbhd<<<nbu + ceil_div(ncells, 4), 256, 0, st>>>(nunits, ncells, nbu, cu, units, cstart,
+                                                         (int64_t*)cand, (int32_t*)info);
     if ((s = scan_i64(ctx, st, (int64_t*)cand, (int64_t*)woff, nunits))) return s;
   }
   // staging bound of k_plan: three times the largest mean cell occupancy
@@ -907,9 +944,9 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   // waves per unit of the enumeration: more for larger cells
   const int plan_waves = max_mean > 96.0 ? 4 : max_mean > 48.0 ? 2 : 1;
   occ_cap = occ_cap < 64 ? 64 : occ_cap > kMaxCellAtoms ? kMaxCellAtoms : occ_cap;
+  int first_occ = 0, first_nbhd = 0;
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (n > 0) {
-      k_nbhd<<<ceil_div(ncells, 4), 256, 0, st>>>(ncells, cu, units, cstart, (int32_t*)info);
       {
         ProfScope ps(ctx, st, "nblist_plan");
         windows = wb.p;
@@ -937,16 +974,21 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
                                 (int64_t*)P.unit_off.p + nunits, hd);
     TK_HIP(hipGetLastError());
     TK_HIP(hipStreamSynchronize(st));
+    ctx->nb_info_zero = true;
+    if (attempt == 1) {   // the rerun did not repeat the cell sort or the neighbourhood sizes
+      h[1] = first_occ;
+      h[5] = first_nbhd;
+    }
     if (h[0] != 0) return h[0];
     if (h[4] == 0) break;
     if (attempt == 1) return TK_E_HIP;
     // windows or staging bound did not fit: exact sizes, enumerate again
+    first_occ = h[1];
+    first_nbhd = h[5];
     const int64_t need = *(int64_t*)(h + 8);
     if ((s = ensure(wb, sizeof(uint32_t) * (size_t)need))) return s;
     occ_cap = kMaxCellAtoms;
-    // clear only the overflow flag: the occupancy (from the cell sort, not
-    // rerun) and the maxima (rerun, idempotent) stay
-    TK_HIP(hipMemsetAsync((int32_t*)info + 4, 0, sizeof(int32_t), st));
+    ctx->nb_info_zero = false;
   }
   const int64_t list_pairs = h[6];
   *npairs_out = list_pairs;
@@ -966,8 +1008,12 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   if (want_csr) {
     if (list_pairs > cap) return TK_E_CAPACITY;
     const int nb = max_row < kBuckets ? max_row : kBuckets;
-    const size_t lds = sizeof(int) * (2 * (size_t)max_row + 2 * (size_t)nb);
-    if (lds > kMaxLds) return TK_E_CAPACITY;
+    const size_t lds1 = sizeof(int) * (2 * (size_t)max_row + 2 * (size_t)nb);
+    if (lds1 > kMaxLds) return TK_E_CAPACITY;
+    // several rows per workgroup while they fit the default LDS limit
+    const int rpb = lds1 * kRowsPerBlock <= 65536 ? kRowsPerBlock : 1;
+    const size_t lds = lds1 * rpb;
+    if (lds > 65536 && (s = rowsort_attribute(lds))) return s;
     if (n > 0 && list_pairs > 0) {
       {
         ProfScope ps(ctx, st, "nblist_csr_fill");
@@ -978,7 +1024,7 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
       }
       {
         ProfScope ps(ctx, st, "nblist_rowsort");
-        k_rowsort<<<n, 64, lds, st>>>(n, rp, col, max_row);
+        k_rowsort<<<ceil_div(n, rpb), 64 * rpb, lds, st>>>(n, rp, col, max_row);
       }
     }
   }
@@ -986,7 +1032,6 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   P.valid = true;
   P.n = n;
   P.nsys = nsys;
-  P.h_sys = sd;
   P.box = spec.box[0];
   P.cutoff = spec.cutoff[0];
   P.nc = sd[0].nc;

@@ -138,43 +138,111 @@ __global__ __launch_bounds__(256) void k_gather(PlanView pv, Ph ph, double* __re
   for (int f = 0; f < Ph::NG; ++f) out[f * gstride + s] = g[f];
 }
 
-// Sum each atom's partial slots (fixed order) and hand the NA sums to Epi.
-template <int NA, class Epi>
+// Unit-scalar chunks: each system's units are cut into chunks of kChunkUnits
+// (relative to the system's first unit, so a system is cut the same way alone
+// or in a batch); chunks are numbered system by system.
+constexpr int kChunkUnits = 256;
+__device__ __forceinline__ int sys_chunk0(const SysDev* __restrict__ sys, int sy) {
+  int c = 0;
+  for (int k = 0; k < sy; ++k) c += (sys[k + 1].unit0 - sys[k].unit0 + kChunkUnits - 1) / kChunkUnits;
+  return c;
+}
+inline int total_chunks(const Plan& P) {
+  int c = 0;
+  for (int k = 0; k < P.nsys; ++k)
+    c += (P.h_sys[k + 1].unit0 - P.h_sys[k].unit0 + kChunkUnits - 1) / kChunkUnits;
+  return c;
+}
+
+// Sum each atom's partial slots and hand the NA sums to Epi.  kRedLanes
+// lanes per atom (more waves in flight than one thread per atom): lane q
+// sums slots q, q + kRedLanes, ...; the lanes' sums are combined by two
+// butterfly steps, which give every lane of the group the same value (IEEE
+// addition is commutative), so the order is fixed.
+// With NS > 0 and uscal set, block b also sums unit-scalar chunk b (if there
+// is one) into cpart[b][NS], threads in unit order, waves in order.
+constexpr int kRedLanes = 4;
+template <int NA, int NS, class Epi>
 __global__ __launch_bounds__(256) void k_reduce(PlanView pv, const double* __restrict__ partial,
-                                                long pstride, Epi epi) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= pv.n) return;
+                                                long pstride, Epi epi,
+                                                const double* __restrict__ uscal,
+                                                double* __restrict__ cpart) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s0 = g / kRedLanes, q = g % kRedLanes;
+  const bool valid = s0 < pv.n;
+  const int s = valid ? s0 : pv.n - 1;   // lanes past the end repeat the last atom, write nothing
   const int ns = pv.cell_nslot[pv.scell[s]];
   double acc[NA];
 #pragma unroll
   for (int f = 0; f < NA; ++f) acc[f] = 0.0;
 #pragma unroll
-  for (int k = 0; k < kMaxSlots; ++k)   // unrolled: all slot loads in flight at once
+  for (int k0 = 0; k0 < kMaxSlots; k0 += kRedLanes) {   // unrolled: all slot loads in flight
+    const int k = k0 + q;
     if (k < ns)
 #pragma unroll
       for (int f = 0; f < NA; ++f) acc[f] += partial[((long)k * NA + f) * pstride + s];
-  epi(s, pv.perm[s], acc);
-}
-
-// Sum per-unit scalar records in a fixed order, per system:
-// out[s][k] = sum over the units u of system s of uscal[u][k]; one block per
-// (scalar, system).
-template <int NS>
-__global__ __launch_bounds__(256) void k_sum_units(const double* __restrict__ uscal,
-                                                   const SysDev* __restrict__ sys,
-                                                   double* __restrict__ out) {
-  __shared__ double sh[256];
-  const int k = blockIdx.x, sy = blockIdx.y;
-  const int u0 = sys[sy].unit0, u1 = sys[sy + 1].unit0;
-  double v = 0.0;
-  for (int u = u0 + threadIdx.x; u < u1; u += 256) v += uscal[(long)u * NS + k];
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
   }
-  if (threadIdx.x == 0) out[(long)sy * NS + k] = sh[0];
+#pragma unroll
+  for (int f = 0; f < NA; ++f) {
+    acc[f] += __shfl_xor(acc[f], 1);
+    acc[f] += __shfl_xor(acc[f], 2);
+  }
+  if (valid && q == 0) epi(s, pv.perm[s], acc);
+  if constexpr (NS > 0) {
+    if (!uscal) return;
+    // this block's chunk: system sy, chunk c of it (uniform over the block)
+    int b = blockIdx.x, sy = 0, u0 = 0, u1 = 0;
+    for (; sy < pv.nsys; ++sy) {
+      u0 = pv.sys[sy].unit0;
+      u1 = pv.sys[sy + 1].unit0;
+      const int nch = (u1 - u0 + kChunkUnits - 1) / kChunkUnits;
+      if (b < nch) break;
+      b -= nch;
+    }
+    if (sy >= pv.nsys) return;
+    __shared__ double sh[NS][4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int u = u0 + b * kChunkUnits + tid;
+    double v[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) v[k] = u < u1 ? uscal[(long)u * NS + k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+      if (lane == 0) sh[k][w] = v[k];
+    }
+    __syncthreads();
+    if (tid < NS) cpart[(long)blockIdx.x * NS + tid] = ((sh[tid][0] + sh[tid][1]) + sh[tid][2]) + sh[tid][3];
+  }
+}
+static_assert(kRedLanes == 4, "the butterfly above has two steps");
+
+// Per system: sum its chunk partials in order and write the energies and
+// virial.  Record layout: NS = 11: E_a, E_b, W[9] -> energy {E_a + E_b, E_a,
+// E_b}; NS = 10: E, W[9] -> energy {E}.  One wave per system.
+template <int NS>
+__global__ __launch_bounds__(64) void k_sum_finish(const double* __restrict__ cpart,
+                                                   const SysDev* __restrict__ sys,
+                                                   double* __restrict__ energy,
+                                                   double* __restrict__ virial) {
+  static_assert(NS == 10 || NS == 11, "energy records");
+  __shared__ double sh[NS];
+  const int sy = blockIdx.x, tid = threadIdx.x;
+  const int c0 = sys_chunk0(sys, sy);
+  const int nch = (sys[sy + 1].unit0 - sys[sy].unit0 + kChunkUnits - 1) / kChunkUnits;
+  if (tid < NS) {
+    double t = 0.0;
+    for (int c = 0; c < nch; ++c) t += cpart[(long)(c0 + c) * NS + tid];
+    constexpr int ne = NS - 9;   // energies in the record
+    if (tid >= ne) virial[9 * sy + tid - ne] = t;
+    else if (NS == 10) energy[sy] = t;
+    else energy[3 * sy + 1 + tid] = t;
+    sh[tid] = t;
+  }
+  if (NS == 11) {
+    __syncthreads();
+    if (tid == 0) energy[3 * sy] = sh[0] + sh[1];
+  }
 }
 
 // LDS of k_units<Ph, W>: both cells' fields and W accumulator copies each.

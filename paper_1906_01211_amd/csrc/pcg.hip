@@ -207,7 +207,6 @@ constexpr int kMvThreads = 512;    // mat-vec workgroups: 8 waves per cell
 constexpr int kMvWaves = kMvThreads / 64;
 constexpr int kMvBatch = 4;        // pairs per thread whose loads are issued together
 constexpr int kMvStageBatch = 3;   // staged atoms per thread whose loads are issued together
-constexpr int kMvSub = 4;          // pairs per thread whose LDS reads are issued together
 
 template <class R>
 struct MvArgs {
@@ -238,7 +237,7 @@ struct MvArgs {
 
 template <class R, int kMode, bool kStage, bool kMulti>
 __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) double lds[];
   __shared__ double red[3 * 16];
   __shared__ int e_role[kEntRow], e_src[kEntRow], e_off[kEntRow], e_pre[kEntRow];
   __shared__ long e_uoff[kEntRow];
@@ -300,10 +299,11 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   const long ps = A.pstride;
   // operand v + beta * pold: for k = 0 (and modes 0, 2) beta = 0 and pold = v
   const double* pold = (kMode == 1 && A.k >= 1) ? A.pold : A.v;
-  // LDS: staged atoms (x y z v0 v1 v2, stride SC), then [wave][3][OC] accumulators
+  // LDS: staged atoms, 48 bytes each (x y | z v0 | v1 v2: three 16-byte
+  // reads per atom), then [wave][3][OC] accumulators
   const int SC = kStage ? A.stage_cap : A.own_cap, OC = A.own_cap;
-  double* L = lds;
-  double* ACC = L + 6 * SC;
+  double2* L2 = (double2*)lds;
+  double* ACC = lds + 6 * SC;
   const int own0 = kStage ? e_off[hd.self_j] : 0;
   const int total = kStage ? e_off[ne] : nown;
   const int T = e_pre[ne];
@@ -343,31 +343,34 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
       if (src[m] < 0) continue;
       const int i = i0 + m * kMvThreads;
 #pragma unroll
-      for (int d = 0; d < 6; ++d) L[d * SC + i] = f[m][d];
+      for (int k = 0; k < 3; ++k) L2[3 * i + k] = make_double2(f[m][2 * k], f[m][2 * k + 1]);
     }
   };
-  // pair batches: entry index, code and factors of kMvBatch pairs per thread
-  int ej[kMvBatch];
-  uint32_t cd[kMvBatch];
-  R g1s[kMvBatch], g2s[kMvBatch];
+  // pair batches: entry index, code and factors of kMvBatch pairs per thread,
+  // double-buffered: batch k + 1 is loaded while batch k is processed (its
+  // LDS entry reads come before batch k's LDS atomics, so they do not wait
+  // for them)
+  int ej[2][kMvBatch];
+  uint32_t cd[2][kMvBatch];
+  R g1s[2][kMvBatch], g2s[2][kMvBatch];
   int j = 0;   // entry of the thread's current pair (pairs are visited in increasing order)
-  const auto batch_load = [&](int v0) {
+  const auto batch_load = [&](int v0, int buf) {
 #pragma unroll
     for (int m = 0; m < kMvBatch; ++m) {
       const int vix = v0 + m * kMvThreads;
-      ej[m] = -1;
+      ej[buf][m] = -1;
       if (vix < T) {
         while (vix >= e_pre[j + 1]) ++j;
-        ej[m] = j;
+        ej[buf][m] = j;
         const long p = e_uoff[j] + (vix - e_pre[j]);
-        cd[m] = pv.codes[p];
-        g1s[m] = A.gc[p];
-        g2s[m] = A.gc[A.gcs + p];
+        cd[buf][m] = pv.codes[p];
+        g1s[buf][m] = A.gc[p];
+        g2s[buf][m] = A.gc[A.gcs + p];
       }
     }
   };
   stage_load(tid);
-  batch_load(tid);
+  batch_load(tid, 0);
   double al0 = 0.0, rhs0[3] = {0.0, 0.0, 0.0};
   if (tid < nown) {
     al0 = A.alpha_s[hs + tid];
@@ -386,71 +389,62 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   }
   __syncthreads();
   double* MY = ACC + w * 3 * OC;   // this wave's copy: MY[d * nown + t]
-  for (int v0 = tid; v0 < T; v0 += kMvThreads * kMvBatch) {
-    if (v0 != tid) batch_load(v0);   // round 3 onwards
-    // sub-batches of kMvSub pairs: every LDS read of the sub-batch is issued
-    // before its accumulations (the compiler cannot move reads of L past the
-    // LDS atomics on MY, which it must assume may alias)
+  constexpr int kStep = kMvThreads * kMvBatch;
+  const auto process = [&](int buf) {
 #pragma unroll
-    for (int m0 = 0; m0 < kMvBatch; m0 += kMvSub) {
-      double co[kMvSub][3], cb[kMvSub][3];
-      int io[kMvSub], ib[kMvSub];
+    for (int m = 0; m < kMvBatch; ++m) {
+      if (ej[buf][m] < 0) continue;
+      const int role = e_role[ej[buf][m]];
+      const int offs = kStage ? e_off[ej[buf][m]] : e_src[ej[buf][m]];
+      const int a = (int)(cd[buf][m] & 0xffffu), b = (int)(cd[buf][m] >> 16);
+      const int own = role == 1 ? b : a;
+      const int oth = offs + (role == 1 ? a : b);   // LDS index, or sorted index
+      const int ownL = own0 + own;
+      const R g1 = g1s[buf][m], g2 = g2s[buf][m];
+      double xo[3], vo64[3];
+      if (kStage) {
+        const double2 q0 = L2[3 * oth], q1 = L2[3 * oth + 1], q2 = L2[3 * oth + 2];
+        xo[0] = q0.x;
+        xo[1] = q0.y;
+        xo[2] = q1.x;
+        vo64[0] = q1.y;
+        vo64[1] = q2.x;
+        vo64[2] = q2.y;
+      } else {
+        xo[0] = A.pos[oth];
+        xo[1] = A.pos[ps + oth];
+        xo[2] = A.pos[2 * ps + oth];
 #pragma unroll
-      for (int mm = 0; mm < kMvSub; ++mm) {
-        const int m = m0 + mm;
-        io[mm] = -1;
-        ib[mm] = -1;
-        if (ej[m] < 0) continue;
-        const int role = e_role[ej[m]];
-        const int offs = kStage ? e_off[ej[m]] : e_src[ej[m]];
-        const int a = (int)(cd[m] & 0xffffu), b = (int)(cd[m] >> 16);
-        const int own = role == 1 ? b : a;
-        const int oth = offs + (role == 1 ? a : b);   // LDS index, or sorted index
-        const int ownL = own0 + own;
-        const R g1 = g1s[m], g2 = g2s[m];
-        double xo[3], vo64[3];
-        if (kStage) {
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            xo[d] = L[d * SC + oth];
-            vo64[d] = L[(3 + d) * SC + oth];
-          }
-        } else {
-          xo[0] = A.pos[oth];
-          xo[1] = A.pos[ps + oth];
-          xo[2] = A.pos[2 * ps + oth];
-#pragma unroll
-          for (int d = 0; d < 3; ++d) vo64[d] = fma(beta, pold[3 * oth + d], A.v[3 * oth + d]);
-        }
-        R dv[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const double t = xo[d] - L[d * SC + ownL];
-          dv[d] = R(fma(-box, rint(t * inv_box), t));
-        }
-        const R vo[3] = {R(vo64[0]), R(vo64[1]), R(vo64[2])};
-        const R so = (vo[0] * dv[0] + vo[1] * dv[1] + vo[2] * dv[2]) * g2;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) co[mm][d] = (double)(dv[d] * so - vo[d] * g1);
-        io[mm] = own;
-        if (role == 2) {   // self unit: the other atom is also this cell's
-          const R va[3] = {R(L[3 * SC + ownL]), R(L[4 * SC + ownL]), R(L[5 * SC + ownL])};
-          const R sa = (va[0] * dv[0] + va[1] * dv[1] + va[2] * dv[2]) * g2;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) cb[mm][d] = (double)(dv[d] * sa - va[d] * g1);
-          ib[mm] = b;
-        }
+        for (int d = 0; d < 3; ++d) vo64[d] = fma(beta, pold[3 * oth + d], A.v[3 * oth + d]);
       }
+      const double2 w0 = L2[3 * ownL], w1 = L2[3 * ownL + 1];
+      const double xw[3] = {w0.x, w0.y, w1.x};
+      R dv[3];
 #pragma unroll
-      for (int mm = 0; mm < kMvSub; ++mm) {
-        if (io[mm] >= 0)
+      for (int d = 0; d < 3; ++d) {
+        const double t = xo[d] - xw[d];
+        dv[d] = R(fma(-box, rint(t * inv_box), t));
+      }
+      const R vo[3] = {R(vo64[0]), R(vo64[1]), R(vo64[2])};
+      const R so = (vo[0] * dv[0] + vo[1] * dv[1] + vo[2] * dv[2]) * g2;
 #pragma unroll
-          for (int d = 0; d < 3; ++d) lds_add(&MY[d * nown + io[mm]], co[mm][d]);
-        if (ib[mm] >= 0)
+      for (int d = 0; d < 3; ++d) lds_add(&MY[d * nown + own], (double)(dv[d] * so - vo[d] * g1));
+      if (role == 2) {   // self unit: the other atom is also this cell's
+        const double2 w2 = L2[3 * ownL + 2];
+        const R va[3] = {R(w1.y), R(w2.x), R(w2.y)};
+        const R sa = (va[0] * dv[0] + va[1] * dv[1] + va[2] * dv[2]) * g2;
 #pragma unroll
-          for (int d = 0; d < 3; ++d) lds_add(&MY[d * nown + ib[mm]], cb[mm][d]);
+        for (int d = 0; d < 3; ++d) lds_add(&MY[d * nown + b], (double)(dv[d] * sa - va[d] * g1));
       }
     }
+  };
+  // two batches per trip, so that the buffer index is a constant
+  for (int v0 = tid; v0 < T; v0 += 2 * kStep) {
+    if (v0 + kStep < T) batch_load(v0 + kStep, 1);
+    process(0);
+    if (v0 + kStep >= T) break;
+    if (v0 + 2 * kStep < T) batch_load(v0 + 2 * kStep, 0);
+    process(1);
   }
   __syncthreads();
   double sv[2] = {0.0, 0.0};
@@ -463,7 +457,7 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
       double fs = 0.0;
 #pragma unroll
       for (int ww = 0; ww < kMvWaves; ++ww) fs += ACC[ww * 3 * OC + d * nown + t];
-      const double vv = L[(3 + d) * SC + own0 + t];
+      const double vv = lds[6 * (own0 + t) + 3 + d];
       const double av = al > 0.0 ? vv / al - (fs + A.cself * vv) : 0.0;   // (A v)_s
       if (kMode == 1) {
         A.pnew[3 * s + d] = vv;

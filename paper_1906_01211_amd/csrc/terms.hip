@@ -12,29 +12,6 @@ namespace {
 
 }  // namespace
 
-// Per system: energy[3] = (total, non-excluded, exclusion correction) and the
-// virial from the 11 unit sums.
-__global__ void k_finish_energy3(int nsys, const double* __restrict__ sums, double* energy,
-                                 double* virial) {
-  const int sy = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sy >= nsys) return;
-  const double* sm = sums + 11 * sy;
-  energy[3 * sy] = sm[0] + sm[1];
-  energy[3 * sy + 1] = sm[0];
-  energy[3 * sy + 2] = sm[1];
-  for (int k = 0; k < 9; ++k) virial[9 * sy + k] = sm[2 + k];
-}
-
-// Per system: energy and virial from the 10 unit sums.
-__global__ void k_finish_energy1(int nsys, const double* __restrict__ sums, double* energy,
-                                 double* virial) {
-  const int sy = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sy >= nsys) return;
-  const double* sm = sums + 10 * sy;
-  energy[sy] = sm[0];
-  for (int k = 0; k < 9; ++k) virial[9 * sy + k] = sm[1 + k];
-}
-
 namespace {
 
 tk_status common_args(tk_ctx* ctx, const tk_system* sys, const tk_nblist* list, double cutoff,
@@ -63,7 +40,7 @@ tk_status launch_tmat(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_syste
   ph.molid = sys->molid;
   ph.perm_ = (const int32_t*)P.perm.p;
   EpiMutual epi{out, mu, polarity, ph.g.cself, include_diag};
-  return run_term(ctx, st, P, ph, epi, nullptr);
+  return run_term(ctx, st, P, ph, epi, nullptr, nullptr);
 }
 
 
@@ -82,8 +59,6 @@ tk_status tk_empole_real(tk_ctx* ctx, void* stream, const tk_system* sys, const 
   if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !energy || !virial) return TK_E_ARG;
   if (sys->n > 0 && (!mpole || !force)) return TK_E_ARG;
   hipStream_t st = (hipStream_t)stream;
-  void* sums;
-  if ((s = scratch(ctx, "sums", sizeof(double) * 32, &sums))) return s;
   if (sys->n == 0) {
     TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
     TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
@@ -93,17 +68,14 @@ tk_status tk_empole_real(tk_ctx* ctx, void* stream, const tk_system* sys, const 
     EmpolePh<double> ph;
     ph.xyz = sys->xyz; ph.mpole = mpole; ph.molid = sys->molid;
     ph.g.set(sys->box, cutoff, ewald_beta);
-    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
   } else {
     EmpolePh<float> ph;
     ph.xyz = sys->xyz; ph.mpole = mpole; ph.molid = sys->molid;
     ph.g.set(sys->box, cutoff, ewald_beta);
-    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
   }
-  if (s) return s;
-  k_finish_energy3<<<1, 64, 0, st>>>(1, (double*)sums, energy, virial);
-  TK_HIP(hipGetLastError());
-  return TK_OK;
+  return s;
 }
 
 tk_status tk_echarge_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
@@ -115,8 +87,6 @@ tk_status tk_echarge_real(tk_ctx* ctx, void* stream, const tk_system* sys, const
   if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !energy || !virial) return TK_E_ARG;
   if (sys->n > 0 && (!q || !force)) return TK_E_ARG;
   hipStream_t st = (hipStream_t)stream;
-  void* sums;
-  if ((s = scratch(ctx, "sums", sizeof(double) * 32, &sums))) return s;
   if (sys->n == 0) {
     TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
     TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
@@ -126,17 +96,14 @@ tk_status tk_echarge_real(tk_ctx* ctx, void* stream, const tk_system* sys, const
     ChargePh<double> ph;
     ph.xyz = sys->xyz; ph.q = q; ph.molid = sys->molid;
     ph.g.set(sys->box, cutoff, ewald_beta);
-    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
   } else {
     ChargePh<float> ph;
     ph.xyz = sys->xyz; ph.q = q; ph.molid = sys->molid;
     ph.g.set(sys->box, cutoff, ewald_beta);
-    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
   }
-  if (s) return s;
-  k_finish_energy3<<<1, 64, 0, st>>>(1, (double*)sums, energy, virial);
-  TK_HIP(hipGetLastError());
-  return TK_OK;
+  return s;
 }
 
 tk_status tk_efield_direct(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
@@ -186,8 +153,6 @@ tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nbli
     return TK_E_ARG;
   if (sys->n > 0 && (!radius_or_sigma || !eps || !force)) return TK_E_ARG;
   hipStream_t st = (hipStream_t)stream;
-  void* sums;
-  if ((s = scratch(ctx, "sums", sizeof(double) * 32, &sums))) return s;
   if (sys->n == 0) {
     TK_HIP(hipMemsetAsync(energy, 0, sizeof(double), st));
     TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
@@ -196,16 +161,13 @@ tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nbli
   if (prec == TK_FP64) {
     VdwPh<double> ph;
     ph.set(sys, form, radius_or_sigma, eps, cutoff, taper_on_frac, hal_delta, hal_gamma);
-    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
   } else {
     VdwPh<float> ph;
     ph.set(sys, form, radius_or_sigma, eps, cutoff, taper_on_frac, hal_delta, hal_gamma);
-    s = run_term(ctx, st, *P, ph, EpiForce{force}, (double*)sums);
+    s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
   }
-  if (s) return s;
-  k_finish_energy1<<<1, 64, 0, st>>>(1, (double*)sums, energy, virial);
-  TK_HIP(hipGetLastError());
-  return TK_OK;
+  return s;
 }
 
 }  // extern "C"

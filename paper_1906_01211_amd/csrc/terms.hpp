@@ -742,10 +742,12 @@ struct EpiMutual {   // mutual field (T + cI) mu, or A mu = mu/alpha - field
   }
 };
 
-// Launch one pair term over a plan: units -> per-atom reduce (Epi) -> scalars.
+// Launch one pair term over a plan: units -> per-atom reduce (Epi) ->
+// per-system energies and virial (terms with unit scalars; energy and virial
+// are device arrays of [nsys][NS - 9] and [nsys][9]).
 template <class Ph, class Epi>
 tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, const Epi& epi,
-                   double* sums_out) {
+                   double* energy, double* virial) {
   const long pstride = pad64(P.n);
   void *partial, *uscal;
   tk_status s;
@@ -765,13 +767,24 @@ tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, con
     ProfScope ps(ctx, st, std::string("units_") + Ph::kName + Ph::kTag);
     launch_units(P, phg, (double*)partial, pstride, (double*)uscal, st);
   }
+  const bool sums = Ph::NS > 0 && energy && virial;
+  const int nchunk = sums ? total_chunks(P) : 0;
+  void* cpart = nullptr;
+  if (sums && (s = scratch(ctx, "chunk_sums", sizeof(double) * (Ph::NS > 0 ? Ph::NS : 1) *
+                                                  (size_t)(nchunk > 0 ? nchunk : 1),
+                           &cpart)))
+    return s;
   {
     ProfScope ps(ctx, st, "reduce_atoms");
-    k_reduce<Ph::NA, Epi><<<ceil_div(P.n, 256), 256, 0, st>>>(pv, (double*)partial, pstride, epi);
+    const int nb = std::max(ceil_div((long)P.n * kRedLanes, 256), nchunk);
+    k_reduce<Ph::NA, Ph::NS, Epi><<<nb, 256, 0, st>>>(pv, (double*)partial, pstride, epi,
+                                                      sums ? (const double*)uscal : nullptr,
+                                                      (double*)cpart);
   }
-  if (Ph::NS > 0 && sums_out)
-    k_sum_units<(Ph::NS > 0 ? Ph::NS : 1)><<<dim3(Ph::NS > 0 ? Ph::NS : 1, P.nsys), 256, 0, st>>>(
-        (double*)uscal, pv.sys, sums_out);
+  if constexpr (Ph::NS > 0) {
+    if (sums)
+      k_sum_finish<Ph::NS><<<P.nsys, 64, 0, st>>>((const double*)cpart, pv.sys, energy, virial);
+  }
   TK_HIP(hipGetLastError());
   return TK_OK;
 }
@@ -791,7 +804,7 @@ inline tk_status launch_efield(tk_ctx* ctx, hipStream_t st, const Plan& P, const
   ph.thole = thole;
   ph.g.set(sys->box, cutoff, beta);
   EpiPermField e2{out, mpole, ph.g.cself, sorted_out};
-  return run_term(ctx, st, P, ph, e2, nullptr);
+  return run_term(ctx, st, P, ph, e2, nullptr, nullptr);
 }
 
 }  // namespace tk

@@ -109,7 +109,7 @@ struct Plan {
   const int32_t* cu_p = nullptr;
   const int32_t* order_p = nullptr;
   int32_t nsys = 1;
-  std::vector<SysDev> h_sys;           // host copy, with a final entry holding the totals
+  std::vector<SysDev> h_sys;           // host copy of sysd (as uploaded), with a final entry holding the totals
   DevBuf sysd, cell_sys, bunits, bnslot, bcu, border, tplp;
   PlanView view() const {
     PlanView v;
@@ -162,6 +162,7 @@ struct tk_ctx {
   void* pinned_dev = nullptr;                  // its device address
   size_t pinned_bytes = 0;
   int pcg_hint[tk::kNumPlans][2] = {};         // last solve's iteration count per plan slot, precision
+  bool nb_info_zero = false;                   // the list builder's status words are zero
 };
 
 namespace tk {
