@@ -147,15 +147,20 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T* total) {
 }
 
 template <class T>
-__global__ __launch_bounds__(kScanBlock) void k_scan_sums(const T* in, long len, T* bsum) {
-  __shared__ T sh[kScanBlock];
-  long base = (long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+__device__ __forceinline__ void scan_sums_body(const T* in, long len, T* bsum, int b, T* sh) {
+  long base = (long)b * kScanTile + threadIdx.x * kScanItems;
   T s = 0;
   for (int q = 0; q < kScanItems; ++q)
     if (base + q < len) s += in[base + q];
   T tot;
   block_exclusive_scan<T>(s, sh, &tot);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+  if (threadIdx.x == 0) bsum[b] = tot;
+}
+
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(const T* in, long len, T* bsum) {
+  __shared__ T sh[kScanBlock];
+  scan_sums_body<T>(in, len, bsum, blockIdx.x, sh);
 }
 
 template <class T>
@@ -264,14 +269,13 @@ __global__ __launch_bounds__(kScan1Threads) void k_scan1(const T* __restrict__ i
 // Final pass that finds its own carry: block b sums the tile totals of the
 // blocks before it (fixed order), so no separate pass over the totals.
 template <class T>
-__global__ __launch_bounds__(kScanBlock) void k_scan_final_carry(const T* in, long len,
-                                                                 const T* bsum, T* out) {
-  __shared__ T sh[kScanBlock];
+__device__ __forceinline__ void scan_final_carry_body(const T* in, long len, const T* bsum, T* out,
+                                                      int b, int nb, T* sh) {
   T c = 0;
-  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanBlock) c += bsum[b];
+  for (int k = threadIdx.x; k < b; k += kScanBlock) c += bsum[k];
   T ctot;
   block_exclusive_scan<T>(c, sh, &ctot);
-  long base = (long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  long base = (long)b * kScanTile + threadIdx.x * kScanItems;
   T v[kScanItems], s = 0;
   for (int q = 0; q < kScanItems; ++q) {
     v[q] = base + q < len ? in[base + q] : T(0);
@@ -283,7 +287,37 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final_carry(const T* in, lo
     if (base + q < len) out[base + q] = ex;
     ex += v[q];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[len] = ctot + tot;
+  if (b == nb - 1 && threadIdx.x == 0) out[len] = ctot + tot;
+}
+
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_final_carry(const T* in, long len,
+                                                                 const T* bsum, T* out) {
+  __shared__ T sh[kScanBlock];
+  scan_final_carry_body<T>(in, len, bsum, out, blockIdx.x, gridDim.x, sh);
+}
+
+// Two independent scans in the same two launches (blocks [0, nb1) scan the
+// first array, the rest the second).
+template <class T1, class T2>
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums2(const T1* in1, long len1, T1* bs1,
+                                                           int nb1, const T2* in2, long len2,
+                                                           T2* bs2) {
+  __shared__ T1 sh1[kScanBlock];
+  __shared__ T2 sh2[kScanBlock];
+  if ((int)blockIdx.x < nb1) scan_sums_body<T1>(in1, len1, bs1, blockIdx.x, sh1);
+  else scan_sums_body<T2>(in2, len2, bs2, blockIdx.x - nb1, sh2);
+}
+
+template <class T1, class T2>
+__global__ __launch_bounds__(kScanBlock) void k_scan_final2(const T1* in1, long len1, const T1* bs1,
+                                                            T1* out1, int nb1, const T2* in2,
+                                                            long len2, const T2* bs2, T2* out2) {
+  __shared__ T1 sh1[kScanBlock];
+  __shared__ T2 sh2[kScanBlock];
+  const int nb2 = gridDim.x - nb1;
+  if ((int)blockIdx.x < nb1) scan_final_carry_body<T1>(in1, len1, bs1, out1, blockIdx.x, nb1, sh1);
+  else scan_final_carry_body<T2>(in2, len2, bs2, out2, blockIdx.x - nb1, nb2, sh2);
 }
 
 template <class T>
@@ -320,6 +354,27 @@ tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out,
 
 tk_status scan_i64(tk_ctx* ctx, hipStream_t st, const int64_t* in, int64_t* out, long len) {
   return scan_t<int64_t>(ctx, st, in, out, len, "scan_bsum64");
+}
+
+tk_status scan_pair(tk_ctx* ctx, hipStream_t st, const int32_t* in1, int32_t* out1, int len1,
+                    const int64_t* in2, int64_t* out2, long len2) {
+  const int nb1 = ceil_div(len1 > 0 ? len1 : 1, kScanTile);
+  const int nb2 = ceil_div(len2 > 0 ? len2 : 1, kScanTile);
+  if (nb1 > kScan2MaxBlocks || nb2 > kScan2MaxBlocks) {
+    tk_status s = scan_i32(ctx, st, in1, out1, len1);
+    return s ? s : scan_i64(ctx, st, in2, out2, len2);
+  }
+  void *b1, *b2;
+  tk_status s;
+  if ((s = scratch(ctx, "scan_bsum32", sizeof(int32_t) * (nb1 + 1), &b1)) ||
+      (s = scratch(ctx, "scan_bsum64", sizeof(int64_t) * (nb2 + 1), &b2)))
+    return s;
+  k_scan_sums2<int32_t, int64_t><<<nb1 + nb2, kScanBlock, 0, st>>>(in1, len1, (int32_t*)b1, nb1,
+                                                                   in2, len2, (int64_t*)b2);
+  k_scan_final2<int32_t, int64_t><<<nb1 + nb2, kScanBlock, 0, st>>>(
+      in1, len1, (const int32_t*)b1, out1, nb1, in2, len2, (const int64_t*)b2, out2);
+  TK_HIP(hipGetLastError());
+  return TK_OK;
 }
 
 static hipEvent_t take_event(tk_ctx* ctx) {

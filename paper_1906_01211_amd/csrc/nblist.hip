@@ -956,12 +956,14 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
             (long)(wb.bytes / 4), (uint32_t*)windows, (int32_t*)P.unit_cnt.p, (int64_t*)cnt64,
             (int32_t*)regcnt, (int2*)nfilt, (int32_t*)P.slots.p, (int32_t*)info, occ_cap);
       }
-      k_row_slots<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)P.perm.p, (int32_t*)P.scell.p,
-                                                     nslot, pstride, (int32_t*)P.slots.p,
-                                                     (int32_t*)rcnt, (int32_t*)info);
-      if ((s = scan_i32(ctx, st, (int32_t*)rcnt, rp, n))) return s;
-      // dense code offsets (and the unit-based pair total for the readback)
-      if ((s = scan_i64(ctx, st, (int64_t*)cnt64, (int64_t*)P.unit_off.p, nunits))) return s;
+      k_row_slots<<<ceil_div(n, 256), 256, 0, st>>>(
+          n, (int32_t*)P.perm.p, (int32_t*)P.scell.p, nslot, pstride, (int32_t*)P.slots.p,
+          (int32_t*)rcnt, (int32_t*)info);
+      // row pointers, and the dense code offsets (with the unit-based pair
+      // total for the readback)
+      if ((s = scan_pair(ctx, st, (int32_t*)rcnt, rp, n, (int64_t*)cnt64, (int64_t*)P.unit_off.p,
+                         nunits)))
+        return s;
     } else {
       TK_HIP(hipMemsetAsync(P.unit_cnt.p, 0, sizeof(int32_t) * nunits, st));
       TK_HIP(hipMemsetAsync(P.unit_off.p, 0, sizeof(int64_t) * (nunits + 1), st));

@@ -812,19 +812,13 @@ struct Solver {
     return ph;
   }
 
-  // Static per-atom fields of the mat-vec, gathered once per solve: the
-  // coordinates; for the mixed form also the damping fields of the
-  // on-the-fly FP64 mat-vec (the first three fields coincide).
+  // Static per-atom fields of the mixed form's mat-vecs, gathered once per
+  // solve: the coordinates and the damping fields of the on-the-fly FP64
+  // mat-vec.  (The FP64 form reuses the coordinates that the permanent-field
+  // pass gathered: fields 0-2 of its sorted SoA rows, same stride.)
   void gather_geometry() {
-    if (prec == TK_MIXED) {
-      TmatPh<double> ph = tmat64(nullptr);
-      k_gather<TmatPh<double>><<<ceil_div(P->n, 256), 256, 0, st>>>(pv, ph, gathered, pstride);
-    } else {
-      TmatCachedPh<double> ph;
-      ph.xyz = xyz;
-      k_gather<TmatCachedPh<double>><<<ceil_div(P->n, 256), 256, 0, st>>>(pv, ph, gathered,
-                                                                          pstride);
-    }
+    TmatPh<double> ph = tmat64(nullptr);
+    k_gather<TmatPh<double>><<<ceil_div(P->n, 256), 256, 0, st>>>(pv, ph, gathered, pstride);
   }
 
   // FP64 mat-vec of v on the fly into the partial slots (mixed form)
@@ -1010,7 +1004,10 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                       : launch_efield<float>(ctx, st, *P, &sys1, mpole, polarity, thole,
                                              ewald_beta, cutoff, S.b, 1, (float*)S.gc, S.gcs);
   if (s) return s;
-  S.gather_geometry();
+  if (prec == TK_FP64)   // the FP64 mat-vec reads only coordinates: the ones the field pass gathered
+    S.gathered = (double*)ctx->scratch["gathered"].p;
+  else
+    S.gather_geometry();
   k_cs_setup<<<xcd_grid(S.ncells), kCellThreads, 0, st>>>(S.pv, polarity, mu_guess, guess_on, S.b,
                                                           S.alpha_s, S.x, S.npart, S.hdr, S.ent);
   const int slot = (int)(P - ctx->plans);

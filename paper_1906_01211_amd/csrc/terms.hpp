@@ -518,60 +518,6 @@ struct TmatPh {
   }
 };
 
-// Mutual field from radial factors cached by the permanent-field pass
-// (EfieldPh::gc): per pair only the minimum-image vector is recomputed.
-// Fields: x y z | mu(3)
-template <class R>
-struct TmatCachedPh {
-  static constexpr int NF = 6, NA = 3, NS = 0, NG = 3;
-  static constexpr const char* kName = "tmatc";
-  static constexpr int kWaves = 4;   // waves per unit (pairs.hpp launch_units)
-  static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
-  const int* done = nullptr;   // solver flag (status; 0 while iterating)
-  int run_when_done = 0;       // 0: skip once the solver has finished; 1: skip until it has
-  __device__ bool skip() const { return done && ((*done != 0) != (run_when_done != 0)); }
-  __device__ void prologue(int, int) const {}
-  const R* gc = nullptr;
-  long gcs = 0;
-  double box, inv_box;
-  __device__ void set_sys(const SysDev& d, int) {
-    box = d.box;
-    inv_box = d.inv_box;
-  }
-  const double* xyz = nullptr;
-  const double* mu = nullptr;        // sorted order
-  const double* zdir = nullptr;      // stage p = z + beta * p when set
-  const double* beta_dir = nullptr;
-  const double* sorted = nullptr;
-  long gstride = 0;
-  __device__ void gather(int i, double* g) const {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) g[c] = xyz[3 * i + c];
-  }
-  __device__ void stage_dyn(double* L, int cap, int t, int s) const {
-    const double bd = zdir ? *beta_dir : 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      L[(3 + c) * cap + t] = zdir ? fma(bd, mu[3 * s + c], zdir[3 * s + c]) : mu[3 * s + c];
-  }
-  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
-                       double* AK, double*, long p) const {
-    const R g1 = gc[p], g2 = gc[gcs + p];
-    double dd[3];
-    image3(LH, LK, cap, a, b, box, inv_box, dd);
-    const R d[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
-    const R ui[3] = {R(LH[3 * cap + a]), R(LH[4 * cap + a]), R(LH[5 * cap + a])};
-    const R uj[3] = {R(LK[3 * cap + b]), R(LK[4 * cap + b]), R(LK[5 * cap + b])};
-    const R di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
-    const R dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
-    const R si = dj * g2, sj = di * g2;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      lds_add(&AH[c * cap + a], (double)(d[c] * si - uj[c] * g1));
-      lds_add(&AK[c * cap + b], (double)(d[c] * sj - ui[c] * g1));
-    }
-  }
-};
 
 // Halgren 14-7 / LJ 12-6 with the quintic taper.
 // Fields: x y z | radius (HAL R or LJ sigma) | sqrt(eps) | molid

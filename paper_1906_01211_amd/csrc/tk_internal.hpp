@@ -185,6 +185,9 @@ CellTables& cell_tables(tk_ctx* ctx, int nc);
 // Exclusive scan of int32 counts: out[0..len] with out[len] = total.
 tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len);
 tk_status scan_i64(tk_ctx* ctx, hipStream_t st, const int64_t* in, int64_t* out, long len);
+// Both exclusive scans (out[len] = total) in two launches.
+tk_status scan_pair(tk_ctx* ctx, hipStream_t st, const int32_t* in1, int32_t* out1, int len1,
+                    const int64_t* in2, int64_t* out2, long len2);
 
 // Systems of a plan (host arrays): atom0[nsys+1] offsets, box[nsys],
 // list cutoff[nsys].
