@@ -100,13 +100,21 @@ class AmoebaStep:
         self.thole = torch.as_tensor(w.thole, device=dev)
         self.rad = torch.as_tensor(w.vdw_rad, device=dev)
         self.eps = torch.as_tensor(w.vdw_eps, device=dev)
+        self.side = torch.cuda.Stream(device=dev)   # default priority
         self.info = None
 
     def __call__(self):
+        import torch
         c, s, p = self.ctx, self.s, self.prec
-        l7 = c.nblist(self.sys, s["rc_ewald"] + s["skin"], plan_slot=0)
-        l9 = c.nblist(self.sys, s["rc_vdw"] + s["skin"], plan_slot=1)
+        main = torch.cuda.current_stream(c.device)
+        # the two lists are built concurrently (the 9 A one on a second stream),
+        # with one host synchronisation; the second stream first waits for the
+        # previous step's use of its plan slot
+        self.side.wait_stream(main)
+        l7, l9 = c.nblists(self.sys, [s["rc_ewald"] + s["skin"], s["rc_vdw"] + s["skin"]],
+                           [0, 1], streams=[main, self.side])
         c.empole_real(self.sys, l7, self.mpole, s["beta"], s["rc_ewald"], prec=p)
+        main.wait_stream(self.side)   # the 9 A list is complete before the solver starts
         _, self.info = c.polarize_pcg(self.sys, l7, self.mpole, self.pol, self.thole, s["beta"],
                                       s["rc_ewald"], tol_debye=s["tol_debye"],
                                       maxiter=s["maxiter"], prec=p)

@@ -125,6 +125,25 @@ tk_status tk_nblist_build(tk_ctx* ctx, void* stream, const tk_system* sys, doubl
                           int64_t* npairs);
 
 /*
+ * Several neighbour lists of the same atoms (e.g. the Ewald and the vdW list
+ * of a step, section "Hotspots": both list builders are on the profile),
+ * 1 <= nlists <= 4.  List k is exactly what tk_nblist_build(ctx, streams[k],
+ * sys, cutoffs[k], plan_slots[k], row_ptrs[k], cols[k], caps[k], &npairs[k])
+ * gives; the builds share one host synchronisation per distinct stream, and
+ * builds on different streams run concurrently.  All arrays are host arrays of
+ * nlists entries; streams may be NULL (all lists on the default stream) and
+ * entries may repeat; row_ptrs/cols/caps may be NULL (plans only) or hold NULL
+ * entries.  The plan slots must be distinct.  On return each list's results
+ * (CSR and plan) are queued on its stream: work that uses list k on another
+ * stream must wait for streams[k].  Errors as tk_nblist_build; on an error the
+ * lists after the failing one are left empty.
+ */
+tk_status tk_nblist_build_multi(tk_ctx* ctx, int32_t nlists, void* const* streams,
+                                const tk_system* sys, const double* cutoffs,
+                                const int32_t* plan_slots, int32_t* const* row_ptrs,
+                                int32_t* const* cols, const int64_t* caps, int64_t* npairs);
+
+/*
  * Real-space Ewald permanent-multipole energy, forces and virial (the
  * multipolar permanent electrostatic routine of section "Hotspots").
  * mpole: device [n][10] = q, mu_x, mu_y, mu_z, Theta_xx, Theta_xy, Theta_xz,

@@ -80,12 +80,11 @@ extern "C" tk_status tk_batch_step(tk_ctx* ctx, void* stream, const tk_batch* b,
     c9[k] = r9[k] + p->skin;
   }
   hipStream_t st = (hipStream_t)stream;
-  int64_t np7 = 0, np9 = 0;
-  const PlanSpec s7{nsys, b->atom_off, b->box, c7.data()};
-  const PlanSpec s9{nsys, b->atom_off, b->box, c9.data()};
-  if ((s = build_plan(ctx, st, kBatchPlan7, n, b->xyz, s7, nullptr, nullptr, 0, &np7)) ||
-      (s = build_plan(ctx, st, kBatchPlan9, n, b->xyz, s9, nullptr, nullptr, 0, &np9)))
-    return s;
+  int64_t npairs[2] = {0, 0};
+  const PlanSpec specs[2] = {{nsys, b->atom_off, b->box, c7.data()},
+                             {nsys, b->atom_off, b->box, c9.data()}};
+  const int slots[2] = {kBatchPlan7, kBatchPlan9};
+  if ((s = build_plans(ctx, st, 2, slots, n, b->xyz, specs, npairs))) return s;
   const Plan& P7 = ctx->plans[kBatchPlan7];
   const Plan& P9 = ctx->plans[kBatchPlan9];
   // device outputs of the per-system scalars: e3 | w3 | e1 | w1, then vdW cutoffs

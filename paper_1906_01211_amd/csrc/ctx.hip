@@ -348,26 +348,31 @@ static tk_status scan_t(tk_ctx* ctx, hipStream_t st, const T* in, T* out, long l
   return TK_OK;
 }
 
-tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len) {
-  return scan_t<int32_t>(ctx, st, in, out, len, "scan_bsum32");
+static std::string scan_name(const char* base, int job) {
+  return job ? std::string(base) + "." + std::to_string(job) : std::string(base);
 }
 
-tk_status scan_i64(tk_ctx* ctx, hipStream_t st, const int64_t* in, int64_t* out, long len) {
-  return scan_t<int64_t>(ctx, st, in, out, len, "scan_bsum64");
+tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len, int job) {
+  return scan_t<int32_t>(ctx, st, in, out, len, scan_name("scan_bsum32", job).c_str());
+}
+
+tk_status scan_i64(tk_ctx* ctx, hipStream_t st, const int64_t* in, int64_t* out, long len,
+                   int job) {
+  return scan_t<int64_t>(ctx, st, in, out, len, scan_name("scan_bsum64", job).c_str());
 }
 
 tk_status scan_pair(tk_ctx* ctx, hipStream_t st, const int32_t* in1, int32_t* out1, int len1,
-                    const int64_t* in2, int64_t* out2, long len2) {
+                    const int64_t* in2, int64_t* out2, long len2, int job) {
   const int nb1 = ceil_div(len1 > 0 ? len1 : 1, kScanTile);
   const int nb2 = ceil_div(len2 > 0 ? len2 : 1, kScanTile);
   if (nb1 > kScan2MaxBlocks || nb2 > kScan2MaxBlocks) {
-    tk_status s = scan_i32(ctx, st, in1, out1, len1);
-    return s ? s : scan_i64(ctx, st, in2, out2, len2);
+    tk_status s = scan_i32(ctx, st, in1, out1, len1, job);
+    return s ? s : scan_i64(ctx, st, in2, out2, len2, job);
   }
   void *b1, *b2;
   tk_status s;
-  if ((s = scratch(ctx, "scan_bsum32", sizeof(int32_t) * (nb1 + 1), &b1)) ||
-      (s = scratch(ctx, "scan_bsum64", sizeof(int64_t) * (nb2 + 1), &b2)))
+  if ((s = scratch(ctx, scan_name("scan_bsum32", job).c_str(), sizeof(int32_t) * (nb1 + 1), &b1)) ||
+      (s = scratch(ctx, scan_name("scan_bsum64", job).c_str(), sizeof(int64_t) * (nb2 + 1), &b2)))
     return s;
   k_scan_sums2<int32_t, int64_t><<<nb1 + nb2, kScanBlock, 0, st>>>(in1, len1, (int32_t*)b1, nb1,
                                                                    in2, len2, (int64_t*)b2);

@@ -746,22 +746,68 @@ static tk_status upload_tables(CellTables& T) {
   return TK_OK;
 }
 
-tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double* xyz,
-                     const PlanSpec& spec, int32_t* row_ptr, int32_t* col, int64_t cap,
-                     int64_t* npairs_out) {
-  if (!npairs_out) return TK_E_ARG;
-  *npairs_out = 0;
-  const int nsys = spec.nsys;
-  if (nsys < 1 || slot < 0 || slot >= kNumPlans || cap < 0 || n < 0) return TK_E_ARG;
-  if (col && !row_ptr) return TK_E_ARG;
-  if (n > 0 && !xyz) return TK_E_ARG;
-  Plan& P = ctx->plans[slot];
-  P.valid = false;
-  // per-system cell grids and exact list tests
-  std::vector<SysDev> sd(nsys + 1);
-  std::vector<CellTables*> tabs(nsys);
-  int ncells = 0, nunits = 0;
-  double est = 16.0 * n + 65536.0;
+// One list build, split at its host synchronisation so that several builds
+// (on one or several streams) share it: begin() queues everything up to the
+// readback, finish() checks the readback (rerunning the enumeration in the
+// rare case that a bound was short), then queues the compaction and the CSR.
+// Each build of a group has its own scratch (names suffixed by its index) and
+// its own pinned readback and staging regions.
+constexpr int kMaxBuildJobs = 4;
+constexpr size_t kStageBase = 4096;   // pinned: [64 k, 64 k + 64) readback of build k; staging after
+
+struct BuildJob {
+  // request
+  int slot = 0, n = 0, job = 0;
+  const double* xyz = nullptr;
+  PlanSpec spec{};
+  int32_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  int64_t cap = 0;
+  int64_t* npairs_out = nullptr;
+  hipStream_t st = nullptr;
+  // state between the phases
+  Plan* P = nullptr;
+  std::vector<SysDev> sd;
+  std::vector<CellTables*> tabs;
+  int nsys = 0, ncells = 0, nunits = 0, occ_cap = 0, plan_waves = 1;
+  long pstride = 0;
+  double est = 0.0;
+  DevBuf* wb = nullptr;
+  void *u = nullptr, *cell = nullptr, *ccount = nullptr, *cursor = nullptr, *tmp = nullptr,
+       *info = nullptr, *cand = nullptr, *rcnt = nullptr, *rptr = nullptr, *woff = nullptr,
+       *cnt64 = nullptr, *regcnt = nullptr, *nfilt = nullptr;
+  int32_t *h = nullptr, *hd = nullptr, *rp = nullptr;
+  char *stage = nullptr;   // pinned staging of the system table (and batch template pointers)
+  const SysDev* sysd = nullptr;
+  const Unit* units = nullptr;
+  const int32_t *nslot = nullptr, *cu = nullptr, *order = nullptr, *cell_sys = nullptr;
+
+  std::string nm(const char* base) const {
+    return job ? std::string(base) + "." + std::to_string(job) : std::string(base);
+  }
+  size_t stage_bytes() const {   // 256-byte aligned
+    const size_t b = sizeof(SysDev) * (spec.nsys + 1) + sizeof(TplPtrs) * spec.nsys;
+    return (b + 255) / 256 * 256;
+  }
+};
+
+// Checks, per-system cell grids and the window estimate.
+static tk_status build_check(tk_ctx* ctx, BuildJob& J) {
+  if (!J.npairs_out) return TK_E_ARG;
+  *J.npairs_out = 0;
+  const PlanSpec& spec = J.spec;
+  const int nsys = spec.nsys, n = J.n;
+  if (nsys < 1 || J.slot < 0 || J.slot >= kNumPlans || J.cap < 0 || n < 0) return TK_E_ARG;
+  if (J.col && !J.row_ptr) return TK_E_ARG;
+  if (n > 0 && !J.xyz) return TK_E_ARG;
+  if (spec.atom0[0] != 0 || spec.atom0[nsys] != n) return TK_E_ARG;
+  J.P = &ctx->plans[J.slot];
+  J.P->valid = false;
+  J.nsys = nsys;
+  J.sd.assign(nsys + 1, SysDev{});
+  J.tabs.assign(nsys, nullptr);
+  J.ncells = J.nunits = 0;
+  J.est = 16.0 * n + 65536.0;
   tk_status s;
   for (int k = 0; k < nsys; ++k) {
     const double box = spec.box[k], cut = spec.cutoff[k];
@@ -773,93 +819,137 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
     if (nc < 1) nc = 1;
     CellTables& T = cell_tables(ctx, nc);
     if ((s = upload_tables(T))) return s;
-    tabs[k] = &T;
+    J.tabs[k] = &T;
     const uint64_t rq = (uint64_t)std::floor((cut / box) * kTwo32);
-    SysDev& d = sd[k];
+    SysDev& d = J.sd[k];
     d.box = box;
     d.inv_box = 1.0 / box;
     d.rq2 = rq * rq;
     d.lo = (double)d.rq2 * (1.0 - 0x1p-50);
     d.hi = (double)d.rq2 * (1.0 + 0x1p-50);
     d.nc = nc;
-    d.cell0 = ncells;
-    d.unit0 = nunits;
+    d.cell0 = J.ncells;
+    d.unit0 = J.nunits;
     d.atom0 = spec.atom0[k];
-    ncells += T.ncells;
-    nunits += T.nunits;
+    J.ncells += T.ncells;
+    J.nunits += T.nunits;
     // candidate windows: sum over units of |H||K|, estimated from the density
     // (the buffer grows, and the enumeration reruns, if the estimate is short)
     const double mean = (double)na / T.ncells;
-    est += 1.15 * (double)T.nunits * mean * mean;
+    J.est += 1.15 * (double)T.nunits * mean * mean;
   }
-  if (spec.atom0[0] != 0 || spec.atom0[nsys] != n) return TK_E_ARG;
-  sd[nsys] = SysDev{};
-  sd[nsys].cell0 = ncells;
-  sd[nsys].unit0 = nunits;
-  sd[nsys].atom0 = n;
+  SysDev& t = J.sd[nsys];
+  t.cell0 = J.ncells;
+  t.unit0 = J.nunits;
+  t.atom0 = n;
+  return TK_OK;
+}
+
+// The enumeration and everything that depends on it up to the readback.
+static tk_status enqueue_enumeration(tk_ctx* ctx, BuildJob& J) {
+  Plan& P = *J.P;
+  const hipStream_t st = J.st;
+  const int n = J.n, nunits = J.nunits;
+  tk_status s;
+  const int32_t* cstart = (const int32_t*)P.cell_start.p;
+  if (n > 0) {
+    {
+      ProfScope ps(ctx, st, "nblist_plan");
+      const size_t plds = (2 * sizeof(uint4) + 4 * sizeof(int)) * (size_t)J.occ_cap;
+      k_plan<<<nunits, 64 * J.plan_waves, plds, st>>>(
+          nunits, J.units, cstart, (uint4*)P.us.p, J.sysd, J.cell_sys, J.pstride,
+          (int64_t*)J.woff, (long)(J.wb->bytes / 4), (uint32_t*)J.wb->p, (int32_t*)P.unit_cnt.p,
+          (int64_t*)J.cnt64, (int32_t*)J.regcnt, (int2*)J.nfilt, (int32_t*)P.slots.p,
+          (int32_t*)J.info, J.occ_cap);
+    }
+    k_row_slots<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)P.perm.p, (int32_t*)P.scell.p,
+                                                   J.nslot, J.pstride, (int32_t*)P.slots.p,
+                                                   (int32_t*)J.rcnt, (int32_t*)J.info);
+    // row pointers, and the dense code offsets (with the unit-based pair
+    // total for the readback)
+    if ((s = scan_pair(ctx, st, (int32_t*)J.rcnt, J.rp, n, (int64_t*)J.cnt64,
+                       (int64_t*)P.unit_off.p, nunits, J.job)))
+      return s;
+  } else {
+    TK_HIP(hipMemsetAsync(P.unit_cnt.p, 0, sizeof(int32_t) * nunits, st));
+    TK_HIP(hipMemsetAsync(P.unit_off.p, 0, sizeof(int64_t) * (nunits + 1), st));
+    TK_HIP(hipMemsetAsync(J.woff, 0, sizeof(int64_t) * (nunits + 1), st));
+    TK_HIP(hipMemsetAsync(J.rp, 0, sizeof(int32_t), st));
+  }
+  // one readback: status, max occupancy, max row, pairs, window overflow,
+  // max neighbourhood, list total
+  k_readback<<<1, 1, 0, st>>>((int32_t*)J.info, J.rp + n, (int64_t*)J.woff + nunits,
+                              (int64_t*)P.unit_off.p + nunits, J.hd);
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+// Everything up to the readback, queued on J.st (no synchronisation).
+// hb/hdb: the group's pinned buffer (host and device addresses).
+static tk_status build_begin(tk_ctx* ctx, BuildJob& J, char* hb, char* hdb) {
+  Plan& P = *J.P;
+  const hipStream_t st = J.st;
+  const int n = J.n, nsys = J.nsys, ncells = J.ncells, nunits = J.nunits;
+  const std::vector<SysDev>& sd = J.sd;
   const int nn = n > 0 ? n : 1;
-  const long pstride = (nn + 63) / 64 * 64;
-  const bool want_csr = row_ptr != nullptr;
+  J.pstride = (nn + 63) / 64 * 64;
+  tk_status s;
   if ((s = ensure(P.perm, sizeof(int32_t) * nn)) || (s = ensure(P.scell, sizeof(int32_t) * nn)) ||
       (s = ensure(P.cell_start, sizeof(int32_t) * (ncells + 1))) ||
       (s = ensure(P.unit_off, sizeof(int64_t) * (nunits + 1))) ||
       (s = ensure(P.unit_cnt, sizeof(int32_t) * nunits)) ||
       (s = ensure(P.us, sizeof(uint4) * nn)) ||
-      (s = ensure(P.slots, sizeof(int32_t) * kMaxSlots * pstride)))
+      (s = ensure(P.slots, sizeof(int32_t) * kMaxSlots * J.pstride)))
     return s;
   const void* sysd_was = P.sysd.p;
   if ((s = ensure(P.sysd, sizeof(SysDev) * (nsys + 1)))) return s;
-  // candidate windows: scratch shared by every build (the plan keeps the
-  // dense codes); grown to the exact size and rerun if the estimate is short
-  void* windows = nullptr;
-  DevBuf& wb = ctx->scratch["nb_windows"];
-  if (wb.bytes < sizeof(uint32_t) * (size_t)est && (s = ensure(wb, sizeof(uint32_t) * (size_t)est)))
+  // candidate windows: scratch of the build (the plan keeps the dense
+  // codes); grown to the exact size and rerun if the estimate is short
+  J.wb = &ctx->scratch[J.nm("nb_windows")];
+  if (J.wb->bytes < sizeof(uint32_t) * (size_t)J.est &&
+      (s = ensure(*J.wb, sizeof(uint32_t) * (size_t)J.est)))
     return s;
-  void *u, *cell, *ccount, *cursor, *tmp, *info, *cand, *rcnt, *rptr, *woff, *cnt64, *regcnt, *nfilt;
-  if ((s = scratch(ctx, "nb_u", sizeof(uint32_t) * 3 * nn, &u)) ||
-      (s = scratch(ctx, "nb_cell", sizeof(int32_t) * nn, &cell)) ||
-      (s = scratch(ctx, "nb_ccount", sizeof(int32_t) * (ncells + 1), &ccount)) ||
-      (s = scratch(ctx, "nb_cursor", sizeof(int32_t) * ncells, &cursor)) ||
-      (s = scratch(ctx, "nb_tmp", sizeof(int32_t) * nn, &tmp)) ||
-      (s = scratch(ctx, "nb_info", sizeof(int32_t) * 8, &info)) ||
-      (s = scratch(ctx, "nb_cand", sizeof(int64_t) * (nunits + 1), &cand)) ||
-      (s = scratch(ctx, "nb_woff", sizeof(int64_t) * (nunits + 1), &woff)) ||
-      (s = scratch(ctx, "nb_cnt64", sizeof(int64_t) * (nunits + 1), &cnt64)) ||
-      (s = scratch(ctx, "nb_rcnt", sizeof(int32_t) * (nn + 1), &rcnt)) ||
-      (s = scratch(ctx, "nb_rptr", sizeof(int32_t) * (nn + 1), &rptr)) ||
-      (s = scratch(ctx, "nb_regcnt", sizeof(int32_t) * kPlanRegions * (size_t)nunits, &regcnt)) ||
-      (s = scratch(ctx, "nb_nfilt", sizeof(int2) * (size_t)nunits, &nfilt)))
+  if ((s = scratch(ctx, J.nm("nb_u").c_str(), sizeof(uint32_t) * 3 * nn, &J.u)) ||
+      (s = scratch(ctx, J.nm("nb_cell").c_str(), sizeof(int32_t) * nn, &J.cell)) ||
+      (s = scratch(ctx, J.nm("nb_ccount").c_str(), sizeof(int32_t) * (ncells + 1), &J.ccount)) ||
+      (s = scratch(ctx, J.nm("nb_cursor").c_str(), sizeof(int32_t) * ncells, &J.cursor)) ||
+      (s = scratch(ctx, J.nm("nb_tmp").c_str(), sizeof(int32_t) * nn, &J.tmp)) ||
+      (s = scratch(ctx, J.nm("nb_info").c_str(), sizeof(int32_t) * 8, &J.info)) ||
+      (s = scratch(ctx, J.nm("nb_cand").c_str(), sizeof(int64_t) * (nunits + 1), &J.cand)) ||
+      (s = scratch(ctx, J.nm("nb_woff").c_str(), sizeof(int64_t) * (nunits + 1), &J.woff)) ||
+      (s = scratch(ctx, J.nm("nb_cnt64").c_str(), sizeof(int64_t) * (nunits + 1), &J.cnt64)) ||
+      (s = scratch(ctx, J.nm("nb_rcnt").c_str(), sizeof(int32_t) * (nn + 1), &J.rcnt)) ||
+      (s = scratch(ctx, J.nm("nb_rptr").c_str(), sizeof(int32_t) * (nn + 1), &J.rptr)) ||
+      (s = scratch(ctx, J.nm("nb_regcnt").c_str(), sizeof(int32_t) * kPlanRegions * (size_t)nunits,
+                   &J.regcnt)) ||
+      (s = scratch(ctx, J.nm("nb_nfilt").c_str(), sizeof(int2) * (size_t)nunits, &J.nfilt)))
     return s;
-  // pinned staging: [0, 4096) readback; then the system table
+  // pinned: this build's readback slot, then its staging region
+  J.h = (int32_t*)(hb + 64 * J.job);
+  J.hd = (int32_t*)(hdb + 64 * J.job);
+  char* stage = J.stage;
   const size_t sys_bytes = sizeof(SysDev) * (nsys + 1);
-  const size_t tpl_off = 4096 + sys_bytes;
-  const size_t stage_bytes = tpl_off + sizeof(TplPtrs) * nsys;
-  char *hb, *hdb;
-  if ((s = pinned(ctx, stage_bytes, (void**)&hb, (void**)&hdb))) return s;
-  int32_t* h = (int32_t*)hb;
-  int32_t* hd = (int32_t*)hdb;
-  // the previous build's readback of this context has been consumed (every
-  // build synchronises before returning), so the staging area is free.  The
-  // system table is uploaded only when it differs from the plan's copy.
+  // the previous readback and staging of this context have been consumed
+  // (every group synchronises before it returns).  The system table is
+  // uploaded only when it differs from the plan's copy.
   if (P.sysd.p != sysd_was || P.h_sys.size() != sd.size() ||
       std::memcmp(P.h_sys.data(), sd.data(), sys_bytes) != 0) {
-    std::memcpy(hb + 4096, sd.data(), sys_bytes);
-    TK_HIP(hipMemcpyAsync(P.sysd.p, hb + 4096, sys_bytes, hipMemcpyHostToDevice, st));
+    std::memcpy(stage, sd.data(), sys_bytes);
+    TK_HIP(hipMemcpyAsync(P.sysd.p, stage, sys_bytes, hipMemcpyHostToDevice, st));
     P.h_sys = sd;
   }
-  const SysDev* sysd = (const SysDev*)P.sysd.p;
-  const Unit* units;
-  const int32_t *nslot, *cu, *order, *cell_sys = nullptr;
+  J.sysd = (const SysDev*)P.sysd.p;
+  J.cell_sys = nullptr;
   if (nsys == 1) {
-    units = (const Unit*)tabs[0]->units_d.p;
-    nslot = (const int32_t*)tabs[0]->nslot_d.p;
-    cu = (const int32_t*)tabs[0]->cu_d.p;
-    order = (const int32_t*)tabs[0]->order_d.p;
+    J.units = (const Unit*)J.tabs[0]->units_d.p;
+    J.nslot = (const int32_t*)J.tabs[0]->nslot_d.p;
+    J.cu = (const int32_t*)J.tabs[0]->cu_d.p;
+    J.order = (const int32_t*)J.tabs[0]->order_d.p;
   } else {
-    TplPtrs* tp = (TplPtrs*)(hb + tpl_off);
+    TplPtrs* tp = (TplPtrs*)(stage + sys_bytes);
     for (int k = 0; k < nsys; ++k)
-      tp[k] = TplPtrs{(const Unit*)tabs[k]->units_d.p, (const int32_t*)tabs[k]->nslot_d.p,
-                      (const int32_t*)tabs[k]->cu_d.p, (const int32_t*)tabs[k]->order_d.p};
+      tp[k] = TplPtrs{(const Unit*)J.tabs[k]->units_d.p, (const int32_t*)J.tabs[k]->nslot_d.p,
+                      (const int32_t*)J.tabs[k]->cu_d.p, (const int32_t*)J.tabs[k]->order_d.p};
     if ((s = ensure(P.tplp, sizeof(TplPtrs) * nsys)) ||
         (s = ensure(P.bunits, sizeof(Unit) * nunits)) ||
         (s = ensure(P.bnslot, sizeof(int32_t) * ncells)) ||
@@ -868,132 +958,116 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
         (s = ensure(P.border, sizeof(int32_t) * ncells)))
       return s;
     TK_HIP(hipMemcpyAsync(P.tplp.p, tp, sizeof(TplPtrs) * nsys, hipMemcpyHostToDevice, st));
-    k_batch_units<<<ceil_div(nunits, 256), 256, 0, st>>>(nunits, nsys, sysd,
+    k_batch_units<<<ceil_div(nunits, 256), 256, 0, st>>>(nunits, nsys, J.sysd,
                                                          (const TplPtrs*)P.tplp.p,
                                                          (Unit*)P.bunits.p);
-    k_batch_cells<<<ceil_div(ncells, 256), 256, 0, st>>>(ncells, nsys, sysd,
+    k_batch_cells<<<ceil_div(ncells, 256), 256, 0, st>>>(ncells, nsys, J.sysd,
                                                          (const TplPtrs*)P.tplp.p,
                                                          (int32_t*)P.bnslot.p, (int32_t*)P.bcu.p,
                                                          (int32_t*)P.cell_sys.p,
                                                          (int32_t*)P.border.p);
-    units = (const Unit*)P.bunits.p;
-    nslot = (const int32_t*)P.bnslot.p;
-    cu = (const int32_t*)P.bcu.p;
-    order = (const int32_t*)P.border.p;
-    cell_sys = (const int32_t*)P.cell_sys.p;
+    J.units = (const Unit*)P.bunits.p;
+    J.nslot = (const int32_t*)P.bnslot.p;
+    J.cu = (const int32_t*)P.bcu.p;
+    J.order = (const int32_t*)P.border.p;
+    J.cell_sys = (const int32_t*)P.cell_sys.p;
   }
   // status words: zero after every completed build (the readback clears them)
-  if (!ctx->nb_info_zero) TK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * 8, st));
-  ctx->nb_info_zero = false;
+  if (!ctx->nb_info_zero[J.job]) TK_HIP(hipMemsetAsync(J.info, 0, sizeof(int32_t) * 8, st));
+  ctx->nb_info_zero[J.job] = false;
   const int32_t* cstart = (const int32_t*)P.cell_start.p;
-  int32_t* rp = want_csr ? row_ptr : (int32_t*)rptr;
+  J.rp = J.row_ptr ? J.row_ptr : (int32_t*)J.rptr;
+  int32_t* info = (int32_t*)J.info;
   if (n > 0 && ncells <= kMaxHistCells) {
     const int nblk = ceil_div(n, kHistBlock);
     const long hl = (long)ncells * nblk;
     void *H, *Hoff;
-    if ((s = scratch(ctx, "nb_hist", sizeof(int32_t) * hl, &H)) ||
-        (s = scratch(ctx, "nb_hist_off", sizeof(int32_t) * (hl + 1), &Hoff)))
+    if ((s = scratch(ctx, J.nm("nb_hist").c_str(), sizeof(int32_t) * hl, &H)) ||
+        (s = scratch(ctx, J.nm("nb_hist_off").c_str(), sizeof(int32_t) * (hl + 1), &Hoff)))
       return s;
     {
       ProfScope ps(ctx, st, "nblist_quantize");
-      k_quantize_hist<<<nblk, kHistBlock, 0, st>>>(n, xyz, sysd, nsys, ncells, (uint32_t*)u,
-                                                    (int32_t*)cell, (int32_t*)H, (int32_t*)info);
+      k_quantize_hist<<<nblk, kHistBlock, 0, st>>>(n, J.xyz, J.sysd, nsys, ncells,
+                                                    (uint32_t*)J.u, (int32_t*)J.cell,
+                                                    (int32_t*)H, info);
     }
-    if ((s = scan_i32(ctx, st, (int32_t*)H, (int32_t*)Hoff, (int)hl))) return s;
+    if ((s = scan_i32(ctx, st, (int32_t*)H, (int32_t*)Hoff, (int)hl, J.job))) return s;
     {
       ProfScope ps(ctx, st, "nblist_cellsort");
-      k_scatter_stable<<<nblk, kHistBlock, 0, st>>>(n, ncells, (int32_t*)cell, (int32_t*)Hoff,
-                                                     (uint32_t*)u, (int32_t*)P.perm.p,
+      k_scatter_stable<<<nblk, kHistBlock, 0, st>>>(n, ncells, (int32_t*)J.cell, (int32_t*)Hoff,
+                                                     (uint32_t*)J.u, (int32_t*)P.perm.p,
                                                      (int32_t*)P.scell.p, (uint4*)P.us.p,
-                                                     (int32_t*)P.cell_start.p, (int32_t*)info);
+                                                     (int32_t*)P.cell_start.p, info);
     }
   } else if (n > 0) {
-    TK_HIP(hipMemsetAsync(ccount, 0, sizeof(int32_t) * (ncells + 1), st));
-    TK_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * ncells, st));
+    TK_HIP(hipMemsetAsync(J.ccount, 0, sizeof(int32_t) * (ncells + 1), st));
+    TK_HIP(hipMemsetAsync(J.cursor, 0, sizeof(int32_t) * ncells, st));
     {
       ProfScope ps(ctx, st, "nblist_quantize");
-      k_quantize<<<ceil_div(n, 256), 256, 0, st>>>(n, xyz, sysd, nsys, (uint32_t*)u,
-                                                    (int32_t*)cell, (int32_t*)ccount,
-                                                    (int32_t*)info);
+      k_quantize<<<ceil_div(n, 256), 256, 0, st>>>(n, J.xyz, J.sysd, nsys, (uint32_t*)J.u,
+                                                    (int32_t*)J.cell, (int32_t*)J.ccount, info);
     }
-    if ((s = scan_i32(ctx, st, (int32_t*)ccount, (int32_t*)P.cell_start.p, ncells))) return s;
-    k_scatter<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)cell, cstart, (int32_t*)cursor,
-                                                 (int32_t*)tmp);
+    if ((s = scan_i32(ctx, st, (int32_t*)J.ccount, (int32_t*)P.cell_start.p, ncells, J.job)))
+      return s;
+    k_scatter<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)J.cell, cstart, (int32_t*)J.cursor,
+                                                 (int32_t*)J.tmp);
     {
       ProfScope ps(ctx, st, "nblist_cellsort");
-      k_cellsort<<<ncells, 64, 0, st>>>(cstart, (int32_t*)tmp, (uint32_t*)u, (int32_t*)P.perm.p,
-                                        (int32_t*)P.scell.p, (uint4*)P.us.p, (int32_t*)info);
+      k_cellsort<<<ncells, 64, 0, st>>>(cstart, (int32_t*)J.tmp, (uint32_t*)J.u,
+                                        (int32_t*)P.perm.p, (int32_t*)P.scell.p, (uint4*)P.us.p,
+                                        info);
     }
   } else {
     TK_HIP(hipMemsetAsync(P.cell_start.p, 0, sizeof(int32_t) * (ncells + 1), st));
   }
   if (n > 0) {
     const int nbu = ceil_div(nunits, 256);
-    k_cand_nbhd<<<nbu + ceil_div(ncells, 4), 256, 0, st>>>(nunits, ncells, nbu, cu, units, cstart,
-                                                         (int64_t*)cand, (int32_t*)info);
-    if ((s = scan_i64(ctx, st, (int64_t*)cand, (int64_t*)woff, nunits))) return s;
+    k_cand_nbhd<<<nbu + ceil_div(ncells, 4), 256, 0, st>>>(nunits, ncells, nbu, J.cu, J.units,
+                                                         cstart, (int64_t*)J.cand, info);
+    if ((s = scan_i64(ctx, st, (int64_t*)J.cand, (int64_t*)J.woff, nunits, J.job))) return s;
   }
   // staging bound of k_plan: three times the largest mean cell occupancy
   // (at least 64); a denser cell makes the build rerun with kMaxCellAtoms
   double max_mean = 0.0;
   for (int k = 0; k < nsys; ++k) {
     const int cells = sd[k + 1].cell0 - sd[k].cell0;
-    max_mean = std::fmax(max_mean, (double)(spec.atom0[k + 1] - spec.atom0[k]) / cells);
+    max_mean = std::fmax(max_mean, (double)(J.spec.atom0[k + 1] - J.spec.atom0[k]) / cells);
   }
   int occ_cap = (int)std::ceil(3.0 * max_mean);
+  J.occ_cap = occ_cap < 64 ? 64 : occ_cap > kMaxCellAtoms ? kMaxCellAtoms : occ_cap;
   // waves per unit of the enumeration: more for larger cells
-  const int plan_waves = max_mean > 96.0 ? 4 : max_mean > 48.0 ? 2 : 1;
-  occ_cap = occ_cap < 64 ? 64 : occ_cap > kMaxCellAtoms ? kMaxCellAtoms : occ_cap;
-  int first_occ = 0, first_nbhd = 0;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    if (n > 0) {
-      {
-        ProfScope ps(ctx, st, "nblist_plan");
-        windows = wb.p;
-        const size_t plds = (2 * sizeof(uint4) + 4 * sizeof(int)) * (size_t)occ_cap;
-        k_plan<<<nunits, 64 * plan_waves, plds, st>>>(
-            nunits, units, cstart, (uint4*)P.us.p, sysd, cell_sys, pstride, (int64_t*)woff,
-            (long)(wb.bytes / 4), (uint32_t*)windows, (int32_t*)P.unit_cnt.p, (int64_t*)cnt64,
-            (int32_t*)regcnt, (int2*)nfilt, (int32_t*)P.slots.p, (int32_t*)info, occ_cap);
-      }
-      k_row_slots<<<ceil_div(n, 256), 256, 0, st>>>(
-          n, (int32_t*)P.perm.p, (int32_t*)P.scell.p, nslot, pstride, (int32_t*)P.slots.p,
-          (int32_t*)rcnt, (int32_t*)info);
-      // row pointers, and the dense code offsets (with the unit-based pair
-      // total for the readback)
-      if ((s = scan_pair(ctx, st, (int32_t*)rcnt, rp, n, (int64_t*)cnt64, (int64_t*)P.unit_off.p,
-                         nunits)))
-        return s;
-    } else {
-      TK_HIP(hipMemsetAsync(P.unit_cnt.p, 0, sizeof(int32_t) * nunits, st));
-      TK_HIP(hipMemsetAsync(P.unit_off.p, 0, sizeof(int64_t) * (nunits + 1), st));
-      TK_HIP(hipMemsetAsync(woff, 0, sizeof(int64_t) * (nunits + 1), st));
-      TK_HIP(hipMemsetAsync(rp, 0, sizeof(int32_t), st));
-    }
-    // one readback: status, max occupancy, max row, pairs, window overflow,
-    // max neighbourhood, list total
-    k_readback<<<1, 1, 0, st>>>((int32_t*)info, rp + n, (int64_t*)woff + nunits,
-                                (int64_t*)P.unit_off.p + nunits, hd);
-    TK_HIP(hipGetLastError());
-    TK_HIP(hipStreamSynchronize(st));
-    ctx->nb_info_zero = true;
-    if (attempt == 1) {   // the rerun did not repeat the cell sort or the neighbourhood sizes
-      h[1] = first_occ;
-      h[5] = first_nbhd;
-    }
-    if (h[0] != 0) return h[0];
-    if (h[4] == 0) break;
-    if (attempt == 1) return TK_E_HIP;
-    // windows or staging bound did not fit: exact sizes, enumerate again
-    first_occ = h[1];
-    first_nbhd = h[5];
+  J.plan_waves = max_mean > 96.0 ? 4 : max_mean > 48.0 ? 2 : 1;
+  return enqueue_enumeration(ctx, J);
+}
+
+// After the stream has reached the readback: checks (and the rare rerun),
+// then the compaction and the CSR, queued (no further synchronisation).
+static tk_status build_finish(tk_ctx* ctx, BuildJob& J) {
+  Plan& P = *J.P;
+  const hipStream_t st = J.st;
+  const int n = J.n, nunits = J.nunits;
+  int32_t* h = J.h;
+  tk_status s;
+  ctx->nb_info_zero[J.job] = true;
+  if (h[0] != 0) return h[0];
+  if (h[4] != 0) {
+    // windows or staging bound did not fit: exact sizes, enumerate again (the
+    // rerun repeats neither the cell sort nor the neighbourhood sizes)
+    const int first_occ = h[1], first_nbhd = h[5];
     const int64_t need = *(int64_t*)(h + 8);
-    if ((s = ensure(wb, sizeof(uint32_t) * (size_t)need))) return s;
-    occ_cap = kMaxCellAtoms;
-    ctx->nb_info_zero = false;
+    if ((s = ensure(*J.wb, sizeof(uint32_t) * (size_t)need))) return s;
+    J.occ_cap = kMaxCellAtoms;
+    ctx->nb_info_zero[J.job] = false;
+    if ((s = enqueue_enumeration(ctx, J))) return s;
+    TK_HIP(hipStreamSynchronize(st));
+    ctx->nb_info_zero[J.job] = true;
+    h[1] = first_occ;
+    h[5] = first_nbhd;
+    if (h[0] != 0) return h[0];
+    if (h[4] != 0) return TK_E_HIP;
   }
   const int64_t list_pairs = h[6];
-  *npairs_out = list_pairs;
+  *J.npairs_out = list_pairs;
   if (list_pairs != (int64_t)h[3]) {
     std::fprintf(stderr, "libtk: plan/list pair count mismatch %d vs %d\n", h[3], h[6]);
     return TK_E_HIP;
@@ -1003,12 +1077,13 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
   if ((s = ensure(P.codes, sizeof(uint32_t) * (size_t)(list_pairs > 0 ? list_pairs : 1)))) return s;
   if (n > 0) {
     ProfScope ps(ctx, st, "nblist_compact");
-    k_compact<<<nunits, 256, 0, st>>>((const int64_t*)woff, (const uint32_t*)windows,
-                                     (const int64_t*)P.unit_off.p, (const int32_t*)regcnt,
-                                     (const int2*)nfilt, plan_waves, (uint32_t*)P.codes.p);
+    k_compact<<<nunits, 256, 0, st>>>((const int64_t*)J.woff, (const uint32_t*)J.wb->p,
+                                     (const int64_t*)P.unit_off.p, (const int32_t*)J.regcnt,
+                                     (const int2*)J.nfilt, J.plan_waves, (uint32_t*)P.codes.p);
   }
-  if (want_csr) {
-    if (list_pairs > cap) return TK_E_CAPACITY;
+  const int32_t* cstart = (const int32_t*)P.cell_start.p;
+  if (J.row_ptr) {
+    if (list_pairs > J.cap) return TK_E_CAPACITY;
     const int nb = max_row < kBuckets ? max_row : kBuckets;
     const size_t lds1 = sizeof(int) * (2 * (size_t)max_row + 2 * (size_t)nb);
     if (lds1 > kMaxLds) return TK_E_CAPACITY;
@@ -1021,33 +1096,104 @@ tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double*
         ProfScope ps(ctx, st, "nblist_csr_fill");
         const int occ = h[1] > 0 ? h[1] : 1;
         k_csr_fill<<<nunits, 256, sizeof(int) * 6 * (size_t)occ, st>>>(
-            units, cstart, (int32_t*)P.perm.p, pstride, (int64_t*)P.unit_off.p,
-            (int32_t*)P.unit_cnt.p, (uint32_t*)P.codes.p, (int32_t*)P.slots.p, rp, col, occ);
+            J.units, cstart, (int32_t*)P.perm.p, J.pstride, (int64_t*)P.unit_off.p,
+            (int32_t*)P.unit_cnt.p, (uint32_t*)P.codes.p, (int32_t*)P.slots.p, J.rp, J.col, occ);
       }
       {
         ProfScope ps(ctx, st, "nblist_rowsort");
-        k_rowsort<<<ceil_div(n, rpb), 64 * rpb, lds, st>>>(n, rp, col, max_row);
+        k_rowsort<<<ceil_div(n, rpb), 64 * rpb, lds, st>>>(n, J.rp, J.col, max_row);
       }
     }
   }
   TK_HIP(hipGetLastError());
   P.valid = true;
   P.n = n;
-  P.nsys = nsys;
-  P.box = spec.box[0];
-  P.cutoff = spec.cutoff[0];
-  P.nc = sd[0].nc;
-  P.ncells = ncells;
+  P.nsys = J.nsys;
+  P.box = J.spec.box[0];
+  P.cutoff = J.spec.cutoff[0];
+  P.nc = J.sd[0].nc;
+  P.ncells = J.ncells;
   P.nunits = nunits;
   P.max_occ = h[1];
   P.max_row = max_row;
   P.max_nbhd = h[5];
   P.npairs = list_pairs;
-  P.units_p = units;
-  P.nslot_p = nslot;
-  P.cu_p = cu;
-  P.order_p = order;
+  P.units_p = J.units;
+  P.nslot_p = J.nslot;
+  P.cu_p = J.cu;
+  P.order_p = J.order;
   return TK_OK;
+}
+
+// A group of builds sharing one host synchronisation per distinct stream.
+static tk_status build_group(tk_ctx* ctx, BuildJob* jobs, int nj) {
+  if (nj < 1 || nj > kMaxBuildJobs) return TK_E_ARG;
+  tk_status s;
+  for (int k = 0; k < nj; ++k) {
+    jobs[k].job = k;
+    for (int m = 0; m < k; ++m)   // two builds of a group may not share a plan slot
+      if (jobs[m].slot == jobs[k].slot) return TK_E_ARG;
+    if ((s = build_check(ctx, jobs[k]))) return s;
+  }
+  // pinned buffer for the whole group, taken before anything is queued
+  size_t bytes = kStageBase;
+  for (int k = 0; k < nj; ++k) bytes += jobs[k].stage_bytes();
+  char *hb, *hdb;
+  if ((s = pinned(ctx, bytes, (void**)&hb, (void**)&hdb))) return s;
+  size_t off = kStageBase;
+  for (int k = 0; k < nj; ++k) {
+    jobs[k].stage = hb + off;
+    off += jobs[k].stage_bytes();
+  }
+  // queue every build; on a failure the builds already queued are waited for
+  // (they write the pinned buffer) before the error is returned
+  int queued = 0;
+  for (; queued < nj; ++queued)
+    if ((s = build_begin(ctx, jobs[queued], hb, hdb))) break;
+  const int nsync = s ? queued : nj;
+  for (int k = 0; k < nsync + (s && queued < nj ? 1 : 0); ++k) {
+    bool seen = false;
+    for (int m = 0; m < k; ++m) seen |= jobs[m].st == jobs[k].st;
+    if (!seen) {
+      const hipError_t e = hipStreamSynchronize(jobs[k].st);
+      if (!s && e != hipSuccess) return hip_status(e, "hipStreamSynchronize");
+    }
+  }
+  if (s) return s;
+  for (int k = 0; k < nj; ++k)
+    if ((s = build_finish(ctx, jobs[k]))) return s;
+  return TK_OK;
+}
+
+tk_status build_plans(tk_ctx* ctx, hipStream_t st, int nj, const int* slots, int n,
+                      const double* xyz, const PlanSpec* specs, int64_t* npairs_out) {
+  if (nj < 1 || nj > kMaxBuildJobs) return TK_E_ARG;
+  BuildJob J[kMaxBuildJobs];
+  for (int k = 0; k < nj; ++k) {
+    J[k].slot = slots[k];
+    J[k].n = n;
+    J[k].xyz = xyz;
+    J[k].spec = specs[k];
+    J[k].npairs_out = &npairs_out[k];
+    J[k].st = st;
+  }
+  return build_group(ctx, J, nj);
+}
+
+tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double* xyz,
+                     const PlanSpec& spec, int32_t* row_ptr, int32_t* col, int64_t cap,
+                     int64_t* npairs_out) {
+  BuildJob J;
+  J.slot = slot;
+  J.n = n;
+  J.xyz = xyz;
+  J.spec = spec;
+  J.row_ptr = row_ptr;
+  J.col = col;
+  J.cap = cap;
+  J.npairs_out = npairs_out;
+  J.st = st;
+  return build_group(ctx, &J, 1);
 }
 
 static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
@@ -1064,6 +1210,33 @@ static tk_status nblist_build_impl(tk_ctx* ctx, hipStream_t st, const tk_system*
   return build_plan(ctx, st, slot, sys->n, sys->xyz, spec, row_ptr, col, cap, npairs_out);
 }
 
+static tk_status nblist_build_multi_impl(tk_ctx* ctx, int nl, void* const* streams,
+                                         const tk_system* sys, const double* cutoffs,
+                                         const int32_t* slots, int32_t* const* row_ptrs,
+                                         int32_t* const* cols, const int64_t* caps,
+                                         int64_t* npairs) {
+  if (nl < 1 || nl > kMaxBuildJobs || !cutoffs || !slots || !npairs) return TK_E_ARG;
+  for (int k = 0; k < nl; ++k) npairs[k] = 0;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  const int32_t atom0[2] = {0, sys->n};
+  BuildJob J[kMaxBuildJobs];
+  for (int k = 0; k < nl; ++k) {
+    if (!(cutoffs[k] > 0.0) || !std::isfinite(cutoffs[k])) return TK_E_ARG;
+    if (slots[k] < 0 || slots[k] >= TK_MAX_PLANS) return TK_E_ARG;
+    J[k].slot = slots[k];
+    J[k].n = sys->n;
+    J[k].xyz = sys->xyz;
+    J[k].spec = PlanSpec{1, atom0, &sys->box, &cutoffs[k]};
+    J[k].row_ptr = row_ptrs ? row_ptrs[k] : nullptr;
+    J[k].col = cols ? cols[k] : nullptr;
+    J[k].cap = caps ? caps[k] : 0;
+    J[k].npairs_out = &npairs[k];
+    J[k].st = streams ? (hipStream_t)streams[k] : nullptr;
+  }
+  return build_group(ctx, J, nl);
+}
+
 }  // namespace tk
 
 extern "C" tk_status tk_nblist_build(tk_ctx* ctx, void* stream, const tk_system* sys, double cutoff,
@@ -1072,4 +1245,14 @@ extern "C" tk_status tk_nblist_build(tk_ctx* ctx, void* stream, const tk_system*
   if (!ctx) return TK_E_ARG;
   return tk::nblist_build_impl(ctx, (hipStream_t)stream, sys, cutoff, plan_slot, row_ptr, col, cap,
                                npairs);
+}
+
+extern "C" tk_status tk_nblist_build_multi(tk_ctx* ctx, int32_t nlists, void* const* streams,
+                                           const tk_system* sys, const double* cutoffs,
+                                           const int32_t* plan_slots, int32_t* const* row_ptrs,
+                                           int32_t* const* cols, const int64_t* caps,
+                                           int64_t* npairs) {
+  if (!ctx) return TK_E_ARG;
+  return tk::nblist_build_multi_impl(ctx, nlists, streams, sys, cutoffs, plan_slots, row_ptrs,
+                                     cols, caps, npairs);
 }

@@ -162,7 +162,7 @@ struct tk_ctx {
   void* pinned_dev = nullptr;                  // its device address
   size_t pinned_bytes = 0;
   int pcg_hint[tk::kNumPlans][2] = {};         // last solve's iteration count per plan slot, precision
-  bool nb_info_zero = false;                   // the list builder's status words are zero
+  bool nb_info_zero[4] = {};                   // per build of a group: its status words are zero
 };
 
 namespace tk {
@@ -183,11 +183,14 @@ tk_status pinned(tk_ctx* ctx, size_t bytes, void** out, void** dev = nullptr);
 CellTables& cell_tables(tk_ctx* ctx, int nc);
 
 // Exclusive scan of int32 counts: out[0..len] with out[len] = total.
-tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len);
-tk_status scan_i64(tk_ctx* ctx, hipStream_t st, const int64_t* in, int64_t* out, long len);
+// job: index of the list build in a group (separate scratch per build).
+tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len,
+                   int job = 0);
+tk_status scan_i64(tk_ctx* ctx, hipStream_t st, const int64_t* in, int64_t* out, long len,
+                   int job = 0);
 // Both exclusive scans (out[len] = total) in two launches.
 tk_status scan_pair(tk_ctx* ctx, hipStream_t st, const int32_t* in1, int32_t* out1, int len1,
-                    const int64_t* in2, int64_t* out2, long len2);
+                    const int64_t* in2, int64_t* out2, long len2, int job = 0);
 
 // Systems of a plan (host arrays): atom0[nsys+1] offsets, box[nsys],
 // list cutoff[nsys].
@@ -202,6 +205,10 @@ struct PlanSpec {
 tk_status build_plan(tk_ctx* ctx, hipStream_t st, int slot, int n, const double* xyz,
                      const PlanSpec& spec, int32_t* row_ptr, int32_t* col, int64_t cap,
                      int64_t* npairs_out);
+// Several plans of the same atoms (no CSR), queued on one stream with one
+// synchronisation.
+tk_status build_plans(tk_ctx* ctx, hipStream_t st, int nj, const int* slots, int n,
+                      const double* xyz, const PlanSpec* specs, int64_t* npairs_out);
 
 // Induced dipoles of every system of plan P (right-hand side, PCG, FP64 true
 // residual and, in the mixed form, refinement).  xyz, molid and the

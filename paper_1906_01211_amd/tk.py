@@ -89,6 +89,8 @@ _SIGS = {
     "tk_destroy": [_vp],
     "tk_strerror": [_i32],
     "tk_nblist_build": [_vp, _vp, C.POINTER(System), _d, _i32, _vp, _vp, _i64, C.POINTER(_i64)],
+    "tk_nblist_build_multi": [_vp, _i32, _vp, C.POINTER(System), _vp, _vp, _vp, _vp, _vp,
+                              C.POINTER(_i64)],
     "tk_empole_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _d, _d, C.c_int, _vp,
                        _vp, _vp],
     "tk_echarge_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _d, _d, C.c_int, _vp,
@@ -218,6 +220,42 @@ class Context:
         _check(st, "tk_nblist_build")
         return ListRef(row_ptr, None if col is None else col[: npairs.value], int(npairs.value),
                        float(cutoff), int(plan_slot))
+
+    def nblists(self, sysref, cutoffs, plan_slots, streams=None, want_csr=True):
+        """Several lists of the same atoms with one host synchronisation
+        (tk_nblist_build_multi).  streams: one torch stream per list (None: the
+        current stream for all); list k's outputs are ready in streams[k]'s
+        order."""
+        n, k = sysref.n, len(cutoffs)
+        cur = torch.cuda.current_stream(self.device)
+        strs = list(streams) if streams is not None else [cur] * k
+        rho = n / sysref.box ** 3
+        caps = [int(n * (2.0 * 3.141592653589793 / 3.0) * c ** 3 * rho * 1.3 + 4096)
+                for c in cutoffs]
+        while True:
+            rps = [torch.empty(n + 1, dtype=torch.int32, device=self.device) if want_csr else None
+                   for _ in range(k)]
+            cols = [torch.empty(max(c, 1), dtype=torch.int32, device=self.device) if want_csr
+                    else None for c in caps]
+            for t, st in zip(rps + cols, strs + strs):
+                if t is not None and st != cur:
+                    t.record_stream(st)   # written (and maybe read) on another stream
+            npairs = (C.c_int64 * k)()
+            arr_st = (C.c_void_p * k)(*[st.cuda_stream for st in strs])
+            arr_cut = (C.c_double * k)(*[float(c) for c in cutoffs])
+            arr_slot = (C.c_int32 * k)(*[int(x) for x in plan_slots])
+            arr_rp = (C.c_void_p * k)(*[None if t is None else t.data_ptr() for t in rps])
+            arr_col = (C.c_void_p * k)(*[None if t is None else t.data_ptr() for t in cols])
+            arr_cap = (C.c_int64 * k)(*[c if want_csr else 0 for c in caps])
+            st = load().tk_nblist_build_multi(self._h, k, arr_st, C.byref(sysref.c), arr_cut,
+                                              arr_slot, arr_rp, arr_col, arr_cap, npairs)
+            if st == E_CAPACITY and want_csr and any(npairs[i] > caps[i] for i in range(k)):
+                caps = [max(caps[i], int(npairs[i])) for i in range(k)]
+                continue
+            _check(st, "tk_nblist_build_multi")
+            return [ListRef(rps[i], None if cols[i] is None else cols[i][: npairs[i]],
+                            int(npairs[i]), float(cutoffs[i]), int(plan_slots[i]))
+                    for i in range(k)]
 
     # -- pair terms ------------------------------------------------------------
     def empole_real(self, sysref, lst, mpole, beta, cutoff, prec=FP64):

@@ -115,6 +115,37 @@ def test_nblist_clustered(ctx, seed):
     assert fmax_rel(np_(f), fo) < 1e-8
 
 
+@pytest.mark.parametrize("two_streams", [False, True])
+def test_nblist_multi(ctx, tk, two_streams):
+    # the Ewald and vdW lists of a step in one call (one or two streams): each
+    # equals the oracle's, and each plan drives its pair term
+    import torch
+    w = water("water7853")
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    main = torch.cuda.current_stream(ctx.device)
+    side = torch.cuda.Stream(device=ctx.device)
+    side.wait_stream(main)
+    l7, l9 = ctx.nblists(sysr, [7.001, 9.001], [0, 1],
+                         streams=[main, side] if two_streams else None)
+    main.wait_stream(side)
+    for lst, rc in ((l7, 7.001), (l9, 9.001)):
+        rp, cp = oracle_list(w, rc)
+        assert_list_equal(lst, rp, cp)
+    e7, _, _ = ctx.empole_real(sysr, l7, w.mpole, S["beta"], S["rc_ewald"])
+    e9, _, _ = ctx.evdw(sysr, l9, tk.VDW_HAL, w.vdw_rad, w.vdw_eps, S["rc_vdw"], S["taper_frac"],
+                        S["dhal"], S["ghal"])
+    rp7, cp7 = oracle_list(w, 7.001)
+    rp9, cp9 = oracle_list(w, 9.001)
+    eo, _, _ = O.empole_real(w.xyz, w.box, w.molid, rp7, cp7, w.mpole, S["beta"], S["rc_ewald"])
+    ev, _, _ = O.evdw(w.xyz, w.box, w.molid, rp9, cp9, 0, w.vdw_rad, w.vdw_eps, S["rc_vdw"])
+    assert rel(np_(e7)[0], eo[0]) < 1e-10
+    assert rel(float(np_(e9).ravel()[0]), ev) < 1e-10
+    # the same slot twice is rejected before anything is queued
+    with pytest.raises(tk.TkError) as e:
+        ctx.nblists(sysr, [7.001, 9.001], [2, 2])
+    assert e.value.status == tk.E_ARG
+
+
 def test_nblist_errors(ctx, tk):
     xyz = np.random.default_rng(0).uniform(0, 10, size=(20, 3))
     sysr = ctx.system(xyz, 10.0, np.arange(20))
