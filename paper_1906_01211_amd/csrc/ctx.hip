@@ -393,19 +393,32 @@ static hipEvent_t take_event(tk_ctx* ctx) {
   return e;
 }
 
-ProfScope::ProfScope(tk_ctx* c, hipStream_t s, const std::string& name) : ctx(c), st(s) {
+ProfScope::ProfScope(tk_ctx* c, hipStream_t s, const std::string& name, bool kernel_events)
+    : ctx(c), st(s) {
   if (!ctx->prof_on || (!ctx->prof_only.empty() && ctx->prof_only != name)) return;
   a = take_event(ctx);
   if (!a) return;
+  if (kernel_events) {
+    b = take_event(ctx);
+    if (!b) {
+      ctx->event_pool.push_back(a);
+      a = nullptr;
+      return;
+    }
+    on_kernel = true;
+  } else {
+    (void)hipEventRecord(a, st);
+  }
   e = &ctx->prof[name];
-  (void)hipEventRecord(a, st);
 }
 
 ProfScope::~ProfScope() {
   if (!e) return;
-  hipEvent_t b = take_event(ctx);
-  if (!b) return;
-  (void)hipEventRecord(b, st);
+  if (!on_kernel) {
+    b = take_event(ctx);
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+  }
   e->pending.emplace_back(a, b);
 }
 

@@ -27,6 +27,8 @@
 #include <cstring>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "terms.hpp"
 
 namespace tk {
@@ -758,15 +760,19 @@ struct Solver {
 
   template <class R, int kMode>
   void launch_mv(const MvArgs<R>& a, const char* name) {
-    ProfScope ps(ctx, st, std::string(name) + prec_tag<R>());
-    const int g = xcd_grid(ncells);
-    if (nsys > 1) {
-      if (stage) k_pcg_mv<R, kMode, true, true><<<g, kMvThreads, mv_lds, st>>>(a);
-      else k_pcg_mv<R, kMode, false, true><<<g, kMvThreads, mv_lds, st>>>(a);
-    } else {
-      if (stage) k_pcg_mv<R, kMode, true, false><<<g, kMvThreads, mv_lds, st>>>(a);
-      else k_pcg_mv<R, kMode, false, false><<<g, kMvThreads, mv_lds, st>>>(a);
-    }
+    // when profiled, the launch itself records its start and stop events
+    ProfScope ps(ctx, st, std::string(name) + prec_tag<R>(), true);
+    const dim3 g(xcd_grid(ncells)), b(kMvThreads);
+    const auto go = [&](void (*kern)(MvArgs<R>)) {
+      if (ps.start())
+        hipExtLaunchKernelGGL(kern, g, b, (uint32_t)mv_lds, st, ps.start(), ps.stop(), 0u, a);
+      else
+        hipLaunchKernelGGL(kern, g, b, mv_lds, st, a);
+    };
+    if (nsys > 1)
+      go(stage ? k_pcg_mv<R, kMode, true, true> : k_pcg_mv<R, kMode, false, true>);
+    else
+      go(stage ? k_pcg_mv<R, kMode, true, false> : k_pcg_mv<R, kMode, false, false>);
   }
 
   // iteration k, first half: convergence test, p_k, q = A p_k

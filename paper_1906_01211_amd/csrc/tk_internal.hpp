@@ -230,13 +230,20 @@ tk_status get_plan(tk_ctx* ctx, const tk_system* sys, const tk_nblist* list, dou
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
 // Brackets one kernel launch with events when kernel timing is on.
+// on_kernel: the scope times one kernel launched with hipExtLaunchKernelGGL
+// and the events start()/stop() (recorded by the dispatch itself, so no
+// marker gaps); otherwise markers are recorded around the scope.  start() is
+// null when the scope is not being timed.
 struct ProfScope {
   tk_ctx* ctx;
   hipStream_t st;
   ProfEntry* e = nullptr;
-  hipEvent_t a = nullptr;
-  ProfScope(tk_ctx* c, hipStream_t s, const std::string& name);
+  hipEvent_t a = nullptr, b = nullptr;
+  bool on_kernel = false;
+  ProfScope(tk_ctx* c, hipStream_t s, const std::string& name, bool kernel_events = false);
   ~ProfScope();
+  hipEvent_t start() const { return on_kernel ? a : nullptr; }
+  hipEvent_t stop() const { return on_kernel ? b : nullptr; }
 };
 
 }  // namespace tk
