@@ -109,7 +109,9 @@ class AmoebaStep:
         main = torch.cuda.current_stream(c.device)
         # the two lists are built concurrently (the 9 A one on a second stream),
         # with one host synchronisation; the second stream first waits for the
-        # previous step's use of its plan slot
+        # previous step's use of its plan slot.  (Running the multipole and
+        # HAL kernels concurrently as well was measured slower: each fills
+        # the GPU on its own.)
         self.side.wait_stream(main)
         l7, l9 = c.nblists(self.sys, [s["rc_ewald"] + s["skin"], s["rc_vdw"] + s["skin"]],
                            [0, 1], streams=[main, self.side])

@@ -980,7 +980,8 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                    &S.gc)))
     return s;
   if (prec == TK_MIXED &&
-      (s = scratch(ctx, "partial", sizeof(double) * kMaxSlots * 3 * S.pstride, &partial)))
+      (s = scratch(ctx, per_stream("partial", st).c_str(),
+                   sizeof(double) * kMaxSlots * 3 * S.pstride, &partial)))
     return s;
   S.alpha_s = (double*)alpha_s; S.b = (double*)b; S.x = (double*)x; S.r = (double*)r;
   S.z = (double*)z; S.q = (double*)q; S.dx = (double*)dx; S.rt = (double*)rt;
@@ -1011,7 +1012,7 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                                              ewald_beta, cutoff, S.b, 1, (float*)S.gc, S.gcs);
   if (s) return s;
   if (prec == TK_FP64)   // the FP64 mat-vec reads only coordinates: the ones the field pass gathered
-    S.gathered = (double*)ctx->scratch["gathered"].p;
+    S.gathered = (double*)ctx->scratch[per_stream("gathered", st)].p;
   else
     S.gather_geometry();
   k_cs_setup<<<xcd_grid(S.ncells), kCellThreads, 0, st>>>(S.pv, polarity, mu_guess, guess_on, S.b,

@@ -572,21 +572,27 @@ struct VdwPh {
     g[4] = sqrt(eps[i]);
     g[5] = (double)molid[i];
   }
-  // HAL / LJ pair energy and de/dr with the taper, in arithmetic type T
+  // HAL / LJ pair energy and de/dr with the taper, in arithmetic type T;
+  // ir = 1/r.  The HAL form's three denominators (combining rule for eps,
+  // rho + ghal rv^7, r + dhal rv) share one reciprocal of their product.
   template <class T>
   __device__ __forceinline__ void eval(double r2, T ri, T rj, T si, T sj, T& e, T& dedr,
-                                       T& rr) const {
-    const T r = sqrt_r(T(r2));
-    rr = r;
+                                       T& ir) const {
+    const T irr = rsqrt_r(T(r2));
+    const T r = T(r2) * irr;
+    ir = irr;
     if (form == TK_VDW_HAL) {
       const T ri2 = ri * ri, rj2 = rj * rj;
       const T rv = (ri2 * ri + rj2 * rj) / (ri2 + rj2);
       const T se = si + sj;
-      const T ep = se > T(0) ? T(4) * (si * si) * (sj * sj) / (se * se) : T(0);
+      const bool has = se > T(0);
+      const T se2 = has ? se * se : T(1);
       const T rv2 = rv * rv, rv7 = rv2 * rv2 * rv2 * rv;
       const T r6 = T(r2) * T(r2) * T(r2), rik7 = r6 * r;
-      const T invrho = T(1) / (rik7 + T(ghal) * rv7);
-      const T invtmp = T(1) / (r + T(dhal) * rv);
+      const T d3 = rik7 + T(ghal) * rv7, d4 = r + T(dhal) * rv;
+      const T ip = T(1) / (se2 * d3 * d4);
+      const T invrho = se2 * d4 * ip, invtmp = se2 * d3 * ip;
+      const T ep = has ? T(4) * (si * si) * (sj * sj) * (d3 * d4 * ip) : T(0);
       const T tb = T(1.0 + dhal) * rv * invtmp;
       const T tb2 = tb * tb, t7 = tb2 * tb2 * tb2 * tb;
       const T w = T(1.0 + ghal) * rv7 * invrho;
@@ -595,10 +601,10 @@ struct VdwPh {
     } else {
       const T sg = T(0.5) * (ri + rj);
       const T ep = si * sj;
-      const T q = sg * sg / T(r2);
+      const T q = sg * sg * (irr * irr);
       const T sr6 = q * q * q;
       e = T(4) * ep * (sr6 * sr6 - sr6);
-      dedr = T(4) * ep * (T(-12) * sr6 * sr6 + T(6) * sr6) / r;
+      dedr = T(4) * ep * (T(-12) * sr6 * sr6 + T(6) * sr6) * irr;
     }
     if ((double)r > ron) {
       const T x = (r - T(ron)) * T(tw_inv);
@@ -617,22 +623,22 @@ struct VdwPh {
     if (!(r2 <= rc2)) return;
     double en, f;
     if (std::is_same<R, float>::value && !(r2 < kMixedCloseR2)) {
-      R e, dedr, r;
+      R e, dedr, ir;
       eval<R>(r2, R(LH[3 * cap + a]), R(LK[3 * cap + b]), R(LH[4 * cap + a]), R(LK[4 * cap + b]),
-              e, dedr, r);
-      f = (double)dedr / (double)r;
+              e, dedr, ir);
+      f = (double)dedr * (double)ir;
       // the vdW energy is a sum of cancelling attractive and repulsive terms:
       // in the mixed form it is evaluated in FP64 (forces stay FP32)
-      double ed, dd64, rd;
+      double ed, dd64, ird;
       eval<double>(r2, LH[3 * cap + a], LK[3 * cap + b], LH[4 * cap + a], LK[4 * cap + b], ed, dd64,
-                   rd);
+                   ird);
       en = ed;
     } else {   // FP64 form; in the mixed form also close pairs
-      double e, dedr, r;
+      double e, dedr, ir;
       eval<double>(r2, LH[3 * cap + a], LK[3 * cap + b], LH[4 * cap + a], LK[4 * cap + b], e, dedr,
-                   r);
+                   ir);
       en = e;
-      f = dedr / r;
+      f = dedr * ir;
     }
     sc[0] += en;
 #pragma unroll
@@ -697,14 +703,18 @@ tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, con
   const long pstride = pad64(P.n);
   void *partial, *uscal;
   tk_status s;
-  if ((s = scratch(ctx, "partial", sizeof(double) * kMaxSlots * Ph::NA * pstride, &partial)) ||
-      (s = scratch(ctx, "uscal", sizeof(double) * (size_t)P.nunits * (Ph::NS > 0 ? Ph::NS : 1),
+  const size_t ns1 = Ph::NS > 0 ? Ph::NS : 1;
+  if ((s = scratch(ctx, per_stream("partial", st).c_str(),
+                   sizeof(double) * kMaxSlots * Ph::NA * pstride, &partial)) ||
+      (s = scratch(ctx, per_stream("uscal", st).c_str(), sizeof(double) * (size_t)P.nunits * ns1,
                    &uscal)))
     return s;
   PlanView pv = P.view();
   if (unit_lds_bytes<Ph>(P, 1) > kMaxLds) return TK_E_CAPACITY;
   void* gathered;
-  if ((s = scratch(ctx, "gathered", sizeof(double) * Ph::NG * pstride, &gathered))) return s;
+  if ((s = scratch(ctx, per_stream("gathered", st).c_str(), sizeof(double) * Ph::NG * pstride,
+                   &gathered)))
+    return s;
   Ph phg = ph;
   phg.sorted = (const double*)gathered;
   phg.gstride = pstride;
@@ -716,9 +726,8 @@ tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, con
   const bool sums = Ph::NS > 0 && energy && virial;
   const int nchunk = sums ? total_chunks(P) : 0;
   void* cpart = nullptr;
-  if (sums && (s = scratch(ctx, "chunk_sums", sizeof(double) * (Ph::NS > 0 ? Ph::NS : 1) *
-                                                  (size_t)(nchunk > 0 ? nchunk : 1),
-                           &cpart)))
+  if (sums && (s = scratch(ctx, per_stream("chunk_sums", st).c_str(),
+                           sizeof(double) * ns1 * (size_t)(nchunk > 0 ? nchunk : 1), &cpart)))
     return s;
   {
     ProfScope ps(ctx, st, "reduce_atoms");

@@ -183,6 +183,14 @@ tk_status pinned(tk_ctx* ctx, size_t bytes, void** out, void** dev = nullptr);
 CellTables& cell_tables(tk_ctx* ctx, int nc);
 
 // Exclusive scan of int32 counts: out[0..len] with out[len] = total.
+// Scratch of work that may run on several streams of one context at the
+// same time (the pair terms): one buffer set per stream.
+inline std::string per_stream(const char* base, hipStream_t st) {
+  if (!st) return base;
+  char buf[40];
+  std::snprintf(buf, sizeof buf, "@%p", (void*)st);
+  return std::string(base) + buf;
+}
 // job: index of the list build in a group (separate scratch per build).
 tk_status scan_i32(tk_ctx* ctx, hipStream_t st, const int32_t* in, int32_t* out, int len,
                    int job = 0);

@@ -146,6 +146,37 @@ def test_nblist_multi(ctx, tk, two_streams):
     assert e.value.status == tk.E_ARG
 
 
+def test_pair_terms_on_streams(ctx, tk):
+    # multipoles and HAL of one context on two streams at once (each stream has
+    # its own scratch) give bitwise what they give one after the other
+    import torch
+    w = water("water7853")
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    l7, l9 = ctx.nblists(sysr, [7.001, 9.001], [0, 1])
+
+    def run():
+        em = ctx.empole_real(sysr, l7, w.mpole, S["beta"], S["rc_ewald"])
+        ev = ctx.evdw(sysr, l9, tk.VDW_HAL, w.vdw_rad, w.vdw_eps, S["rc_vdw"], S["taper_frac"],
+                      S["dhal"], S["ghal"])
+        return em, ev
+
+    em0, ev0 = run()
+    main = torch.cuda.current_stream(ctx.device)
+    s1, s2 = torch.cuda.Stream(device=ctx.device), torch.cuda.Stream(device=ctx.device)
+    s1.wait_stream(main)
+    s2.wait_stream(main)
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            em = ctx.empole_real(sysr, l7, w.mpole, S["beta"], S["rc_ewald"])
+        with torch.cuda.stream(s2):
+            ev = ctx.evdw(sysr, l9, tk.VDW_HAL, w.vdw_rad, w.vdw_eps, S["rc_vdw"],
+                          S["taper_frac"], S["dhal"], S["ghal"])
+        main.wait_stream(s1)
+        main.wait_stream(s2)
+        for a, b in zip(em + ev, em0 + ev0):
+            assert np.array_equal(np_(a), np_(b))
+
+
 def test_nblist_errors(ctx, tk):
     xyz = np.random.default_rng(0).uniform(0, 10, size=(20, 3))
     sysr = ctx.system(xyz, 10.0, np.arange(20))
