@@ -146,6 +146,28 @@ def test_nblist_multi(ctx, tk, two_streams):
     assert e.value.status == tk.E_ARG
 
 
+def test_nblist_multi_four_and_empty(ctx, tk):
+    # four lists on two streams (two per stream), then an empty system
+    import torch
+    rng = np.random.default_rng(11)
+    box, n = 21.0, 900
+    xyz = rng.uniform(0.0, box, size=(n, 3))
+    sysr = ctx.system(xyz, box, np.arange(n) // 3)
+    main = torch.cuda.current_stream(ctx.device)
+    side = torch.cuda.Stream(device=ctx.device)
+    side.wait_stream(main)
+    cuts = [2.5, 4.0, 6.0, 10.4]
+    lists = ctx.nblists(sysr, cuts, [4, 5, 6, 7], streams=[main, side, main, side])
+    main.wait_stream(side)
+    for lst, rc in zip(lists, cuts):
+        rp, cp = O.nblist(xyz, box, rc)
+        assert_list_equal(lst, rp, cp)
+    empty = ctx.system(np.zeros((0, 3)), box, np.zeros(0, dtype=np.int32))
+    l0, l1 = ctx.nblists(empty, [3.0, 5.0], [4, 5])
+    assert l0.npairs == 0 and l1.npairs == 0
+    assert np.array_equal(np_(l0.row_ptr), [0]) and np.array_equal(np_(l1.row_ptr), [0])
+
+
 def test_pair_terms_on_streams(ctx, tk):
     # multipoles and HAL of one context on two streams at once (each stream has
     # its own scratch) give bitwise what they give one after the other
