@@ -34,7 +34,13 @@
  *    forces, fields and all solver reductions accumulated in FP64).
  *  - A tk_ctx owns scratch device memory (grown on demand, never shrunk, never
  *    freed between calls) and up to TK_MAX_PLANS neighbour-list plans.  A
- *    context is not thread safe; use one per host thread.
+ *    context is not thread safe; use one per host thread.  Work of one context
+ *    queued on different streams may run concurrently where it touches
+ *    different memory: the pair terms keep their scratch per stream and the
+ *    builds of one tk_nblist_build_multi call have their own; the solver
+ *    (tk_polarize_pcg) has one scratch set per context, so two solves of a
+ *    context must be ordered, and a plan slot must not be rebuilt while work
+ *    that reads it is still queued on another stream.
  */
 #ifndef TK_H
 #define TK_H

@@ -1150,8 +1150,9 @@ static tk_status build_group(tk_ctx* ctx, BuildJob* jobs, int nj) {
   int queued = 0;
   for (; queued < nj; ++queued)
     if ((s = build_begin(ctx, jobs[queued], hb, hdb))) break;
-  const int nsync = s ? queued : nj;
-  for (int k = 0; k < nsync + (s && queued < nj ? 1 : 0); ++k) {
+  // builds to wait for: all, or those queued (in full or in part) before a failure
+  const int nwait = s ? queued + 1 : nj;
+  for (int k = 0; k < nwait; ++k) {
     bool seen = false;
     for (int m = 0; m < k; ++m) seen |= jobs[m].st == jobs[k].st;
     if (!seen) {
