@@ -36,7 +36,6 @@ namespace {
 
 constexpr int kChunk = 6;
 constexpr int kCellThreads = 256;   // per-cell workgroups
-constexpr int kCellWaves = kCellThreads / 64;
 
 struct PcgState {
   double rho, gamma, alpha, beta, zz, rms, rms0, rms_true, epol, tol;

@@ -48,7 +48,7 @@ struct Pinned {
   size_t bytes = 0;
   tk_status ensure(size_t want) {
     if (want <= bytes) return TK_OK;
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
     p = nullptr;
     bytes = 0;
     if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) return TK_E_NOMEM;
@@ -56,7 +56,7 @@ struct Pinned {
     return TK_OK;
   }
   ~Pinned() {
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
   }
 };
 
@@ -66,7 +66,7 @@ struct Dev {
   size_t bytes = 0;
   tk_status ensure(size_t want) {
     if (want <= bytes) return TK_OK;
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
     if (hipMalloc(&p, want) != hipSuccess) return TK_E_NOMEM;
@@ -74,7 +74,7 @@ struct Dev {
     return TK_OK;
   }
   ~Dev() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   }
 };
 
@@ -182,7 +182,7 @@ tk_status tk_server::run(std::vector<std::shared_ptr<Req>>& batch,
 }
 
 void tk_server::loop() {
-  hipSetDevice(device);
+  (void)hipSetDevice(device);   // the worker thread's device (checked at creation)
   for (;;) {
     std::vector<std::shared_ptr<Req>> batch;
     std::vector<const std::vector<double>*> guesses;
@@ -330,7 +330,7 @@ void tk_server_destroy(tk_server* srv) {
   }
   srv->cv_work.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
-  hipStreamDestroy(srv->stream);
+  (void)hipStreamDestroy(srv->stream);
   tk_destroy(srv->ctx);
   delete srv;
 }
