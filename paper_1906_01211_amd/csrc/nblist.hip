@@ -29,7 +29,9 @@ __device__ __forceinline__ bool pair_in(const uint4& a, const uint4& b, uint64_t
 
 // Fast form of the exact test: the FP64 sum of squares of the (exact) integer
 // differences is within 3 ulp of the true value, so outside a +-2^-50 band
-// around rq^2 it decides; inside the band the exact 64-bit test decides.
+// around rq^2 it decides; inside the band the exact 64-bit test decides.  The
+// exact test runs only when some lane of the wave is in the band (a
+// wave-uniform branch, almost never taken); every lane of the wave must call.
 struct PairTest {
   uint64_t rq2;
   double lo, hi;
@@ -39,7 +41,9 @@ struct PairTest {
                  dz = (double)(int32_t)(b.z - a.z);
     const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
     bool in = d2 < lo;
-    if (!in && d2 <= hi) in = pair_in(a, b, rq2);   // rare: inside the rounding band
+    const bool band = !in && d2 <= hi;
+    if (__builtin_expect(__ballot(band) != 0, 0))
+      if (band) in = pair_in(a, b, rq2);
     return in;
   }
 };
