@@ -410,15 +410,26 @@ __global__ __launch_bounds__(64 * kPlanMaxWaves) void k_plan(
 // Per unit: move the unit's pair codes from the regions of its candidate
 // window to its place in the dense code array (windows are sized by
 // candidates, the dense array by listed pairs), regions in (chunk, wave)
-// order.
+// order; and write the unit's record for the pair kernels (see UnitRec).
 __global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ woff,
                                                  const uint32_t* __restrict__ windows,
                                                  const int64_t* __restrict__ doff,
                                                  const int32_t* __restrict__ rcnt,
                                                  const int2* __restrict__ nfilt, int W,
-                                                 uint32_t* __restrict__ codes) {
+                                                 uint32_t* __restrict__ codes,
+                                                 const Unit* __restrict__ units,
+                                                 const int32_t* __restrict__ cstart,
+                                                 const int32_t* __restrict__ unit_cnt,
+                                                 const int32_t* __restrict__ cell_sys,
+                                                 UnitRec* __restrict__ rec) {
   __shared__ int rs[kPlanRegions], rd[kPlanRegions + 1];
   const int u = blockIdx.x, tid = threadIdx.x;
+  if (tid == 64) {   // a lane of the second wave: the record, beside wave 0's prefix
+    const Unit un = units[u];
+    const int hs = cstart[un.h], ks = cstart[un.k];
+    rec[u] = UnitRec{hs, cstart[un.h + 1] - hs, ks, cstart[un.k + 1] - ks, un.slot_h, un.slot_k,
+                     cell_sys ? cell_sys[un.h] : 0, unit_cnt[u], doff[u]};
+  }
   const int2 nf = nfilt[u];
   const int nhf = nf.x, nkf = nf.y;
   const int nr = ((nhf + 63) >> 6) * W;
@@ -1077,15 +1088,20 @@ static tk_status build_finish(tk_ctx* ctx, BuildJob& J) {
     return TK_E_HIP;
   }
   const int max_row = h[2];
-  // dense codes at unit_off (the exclusive scan of the unit counts)
-  if ((s = ensure(P.codes, sizeof(uint32_t) * (size_t)(list_pairs > 0 ? list_pairs : 1)))) return s;
+  // dense codes at unit_off (the exclusive scan of the unit counts), and the
+  // per-unit records of the pair kernels
+  if ((s = ensure(P.codes, sizeof(uint32_t) * (size_t)(list_pairs > 0 ? list_pairs : 1))) ||
+      (s = ensure(P.urec, sizeof(UnitRec) * (size_t)(nunits > 0 ? nunits : 1))))
+    return s;
+  const int32_t* cstart = (const int32_t*)P.cell_start.p;
   if (n > 0) {
     ProfScope ps(ctx, st, "nblist_compact");
     k_compact<<<nunits, 256, 0, st>>>((const int64_t*)J.woff, (const uint32_t*)J.wb->p,
                                      (const int64_t*)P.unit_off.p, (const int32_t*)J.regcnt,
-                                     (const int2*)J.nfilt, J.plan_waves, (uint32_t*)P.codes.p);
+                                     (const int2*)J.nfilt, J.plan_waves, (uint32_t*)P.codes.p,
+                                     J.units, cstart, (const int32_t*)P.unit_cnt.p, J.cell_sys,
+                                     (UnitRec*)P.urec.p);
   }
-  const int32_t* cstart = (const int32_t*)P.cell_start.p;
   if (J.row_ptr) {
     if (list_pairs > J.cap) return TK_E_CAPACITY;
     const int nb = max_row < kBuckets ? max_row : kBuckets;

@@ -53,13 +53,10 @@ __global__ __launch_bounds__(64 * W) void k_units(PlanView pv, Ph ph, double* __
   if (ph.skip()) return;   // solver finished: nothing to do
   const int u = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const Unit un = pv.units[u];
-  if (pv.nsys > 1) {   // batch: this unit's system geometry
-    const int sy = pv.cell_sys[un.h];
-    ph.set_sys(pv.sys[sy], sy);
-  }
-  const int hs = pv.cell_start[un.h], nh = pv.cell_start[un.h + 1] - hs;
-  const int ks = pv.cell_start[un.k], nk = pv.cell_start[un.k + 1] - ks;
+  const UnitRec un = pv.urec[u];   // one read: cells, slots, system, pairs
+  if (pv.nsys > 1) ph.set_sys(pv.sys[un.sy], un.sy);   // batch: this unit's system geometry
+  const int hs = un.hs, nh = un.nh;
+  const int ks = un.ks, nk = un.nk;
   const int cap = pv.max_occ;
   ph.prologue(tid, NT);
   double* LH = lds;
@@ -86,7 +83,7 @@ __global__ __launch_bounds__(64 * W) void k_units(PlanView pv, Ph ph, double* __
   for (int k = 0; k < NS1; ++k) sc[k] = 0.0;
   double* MH = AH + w * Ph::NA * cap;
   double* MK = AK + w * Ph::NA * cap;
-  const long p0 = pv.unit_off[u], p1 = p0 + pv.unit_cnt[u];
+  const long p0 = un.off, p1 = p0 + un.cnt;
   for (long p = p0 + tid; p < p1; p += NT) {
     const uint32_t code = pv.codes[p];
     ph.pair(LH, LK, cap, (int)(code & 0xffffu), (int)(code >> 16), MH, MK, sc, p);

@@ -39,6 +39,14 @@ struct Unit {
   int32_t h, k, slot_h, slot_k;
 };
 
+// Everything a pair kernel's workgroup needs about its unit, in one record
+// (built once per list): the two cells' first sorted atom and size, the
+// partial-result slots, the system, and the unit's listed pairs.
+struct UnitRec {
+  int32_t hs, nh, ks, nk, slot_h, slot_k, sy, cnt;
+  int64_t off;
+};
+
 // One system of a plan.  A plan holds one system (the single-system entry
 // points) or a batch of independent systems (the serving path): each system
 // has its own box, cell grid and list cutoff; its cells, units and atoms are
@@ -67,6 +75,7 @@ struct PlanView {
   int32_t nsys;
   const SysDev* sys;          // [nsys]
   const int32_t* cell_sys;    // [ncells] system of each cell; nullptr when nsys == 1
+  const UnitRec* urec;        // [nunits]
 };
 
 // Workgroups are dispatched to the 8 XCDs round-robin.  Per-cell kernels
@@ -103,7 +112,7 @@ struct Plan {
   int32_t nc = 0, ncells = 0, nunits = 0, max_occ = 0, max_row = 0;
   int32_t max_nbhd = 0;   // max over cells of the atoms in the cell's neighbour cells (itself included)
   int64_t npairs = 0;
-  DevBuf perm, scell, cell_start, unit_off, unit_cnt, codes, us, slots;
+  DevBuf perm, scell, cell_start, unit_off, unit_cnt, codes, us, slots, urec;
   const Unit* units_p = nullptr;       // device cell tables (shared by plans with the same
   const int32_t* nslot_p = nullptr;    // nc for one system; built per batch otherwise)
   const int32_t* cu_p = nullptr;
@@ -124,6 +133,7 @@ struct Plan {
     v.codes = (const uint32_t*)codes.p;
     v.cell_units = cu_p;
     v.cell_order = order_p;
+    v.urec = (const UnitRec*)urec.p;
     return v;
   }
 };
