@@ -63,6 +63,10 @@ def lib():
         L.or_polarize_pcg.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
                                       C.c_double, C.c_double, C.c_double, C.c_int, C.c_void_p,
                                       _dp, C.POINTER(PcgInfo)]
+        L.or_thole_l9.argtypes = [C.c_double] * 5
+        L.or_thole_l9.restype = C.c_double
+        L.or_epolar_real.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp, _dp,
+                                     C.c_double, C.c_double, _dp, _dp, _dp]
         L.or_evdw.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, C.c_int, _dp, _dp,
                               C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
         L.or_eself.argtypes = [C.c_int, _dp, C.c_double]
@@ -195,6 +199,26 @@ def tmatvec(xyz, box, row_ptr, col, polarity, thole_a, beta, cutoff, mu, include
     if st:
         raise OracleError(st)
     return out
+
+
+def thole_l9(r, ai, aj, ti, tj):
+    return lib().or_thole_l9(r, ai, aj, ti, tj)
+
+
+def epolar_real(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, mu, beta, cutoff):
+    """Polarization pair energies {total, induced-permanent, induced-induced},
+    forces and virial at fixed induced dipoles mu (or_epolar_real)."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    energy = np.zeros(3)
+    force = np.zeros((n, 3))
+    virial = np.zeros((3, 3))
+    st = lib().or_epolar_real(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _d(mpole),
+                              _d(polarity), _d(thole_a), _d(mu), beta, cutoff, energy, force,
+                              virial)
+    if st:
+        raise OracleError(st)
+    return energy, force, virial
 
 
 def polarize_pcg(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta, cutoff,

@@ -586,6 +586,94 @@ int or_polarize_pcg(int n, const double* xyz, double box, const int32_t* molid,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Polarization forces (the induced-dipole gradient routine that the Rel
+ * profile ranks second among the AMOEBA hotspots, section "Hotspots").
+ *
+ * With A = 1/alpha - (T + cI) the operator of the polarization equations and
+ * E_p the permanent field, the polarization energy is the minimum over mu of
+ *   E(r, mu) = C [ 1/2 mu.A(r) mu - mu.E_p(r) ],
+ * reached where A mu = E_p, with value -1/2 C mu.E_p (the solver's E_pol).
+ * Reading: the force is -dE/dr at fixed mu.  At the converged dipoles this
+ * is the gradient of E_pol itself (dE/dmu = 0 there); at any other mu it is
+ * the gradient of E(r, mu) for that mu.
+ *
+ * The position-dependent part of E(r, mu) is a sum over listed pairs with
+ * r <= rc.  Writing an induced dipole as the multipole (0, mu, 0):
+ *   e_ip = U(mu_i, M_j; gp) + U(M_i, mu_j; gp)     (= -C mu_i.E_i<-j - C mu_j.E_j<-i)
+ *   e_ii = U(mu_i, mu_j; gm)                        (= -C mu_i.T2 mu_j)
+ * where U is the multipole pair energy of or_mpole_pair and the radial
+ * families are those of the two fields:
+ *   gp_n = B_n - (1 - s l_(2n+1)) R_n   (s = 0 for equal molid, else 1),
+ *   gm_n = B_n - (1 - l_(2n+1)) R_n     (every pair).
+ * The Thole factors obey (l_(2n+1) R_n)' = -r l_(2n+3) R_(n+1), as B_n and
+ * R_n do, so or_mpole_pair's gradient rule holds for these families too;
+ * the gradient of the quadrupole field term needs one more factor,
+ *   l9 = 1 - (1 + x + 18/35 x^2 + 9/35 x^3) e^-x.
+ * energy[0] = e_ip + e_ii summed, energy[1] = sum of e_ip, energy[2] = sum
+ * of e_ii; forces F = -dE/dx; virial W_ab = sum over pairs of r_a de/dr_b. */
+double or_thole_l9(double r, double ai, double aj, double ti, double tj) {
+  double prod = ai * aj;
+  if (prod == 0.0) return 1.0;
+  double a = ti < tj ? ti : tj;
+  double x = a * r * r * r / sqrt(prod);
+  return 1.0 - (1.0 + x + (18.0 / 35.0) * x * x + (9.0 / 35.0) * x * x * x) * exp(-x);
+}
+
+int or_epolar_real(int n, const double* xyz, double box, const int32_t* molid,
+                   const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                   const double* polarity, const double* thole, const double* mu, double beta,
+                   double rc, double* energy, double* force, double* virial) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  double rc2 = rc * rc;
+  energy[0] = energy[1] = energy[2] = 0.0;
+  for (int k = 0; k < 9; ++k) virial[k] = 0.0;
+  for (int k = 0; k < 3 * n; ++k) force[k] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int j = col[p];
+      double d[3], r2;
+      or_image(xyz + 3 * i, xyz + 3 * j, box, d, &r2);
+      if (!(r2 <= rc2)) continue;
+      double r = sqrt(r2), B[6], R[6], l[5];
+      or_radial(r, beta, 5, B, R);
+      or_thole(r, polarity[i], polarity[j], thole[i], thole[j], &l[1], &l[2], &l[3]);
+      l[4] = or_thole_l9(r, polarity[i], polarity[j], thole[i], thole[j]);
+      double s = molid[i] == molid[j] ? 0.0 : 1.0;
+      /* l[n] multiplies R_n; R_0 (and R_5) never meet a nonzero coefficient
+       * when one side is a pure dipole: c0 = c4 = 0 */
+      double gp[6], gm[6];
+      gp[0] = gm[0] = 0.0;
+      gp[5] = gm[5] = 0.0;
+      for (int k = 1; k <= 4; ++k) {
+        gp[k] = B[k] - (1.0 - s * l[k]) * R[k];
+        gm[k] = B[k] - (1.0 - l[k]) * R[k];
+      }
+      double ind_i[10] = {0.0}, ind_j[10] = {0.0};
+      for (int a = 0; a < 3; ++a) {
+        ind_i[1 + a] = mu[3 * i + a];
+        ind_j[1 + a] = mu[3 * j + a];
+      }
+      double e1, e2, e3, de1[3], de2[3], de3[3];
+      or_mpole_pair(d, ind_i, mpole + 10 * j, gp, &e1, de1);
+      or_mpole_pair(d, mpole + 10 * i, ind_j, gp, &e2, de2);
+      or_mpole_pair(d, ind_i, ind_j, gm, &e3, de3);
+      energy[1] += e1 + e2;
+      energy[2] += e3;
+      for (int a = 0; a < 3; ++a) {
+        double de = de1[a] + de2[a] + de3[a];
+        force[3 * i + a] += de;
+        force[3 * j + a] -= de;
+      }
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) virial[3 * a + b] += d[a] * (de1[b] + de2[b] + de3[b]);
+    }
+  }
+  energy[0] = energy[1] + energy[2];
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* van der Waals (the Halgren 14-7 and LJ 12-6 routines of the Rel profile).
  * HAL, in the quantities of the paper's compute loop (Listing
  * "calculation"): rv = R_ij, rv7 = rv^7, rik7 = r^7,
