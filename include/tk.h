@@ -225,6 +225,31 @@ tk_status tk_polarize_pcg(tk_ctx* ctx, void* stream, const tk_system* sys, const
                           int prec, const double* mu_guess, double* mu_out, tk_pcg_info* info);
 
 /*
+ * Real-space polarization forces (epolar1 in the Rel profile, the second
+ * AMOEBA hotspot of section "Hotspots").  The polarization energy is the
+ * minimum over mu of C [1/2 mu.A mu - mu.E_perm] (A, E_perm as above),
+ * -1/2 C mu.E_perm at the solution.  This call returns -d/dx of that
+ * expression at the given, fixed mu: at converged dipoles, the gradient of
+ * the polarization energy itself.  For each listed pair with r <= cutoff,
+ * with an induced dipole written as the multipole (0, mu, 0) and U the pair
+ * energy of tk_empole_real:
+ *   e_ip = U(mu_i, M_j; gp) + U(M_i, mu_j; gp) = -C (mu_i.E_i<-j + mu_j.E_j<-i),
+ *   e_ii = U(mu_i, mu_j; gm) = -C mu_i.T2 mu_j,
+ * gp_n = B_n - (1 - s l_(2n+1)) R_n (s = 0 within a molecule, else 1),
+ * gm_n = B_n - (1 - l_(2n+1)) R_n, Thole factors as in tk_efield_direct plus
+ * l9 = 1 - (1 + x + 18/35 x^2 + 9/35 x^3) e^-x for the quadrupole term.
+ * mu: device [n][3] (e A), e.g. tk_polarize_pcg's mu_out.  energy: device
+ * [3] = e_ip + e_ii, sum of e_ip, sum of e_ii (the self and 1/2 mu.mu/alpha
+ * terms do not depend on positions and are not included; at the solution
+ * -1/2 C mu.E_perm is tk_pcg_info.epol).  force: device [n][3];
+ * virial: device [3][3], W_ab = sum over pairs r_a de/dr_b.
+ */
+tk_status tk_epolar_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                         const double* mpole, const double* polarity, const double* thole,
+                         const double* mu, double ewald_beta, double cutoff, int prec,
+                         double* energy, double* force, double* virial);
+
+/*
  * van der Waals (ehal / elj in the Rel profile).  form = TK_VDW_HAL: Halgren
  * buffered 14-7, e = eps_ij [(1+d) R_ij/(r + d R_ij)]^7
  * [(1+g) R_ij^7/(r^7 + g R_ij^7) - 2], R_ij = (R_i^3+R_j^3)/(R_i^2+R_j^2),

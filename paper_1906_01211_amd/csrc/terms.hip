@@ -140,6 +140,34 @@ tk_status tk_tmatvec(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_n
                                               cutoff, include_diag, mu, out);
 }
 
+tk_status tk_epolar_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                         const double* mpole, const double* polarity, const double* thole,
+                         const double* mu, double ewald_beta, double cutoff, int prec,
+                         double* energy, double* force, double* virial) {
+  const Plan* P;
+  tk_status s = common_args(ctx, sys, list, cutoff, prec, &P);
+  if (s) return s;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !energy || !virial) return TK_E_ARG;
+  if (sys->n > 0 && (!mpole || !polarity || !thole || !mu || !force)) return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (sys->n == 0) {
+    TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
+    TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
+    return TK_OK;
+  }
+  auto run = [&](auto ph) {
+    ph.xyz = sys->xyz;
+    ph.mpole = mpole;
+    ph.molid = sys->molid;
+    ph.polarity = polarity;
+    ph.thole = thole;
+    ph.mu = mu;
+    ph.g.set(sys->box, cutoff, ewald_beta);
+    return run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
+  };
+  return prec == TK_FP64 ? run(EpolarPh<double>{}) : run(EpolarPh<float>{});
+}
+
 tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
                   int form, const double* radius_or_sigma, const double* eps, double cutoff,
                   double taper_on_frac, double hal_delta, double hal_gamma, int prec,

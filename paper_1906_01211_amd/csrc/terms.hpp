@@ -110,6 +110,26 @@ __device__ __forceinline__ void thole_damp(R r, R isa_i, R isa_j, R ti, R tj, R&
   l7 = R(1) - (R(1) + x + R(0.6) * x * x) * e;
 }
 
+// l3, l5, l7 and l9 = 1 - (1 + x + 18/35 x^2 + 9/35 x^3) e^-x; the family
+// (l_(2n+1) R_n) obeys the same gradient rule as B_n and R_n, l9 being the
+// factor the gradient of the damped quadrupole field needs.
+template <class R>
+__device__ __forceinline__ void thole_damp9(R r, R isa_i, R isa_j, R ti, R tj, R* l) {
+  const R pr = isa_i * isa_j;
+  if (pr == R(0)) {
+    l[0] = l[1] = l[2] = l[3] = R(1);
+    return;
+  }
+  const R a = ti < tj ? ti : tj;
+  const R x = a * r * r * r * pr;
+  const R e = exp_neg(-x);
+  const R x2 = x * x;
+  l[0] = R(1) - e;
+  l[1] = R(1) - (R(1) + x) * e;
+  l[2] = R(1) - (R(1) + x + R(0.6) * x2) * e;
+  l[3] = R(1) - (R(1) + x + R(18.0 / 35.0) * x2 + R(9.0 / 35.0) * x2 * x) * e;
+}
+
 __device__ __forceinline__ double inv_sqrt_alpha(double a) { return a > 0.0 ? 1.0 / sqrt(a) : 0.0; }
 
 // --------------------------------------------------------------------------
@@ -648,6 +668,132 @@ struct VdwPh {
       lds_add(&AK[c * cap + b], -de);
 #pragma unroll
       for (int k = 0; k < 3; ++k) sc[1 + 3 * c + k] += dd[c] * f * dd[k];
+    }
+  }
+};
+
+// Polarization forces at fixed induced dipoles p: the pair energies
+//   e_ip = U(p_i, M_j; gp) + U(M_i, p_j; gp),   e_ii = U(p_i, p_j; gm)
+// (U the multipole pair energy, an induced dipole the multipole (0, p, 0)),
+// gp_n = B_n - (1 - s l_(2n+1)) R_n with s = 0 within a molecule,
+// gm_n = B_n - (1 - l_(2n+1)) R_n; forces -de/dx, virial r_a de/dr_b.
+// With one side a pure dipole only n = 1..3 carry coefficients.
+// Fields: x y z | q mu(3) Theta(6) | molid | isa | thole | p(3)
+template <class R>
+struct EpolarPh {
+  static constexpr int NF = 19, NA = 3, NS = 11;
+  static constexpr const char* kName = "epolar";
+  static constexpr int kWaves = 2;   // waves per unit (pairs.hpp launch_units)
+  static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
+  __device__ bool skip() const { return false; }
+  __device__ void prologue(int tid, int nt) const { erfcx_stage<R>(tid, nt); }
+  const double* xyz;
+  const double* mpole;
+  const int32_t* molid;
+  const double* polarity;
+  const double* thole;
+  const double* mu;
+  Geom g;
+  __device__ void set_sys(const SysDev& d, int) {
+    g.box = d.box;
+    g.inv_box = d.inv_box;
+  }
+  static constexpr int NG = 19;   // fields gathered once per call (sorted SoA)
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void stage_dyn(double*, int, int, int) const {}
+  __device__ void gather(int i, double* g) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] = xyz[3 * i + c];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) g[3 + k] = mpole[10 * i + k];
+    g[13] = (double)molid[i];
+    g[14] = inv_sqrt_alpha(polarity[i]);
+    g[15] = thole[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[16 + c] = mu[3 * i + c];
+  }
+  // pair energies (e_ip, e_ii) and de/dr in arithmetic type T; with T = float
+  // the caller routes same-molecule pairs to T = double
+  template <class T>
+  __device__ __forceinline__ void eval(const double* LH, const double* LK, int cap, int a, int b,
+                                       const double* dd, double r2, bool excl, double* de,
+                                       double& eip, double& eii) const {
+    const T rinv = rsqrt_r(T(r2));
+    const T r = T(r2) * rinv;
+    T B[5], Rb[5];
+    radial<T, 4>(g, r, rinv, B, Rb, r2);
+    T l[4];
+    thole_damp9<T>(r, T(LH[14 * cap + a]), T(LK[14 * cap + b]), T(LH[15 * cap + a]),
+                   T(LK[15 * cap + b]), l);
+    T gp[5], gm[4];   // indexed by n; entry 0 unused
+#pragma unroll
+    for (int n = 1; n <= 4; ++n) {
+      const T bare = Rb[n] - l[n - 1] * Rb[n];   // (1 - l_(2n+1)) R_n
+      gp[n] = excl ? B[n] - Rb[n] : B[n] - bare;
+      if (n <= 3) gm[n] = B[n] - bare;
+    }
+    const T d[3] = {T(dd[0]), T(dd[1]), T(dd[2])};
+    const T qi = T(LH[3 * cap + a]), qj = T(LK[3 * cap + b]);
+    const T ui[3] = {T(LH[4 * cap + a]), T(LH[5 * cap + a]), T(LH[6 * cap + a])};
+    const T uj[3] = {T(LK[4 * cap + b]), T(LK[5 * cap + b]), T(LK[6 * cap + b])};
+    const T ti[6] = {T(LH[7 * cap + a]), T(LH[8 * cap + a]), T(LH[9 * cap + a]),
+                     T(LH[10 * cap + a]), T(LH[11 * cap + a]), T(LH[12 * cap + a])};
+    const T tj[6] = {T(LK[7 * cap + b]), T(LK[8 * cap + b]), T(LK[9 * cap + b]),
+                     T(LK[10 * cap + b]), T(LK[11 * cap + b]), T(LK[12 * cap + b])};
+    const T pi[3] = {T(LH[16 * cap + a]), T(LH[17 * cap + a]), T(LH[18 * cap + a])};
+    const T pj[3] = {T(LK[16 * cap + b]), T(LK[17 * cap + b]), T(LK[18 * cap + b])};
+    auto tmul = [](const T* t, const T* x, T* y) {
+      y[0] = t[0] * x[0] + t[1] * x[1] + t[2] * x[2];
+      y[1] = t[1] * x[0] + t[3] * x[1] + t[4] * x[2];
+      y[2] = t[2] * x[0] + t[4] * x[1] + t[5] * x[2];
+    };
+    auto dot = [](const T* x, const T* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+    T vi[3], vj[3], tipj[3], tjpi[3];
+    tmul(ti, d, vi);
+    tmul(tj, d, vj);
+    tmul(ti, pj, tipj);
+    tmul(tj, pi, tjpi);
+    const T di = dot(ui, d), dj = dot(uj, d), Qi = dot(d, vi), Qj = dot(d, vj);
+    const T ei = dot(pi, d), ej = dot(pj, d), pp = dot(pi, pj);
+    // induced-permanent coefficients (n = 1..3)
+    const T c1 = qj * ei - qi * ej + dot(pi, uj) + dot(ui, pj);
+    const T c2 = -(ei * dj + di * ej) + T(2) * (dot(pj, vi) - dot(pi, vj));
+    const T c3 = ei * Qj - ej * Qi;
+    const T sp = c1 * gp[2] + c2 * gp[3] + c3 * gp[4];
+    const T sm = pp * gm[2] - ei * ej * gm[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T dc1 = qj * pi[c] - qi * pj[c];
+      const T dc2 = -(dj * pi[c] + ei * uj[c] + ej * ui[c] + di * pj[c]) +
+                    T(2) * (tipj[c] - tjpi[c]);
+      const T dc3 = Qj * pi[c] + T(2) * ei * vj[c] - Qi * pj[c] - T(2) * ej * vi[c];
+      const T dm2 = -(ej * pi[c] + ei * pj[c]);
+      de[c] = kCoulomb * (double)(dc1 * gp[1] + dc2 * gp[2] + dc3 * gp[3] + dm2 * gm[2] -
+                                  (sp + sm) * d[c]);
+    }
+    eip = kCoulomb * (double)(c1 * gp[1] + c2 * gp[2] + c3 * gp[3]);
+    eii = kCoulomb * (double)(pp * gm[1] - ei * ej * gm[2]);
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double* sc, long) const {
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
+    if (!(r2 <= g.rc2)) return;
+    const bool excl = LH[13 * cap + a] == LK[13 * cap + b];
+    double de[3], eip, eii;
+    if (std::is_same<R, float>::value && (excl || r2 < kMixedCloseR2))
+      eval<double>(LH, LK, cap, a, b, dd, r2, excl, de, eip, eii);
+    else
+      eval<R>(LH, LK, cap, a, b, dd, r2, excl, de, eip, eii);
+    sc[0] += eip;
+    sc[1] += eii;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lds_add(&AH[c * cap + a], de[c]);
+      lds_add(&AK[c * cap + b], -de[c]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) sc[2 + 3 * c + q] += dd[c] * de[q];
     }
   }
 };

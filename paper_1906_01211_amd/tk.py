@@ -101,6 +101,8 @@ _SIGS = {
                    C.c_int, _vp, _vp],
     "tk_polarize_pcg": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d, _d,
                         _i32, C.c_int, _vp, _vp, C.POINTER(PcgInfo)],
+    "tk_epolar_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
+                       _d, C.c_int, _vp, _vp, _vp],
     "tk_evdw": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), C.c_int, _vp, _vp, _d, _d, _d, _d,
                 C.c_int, _vp, _vp, _vp],
     "tk_batch_step": [_vp, _vp, C.POINTER(Batch), C.POINTER(StepParams), _vp, _vp, _vp, _vp, _vp,
@@ -313,6 +315,19 @@ class Context:
         if st not in (OK, E_NOCONV, E_BREAKDOWN):
             _check(st, "tk_polarize_pcg")
         return out, {k: getattr(info, k) for k, _ in PcgInfo._fields_}
+
+    def epolar_real(self, sysref, lst, mpole, polarity, thole, mu, beta, cutoff, prec=FP64):
+        mp = _dev(mpole, torch.float64, self.device)
+        pol = _dev(polarity, torch.float64, self.device)
+        th = _dev(thole, torch.float64, self.device)
+        m = _dev(mu, torch.float64, self.device)
+        e = torch.empty(3, dtype=torch.float64, device=self.device)
+        f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
+        _check(load().tk_epolar_real(self._h, _stream(self.device), C.byref(sysref.c),
+                                     C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), _ptr(m), beta,
+                                     cutoff, prec, _ptr(e), _ptr(f), _ptr(w)), "tk_epolar_real")
+        return e, f, w
 
     def evdw(self, sysref, lst, form, rad, eps, cutoff, taper_frac=0.9, dhal=0.07, ghal=0.12,
              prec=FP64):
