@@ -37,6 +37,14 @@ MV_BYTES_PER_ATOM = 24 + 24 + 24 + 8 + 24 + 24
 # fields: pair vector 9, two dot products 10, two field updates 12, scale 2).
 MV_FLOPS_PER_PAIR = 33
 PEAK_FP64_TFLOPS = 78.6
+# FP64 vector issue peak in lane-instructions per second: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz (an FMA, an add and a multiply each take one slot).
+PEAK_FP64_LANE_INSTR = 256 * 64 * 2.4e9
+# FP64 vector instructions per evaluated pair of the polarization-force
+# kernel (k_units<EpolarPh<double>, 2>): static count in its gfx950 assembly,
+# nearly all of it the pair evaluation (radial functions, Thole factors,
+# multipole algebra, gradient, virial).
+EPOLAR_FP64_INSTR_PER_PAIR = 390
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
@@ -238,7 +246,7 @@ def main():
         "roofline": roof,
     }
     if not a.no_extras:
-        out["extras"] = extras(ctx, tk, w, a, prec)
+        out["extras"] = extras(ctx, tk, w, a, prec, n7)
     if not a.no_serving:
         out["serving"] = serving(tk, a.serving_requests)
     if not a.no_cpu_baseline:
@@ -247,8 +255,9 @@ def main():
     print(json.dumps(out))
 
 
-def extras(ctx, tk, w, a, prec):
-    """Mixed-vs-FP64 step and the charge + LJ path (not part of `value`)."""
+def extras(ctx, tk, w, a, prec, n7):
+    """Mixed-vs-FP64 step, the charge + LJ path and the polarization forces
+    (not part of `value`)."""
     import torch
     res = {}
     other = tk.MIXED if prec == tk.FP64 else tk.FP64
@@ -273,7 +282,41 @@ def extras(ctx, tk, w, a, prec):
         res[f"charge_lj_step_ms_{name}"] = ms
         res["charge_lj_pairs_12A"] = int(l12.npairs)
         res[f"charge_lj_pairs_per_s_{name}"] = 2 * l12.npairs / (ms * 1e-3)
+    res["epolar"] = epolar_leg(ctx, tk, w, n7)
     return res
+
+
+def epolar_leg(ctx, tk, w, n7):
+    """Polarization forces at the converged dipoles of the water box: one call
+    (gather, pair kernel, reduction) and its pair kernel alone, FP64 and mixed."""
+    import torch
+    s = synth.AMOEBA_SETTINGS
+    dev = ctx.device
+    sysw = ctx.system(w.xyz, w.box, w.molid)
+    l7 = ctx.nblist(sysw, s["rc_ewald"] + s["skin"], plan_slot=3)
+    mp = torch.as_tensor(w.mpole, device=dev)
+    pol = torch.as_tensor(w.polarity, device=dev)
+    th = torch.as_tensor(w.thole, device=dev)
+    out = {"pairs": n7}
+    for name, pr, tag in (("fp64", tk.FP64, "fp64"), ("mixed", tk.MIXED, "fp32")):
+        mu, _ = ctx.polarize_pcg(sysw, l7, mp, pol, th, s["beta"], s["rc_ewald"],
+                                 tol_debye=s["tol_debye"], maxiter=s["maxiter"], prec=pr)
+
+        def call():
+            ctx.epolar_real(sysw, l7, mp, pol, th, mu, s["beta"], s["rc_ewald"], prec=pr)
+        kname = "units_epolar_" + tag
+        ctx.profile(True, only=kname)
+        ms = timed(call, 20, 3) * 1e3
+        kp = ctx.profile_read()
+        ctx.profile(False)
+        kus = kp[kname]["ms"] / kp[kname]["launches"] * 1e3
+        out[f"call_ms_{name}"] = round(ms, 4)
+        out[f"kernel_us_{name}"] = round(kus, 2)
+        out[f"pairs_per_s_{name}"] = n7 / (kus * 1e-6)
+        if pr == tk.FP64:
+            out["alu_frac_fp64"] = round(EPOLAR_FP64_INSTR_PER_PAIR * n7 / (kus * 1e-6) /
+                                         PEAK_FP64_LANE_INSTR, 4)
+    return out
 
 
 _serving_systems = {}
