@@ -73,6 +73,13 @@ def lib():
         L.or_eself.restype = C.c_double
         L.or_erecip.argtypes = [C.c_int, _dp, C.c_double, _dp, C.c_double, C.c_int]
         L.or_erecip.restype = C.c_double
+        L.or_erecip_grad.argtypes = [C.c_int, _dp, C.c_double, _dp, C.c_double, C.c_int, _dp, _dp]
+        L.or_bspline.argtypes = [C.c_int, C.c_double, C.c_int]
+        L.or_bspline.restype = C.c_double
+        L.or_spline_mod.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.or_spline_mod.restype = C.c_double
+        L.or_pme_mpole.argtypes = [C.c_int, _dp, C.c_double, _dp, C.c_double, C.c_int, C.c_int,
+                                   C.POINTER(C.c_double), _dp, C.c_void_p]
         _lib = L
     return _lib
 
@@ -275,3 +282,37 @@ def dense_operator(xyz, box, row_ptr, col, polarity, thole_a, beta, cutoff):
         A[:, k] = tmatvec(xyz, box, row_ptr, col, polarity, thole_a, beta, cutoff,
                           e.reshape(n, 3), include_diag=1).ravel()
     return A
+
+
+def erecip_grad(xyz, box, mpole, beta, kmax):
+    """Reciprocal-space forces and field by the plain k-sum (or_erecip_grad)."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    force = np.zeros((n, 3))
+    field = np.zeros((n, 3))
+    st = lib().or_erecip_grad(n, xyz, box, _d(mpole), beta, kmax, force, field)
+    if st:
+        raise OracleError(st)
+    return force, field
+
+
+def bspline(p, x, deriv=0):
+    return lib().or_bspline(p, x, deriv)
+
+
+def spline_mod(p, K, m):
+    return lib().or_spline_mod(p, K, m)
+
+
+def pme_mpole(xyz, box, mpole, beta, K, order=5):
+    """Smooth-PME reciprocal energy, forces and field (or_pme_mpole)."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    e = C.c_double()
+    force = np.zeros((n, 3))
+    field = np.zeros((n, 3))
+    st = lib().or_pme_mpole(n, xyz, box, _d(mpole), beta, K, order, C.byref(e), force,
+                            field.ctypes.data_as(C.c_void_p))
+    if st:
+        raise OracleError(st)
+    return e.value, force, field

@@ -799,3 +799,293 @@ double or_erecip(int n, const double* xyz, double box, const double* mpole, doub
       }
   return OR_COULOMB * sum / (2.0 * vol);
 }
+
+/* Reciprocal-space forces and field by the same k-sum (validation only).
+ * With a_j = qj - Thj:kk + i muj.k and S(k) = sum_j a_j exp(i k.r_j):
+ *   potential phi(y) = (1/V) sum_k G(k) Re[exp(i k.y) conj S(k)],
+ *   G(k) = (4 pi/k^2) exp(-k^2/(4 beta^2));
+ *   field_i = -grad phi(r_i) (no Coulomb constant; it includes the site's
+ *   own contribution, which the Ewald self field removes);
+ *   force_j = -dE/dr_j = (C/V) sum_k G(k) k Im[a_j exp(i k.r_j) conj S(k)]. */
+int or_erecip_grad(int n, const double* xyz, double box, const double* mpole, double beta,
+                   int kmax, double* force, double* field) {
+  if (n < 0 || !(box > 0.0) || !(beta > 0.0) || kmax < 0) return OR_E_ARG;
+  const double twopi = 6.283185307179586477;
+  double vol = box * box * box;
+  double* ar = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double* ai = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double* cr = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double* ci = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int k = 0; k < 3 * n; ++k) force[k] = field[k] = 0.0;
+  for (int mx = -kmax; mx <= kmax; ++mx)
+    for (int my = -kmax; my <= kmax; ++my)
+      for (int mz = -kmax; mz <= kmax; ++mz) {
+        if (!mx && !my && !mz) continue;
+        double k[3] = {twopi * mx / box, twopi * my / box, twopi * mz / box};
+        double k2 = or_dot(k, k);
+        double G = exp(-k2 / (4.0 * beta * beta)) * 4.0 * M_PI / k2;
+        if (G < 1e-300) continue;
+        double sr = 0.0, si = 0.0;
+        for (int j = 0; j < n; ++j) {
+          double q, u[3], t[3][3], tk[3];
+          or_unpack(mpole + 10 * j, &q, u, t);
+          or_matvec3(t, k, tk);
+          ar[j] = q - or_dot(k, tk);
+          ai[j] = or_dot(u, k);
+          double ph = or_dot(k, xyz + 3 * j);
+          cr[j] = cos(ph);
+          ci[j] = sin(ph);
+          sr += ar[j] * cr[j] - ai[j] * ci[j];
+          si += ar[j] * ci[j] + ai[j] * cr[j];
+        }
+        for (int j = 0; j < n; ++j) {
+          /* a_j e^{ik.r_j} conj(S) and e^{ik.r_j} conj(S): imaginary parts */
+          double tr = ar[j] * cr[j] - ai[j] * ci[j], ti = ar[j] * ci[j] + ai[j] * cr[j];
+          double im_f = ti * sr - tr * si;
+          double im_e = ci[j] * sr - cr[j] * si;
+          for (int a = 0; a < 3; ++a) {
+            force[3 * j + a] += OR_COULOMB / vol * G * k[a] * im_f;
+            field[3 * j + a] += G * k[a] * im_e / vol;
+          }
+        }
+      }
+  free(ar); free(ai); free(cr); free(ci);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Smooth particle-mesh Ewald for the reciprocal-space multipole energy (the
+ * reciprocal multipole routine that section "Hotspots" names beside the
+ * real-space one; the paper leaves it unvectorized).  Reading: the textbook
+ * smooth PME of Essmann et al. (1995) with cardinal B-splines, extended to
+ * dipoles and quadrupoles by differentiating the spline (as in Sagui,
+ * Pedersen and Darden, 2004); no further correction of the spline moduli.
+ *
+ * Cardinal B-spline of order p on (0, p):
+ *   M_2(x) = 1 - |x - 1|,  M_p(x) = [x M_(p-1)(x) + (p - x) M_(p-1)(x - 1)] / (p - 1),
+ *   M_p'(x) = M_(p-1)(x) - M_(p-1)(x - 1)   (deriv <= p - 2). */
+double or_bspline(int p, double x, int deriv) {
+  if (deriv > 0) return or_bspline(p - 1, x, deriv - 1) - or_bspline(p - 1, x - 1.0, deriv - 1);
+  if (!(x > 0.0) || !(x < p)) return 0.0;
+  if (p == 2) return 1.0 - fabs(x - 1.0);
+  return (x * or_bspline(p - 1, x, 0) + (p - x) * or_bspline(p - 1, x - 1.0, 0)) / (p - 1);
+}
+
+/* Spline modulus D(m) = |sum_{k=0}^{p-2} M_p(k+1) exp(2 pi i m k/K)|^2, so that
+ * |b(m)|^2 = 1/D(m).  Reading: where D vanishes (m = K/2 for odd p) it is
+ * replaced by the mean of its two neighbours. */
+static double or_spline_mod_raw(int p, int K, int m) {
+  double sr = 0.0, si = 0.0;
+  for (int k = 0; k <= p - 2; ++k) {
+    double w = or_bspline(p, k + 1.0, 0), ang = 6.283185307179586477 * m * k / K;
+    sr += w * cos(ang);
+    si += w * sin(ang);
+  }
+  return sr * sr + si * si;
+}
+
+double or_spline_mod(int p, int K, int m) {
+  double d = or_spline_mod_raw(p, K, m);
+  if (d < 1e-10)
+    d = 0.5 * (or_spline_mod_raw(p, K, (m + K - 1) % K) + or_spline_mod_raw(p, K, (m + 1) % K));
+  return d;
+}
+
+/* Reciprocal-space multipole energy, forces and field by smooth PME on a
+ * K x K x K grid with splines of order p, 5 <= p <= 8 (quadrupole forces need
+ * the third derivative of the spline), K >= 2p.  In the order of the method:
+ *  1. u_j = K frac(x_j / L) per axis; the weights of grid point g are the
+ *     tensor product of M_p(u_j - g) (g = floor(u_j) - t, t = 0..p-1, taken
+ *     mod K), and d/dx of a weight is (K/L) M_p'.
+ *  2. Spread: Q(g) = sum_j [qj M + muj.grad M + Thj:grad grad M](u_j - g),
+ *     which interpolates S(k) as b(m) sum_g Q(g) exp(2 pi i m.g/K).
+ *  3. F(m) = sum_g Q(g) exp(+2 pi i m.g/K) (plain separable DFT).
+ *  4. W(m) = (4 pi/k^2) exp(-k^2/(4 beta^2)) / (V D(m1) D(m2) D(m3)), k = 2 pi m'/L
+ *     with m' the signed frequency (m' = m for m <= K/2, else m - K); W(0) = 0.
+ *  5. phi(g) = sum_m W(m) F(m) exp(-2 pi i m.g/K): the potential on the grid
+ *     (e/A), E = (C/2) sum_g Q(g) phi(g).
+ *  6. Interpolate phi and its derivatives up to third order at each site:
+ *     phi^(abc)(r_j) = sum_g phi(g) d^abc M(u_j - g).
+ * Then energy = (C/2) sum_j [qj phi + muj.grad phi + Thj:grad grad phi],
+ * force_j = -C [qj grad phi + (grad grad phi) muj + (grad grad grad phi):Thj],
+ * field_j = -grad phi(r_j) (includes the site's own contribution, as the
+ * k-sum field does).  field may be NULL. */
+int or_pme_mpole(int n, const double* xyz, double box, const double* mpole, double beta, int K,
+                 int p, double* energy, double* force, double* field) {
+  if (n < 0 || !(box > 0.0) || !(beta > 0.0) || K < 2 * p || p < 5 || p > 8) return OR_E_ARG;
+  const double twopi = 6.283185307179586477;
+  size_t KK = (size_t)K * K * K;
+  double* Q = (double*)calloc(KK, sizeof(double));
+  double* Fr = (double*)malloc(sizeof(double) * KK);
+  double* Fi = (double*)malloc(sizeof(double) * KK);
+  double* Tr = (double*)malloc(sizeof(double) * KK);
+  double* Ti = (double*)malloc(sizeof(double) * KK);
+  double* phi = (double*)malloc(sizeof(double) * KK);
+  double* cs = (double*)malloc(sizeof(double) * (size_t)K * K);
+  double* sn = (double*)malloc(sizeof(double) * (size_t)K * K);
+  double* th = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 3 * p * 4);
+  int* g0 = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1) * 3);
+  double kl = K / box;
+  /* 1. spline weights and derivatives, th[j][axis][t][d] */
+  for (int j = 0; j < n; ++j)
+    for (int a = 0; a < 3; ++a) {
+      double x = xyz[3 * j + a] / box;
+      double u = K * (x - floor(x));
+      int i0 = (int)floor(u);
+      double w = u - i0;
+      g0[3 * j + a] = i0;
+      for (int t = 0; t < p; ++t)
+        for (int d = 0; d < 4; ++d)
+          th[(((size_t)j * 3 + a) * p + t) * 4 + d] =
+              or_bspline(p, w + t, d) * pow(kl, d);
+    }
+#define TH(j, a, t, d) th[((((size_t)(j)) * 3 + (a)) * p + (t)) * 4 + (d)]
+#define GIX(j, a, t) ((((g0[3 * (j) + (a)] - (t)) % K) + K) % K)
+  /* 2. spread */
+  for (int j = 0; j < n; ++j) {
+    double q, u[3], T[3][3];
+    or_unpack(mpole + 10 * j, &q, u, T);
+    for (int t1 = 0; t1 < p; ++t1)
+      for (int t2 = 0; t2 < p; ++t2)
+        for (int t3 = 0; t3 < p; ++t3) {
+          int tt[3] = {t1, t2, t3};
+          double v = 0.0;
+          /* derivative orders (dx, dy, dz) with dx + dy + dz <= 2 */
+          for (int dx = 0; dx <= 2; ++dx)
+            for (int dy = 0; dy <= 2 - dx; ++dy)
+              for (int dz = 0; dz <= 2 - dx - dy; ++dz) {
+                double wgt = TH(j, 0, tt[0], dx) * TH(j, 1, tt[1], dy) * TH(j, 2, tt[2], dz);
+                int ord = dx + dy + dz;
+                double c = 0.0;
+                if (ord == 0) c = q;
+                else if (ord == 1) c = dx ? u[0] : (dy ? u[1] : u[2]);
+                else {
+                  /* Theta : grad grad, full symmetric sum */
+                  int ia = dx ? 0 : (dy ? 1 : 2);
+                  int ib = dx == 2 ? 0 : (dy == 2 ? 1 : (dz == 2 ? 2 : -1));
+                  if (ib >= 0) c = T[ia][ia];
+                  else {
+                    int i1 = dx ? 0 : 1, i2 = dz ? 2 : 1;
+                    c = 2.0 * T[i1][i2];
+                  }
+                }
+                v += c * wgt;
+              }
+          size_t g = ((size_t)GIX(j, 0, t1) * K + GIX(j, 1, t2)) * K + GIX(j, 2, t3);
+          Q[g] += v;
+        }
+  }
+  /* 3. F(m) = sum_g Q(g) exp(+2 pi i m.g/K), one axis at a time */
+  for (int m = 0; m < K; ++m)
+    for (int g = 0; g < K; ++g) {
+      cs[m * K + g] = cos(twopi * (double)((long)m * g % K) / K);
+      sn[m * K + g] = sin(twopi * (double)((long)m * g % K) / K);
+    }
+  for (size_t k = 0; k < KK; ++k) { Fr[k] = Q[k]; Fi[k] = 0.0; }
+  for (int axis = 0; axis < 3; ++axis) {
+    for (int a = 0; a < K; ++a)
+      for (int b = 0; b < K; ++b)
+        for (int m = 0; m < K; ++m) {
+          double sr = 0.0, si = 0.0;
+          for (int g = 0; g < K; ++g) {
+            size_t idx = axis == 0 ? ((size_t)g * K + a) * K + b
+                       : axis == 1 ? ((size_t)a * K + g) * K + b : ((size_t)a * K + b) * K + g;
+            sr += Fr[idx] * cs[m * K + g] - Fi[idx] * sn[m * K + g];
+            si += Fr[idx] * sn[m * K + g] + Fi[idx] * cs[m * K + g];
+          }
+          size_t o = axis == 0 ? ((size_t)m * K + a) * K + b
+                   : axis == 1 ? ((size_t)a * K + m) * K + b : ((size_t)a * K + b) * K + m;
+          Tr[o] = sr;
+          Ti[o] = si;
+        }
+    memcpy(Fr, Tr, sizeof(double) * KK);
+    memcpy(Fi, Ti, sizeof(double) * KK);
+  }
+  /* 4. multiply by W(m) */
+  double vol = box * box * box;
+  for (int m1 = 0; m1 < K; ++m1)
+    for (int m2 = 0; m2 < K; ++m2)
+      for (int m3 = 0; m3 < K; ++m3) {
+        size_t idx = ((size_t)m1 * K + m2) * K + m3;
+        int s1 = m1 <= K / 2 ? m1 : m1 - K, s2 = m2 <= K / 2 ? m2 : m2 - K,
+            s3 = m3 <= K / 2 ? m3 : m3 - K;
+        double W = 0.0;
+        if (s1 || s2 || s3) {
+          double k[3] = {twopi * s1 / box, twopi * s2 / box, twopi * s3 / box};
+          double k2 = or_dot(k, k);
+          W = 4.0 * M_PI / k2 * exp(-k2 / (4.0 * beta * beta)) /
+              (vol * or_spline_mod(p, K, m1) * or_spline_mod(p, K, m2) * or_spline_mod(p, K, m3));
+        }
+        Fr[idx] *= W;
+        Fi[idx] *= W;
+      }
+  /* 5. phi(g) = sum_m W F(m) exp(-2 pi i m.g/K) */
+  for (int axis = 0; axis < 3; ++axis) {
+    for (int a = 0; a < K; ++a)
+      for (int b = 0; b < K; ++b)
+        for (int g = 0; g < K; ++g) {
+          double sr = 0.0, si = 0.0;
+          for (int m = 0; m < K; ++m) {
+            size_t idx = axis == 0 ? ((size_t)m * K + a) * K + b
+                       : axis == 1 ? ((size_t)a * K + m) * K + b : ((size_t)a * K + b) * K + m;
+            sr += Fr[idx] * cs[m * K + g] + Fi[idx] * sn[m * K + g];
+            si += Fi[idx] * cs[m * K + g] - Fr[idx] * sn[m * K + g];
+          }
+          size_t o = axis == 0 ? ((size_t)g * K + a) * K + b
+                   : axis == 1 ? ((size_t)a * K + g) * K + b : ((size_t)a * K + b) * K + g;
+          Tr[o] = sr;
+          Ti[o] = si;
+        }
+    memcpy(Fr, Tr, sizeof(double) * KK);
+    memcpy(Fi, Ti, sizeof(double) * KK);
+  }
+  for (size_t k = 0; k < KK; ++k) phi[k] = Fr[k];
+  /* 6. interpolate derivatives up to third order; energy, forces, field */
+  double esum = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double D[4][4][4];
+    for (int dx = 0; dx < 4; ++dx)
+      for (int dy = 0; dy < 4; ++dy)
+        for (int dz = 0; dz < 4; ++dz) D[dx][dy][dz] = 0.0;
+    for (int t1 = 0; t1 < p; ++t1)
+      for (int t2 = 0; t2 < p; ++t2)
+        for (int t3 = 0; t3 < p; ++t3) {
+          double ph = phi[((size_t)GIX(j, 0, t1) * K + GIX(j, 1, t2)) * K + GIX(j, 2, t3)];
+          for (int dx = 0; dx < 4; ++dx)
+            for (int dy = 0; dy < 4 - dx; ++dy)
+              for (int dz = 0; dz < 4 - dx - dy; ++dz)
+                D[dx][dy][dz] += ph * TH(j, 0, t1, dx) * TH(j, 1, t2, dy) * TH(j, 2, t3, dz);
+        }
+    double q, u[3], T[3][3];
+    or_unpack(mpole + 10 * j, &q, u, T);
+    /* derivative along axes (a, b, c): orders counted per axis */
+#define DER1(a) D[(a) == 0][(a) == 1][(a) == 2]
+#define DER2(a, b) D[((a) == 0) + ((b) == 0)][((a) == 1) + ((b) == 1)][((a) == 2) + ((b) == 2)]
+#define DER3(a, b, c) D[((a) == 0) + ((b) == 0) + ((c) == 0)][((a) == 1) + ((b) == 1) + ((c) == 1)] \
+                       [((a) == 2) + ((b) == 2) + ((c) == 2)]
+    double e = q * D[0][0][0];
+    for (int a = 0; a < 3; ++a) {
+      e += u[a] * DER1(a);
+      for (int b = 0; b < 3; ++b) e += T[a][b] * DER2(a, b);
+    }
+    esum += e;
+    for (int a = 0; a < 3; ++a) {
+      double g = q * DER1(a);
+      for (int b = 0; b < 3; ++b) {
+        g += u[b] * DER2(a, b);
+        for (int c = 0; c < 3; ++c) g += T[b][c] * DER3(a, b, c);
+      }
+      force[3 * j + a] = -OR_COULOMB * g;
+      if (field) field[3 * j + a] = -DER1(a);
+    }
+#undef DER1
+#undef DER2
+#undef DER3
+  }
+  *energy = 0.5 * OR_COULOMB * esum;
+#undef TH
+#undef GIX
+  free(Q); free(Fr); free(Fi); free(Tr); free(Ti); free(phi); free(cs); free(sn); free(th);
+  free(g0);
+  return OR_OK;
+}
