@@ -250,6 +250,30 @@ tk_status tk_epolar_real(tk_ctx* ctx, void* stream, const tk_system* sys, const 
                          double* energy, double* force, double* virial);
 
 /*
+ * Reciprocal-space multipole energy, forces and field by smooth particle-mesh
+ * Ewald (the reciprocal multipole routine that section "Hotspots" names beside
+ * the real-space one; the paper leaves it unvectorized).  It approximates the
+ * Ewald sum (C/2V) sum_{k != 0} (4 pi/k^2) exp(-k^2/(4 beta^2)) |S(k)|^2,
+ * S(k) = sum_j (q_j + i mu_j.k - Theta_j:kk) exp(i k.r_j) (tin-foil boundary),
+ * on a grid x grid x grid mesh with cardinal B-splines of the given order:
+ * sites are spread as q M + mu.grad M + Theta:grad grad M, the mesh is
+ * convolved with (4 pi/k^2) exp(-k^2/(4 beta^2)) / (V |b(m)|^-2) by FFTs
+ * (|b(m)|^-2 the spline modulus, at a zero replaced by the mean of its
+ * neighbours), and the potential and its derivatives up to third order are
+ * interpolated back at each site.  mpole: device [n][10] as tk_empole_real;
+ * the coordinates of sys, any values (wrapped into the box).  grid: 16, 32,
+ * 64 or 128; order: 5..8 with grid >= 2 order.  energy: device [1] (NaN if a
+ * site's spread contribution reaches 2^17 e/A^k, outside the fixed-point
+ * range of the deterministic grid); force: device [n][3], -dE/dx; field:
+ * device [n][3] or NULL, -grad phi in e/A^2 (no Coulomb constant), including
+ * each site's own contribution (the real-space self field removes it).  No
+ * real-space, self or virial term.  sys->molid is not used.
+ */
+tk_status tk_pme_mpole(tk_ctx* ctx, void* stream, const tk_system* sys, const double* mpole,
+                       double ewald_beta, int32_t grid, int32_t order, double* energy,
+                       double* force, double* field);
+
+/*
  * van der Waals (ehal / elj in the Rel profile).  form = TK_VDW_HAL: Halgren
  * buffered 14-7, e = eps_ij [(1+d) R_ij/(r + d R_ij)]^7
  * [(1+g) R_ij^7/(r^7 + g R_ij^7) - 2], R_ij = (R_i^3+R_j^3)/(R_i^2+R_j^2),

@@ -1,0 +1,581 @@
+// Reciprocal-space multipole energy, forces and field by smooth particle-mesh
+// Ewald (the reciprocal multipole routine named beside the real-space one in
+// section "Hotspots"; the paper leaves it unvectorized).  Textbook smooth PME
+// with cardinal B-splines of order P, extended to dipoles and quadrupoles by
+// differentiating the spline.
+//
+// One call: zero -> spread -> FFT along z, y -> [FFT along x, multiply by the
+// influence function, inverse FFT along x] -> inverse FFT along y, z ->
+// gather (potential derivatives up to third order at every site) -> energy.
+//
+// The spread grid is accumulated in 64-bit fixed point (2^-40 units) with
+// integer atomics: integer addition is associative, so the grid, and every
+// result after it, is bitwise the same run to run.  A single contribution of
+// magnitude 2^17 or more is refused (the energy comes back NaN); below that
+// the sums of up to 2^6 such contributions at one point stay exact.
+//
+// The FFTs are radix-2 in LDS, one workgroup per batch of grid lines: lines of
+// length K (a power of two, 16..128) along one axis, 256 threads, K/2
+// butterflies per line and stage.  Forward transforms take bit-reversed input
+// (decimation in time), inverse ones natural input (decimation in frequency),
+// so no transform needs a separate permutation pass.
+#include <cmath>
+
+#include "tk_internal.hpp"
+
+namespace tk {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kFix = 1099511627776.0;   // 2^40
+constexpr double kFixMax = 131072.0;       // 2^17
+
+// Cardinal B-spline weights th[t][d] = M_P^(d)(w + t) (t = 0..P-1, d = 0..3)
+// for a fractional offset w in [0, 1), by the recursion
+//   M_k(x) = [x M_(k-1)(x) + (k - x) M_(k-1)(x - 1)] / (k - 1),  M_2 on (0, 2),
+// and the derivatives as differences of lower orders,
+//   M_P'(x) = M_(P-1)(x) - M_(P-1)(x - 1).
+template <int P>
+__device__ __forceinline__ void bspline_table(double w, double th[P][4]) {
+  double A[P + 1][P];   // A[k][t] = M_k(w + t), zero outside t < k
+#pragma unroll
+  for (int k = 0; k <= P; ++k)
+#pragma unroll
+    for (int t = 0; t < P; ++t) A[k][t] = 0.0;
+  A[2][0] = w;
+  A[2][1] = 1.0 - w;
+#pragma unroll
+  for (int k = 3; k <= P; ++k)
+#pragma unroll
+    for (int t = 0; t < k; ++t) {
+      const double x = w + t;
+      const double lo = t < k - 1 ? A[k - 1][t] : 0.0;
+      const double hi = t > 0 ? A[k - 1][t - 1] : 0.0;
+      A[k][t] = (x * lo + (k - x) * hi) / (k - 1);
+    }
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    auto at = [&](int k, int s) { return s >= 0 ? A[k][s] : 0.0; };
+    th[t][0] = A[P][t];
+    th[t][1] = at(P - 1, t) - at(P - 1, t - 1);
+    th[t][2] = at(P - 2, t) - 2.0 * at(P - 2, t - 1) + at(P - 2, t - 2);
+    th[t][3] = at(P - 3, t) - 3.0 * at(P - 3, t - 1) + 3.0 * at(P - 3, t - 2) - at(P - 3, t - 3);
+  }
+}
+
+// Per axis: grid origin i0 = floor(u), weights scaled to d/dx = (K/L) d/du.
+// Axes y and z keep all P rows; along x only row t1 (the lane's plane) is
+// kept, selected by an unrolled compare so that every table stays in
+// registers.
+template <int P>
+__device__ __forceinline__ void site_splines(const double* x, double box, int K, int t1,
+                                             double X[4], double th[2][P][4], int i0[3]) {
+  const double kl = K / box;
+  const double sc[4] = {1.0, kl, kl * kl, kl * kl * kl};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double s = x[a] / box;
+    const double u = K * (s - floor(s));
+    const double fl = floor(u);
+    i0[a] = (int)fl;
+    double t4[P][4];
+    bspline_table<P>(u - fl, t4);
+    if (a == 0) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d) X[d] = 0.0;
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+        if (t == t1)
+#pragma unroll
+          for (int d = 0; d < 4; ++d) X[d] = t4[t][d] * sc[d];
+    } else {
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) th[a - 1][t][d] = t4[t][d] * sc[d];
+    }
+  }
+}
+
+__device__ __forceinline__ int wrap(int g, int K) { return ((g % K) + K) % K; }
+
+__global__ __launch_bounds__(256) void k_pme_zero(unsigned long long* __restrict__ grid, long n,
+                                                  int* __restrict__ flag) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) grid[i] = 0ull;
+  if (i == 0) flag[0] = 0;
+}
+
+// Spread: 8 lanes per site, lane t1 < P takes the P x P points of plane t1.
+//   Q(g) += q M + mu.grad M + Theta:grad grad M   at M = M(u - g)
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_spread(int n, const double* __restrict__ xyz,
+                                                    const double* __restrict__ mpole, double box,
+                                                    int K, unsigned long long* __restrict__ grid,
+                                                    int* __restrict__ flag) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = gid >> 3, t1 = gid & 7;
+  if (j >= n || t1 >= P) return;
+  double X[4], th[2][P][4];
+  int i0[3];
+  site_splines<P>(xyz + 3 * j, box, K, t1, X, th, i0);
+  const double* m = mpole + 10 * j;
+  const double q = m[0], ux = m[1], uy = m[2], uz = m[3];
+  const double txx = m[4], txy = m[5], txz = m[6], tyy = m[7], tyz = m[8], tzz = m[9];
+  const int gx = wrap(i0[0] - t1, K);
+  bool bad = false;
+#pragma unroll
+  for (int t2 = 0; t2 < P; ++t2) {
+    const int gy = wrap(i0[1] - t2, K);
+    const double* Y = th[0][t2];
+#pragma unroll
+    for (int t3 = 0; t3 < P; ++t3) {
+      const double* Z = th[1][t3];
+      const double v = q * X[0] * Y[0] * Z[0] +
+                       ux * X[1] * Y[0] * Z[0] + uy * X[0] * Y[1] * Z[0] + uz * X[0] * Y[0] * Z[1] +
+                       txx * X[2] * Y[0] * Z[0] + tyy * X[0] * Y[2] * Z[0] + tzz * X[0] * Y[0] * Z[2] +
+                       2.0 * (txy * X[1] * Y[1] * Z[0] + txz * X[1] * Y[0] * Z[1] +
+                              tyz * X[0] * Y[1] * Z[1]);
+      bad |= !(fabs(v) < kFixMax);
+      const long long iv = bad ? 0ll : llrint(v * kFix);
+      const int g = (gx * K + gy) * K + wrap(i0[2] - t3, K);
+      atomicAdd(&grid[g], (unsigned long long)iv);
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------- FFT
+template <int K>
+struct Fft {
+  static constexpr int H = K / 2;     // butterflies per line and stage
+  static constexpr int L = 256 / H;   // lines per workgroup
+  static constexpr int LOG = K == 16 ? 4 : K == 32 ? 5 : K == 64 ? 6 : 7;
+  static_assert(K == 16 || K == 32 || K == 64 || K == 128, "grid edge");
+};
+
+__device__ __forceinline__ int bitrev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
+
+// tw[k] = exp(2 pi i k / K), k < K/2
+template <int K>
+__device__ __forceinline__ void twiddles(double2* tw) {
+  for (int k = threadIdx.x; k < K / 2; k += blockDim.x) {
+    double s, c;
+    sincospi(2.0 * k / K, &s, &c);
+    tw[k] = make_double2(c, s);
+  }
+}
+
+// Decimation in time on bit-reversed input, natural output:
+// X(m) = sum_g x(g) exp(sign 2 pi i m g / K).
+template <int K>
+__device__ __forceinline__ void fft_dit(double2* sh, const double2* tw, double sign) {
+  constexpr int H = Fft<K>::H;
+  const int t = threadIdx.x, line = t / H, b = t % H;
+  double2* x = sh + line * K;
+#pragma unroll
+  for (int half = 1; half < K; half <<= 1) {
+    const int grp = b / half, pos = b % half;
+    const int i = grp * 2 * half + pos, j = i + half;
+    const double2 w = tw[pos * (H / half)];
+    const double wr = w.x, wi = sign * w.y;
+    const double2 a = x[i], c = x[j];
+    const double tr = wr * c.x - wi * c.y, ti = wr * c.y + wi * c.x;
+    x[i] = make_double2(a.x + tr, a.y + ti);
+    x[j] = make_double2(a.x - tr, a.y - ti);
+    __syncthreads();
+  }
+}
+
+// Decimation in frequency on natural input, bit-reversed output (same sum).
+template <int K>
+__device__ __forceinline__ void fft_dif(double2* sh, const double2* tw, double sign) {
+  constexpr int H = Fft<K>::H;
+  const int t = threadIdx.x, line = t / H, b = t % H;
+  double2* x = sh + line * K;
+#pragma unroll
+  for (int half = H; half >= 1; half >>= 1) {
+    const int grp = b / half, pos = b % half;
+    const int i = grp * 2 * half + pos, j = i + half;
+    const double2 w = tw[pos * (H / half)];
+    const double wr = w.x, wi = sign * w.y;
+    const double2 a = x[i], c = x[j];
+    const double dr = a.x - c.x, di = a.y - c.y;
+    x[i] = make_double2(a.x + c.x, a.y + c.y);
+    x[j] = make_double2(wr * dr - wi * di, wr * di + wi * dr);
+    __syncthreads();
+  }
+}
+
+// Grid line geometry: line gl of axis ax (0: x, 1: y, 2: z) starts at base
+// and steps by stride; index = (gx K + gy) K + gz.
+template <int K>
+__device__ __forceinline__ void line_geom(int ax, int gl, long& base, long& stride) {
+  const int a = gl / K, b = gl % K;
+  if (ax == 2) { base = ((long)a * K + b) * K; stride = 1; }
+  else if (ax == 1) { base = (long)a * K * K + b; stride = K; }
+  else { base = (long)a * K + b; stride = (long)K * K; }
+}
+
+// Element (line, k) handled by thread t in load/store slot s (two slots):
+// along z (contiguous) consecutive threads take consecutive k of one line;
+// along x, y consecutive threads take consecutive lines (consecutive z).
+template <int K>
+__device__ __forceinline__ void slot(int ax, int t, int s, int& line, int& k) {
+  constexpr int H = Fft<K>::H, L = Fft<K>::L;
+  if (ax == 2) { line = t / H; k = t % H + s * H; }
+  else { line = t % L; k = t / L + s * H; }
+}
+
+// Forward pass along axis ax (z: from the fixed-point grid; y: in place).
+template <int K>
+__global__ __launch_bounds__(256) void k_pme_fft_fwd(int ax, const unsigned long long* __restrict__ fix,
+                                                     double2* __restrict__ cg) {
+  constexpr int L = Fft<K>::L, LOG = Fft<K>::LOG;
+  __shared__ double2 sh[L * K];
+  __shared__ double2 tw[K / 2];
+  twiddles<K>(tw);
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    int line, k;
+    slot<K>(ax, t, s, line, k);
+    long base, stride;
+    line_geom<K>(ax, blockIdx.x * L + line, base, stride);
+    const long g = base + k * stride;
+    const double2 v = fix ? make_double2((double)(long long)fix[g] * (1.0 / kFix), 0.0) : cg[g];
+    sh[line * K + bitrev(k, LOG)] = v;
+  }
+  __syncthreads();
+  fft_dit<K>(sh, tw, 1.0);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    int line, k;
+    slot<K>(ax, t, s, line, k);
+    long base, stride;
+    line_geom<K>(ax, blockIdx.x * L + line, base, stride);
+    cg[base + k * stride] = sh[line * K + k];
+  }
+}
+
+// Spline modulus D(m) = |sum_{k=0}^{P-2} M_P(k+1) exp(2 pi i m k / K)|^2 for
+// m = 0..K-1 into D; where it vanishes (m = K/2, odd P) the mean of the
+// neighbours.
+template <int P, int K>
+__device__ __forceinline__ void spline_moduli(double* D) {
+  double mk[P];   // M_P(k + 1), k = 0..P-2: the table at w = 0 read backwards
+  {
+    double th[P][4];
+    bspline_table<P>(0.0, th);
+#pragma unroll
+    for (int k = 0; k < P - 1; ++k) mk[k] = th[k + 1][0];
+  }
+  for (int m = threadIdx.x; m < K; m += blockDim.x) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int k = 0; k < P - 1; ++k) {
+      double s, c;
+      sincospi(2.0 * ((long)m * k % K) / K, &s, &c);
+      sr += mk[k] * c;
+      si += mk[k] * s;
+    }
+    D[m] = sr * sr + si * si;
+  }
+  __syncthreads();
+  double fixv = 0.0;
+  const int m = threadIdx.x;
+  if (m < K && D[m] < 1e-10) fixv = 0.5 * (D[(m + K - 1) % K] + D[(m + 1) % K]);
+  __syncthreads();
+  if (m < K && fixv != 0.0) D[m] = fixv;
+  __syncthreads();
+}
+
+// Along x: forward transform (the grid is then fully transformed), multiply
+// by W(m) = (4 pi/k^2) exp(-k^2/(4 beta^2)) / (V D(m1) D(m2) D(m3)), W(0) = 0,
+// inverse transform, in place.
+template <int P, int K>
+__global__ __launch_bounds__(256) void k_pme_fft_conv(double2* __restrict__ cg, double box,
+                                                      double beta) {
+  constexpr int H = Fft<K>::H, L = Fft<K>::L, LOG = Fft<K>::LOG;
+  __shared__ double2 sh[L * K];
+  __shared__ double2 tw[K / 2];
+  __shared__ double D[K];
+  twiddles<K>(tw);
+  spline_moduli<P, K>(D);
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    int line, k;
+    slot<K>(0, t, s, line, k);
+    long base, stride;
+    line_geom<K>(0, blockIdx.x * L + line, base, stride);
+    sh[line * K + bitrev(k, LOG)] = cg[base + k * stride];
+  }
+  __syncthreads();
+  fft_dit<K>(sh, tw, 1.0);
+  {
+    const int line = t / H, b = t % H;
+    const int gl = blockIdx.x * L + line, m2 = gl / K, m3 = gl % K;
+    const double vol = box * box * box, f = 2.0 * kPi / box;
+    const int s2 = m2 <= K / 2 ? m2 : m2 - K, s3 = m3 <= K / 2 ? m3 : m3 - K;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int m1 = b + s * H;
+      const int s1 = m1 <= K / 2 ? m1 : m1 - K;
+      double W = 0.0;
+      if (s1 || s2 || s3) {
+        const double k2 = f * f * (double)(s1 * s1 + s2 * s2 + s3 * s3);
+        W = 4.0 * kPi / k2 * exp(-k2 / (4.0 * beta * beta)) / (vol * D[m1] * D[m2] * D[m3]);
+      }
+      double2& e = sh[line * K + m1];
+      e = make_double2(e.x * W, e.y * W);
+    }
+  }
+  __syncthreads();
+  fft_dif<K>(sh, tw, -1.0);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    int line, k;
+    slot<K>(0, t, s, line, k);
+    long base, stride;
+    line_geom<K>(0, blockIdx.x * L + line, base, stride);
+    cg[base + k * stride] = sh[line * K + bitrev(k, LOG)];
+  }
+}
+
+// Inverse pass along axis ax (y: in place; z: real part to phi).
+template <int K>
+__global__ __launch_bounds__(256) void k_pme_fft_inv(int ax, double2* __restrict__ cg,
+                                                     double* __restrict__ phi) {
+  constexpr int L = Fft<K>::L, LOG = Fft<K>::LOG;
+  __shared__ double2 sh[L * K];
+  __shared__ double2 tw[K / 2];
+  twiddles<K>(tw);
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    int line, k;
+    slot<K>(ax, t, s, line, k);
+    long base, stride;
+    line_geom<K>(ax, blockIdx.x * L + line, base, stride);
+    sh[line * K + k] = cg[base + k * stride];
+  }
+  __syncthreads();
+  fft_dif<K>(sh, tw, -1.0);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    int line, k;
+    slot<K>(ax, t, s, line, k);
+    long base, stride;
+    line_geom<K>(ax, blockIdx.x * L + line, base, stride);
+    const double2 v = sh[line * K + bitrev(k, LOG)];
+    if (phi) phi[base + k * stride] = v.x;
+    else cg[base + k * stride] = v;
+  }
+}
+
+// ---------------------------------------------------------------- gather
+// 8 lanes per site; lane t1 < P sums its plane of the P^3 points.  The
+// derivatives of the interpolated potential, D[dx][dy][dz] (dx+dy+dz <= 3),
+// are combined across the 8 lanes by three butterfly steps (fixed order).
+// Lane 0 of the group writes the force -C [q grad phi + (grad grad phi) mu +
+// (grad grad grad phi):Theta], the field -grad phi, and its site's energy
+// term q phi + mu.grad phi + Theta:grad grad phi into the block's partial.
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_gather(int n, const double* __restrict__ xyz,
+                                                    const double* __restrict__ mpole, double box,
+                                                    int K, const double* __restrict__ phi,
+                                                    double* __restrict__ force,
+                                                    double* __restrict__ field,
+                                                    double* __restrict__ epart) {
+  __shared__ double we[4];
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = gid >> 3, t1 = gid & 7;
+  const bool site = j0 < n;
+  const int j = site ? j0 : n - 1;
+  double X[4], th[2][P][4];
+  int i0[3];
+  site_splines<P>(xyz + 3 * j, box, K, t1, X, th, i0);
+  // S[dy][dz] over this lane's plane
+  double S[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) S[a][b] = 0.0;
+  if (site && t1 < P) {
+    const int gx = wrap(i0[0] - t1, K);
+#pragma unroll
+    for (int t2 = 0; t2 < P; ++t2) {
+      const long row = ((long)gx * K + wrap(i0[1] - t2, K)) * K;
+      double z[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t3 = 0; t3 < P; ++t3) {
+        const double v = phi[row + wrap(i0[2] - t3, K)];
+#pragma unroll
+        for (int dz = 0; dz < 4; ++dz) z[dz] += v * th[1][t3][dz];
+      }
+#pragma unroll
+      for (int dy = 0; dy < 4; ++dy)
+#pragma unroll
+        for (int dz = 0; dz < 4 - dy; ++dz) S[dy][dz] += th[0][t2][dy] * z[dz];
+    }
+  }
+  double Dv[4][4][4];
+#pragma unroll
+  for (int dx = 0; dx < 4; ++dx)
+#pragma unroll
+    for (int dy = 0; dy < 4; ++dy)
+#pragma unroll
+      for (int dz = 0; dz < 4; ++dz) {
+        if (dx + dy + dz > 3) {   // resolved at compile time (unrolled)
+          Dv[dx][dy][dz] = 0.0;
+          continue;
+        }
+        double v = site && t1 < P ? X[dx] * S[dy][dz] : 0.0;
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        Dv[dx][dy][dz] = v;
+      }
+  double e = 0.0;
+  if (site && t1 == 0) {
+    const double* m = mpole + 10 * j;
+    const double q = m[0], u[3] = {m[1], m[2], m[3]};
+    const double T[3][3] = {{m[4], m[5], m[6]}, {m[5], m[7], m[8]}, {m[6], m[8], m[9]}};
+    auto d1 = [&](int a) { return Dv[a == 0][a == 1][a == 2]; };
+    auto d2 = [&](int a, int b) {
+      return Dv[(a == 0) + (b == 0)][(a == 1) + (b == 1)][(a == 2) + (b == 2)];
+    };
+    auto d3 = [&](int a, int b, int c) {
+      return Dv[(a == 0) + (b == 0) + (c == 0)][(a == 1) + (b == 1) + (c == 1)]
+               [(a == 2) + (b == 2) + (c == 2)];
+    };
+    e = q * Dv[0][0][0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      e += u[a] * d1(a);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) e += T[a][b] * d2(a, b);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double g = q * d1(a);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        g += u[b] * d2(a, b);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g += T[b][c] * d3(a, b, c);
+      }
+      force[3 * j + a] = -kCoulomb * g;
+      if (field) field[3 * j + a] = -d1(a);
+    }
+  }
+  // block partial of the site energies: wave sums in lane order, then waves
+  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
+  if ((threadIdx.x & 63) == 0) we[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) epart[blockIdx.x] = ((we[0] + we[1]) + we[2]) + we[3];
+}
+
+// energy = (C/2) sum of the partials in block order; NaN if the spread refused
+// a contribution.
+__global__ __launch_bounds__(256) void k_pme_energy(const double* __restrict__ epart, int nb,
+                                                    const int* __restrict__ flag,
+                                                    double* __restrict__ energy) {
+  __shared__ double we[4];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += epart[b];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) we[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = ((we[0] + we[1]) + we[2]) + we[3];
+    energy[0] = flag[0] ? __builtin_nan("") : 0.5 * kCoulomb * t;
+  }
+}
+
+template <int P, int K>
+tk_status run_pme(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* mpole,
+                  double beta, double* energy, double* force, double* field) {
+  const long KK = (long)K * K * K;
+  const int n = sys->n;
+  const int nb = ceil_div((long)n * 8, 256);
+  void *fix, *cg, *phi, *epart, *flag;
+  tk_status s;
+  if ((s = scratch(ctx, per_stream("pme_fix", st).c_str(), sizeof(unsigned long long) * KK, &fix)) ||
+      (s = scratch(ctx, per_stream("pme_c", st).c_str(), sizeof(double2) * KK, &cg)) ||
+      (s = scratch(ctx, per_stream("pme_phi", st).c_str(), sizeof(double) * KK, &phi)) ||
+      (s = scratch(ctx, per_stream("pme_part", st).c_str(), sizeof(double) * (nb > 0 ? nb : 1),
+                   &epart)) ||
+      (s = scratch(ctx, per_stream("pme_flag", st).c_str(), sizeof(int) * 64, &flag)))
+    return s;
+  auto* fx = (unsigned long long*)fix;
+  auto* c2 = (double2*)cg;
+  const int nlines = K * K / Fft<K>::L;
+  {
+    ProfScope ps(ctx, st, "pme_spread");
+    k_pme_zero<<<ceil_div(KK, 256), 256, 0, st>>>(fx, KK, (int*)flag);
+    if (n > 0)
+      k_pme_spread<P><<<nb, 256, 0, st>>>(n, sys->xyz, mpole, sys->box, K, fx, (int*)flag);
+  }
+  {
+    ProfScope ps(ctx, st, "pme_fft");
+    k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(2, fx, c2);
+    k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(1, nullptr, c2);
+    k_pme_fft_conv<P, K><<<nlines, 256, 0, st>>>(c2, sys->box, beta);
+    k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(1, c2, nullptr);
+    k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(2, c2, (double*)phi);
+  }
+  {
+    ProfScope ps(ctx, st, "pme_gather");
+    if (n > 0)
+      k_pme_gather<P><<<nb, 256, 0, st>>>(n, sys->xyz, mpole, sys->box, K, (const double*)phi,
+                                           force, field, (double*)epart);
+    k_pme_energy<<<1, 256, 0, st>>>((const double*)epart, n > 0 ? nb : 0, (const int*)flag,
+                                    energy);
+  }
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+template <int P>
+tk_status run_pme_k(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* mpole,
+                    double beta, int K, double* energy, double* force, double* field) {
+  switch (K) {
+    case 16: return run_pme<P, 16>(ctx, st, sys, mpole, beta, energy, force, field);
+    case 32: return run_pme<P, 32>(ctx, st, sys, mpole, beta, energy, force, field);
+    case 64: return run_pme<P, 64>(ctx, st, sys, mpole, beta, energy, force, field);
+    case 128: return run_pme<P, 128>(ctx, st, sys, mpole, beta, energy, force, field);
+    default: return TK_E_ARG;
+  }
+}
+
+}  // namespace
+
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+tk_status tk_pme_mpole(tk_ctx* ctx, void* stream, const tk_system* sys, const double* mpole,
+                       double ewald_beta, int32_t grid, int32_t order, double* energy,
+                       double* force, double* field) {
+  if (!ctx) return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (!(ewald_beta > 0.0) || !std::isfinite(ewald_beta) || !energy) return TK_E_ARG;
+  if (grid != 16 && grid != 32 && grid != 64 && grid != 128) return TK_E_ARG;
+  if (order < 5 || order > 8 || grid < 2 * order) return TK_E_ARG;
+  if (sys->n > 0 && (!mpole || !force)) return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  switch (order) {
+    case 5: return run_pme_k<5>(ctx, st, sys, mpole, ewald_beta, grid, energy, force, field);
+    case 6: return run_pme_k<6>(ctx, st, sys, mpole, ewald_beta, grid, energy, force, field);
+    case 7: return run_pme_k<7>(ctx, st, sys, mpole, ewald_beta, grid, energy, force, field);
+    default: return run_pme_k<8>(ctx, st, sys, mpole, ewald_beta, grid, energy, force, field);
+  }
+}
+
+}  // extern "C"

@@ -103,6 +103,7 @@ _SIGS = {
                         _i32, C.c_int, _vp, _vp, C.POINTER(PcgInfo)],
     "tk_epolar_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
                        _d, C.c_int, _vp, _vp, _vp],
+    "tk_pme_mpole": [_vp, _vp, C.POINTER(System), _vp, _d, _i32, _i32, _vp, _vp, _vp],
     "tk_evdw": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), C.c_int, _vp, _vp, _d, _d, _d, _d,
                 C.c_int, _vp, _vp, _vp],
     "tk_batch_step": [_vp, _vp, C.POINTER(Batch), C.POINTER(StepParams), _vp, _vp, _vp, _vp, _vp,
@@ -328,6 +329,17 @@ class Context:
                                      C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), _ptr(m), beta,
                                      cutoff, prec, _ptr(e), _ptr(f), _ptr(w)), "tk_epolar_real")
         return e, f, w
+
+    def pme_mpole(self, sysref, mpole, beta, grid, order=5, want_field=True):
+        mp = _dev(mpole, torch.float64, self.device)
+        e = torch.empty(1, dtype=torch.float64, device=self.device)
+        f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        fld = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device) if want_field \
+            else None
+        _check(load().tk_pme_mpole(self._h, _stream(self.device), C.byref(sysref.c), _ptr(mp), beta,
+                                   int(grid), int(order), _ptr(e), _ptr(f),
+                                   None if fld is None else _ptr(fld)), "tk_pme_mpole")
+        return e, f, fld
 
     def evdw(self, sysref, lst, form, rad, eps, cutoff, taper_frac=0.9, dhal=0.07, ghal=0.12,
              prec=FP64):

@@ -1,0 +1,105 @@
+"""Reciprocal-space PME (tk_pme_mpole) against the FP64 CPU oracle's smooth
+PME on the same grid and spline order: energy within 1e-10 relative, forces
+and field within 1e-8 of their RMS; determinism, edge cases and errors."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_01211_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+S = synth.AMOEBA_SETTINGS
+_cache = {}
+
+
+@pytest.fixture(scope="module")
+def tk():
+    import torch
+    from paper_1906_01211_amd import tk as _tk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _tk.load()
+    return _tk
+
+
+@pytest.fixture(scope="module")
+def ctx(tk):
+    c = tk.Context(0)
+    yield c
+    c.close()
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def fmax_rel(got, ref):
+    return np.abs(np.asarray(got) - ref).max() / np.sqrt(np.mean(ref ** 2))
+
+
+def check(ctx, xyz, box, mpole, beta, K, p):
+    sysr = ctx.system(xyz, box, np.zeros(len(xyz), np.int32))
+    print(f"pme n={len(xyz)} K={K} p={p}", flush=True)
+    e, f, fld = ctx.pme_mpole(sysr, mpole, beta, K, p)
+    eo, fo, fldo = O.pme_mpole(xyz, box, mpole, beta, K, p)
+    assert abs(np_(e)[0] - eo) <= 1e-10 * abs(eo), (np_(e)[0], eo)
+    assert fmax_rel(np_(f), fo) < 1e-8
+    assert fmax_rel(np_(fld), fldo) < 1e-8
+    return e, f, fld
+
+
+@pytest.mark.parametrize("K,p", [(16, 5), (32, 5), (32, 8), (16, 6), (16, 7)])
+def test_pme_water216(ctx, K, p):
+    w = _cache.setdefault("water216", synth.make("water216"))
+    check(ctx, w.xyz, w.box, w.mpole, S["beta"], K, p)
+
+
+def test_pme_water7853_grid64(ctx):
+    w = _cache.setdefault("water7853", synth.make("water7853"))
+    check(ctx, w.xyz, w.box, w.mpole, S["beta"], 64, 5)
+
+
+@pytest.mark.parametrize("n,box,seed", [(1, 12.0, 0), (7, 10.0, 1), (300, 20.0, 2)])
+def test_pme_random_sites(ctx, n, box, seed):
+    # sites anywhere (negative coordinates and several boxes away included)
+    rng = np.random.default_rng(seed)
+    xyz = rng.uniform(-2 * box, 3 * box, size=(n, 3))
+    m = rng.normal(0, 0.3, size=(n, 10))
+    m[:, 9] = -(m[:, 4] + m[:, 7])
+    check(ctx, xyz, box, m, 0.45, 32, 5)
+
+
+def test_pme_grid128(ctx):
+    w = _cache.setdefault("water216", synth.make("water216"))
+    rng = np.random.default_rng(4)
+    idx = rng.choice(w.n, 60, replace=False)
+    check(ctx, w.xyz[idx], w.box, w.mpole[idx], S["beta"], 128, 5)
+
+
+def test_pme_deterministic_and_no_field(ctx):
+    w = _cache.setdefault("water7853", synth.make("water7853"))
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    e1, f1, fl1 = ctx.pme_mpole(sysr, w.mpole, S["beta"], 64, 5)
+    e2, f2, fl2 = ctx.pme_mpole(sysr, w.mpole, S["beta"], 64, 5, want_field=False)
+    assert fl2 is None
+    assert np.array_equal(np_(e1), np_(e2)) and np.array_equal(np_(f1), np_(f2))
+
+
+def test_pme_edge_cases_and_errors(ctx, tk):
+    empty = ctx.system(np.zeros((0, 3)), 20.0, np.zeros(0, np.int32))
+    e, f, _ = ctx.pme_mpole(empty, np.zeros((0, 10)), S["beta"], 16, 5)
+    assert np_(e)[0] == 0.0 and f.shape == (0, 3)
+    w = _cache.setdefault("water216", synth.make("water216"))
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    for K, p, beta in ((48, 5, S["beta"]), (16, 4, S["beta"]), (16, 9, S["beta"]),
+                       (8, 5, S["beta"]), (16, 5, 0.0)):
+        with pytest.raises(tk.TkError):
+            ctx.pme_mpole(sysr, w.mpole, beta, K, p)
+    # a contribution outside the fixed-point range gives a NaN energy, not a wrong number
+    big = w.mpole.copy()
+    big[5, 0] = 1e6
+    e, _, _ = ctx.pme_mpole(sysr, big, S["beta"], 16, 5)
+    assert np.isnan(np_(e)[0])
+    # and the next call with ordinary input is clean again
+    check(ctx, w.xyz, w.box, w.mpole, S["beta"], 16, 5)
