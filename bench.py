@@ -256,8 +256,8 @@ def main():
 
 
 def extras(ctx, tk, w, a, prec, n7):
-    """Mixed-vs-FP64 step, the charge + LJ path and the polarization forces
-    (not part of `value`)."""
+    """Mixed-vs-FP64 step, the charge + LJ path, the polarization forces and
+    the reciprocal-space PME (not part of `value`)."""
     import torch
     res = {}
     other = tk.MIXED if prec == tk.FP64 else tk.FP64
@@ -283,7 +283,38 @@ def extras(ctx, tk, w, a, prec, n7):
         res["charge_lj_pairs_12A"] = int(l12.npairs)
         res[f"charge_lj_pairs_per_s_{name}"] = 2 * l12.npairs / (ms * 1e-3)
     res["epolar"] = epolar_leg(ctx, tk, w, n7)
+    res["pme"] = pme_leg(ctx, tk, w)
     return res
+
+
+def pme_leg(ctx, tk, w, grid=64, order=5):
+    """Reciprocal-space multipoles by smooth PME on the water box (64^3 mesh,
+    order-5 splines): whole call and its three stages (spread, the five FFT
+    passes with the convolution, gather + energy)."""
+    import torch
+    s = synth.AMOEBA_SETTINGS
+    sysw = ctx.system(w.xyz, w.box, w.molid)
+    mp = torch.as_tensor(w.mpole, device=ctx.device)
+
+    def call():
+        ctx.pme_mpole(sysw, mp, s["beta"], grid, order)
+    ms = timed(call, 20, 3) * 1e3
+    ctx.profile(True)
+    timed(call, 20, 0)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    out = {"grid": grid, "order": order, "atoms": w.n, "call_ms": round(ms, 4)}
+    for k in ("pme_spread", "pme_fft", "pme_gather"):
+        if k in prof:
+            out[k + "_us"] = round(prof[k]["ms"] / prof[k]["launches"] * 1e3, 2)
+    # the five FFT passes each read and write the complex mesh (the first reads
+    # the 8-byte fixed-point mesh, the last writes the 8-byte real potential)
+    kk = grid ** 3
+    fft_bytes = kk * (8 + 16) + 3 * kk * 32 + kk * (16 + 8)
+    if "pme_fft_us" in out:
+        out["fft_bytes"] = fft_bytes
+        out["fft_hbm_frac"] = round(fft_bytes / (out["pme_fft_us"] * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
+    return out
 
 
 def epolar_leg(ctx, tk, w, n7):

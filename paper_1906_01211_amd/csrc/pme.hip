@@ -4,13 +4,13 @@
 // with cardinal B-splines of order P, extended to dipoles and quadrupoles by
 // differentiating the spline.
 //
-// One call: zero -> spread -> FFT along z, y -> [FFT along x, multiply by the
+// One call: bin sites by x -> spread by mesh tiles -> FFT along z, y -> [FFT along x, multiply by the
 // influence function, inverse FFT along x] -> inverse FFT along y, z ->
 // gather (potential derivatives up to third order at every site) -> energy.
 //
 // The spread grid is accumulated in 64-bit fixed point (2^-40 units) with
-// integer atomics: integer addition is associative, so the grid, and every
-// result after it, is bitwise the same run to run.  A single contribution of
+// LDS integer atomics: integer addition is associative, so the grid, and
+// every result after it, is bitwise the same run to run.  A single contribution of
 // magnitude 2^17 or more is refused (the energy comes back NaN); below that
 // the sums of up to 2^6 such contributions at one point stay exact.
 //
@@ -52,7 +52,7 @@ __device__ __forceinline__ void bspline_table(double w, double th[P][4]) {
       const double x = w + t;
       const double lo = t < k - 1 ? A[k - 1][t] : 0.0;
       const double hi = t > 0 ? A[k - 1][t - 1] : 0.0;
-      A[k][t] = (x * lo + (k - x) * hi) / (k - 1);
+      A[k][t] = (x * lo + (k - x) * hi) * (1.0 / (k - 1));
     }
 #pragma unroll
   for (int t = 0; t < P; ++t) {
@@ -78,7 +78,7 @@ __device__ __forceinline__ void site_splines(const double* x, double box, int K,
     const double s = x[a] / box;
     const double u = K * (s - floor(s));
     const double fl = floor(u);
-    i0[a] = (int)fl;
+    i0[a] = fl >= 0.0 && fl <= K ? (int)fl : 0;   // NaN: any in-range index (weights NaN)
     double t4[P][4];
     bspline_table<P>(u - fl, t4);
     if (a == 0) {
@@ -100,50 +100,159 @@ __device__ __forceinline__ void site_splines(const double* x, double box, int K,
 
 __device__ __forceinline__ int wrap(int g, int K) { return ((g % K) + K) % K; }
 
-__global__ __launch_bounds__(256) void k_pme_zero(unsigned long long* __restrict__ grid, long n,
-                                                  int* __restrict__ flag) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) grid[i] = 0ull;
-  if (i == 0) flag[0] = 0;
+// The spread is owned by mesh tiles: sites are binned by their x grid index
+// (a counting sort; the order inside a bin does not matter, integer sums being
+// exact), and one workgroup per tile (a whole x-plane; half a plane at
+// K = 128, to fit the LDS) adds, in LDS,
+// the contributions of the sites whose x-row reaches its plane (bins gx..gx+P-1),
+// then stores the tile.  No global atomics, and every mesh point is written
+// once, so the mesh needs no clearing.
+constexpr int kSpreadThreads = 1024;   // one workgroup per spread tile
+
+// The x grid index of the spline code, mod K (a fraction that rounds up to
+// 1 gives K, i.e. 0).  A non-finite coordinate maps to bin 0: its weights are
+// NaN, which the spread refuses (the energy comes back NaN).
+__device__ __forceinline__ int xbin(const double* x, double box, int K) {
+  const double s = x[0] / box;
+  const double f = floor(K * (s - floor(s)));
+  return f >= 0.0 && f < K ? (int)f : 0;
 }
 
-// Spread: 8 lanes per site, lane t1 < P takes the P x P points of plane t1.
+// Counting sort by x-bin without global atomics: each block of 256 sites
+// counts its bins in LDS (slot = rank inside its block and bin) and stores its
+// counts; block 0 also clears the refusal flag.
+__global__ __launch_bounds__(256) void k_pme_bin(int n, const double* __restrict__ xyz, double box,
+                                                 int K, int* __restrict__ bcnt,
+                                                 int* __restrict__ bin, int* __restrict__ slot,
+                                                 int* __restrict__ flag) {
+  __shared__ int h[128];
+  if ((int)threadIdx.x < K) h[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 0;
+  __syncthreads();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
+    const int b = xbin(xyz + 3 * j, box, K);
+    bin[j] = b;
+    slot[j] = atomicAdd(&h[b], 1);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < K) bcnt[blockIdx.x * K + threadIdx.x] = h[threadIdx.x];
+}
+
+// Same blocks as k_pme_bin: per bin, the total over all blocks and the count
+// in the blocks before this one; the exclusive prefix of the totals gives the
+// bin starts (stored by block 0, start[0..K]).
+__global__ __launch_bounds__(256) void k_pme_scatter(int n, int K, int nblk,
+                                                     const int* __restrict__ bcnt,
+                                                     const int* __restrict__ bin,
+                                                     const int* __restrict__ slot,
+                                                     int* __restrict__ start,
+                                                     int* __restrict__ list) {
+  __shared__ int tot[256], off[256], pre[129];
+  {
+    // thread (r, b): bin b = tid % K, blocks q = r, r + R, ... (R = 256 / K)
+    const int R = (int)blockDim.x / K, b = threadIdx.x % K, r = threadIdx.x / K;
+    int t = 0, o = 0;
+#pragma unroll 4
+    for (int q = r; q < nblk; q += R) {
+      const int c = bcnt[q * K + b];
+      t += c;
+      o += q < (int)blockIdx.x ? c : 0;
+    }
+    tot[threadIdx.x] = t;
+    off[threadIdx.x] = o;
+    __syncthreads();
+    if (r == 0) {
+      for (int k = 1; k < R; ++k) {
+        t += tot[k * K + b];
+        o += off[k * K + b];
+      }
+    }
+    __syncthreads();
+    if (r == 0) {
+      tot[b] = t;
+      off[b] = o;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b < K; ++b) {
+      pre[b] = acc;
+      acc += tot[b];
+    }
+    pre[K] = acc;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && (int)threadIdx.x <= K) start[threadIdx.x] = pre[threadIdx.x];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
+    const int b = bin[j];
+    list[pre[b] + off[b] + slot[j]] = j;
+  }
+}
+
 //   Q(g) += q M + mu.grad M + Theta:grad grad M   at M = M(u - g)
-template <int P>
-__global__ __launch_bounds__(256) void k_pme_spread(int n, const double* __restrict__ xyz,
+template <int K>
+constexpr int spread_rows() { return K <= 64 ? K : K / 2; }
+
+template <int P, int K>
+__global__ __launch_bounds__(kSpreadThreads) void k_pme_spread(const double* __restrict__ xyz,
                                                     const double* __restrict__ mpole, double box,
-                                                    int K, unsigned long long* __restrict__ grid,
+                                                    const int* __restrict__ start,
+                                                    const int* __restrict__ list,
+                                                    unsigned long long* __restrict__ grid,
                                                     int* __restrict__ flag) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = gid >> 3, t1 = gid & 7;
-  if (j >= n || t1 >= P) return;
-  double X[4], th[2][P][4];
-  int i0[3];
-  site_splines<P>(xyz + 3 * j, box, K, t1, X, th, i0);
-  const double* m = mpole + 10 * j;
-  const double q = m[0], ux = m[1], uy = m[2], uz = m[3];
-  const double txx = m[4], txy = m[5], txz = m[6], tyy = m[7], tyz = m[8], tzz = m[9];
-  const int gx = wrap(i0[0] - t1, K);
+  constexpr int YB = spread_rows<K>();
+  constexpr int NYB = K / YB;
+  __shared__ unsigned long long tile[YB * K];
+  const int gx = blockIdx.x / NYB, y0 = (blockIdx.x % NYB) * YB;
+  for (int i = threadIdx.x; i < YB * K; i += blockDim.x) tile[i] = 0ull;
+  __syncthreads();
   bool bad = false;
+#pragma unroll 1
+  for (int t1 = 0; t1 < P; ++t1) {
+    const int b = (gx + t1) % K;
+    const int s1 = start[b + 1];
+#pragma unroll 1
+    for (int s = start[b] + threadIdx.x; s < s1; s += blockDim.x) {
+      const int j = list[s];
+      if (NYB > 1) {   // rows i0y - t2 (t2 < P) miss this tile: skip the spline work
+        const double sy = xyz[3 * j + 1] / box;
+        const double fy = floor(K * (sy - floor(sy)));
+        const int iy = fy >= 0.0 && fy <= K ? (int)fy : 0;
+        if (wrap(iy - y0, K) >= YB + P - 1) continue;
+      }
+      double X[4], th[2][P][4];
+      int i0[3];
+      site_splines<P>(xyz + 3 * j, box, K, t1, X, th, i0);
+      const double* m = mpole + 10 * j;
+      const double q = m[0], ux = m[1], uy = m[2], uz = m[3];
+      const double txx = m[4], txy = m[5], txz = m[6], tyy = m[7], tyz = m[8], tzz = m[9];
 #pragma unroll
-  for (int t2 = 0; t2 < P; ++t2) {
-    const int gy = wrap(i0[1] - t2, K);
-    const double* Y = th[0][t2];
+      for (int t2 = 0; t2 < P; ++t2) {
+        const int ly = wrap(i0[1] - t2 - y0, K);
+        if (ly >= YB) continue;
+        const double* Y = th[0][t2];
 #pragma unroll
-    for (int t3 = 0; t3 < P; ++t3) {
-      const double* Z = th[1][t3];
-      const double v = q * X[0] * Y[0] * Z[0] +
-                       ux * X[1] * Y[0] * Z[0] + uy * X[0] * Y[1] * Z[0] + uz * X[0] * Y[0] * Z[1] +
-                       txx * X[2] * Y[0] * Z[0] + tyy * X[0] * Y[2] * Z[0] + tzz * X[0] * Y[0] * Z[2] +
-                       2.0 * (txy * X[1] * Y[1] * Z[0] + txz * X[1] * Y[0] * Z[1] +
-                              tyz * X[0] * Y[1] * Z[1]);
-      bad |= !(fabs(v) < kFixMax);
-      const long long iv = bad ? 0ll : llrint(v * kFix);
-      const int g = (gx * K + gy) * K + wrap(i0[2] - t3, K);
-      atomicAdd(&grid[g], (unsigned long long)iv);
+        for (int t3 = 0; t3 < P; ++t3) {
+          const double* Z = th[1][t3];
+          const double v =
+              q * X[0] * Y[0] * Z[0] +
+              ux * X[1] * Y[0] * Z[0] + uy * X[0] * Y[1] * Z[0] + uz * X[0] * Y[0] * Z[1] +
+              txx * X[2] * Y[0] * Z[0] + tyy * X[0] * Y[2] * Z[0] + tzz * X[0] * Y[0] * Z[2] +
+              2.0 * (txy * X[1] * Y[1] * Z[0] + txz * X[1] * Y[0] * Z[1] + tyz * X[0] * Y[1] * Z[1]);
+          bad |= !(fabs(v) < kFixMax);
+          const long long iv = bad ? 0ll : llrint(v * kFix);
+          atomicAdd(&tile[ly * K + wrap(i0[2] - t3, K)], (unsigned long long)iv);
+        }
+      }
     }
   }
   if (bad) atomicOr(flag, 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < YB * K; i += blockDim.x)
+    grid[((long)gx * K + y0 + i / K) * K + i % K] = tile[i];
 }
 
 // ---------------------------------------------------------------- FFT
@@ -501,9 +610,12 @@ tk_status run_pme(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const doubl
   const long KK = (long)K * K * K;
   const int n = sys->n;
   const int nb = ceil_div((long)n * 8, 256);
-  void *fix, *cg, *phi, *epart, *flag;
+  void *fix, *cg, *phi, *epart, *flag, *bins;
   tk_status s;
+  const size_t nn = n > 0 ? n : 1;
   if ((s = scratch(ctx, per_stream("pme_fix", st).c_str(), sizeof(unsigned long long) * KK, &fix)) ||
+      (s = scratch(ctx, per_stream("pme_bins", st).c_str(),
+                   sizeof(int) * (3 * nn + (size_t)(ceil_div(n, 256) + 1) * K + K + 2), &bins)) ||
       (s = scratch(ctx, per_stream("pme_c", st).c_str(), sizeof(double2) * KK, &cg)) ||
       (s = scratch(ctx, per_stream("pme_phi", st).c_str(), sizeof(double) * KK, &phi)) ||
       (s = scratch(ctx, per_stream("pme_part", st).c_str(), sizeof(double) * (nb > 0 ? nb : 1),
@@ -513,11 +625,18 @@ tk_status run_pme(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const doubl
   auto* fx = (unsigned long long*)fix;
   auto* c2 = (double2*)cg;
   const int nlines = K * K / Fft<K>::L;
+  const int na = n > 0 ? ceil_div(n, 256) : 1;   // sort blocks (one even when empty)
+  int* bcnt = (int*)bins;
+  int* start = bcnt + (size_t)na * K;
+  int* bin = start + K + 1;
+  int* slot = bin + nn;
+  int* list = slot + nn;
   {
     ProfScope ps(ctx, st, "pme_spread");
-    k_pme_zero<<<ceil_div(KK, 256), 256, 0, st>>>(fx, KK, (int*)flag);
-    if (n > 0)
-      k_pme_spread<P><<<nb, 256, 0, st>>>(n, sys->xyz, mpole, sys->box, K, fx, (int*)flag);
+    k_pme_bin<<<na, 256, 0, st>>>(n, sys->xyz, sys->box, K, bcnt, bin, slot, (int*)flag);
+    k_pme_scatter<<<na, 256, 0, st>>>(n, K, na, bcnt, bin, slot, start, list);
+    k_pme_spread<P, K><<<K * (K / spread_rows<K>()), kSpreadThreads, 0, st>>>(
+        sys->xyz, mpole, sys->box, start, list, fx, (int*)flag);
   }
   {
     ProfScope ps(ctx, st, "pme_fft");

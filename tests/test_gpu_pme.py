@@ -101,5 +101,10 @@ def test_pme_edge_cases_and_errors(ctx, tk):
     big[5, 0] = 1e6
     e, _, _ = ctx.pme_mpole(sysr, big, S["beta"], 16, 5)
     assert np.isnan(np_(e)[0])
+    # a non-finite coordinate: NaN energy as well
+    bad = w.xyz.copy()
+    bad[7, 0] = np.nan
+    e, _, _ = ctx.pme_mpole(ctx.system(bad, w.box, w.molid), w.mpole, S["beta"], 16, 5)
+    assert np.isnan(np_(e)[0])
     # and the next call with ordinary input is clean again
     check(ctx, w.xyz, w.box, w.mpole, S["beta"], 16, 5)
