@@ -80,6 +80,10 @@ def lib():
         L.or_spline_mod.restype = C.c_double
         L.or_pme_mpole.argtypes = [C.c_int, _dp, C.c_double, _dp, C.c_double, C.c_int, C.c_int,
                                    C.POINTER(C.c_double), _dp, C.c_void_p]
+        L.or_polarize_pcg_ewald.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp,
+                                            _dp, C.c_double, C.c_double, C.c_int, C.c_int,
+                                            C.c_double, C.c_int, C.c_void_p, _dp,
+                                            C.POINTER(PcgInfo)]
         _lib = L
     return _lib
 
@@ -242,6 +246,27 @@ def polarize_pcg(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta, 
     st = lib().or_polarize_pcg(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _d(mpole),
                                _d(polarity), _d(thole_a), beta, cutoff, tol_debye, int(maxiter),
                                guess, mu, C.byref(info))
+    if st not in (OK, E_NOCONV, E_BREAKDOWN):
+        raise OracleError(st)
+    return mu, {k: getattr(info, k) for k, _ in PcgInfo._fields_}
+
+
+def polarize_pcg_ewald(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta, cutoff,
+                       grid, order=5, tol_debye=1e-5, maxiter=100, mu_guess=None):
+    """The solve with the full Ewald operator (PME reciprocal part on a grid^3
+    mesh); returns (mu[n,3], info dict) as polarize_pcg."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    mu = np.zeros((n, 3))
+    info = PcgInfo()
+    guess = None
+    if mu_guess is not None:
+        guess_arr = _d(mu_guess)
+        guess = guess_arr.ctypes.data_as(C.c_void_p)
+    st = lib().or_polarize_pcg_ewald(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _d(mpole),
+                                     _d(polarity), _d(thole_a), beta, cutoff, int(grid),
+                                     int(order), tol_debye, int(maxiter), guess, mu,
+                                     C.byref(info))
     if st not in (OK, E_NOCONV, E_BREAKDOWN):
         raise OracleError(st)
     return mu, {k: getattr(info, k) for k, _ in PcgInfo._fields_}

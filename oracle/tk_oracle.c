@@ -507,11 +507,50 @@ static double or_rmsd(int n, const double* z, int npol) {
   return OR_DEBYE * sqrt(s / npol);
 }
 
-int or_polarize_pcg(int n, const double* xyz, double box, const int32_t* molid,
-                    const int32_t* row_ptr, const int32_t* col, const double* mpole,
-                    const double* polarity, const double* thole, double beta, double rc,
-                    double tol_debye, int maxiter, const double* mu_guess, double* mu_out,
-                    or_pcg_info* info) {
+/* Optional reciprocal-space part of the polarization equations (the full
+ * Ewald operator): the smooth-PME field of the dipoles themselves is added to
+ * the dipole field of the operator, and the PME field of the permanent
+ * multipoles to the right-hand side.  K = 0: real space only. */
+typedef struct {
+  int K, p;
+} or_recip;
+
+int or_pme_mpole(int n, const double* xyz, double box, const double* mpole, double beta, int K,
+                 int p, double* energy, double* force, double* field);
+
+/* PME field of dipoles v (no charges or quadrupoles) into fld. */
+static void or_recip_dipole_field(int n, const double* xyz, double box, double beta,
+                                  const or_recip* rp, const double* v, double* fld) {
+  double* m = (double*)calloc((size_t)(n > 0 ? n : 1) * 10, sizeof(double));
+  double* f = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+  double e;
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) m[10 * i + 1 + a] = v[3 * i + a];
+  or_pme_mpole(n, xyz, box, m, beta, rp->K, rp->p, &e, f, fld);
+  free(m);
+  free(f);
+}
+
+/* out = A v: the real-space operator of or_tmatvec minus, with a reciprocal
+ * part, the PME dipole field (rows of alpha = 0 stay zero). */
+static void or_apply_A(int n, const double* xyz, double box, const int32_t* row_ptr,
+                       const int32_t* col, const double* polarity, const double* thole,
+                       double beta, double rc, const or_recip* rp, const double* v, double* out) {
+  or_tmatvec(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, 1, v, out);
+  if (!rp) return;
+  double* fld = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+  or_recip_dipole_field(n, xyz, box, beta, rp, v, fld);
+  for (int i = 0; i < n; ++i)
+    if (polarity[i] > 0.0)
+      for (int a = 0; a < 3; ++a) out[3 * i + a] -= fld[3 * i + a];
+  free(fld);
+}
+
+static int or_pcg(int n, const double* xyz, double box, const int32_t* molid,
+                  const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                  const double* polarity, const double* thole, double beta, double rc,
+                  const or_recip* rp, double tol_debye, int maxiter, const double* mu_guess,
+                  double* mu_out, or_pcg_info* info) {
   int st = or_pair_args(n, box, rc);
   if (st) return st;
   if (maxiter < 0 || !(tol_debye >= 0.0)) return OR_E_ARG;
@@ -527,12 +566,21 @@ int or_polarize_pcg(int n, const double* xyz, double box, const int32_t* molid,
   int npol = 0;
   for (int i = 0; i < n; ++i) npol += polarity[i] > 0.0;
   or_efield_direct(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, b);
+  if (rp) {
+    double e;
+    double* f = (double*)malloc(sizeof(double) * m);
+    double* fr = (double*)malloc(sizeof(double) * m);
+    or_pme_mpole(n, xyz, box, mpole, beta, rp->K, rp->p, &e, f, fr);
+    for (int k = 0; k < 3 * n; ++k) b[k] += fr[k];
+    free(f);
+    free(fr);
+  }
   for (int i = 0; i < n; ++i)
     for (int a = 0; a < 3; ++a) {
       int k = 3 * i + a;
       x[k] = mu_guess ? (polarity[i] > 0.0 ? mu_guess[k] : 0.0) : polarity[i] * b[k];
     }
-  or_tmatvec(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, 1, x, q);
+  or_apply_A(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, rp, x, q);
   double rho = 0.0;
   for (int i = 0; i < n; ++i)
     for (int a = 0; a < 3; ++a) {
@@ -548,7 +596,7 @@ int or_polarize_pcg(int n, const double* xyz, double box, const int32_t* molid,
     rms = or_rmsd(n, z, npol);
     if (rms <= tol_debye) { converged = 1; break; }
     if (it == maxiter) { status = OR_E_NOCONV; break; }
-    or_tmatvec(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, 1, p, q);
+    or_apply_A(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, rp, p, q);
     double gam = 0.0;
     for (int k = 0; k < 3 * n; ++k) gam += p[k] * q[k];
     if (!(gam > 0.0)) { status = OR_E_BREAKDOWN; break; }
@@ -566,7 +614,7 @@ int or_polarize_pcg(int n, const double* xyz, double box, const int32_t* molid,
     rho = rho1;
   }
   /* final true residual, from a fresh mat-vec */
-  or_tmatvec(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, 1, x, q);
+  or_apply_A(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, rp, x, q);
   for (int i = 0; i < n; ++i)
     for (int a = 0; a < 3; ++a) {
       int k = 3 * i + a;
@@ -583,6 +631,30 @@ int or_polarize_pcg(int n, const double* xyz, double box, const int32_t* molid,
   info->epol = -0.5 * OR_COULOMB * epol;
   free(b); free(r); free(z); free(p); free(q);
   return status;
+}
+
+int or_polarize_pcg(int n, const double* xyz, double box, const int32_t* molid,
+                    const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                    const double* polarity, const double* thole, double beta, double rc,
+                    double tol_debye, int maxiter, const double* mu_guess, double* mu_out,
+                    or_pcg_info* info) {
+  return or_pcg(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, NULL,
+                tol_debye, maxiter, mu_guess, mu_out, info);
+}
+
+/* The same solve with the full Ewald operator: the PME reciprocal field of
+ * the dipoles (grid K, order p) in A, that of the permanent multipoles in the
+ * right-hand side (E_perm = real-space field + self field + reciprocal
+ * field).  E_pol = -1/2 C mu.E_perm with the full field. */
+int or_polarize_pcg_ewald(int n, const double* xyz, double box, const int32_t* molid,
+                          const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                          const double* polarity, const double* thole, double beta, double rc,
+                          int K, int p, double tol_debye, int maxiter, const double* mu_guess,
+                          double* mu_out, or_pcg_info* info) {
+  if (!(beta > 0.0) || K < 2 * p || p < 5 || p > 8) return OR_E_ARG;
+  or_recip rp = {K, p};
+  return or_pcg(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, &rp,
+                tol_debye, maxiter, mu_guess, mu_out, info);
 }
 
 /* ------------------------------------------------------------------------ */

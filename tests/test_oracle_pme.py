@@ -157,3 +157,57 @@ def test_pme_grid_shift_invariance_and_arguments():
     for K_, p_ in ((8, 5), (16, 4), (20, 9)):
         with pytest.raises(O.OracleError):
             O.pme_mpole(w.xyz, w.box, w.mpole, beta, K_, p_)
+
+
+# ---------------------------------------------------------------- full-Ewald polarization
+def _ewald_box():
+    w = small_box()
+    rc = 4.69
+    rp, cp = O.nblist(w.xyz, w.box, rc)
+    return w, rp, cp, rc
+
+
+def _apply_full(w, rp, cp, rc, beta, K, p, v):
+    """A v of the full operator from the separately pinned pieces."""
+    Av = O.tmatvec(w.xyz, w.box, rp, cp, w.polarity, w.thole, beta, rc, v, include_diag=1)
+    m = np.zeros((w.n, 10))
+    m[:, 1:4] = v
+    _, _, fld = O.pme_mpole(w.xyz, w.box, m, beta, K, p)
+    return Av - np.where(w.polarity[:, None] > 0, fld, 0.0)
+
+
+def test_ewald_pcg_solves_the_composed_system():
+    # the converged dipoles satisfy A x = E_perm with A and E_perm composed of
+    # the real-space mat-vec, the permanent field and the PME fields
+    w, rp, cp, rc = _ewald_box()
+    beta, K, p = 0.9, 16, 5
+    mu, info = O.polarize_pcg_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                    beta, rc, K, p, tol_debye=1e-11, maxiter=200)
+    assert info["converged"] == 1
+    b = O.efield_direct(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, beta, rc)
+    b += O.pme_mpole(w.xyz, w.box, w.mpole, beta, K, p)[2]
+    r = b - _apply_full(w, rp, cp, rc, beta, K, p, mu)
+    assert DEBYE * np.sqrt(np.sum((w.polarity[:, None] * r) ** 2) / w.n) < 1e-10
+    assert info["epol"] == pytest.approx(-0.5 * C * np.sum(mu * b), rel=1e-12)
+    # the composed operator is symmetric (PME spreads and gathers with the same splines)
+    rng = np.random.default_rng(5)
+    u, v = rng.normal(size=(2, w.n, 3))
+    Au = _apply_full(w, rp, cp, rc, beta, K, p, u)
+    Av = _apply_full(w, rp, cp, rc, beta, K, p, v)
+    assert np.sum(u * Av) == pytest.approx(np.sum(v * Au), rel=1e-12)
+
+
+def test_ewald_polarization_energy_does_not_depend_on_the_split():
+    # with the reciprocal part the polarization energy is the physical one:
+    # changing beta moves work between real and reciprocal space only (here
+    # limited by the PME error, ~1e-6); without it the energy moves by far more
+    w, rp, cp, rc = _ewald_box()
+    e = []
+    for beta, K in ((0.9, 32), (1.0, 40)):
+        _, info = O.polarize_pcg_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity,
+                                       w.thole, beta, rc, K, 8, tol_debye=1e-10, maxiter=200)
+        e.append(info["epol"])
+    assert e[0] == pytest.approx(e[1], rel=2e-6)
+    real = [O.polarize_pcg(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, beta, rc,
+                           tol_debye=1e-10, maxiter=200)[1]["epol"] for beta in (0.9, 1.0)]
+    assert abs(real[0] - real[1]) > 1e3 * abs(e[0] - e[1])
