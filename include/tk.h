@@ -225,6 +225,25 @@ tk_status tk_polarize_pcg(tk_ctx* ctx, void* stream, const tk_system* sys, const
                           int prec, const double* mu_guess, double* mu_out, tk_pcg_info* info);
 
 /*
+ * Induced dipoles with the full Ewald operator: tk_polarize_pcg with the
+ * reciprocal space included (the reciprocal polarization routine named in
+ * section "Hotspots").  The operator is A = diag(1/alpha) - T - cI - R, R mu
+ * the smooth-PME field of the dipoles themselves (as tk_pme_mpole's field with
+ * mu as the only multipoles, each site's own contribution included), and the
+ * right-hand side is E_perm = tk_efield_direct's field + the PME field of the
+ * permanent multipoles.  Rows of atoms with alpha = 0 stay zero.  Same
+ * stopping rule, guess, outputs and synchronisation as tk_polarize_pcg;
+ * info->epol = -1/2 C mu.E_perm with the full field.  FP64 only; grid and
+ * order as tk_pme_mpole; ewald_beta > 0.
+ */
+tk_status tk_polarize_pcg_ewald(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                const tk_nblist* list, const double* mpole,
+                                const double* polarity, const double* thole, double ewald_beta,
+                                double cutoff, int32_t grid, int32_t order, double tol_debye,
+                                int32_t maxiter, const double* mu_guess, double* mu_out,
+                                tk_pcg_info* info);
+
+/*
  * Real-space polarization forces (epolar1 in the Rel profile, the second
  * AMOEBA hotspot of section "Hotspots").  The polarization energy is the
  * minimum over mu of C [1/2 mu.A mu - mu.E_perm] (A, E_perm as above),

@@ -24,6 +24,7 @@
 // once for its cells.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -230,6 +231,13 @@ struct MvArgs {
   double* part;         // [2][ncells] per-cell partials
   const double* pz_cur;    // [2][ncells] partials of r.z | z.z of iteration k
   const double* pz_prev;   // [2][ncells] of iteration k - 1
+  // full Ewald operator (one system, FP64): the PME field of the operand is
+  // subtracted from A v.  Modes 0, 2: rz = field of x.  Mode 1: rz = field of
+  // z_k, and the field of p_k = z_k + beta p_(k-1) is rz + beta rf_old (the
+  // field is linear), stored in rf_new for the next iteration.
+  const double* rz;
+  const double* rf_old;
+  double* rf_new;
   int k;
   int stage_cap, own_cap;
   PcgState* st;
@@ -459,7 +467,15 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
 #pragma unroll
       for (int ww = 0; ww < kMvWaves; ++ww) fs += ACC[ww * 3 * OC + d * nown + t];
       const double vv = lds[6 * (own0 + t) + 3 + d];
-      const double av = al > 0.0 ? vv / al - (fs + A.cself * vv) : 0.0;   // (A v)_s
+      double av = al > 0.0 ? vv / al - (fs + A.cself * vv) : 0.0;   // (A v)_s
+      if (A.rz) {
+        double rf = A.rz[3 * s + d];
+        if (kMode == 1) {
+          if (A.k >= 1) rf = fma(beta, A.rf_old[3 * s + d], rf);
+          A.rf_new[3 * s + d] = rf;
+        }
+        if (al > 0.0) av -= rf;
+      }
       if (kMode == 1) {
         A.pnew[3 * s + d] = vv;
         A.q[3 * s + d] = av;
@@ -737,6 +753,20 @@ struct Solver {
   PcgState* host_dev;   // its device address
   int32_t* active;      // [nsys] device copy of the refinement mask
   int32_t* active_h;    // pinned staging of the mask
+  int pme_grid = 0, pme_order = 0;   // full Ewald operator (one system, FP64) when set
+  double* rz = nullptr;              // PME field of the current operand
+  double* rfb[2] = {nullptr, nullptr};   // PME field of p_k (k even, odd)
+
+  // PME field of v (sorted) into rz; run_when_done as the iteration
+  // kernels: 0 while the solve runs, 1 for the stopped solve's residual,
+  // -1 always
+  tk_status queue_pme(const double* v, int run_when_done) {
+    if (!pme_grid) return TK_OK;
+    const int32_t* done =
+        run_when_done < 0 ? nullptr : (const int32_t*)((const char*)state + offsetof(PcgState, done));
+    return pme_dipole_field(ctx, st, P->n, P->box, gathered, pstride, v, beta, pme_grid, pme_order,
+                            rz, done, run_when_done < 0 ? 0 : run_when_done);
+  }
 
   template <class R>
   MvArgs<R> mv_args() const {
@@ -786,6 +816,11 @@ struct Solver {
     a.pz_cur = pz[k & 1];
     a.pz_prev = pz[(k + 1) & 1];
     a.k = k;
+    if (pme_grid) {
+      a.rz = rz;
+      a.rf_old = rfb[(k + 1) & 1];
+      a.rf_new = rfb[k & 1];
+    }
     launch_mv<R, 1>(a, "pcg_mv");
   }
 
@@ -842,6 +877,10 @@ struct Solver {
       a.pold = x;
       a.rhs = rhs;
       a.part = part;
+      if (pme_grid) {
+        queue_pme(x, 1);
+        a.rz = rz;
+      }
       launch_mv<double, 2>(a, "pcg_mv_residual");
     } else {
       matvec64_tiles(x);
@@ -891,6 +930,7 @@ struct Solver {
   tk_status run(const double* rhs, double tol, int maxiter, int first_chunk, bool residual,
                 const int32_t* act) {
     k_cs_init<<<nsys, 64, 0, st>>>(pv, npart, state, tol, maxiter, act);
+    tk_status s0;
     {
       MvArgs<R> a = mv_args<R>();
       a.v = x;
@@ -899,8 +939,13 @@ struct Solver {
       a.r = r;
       a.z = z;
       a.part = pz[0];
+      if (pme_grid) {
+        if ((s0 = queue_pme(x, -1))) return s0;
+        a.rz = rz;
+      }
       launch_mv<R, 0>(a, "pcg_mv0");
     }
+    if ((s0 = queue_pme(z, 0))) return s0;
     queue_mv<R>(0);
     int k = 0;   // index of the last queued first half
     int chunk = first_chunk > 0 ? first_chunk : kChunk;
@@ -908,6 +953,7 @@ struct Solver {
       if (chunk > maxiter - k) chunk = maxiter - k;
       for (int c = 0; c < chunk; ++c) {
         queue_update(k);
+        if ((s0 = queue_pme(z, 0))) return s0;
         queue_mv<R>(++k);
       }
       if (residual) queue_true_residual(rhs);
@@ -926,8 +972,11 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                         const int32_t* molid, const double* mpole, const double* polarity,
                         const double* thole, double ewald_beta, double cutoff, double tol_debye,
                         int32_t maxiter, int prec, const double* mu_guess,
-                        const int32_t* guess_on, double* mu_out, tk_pcg_info* info) {
+                        const int32_t* guess_on, double* mu_out, tk_pcg_info* info,
+                        int pme_grid, int pme_order) {
   const int nsys = P->nsys;
+  if (pme_grid && (prec != TK_FP64 || nsys != 1 || !pme_args_ok(pme_grid, pme_order)))
+    return TK_E_ARG;
   for (int k = 0; k < nsys; ++k) info[k] = tk_pcg_info{};
   const int n = P->n;
   if (n == 0) {
@@ -992,6 +1041,17 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   S.active = (int32_t*)act;
   S.hdr = (MvHdr*)hdr;
   S.ent = (MvEnt*)ent;
+  if (pme_grid) {
+    void *rz, *rf0, *rf1;
+    if ((s = scratch(ctx, "pcg_rz", v3, &rz)) || (s = scratch(ctx, "pcg_rf0", v3, &rf0)) ||
+        (s = scratch(ctx, "pcg_rf1", v3, &rf1)))
+      return s;
+    S.pme_grid = pme_grid;
+    S.pme_order = pme_order;
+    S.rz = (double*)rz;
+    S.rfb[0] = (double*)rf0;
+    S.rfb[1] = (double*)rf1;
+  }
   if (unit_lds_bytes<EfieldPh<double>>(*P, 1) > kMaxLds) return TK_E_CAPACITY;
   if ((s = mv_attributes(S.mv_lds))) return s;
   // pinned: [1024, ...) host state mirrors, then the refinement mask
@@ -1014,6 +1074,11 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
     S.gathered = (double*)ctx->scratch[per_stream("gathered", st)].p;
   else
     S.gather_geometry();
+  // full Ewald: the reciprocal permanent field joins the right-hand side (the
+  // PME scratch is separate from the gathered coordinates above)
+  if (pme_grid && (s = pme_perm_field_add(ctx, st, &sys1, mpole, ewald_beta, pme_grid, pme_order,
+                                          (const int32_t*)P->perm.p, S.b)))
+    return s;
   k_cs_setup<<<xcd_grid(S.ncells), kCellThreads, 0, st>>>(S.pv, polarity, mu_guess, guess_on, S.b,
                                                           S.alpha_s, S.x, S.npart, S.hdr, S.ent);
   const int slot = (int)(P - ctx->plans);
@@ -1105,7 +1170,35 @@ extern "C" tk_status tk_polarize_pcg(tk_ctx* ctx, void* stream, const tk_system*
   if (!mpole || !polarity || !thole || !mu_out) return TK_E_ARG;
   if ((s = solve_dipoles(ctx, (hipStream_t)stream, P, sys->xyz, sys->molid, mpole, polarity, thole,
                          ewald_beta, cutoff, tol_debye, maxiter, prec, mu_guess, nullptr, mu_out,
-                         info)))
+                         info, 0, 0)))
+    return s;
+  return info->status;
+}
+
+extern "C" tk_status tk_polarize_pcg_ewald(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                           const tk_nblist* list, const double* mpole,
+                                           const double* polarity, const double* thole,
+                                           double ewald_beta, double cutoff, int32_t grid,
+                                           int32_t order, double tol_debye, int32_t maxiter,
+                                           const double* mu_guess, double* mu_out,
+                                           tk_pcg_info* info) {
+  if (!ctx || !info) return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (!(ewald_beta > 0.0) || !std::isfinite(ewald_beta) || !(tol_debye >= 0.0) || maxiter < 0 ||
+      !pme_args_ok(grid, order))
+    return TK_E_ARG;
+  const Plan* P;
+  if ((s = get_plan(ctx, sys, list, cutoff, &P))) return s;
+  *info = tk_pcg_info{};
+  if (sys->n == 0) {
+    info->converged = 1;
+    return TK_OK;
+  }
+  if (!mpole || !polarity || !thole || !mu_out) return TK_E_ARG;
+  if ((s = solve_dipoles(ctx, (hipStream_t)stream, P, sys->xyz, sys->molid, mpole, polarity, thole,
+                         ewald_beta, cutoff, tol_debye, maxiter, TK_FP64, mu_guess, nullptr,
+                         mu_out, info, grid, order)))
     return s;
   return info->status;
 }

@@ -31,6 +31,48 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kFix = 1099511627776.0;   // 2^40
 constexpr double kFixMax = 131072.0;       // 2^17
 
+// The sites of a PME call: caller-order multipoles ([n][3] coordinates,
+// [n][10] multipoles), or dipoles in a solver's sorted order (coordinates as
+// SoA rows with a stride, [n][3] dipoles; charges and quadrupoles zero at
+// compile time).
+struct SrcMpole {
+  const double* xyz;
+  const double* mpole;
+  __device__ void pos(int j, double x[3]) const {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = xyz[3 * j + a];
+  }
+  __device__ void mp(int j, double m[10]) const {
+#pragma unroll
+    for (int k = 0; k < 10; ++k) m[k] = mpole[10 * j + k];
+  }
+};
+
+struct SrcDipole {
+  const double* p;   // p[a * ps + j]
+  long ps;
+  const double* v;   // v[3 j + a]
+  __device__ void pos(int j, double x[3]) const {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = p[a * ps + j];
+  }
+  __device__ void mp(int j, double m[10]) const {
+#pragma unroll
+    for (int k = 0; k < 10; ++k) m[k] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) m[1 + a] = v[3 * j + a];
+  }
+};
+
+// Launches queued ahead by the iterative solver read its state: with done
+// set, a launch returns at once while *done != 0 (when = 0: the solve has
+// stopped) or while *done == 0 (when = 1: work for the stopped solve only).
+struct Gate {
+  const int32_t* done = nullptr;
+  int when = 0;
+  __device__ bool closed() const { return done && (when ? *done == 0 : *done != 0); }
+};
+
 // Cardinal B-spline weights th[t][d] = M_P^(d)(w + t) (t = 0..P-1, d = 0..3)
 // for a fractional offset w in [0, 1), by the recursion
 //   M_k(x) = [x M_(k-1)(x) + (k - x) M_(k-1)(x - 1)] / (k - 1),  M_2 on (0, 2),
@@ -121,17 +163,21 @@ __device__ __forceinline__ int xbin(const double* x, double box, int K) {
 // Counting sort by x-bin without global atomics: each block of 256 sites
 // counts its bins in LDS (slot = rank inside its block and bin) and stores its
 // counts; block 0 also clears the refusal flag.
-__global__ __launch_bounds__(256) void k_pme_bin(int n, const double* __restrict__ xyz, double box,
-                                                 int K, int* __restrict__ bcnt,
-                                                 int* __restrict__ bin, int* __restrict__ slot,
-                                                 int* __restrict__ flag) {
+template <class Src>
+__global__ __launch_bounds__(256) void k_pme_bin(int n, Src src, double box, int K,
+                                                 int* __restrict__ bcnt, int* __restrict__ bin,
+                                                 int* __restrict__ slot, int* __restrict__ flag,
+                                                 Gate gate) {
+  if (gate.closed()) return;
   __shared__ int h[128];
   if ((int)threadIdx.x < K) h[threadIdx.x] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 0;
   __syncthreads();
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) {
-    const int b = xbin(xyz + 3 * j, box, K);
+    double x[3];
+    src.pos(j, x);
+    const int b = xbin(x, box, K);
     bin[j] = b;
     slot[j] = atomicAdd(&h[b], 1);
   }
@@ -147,7 +193,8 @@ __global__ __launch_bounds__(256) void k_pme_scatter(int n, int K, int nblk,
                                                      const int* __restrict__ bin,
                                                      const int* __restrict__ slot,
                                                      int* __restrict__ start,
-                                                     int* __restrict__ list) {
+                                                     int* __restrict__ list, Gate gate) {
+  if (gate.closed()) return;
   __shared__ int tot[256], off[256], pre[129];
   {
     // thread (r, b): bin b = tid % K, blocks q = r, r + R, ... (R = 256 / K)
@@ -196,13 +243,13 @@ __global__ __launch_bounds__(256) void k_pme_scatter(int n, int K, int nblk,
 template <int K>
 constexpr int spread_rows() { return K <= 64 ? K : K / 2; }
 
-template <int P, int K>
-__global__ __launch_bounds__(kSpreadThreads) void k_pme_spread(const double* __restrict__ xyz,
-                                                    const double* __restrict__ mpole, double box,
+template <int P, int K, class Src>
+__global__ __launch_bounds__(kSpreadThreads) void k_pme_spread(Src src, double box,
                                                     const int* __restrict__ start,
                                                     const int* __restrict__ list,
                                                     unsigned long long* __restrict__ grid,
-                                                    int* __restrict__ flag) {
+                                                    int* __restrict__ flag, Gate gate) {
+  if (gate.closed()) return;
   constexpr int YB = spread_rows<K>();
   constexpr int NYB = K / YB;
   __shared__ unsigned long long tile[YB * K];
@@ -217,16 +264,19 @@ __global__ __launch_bounds__(kSpreadThreads) void k_pme_spread(const double* __r
 #pragma unroll 1
     for (int s = start[b] + threadIdx.x; s < s1; s += blockDim.x) {
       const int j = list[s];
+      double xj[3];
+      src.pos(j, xj);
       if (NYB > 1) {   // rows i0y - t2 (t2 < P) miss this tile: skip the spline work
-        const double sy = xyz[3 * j + 1] / box;
+        const double sy = xj[1] / box;
         const double fy = floor(K * (sy - floor(sy)));
         const int iy = fy >= 0.0 && fy <= K ? (int)fy : 0;
         if (wrap(iy - y0, K) >= YB + P - 1) continue;
       }
       double X[4], th[2][P][4];
       int i0[3];
-      site_splines<P>(xyz + 3 * j, box, K, t1, X, th, i0);
-      const double* m = mpole + 10 * j;
+      site_splines<P>(xj, box, K, t1, X, th, i0);
+      double m[10];
+      src.mp(j, m);
       const double q = m[0], ux = m[1], uy = m[2], uz = m[3];
       const double txx = m[4], txy = m[5], txz = m[6], tyy = m[7], tyz = m[8], tzz = m[9];
 #pragma unroll
@@ -340,7 +390,8 @@ __device__ __forceinline__ void slot(int ax, int t, int s, int& line, int& k) {
 // Forward pass along axis ax (z: from the fixed-point grid; y: in place).
 template <int K>
 __global__ __launch_bounds__(256) void k_pme_fft_fwd(int ax, const unsigned long long* __restrict__ fix,
-                                                     double2* __restrict__ cg) {
+                                                     double2* __restrict__ cg, Gate gate) {
+  if (gate.closed()) return;
   constexpr int L = Fft<K>::L, LOG = Fft<K>::LOG;
   __shared__ double2 sh[L * K];
   __shared__ double2 tw[K / 2];
@@ -405,7 +456,8 @@ __device__ __forceinline__ void spline_moduli(double* D) {
 // inverse transform, in place.
 template <int P, int K>
 __global__ __launch_bounds__(256) void k_pme_fft_conv(double2* __restrict__ cg, double box,
-                                                      double beta) {
+                                                      double beta, Gate gate) {
+  if (gate.closed()) return;
   constexpr int H = Fft<K>::H, L = Fft<K>::L, LOG = Fft<K>::LOG;
   __shared__ double2 sh[L * K];
   __shared__ double2 tw[K / 2];
@@ -456,7 +508,8 @@ __global__ __launch_bounds__(256) void k_pme_fft_conv(double2* __restrict__ cg, 
 // Inverse pass along axis ax (y: in place; z: real part to phi).
 template <int K>
 __global__ __launch_bounds__(256) void k_pme_fft_inv(int ax, double2* __restrict__ cg,
-                                                     double* __restrict__ phi) {
+                                                     double* __restrict__ phi, Gate gate) {
+  if (gate.closed()) return;
   constexpr int L = Fft<K>::L, LOG = Fft<K>::LOG;
   __shared__ double2 sh[L * K];
   __shared__ double2 tw[K / 2];
@@ -587,6 +640,54 @@ __global__ __launch_bounds__(256) void k_pme_gather(int n, const double* __restr
   if (threadIdx.x == 0) epart[blockIdx.x] = ((we[0] + we[1]) + we[2]) + we[3];
 }
 
+// Field only, -grad phi at each site (8 lanes per site as in k_pme_gather,
+// first derivatives only): the reciprocal field of a solver's dipoles, in the
+// sites' own order.
+template <int P, class Src>
+__global__ __launch_bounds__(256) void k_pme_field(int n, Src src, double box, int K,
+                                                   const double* __restrict__ phi,
+                                                   double* __restrict__ out, Gate gate) {
+  if (gate.closed()) return;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = gid >> 3, t1 = gid & 7;
+  const bool site = j0 < n;
+  const int j = site ? j0 : n - 1;
+  double xj[3];
+  src.pos(j, xj);
+  double X[4], th[2][P][4];
+  int i0[3];
+  site_splines<P>(xj, box, K, t1, X, th, i0);
+  double S00 = 0.0, S10 = 0.0, S01 = 0.0;   // S[dy][dz] with dy + dz <= 1
+  if (site && t1 < P) {
+    const int gx = wrap(i0[0] - t1, K);
+#pragma unroll
+    for (int t2 = 0; t2 < P; ++t2) {
+      const long row = ((long)gx * K + wrap(i0[1] - t2, K)) * K;
+      double z0 = 0.0, z1 = 0.0;
+#pragma unroll
+      for (int t3 = 0; t3 < P; ++t3) {
+        const double v = phi[row + wrap(i0[2] - t3, K)];
+        z0 += v * th[1][t3][0];
+        z1 += v * th[1][t3][1];
+      }
+      S00 += th[0][t2][0] * z0;
+      S10 += th[0][t2][1] * z0;
+      S01 += th[0][t2][0] * z1;
+    }
+  }
+  const bool on = site && t1 < P;
+  double g[3] = {on ? X[1] * S00 : 0.0, on ? X[0] * S10 : 0.0, on ? X[0] * S01 : 0.0};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    g[a] += __shfl_xor(g[a], 1);
+    g[a] += __shfl_xor(g[a], 2);
+    g[a] += __shfl_xor(g[a], 4);
+  }
+  if (site && t1 == 0)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[3 * j + a] = -g[a];
+}
+
 // energy = (C/2) sum of the partials in block order; NaN if the spread refused
 // a contribution.
 __global__ __launch_bounds__(256) void k_pme_energy(const double* __restrict__ epart, int nb,
@@ -604,58 +705,104 @@ __global__ __launch_bounds__(256) void k_pme_energy(const double* __restrict__ e
   }
 }
 
-template <int P, int K>
-tk_status run_pme(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* mpole,
-                  double beta, double* energy, double* force, double* field) {
+// Bin, spread and convolve: the potential phi on the mesh (scratch of this
+// stream), and the spread's refusal flag.
+template <int P, int K, class Src>
+tk_status mesh_potential(tk_ctx* ctx, hipStream_t st, int n, Src src, double box, double beta,
+                         Gate gate, double** phi_out, int** flag_out) {
   const long KK = (long)K * K * K;
-  const int n = sys->n;
-  const int nb = ceil_div((long)n * 8, 256);
-  void *fix, *cg, *phi, *epart, *flag, *bins;
-  tk_status s;
   const size_t nn = n > 0 ? n : 1;
+  const int na = n > 0 ? ceil_div(n, 256) : 1;   // sort blocks (one even when empty)
+  void *fix, *cg, *phi, *flag, *bins;
+  tk_status s;
   if ((s = scratch(ctx, per_stream("pme_fix", st).c_str(), sizeof(unsigned long long) * KK, &fix)) ||
       (s = scratch(ctx, per_stream("pme_bins", st).c_str(),
-                   sizeof(int) * (3 * nn + (size_t)(ceil_div(n, 256) + 1) * K + K + 2), &bins)) ||
+                   sizeof(int) * (3 * nn + (size_t)(na + 1) * K + K + 2), &bins)) ||
       (s = scratch(ctx, per_stream("pme_c", st).c_str(), sizeof(double2) * KK, &cg)) ||
       (s = scratch(ctx, per_stream("pme_phi", st).c_str(), sizeof(double) * KK, &phi)) ||
-      (s = scratch(ctx, per_stream("pme_part", st).c_str(), sizeof(double) * (nb > 0 ? nb : 1),
-                   &epart)) ||
       (s = scratch(ctx, per_stream("pme_flag", st).c_str(), sizeof(int) * 64, &flag)))
     return s;
   auto* fx = (unsigned long long*)fix;
   auto* c2 = (double2*)cg;
-  const int nlines = K * K / Fft<K>::L;
-  const int na = n > 0 ? ceil_div(n, 256) : 1;   // sort blocks (one even when empty)
   int* bcnt = (int*)bins;
   int* start = bcnt + (size_t)na * K;
   int* bin = start + K + 1;
   int* slot = bin + nn;
   int* list = slot + nn;
+  const int nlines = K * K / Fft<K>::L;
   {
     ProfScope ps(ctx, st, "pme_spread");
-    k_pme_bin<<<na, 256, 0, st>>>(n, sys->xyz, sys->box, K, bcnt, bin, slot, (int*)flag);
-    k_pme_scatter<<<na, 256, 0, st>>>(n, K, na, bcnt, bin, slot, start, list);
-    k_pme_spread<P, K><<<K * (K / spread_rows<K>()), kSpreadThreads, 0, st>>>(
-        sys->xyz, mpole, sys->box, start, list, fx, (int*)flag);
+    k_pme_bin<Src><<<na, 256, 0, st>>>(n, src, box, K, bcnt, bin, slot, (int*)flag, gate);
+    k_pme_scatter<<<na, 256, 0, st>>>(n, K, na, bcnt, bin, slot, start, list, gate);
+    k_pme_spread<P, K, Src><<<K * (K / spread_rows<K>()), kSpreadThreads, 0, st>>>(
+        src, box, start, list, fx, (int*)flag, gate);
   }
   {
     ProfScope ps(ctx, st, "pme_fft");
-    k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(2, fx, c2);
-    k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(1, nullptr, c2);
-    k_pme_fft_conv<P, K><<<nlines, 256, 0, st>>>(c2, sys->box, beta);
-    k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(1, c2, nullptr);
-    k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(2, c2, (double*)phi);
+    k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(2, fx, c2, gate);
+    k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(1, nullptr, c2, gate);
+    k_pme_fft_conv<P, K><<<nlines, 256, 0, st>>>(c2, box, beta, gate);
+    k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(1, c2, nullptr, gate);
+    k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(2, c2, (double*)phi, gate);
   }
+  *phi_out = (double*)phi;
+  *flag_out = (int*)flag;
+  return TK_OK;
+}
+
+template <int P, int K>
+tk_status run_pme(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* mpole,
+                  double beta, double* energy, double* force, double* field) {
+  const int n = sys->n;
+  const int nb = ceil_div((long)n * 8, 256);
+  double* phi;
+  int* flag;
+  void* epart;
+  tk_status s;
+  if ((s = scratch(ctx, per_stream("pme_part", st).c_str(), sizeof(double) * (nb > 0 ? nb : 1),
+                   &epart)))
+    return s;
+  if ((s = mesh_potential<P, K>(ctx, st, n, SrcMpole{sys->xyz, mpole}, sys->box, beta, Gate{},
+                                &phi, &flag)))
+    return s;
   {
     ProfScope ps(ctx, st, "pme_gather");
     if (n > 0)
-      k_pme_gather<P><<<nb, 256, 0, st>>>(n, sys->xyz, mpole, sys->box, K, (const double*)phi,
-                                           force, field, (double*)epart);
-    k_pme_energy<<<1, 256, 0, st>>>((const double*)epart, n > 0 ? nb : 0, (const int*)flag,
-                                    energy);
+      k_pme_gather<P><<<nb, 256, 0, st>>>(n, sys->xyz, mpole, sys->box, K, phi, force, field,
+                                           (double*)epart);
+    k_pme_energy<<<1, 256, 0, st>>>((const double*)epart, n > 0 ? nb : 0, flag, energy);
   }
   TK_HIP(hipGetLastError());
   return TK_OK;
+}
+
+template <int P, int K>
+tk_status run_pme_dipoles(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos,
+                          long ps, const double* v, double beta, double* out, Gate gate) {
+  double* phi;
+  int* flag;
+  tk_status s;
+  const SrcDipole src{pos, ps, v};
+  if ((s = mesh_potential<P, K>(ctx, st, n, src, box, beta, gate, &phi, &flag))) return s;
+  {
+    ProfScope ps_(ctx, st, "pme_field");
+    if (n > 0)
+      k_pme_field<P, SrcDipole><<<ceil_div((long)n * 8, 256), 256, 0, st>>>(n, src, box, K, phi,
+                                                                         out, gate);
+  }
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+// b[3 s + a] += f[3 perm[s] + a]
+__global__ __launch_bounds__(256) void k_add_permuted(int n, const int32_t* __restrict__ perm,
+                                                      const double* __restrict__ f,
+                                                      double* __restrict__ b) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int i = perm[s];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) b[3 * s + a] += f[3 * i + a];
 }
 
 template <int P>
@@ -670,7 +817,71 @@ tk_status run_pme_k(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const dou
   }
 }
 
+template <int P>
+tk_status run_dip_k(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos, long ps,
+                    const double* v, double beta, int K, double* out, Gate gate) {
+  switch (K) {
+    case 16: return run_pme_dipoles<P, 16>(ctx, st, n, box, pos, ps, v, beta, out, gate);
+    case 32: return run_pme_dipoles<P, 32>(ctx, st, n, box, pos, ps, v, beta, out, gate);
+    case 64: return run_pme_dipoles<P, 64>(ctx, st, n, box, pos, ps, v, beta, out, gate);
+    case 128: return run_pme_dipoles<P, 128>(ctx, st, n, box, pos, ps, v, beta, out, gate);
+    default: return TK_E_ARG;
+  }
+}
+
+tk_status pme_dispatch(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* mpole,
+                       double beta, int K, int order, double* energy, double* force,
+                       double* field) {
+  switch (order) {
+    case 5: return run_pme_k<5>(ctx, st, sys, mpole, beta, K, energy, force, field);
+    case 6: return run_pme_k<6>(ctx, st, sys, mpole, beta, K, energy, force, field);
+    case 7: return run_pme_k<7>(ctx, st, sys, mpole, beta, K, energy, force, field);
+    case 8: return run_pme_k<8>(ctx, st, sys, mpole, beta, K, energy, force, field);
+    default: return TK_E_ARG;
+  }
+}
+
 }  // namespace
+
+bool pme_args_ok(int grid, int order) {
+  return (grid == 16 || grid == 32 || grid == 64 || grid == 128) && order >= 5 && order <= 8 &&
+         grid >= 2 * order;
+}
+
+tk_status pme_dipole_field(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos,
+                           long ps, const double* v, double beta, int grid, int order,
+                           double* out, const int32_t* done, int run_when_done) {
+  if (!pme_args_ok(grid, order)) return TK_E_ARG;
+  Gate gate;
+  gate.done = done;
+  gate.when = run_when_done;
+  switch (order) {
+    case 5: return run_dip_k<5>(ctx, st, n, box, pos, ps, v, beta, grid, out, gate);
+    case 6: return run_dip_k<6>(ctx, st, n, box, pos, ps, v, beta, grid, out, gate);
+    case 7: return run_dip_k<7>(ctx, st, n, box, pos, ps, v, beta, grid, out, gate);
+    default: return run_dip_k<8>(ctx, st, n, box, pos, ps, v, beta, grid, out, gate);
+  }
+}
+
+tk_status pme_perm_field_add(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
+                             const double* mpole, double beta, int grid, int order,
+                             const int32_t* perm, double* b_sorted) {
+  if (!pme_args_ok(grid, order)) return TK_E_ARG;
+  const int n = sys->n;
+  if (n == 0) return TK_OK;
+  void *tmp;
+  tk_status s;
+  if ((s = scratch(ctx, per_stream("pme_perm", st).c_str(), sizeof(double) * (7 * (size_t)n + 1),
+                   &tmp)))
+    return s;
+  double* e = (double*)tmp;
+  double* f = e + 1;
+  double* fld = f + 3 * (size_t)n;
+  if ((s = pme_dispatch(ctx, st, sys, mpole, beta, grid, order, e, f, fld))) return s;
+  k_add_permuted<<<ceil_div(n, 256), 256, 0, st>>>(n, perm, fld, b_sorted);
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
 
 }  // namespace tk
 
@@ -685,16 +896,10 @@ tk_status tk_pme_mpole(tk_ctx* ctx, void* stream, const tk_system* sys, const do
   tk_status s = check_system(sys);
   if (s) return s;
   if (!(ewald_beta > 0.0) || !std::isfinite(ewald_beta) || !energy) return TK_E_ARG;
-  if (grid != 16 && grid != 32 && grid != 64 && grid != 128) return TK_E_ARG;
-  if (order < 5 || order > 8 || grid < 2 * order) return TK_E_ARG;
+  if (!pme_args_ok(grid, order)) return TK_E_ARG;
   if (sys->n > 0 && (!mpole || !force)) return TK_E_ARG;
-  hipStream_t st = (hipStream_t)stream;
-  switch (order) {
-    case 5: return run_pme_k<5>(ctx, st, sys, mpole, ewald_beta, grid, energy, force, field);
-    case 6: return run_pme_k<6>(ctx, st, sys, mpole, ewald_beta, grid, energy, force, field);
-    case 7: return run_pme_k<7>(ctx, st, sys, mpole, ewald_beta, grid, energy, force, field);
-    default: return run_pme_k<8>(ctx, st, sys, mpole, ewald_beta, grid, energy, force, field);
-  }
+  return pme_dispatch(ctx, (hipStream_t)stream, sys, mpole, ewald_beta, grid, order, energy, force,
+                      field);
 }
 
 }  // extern "C"

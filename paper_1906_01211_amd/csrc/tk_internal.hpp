@@ -234,11 +234,24 @@ tk_status build_plans(tk_ctx* ctx, hipStream_t st, int nj, const int* slots, int
 // the systems whose guess_on entry (device [nsys], nullable: all) is nonzero;
 // info[P->nsys] is host memory.  Synchronises the stream while solving;
 // mu_out is written in stream order after the return.
+// Reciprocal space (smooth PME, pme.hip).  grid: 16, 32, 64 or 128; order 5..8.
+bool pme_args_ok(int grid, int order);
+// -grad phi of dipoles v ([n][3], the sites' own order) at positions
+// pos[a * ps + j], into out; with done set, the launches return at once while
+// *done != 0 (run_when_done 0) or while *done == 0 (run_when_done 1).
+tk_status pme_dipole_field(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos,
+                           long ps, const double* v, double beta, int grid, int order,
+                           double* out, const int32_t* done, int run_when_done);
+// b_sorted[3 s + a] += reciprocal field of the permanent multipoles at site perm[s].
+tk_status pme_perm_field_add(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
+                             const double* mpole, double beta, int grid, int order,
+                             const int32_t* perm, double* b_sorted);
 tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double* xyz,
                         const int32_t* molid, const double* mpole, const double* polarity,
                         const double* thole, double ewald_beta, double cutoff, double tol_debye,
                         int32_t maxiter, int prec, const double* mu_guess,
-                        const int32_t* guess_on, double* mu_out, tk_pcg_info* info);
+                        const int32_t* guess_on, double* mu_out, tk_pcg_info* info,
+                        int pme_grid = 0, int pme_order = 0);
 
 // Checks shared by the pair entry points.
 tk_status check_system(const tk_system* sys);

@@ -104,6 +104,8 @@ _SIGS = {
     "tk_epolar_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
                        _d, C.c_int, _vp, _vp, _vp],
     "tk_pme_mpole": [_vp, _vp, C.POINTER(System), _vp, _d, _i32, _i32, _vp, _vp, _vp],
+    "tk_polarize_pcg_ewald": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d,
+                              _d, _i32, _i32, _d, _i32, _vp, _vp, C.POINTER(PcgInfo)],
     "tk_evdw": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), C.c_int, _vp, _vp, _d, _d, _d, _d,
                 C.c_int, _vp, _vp, _vp],
     "tk_batch_step": [_vp, _vp, C.POINTER(Batch), C.POINTER(StepParams), _vp, _vp, _vp, _vp, _vp,
@@ -315,6 +317,22 @@ class Context:
                                     C.byref(info))
         if st not in (OK, E_NOCONV, E_BREAKDOWN):
             _check(st, "tk_polarize_pcg")
+        return out, {k: getattr(info, k) for k, _ in PcgInfo._fields_}
+
+    def polarize_pcg_ewald(self, sysref, lst, mpole, polarity, thole, beta, cutoff, grid,
+                           order=5, tol_debye=1e-5, maxiter=100, mu_guess=None):
+        mp = _dev(mpole, torch.float64, self.device)
+        pol = _dev(polarity, torch.float64, self.device)
+        th = _dev(thole, torch.float64, self.device)
+        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device)
+        out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        info = PcgInfo()
+        st = load().tk_polarize_pcg_ewald(self._h, _stream(self.device), C.byref(sysref.c),
+                                          C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), beta,
+                                          cutoff, int(grid), int(order), tol_debye, int(maxiter),
+                                          _ptr(g), _ptr(out), C.byref(info))
+        if st not in (OK, E_NOCONV, E_BREAKDOWN):
+            _check(st, "tk_polarize_pcg_ewald")
         return out, {k: getattr(info, k) for k, _ in PcgInfo._fields_}
 
     def epolar_real(self, sysref, lst, mpole, polarity, thole, mu, beta, cutoff, prec=FP64):

@@ -108,3 +108,74 @@ def test_pme_edge_cases_and_errors(ctx, tk):
     assert np.isnan(np_(e)[0])
     # and the next call with ordinary input is clean again
     check(ctx, w.xyz, w.box, w.mpole, S["beta"], 16, 5)
+
+
+# ---------------------------------------------------------------- full-Ewald solve
+def _ewald_case(ctx, name, K, p):
+    w = _cache.setdefault(name, synth.make(name))
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, 7.001, plan_slot=2)
+    key = (name, "list")
+    if key not in _cache:
+        _cache[key] = O.nblist(w.xyz, w.box, 7.001)
+    rp, cp = _cache[key]
+    return w, sysr, lst, rp, cp
+
+
+@pytest.mark.parametrize("k", [0, 1, 4])
+def test_pcg_ewald_iterates(ctx, k):
+    # fixed iteration counts: every iterate equals the oracle's
+    w, sysr, lst, rp, cp = _ewald_case(ctx, "water216", 32, 5)
+    print(f"pcg ewald water216 k={k}", flush=True)
+    mu, info = ctx.polarize_pcg_ewald(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0, 32,
+                                      5, tol_debye=0.0, maxiter=k)
+    mo, io = O.polarize_pcg_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                  S["beta"], 7.0, 32, 5, tol_debye=0.0, maxiter=k)
+    assert info["iters"] == io["iters"] == k and info["status"] == io["status"]
+    assert np.abs(np_(mu) - mo).max() <= 1e-10 * np.abs(mo).max()
+    assert abs(info["epol"] - io["epol"]) <= 1e-10 * abs(io["epol"])
+    # the reciprocal field passes through the 2^-40 fixed-point mesh (absolute
+    # ~1e-12 e/A^2), small against these residual norms but not at 1e-8
+    assert abs(info["rms_debye"] - io["rms_debye"]) <= 1e-7 * io["rms_debye"]
+
+
+@pytest.mark.parametrize("name,K,p", [("water216", 32, 5), ("water216", 16, 8),
+                                      ("water7853", 64, 5)])
+def test_pcg_ewald_converged(ctx, name, K, p):
+    w, sysr, lst, rp, cp = _ewald_case(ctx, name, K, p)
+    print(f"pcg ewald {name} K={K} p={p}", flush=True)
+    mu, info = ctx.polarize_pcg_ewald(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0, K,
+                                      p, tol_debye=S["tol_debye"])
+    mo, io = O.polarize_pcg_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                  S["beta"], 7.0, K, p, tol_debye=S["tol_debye"])
+    assert info["converged"] == io["converged"] == 1 and info["iters"] == io["iters"]
+    assert np.abs(np_(mu) - mo).max() <= 1e-10 * np.abs(mo).max()
+    assert abs(info["epol"] - io["epol"]) <= 1e-10 * abs(io["epol"])
+    # a converged true residual (~3e-6 D) against the mesh's fixed-point
+    # rounding of the reciprocal field (~1e-11 D)
+    assert abs(info["rms_true_debye"] - io["rms_true_debye"]) <= 1e-5 * io["rms_true_debye"]
+    # the plain real-space solve on the same context is unaffected afterwards
+    m2, i2 = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
+                              tol_debye=S["tol_debye"])
+    m3, i3 = O.polarize_pcg(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                            S["beta"], 7.0, tol_debye=S["tol_debye"])
+    assert i2["iters"] == i3["iters"]
+    assert np.abs(np_(m2) - m3).max() <= 1e-10 * np.abs(m3).max()
+
+
+def test_pcg_ewald_guess_zero_polarizability_and_errors(ctx, tk):
+    w, sysr, lst, rp, cp = _ewald_case(ctx, "water216", 16, 5)
+    mo, io = O.polarize_pcg_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                  S["beta"], 7.0, 16, 5, tol_debye=1e-9, maxiter=100)
+    # converged dipoles as the guess: zero or one iteration, same answer
+    mu, info = ctx.polarize_pcg_ewald(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0, 16,
+                                      5, tol_debye=1e-5, mu_guess=mo)
+    assert info["converged"] == 1 and info["iters"] <= 1
+    assert np.abs(np_(mu) - mo).max() <= 1e-6 * np.abs(mo).max()
+    # no polarizable atom: zero dipoles at once
+    mu0, info0 = ctx.polarize_pcg_ewald(sysr, lst, w.mpole, np.zeros(w.n), w.thole, S["beta"],
+                                        7.0, 16, 5)
+    assert info0["converged"] == 1 and info0["iters"] == 0 and not np.any(np_(mu0))
+    for K, p, beta in ((48, 5, S["beta"]), (16, 4, S["beta"]), (16, 5, 0.0)):
+        with pytest.raises(tk.TkError):
+            ctx.polarize_pcg_ewald(sysr, lst, w.mpole, w.polarity, w.thole, beta, 7.0, K, p)
