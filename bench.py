@@ -290,7 +290,8 @@ def extras(ctx, tk, w, a, prec, n7):
 def pme_leg(ctx, tk, w, grid=64, order=5):
     """Reciprocal-space multipoles by smooth PME on the water box (64^3 mesh,
     order-5 splines): whole call and its three stages (spread, the five FFT
-    passes with the convolution, gather + energy)."""
+    passes with the convolution, gather + energy); and the induced-dipole
+    solve with the full Ewald operator beside the real-space one."""
     import torch
     s = synth.AMOEBA_SETTINGS
     sysw = ctx.system(w.xyz, w.box, w.molid)
@@ -314,6 +315,25 @@ def pme_leg(ctx, tk, w, grid=64, order=5):
     if "pme_fft_us" in out:
         out["fft_bytes"] = fft_bytes
         out["fft_hbm_frac"] = round(fft_bytes / (out["pme_fft_us"] * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
+    # induced dipoles with the full Ewald operator beside the real-space solve
+    # (same list, tolerance and guess; the right-hand sides included)
+    l7 = ctx.nblist(sysw, s["rc_ewald"] + s["skin"], plan_slot=3)
+    pol = torch.as_tensor(w.polarity, device=ctx.device)
+    th = torch.as_tensor(w.thole, device=ctx.device)
+    info = {}
+
+    def ewald():
+        _, info["ewald"] = ctx.polarize_pcg_ewald(sysw, l7, mp, pol, th, s["beta"], s["rc_ewald"],
+                                                  grid, order, tol_debye=s["tol_debye"],
+                                                  maxiter=s["maxiter"])
+
+    def real():
+        _, info["real"] = ctx.polarize_pcg(sysw, l7, mp, pol, th, s["beta"], s["rc_ewald"],
+                                           tol_debye=s["tol_debye"], maxiter=s["maxiter"])
+    out["pcg_ewald_ms"] = round(timed(ewald, 10, 2) * 1e3, 4)
+    out["pcg_ewald_iters"] = info["ewald"]["iters"]
+    out["pcg_real_ms"] = round(timed(real, 10, 2) * 1e3, 4)
+    out["pcg_real_iters"] = info["real"]["iters"]
     return out
 
 
