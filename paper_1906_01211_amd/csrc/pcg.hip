@@ -764,8 +764,8 @@ struct Solver {
     if (!pme_grid) return TK_OK;
     const int32_t* done =
         run_when_done < 0 ? nullptr : (const int32_t*)((const char*)state + offsetof(PcgState, done));
-    return pme_dipole_field(ctx, st, P->n, P->box, gathered, pstride, v, beta, pme_grid, pme_order,
-                            rz, done, run_when_done < 0 ? 0 : run_when_done);
+    return pme_prepared_dipole_field(ctx, st, P->n, P->box, v, beta, pme_grid, pme_order, rz,
+                                     done, run_when_done < 0 ? 0 : run_when_done);
   }
 
   template <class R>
@@ -1078,6 +1078,10 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   // PME scratch is separate from the gathered coordinates above)
   if (pme_grid && (s = pme_perm_field_add(ctx, st, &sys1, mpole, ewald_beta, pme_grid, pme_order,
                                           (const int32_t*)P->perm.p, S.b)))
+    return s;
+  // the sites of every iteration's dipole field: sorted and tabulated once
+  if (pme_grid && (s = pme_prepare_sites(ctx, st, n, P->box, S.gathered, S.pstride, pme_grid,
+                                         pme_order)))
     return s;
   k_cs_setup<<<xcd_grid(S.ncells), kCellThreads, 0, st>>>(S.pv, polarity, mu_guess, guess_on, S.b,
                                                           S.alpha_s, S.x, S.npart, S.hdr, S.ent);

@@ -149,7 +149,11 @@ __device__ __forceinline__ int wrap(int g, int K) { return ((g % K) + K) % K; }
 // the contributions of the sites whose x-row reaches its plane (bins gx..gx+P-1),
 // then stores the tile.  No global atomics, and every mesh point is written
 // once, so the mesh needs no clearing.
-constexpr int kSpreadThreads = 1024;   // one workgroup per spread tile
+// One workgroup per spread tile: 1024 threads, 512 for orders 7 and 8 (their
+// larger spline tables need more than the 128 registers of a 1024-thread
+// workgroup).
+template <int P>
+constexpr int spread_threads() { return P <= 6 ? 1024 : 512; }
 
 // The x grid index of the spline code, mod K (a fraction that rounds up to
 // 1 gives K, i.e. 0).  A non-finite coordinate maps to bin 0: its weights are
@@ -244,7 +248,7 @@ template <int K>
 constexpr int spread_rows() { return K <= 64 ? K : K / 2; }
 
 template <int P, int K, class Src>
-__global__ __launch_bounds__(kSpreadThreads) void k_pme_spread(Src src, double box,
+__global__ __launch_bounds__(spread_threads<P>()) void k_pme_spread(Src src, double box,
                                                     const int* __restrict__ start,
                                                     const int* __restrict__ list,
                                                     unsigned long long* __restrict__ grid,
@@ -640,52 +644,145 @@ __global__ __launch_bounds__(256) void k_pme_gather(int n, const double* __restr
   if (threadIdx.x == 0) epart[blockIdx.x] = ((we[0] + we[1]) + we[2]) + we[3];
 }
 
-// Field only, -grad phi at each site (8 lanes per site as in k_pme_gather,
-// first derivatives only): the reciprocal field of a solver's dipoles, in the
-// sites' own order.
-template <int P, class Src>
-__global__ __launch_bounds__(256) void k_pme_field(int n, Src src, double box, int K,
-                                                   const double* __restrict__ phi,
-                                                   double* __restrict__ out, Gate gate) {
+// ---------------------------------------------------------------- prepared sites
+// While a solver iterates, the sites do not move: their x-bin order and
+// spline weights (value and first derivative per axis, scaled to d/dx) are
+// computed once per solve and read by every iteration's spread and field.
+// Tables are indexed by sorted position s (SoA rows of n), so that a tile's
+// sites are read with coalesced loads.
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_tables(int n, SrcDipole src, double box, int K,
+                                                    const int* __restrict__ list,
+                                                    int* __restrict__ I0,
+                                                    double* __restrict__ TB) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int j = list[s];
+  double x[3];
+  src.pos(j, x);
+  const double kl = K / box;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double f = x[a] / box;
+    const double u = K * (f - floor(f));
+    const double fl = floor(u);
+    I0[a * n + s] = fl >= 0.0 && fl <= K ? (int)fl : 0;
+    double t4[P][4];
+    bspline_table<P>(u - fl, t4);
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      TB[(long)((a * P + t) * 2) * n + s] = t4[t][0];
+      TB[(long)((a * P + t) * 2 + 1) * n + s] = t4[t][1] * kl;
+    }
+  }
+}
+
+// Dipole spread from the tables: one workgroup per x-plane (as k_pme_spread).
+template <int P, int K>
+__global__ __launch_bounds__(spread_threads<P>()) void k_pme_spread_tab(
+    int n, const int* __restrict__ start, const int* __restrict__ list,
+    const int* __restrict__ I0, const double* __restrict__ TB, const double* __restrict__ v,
+    unsigned long long* __restrict__ grid, int* __restrict__ flag, Gate gate) {
+  if (gate.closed()) return;
+  constexpr int YB = spread_rows<K>();
+  constexpr int NYB = K / YB;
+  __shared__ unsigned long long tile[YB * K];
+  const int gx = blockIdx.x / NYB, y0 = (blockIdx.x % NYB) * YB;
+  for (int i = threadIdx.x; i < YB * K; i += blockDim.x) tile[i] = 0ull;
+  __syncthreads();   // flag: cleared once per solve, by the preparation
+  bool bad = false;
+#pragma unroll 1
+  for (int t1 = 0; t1 < P; ++t1) {
+    const int b = (gx + t1) % K;
+    const int s1 = start[b + 1];
+#pragma unroll 1
+    for (int s = start[b] + threadIdx.x; s < s1; s += blockDim.x) {
+      const int iy = I0[n + s];
+      if (NYB > 1 && wrap(iy - y0, K) >= YB + P - 1) continue;
+      const int iz = I0[2 * n + s];
+      const int j = list[s];
+      const double vx = v[3 * j], vy = v[3 * j + 1], vz = v[3 * j + 2];
+      const double X0 = TB[(long)(t1 * 2) * n + s], X1 = TB[(long)(t1 * 2 + 1) * n + s];
+      double Y[P][2], Z[P][2];
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        Y[t][0] = TB[(long)((P + t) * 2) * n + s];
+        Y[t][1] = TB[(long)((P + t) * 2 + 1) * n + s];
+        Z[t][0] = TB[(long)((2 * P + t) * 2) * n + s];
+        Z[t][1] = TB[(long)((2 * P + t) * 2 + 1) * n + s];
+      }
+      const double ax = vx * X1, a0 = X0;
+#pragma unroll
+      for (int t2 = 0; t2 < P; ++t2) {
+        const int ly = wrap(iy - t2 - y0, K);
+        if (ly >= YB) continue;
+        const double c0 = ax * Y[t2][0] + a0 * vy * Y[t2][1];   // times Z0
+        const double c1 = a0 * vz * Y[t2][0];                    // times Z1
+#pragma unroll
+        for (int t3 = 0; t3 < P; ++t3) {
+          const double val = c0 * Z[t3][0] + c1 * Z[t3][1];
+          bad |= !(fabs(val) < kFixMax);
+          const long long iv = bad ? 0ll : llrint(val * kFix);
+          atomicAdd(&tile[ly * K + wrap(iz - t3, K)], (unsigned long long)iv);
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < YB * K; i += blockDim.x)
+    grid[((long)gx * K + y0 + i / K) * K + i % K] = tile[i];
+}
+
+// Field from the tables, 8 lanes per sorted site (lane t1 its plane);
+// out in the sites' own order (out[3 list[s] + a]).
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_field_tab(int n, int K, const int* __restrict__ list,
+                                                       const int* __restrict__ I0,
+                                                       const double* __restrict__ TB,
+                                                       const double* __restrict__ phi,
+                                                       const int* __restrict__ flag,
+                                                       double* __restrict__ out, Gate gate) {
   if (gate.closed()) return;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j0 = gid >> 3, t1 = gid & 7;
-  const bool site = j0 < n;
-  const int j = site ? j0 : n - 1;
-  double xj[3];
-  src.pos(j, xj);
-  double X[4], th[2][P][4];
-  int i0[3];
-  site_splines<P>(xj, box, K, t1, X, th, i0);
-  double S00 = 0.0, S10 = 0.0, S01 = 0.0;   // S[dy][dz] with dy + dz <= 1
+  const int s0 = gid >> 3, t1 = gid & 7;
+  const bool site = s0 < n;
+  const int s = site ? s0 : n - 1;
+  double g[3] = {0.0, 0.0, 0.0};
   if (site && t1 < P) {
-    const int gx = wrap(i0[0] - t1, K);
+    const int gx = wrap(I0[s] - t1, K), iy = I0[n + s], iz = I0[2 * n + s];
+    const double X0 = TB[(long)(t1 * 2) * n + s], X1 = TB[(long)(t1 * 2 + 1) * n + s];
+    double S00 = 0.0, S10 = 0.0, S01 = 0.0;
 #pragma unroll
     for (int t2 = 0; t2 < P; ++t2) {
-      const long row = ((long)gx * K + wrap(i0[1] - t2, K)) * K;
+      const long row = ((long)gx * K + wrap(iy - t2, K)) * K;
       double z0 = 0.0, z1 = 0.0;
 #pragma unroll
       for (int t3 = 0; t3 < P; ++t3) {
-        const double v = phi[row + wrap(i0[2] - t3, K)];
-        z0 += v * th[1][t3][0];
-        z1 += v * th[1][t3][1];
+        const double val = phi[row + wrap(iz - t3, K)];
+        z0 += val * TB[(long)((2 * P + t3) * 2) * n + s];
+        z1 += val * TB[(long)((2 * P + t3) * 2 + 1) * n + s];
       }
-      S00 += th[0][t2][0] * z0;
-      S10 += th[0][t2][1] * z0;
-      S01 += th[0][t2][0] * z1;
+      S00 += TB[(long)((P + t2) * 2) * n + s] * z0;
+      S10 += TB[(long)((P + t2) * 2 + 1) * n + s] * z0;
+      S01 += TB[(long)((P + t2) * 2) * n + s] * z1;
     }
+    g[0] = X1 * S00;
+    g[1] = X0 * S10;
+    g[2] = X0 * S01;
   }
-  const bool on = site && t1 < P;
-  double g[3] = {on ? X[1] * S00 : 0.0, on ? X[0] * S10 : 0.0, on ? X[0] * S01 : 0.0};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     g[a] += __shfl_xor(g[a], 1);
     g[a] += __shfl_xor(g[a], 2);
     g[a] += __shfl_xor(g[a], 4);
   }
-  if (site && t1 == 0)
+  const bool refused = flag[0] != 0;
+  if (site && t1 == 0) {
+    const int j = list[s];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) out[3 * j + a] = -g[a];
+    for (int a = 0; a < 3; ++a) out[3 * j + a] = refused ? __builtin_nan("") : -g[a];
+  }
 }
 
 // energy = (C/2) sum of the partials in block order; NaN if the spread refused
@@ -703,6 +800,20 @@ __global__ __launch_bounds__(256) void k_pme_energy(const double* __restrict__ e
     const double t = ((we[0] + we[1]) + we[2]) + we[3];
     energy[0] = flag[0] ? __builtin_nan("") : 0.5 * kCoulomb * t;
   }
+}
+
+// Five mesh passes: forward along z, y; forward x, influence function,
+// inverse x; inverse along y, z (real part into phi).
+template <int P, int K>
+void mesh_fft(tk_ctx* ctx, hipStream_t st, const unsigned long long* fx, double2* c2, double* phi,
+              double box, double beta, Gate gate) {
+  const int nlines = K * K / Fft<K>::L;
+  ProfScope ps(ctx, st, "pme_fft");
+  k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(2, fx, c2, gate);
+  k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(1, nullptr, c2, gate);
+  k_pme_fft_conv<P, K><<<nlines, 256, 0, st>>>(c2, box, beta, gate);
+  k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(1, c2, nullptr, gate);
+  k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(2, c2, phi, gate);
 }
 
 // Bin, spread and convolve: the potential phi on the mesh (scratch of this
@@ -729,24 +840,97 @@ tk_status mesh_potential(tk_ctx* ctx, hipStream_t st, int n, Src src, double box
   int* bin = start + K + 1;
   int* slot = bin + nn;
   int* list = slot + nn;
-  const int nlines = K * K / Fft<K>::L;
   {
     ProfScope ps(ctx, st, "pme_spread");
     k_pme_bin<Src><<<na, 256, 0, st>>>(n, src, box, K, bcnt, bin, slot, (int*)flag, gate);
     k_pme_scatter<<<na, 256, 0, st>>>(n, K, na, bcnt, bin, slot, start, list, gate);
-    k_pme_spread<P, K, Src><<<K * (K / spread_rows<K>()), kSpreadThreads, 0, st>>>(
+    k_pme_spread<P, K, Src><<<K * (K / spread_rows<K>()), spread_threads<P>(), 0, st>>>(
         src, box, start, list, fx, (int*)flag, gate);
   }
-  {
-    ProfScope ps(ctx, st, "pme_fft");
-    k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(2, fx, c2, gate);
-    k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(1, nullptr, c2, gate);
-    k_pme_fft_conv<P, K><<<nlines, 256, 0, st>>>(c2, box, beta, gate);
-    k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(1, c2, nullptr, gate);
-    k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(2, c2, (double*)phi, gate);
-  }
+  mesh_fft<P, K>(ctx, st, fx, c2, (double*)phi, box, beta, gate);
   *phi_out = (double*)phi;
   *flag_out = (int*)flag;
+  return TK_OK;
+}
+
+// Prepared sites of a solve (see k_pme_tables): sort buffers, then I0 [3][n],
+// then the weight table [6 P][n].
+struct Sites {
+  int* bcnt;
+  int* start;
+  int* bin;
+  int* slot;
+  int* list;
+  int* I0;
+  double* TB;
+  int* flag;
+};
+
+template <int P, int K>
+tk_status sites_layout(tk_ctx* ctx, hipStream_t st, int n, Sites& S) {
+  const size_t nn = n > 0 ? n : 1;
+  const int na = n > 0 ? ceil_div(n, 256) : 1;
+  void *ints, *tb, *flag;
+  tk_status s;
+  if ((s = scratch(ctx, per_stream("pme_sites_i", st).c_str(),
+                   sizeof(int) * ((size_t)na * K + K + 1 + 6 * nn), &ints)) ||
+      (s = scratch(ctx, per_stream("pme_sites_tb", st).c_str(), sizeof(double) * 6 * P * nn,
+                   &tb)) ||
+      (s = scratch(ctx, per_stream("pme_flag", st).c_str(), sizeof(int) * 64, &flag)))
+    return s;
+  S.bcnt = (int*)ints;
+  S.start = S.bcnt + (size_t)na * K;
+  S.bin = S.start + K + 1;
+  S.slot = S.bin + nn;
+  S.list = S.slot + nn;
+  S.I0 = S.list + nn;
+  S.TB = (double*)tb;
+  S.flag = (int*)flag;
+  return TK_OK;
+}
+
+template <int P, int K>
+tk_status prepare_sites(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos,
+                        long ps) {
+  Sites S;
+  tk_status s;
+  if ((s = sites_layout<P, K>(ctx, st, n, S))) return s;
+  const int na = n > 0 ? ceil_div(n, 256) : 1;
+  const SrcDipole src{pos, ps, nullptr};
+  ProfScope ps_(ctx, st, "pme_prepare");
+  k_pme_bin<SrcDipole><<<na, 256, 0, st>>>(n, src, box, K, S.bcnt, S.bin, S.slot, S.flag, Gate{});
+  k_pme_scatter<<<na, 256, 0, st>>>(n, K, na, S.bcnt, S.bin, S.slot, S.start, S.list, Gate{});
+  if (n > 0) k_pme_tables<P><<<na, 256, 0, st>>>(n, src, box, K, S.list, S.I0, S.TB);
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+template <int P, int K>
+tk_status field_prepared(tk_ctx* ctx, hipStream_t st, int n, double box, const double* v,
+                         double beta, double* out, Gate gate) {
+  Sites S;
+  tk_status s;
+  if ((s = sites_layout<P, K>(ctx, st, n, S))) return s;
+  const long KK = (long)K * K * K;
+  void *fix, *cg, *phi;
+  if ((s = scratch(ctx, per_stream("pme_fix", st).c_str(), sizeof(unsigned long long) * KK, &fix)) ||
+      (s = scratch(ctx, per_stream("pme_c", st).c_str(), sizeof(double2) * KK, &cg)) ||
+      (s = scratch(ctx, per_stream("pme_phi", st).c_str(), sizeof(double) * KK, &phi)))
+    return s;
+  auto* fx = (unsigned long long*)fix;
+  {
+    ProfScope ps(ctx, st, "pme_spread");
+    k_pme_spread_tab<P, K><<<K * (K / spread_rows<K>()), spread_threads<P>(), 0, st>>>(
+        n, S.start, S.list, S.I0, S.TB, v, fx, S.flag, gate);
+  }
+  mesh_fft<P, K>(ctx, st, fx, (double2*)cg, (double*)phi, box, beta, gate);
+  {
+    ProfScope ps(ctx, st, "pme_field");
+    if (n > 0)
+      k_pme_field_tab<P><<<ceil_div((long)n * 8, 256), 256, 0, st>>>(
+          n, K, S.list, S.I0, S.TB, (const double*)phi, S.flag, out, gate);
+  }
+  TK_HIP(hipGetLastError());
   return TK_OK;
 }
 
@@ -776,24 +960,6 @@ tk_status run_pme(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const doubl
   return TK_OK;
 }
 
-template <int P, int K>
-tk_status run_pme_dipoles(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos,
-                          long ps, const double* v, double beta, double* out, Gate gate) {
-  double* phi;
-  int* flag;
-  tk_status s;
-  const SrcDipole src{pos, ps, v};
-  if ((s = mesh_potential<P, K>(ctx, st, n, src, box, beta, gate, &phi, &flag))) return s;
-  {
-    ProfScope ps_(ctx, st, "pme_field");
-    if (n > 0)
-      k_pme_field<P, SrcDipole><<<ceil_div((long)n * 8, 256), 256, 0, st>>>(n, src, box, K, phi,
-                                                                         out, gate);
-  }
-  TK_HIP(hipGetLastError());
-  return TK_OK;
-}
-
 // b[3 s + a] += f[3 perm[s] + a]
 __global__ __launch_bounds__(256) void k_add_permuted(int n, const int32_t* __restrict__ perm,
                                                       const double* __restrict__ f,
@@ -817,18 +983,6 @@ tk_status run_pme_k(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const dou
   }
 }
 
-template <int P>
-tk_status run_dip_k(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos, long ps,
-                    const double* v, double beta, int K, double* out, Gate gate) {
-  switch (K) {
-    case 16: return run_pme_dipoles<P, 16>(ctx, st, n, box, pos, ps, v, beta, out, gate);
-    case 32: return run_pme_dipoles<P, 32>(ctx, st, n, box, pos, ps, v, beta, out, gate);
-    case 64: return run_pme_dipoles<P, 64>(ctx, st, n, box, pos, ps, v, beta, out, gate);
-    case 128: return run_pme_dipoles<P, 128>(ctx, st, n, box, pos, ps, v, beta, out, gate);
-    default: return TK_E_ARG;
-  }
-}
-
 tk_status pme_dispatch(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* mpole,
                        double beta, int K, int order, double* energy, double* force,
                        double* field) {
@@ -848,18 +1002,54 @@ bool pme_args_ok(int grid, int order) {
          grid >= 2 * order;
 }
 
-tk_status pme_dipole_field(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos,
-                           long ps, const double* v, double beta, int grid, int order,
-                           double* out, const int32_t* done, int run_when_done) {
+namespace {
+template <int P>
+tk_status prepare_k(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos, long ps,
+                    int K) {
+  switch (K) {
+    case 16: return prepare_sites<P, 16>(ctx, st, n, box, pos, ps);
+    case 32: return prepare_sites<P, 32>(ctx, st, n, box, pos, ps);
+    case 64: return prepare_sites<P, 64>(ctx, st, n, box, pos, ps);
+    case 128: return prepare_sites<P, 128>(ctx, st, n, box, pos, ps);
+    default: return TK_E_ARG;
+  }
+}
+template <int P>
+tk_status field_k(tk_ctx* ctx, hipStream_t st, int n, double box, const double* v, double beta,
+                  int K, double* out, Gate gate) {
+  switch (K) {
+    case 16: return field_prepared<P, 16>(ctx, st, n, box, v, beta, out, gate);
+    case 32: return field_prepared<P, 32>(ctx, st, n, box, v, beta, out, gate);
+    case 64: return field_prepared<P, 64>(ctx, st, n, box, v, beta, out, gate);
+    case 128: return field_prepared<P, 128>(ctx, st, n, box, v, beta, out, gate);
+    default: return TK_E_ARG;
+  }
+}
+}  // namespace
+
+tk_status pme_prepare_sites(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos,
+                            long ps, int grid, int order) {
+  if (!pme_args_ok(grid, order)) return TK_E_ARG;
+  switch (order) {
+    case 5: return prepare_k<5>(ctx, st, n, box, pos, ps, grid);
+    case 6: return prepare_k<6>(ctx, st, n, box, pos, ps, grid);
+    case 7: return prepare_k<7>(ctx, st, n, box, pos, ps, grid);
+    default: return prepare_k<8>(ctx, st, n, box, pos, ps, grid);
+  }
+}
+
+tk_status pme_prepared_dipole_field(tk_ctx* ctx, hipStream_t st, int n, double box,
+                                    const double* v, double beta, int grid, int order,
+                                    double* out, const int32_t* done, int run_when_done) {
   if (!pme_args_ok(grid, order)) return TK_E_ARG;
   Gate gate;
   gate.done = done;
   gate.when = run_when_done;
   switch (order) {
-    case 5: return run_dip_k<5>(ctx, st, n, box, pos, ps, v, beta, grid, out, gate);
-    case 6: return run_dip_k<6>(ctx, st, n, box, pos, ps, v, beta, grid, out, gate);
-    case 7: return run_dip_k<7>(ctx, st, n, box, pos, ps, v, beta, grid, out, gate);
-    default: return run_dip_k<8>(ctx, st, n, box, pos, ps, v, beta, grid, out, gate);
+    case 5: return field_k<5>(ctx, st, n, box, v, beta, grid, out, gate);
+    case 6: return field_k<6>(ctx, st, n, box, v, beta, grid, out, gate);
+    case 7: return field_k<7>(ctx, st, n, box, v, beta, grid, out, gate);
+    default: return field_k<8>(ctx, st, n, box, v, beta, grid, out, gate);
   }
 }
 

@@ -236,12 +236,19 @@ tk_status build_plans(tk_ctx* ctx, hipStream_t st, int nj, const int* slots, int
 // mu_out is written in stream order after the return.
 // Reciprocal space (smooth PME, pme.hip).  grid: 16, 32, 64 or 128; order 5..8.
 bool pme_args_ok(int grid, int order);
-// -grad phi of dipoles v ([n][3], the sites' own order) at positions
-// pos[a * ps + j], into out; with done set, the launches return at once while
-// *done != 0 (run_when_done 0) or while *done == 0 (run_when_done 1).
-tk_status pme_dipole_field(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos,
-                           long ps, const double* v, double beta, int grid, int order,
-                           double* out, const int32_t* done, int run_when_done);
+// -grad phi of dipoles v ([n][3], the sites' own order) for a solve whose
+// sites (positions pos[a * ps + j]) do not move: pme_prepare_sites sorts
+// the sites and tabulates their spline weights once (this stream's scratch);
+// pme_prepared_dipole_field then takes only the dipoles; with done set, its
+// launches return at once while *done != 0 (run_when_done 0) or while
+// *done == 0 (run_when_done 1).  A contribution
+// refused by the fixed-point spread makes this and every later field of the
+// solve NaN.
+tk_status pme_prepare_sites(tk_ctx* ctx, hipStream_t st, int n, double box, const double* pos,
+                            long ps, int grid, int order);
+tk_status pme_prepared_dipole_field(tk_ctx* ctx, hipStream_t st, int n, double box,
+                                    const double* v, double beta, int grid, int order,
+                                    double* out, const int32_t* done, int run_when_done);
 // b_sorted[3 s + a] += reciprocal field of the permanent multipoles at site perm[s].
 tk_status pme_perm_field_add(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
                              const double* mpole, double beta, int grid, int order,
