@@ -179,3 +179,29 @@ def test_pcg_ewald_guess_zero_polarizability_and_errors(ctx, tk):
     for K, p, beta in ((48, 5, S["beta"]), (16, 4, S["beta"]), (16, 5, 0.0)):
         with pytest.raises(tk.TkError):
             ctx.polarize_pcg_ewald(sysr, lst, w.mpole, w.polarity, w.thole, beta, 7.0, K, p)
+
+
+def test_full_ewald_polarization_forces(ctx):
+    # the composition of the oracle pin, on the device: real-space
+    # polarization forces plus the difference of two PME force calls, at each
+    # side's own converged full-Ewald dipoles
+    w, sysr, lst, rp, cp = _ewald_case(ctx, "water216", 32, 5)
+    beta, K, p = S["beta"], 32, 5
+    mu, _ = ctx.polarize_pcg_ewald(sysr, lst, w.mpole, w.polarity, w.thole, beta, 7.0, K, p,
+                                   tol_debye=1e-9)
+    mo, _ = O.polarize_pcg_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                 beta, 7.0, K, p, tol_debye=1e-9)
+    import torch
+    mpg = torch.as_tensor(w.mpole, device=mu.device).clone()
+    mpg[:, 1:4] += mu
+    _, f, _ = ctx.epolar_real(sysr, lst, w.mpole, w.polarity, w.thole, mu, beta, 7.0)
+    _, f1, _ = ctx.pme_mpole(sysr, mpg, beta, K, p, want_field=False)
+    _, f0, _ = ctx.pme_mpole(sysr, w.mpole, beta, K, p, want_field=False)
+    F = np_(f) + np_(f1) - np_(f0)
+    _, fo, _ = O.epolar_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, mo,
+                             beta, 7.0)
+    m2 = w.mpole.copy()
+    m2[:, 1:4] += mo
+    Fo = fo + O.pme_mpole(w.xyz, w.box, m2, beta, K, p)[1] - O.pme_mpole(w.xyz, w.box, w.mpole,
+                                                                        beta, K, p)[1]
+    assert fmax_rel(F, Fo) < 1e-8

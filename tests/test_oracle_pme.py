@@ -211,3 +211,35 @@ def test_ewald_polarization_energy_does_not_depend_on_the_split():
     real = [O.polarize_pcg(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, beta, rc,
                            tol_debye=1e-10, maxiter=200)[1]["epol"] for beta in (0.9, 1.0)]
     assert abs(real[0] - real[1]) > 1e3 * abs(e[0] - e[1])
+
+
+def test_full_ewald_polarization_forces_compose():
+    # at fixed mu the reciprocal part of the polarization energy is
+    # E_pme(M + mu) - E_pme(M) (the cross term -C mu.E_perm_recip plus the
+    # dipoles' own -1/2 C mu.R mu), so the full-Ewald polarization force is
+    # the real-space one plus the difference of two PME forces; at converged
+    # dipoles it is the gradient of E_pol with the dipoles re-solved
+    w = synth.amoeba_water_box(20, 8.6, 4)
+    rc, beta, K, p = 4.29, 0.9, 16, 5
+    rp, cp = O.nblist(w.xyz, w.box, rc)
+
+    def solve(xyz):
+        mu, info = O.polarize_pcg_ewald(xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                        beta, rc, K, p, tol_debye=1e-12, maxiter=300)
+        assert info["converged"] == 1
+        return mu, info["epol"]
+    mu, _ = solve(w.xyz)
+    _, F, _ = O.epolar_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, mu, beta,
+                            rc)
+    m2 = w.mpole.copy()
+    m2[:, 1:4] += mu
+    F += (O.pme_mpole(w.xyz, w.box, m2, beta, K, p)[1] -
+          O.pme_mpole(w.xyz, w.box, w.mpole, beta, K, p)[1])
+    h = 1e-5
+    for i in (0, 5, 33):
+        for a in range(3):
+            xp, xm = w.xyz.copy(), w.xyz.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            g = (solve(xp)[1] - solve(xm)[1]) / (2 * h)
+            assert abs(F[i, a] + g) <= 1e-8 * np.abs(F).max()
