@@ -84,6 +84,9 @@ def lib():
                                             _dp, C.c_double, C.c_double, C.c_int, C.c_int,
                                             C.c_double, C.c_int, C.c_void_p, _dp,
                                             C.POINTER(PcgInfo)]
+        L.or_rotate_mpole.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _dp, _dp]
+        L.or_empole_frames.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _ip, _ip, _dp,
+                                       C.c_double, C.c_double, _dp, _dp]
         _lib = L
     return _lib
 
@@ -341,3 +344,30 @@ def pme_mpole(xyz, box, mpole, beta, K, order=5):
     if st:
         raise OracleError(st)
     return e.value, force, field
+
+
+FRAME_NONE, FRAME_Z_THEN_X, FRAME_BISECTOR = 0, 1, 2
+
+
+def rotate_mpole(xyz, box, ftype, fatoms, local):
+    """Lab-frame multipoles from local-frame ones (or_rotate_mpole)."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    out = np.zeros((n, 10))
+    st = lib().or_rotate_mpole(n, xyz, box, _i(ftype), _i(fatoms), _d(local), out)
+    if st:
+        raise OracleError(st)
+    return out
+
+
+def empole_frames(xyz, box, molid, row_ptr, col, ftype, fatoms, local, beta, cutoff):
+    """Energies and forces (torques included) with local-frame multipoles."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    energy = np.zeros(3)
+    force = np.zeros((n, 3))
+    st = lib().or_empole_frames(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _i(ftype),
+                                _i(fatoms), _d(local), beta, cutoff, energy, force)
+    if st:
+        raise OracleError(st)
+    return energy, force

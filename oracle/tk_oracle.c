@@ -1161,3 +1161,216 @@ int or_pme_mpole(int n, const double* xyz, double box, const double* mpole, doub
   free(g0);
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Local-frame multipoles (the rotation and torque steps that section
+ * "Hotspots" lists beside the multipole routines).  Reading (the paper gives
+ * no frame definitions): the usual AMOEBA frames, with d_z = r_zatom - r_i and
+ * d_x = r_xatom - r_i (minimum image):
+ *   type 0 (none):      R = I;
+ *   type 1 (Z-then-X):  z = d_z/|d_z|, x = unit(d_x - (d_x.z) z);
+ *   type 2 (bisector):  z = unit(d_z/|d_z| + d_x/|d_x|), x = unit(u_x - (u_x.z) z),
+ *                       u_x = d_x/|d_x|;
+ * y = z cross x.  With R = [x y z] (columns), the lab-frame multipoles are
+ *   q = q_loc, mu = R mu_loc, Theta = R Theta_loc R^T.
+ * Values are carried with their derivatives with respect to the nine
+ * coordinates of (r_i, r_zatom, r_xatom) (forward-mode dual numbers), so the
+ * rotated multipoles come with their exact Jacobian. */
+typedef struct {
+  double v, d[9];
+} or_dual;
+
+static or_dual od_const(double v) {
+  or_dual r;
+  r.v = v;
+  for (int k = 0; k < 9; ++k) r.d[k] = 0.0;
+  return r;
+}
+static or_dual od_add(or_dual a, or_dual b) {
+  or_dual r;
+  r.v = a.v + b.v;
+  for (int k = 0; k < 9; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+static or_dual od_sub(or_dual a, or_dual b) {
+  or_dual r;
+  r.v = a.v - b.v;
+  for (int k = 0; k < 9; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+static or_dual od_mul(or_dual a, or_dual b) {
+  or_dual r;
+  r.v = a.v * b.v;
+  for (int k = 0; k < 9; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+static or_dual od_div(or_dual a, or_dual b) {
+  or_dual r;
+  r.v = a.v / b.v;
+  for (int k = 0; k < 9; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  return r;
+}
+static or_dual od_sqrt(or_dual a) {
+  or_dual r;
+  r.v = sqrt(a.v);
+  for (int k = 0; k < 9; ++k) r.d[k] = a.d[k] / (2.0 * r.v);
+  return r;
+}
+static or_dual od_dot3(const or_dual* a, const or_dual* b) {
+  return od_add(od_add(od_mul(a[0], b[0]), od_mul(a[1], b[1])), od_mul(a[2], b[2]));
+}
+static void od_unit3(const or_dual* a, or_dual* out) {
+  or_dual nrm = od_sqrt(od_dot3(a, a));
+  for (int c = 0; c < 3; ++c) out[c] = od_div(a[c], nrm);
+}
+
+/* Frame vectors of site i (as duals over r_i, r_zatom, r_xatom), minimum image. */
+static void or_frame_axes(const double* xyz, double box, int i, int type, int iz, int ix,
+                          or_dual ax[3][3]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) ax[a][b] = od_const(a == b ? 1.0 : 0.0);
+  if (type == 0) return;
+  or_dual dz[3], dx[3];
+  for (int c = 0; c < 3; ++c) {
+    double tz = xyz[3 * iz + c] - xyz[3 * i + c], tx = xyz[3 * ix + c] - xyz[3 * i + c];
+    dz[c] = od_const(tz - box * rint(tz / box));
+    dx[c] = od_const(tx - box * rint(tx / box));
+    dz[c].d[c] = -1.0;        /* d/dr_i */
+    dz[c].d[3 + c] = 1.0;     /* d/dr_zatom */
+    dx[c].d[c] = -1.0;
+    dx[c].d[6 + c] = 1.0;     /* d/dr_xatom */
+  }
+  or_dual z[3], x[3], ux[3];
+  if (type == 1) {
+    od_unit3(dz, z);
+    for (int c = 0; c < 3; ++c) ux[c] = dx[c];
+  } else {
+    or_dual uz[3], s[3];
+    od_unit3(dz, uz);
+    od_unit3(dx, ux);
+    for (int c = 0; c < 3; ++c) s[c] = od_add(uz[c], ux[c]);
+    od_unit3(s, z);
+  }
+  or_dual p = od_dot3(ux, z), w[3];
+  for (int c = 0; c < 3; ++c) w[c] = od_sub(ux[c], od_mul(p, z[c]));
+  od_unit3(w, x);
+  or_dual y[3];
+  y[0] = od_sub(od_mul(z[1], x[2]), od_mul(z[2], x[1]));
+  y[1] = od_sub(od_mul(z[2], x[0]), od_mul(z[0], x[2]));
+  y[2] = od_sub(od_mul(z[0], x[1]), od_mul(z[1], x[0]));
+  for (int c = 0; c < 3; ++c) {   /* columns x, y, z */
+    ax[c][0] = x[c];
+    ax[c][1] = y[c];
+    ax[c][2] = z[c];
+  }
+}
+
+/* Lab-frame multipoles of site i as duals (10 components, stored layout). */
+static void or_rotate_site(const double* xyz, double box, int i, int type, int iz, int ix,
+                           const double* loc, or_dual out[10]) {
+  or_dual R[3][3];
+  or_frame_axes(xyz, box, i, type, iz, ix, R);
+  double tl[3][3];
+  tl[0][0] = loc[4]; tl[0][1] = tl[1][0] = loc[5]; tl[0][2] = tl[2][0] = loc[6];
+  tl[1][1] = loc[7]; tl[1][2] = tl[2][1] = loc[8]; tl[2][2] = loc[9];
+  out[0] = od_const(loc[0]);
+  for (int a = 0; a < 3; ++a) {
+    or_dual s = od_const(0.0);
+    for (int b = 0; b < 3; ++b) s = od_add(s, od_mul(R[a][b], od_const(loc[1 + b])));
+    out[1 + a] = s;
+  }
+  const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+  for (int k = 0; k < 6; ++k) {
+    or_dual s = od_const(0.0);
+    for (int c = 0; c < 3; ++c)
+      for (int d = 0; d < 3; ++d)
+        s = od_add(s, od_mul(od_mul(R[ia[k]][c], od_const(tl[c][d])), R[ib[k]][d]));
+    out[4 + k] = s;
+  }
+}
+
+static int or_frames_args(int n, const int32_t* ftype, const int32_t* fatoms) {
+  for (int i = 0; i < n; ++i) {
+    int t = ftype[i];
+    if (t < 0 || t > 2) return OR_E_ARG;
+    if (t > 0) {
+      int iz = fatoms[2 * i], ix = fatoms[2 * i + 1];
+      if (iz < 0 || iz >= n || ix < 0 || ix >= n || iz == i || ix == i || iz == ix) return OR_E_ARG;
+    }
+  }
+  return OR_OK;
+}
+
+int or_rotate_mpole(int n, const double* xyz, double box, const int32_t* ftype,
+                    const int32_t* fatoms, const double* local, double* global) {
+  if (n < 0 || !(box > 0.0)) return OR_E_ARG;
+  int st = or_frames_args(n, ftype, fatoms);
+  if (st) return st;
+  for (int i = 0; i < n; ++i) {
+    or_dual m[10];
+    or_rotate_site(xyz, box, i, ftype[i], fatoms[2 * i], fatoms[2 * i + 1], local + 10 * i, m);
+    for (int k = 0; k < 10; ++k) global[10 * i + k] = m[k].v;
+  }
+  return OR_OK;
+}
+
+/* Permanent-multipole real-space energy and forces with local frames.  The
+ * energy is that of or_empole_real at the rotated multipoles M(x).  Its
+ * gradient has the direct part (or_empole_real's forces at fixed M) and the
+ * frame part: with G_i,c = dE/dM_i,c, which is the pair energy with a unit
+ * multipole in component c of site i (E is linear in each site's
+ * multipoles), the force on atom k gains -sum_i sum_c G_i,c dM_i,c/dx_k over
+ * the sites i whose frame contains k.  energy[3] as or_empole_real. */
+int or_empole_frames(int n, const double* xyz, double box, const int32_t* molid,
+                     const int32_t* row_ptr, const int32_t* col, const int32_t* ftype,
+                     const int32_t* fatoms, const double* local, double beta, double rc,
+                     double* energy, double* force) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  if ((st = or_frames_args(n, ftype, fatoms))) return st;
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  or_dual* M = (or_dual*)malloc(sizeof(or_dual) * 10 * nn);
+  double* Mg = (double*)calloc(10 * nn, sizeof(double));
+  double* G = (double*)calloc(10 * nn, sizeof(double));
+  double vir[9];
+  for (int i = 0; i < n; ++i) {
+    or_rotate_site(xyz, box, i, ftype[i], fatoms[2 * i], fatoms[2 * i + 1], local + 10 * i,
+                   M + 10 * i);
+    for (int k = 0; k < 10; ++k) Mg[10 * i + k] = M[10 * i + k].v;
+  }
+  or_empole_real(n, xyz, box, molid, row_ptr, col, Mg, beta, rc, energy, force, vir);
+  double rc2 = rc * rc;
+  for (int i = 0; i < n; ++i)
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int j = col[p];
+      double d[3], r2;
+      or_image(xyz + 3 * i, xyz + 3 * j, box, d, &r2);
+      if (!(r2 <= rc2)) continue;
+      double r = sqrt(r2), B[6], R[6], g[6];
+      or_radial(r, beta, 5, B, R);
+      int excl = molid[i] == molid[j];
+      for (int k = 0; k <= 5; ++k) g[k] = excl ? B[k] - R[k] : B[k];
+      for (int c = 0; c < 10; ++c) {
+        double unit[10] = {0.0}, e, de[3];
+        unit[c] = 1.0;
+        or_mpole_pair(d, unit, Mg + 10 * j, g, &e, de);
+        G[10 * i + c] += e;
+        or_mpole_pair(d, Mg + 10 * i, unit, g, &e, de);
+        G[10 * j + c] += e;
+      }
+    }
+  for (int i = 0; i < n; ++i) {
+    if (ftype[i] == 0) continue;
+    int who[3] = {i, fatoms[2 * i], fatoms[2 * i + 1]};
+    for (int s = 0; s < 3; ++s)
+      for (int a = 0; a < 3; ++a) {
+        double g = 0.0;
+        for (int c = 0; c < 10; ++c) g += G[10 * i + c] * M[10 * i + c].d[3 * s + a];
+        force[3 * who[s] + a] -= g;
+      }
+  }
+  free(M);
+  free(Mg);
+  free(G);
+  return OR_OK;
+}

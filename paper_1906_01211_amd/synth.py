@@ -143,6 +143,45 @@ def charge_lj_water_box(n_w: int, box: float, seed: int) -> WaterBox:
         params=dict(kind="charge_lj", n_w=n_w, seed=seed))
 
 
+FRAME_NONE, FRAME_Z_THEN_X, FRAME_BISECTOR = 0, 1, 2
+
+
+def water_frames(n_w: int):
+    """Local-frame topology of n_w waters (atoms O, H1, H2 per molecule): O
+    bisector (z atom H1, x atom H2); each H Z-then-X (z atom O, x atom the
+    other H).  Returns (frame_type[n] int32, frame_atoms[n, 2] int32)."""
+    n = 3 * n_w
+    base = 3 * np.arange(n_w)
+    ftype = np.zeros(n, np.int32)
+    fat = np.zeros((n, 2), np.int32)
+    ftype[base] = FRAME_BISECTOR
+    fat[base, 0], fat[base, 1] = base + 1, base + 2
+    for h, other in ((1, 2), (2, 1)):
+        ftype[base + h] = FRAME_Z_THEN_X
+        fat[base + h, 0], fat[base + h, 1] = base, base + other
+    return ftype, fat
+
+
+def water_local_multipoles(n_w: int, seed: int) -> np.ndarray:
+    """Multipoles in the local frames of water_frames: O -0.52 / H +0.26,
+    dipoles along the local z axis (O 0.15, H -0.06 e A) with a small
+    in-plane component, traceless quadrupoles (diagonal plus a small xz
+    term), every value jittered by a few per cent (seeded)."""
+    rng = np.random.default_rng(seed)
+    n = 3 * n_w
+    is_o = (np.arange(n) % 3) == 0
+    m = np.zeros((n, 10))
+    m[:, 0] = np.where(is_o, -0.52, 0.26)
+    m[:, 1] = np.where(is_o, 0.0, 0.02)
+    m[:, 3] = np.where(is_o, 0.15, -0.06)
+    m[:, 4] = np.where(is_o, 0.30, 0.03)
+    m[:, 7] = np.where(is_o, -0.45, -0.02)
+    m[:, 6] = np.where(is_o, 0.0, 0.01)
+    m[:, 1:] *= 1.0 + 0.05 * rng.standard_normal((n, 9))
+    m[:, 9] = -(m[:, 4] + m[:, 7])
+    return m
+
+
 # Workload settings (readings: Ewald beta with erfc(beta rc) ~ 1e-8 at 7 A,
 # list cutoffs = kernel cutoffs + 1e-3 A skin, taper on [0.9 rc, rc]).
 AMOEBA_SETTINGS = dict(rc_ewald=7.0, rc_vdw=9.0, skin=1e-3, beta=0.5446, tol_debye=1e-5,

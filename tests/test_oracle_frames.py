@@ -1,0 +1,124 @@
+"""Pins of the oracle's local-frame multipoles: the frame axes, the rotation
+to the lab frame, rigid-rotation invariance of the energy, and the forces
+(torques included) against finite differences of the energy."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_01211_amd import synth
+
+BETA = 0.5446
+
+
+def waters(n_w=27, box=9.4, seed=2):
+    w = synth.amoeba_water_box(n_w, box, seed)
+    ft, fa = synth.water_frames(n_w)
+    loc = synth.water_local_multipoles(n_w, seed)
+    return w, ft, fa, loc
+
+
+def unit_dipoles_rotated(w, ft, fa, axis):
+    loc = np.zeros((w.n, 10))
+    loc[:, 1 + axis] = 1.0
+    return O.rotate_mpole(w.xyz, w.box, ft, fa, loc)[:, 1:4]
+
+
+def test_frame_axes_orthonormal_and_defined_as_stated():
+    w, ft, fa, _ = waters()
+    X, Y, Z = (unit_dipoles_rotated(w, ft, fa, a) for a in range(3))
+    for A in (X, Y, Z):
+        assert np.allclose(np.sum(A * A, axis=1), 1.0, atol=1e-14)
+    assert np.allclose(np.sum(X * Y, axis=1), 0.0, atol=1e-14)
+    assert np.allclose(np.sum(X * Z, axis=1), 0.0, atol=1e-14)
+    assert np.allclose(np.cross(Z, X), Y, atol=1e-14)   # right-handed
+    d = lambda i, j: (w.xyz[j] - w.xyz[i]) - w.box * np.rint((w.xyz[j] - w.xyz[i]) / w.box)
+    for m in (0, 7, 20):
+        o, h1, h2 = 3 * m, 3 * m + 1, 3 * m + 2
+        u1, u2 = d(o, h1), d(o, h2)
+        u1, u2 = u1 / np.linalg.norm(u1), u2 / np.linalg.norm(u2)
+        bis = (u1 + u2) / np.linalg.norm(u1 + u2)
+        assert np.allclose(Z[o], bis, atol=1e-14)               # bisector
+        assert abs(X[o] @ np.cross(u1, u2)) < 1e-14             # x in the HOH plane
+        assert X[o] @ u2 > 0
+        zh = d(h1, o) / np.linalg.norm(d(h1, o))
+        assert np.allclose(Z[h1], zh, atol=1e-14)               # Z-then-X
+        assert abs(X[h1] @ zh) < 1e-14 and X[h1] @ d(h1, h2) > 0
+
+
+def test_rotation_keeps_invariants_and_none_is_identity():
+    w, ft, fa, loc = waters()
+    g = O.rotate_mpole(w.xyz, w.box, ft, fa, loc)
+    assert np.array_equal(g[:, 0], loc[:, 0])
+    assert np.allclose(np.linalg.norm(g[:, 1:4], axis=1), np.linalg.norm(loc[:, 1:4], axis=1),
+                       rtol=1e-14)
+    def full(m):
+        T = np.zeros((len(m), 3, 3))
+        T[:, 0, 0], T[:, 0, 1], T[:, 0, 2] = m[:, 4], m[:, 5], m[:, 6]
+        T[:, 1, 1], T[:, 1, 2], T[:, 2, 2] = m[:, 7], m[:, 8], m[:, 9]
+        return T + np.transpose(T, (0, 2, 1)) - T * np.eye(3)
+    Tl, Tg = full(loc), full(g)
+    assert np.allclose(np.trace(Tg, axis1=1, axis2=2), 0.0, atol=1e-14)
+    assert np.allclose(np.einsum("nab,nab->n", Tg, Tg), np.einsum("nab,nab->n", Tl, Tl),
+                       rtol=1e-13)
+    none = O.rotate_mpole(w.xyz, w.box, np.zeros(w.n, np.int32), fa, loc)
+    assert np.array_equal(none, loc)
+
+
+def test_energy_invariant_under_rigid_rotation_with_frames():
+    # isolated cluster in a large box: rotating every position rigidly leaves
+    # the local-frame energy unchanged; lab-frame multipoles would not follow
+    w, ft, fa, loc = waters(n_w=8, box=7.0, seed=3)
+    box = 60.0
+    xyz = w.xyz + 26.0
+    rp, cp = O.nblist(xyz, box, 29.0)
+    th = 0.7
+    Rz = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1.0]])
+    Rx = np.array([[1.0, 0, 0], [0, np.cos(1.1), -np.sin(1.1)], [0, np.sin(1.1), np.cos(1.1)]])
+    c = xyz.mean(axis=0)
+    xyz2 = (xyz - c) @ (Rx @ Rz).T + c
+    e1, _ = O.empole_frames(xyz, box, w.molid, rp, cp, ft, fa, loc, 0.0, 29.0)
+    e2, _ = O.empole_frames(xyz2, box, w.molid, rp, cp, ft, fa, loc, 0.0, 29.0)
+    assert e2[0] == pytest.approx(e1[0], rel=1e-12)
+    lab = O.rotate_mpole(xyz, box, ft, fa, loc)
+    e3, _, _ = O.empole_real(xyz2, box, w.molid, rp, cp, lab, 0.0, 29.0)
+    assert abs(e3[0] - e1[0]) > 1e-3 * abs(e1[0])
+
+
+def test_forces_with_torques_are_minus_energy_gradient():
+    # E(x) = real-space multipole energy at the multipoles rotated from the
+    # current positions, from the separately pinned rotation and energy
+    w, ft, fa, loc = waters()
+    rc = 4.0
+    rp, cp = O.nblist(w.xyz, w.box, rc + 0.5)
+    e, F = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, BETA, rc)
+
+    def E(xyz):
+        g = O.rotate_mpole(xyz, w.box, ft, fa, loc)
+        return O.empole_real(xyz, w.box, w.molid, rp, cp, g, BETA, rc)[0][0]
+    assert e[0] == pytest.approx(E(w.xyz), rel=1e-14)
+    h = 1e-5
+    for i in (0, 1, 2, 31, 45):
+        for a in range(3):
+            xp, xm = w.xyz.copy(), w.xyz.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            g = (E(xp) - E(xm)) / (2 * h)
+            assert F[i, a] == pytest.approx(-g, rel=1e-6, abs=1e-7 * np.abs(F).max())
+    assert np.allclose(F.sum(axis=0), 0.0, atol=1e-10 * np.abs(F).max())
+
+
+def test_no_frames_is_plain_multipoles_and_bad_frames():
+    w, ft, fa, loc = waters(n_w=8, box=7.0)
+    rp, cp = O.nblist(w.xyz, w.box, 3.4)
+    zero = np.zeros(w.n, np.int32)
+    e, F = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, zero, fa, loc, BETA, 3.4)
+    e0, F0, _ = O.empole_real(w.xyz, w.box, w.molid, rp, cp, loc, BETA, 3.4)
+    assert np.array_equal(e, e0) and np.array_equal(F, F0)
+    bad = fa.copy()
+    bad[0, 0] = 0   # the site itself
+    with pytest.raises(O.OracleError):
+        O.rotate_mpole(w.xyz, w.box, ft, bad, loc)
+    badt = ft.copy()
+    badt[3] = 7
+    with pytest.raises(O.OracleError):
+        O.empole_frames(w.xyz, w.box, w.molid, rp, cp, badt, fa, loc, BETA, 3.4)
