@@ -244,6 +244,43 @@ tk_status tk_polarize_pcg_ewald(tk_ctx* ctx, void* stream, const tk_system* sys,
                                 tk_pcg_info* info);
 
 /*
+ * Local-frame multipoles (the rotation step that section "Hotspots" lists
+ * beside the multipole routines).  frame_type: device [n] int32, 0 none,
+ * 1 Z-then-X, 2 bisector (TK_FRAME_*); frame_atoms: device [n][2] int32, the
+ * z-atom and x-atom of each site (ignored for type 0; distinct, not the site,
+ * in [0, n)).  With d_z = r_zatom - r_i, d_x = r_xatom - r_i (minimum image):
+ * Z-then-X z = unit(d_z), x = unit(d_x - (d_x.z) z); bisector
+ * z = unit(unit(d_z) + unit(d_x)), x = unit(u - (u.z) z), u = unit(d_x);
+ * y = z x x.  With R = [x y z]: q = q_loc, mu = R mu_loc,
+ * Theta = R Theta_loc R^T.  mpole_local, mpole_global: device [n][10] in
+ * the layout of tk_empole_real.  An invalid frame copies the site's local
+ * multipoles unchanged.
+ */
+#define TK_FRAME_NONE 0
+#define TK_FRAME_Z_THEN_X 1
+#define TK_FRAME_BISECTOR 2
+tk_status tk_rotate_mpole(tk_ctx* ctx, void* stream, const tk_system* sys,
+                          const int32_t* frame_type, const int32_t* frame_atoms,
+                          const double* mpole_local, double* mpole_global);
+
+/*
+ * Real-space permanent-multipole energy and forces with local-frame
+ * multipoles (the multipole routine with its torque step): the energy of
+ * tk_empole_real at the rotated multipoles M(x), and its full gradient, the
+ * direct pair forces plus the frame part -sum_c dE/dM_i,c dM_i,c/dx for the
+ * site and its two frame atoms.  FP64.  energy: device [3] as
+ * tk_empole_real (all three NaN if a frame is invalid); force: device [n][3];
+ * mpole_global: device [n][10] receiving the rotated multipoles, or NULL.
+ * The frame forces are added with atomics: reproducible to rounding, not
+ * bitwise.  No virial.
+ */
+tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
+                           const tk_nblist* list, const int32_t* frame_type,
+                           const int32_t* frame_atoms, const double* mpole_local,
+                           double ewald_beta, double cutoff, double* energy, double* force,
+                           double* mpole_global);
+
+/*
  * Real-space polarization forces (epolar1 in the Rel profile, the second
  * AMOEBA hotspot of section "Hotspots").  The polarization energy is the
  * minimum over mu of C [1/2 mu.A mu - mu.E_perm] (A, E_perm as above),

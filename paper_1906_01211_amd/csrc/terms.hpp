@@ -672,6 +672,116 @@ struct VdwPh {
   }
 };
 
+// Derivatives of the permanent-multipole energy with respect to each site's
+// own (lab-frame) multipoles, G_i,c = dE/dM_i,c (10 per site, stored layout:
+// an off-diagonal quadrupole component counts both of its matrix entries).
+// E is bilinear, so G_i is minus the potential/field/field-gradient that the
+// other sites make at i, in the energy's own radial families (g_n = B_n, or
+// B_n - R_n within a molecule).  FP64.  Fields as EmpolePh.
+template <class R>
+struct MderivPh {
+  static constexpr int NF = 14, NA = 10, NS = 0;
+  static constexpr const char* kName = "mderiv";
+  static constexpr int kWaves = 2;
+  static constexpr const char* kTag = "_fp64";
+  __device__ bool skip() const { return false; }
+  __device__ void prologue(int tid, int nt) const { erfcx_stage<double>(tid, nt); }
+  const double* xyz;
+  const double* mpole;
+  const int32_t* molid;
+  Geom g;
+  __device__ void set_sys(const SysDev& d, int) {
+    g.box = d.box;
+    g.inv_box = d.inv_box;
+  }
+  static constexpr int NG = 14;
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void stage_dyn(double*, int, int, int) const {}
+  __device__ void gather(int i, double* gg) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gg[c] = xyz[3 * i + c];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) gg[3 + k] = mpole[10 * i + k];
+    gg[13] = (double)molid[i];
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double*, long) const {
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
+    if (!(r2 <= g.rc2)) return;
+    const bool excl = LH[13 * cap + a] == LK[13 * cap + b];
+    double B[5], Rb[5];
+    radial_pair<double, 4>(g, r2, excl, B, Rb);
+    double gn[5];
+#pragma unroll
+    for (int n = 0; n < 5; ++n) gn[n] = excl ? B[n] - Rb[n] : B[n];
+    const double* d = dd;
+    const double qi = LH[3 * cap + a], qj = LK[3 * cap + b];
+    const double ui[3] = {LH[4 * cap + a], LH[5 * cap + a], LH[6 * cap + a]};
+    const double uj[3] = {LK[4 * cap + b], LK[5 * cap + b], LK[6 * cap + b]};
+    double ti[3][3], tj[3][3];
+    {
+      const double* h = LH + 7 * cap + a;
+      const double* k = LK + 7 * cap + b;
+      ti[0][0] = h[0]; ti[0][1] = ti[1][0] = h[cap]; ti[0][2] = ti[2][0] = h[2 * cap];
+      ti[1][1] = h[3 * cap]; ti[1][2] = ti[2][1] = h[4 * cap]; ti[2][2] = h[5 * cap];
+      tj[0][0] = k[0]; tj[0][1] = tj[1][0] = k[cap]; tj[0][2] = tj[2][0] = k[2 * cap];
+      tj[1][1] = k[3 * cap]; tj[1][2] = tj[2][1] = k[4 * cap]; tj[2][2] = k[5 * cap];
+    }
+    double vi[3], vj[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      vi[c] = ti[c][0] * d[0] + ti[c][1] * d[1] + ti[c][2] * d[2];
+      vj[c] = tj[c][0] * d[0] + tj[c][1] * d[1] + tj[c][2] * d[2];
+    }
+    const double di = ui[0] * d[0] + ui[1] * d[1] + ui[2] * d[2];
+    const double dj = uj[0] * d[0] + uj[1] * d[1] + uj[2] * d[2];
+    const double Qi = d[0] * vi[0] + d[1] * vi[1] + d[2] * vi[2];
+    const double Qj = d[0] * vj[0] + d[1] * vj[1] + d[2] * vj[2];
+    double Gi[10], Gj[10];
+    // d/dq, d/dmu (from c0..c3)
+    Gi[0] = qj * gn[0] - dj * gn[1] + Qj * gn[2];
+    Gj[0] = qi * gn[0] + di * gn[1] + Qi * gn[2];
+    const double si = qj * gn[1] - dj * gn[2] + Qj * gn[3];
+    const double sj = -qi * gn[1] - di * gn[2] - Qi * gn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Gi[1 + c] = si * d[c] + gn[1] * uj[c] - 2.0 * gn[2] * vj[c];
+      Gj[1 + c] = sj * d[c] + gn[1] * ui[c] + 2.0 * gn[2] * vi[c];
+    }
+    // d/dTheta_ab (c2, c3, c4), stored components: off-diagonal = ab + ba
+    const double wi = qj * gn[2] - dj * gn[3] + Qj * gn[4];
+    const double wj = qi * gn[2] + di * gn[3] + Qi * gn[4];
+    const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int p = ia[k], q = ib[k];
+      const auto ent_i = [&](int x, int y) {
+        return wi * d[x] * d[y] + 2.0 * gn[2] * (uj[x] * d[y] + tj[x][y]) - 4.0 * gn[3] * vj[x] * d[y];
+      };
+      const auto ent_j = [&](int x, int y) {
+        return wj * d[x] * d[y] + 2.0 * gn[2] * (-ui[x] * d[y] + ti[x][y]) - 4.0 * gn[3] * vi[x] * d[y];
+      };
+      Gi[4 + k] = p == q ? ent_i(p, p) : ent_i(p, q) + ent_i(q, p);
+      Gj[4 + k] = p == q ? ent_j(p, p) : ent_j(p, q) + ent_j(q, p);
+    }
+#pragma unroll
+    for (int c = 0; c < 10; ++c) {
+      lds_add(&AH[c * cap + a], kCoulomb * Gi[c]);
+      lds_add(&AK[c * cap + b], kCoulomb * Gj[c]);
+    }
+  }
+};
+
+struct EpiStore10 {   // the sums are the site's dE/dM (10), caller order
+  double* out;
+  __device__ void operator()(int, int i, const double* a) const {
+#pragma unroll
+    for (int c = 0; c < 10; ++c) out[10 * i + c] = a[c];
+  }
+};
+
 // Polarization forces at fixed induced dipoles p: the pair energies
 //   e_ip = U(p_i, M_j; gp) + U(M_i, p_j; gp),   e_ii = U(p_i, p_j; gm)
 // (U the multipole pair energy, an induced dipole the multipole (0, p, 0)),

@@ -106,6 +106,9 @@ _SIGS = {
     "tk_pme_mpole": [_vp, _vp, C.POINTER(System), _vp, _d, _i32, _i32, _vp, _vp, _vp],
     "tk_polarize_pcg_ewald": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d,
                               _d, _i32, _i32, _d, _i32, _vp, _vp, C.POINTER(PcgInfo)],
+    "tk_rotate_mpole": [_vp, _vp, C.POINTER(System), _vp, _vp, _vp, _vp],
+    "tk_empole_frames": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
+                         _vp, _vp, _vp],
     "tk_evdw": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), C.c_int, _vp, _vp, _d, _d, _d, _d,
                 C.c_int, _vp, _vp, _vp],
     "tk_batch_step": [_vp, _vp, C.POINTER(Batch), C.POINTER(StepParams), _vp, _vp, _vp, _vp, _vp,
@@ -358,6 +361,27 @@ class Context:
                                    int(grid), int(order), _ptr(e), _ptr(f),
                                    None if fld is None else _ptr(fld)), "tk_pme_mpole")
         return e, f, fld
+
+    def rotate_mpole(self, sysref, frame_type, frame_atoms, mpole_local):
+        ft = _dev(frame_type, torch.int32, self.device)
+        fa = _dev(frame_atoms, torch.int32, self.device)
+        ml = _dev(mpole_local, torch.float64, self.device)
+        out = torch.empty((sysref.n, 10), dtype=torch.float64, device=self.device)
+        _check(load().tk_rotate_mpole(self._h, _stream(self.device), C.byref(sysref.c), _ptr(ft),
+                                      _ptr(fa), _ptr(ml), _ptr(out)), "tk_rotate_mpole")
+        return out
+
+    def empole_frames(self, sysref, lst, frame_type, frame_atoms, mpole_local, beta, cutoff):
+        ft = _dev(frame_type, torch.int32, self.device)
+        fa = _dev(frame_atoms, torch.int32, self.device)
+        ml = _dev(mpole_local, torch.float64, self.device)
+        e = torch.empty(3, dtype=torch.float64, device=self.device)
+        f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        mg = torch.empty((sysref.n, 10), dtype=torch.float64, device=self.device)
+        _check(load().tk_empole_frames(self._h, _stream(self.device), C.byref(sysref.c),
+                                       C.byref(lst.c), _ptr(ft), _ptr(fa), _ptr(ml), beta, cutoff,
+                                       _ptr(e), _ptr(f), _ptr(mg)), "tk_empole_frames")
+        return e, f, mg
 
     def evdw(self, sysref, lst, form, rad, eps, cutoff, taper_frac=0.9, dhal=0.07, ghal=0.12,
              prec=FP64):
