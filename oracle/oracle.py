@@ -87,6 +87,8 @@ def lib():
         L.or_rotate_mpole.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _dp, _dp]
         L.or_empole_frames.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _ip, _ip, _dp,
                                        C.c_double, C.c_double, _dp, _dp]
+        L.or_vdw_sites.argtypes = [C.c_int, _dp, C.c_double, _ip, _dp, _dp]
+        L.or_vdw_forces_to_atoms.argtypes = [C.c_int, _ip, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -371,3 +373,24 @@ def empole_frames(xyz, box, molid, row_ptr, col, ftype, fatoms, local, beta, cut
     if st:
         raise OracleError(st)
     return energy, force
+
+
+def vdw_sites(xyz, box, parent, red):
+    """vdW site positions with hydrogen reduction (or_vdw_sites)."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    out = np.zeros((n, 3))
+    st = lib().or_vdw_sites(n, xyz, box, _i(parent), _d(red), out)
+    if st:
+        raise OracleError(st)
+    return out
+
+
+def vdw_forces_to_atoms(parent, red, fsite):
+    fsite = _d(fsite)
+    n = fsite.shape[0]
+    out = np.zeros((n, 3))
+    st = lib().or_vdw_forces_to_atoms(n, _i(parent), _d(red), fsite, out)
+    if st:
+        raise OracleError(st)
+    return out

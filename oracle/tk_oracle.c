@@ -1374,3 +1374,47 @@ int or_empole_frames(int n, const double* xyz, double box, const int32_t* molid,
   free(G);
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* vdW hydrogen reduction (the "vdW hydrogen reduction" of AMOEBA's Halgren
+ * term).  Reading: a site with parent p >= 0 sits at r_p + red_i (r_i - r_p)
+ * (minimum image of r_i - r_p); other sites at their atoms.  Site forces go
+ * back by the chain rule: atom i receives red_i f_i, its parent
+ * (1 - red_i) f_i. */
+int or_vdw_sites(int n, const double* xyz, double box, const int32_t* parent, const double* red,
+                 double* sites) {
+  if (n < 0 || !(box > 0.0)) return OR_E_ARG;
+  for (int i = 0; i < n; ++i) {
+    int p = parent[i];
+    if (p >= n || p == i) return OR_E_ARG;
+    for (int a = 0; a < 3; ++a) {
+      if (p < 0) {
+        sites[3 * i + a] = xyz[3 * i + a];
+      } else {
+        double d = xyz[3 * i + a] - xyz[3 * p + a];
+        d -= box * rint(d / box);
+        sites[3 * i + a] = xyz[3 * p + a] + red[i] * d;
+      }
+    }
+  }
+  return OR_OK;
+}
+
+int or_vdw_forces_to_atoms(int n, const int32_t* parent, const double* red, const double* fsite,
+                           double* fatom) {
+  for (int i = 0; i < n; ++i)
+    if (parent[i] >= n || parent[i] == i) return OR_E_ARG;
+  for (int k = 0; k < 3 * n; ++k) fatom[k] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    int p = parent[i];
+    for (int a = 0; a < 3; ++a) {
+      if (p < 0) {
+        fatom[3 * i + a] += fsite[3 * i + a];
+      } else {
+        fatom[3 * i + a] += red[i] * fsite[3 * i + a];
+        fatom[3 * p + a] += (1.0 - red[i]) * fsite[3 * i + a];
+      }
+    }
+  }
+  return OR_OK;
+}

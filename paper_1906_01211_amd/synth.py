@@ -162,6 +162,20 @@ def water_frames(n_w: int):
     return ftype, fat
 
 
+def water_vdw_reduction(n_w: int, red_h: float = 0.91):
+    """vdW reduction topology of n_w waters: each H's parent is its O, with
+    reduction factor red_h (AMOEBA water's value, 0.91); O has none.  Returns
+    (parent[n] int32, -1 for none; red[n] float64)."""
+    n = 3 * n_w
+    parent = np.full(n, -1, np.int32)
+    red = np.ones(n)
+    base = 3 * np.arange(n_w)
+    for h in (1, 2):
+        parent[base + h] = base
+        red[base + h] = red_h
+    return parent, red
+
+
 def water_local_multipoles(n_w: int, seed: int) -> np.ndarray:
     """Multipoles in the local frames of water_frames: O -0.52 / H +0.26,
     dipoles along the local z axis (O 0.15, H -0.06 e A) with a small

@@ -122,3 +122,44 @@ def test_no_frames_is_plain_multipoles_and_bad_frames():
     badt[3] = 7
     with pytest.raises(O.OracleError):
         O.empole_frames(w.xyz, w.box, w.molid, rp, cp, badt, fa, loc, BETA, 3.4)
+
+
+# ---------------------------------------------------------------- vdW hydrogen reduction
+def test_vdw_reduction_sites_and_forces():
+    w = synth.amoeba_water_box(27, 9.4, 2)
+    parent, red = synth.water_vdw_reduction(27)
+    sites = O.vdw_sites(w.xyz, w.box, parent, red)
+    # O at its atom; each H site on its O-H bond at 0.91 of the bond length
+    assert np.array_equal(sites[0::3], w.xyz[0::3])
+    for h in (1, 2):
+        d = w.xyz[h::3] - w.xyz[0::3]
+        d -= w.box * np.rint(d / w.box)
+        s = sites[h::3] - w.xyz[0::3]
+        assert np.allclose(np.linalg.norm(s, axis=1), 0.91 * np.linalg.norm(d, axis=1), rtol=1e-14)
+        assert np.allclose(np.cross(s, d), 0.0, atol=1e-14)
+    # forces on atoms are minus the gradient of E(sites(x))
+    rc = 4.0
+    rp, cp = O.nblist(sites, w.box, rc + 0.5)
+
+    def E(xyz):
+        return O.evdw(O.vdw_sites(xyz, w.box, parent, red), w.box, w.molid, rp, cp, 0, w.vdw_rad,
+                      w.vdw_eps, rc)[0]
+    _, fs, _ = O.evdw(sites, w.box, w.molid, rp, cp, 0, w.vdw_rad, w.vdw_eps, rc)
+    F = O.vdw_forces_to_atoms(parent, red, fs)
+    assert np.allclose(F.sum(axis=0), fs.sum(axis=0), atol=1e-12 * np.abs(fs).max())
+    h = 1e-5
+    for i in (0, 1, 2, 40):
+        for a in range(3):
+            xp, xm = w.xyz.copy(), w.xyz.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            g = (E(xp) - E(xm)) / (2 * h)
+            assert F[i, a] == pytest.approx(-g, rel=1e-6, abs=1e-8 * np.abs(F).max())
+    # red = 1 everywhere: sites are the atoms, forces unchanged
+    ones = np.ones(w.n)
+    assert np.array_equal(O.vdw_sites(w.xyz, w.box, parent, ones), w.xyz)
+    assert np.array_equal(O.vdw_forces_to_atoms(parent, ones, fs), fs)
+    bad = parent.copy()
+    bad[4] = 4
+    with pytest.raises(O.OracleError):
+        O.vdw_sites(w.xyz, w.box, bad, red)
