@@ -281,6 +281,23 @@ tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
                            double* mpole_global);
 
 /*
+ * vdW hydrogen reduction (AMOEBA's Halgren term puts a hydrogen's vdW site on
+ * its bond).  tk_vdw_sites: site i at r_p + red_i (r_i - r_p), minimum image,
+ * for parent[i] = p >= 0, else at r_i; an invalid parent (>= n or i) gives a
+ * NaN site.  parent: device [n] int32 (-1: none); red: device [n];
+ * sites: device [n][3].  The caller lists and evaluates the sites with
+ * tk_nblist_build and tk_evdw on a tk_system holding them, then
+ * tk_vdw_site_forces maps the site forces to atoms by the chain rule: atom i
+ * receives red_i f_i, its parent (1 - red_i) f_i (added with atomics:
+ * reproducible to rounding).  site_force, atom_force: device [n][3],
+ * distinct.  The site virial of tk_evdw is not mapped.
+ */
+tk_status tk_vdw_sites(tk_ctx* ctx, void* stream, const tk_system* sys, const int32_t* parent,
+                       const double* red, double* sites);
+tk_status tk_vdw_site_forces(tk_ctx* ctx, void* stream, int32_t n, const int32_t* parent,
+                             const double* red, const double* site_force, double* atom_force);
+
+/*
  * Real-space polarization forces (epolar1 in the Rel profile, the second
  * AMOEBA hotspot of section "Hotspots").  The polarization energy is the
  * minimum over mu of C [1/2 mu.A mu - mu.E_perm] (A, E_perm as above),

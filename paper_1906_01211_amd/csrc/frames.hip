@@ -208,6 +208,60 @@ __global__ __launch_bounds__(256) void k_frames_torque(int n, const double* __re
   }
 }
 
+// vdW hydrogen reduction: site i at r_p + red_i (r_i - r_p) (minimum image)
+// for a parent p, else at r_i; an invalid parent gives a NaN site.
+__global__ __launch_bounds__(256) void k_vdw_sites(int n, const double* __restrict__ xyz, double box,
+                                                   const int32_t* __restrict__ parent,
+                                                   const double* __restrict__ red,
+                                                   double* __restrict__ sites) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = parent[i];
+  if (p < 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sites[3 * i + a] = xyz[3 * i + a];
+    return;
+  }
+  if (p >= n || p == i) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sites[3 * i + a] = __builtin_nan("");
+    return;
+  }
+  const double inv = 1.0 / box, r = red[i];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double d = xyz[3 * i + a] - xyz[3 * p + a];
+    sites[3 * i + a] = xyz[3 * p + a] + r * (d - box * rint(d * inv));
+  }
+}
+
+// Site forces to atoms: atom i takes red_i f_i (all of f_i without a
+// parent), then each parent adds (1 - red_i) f_i with an atomic add.
+__global__ __launch_bounds__(256) void k_vdw_own(int n, const int32_t* __restrict__ parent,
+                                                 const double* __restrict__ red,
+                                                 const double* __restrict__ fsite,
+                                                 double* __restrict__ fatom) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = parent[i];
+  const double r = (p >= 0 && p < n && p != i) ? red[i] : 1.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) fatom[3 * i + a] = r * fsite[3 * i + a];
+}
+
+__global__ __launch_bounds__(256) void k_vdw_parent(int n, const int32_t* __restrict__ parent,
+                                                    const double* __restrict__ red,
+                                                    const double* __restrict__ fsite,
+                                                    double* __restrict__ fatom) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = parent[i];
+  if (p < 0 || p >= n || p == i) return;
+  const double w = 1.0 - red[i];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) atomicAdd(&fatom[3 * p + a], w * fsite[3 * i + a]);
+}
+
 }  // namespace
 
 }  // namespace tk
@@ -287,6 +341,31 @@ tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
                                                       frame_atoms, mpole_local, (const double*)G,
                                                       force, (const int*)flag, energy);
   }
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+tk_status tk_vdw_sites(tk_ctx* ctx, void* stream, const tk_system* sys, const int32_t* parent,
+                       const double* red, double* sites) {
+  if (!ctx) return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (sys->n == 0) return TK_OK;
+  if (!parent || !red || !sites) return TK_E_ARG;
+  k_vdw_sites<<<ceil_div(sys->n, 256), 256, 0, (hipStream_t)stream>>>(sys->n, sys->xyz, sys->box,
+                                                                     parent, red, sites);
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+tk_status tk_vdw_site_forces(tk_ctx* ctx, void* stream, int32_t n, const int32_t* parent,
+                             const double* red, const double* site_force, double* atom_force) {
+  if (!ctx || n < 0) return TK_E_ARG;
+  if (n == 0) return TK_OK;
+  if (!parent || !red || !site_force || !atom_force || site_force == atom_force) return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  k_vdw_own<<<ceil_div(n, 256), 256, 0, st>>>(n, parent, red, site_force, atom_force);
+  k_vdw_parent<<<ceil_div(n, 256), 256, 0, st>>>(n, parent, red, site_force, atom_force);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }

@@ -109,6 +109,8 @@ _SIGS = {
     "tk_rotate_mpole": [_vp, _vp, C.POINTER(System), _vp, _vp, _vp, _vp],
     "tk_empole_frames": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
                          _vp, _vp, _vp],
+    "tk_vdw_sites": [_vp, _vp, C.POINTER(System), _vp, _vp, _vp],
+    "tk_vdw_site_forces": [_vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "tk_evdw": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), C.c_int, _vp, _vp, _d, _d, _d, _d,
                 C.c_int, _vp, _vp, _vp],
     "tk_batch_step": [_vp, _vp, C.POINTER(Batch), C.POINTER(StepParams), _vp, _vp, _vp, _vp, _vp,
@@ -382,6 +384,23 @@ class Context:
                                        C.byref(lst.c), _ptr(ft), _ptr(fa), _ptr(ml), beta, cutoff,
                                        _ptr(e), _ptr(f), _ptr(mg)), "tk_empole_frames")
         return e, f, mg
+
+    def vdw_sites(self, sysref, parent, red):
+        par = _dev(parent, torch.int32, self.device)
+        rd = _dev(red, torch.float64, self.device)
+        out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        _check(load().tk_vdw_sites(self._h, _stream(self.device), C.byref(sysref.c), _ptr(par),
+                                   _ptr(rd), _ptr(out)), "tk_vdw_sites")
+        return out
+
+    def vdw_site_forces(self, parent, red, site_force):
+        par = _dev(parent, torch.int32, self.device)
+        rd = _dev(red, torch.float64, self.device)
+        fs = _dev(site_force, torch.float64, self.device)
+        out = torch.empty_like(fs)
+        _check(load().tk_vdw_site_forces(self._h, _stream(self.device), int(fs.shape[0]), _ptr(par),
+                                         _ptr(rd), _ptr(fs), _ptr(out)), "tk_vdw_site_forces")
+        return out
 
     def evdw(self, sysref, lst, form, rad, eps, cutoff, taper_frac=0.9, dhal=0.07, ghal=0.12,
              prec=FP64):

@@ -100,3 +100,31 @@ def test_frames_invalid_and_empty(ctx, tk):
     e, f, _ = ctx.empole_frames(empty, l0, np.zeros(0, np.int32), np.zeros((0, 2), np.int32),
                                 np.zeros((0, 10)), S["beta"], 7.0)
     assert np.all(np_(e) == 0.0) and f.shape == (0, 3)
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+def test_vdw_reduction_chain(ctx, name):
+    # sites -> list on the sites -> HAL on the sites -> forces on the atoms
+    w = _cache.setdefault(name, synth.make(name))
+    parent, red = synth.water_vdw_reduction(w.n // 3)
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    sites = ctx.vdw_sites(sysr, parent, red)
+    so = O.vdw_sites(w.xyz, w.box, parent, red)
+    assert np.abs(np_(sites) - so).max() <= 1e-13 * w.box
+    ssys = ctx.system(sites, w.box, w.molid)
+    lst = ctx.nblist(ssys, 9.001, plan_slot=3)
+    e, fs, _ = ctx.evdw(ssys, lst, 0, w.vdw_rad, w.vdw_eps, 9.0)
+    f = ctx.vdw_site_forces(parent, red, fs)
+    rp, cp = O.nblist(so, w.box, 9.001)
+    eo, fso, _ = O.evdw(so, w.box, w.molid, rp, cp, 0, w.vdw_rad, w.vdw_eps, 9.0)
+    fo = O.vdw_forces_to_atoms(parent, red, fso)
+    assert abs(float(e) - eo) <= 1e-10 * abs(eo)
+    assert fmax_rel(np_(f), fo) < 1e-8
+
+
+def test_vdw_reduction_invalid_parent(ctx):
+    w = _cache.setdefault("water216", synth.make("water216"))
+    parent, red = synth.water_vdw_reduction(w.n // 3)
+    parent[4] = 4
+    sites = np_(ctx.vdw_sites(ctx.system(w.xyz, w.box, w.molid), parent, red))
+    assert np.all(np.isnan(sites[4])) and np.all(np.isfinite(np.delete(sites, 4, axis=0)))
