@@ -256,8 +256,8 @@ def main():
 
 
 def extras(ctx, tk, w, a, prec, n7):
-    """Mixed-vs-FP64 step, the charge + LJ path, the polarization forces and
-    the reciprocal-space PME (not part of `value`)."""
+    """Mixed-vs-FP64 step, the charge + LJ path, the polarization forces, the
+    reciprocal-space PME and the local frames (not part of `value`)."""
     import torch
     res = {}
     other = tk.MIXED if prec == tk.FP64 else tk.FP64
@@ -284,7 +284,30 @@ def extras(ctx, tk, w, a, prec, n7):
         res[f"charge_lj_pairs_per_s_{name}"] = 2 * l12.npairs / (ms * 1e-3)
     res["epolar"] = epolar_leg(ctx, tk, w, n7)
     res["pme"] = pme_leg(ctx, tk, w)
+    res["frames"] = frames_leg(ctx, tk, w)
     return res
+
+
+def frames_leg(ctx, tk, w):
+    """Local-frame multipoles on the water box: rotation, and the multipole
+    energy and forces with the frame part, beside the lab-frame call."""
+    import torch
+    s = synth.AMOEBA_SETTINGS
+    n_w = w.n // 3
+    ft, fa = synth.water_frames(n_w)
+    dev = ctx.device
+    ft = torch.as_tensor(ft, device=dev)
+    fa = torch.as_tensor(fa, device=dev)
+    loc = torch.as_tensor(synth.water_local_multipoles(n_w, 7), device=dev)
+    sysw = ctx.system(w.xyz, w.box, w.molid)
+    l7 = ctx.nblist(sysw, s["rc_ewald"] + s["skin"], plan_slot=3)
+    mg = ctx.rotate_mpole(sysw, ft, fa, loc)
+    out = {"rotate_ms": round(timed(lambda: ctx.rotate_mpole(sysw, ft, fa, loc), 20, 3) * 1e3, 4)}
+    out["empole_frames_ms"] = round(timed(lambda: ctx.empole_frames(sysw, l7, ft, fa, loc, s["beta"],
+                                                                    s["rc_ewald"]), 20, 3) * 1e3, 4)
+    out["empole_lab_ms"] = round(timed(lambda: ctx.empole_real(sysw, l7, mg, s["beta"],
+                                                               s["rc_ewald"]), 20, 3) * 1e3, 4)
+    return out
 
 
 def pme_leg(ctx, tk, w, grid=64, order=5):
