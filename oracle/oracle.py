@@ -89,6 +89,9 @@ def lib():
                                        C.c_double, C.c_double, _dp, _dp]
         L.or_vdw_sites.argtypes = [C.c_int, _dp, C.c_double, _ip, _dp, _dp]
         L.or_vdw_forces_to_atoms.argtypes = [C.c_int, _ip, _dp, _dp, _dp]
+        L.or_polarize_tcg1.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
+                                       C.c_double, C.c_double, _dp, C.POINTER(C.c_double),
+                                       C.c_void_p]
         _lib = L
     return _lib
 
@@ -394,3 +397,19 @@ def vdw_forces_to_atoms(parent, red, fsite):
     if st:
         raise OracleError(st)
     return out
+
+
+def polarize_tcg1(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta, cutoff,
+                  forces=True):
+    """One-step truncated CG (or_polarize_tcg1): (mu1[n,3], U, force[n,3] or None)."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    mu = np.zeros((n, 3))
+    e = C.c_double()
+    f = np.zeros((n, 3)) if forces else None
+    st = lib().or_polarize_tcg1(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _d(mpole),
+                                _d(polarity), _d(thole_a), beta, cutoff, mu, C.byref(e),
+                                None if f is None else f.ctypes.data_as(C.c_void_p))
+    if st:
+        raise OracleError(st)
+    return mu, e.value, f

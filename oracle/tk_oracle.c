@@ -1418,3 +1418,113 @@ int or_vdw_forces_to_atoms(int n, const int32_t* parent, const double* red, cons
   }
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Truncated conjugate gradient, one step (TCG1; the fixed-cost polarization
+ * solvers that the paper's later versions use).  Reading: diagonal
+ * preconditioner alpha, direct guess, no "peek" step:
+ *   mu0 = alpha E,  r0 = E - A mu0,  p0 = alpha r0,
+ *   gamma = r0.p0,  delta = p0.A p0,  a = gamma/delta,  mu1 = mu0 + a p0,
+ *   U = -1/2 C mu1.E,
+ * with E the permanent field and A the operator of or_tmatvec (rows of
+ * alpha = 0 zero).  U is not variational in mu, so its force is the total
+ * derivative through every step.  Writing s = p0.E,
+ *   w = 2 p0/delta - 2 gamma alpha A p0/delta^2,  v = s w + a mu0,
+ *   u = mu0 + mu1 + v - alpha A v,
+ * the gradient is  dU = -1/2 C [u.dE + v.dT mu0 + s gamma/delta^2 p0.dT p0]
+ * (dA = -dT), i.e. the force is
+ *   F = 1/2 F_ip(u) + 1/2 F_bil(v, mu0) + 1/2 s gamma/delta^2 F_bil(p0, p0),
+ * where, from the pair forces F(mu) of or_epolar_real at dipoles mu,
+ *   F_ip(u) = [F(u) - F(-u)]/2           (the part linear in the dipoles)
+ *   F_ii(w) = [F(w) + F(-w)]/2           (the part quadratic in them)
+ *   F_bil(b, c) = F_ii(b + c) - F_ii(b) - F_ii(c). */
+static double or_dot3n(int n, const double* a, const double* b) {
+  double s = 0.0;
+  for (int k = 0; k < 3 * n; ++k) s += a[k] * b[k];
+  return s;
+}
+
+static void or_epolar_parts(int n, const double* xyz, double box, const int32_t* molid,
+                            const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                            const double* polarity, const double* thole, double beta, double rc,
+                            const double* mu, double* Fplus, double* Fminus) {
+  size_t m = 3 * (size_t)(n > 0 ? n : 1);
+  double* neg = (double*)malloc(sizeof(double) * m);
+  double e[3], w[9];
+  for (int k = 0; k < 3 * n; ++k) neg[k] = -mu[k];
+  or_epolar_real(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, mu, beta, rc, e, Fplus,
+                 w);
+  or_epolar_real(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, neg, beta, rc, e,
+                 Fminus, w);
+  free(neg);
+}
+
+int or_polarize_tcg1(int n, const double* xyz, double box, const int32_t* molid,
+                     const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                     const double* polarity, const double* thole, double beta, double rc,
+                     double* mu_out, double* epol, double* force) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  for (int i = 0; i < n; ++i)
+    if (!(polarity[i] >= 0.0)) return OR_E_ARG;
+  size_t m = 3 * (size_t)(n > 0 ? n : 1);
+  double *E = (double*)malloc(sizeof(double) * m), *mu0 = (double*)malloc(sizeof(double) * m),
+         *r0 = (double*)malloc(sizeof(double) * m), *p0 = (double*)malloc(sizeof(double) * m),
+         *P = (double*)malloc(sizeof(double) * m), *q = (double*)malloc(sizeof(double) * m);
+  or_efield_direct(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, E);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) mu0[3 * i + a] = polarity[i] * E[3 * i + a];
+  or_tmatvec(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, 1, mu0, q);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      int k = 3 * i + a;
+      r0[k] = polarity[i] > 0.0 ? E[k] - q[k] : 0.0;
+      p0[k] = polarity[i] * r0[k];
+    }
+  or_tmatvec(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, 1, p0, P);
+  double gamma = or_dot3n(n, r0, p0), delta = or_dot3n(n, p0, P);
+  double a = delta != 0.0 ? gamma / delta : 0.0;
+  for (int k = 0; k < 3 * n; ++k) mu_out[k] = mu0[k] + a * p0[k];
+  *epol = -0.5 * OR_COULOMB * or_dot3n(n, mu_out, E);
+  if (force) {
+    double s = or_dot3n(n, p0, E);
+    double *v = (double*)malloc(sizeof(double) * m), *u = (double*)malloc(sizeof(double) * m),
+           *Av = (double*)malloc(sizeof(double) * m), *t = (double*)malloc(sizeof(double) * m),
+           *Fp = (double*)malloc(sizeof(double) * m), *Fm = (double*)malloc(sizeof(double) * m);
+    for (int i = 0; i < n; ++i)
+      for (int c = 0; c < 3; ++c) {
+        int k = 3 * i + c;
+        double w = delta != 0.0 ? 2.0 * p0[k] / delta - 2.0 * gamma * polarity[i] * P[k] /
+                                                            (delta * delta)
+                                : 0.0;
+        v[k] = s * w + a * mu0[k];
+      }
+    or_tmatvec(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, 1, v, Av);
+    for (int i = 0; i < n; ++i)
+      for (int c = 0; c < 3; ++c) {
+        int k = 3 * i + c;
+        u[k] = mu0[k] + mu_out[k] + v[k] - polarity[i] * Av[k];
+      }
+    double cb = delta != 0.0 ? s * gamma / (delta * delta) : 0.0;
+    for (int k = 0; k < 3 * n; ++k) force[k] = 0.0;
+    /* 1/2 F_ip(u) = 1/4 [F(u) - F(-u)] */
+    or_epolar_parts(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, u, Fp, Fm);
+    for (int k = 0; k < 3 * n; ++k) force[k] += 0.25 * (Fp[k] - Fm[k]);
+    /* 1/2 F_bil(v, mu0) = 1/2 [F_ii(v + mu0) - F_ii(v) - F_ii(mu0)] */
+    for (int k = 0; k < 3 * n; ++k) t[k] = v[k] + mu0[k];
+    or_epolar_parts(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, t, Fp, Fm);
+    for (int k = 0; k < 3 * n; ++k) force[k] += 0.25 * (Fp[k] + Fm[k]);
+    or_epolar_parts(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, v, Fp, Fm);
+    for (int k = 0; k < 3 * n; ++k) force[k] -= 0.25 * (Fp[k] + Fm[k]);
+    or_epolar_parts(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, mu0, Fp,
+                    Fm);
+    for (int k = 0; k < 3 * n; ++k) force[k] -= 0.25 * (Fp[k] + Fm[k]);
+    /* 1/2 cb F_bil(p0, p0) = cb F_ii(p0) = cb/2 [F(p0) + F(-p0)] */
+    or_epolar_parts(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, p0, Fp,
+                    Fm);
+    for (int k = 0; k < 3 * n; ++k) force[k] += 0.5 * cb * (Fp[k] + Fm[k]);
+    free(v); free(u); free(Av); free(t); free(Fp); free(Fm);
+  }
+  free(E); free(mu0); free(r0); free(p0); free(P); free(q);
+  return OR_OK;
+}
