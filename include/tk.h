@@ -298,6 +298,23 @@ tk_status tk_vdw_site_forces(tk_ctx* ctx, void* stream, int32_t n, const int32_t
                              const double* red, const double* site_force, double* atom_force);
 
 /*
+ * One-step truncated conjugate gradient (TCG1), a fixed-cost polarization
+ * solve with the exact derivative of its energy (the fixed-cost solvers of
+ * the paper's later versions).  With A, E_perm as in tk_polarize_pcg,
+ * diagonal preconditioner alpha, direct guess and no "peek" step:
+ *   mu0 = alpha E,  r0 = E - A mu0,  p0 = alpha r0,  a = (r0.p0)/(p0.A p0),
+ *   mu1 = mu0 + a p0,  U = -1/2 C mu1.E.
+ * mu_out: device [n][3] (mu1); epol: device [1] (U); force: device [n][3]
+ * or NULL, the total derivative -dU/dx through every step (U is not
+ * variational, so this is not tk_epolar_real at mu1).  FP64; no host
+ * synchronisation.
+ */
+tk_status tk_polarize_tcg1(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                           const double* mpole, const double* polarity, const double* thole,
+                           double ewald_beta, double cutoff, double* mu_out, double* epol,
+                           double* force);
+
+/*
  * Real-space polarization forces (epolar1 in the Rel profile, the second
  * AMOEBA hotspot of section "Hotspots").  The polarization energy is the
  * minimum over mu of C [1/2 mu.A mu - mu.E_perm] (A, E_perm as above),

@@ -672,6 +672,138 @@ struct VdwPh {
   }
 };
 
+// Forces of a combination of polarization pair energies (the gradient of a
+// truncated solve): the induced-permanent term for dipoles a, plus the
+// bilinear induced-induced terms for the pairs (b1, c1) and (b2, c2):
+//   e = [U(a_i, M_j; gp) + U(M_i, a_j; gp)]
+//     + sum_m [U(b_i, c_j; gm) + U(c_i, b_j; gm)],
+// radial families as EpolarPh.  Forces -de/dx only.  FP64.
+// Fields: x y z | q mu(3) Theta(6) | molid | isa | thole | a b1 c1 b2 c2 (3 each)
+template <class R>
+struct PolGradPh {
+  static constexpr int NF = 31, NA = 3, NS = 0;
+  static constexpr const char* kName = "polgrad";
+  static constexpr int kWaves = 2;
+  static constexpr const char* kTag = "_fp64";
+  __device__ bool skip() const { return false; }
+  __device__ void prologue(int tid, int nt) const { erfcx_stage<double>(tid, nt); }
+  const double* xyz;
+  const double* mpole;
+  const int32_t* molid;
+  const double* polarity;
+  const double* thole;
+  const double* vec[5];   // a, b1, c1, b2, c2: [n][3] each
+  Geom g;
+  __device__ void set_sys(const SysDev& d, int) {
+    g.box = d.box;
+    g.inv_box = d.inv_box;
+  }
+  static constexpr int NG = 31;
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void stage_dyn(double*, int, int, int) const {}
+  __device__ void gather(int i, double* gg) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gg[c] = xyz[3 * i + c];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) gg[3 + k] = mpole[10 * i + k];
+    gg[13] = (double)molid[i];
+    gg[14] = inv_sqrt_alpha(polarity[i]);
+    gg[15] = thole[i];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gg[16 + 3 * v + c] = vec[v][3 * i + c];
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double*, long) const {
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
+    if (!(r2 <= g.rc2)) return;
+    const bool excl = LH[13 * cap + a] == LK[13 * cap + b];
+    const double rinv = rsqrt_r(r2), r = r2 * rinv;
+    double B[5], Rb[5];
+    radial<double, 4>(g, r, rinv, B, Rb, r2);
+    double l[4];
+    thole_damp9<double>(r, LH[14 * cap + a], LK[14 * cap + b], LH[15 * cap + a],
+                        LK[15 * cap + b], l);
+    double gp[5], gm[4];
+#pragma unroll
+    for (int n = 1; n <= 4; ++n) {
+      const double bare = Rb[n] - l[n - 1] * Rb[n];
+      gp[n] = excl ? B[n] - Rb[n] : B[n] - bare;
+      if (n <= 3) gm[n] = B[n] - bare;
+    }
+    const double* d = dd;
+    const auto dot = [](const double* x, const double* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+    const auto fld = [&](const double* L, int f, int s, double* v) {
+      v[0] = L[f * cap + s];
+      v[1] = L[(f + 1) * cap + s];
+      v[2] = L[(f + 2) * cap + s];
+    };
+    double de[3] = {0.0, 0.0, 0.0};
+    {  // induced-permanent term, dipoles a (as EpolarPh)
+      const double qi = LH[3 * cap + a], qj = LK[3 * cap + b];
+      double ui[3], uj[3], pi[3], pj[3];
+      fld(LH, 4, a, ui);
+      fld(LK, 4, b, uj);
+      fld(LH, 16, a, pi);
+      fld(LK, 16, b, pj);
+      double ti[6], tj[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        ti[k] = LH[(7 + k) * cap + a];
+        tj[k] = LK[(7 + k) * cap + b];
+      }
+      const auto tmul = [](const double* t, const double* x, double* y) {
+        y[0] = t[0] * x[0] + t[1] * x[1] + t[2] * x[2];
+        y[1] = t[1] * x[0] + t[3] * x[1] + t[4] * x[2];
+        y[2] = t[2] * x[0] + t[4] * x[1] + t[5] * x[2];
+      };
+      double vi[3], vj[3], tipj[3], tjpi[3];
+      tmul(ti, d, vi);
+      tmul(tj, d, vj);
+      tmul(ti, pj, tipj);
+      tmul(tj, pi, tjpi);
+      const double di = dot(ui, d), dj = dot(uj, d), Qi = dot(d, vi), Qj = dot(d, vj);
+      const double ei = dot(pi, d), ej = dot(pj, d);
+      const double c1 = qj * ei - qi * ej + dot(pi, uj) + dot(ui, pj);
+      const double c2 = -(ei * dj + di * ej) + 2.0 * (dot(pj, vi) - dot(pi, vj));
+      const double c3 = ei * Qj - ej * Qi;
+      const double sp = c1 * gp[2] + c2 * gp[3] + c3 * gp[4];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double dc1 = qj * pi[c] - qi * pj[c];
+        const double dc2 = -(dj * pi[c] + ei * uj[c] + ej * ui[c] + di * pj[c]) + 2.0 * (tipj[c] - tjpi[c]);
+        const double dc3 = Qj * pi[c] + 2.0 * ei * vj[c] - Qi * pj[c] - 2.0 * ej * vi[c];
+        de[c] += dc1 * gp[1] + dc2 * gp[2] + dc3 * gp[3] - sp * d[c];
+      }
+    }
+    // bilinear induced-induced terms: U(x_i, y_j) = x.y gm1 - (x.d)(y.d) gm2
+    const auto bil = [&](const double* x, const double* y) {
+      const double ex = dot(x, d), ey = dot(y, d), xy = dot(x, y);
+      const double sm = xy * gm[2] - ex * ey * gm[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) de[c] += -(ey * x[c] + ex * y[c]) * gm[2] - sm * d[c];
+    };
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      double bi[3], bj[3], ci[3], cj[3];
+      fld(LH, 19 + 6 * m, a, bi);
+      fld(LK, 19 + 6 * m, b, bj);
+      fld(LH, 22 + 6 * m, a, ci);
+      fld(LK, 22 + 6 * m, b, cj);
+      bil(bi, cj);
+      bil(ci, bj);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lds_add(&AH[c * cap + a], kCoulomb * de[c]);
+      lds_add(&AK[c * cap + b], -kCoulomb * de[c]);
+    }
+  }
+};
+
 // Derivatives of the permanent-multipole energy with respect to each site's
 // own (lab-frame) multipoles, G_i,c = dE/dM_i,c (10 per site, stored layout:
 // an off-diagonal quadrupole component counts both of its matrix entries).

@@ -111,6 +111,8 @@ _SIGS = {
                          _vp, _vp, _vp],
     "tk_vdw_sites": [_vp, _vp, C.POINTER(System), _vp, _vp, _vp],
     "tk_vdw_site_forces": [_vp, _vp, _i32, _vp, _vp, _vp, _vp],
+    "tk_polarize_tcg1": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
+                         _vp, _vp, _vp],
     "tk_evdw": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), C.c_int, _vp, _vp, _d, _d, _d, _d,
                 C.c_int, _vp, _vp, _vp],
     "tk_batch_step": [_vp, _vp, C.POINTER(Batch), C.POINTER(StepParams), _vp, _vp, _vp, _vp, _vp,
@@ -401,6 +403,18 @@ class Context:
         _check(load().tk_vdw_site_forces(self._h, _stream(self.device), int(fs.shape[0]), _ptr(par),
                                          _ptr(rd), _ptr(fs), _ptr(out)), "tk_vdw_site_forces")
         return out
+
+    def polarize_tcg1(self, sysref, lst, mpole, polarity, thole, beta, cutoff, forces=True):
+        mp = _dev(mpole, torch.float64, self.device)
+        pol = _dev(polarity, torch.float64, self.device)
+        th = _dev(thole, torch.float64, self.device)
+        mu = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        e = torch.empty(1, dtype=torch.float64, device=self.device)
+        f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device) if forces else None
+        _check(load().tk_polarize_tcg1(self._h, _stream(self.device), C.byref(sysref.c),
+                                       C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), beta, cutoff,
+                                       _ptr(mu), _ptr(e), _ptr(f)), "tk_polarize_tcg1")
+        return mu, e, f
 
     def evdw(self, sysref, lst, form, rad, eps, cutoff, taper_frac=0.9, dhal=0.07, ghal=0.12,
              prec=FP64):
