@@ -257,7 +257,8 @@ def main():
 
 def extras(ctx, tk, w, a, prec, n7):
     """Mixed-vs-FP64 step, the charge + LJ path, the polarization forces, the
-    reciprocal-space PME and the local frames (not part of `value`)."""
+    reciprocal-space PME, the local frames and the truncated CG (not part of
+    `value`)."""
     import torch
     res = {}
     other = tk.MIXED if prec == tk.FP64 else tk.FP64
@@ -285,7 +286,36 @@ def extras(ctx, tk, w, a, prec, n7):
     res["epolar"] = epolar_leg(ctx, tk, w, n7)
     res["pme"] = pme_leg(ctx, tk, w)
     res["frames"] = frames_leg(ctx, tk, w)
+    res["tcg1"] = tcg_leg(ctx, tk, w)
     return res
+
+
+def tcg_leg(ctx, tk, w):
+    """One-step truncated CG on the water box: dipoles and energy, and with
+    its forces (the total derivative), beside the converged PCG solve."""
+    import torch
+    s = synth.AMOEBA_SETTINGS
+    dev = ctx.device
+    sysw = ctx.system(w.xyz, w.box, w.molid)
+    l7 = ctx.nblist(sysw, s["rc_ewald"] + s["skin"], plan_slot=3)
+    mp = torch.as_tensor(w.mpole, device=dev)
+    pol = torch.as_tensor(w.polarity, device=dev)
+    th = torch.as_tensor(w.thole, device=dev)
+    out = {}
+    out["solve_ms"] = round(timed(lambda: ctx.polarize_tcg1(sysw, l7, mp, pol, th, s["beta"],
+                                                            s["rc_ewald"], forces=False),
+                                  20, 3) * 1e3, 4)
+    out["solve_forces_ms"] = round(timed(lambda: ctx.polarize_tcg1(sysw, l7, mp, pol, th, s["beta"],
+                                                                   s["rc_ewald"]), 20, 3) * 1e3, 4)
+    out["pcg_ms"] = round(timed(lambda: ctx.polarize_pcg(sysw, l7, mp, pol, th, s["beta"],
+                                                         s["rc_ewald"], tol_debye=s["tol_debye"],
+                                                         maxiter=s["maxiter"]), 20, 3) * 1e3, 4)
+    _, e, _ = ctx.polarize_tcg1(sysw, l7, mp, pol, th, s["beta"], s["rc_ewald"], forces=False)
+    _, info = ctx.polarize_pcg(sysw, l7, mp, pol, th, s["beta"], s["rc_ewald"],
+                               tol_debye=s["tol_debye"], maxiter=s["maxiter"])
+    out["epol_tcg1"] = float(e.cpu()[0])
+    out["epol_pcg"] = info["epol"]
+    return out
 
 
 def frames_leg(ctx, tk, w):
