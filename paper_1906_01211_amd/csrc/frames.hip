@@ -279,9 +279,8 @@ tk_status tk_rotate_mpole(tk_ctx* ctx, void* stream, const tk_system* sys,
   if (sys->n == 0) return TK_OK;
   if (!frame_type || !frame_atoms || !mpole_local || !mpole_global) return TK_E_ARG;
   hipStream_t st = (hipStream_t)stream;
-  void* flag;
+  void* flag;   // the kernel's refusal flag (read only by tk_empole_frames, which clears it)
   if ((s = scratch(ctx, per_stream("frames_flag", st).c_str(), 64, &flag))) return s;
-  TK_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
   k_frames_rotate<<<ceil_div(sys->n, 256), 256, 0, st>>>(sys->n, sys->xyz, sys->box, frame_type,
                                                          frame_atoms, mpole_local, mpole_global,
                                                          (int*)flag);
