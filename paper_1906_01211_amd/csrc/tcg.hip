@@ -22,39 +22,74 @@
 
 namespace tk {
 
-template <class R>
-tk_status launch_tmat(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_system* sys,
-                      const double* polarity, const double* thole, double beta, double cutoff,
-                      int include_diag, const double* mu, double* out);
-
 namespace {
 
 constexpr int kDotBlocks = 256;
 
-// Up to three dot products of [3n] vectors: block partials (threads in
+// Epilogue of the field pass: E (permanent field + Ewald self field, as
+// tk_efield_direct) and the direct guess mu0 = alpha E, caller order.
+struct EpiFieldGuess {
+  double* E;
+  double* mu0;
+  const double* mpole;
+  const double* alpha;
+  double cself;
+  __device__ void operator()(int, int i, const double* a) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double e = a[c] + cself * mpole[10 * i + 1 + c];
+      E[3 * i + c] = e;
+      mu0[3 * i + c] = alpha[i] * e;
+    }
+  }
+};
+
+// Epilogue of the first mat-vec: q = A mu0 (as tk_tmatvec with the
+// diagonal), r0 = E - q (zero rows for alpha = 0), p0 = alpha r0.
+struct EpiResidual {
+  const double* mu;
+  const double* alpha;
+  const double* E;
+  double cself;
+  double* r0;
+  double* p0;
+  __device__ void operator()(int, int i, const double* a) const {
+    const double al = alpha[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double m = mu[3 * i + c];
+      const double f = a[c] + cself * m;
+      const double q = al > 0.0 ? m / al - f : 0.0;
+      const double r = al > 0.0 ? E[3 * i + c] - q : 0.0;
+      r0[3 * i + c] = r;
+      p0[3 * i + c] = al * r;
+    }
+  }
+};
+
+// Up to four dot products of [3n] vectors: block partials (threads in
 // order, waves in order), then one block sums the partials in order.
-__global__ __launch_bounds__(256) void k_dots(long m, int nd, const double* __restrict__ a0,
-                                              const double* __restrict__ b0,
-                                              const double* __restrict__ a1,
-                                              const double* __restrict__ b1,
-                                              const double* __restrict__ a2,
-                                              const double* __restrict__ b2,
-                                              double* __restrict__ part) {
-  __shared__ double sh[3][4];
-  double v[3] = {0.0, 0.0, 0.0};
+struct Dots {
+  const double* a[4];
+  const double* b[4];
+};
+
+__global__ __launch_bounds__(256) void k_dots(long m, int nd, Dots D, double* __restrict__ part) {
+  __shared__ double sh[4][4];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (long)gridDim.x * blockDim.x) {
-    v[0] += a0[k] * b0[k];
-    if (nd > 1) v[1] += a1[k] * b1[k];
-    if (nd > 2) v[2] += a2[k] * b2[k];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      if (d < nd) v[d] += D.a[d][k] * D.b[d][k];
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
+  for (int d = 0; d < 4; ++d) {
     for (int o = 32; o > 0; o >>= 1) v[d] += __shfl_xor(v[d], o);
     if (lane == 0) sh[d][w] = v[d];
   }
   __syncthreads();
-  if (threadIdx.x < 3)
+  if ((int)threadIdx.x < nd)
     part[threadIdx.x * kDotBlocks + blockIdx.x] =
         ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) + sh[threadIdx.x][2]) + sh[threadIdx.x][3];
 }
@@ -72,40 +107,17 @@ __global__ __launch_bounds__(256) void k_dots_finish(int nd, const double* __res
   }
 }
 
-// mu0 = alpha E
-__global__ __launch_bounds__(256) void k_tcg_mu0(int n, const double* __restrict__ alpha,
-                                                 const double* __restrict__ E,
-                                                 double* __restrict__ mu0) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) mu0[3 * i + c] = alpha[i] * E[3 * i + c];
-}
-
-// r0 = E - A mu0 (zero rows for alpha = 0), p0 = alpha r0
-__global__ __launch_bounds__(256) void k_tcg_r0(int n, const double* __restrict__ alpha,
-                                                const double* __restrict__ E,
-                                                const double* __restrict__ q,
-                                                double* __restrict__ r0, double* __restrict__ p0) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double al = alpha[i];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const double r = al > 0.0 ? E[3 * i + c] - q[3 * i + c] : 0.0;
-    r0[3 * i + c] = r;
-    p0[3 * i + c] = al * r;
-  }
-}
-
-// S = {gamma, delta, s}: mu1 = mu0 + a p0
+// S = {gamma, delta, s, mu0.E}: mu1 = mu0 + a p0; block 0 writes
+// U = -1/2 C mu1.E = -1/2 C (mu0.E + a s).
 __global__ __launch_bounds__(256) void k_tcg_mu1(int n, const double* __restrict__ S,
                                                  const double* __restrict__ mu0,
                                                  const double* __restrict__ p0,
-                                                 double* __restrict__ mu1) {
+                                                 double* __restrict__ mu1,
+                                                 double* __restrict__ epol) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
   const double a = S[1] != 0.0 ? S[0] / S[1] : 0.0;
+  if (i == 0) epol[0] = -0.5 * kCoulomb * (S[3] + a * S[2]);
+  if (i >= n) return;
 #pragma unroll
   for (int c = 0; c < 3; ++c) mu1[3 * i + c] = mu0[3 * i + c] + a * p0[3 * i + c];
 }
@@ -154,8 +166,19 @@ __global__ __launch_bounds__(256) void k_tcg_grad_in(int n, const double* __rest
   }
 }
 
-__global__ void k_tcg_energy(const double* __restrict__ d, double* __restrict__ epol) {
-  if (threadIdx.x == 0) epol[0] = -0.5 * kCoulomb * d[0];
+// TmatPh for A v in the caller's order
+TmatPh<double> tmat_of(const tk_system* sys, const Plan& P, const double* polarity,
+                       const double* thole, double beta, double cutoff, const double* v) {
+  TmatPh<double> ph;
+  ph.xyz = sys->xyz;
+  ph.mu = v;
+  ph.mu_sorted = 0;
+  ph.polarity = polarity;
+  ph.thole = thole;
+  ph.g.set(sys->box, cutoff, beta);
+  ph.molid = sys->molid;
+  ph.perm_ = (const int32_t*)P.perm.p;
+  return ph;
 }
 
 }  // namespace
@@ -184,37 +207,44 @@ extern "C" tk_status tk_polarize_tcg1(tk_ctx* ctx, void* stream, const tk_system
   if (!mpole || !polarity || !thole || !mu_out) return TK_E_ARG;
   const size_t v3 = sizeof(double) * 3 * (size_t)n;
   void *buf, *part, *S;
-  if ((s = scratch(ctx, per_stream("tcg_vec", st).c_str(), 12 * v3, &buf)) ||
-      (s = scratch(ctx, per_stream("tcg_part", st).c_str(), sizeof(double) * 3 * kDotBlocks, &part)) ||
+  if ((s = scratch(ctx, per_stream("tcg_vec", st).c_str(), 10 * v3, &buf)) ||
+      (s = scratch(ctx, per_stream("tcg_part", st).c_str(), sizeof(double) * 4 * kDotBlocks, &part)) ||
       (s = scratch(ctx, per_stream("tcg_S", st).c_str(), sizeof(double) * 8, &S)))
     return s;
   double* V = (double*)buf;
   const size_t m3 = 3 * (size_t)n;
-  double *E = V, *mu0 = V + m3, *q = V + 2 * m3, *r0 = V + 3 * m3, *p0 = V + 4 * m3,
-         *Pv = V + 5 * m3, *v = V + 6 * m3, *Av = V + 7 * m3, *ga = V + 8 * m3,
-         *gb1 = V + 9 * m3, *gb2 = V + 10 * m3;
-  double* Sd = (double*)S;   // gamma, delta, s, mu1.E
+  double *E = V, *mu0 = V + m3, *r0 = V + 2 * m3, *p0 = V + 3 * m3, *Pv = V + 4 * m3,
+         *v = V + 5 * m3, *Av = V + 6 * m3, *ga = V + 7 * m3, *gb1 = V + 8 * m3,
+         *gb2 = V + 9 * m3;
+  double* Sd = (double*)S;   // gamma, delta, s, mu0.E
   const int nb = ceil_div(n, 256);
-  const tk_system s1{n, sys->xyz, sys->box, sys->molid};
-  if ((s = launch_efield<double>(ctx, st, *P, &s1, mpole, polarity, thole, ewald_beta, cutoff, E,
-                                 0)))
+  // E and mu0 (field pass), r0 and p0 (first mat-vec), P = A p0
+  EfieldPh<double> ef;
+  ef.xyz = sys->xyz;
+  ef.mpole = mpole;
+  ef.molid = sys->molid;
+  ef.polarity = polarity;
+  ef.thole = thole;
+  ef.g.set(sys->box, cutoff, ewald_beta);
+  const double cself = ef.g.cself;
+  if ((s = run_term(ctx, st, *P, ef, EpiFieldGuess{E, mu0, mpole, polarity, cself}, nullptr,
+                    nullptr)))
     return s;
-  k_tcg_mu0<<<nb, 256, 0, st>>>(n, polarity, E, mu0);
-  if ((s = launch_tmat<double>(ctx, st, *P, &s1, polarity, thole, ewald_beta, cutoff, 1, mu0, q)))
+  if ((s = run_term(ctx, st, *P, tmat_of(sys, *P, polarity, thole, ewald_beta, cutoff, mu0),
+                    EpiResidual{mu0, polarity, E, cself, r0, p0}, nullptr, nullptr)))
     return s;
-  k_tcg_r0<<<nb, 256, 0, st>>>(n, polarity, E, q, r0, p0);
-  if ((s = launch_tmat<double>(ctx, st, *P, &s1, polarity, thole, ewald_beta, cutoff, 1, p0, Pv)))
+  if ((s = run_term(ctx, st, *P, tmat_of(sys, *P, polarity, thole, ewald_beta, cutoff, p0),
+                    EpiMutual{Pv, p0, polarity, cself, 1}, nullptr, nullptr)))
     return s;
-  k_dots<<<kDotBlocks, 256, 0, st>>>((long)m3, 3, r0, p0, p0, Pv, p0, E, (double*)part);
-  k_dots_finish<<<1, kDotBlocks, 0, st>>>(3, (const double*)part, Sd);
-  k_tcg_mu1<<<nb, 256, 0, st>>>(n, Sd, mu0, p0, mu_out);
-  k_dots<<<kDotBlocks, 256, 0, st>>>((long)m3, 1, mu_out, E, nullptr, nullptr, nullptr, nullptr,
+  // gamma, delta, s, mu0.E in one pass; mu1 and U
+  k_dots<<<kDotBlocks, 256, 0, st>>>((long)m3, 4, Dots{{r0, p0, p0, mu0}, {p0, Pv, E, E}},
                                      (double*)part);
-  k_dots_finish<<<1, kDotBlocks, 0, st>>>(1, (const double*)part, Sd + 3);
-  k_tcg_energy<<<1, 64, 0, st>>>(Sd + 3, epol);
+  k_dots_finish<<<1, kDotBlocks, 0, st>>>(4, (const double*)part, Sd);
+  k_tcg_mu1<<<nb, 256, 0, st>>>(n, Sd, mu0, p0, mu_out, epol);
   if (force) {
     k_tcg_v<<<nb, 256, 0, st>>>(n, Sd, polarity, mu0, p0, Pv, v);
-    if ((s = launch_tmat<double>(ctx, st, *P, &s1, polarity, thole, ewald_beta, cutoff, 1, v, Av)))
+    if ((s = run_term(ctx, st, *P, tmat_of(sys, *P, polarity, thole, ewald_beta, cutoff, v),
+                      EpiMutual{Av, v, polarity, cself, 1}, nullptr, nullptr)))
       return s;
     k_tcg_grad_in<<<nb, 256, 0, st>>>(n, Sd, polarity, mu0, mu_out, v, Av, p0, ga, gb1, gb2);
     PolGradPh<double> ph;

@@ -43,11 +43,6 @@ tk_status launch_tmat(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_syste
   return run_term(ctx, st, P, ph, epi, nullptr, nullptr);
 }
 
-// (also used by the truncated solve)
-template tk_status launch_tmat<double>(tk_ctx*, hipStream_t, const Plan&, const tk_system*,
-                                       const double*, const double*, double, double, int,
-                                       const double*, double*);
-
 
 }  // namespace tk
 
