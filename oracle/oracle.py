@@ -92,6 +92,8 @@ def lib():
         L.or_polarize_tcg1.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
                                        C.c_double, C.c_double, _dp, C.POINTER(C.c_double),
                                        C.c_void_p]
+        L.or_epolar_frames.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _ip, _ip, _dp,
+                                       _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp]
         _lib = L
     return _lib
 
@@ -413,3 +415,18 @@ def polarize_tcg1(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta,
     if st:
         raise OracleError(st)
     return mu, e.value, f
+
+
+def epolar_frames(xyz, box, molid, row_ptr, col, ftype, fatoms, local, polarity, thole_a, mu, beta,
+                  cutoff):
+    """Polarization pair energies and forces at fixed mu with local-frame multipoles."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    energy = np.zeros(3)
+    force = np.zeros((n, 3))
+    st = lib().or_epolar_frames(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _i(ftype),
+                                _i(fatoms), _d(local), _d(polarity), _d(thole_a), _d(mu), beta,
+                                cutoff, energy, force)
+    if st:
+        raise OracleError(st)
+    return energy, force

@@ -1301,6 +1301,21 @@ static int or_frames_args(int n, const int32_t* ftype, const int32_t* fatoms) {
   return OR_OK;
 }
 
+/* force_k -= sum over sites i with k in their frame of sum_c G_i,c dM_i,c/dx_k */
+static void or_frames_chain(int n, const int32_t* ftype, const int32_t* fatoms, const or_dual* M,
+                            const double* G, double* force) {
+  for (int i = 0; i < n; ++i) {
+    if (ftype[i] == 0) continue;
+    int who[3] = {i, fatoms[2 * i], fatoms[2 * i + 1]};
+    for (int s = 0; s < 3; ++s)
+      for (int a = 0; a < 3; ++a) {
+        double g = 0.0;
+        for (int c = 0; c < 10; ++c) g += G[10 * i + c] * M[10 * i + c].d[3 * s + a];
+        force[3 * who[s] + a] -= g;
+      }
+  }
+}
+
 int or_rotate_mpole(int n, const double* xyz, double box, const int32_t* ftype,
                     const int32_t* fatoms, const double* local, double* global) {
   if (n < 0 || !(box > 0.0)) return OR_E_ARG;
@@ -1359,16 +1374,67 @@ int or_empole_frames(int n, const double* xyz, double box, const int32_t* molid,
         G[10 * j + c] += e;
       }
     }
+  or_frames_chain(n, ftype, fatoms, M, G, force);
+  free(M);
+  free(Mg);
+  free(G);
+  return OR_OK;
+}
+
+/* Polarization energy at fixed induced dipoles with local-frame multipoles:
+ * the pair energies of or_epolar_real at the rotated multipoles M(x), and
+ * their full gradient.  Only the induced-permanent energy depends on M; its
+ * G_i,c is the pair energy U(unit_c at i, mu_j; gp) over the partners j
+ * (and U(mu_i, unit_c at j; gp) from the other side), gp the damped family
+ * of or_epolar_real.  energy[3] as or_epolar_real. */
+int or_epolar_frames(int n, const double* xyz, double box, const int32_t* molid,
+                     const int32_t* row_ptr, const int32_t* col, const int32_t* ftype,
+                     const int32_t* fatoms, const double* local, const double* polarity,
+                     const double* thole, const double* mu, double beta, double rc,
+                     double* energy, double* force) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  if ((st = or_frames_args(n, ftype, fatoms))) return st;
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  or_dual* M = (or_dual*)malloc(sizeof(or_dual) * 10 * nn);
+  double* Mg = (double*)calloc(10 * nn, sizeof(double));
+  double* G = (double*)calloc(10 * nn, sizeof(double));
+  double vir[9];
   for (int i = 0; i < n; ++i) {
-    if (ftype[i] == 0) continue;
-    int who[3] = {i, fatoms[2 * i], fatoms[2 * i + 1]};
-    for (int s = 0; s < 3; ++s)
-      for (int a = 0; a < 3; ++a) {
-        double g = 0.0;
-        for (int c = 0; c < 10; ++c) g += G[10 * i + c] * M[10 * i + c].d[3 * s + a];
-        force[3 * who[s] + a] -= g;
-      }
+    or_rotate_site(xyz, box, i, ftype[i], fatoms[2 * i], fatoms[2 * i + 1], local + 10 * i,
+                   M + 10 * i);
+    for (int k = 0; k < 10; ++k) Mg[10 * i + k] = M[10 * i + k].v;
   }
+  or_epolar_real(n, xyz, box, molid, row_ptr, col, Mg, polarity, thole, mu, beta, rc, energy,
+                 force, vir);
+  double rc2 = rc * rc;
+  for (int i = 0; i < n; ++i)
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int j = col[p];
+      double d[3], r2;
+      or_image(xyz + 3 * i, xyz + 3 * j, box, d, &r2);
+      if (!(r2 <= rc2)) continue;
+      double r = sqrt(r2), B[6], R[6], l[5], gp[6] = {0.0};
+      or_radial(r, beta, 5, B, R);
+      or_thole(r, polarity[i], polarity[j], thole[i], thole[j], &l[1], &l[2], &l[3]);
+      l[4] = or_thole_l9(r, polarity[i], polarity[j], thole[i], thole[j]);
+      double s = molid[i] == molid[j] ? 0.0 : 1.0;
+      for (int k = 1; k <= 4; ++k) gp[k] = B[k] - (1.0 - s * l[k]) * R[k];
+      double ind_i[10] = {0.0}, ind_j[10] = {0.0};
+      for (int a = 0; a < 3; ++a) {
+        ind_i[1 + a] = mu[3 * i + a];
+        ind_j[1 + a] = mu[3 * j + a];
+      }
+      for (int c = 0; c < 10; ++c) {
+        double unit[10] = {0.0}, e, de[3];
+        unit[c] = 1.0;
+        or_mpole_pair(d, unit, ind_j, gp, &e, de);
+        G[10 * i + c] += e;
+        or_mpole_pair(d, ind_i, unit, gp, &e, de);
+        G[10 * j + c] += e;
+      }
+    }
+  or_frames_chain(n, ftype, fatoms, M, G, force);
   free(M);
   free(Mg);
   free(G);

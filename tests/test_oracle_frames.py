@@ -163,3 +163,31 @@ def test_vdw_reduction_sites_and_forces():
     bad[4] = 4
     with pytest.raises(O.OracleError):
         O.vdw_sites(w.xyz, w.box, bad, red)
+
+
+def test_polarization_forces_with_frames_are_minus_gradient():
+    # at fixed induced dipoles, the polarization pair energy depends on the
+    # frame atoms through the rotated permanent multipoles as well
+    w, ft, fa, loc = waters()
+    rc = 4.0
+    rp, cp = O.nblist(w.xyz, w.box, rc + 0.5)
+    mu = np.random.default_rng(4).normal(0, 0.03, (w.n, 3))
+    e, F = O.epolar_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, w.polarity, w.thole, mu,
+                           BETA, rc)
+
+    def E(xyz):
+        g = O.rotate_mpole(xyz, w.box, ft, fa, loc)
+        return O.epolar_real(xyz, w.box, w.molid, rp, cp, g, w.polarity, w.thole, mu, BETA, rc)[0][0]
+    assert e[0] == pytest.approx(E(w.xyz), rel=1e-14)
+    h = 1e-5
+    for i in (0, 1, 2, 31):
+        for a in range(3):
+            xp, xm = w.xyz.copy(), w.xyz.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            g = (E(xp) - E(xm)) / (2 * h)
+            assert F[i, a] == pytest.approx(-g, rel=1e-6, abs=1e-8 * np.abs(F).max())
+    # the frame part is not negligible
+    g = O.rotate_mpole(w.xyz, w.box, ft, fa, loc)
+    _, F0, _ = O.epolar_real(w.xyz, w.box, w.molid, rp, cp, g, w.polarity, w.thole, mu, BETA, rc)
+    assert np.abs(F0 - F).max() > 1e-3 * np.abs(F).max()
