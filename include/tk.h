@@ -281,6 +281,20 @@ tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
                            double* mpole_global);
 
 /*
+ * Polarization forces at fixed induced dipoles with local-frame multipoles:
+ * the pair energies of tk_epolar_real at the rotated multipoles M(x), and
+ * their full gradient, the pair forces plus the frame part of the
+ * induced-permanent energy (its dE/dM through the rotation, as in
+ * tk_empole_frames).  Arguments as tk_empole_frames and tk_epolar_real; FP64;
+ * energy: device [3] (NaN if a frame is invalid); no virial.
+ */
+tk_status tk_epolar_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
+                           const tk_nblist* list, const int32_t* frame_type,
+                           const int32_t* frame_atoms, const double* mpole_local,
+                           const double* polarity, const double* thole, const double* mu,
+                           double ewald_beta, double cutoff, double* energy, double* force);
+
+/*
  * vdW hydrogen reduction (AMOEBA's Halgren term puts a hydrogen's vdW site on
  * its bond).  tk_vdw_sites: site i at r_p + red_i (r_i - r_p), minimum image,
  * for parent[i] = p >= 0, else at r_i; an invalid parent (>= n or i) gives a

@@ -152,6 +152,7 @@ __global__ __launch_bounds__(256) void k_frames_torque(int n, const double* __re
                                                        double* __restrict__ force,
                                                        const int* __restrict__ flag,
                                                        double* __restrict__ energy) {
+  // G: dE/dM per site (10)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0 && flag[0]) {   // a frame was refused: no number is returned as if it were right
 #pragma unroll
@@ -332,6 +333,63 @@ tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
   pd.xyz = sys->xyz;
   pd.mpole = (const double*)mg;
   pd.molid = sys->molid;
+  pd.g.set(sys->box, cutoff, ewald_beta);
+  if ((s = run_term(ctx, st, *P, pd, EpiStore10{(double*)G}, nullptr, nullptr))) return s;
+  {
+    ProfScope ps(ctx, st, "frames_torque");
+    k_frames_torque<<<ceil_div(n, 256), 256, 0, st>>>(n, sys->xyz, sys->box, frame_type,
+                                                      frame_atoms, mpole_local, (const double*)G,
+                                                      force, (const int*)flag, energy);
+  }
+  TK_HIP(hipGetLastError());
+  return TK_OK;
+}
+
+tk_status tk_epolar_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
+                           const tk_nblist* list, const int32_t* frame_type,
+                           const int32_t* frame_atoms, const double* mpole_local,
+                           const double* polarity, const double* thole, const double* mu,
+                           double ewald_beta, double cutoff, double* energy, double* force) {
+  if (!ctx) return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  const Plan* P;
+  if ((s = get_plan(ctx, sys, list, cutoff, &P))) return s;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !energy) return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int n = sys->n;
+  if (n == 0) {
+    TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
+    return TK_OK;
+  }
+  if (!frame_type || !frame_atoms || !mpole_local || !polarity || !thole || !mu || !force)
+    return TK_E_ARG;
+  void *mg, *G, *vir, *flag;
+  if ((s = scratch(ctx, per_stream("frames_G", st).c_str(), sizeof(double) * 10 * (size_t)n, &G)) ||
+      (s = scratch(ctx, per_stream("frames_vir", st).c_str(), sizeof(double) * 9, &vir)) ||
+      (s = scratch(ctx, per_stream("frames_flag", st).c_str(), 64, &flag)) ||
+      (s = scratch(ctx, per_stream("frames_M", st).c_str(), sizeof(double) * 10 * (size_t)n, &mg)))
+    return s;
+  TK_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  k_frames_rotate<<<ceil_div(n, 256), 256, 0, st>>>(n, sys->xyz, sys->box, frame_type, frame_atoms,
+                                                    mpole_local, (double*)mg, (int*)flag);
+  // direct forces and the pair energies at the lab-frame multipoles
+  EpolarPh<double> ph;
+  ph.xyz = sys->xyz;
+  ph.mpole = (const double*)mg;
+  ph.molid = sys->molid;
+  ph.polarity = polarity;
+  ph.thole = thole;
+  ph.mu = mu;
+  ph.g.set(sys->box, cutoff, ewald_beta);
+  if ((s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, (double*)vir))) return s;
+  // dE/dM of the induced-permanent energy, then the frame forces
+  MderivPolPh<double> pd;
+  pd.xyz = sys->xyz;
+  pd.mu = mu;
+  pd.molid = sys->molid;
+  pd.polarity = polarity;
+  pd.thole = thole;
   pd.g.set(sys->box, cutoff, ewald_beta);
   if ((s = run_term(ctx, st, *P, pd, EpiStore10{(double*)G}, nullptr, nullptr))) return s;
   {

@@ -906,6 +906,87 @@ struct MderivPh {
   }
 };
 
+// The same derivatives for the induced-permanent polarization energy at
+// fixed induced dipoles p: each site sees the other's induced dipole as a
+// pure dipole source, in the damped family gp_n = B_n - (1 - s l_(2n+1)) R_n
+// of EpolarPh.  FP64.  Fields: x y z | molid | isa | thole | p(3)
+template <class R>
+struct MderivPolPh {
+  static constexpr int NF = 9, NA = 10, NS = 0;
+  static constexpr const char* kName = "mderiv_pol";
+  static constexpr int kWaves = 2;
+  static constexpr const char* kTag = "_fp64";
+  __device__ bool skip() const { return false; }
+  __device__ void prologue(int tid, int nt) const { erfcx_stage<double>(tid, nt); }
+  const double* xyz;
+  const double* mu;
+  const int32_t* molid;
+  const double* polarity;
+  const double* thole;
+  Geom g;
+  __device__ void set_sys(const SysDev& d, int) {
+    g.box = d.box;
+    g.inv_box = d.inv_box;
+  }
+  static constexpr int NG = 9;
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void stage_dyn(double*, int, int, int) const {}
+  __device__ void gather(int i, double* gg) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gg[c] = xyz[3 * i + c];
+    gg[3] = (double)molid[i];
+    gg[4] = inv_sqrt_alpha(polarity[i]);
+    gg[5] = thole[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gg[6 + c] = mu[3 * i + c];
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double*, long) const {
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
+    if (!(r2 <= g.rc2)) return;
+    const bool excl = LH[3 * cap + a] == LK[3 * cap + b];
+    const double rinv = rsqrt_r(r2), r = r2 * rinv;
+    double B[4], Rb[4];
+    radial<double, 3>(g, r, rinv, B, Rb, r2);
+    double l3, l5, l7;
+    thole_damp<double>(r, LH[4 * cap + a], LK[4 * cap + b], LH[5 * cap + a], LK[5 * cap + b], l3,
+                       l5, l7);
+    const double lf[4] = {0.0, l3, l5, l7};
+    double gp[4];
+#pragma unroll
+    for (int n = 1; n <= 3; ++n) gp[n] = excl ? B[n] - Rb[n] : B[n] - (Rb[n] - lf[n] * Rb[n]);
+    const double* d = dd;
+    const double pi[3] = {LH[6 * cap + a], LH[7 * cap + a], LH[8 * cap + a]};
+    const double pj[3] = {LK[6 * cap + b], LK[7 * cap + b], LK[8 * cap + b]};
+    const double di = pi[0] * d[0] + pi[1] * d[1] + pi[2] * d[2];
+    const double dj = pj[0] * d[0] + pj[1] * d[1] + pj[2] * d[2];
+    double Gi[10], Gj[10];
+    Gi[0] = -dj * gp[1];
+    Gj[0] = di * gp[1];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Gi[1 + c] = -dj * gp[2] * d[c] + gp[1] * pj[c];
+      Gj[1 + c] = -di * gp[2] * d[c] + gp[1] * pi[c];
+    }
+    const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int p = ia[k], q = ib[k];
+      const auto ei = [&](int x, int y) { return -dj * gp[3] * d[x] * d[y] + 2.0 * gp[2] * pj[x] * d[y]; };
+      const auto ej = [&](int x, int y) { return di * gp[3] * d[x] * d[y] - 2.0 * gp[2] * pi[x] * d[y]; };
+      Gi[4 + k] = p == q ? ei(p, p) : ei(p, q) + ei(q, p);
+      Gj[4 + k] = p == q ? ej(p, p) : ej(p, q) + ej(q, p);
+    }
+#pragma unroll
+    for (int c = 0; c < 10; ++c) {
+      lds_add(&AH[c * cap + a], kCoulomb * Gi[c]);
+      lds_add(&AK[c * cap + b], kCoulomb * Gj[c]);
+    }
+  }
+};
+
 struct EpiStore10 {   // the sums are the site's dE/dM (10), caller order
   double* out;
   __device__ void operator()(int, int i, const double* a) const {

@@ -113,6 +113,8 @@ _SIGS = {
     "tk_vdw_site_forces": [_vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "tk_polarize_tcg1": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
                          _vp, _vp, _vp],
+    "tk_epolar_frames": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _vp,
+                         _vp, _d, _d, _vp, _vp],
     "tk_evdw": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), C.c_int, _vp, _vp, _d, _d, _d, _d,
                 C.c_int, _vp, _vp, _vp],
     "tk_batch_step": [_vp, _vp, C.POINTER(Batch), C.POINTER(StepParams), _vp, _vp, _vp, _vp, _vp,
@@ -415,6 +417,22 @@ class Context:
                                        C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), beta, cutoff,
                                        _ptr(mu), _ptr(e), _ptr(f)), "tk_polarize_tcg1")
         return mu, e, f
+
+    def epolar_frames(self, sysref, lst, frame_type, frame_atoms, mpole_local, polarity, thole, mu,
+                      beta, cutoff):
+        ft = _dev(frame_type, torch.int32, self.device)
+        fa = _dev(frame_atoms, torch.int32, self.device)
+        ml = _dev(mpole_local, torch.float64, self.device)
+        pol = _dev(polarity, torch.float64, self.device)
+        th = _dev(thole, torch.float64, self.device)
+        m = _dev(mu, torch.float64, self.device)
+        e = torch.empty(3, dtype=torch.float64, device=self.device)
+        f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        _check(load().tk_epolar_frames(self._h, _stream(self.device), C.byref(sysref.c),
+                                       C.byref(lst.c), _ptr(ft), _ptr(fa), _ptr(ml), _ptr(pol),
+                                       _ptr(th), _ptr(m), beta, cutoff, _ptr(e), _ptr(f)),
+               "tk_epolar_frames")
+        return e, f
 
     def evdw(self, sysref, lst, form, rad, eps, cutoff, taper_frac=0.9, dhal=0.07, ghal=0.12,
              prec=FP64):

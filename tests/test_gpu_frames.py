@@ -128,3 +128,16 @@ def test_vdw_reduction_invalid_parent(ctx):
     parent[4] = 4
     sites = np_(ctx.vdw_sites(ctx.system(w.xyz, w.box, w.molid), parent, red))
     assert np.all(np.isnan(sites[4])) and np.all(np.isfinite(np.delete(sites, 4, axis=0)))
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+def test_epolar_frames_fp64(ctx, name):
+    w, ft, fa, loc, sysr, lst, rp, cp = case(ctx, name)
+    mu = np.random.default_rng(9).normal(0, 0.03, (w.n, 3))
+    e, f = ctx.epolar_frames(sysr, lst, ft, fa, loc, w.polarity, w.thole, mu, S["beta"], 7.0)
+    eo, fo = O.epolar_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, w.polarity, w.thole, mu,
+                             S["beta"], 7.0)
+    e = np_(e)
+    for k in range(3):
+        assert abs(e[k] - eo[k]) <= 1e-10 * abs(eo[k]), (k, e[k], eo[k])
+    assert fmax_rel(np_(f), fo) < 1e-8
