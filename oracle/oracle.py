@@ -58,6 +58,11 @@ def lib():
                                       C.c_double, _dp, _dp, _dp]
         L.or_efield_direct.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
                                        C.c_double, C.c_double, _dp]
+        L.or_efield_intra.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
+                                      C.c_double, C.c_double, C.c_double, _dp]
+        L.or_polarize_pcg2.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
+                                       C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                                       C.c_void_p, _dp, C.POINTER(PcgInfo * 2)]
         L.or_tmatvec.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _dp, _dp, C.c_double,
                                  C.c_double, C.c_int, _dp, _dp]
         L.or_polarize_pcg.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
@@ -211,6 +216,19 @@ def efield_direct(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta,
     return field
 
 
+def efield_intra(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta, cutoff, intra):
+    """The permanent field with same-molecule pairs scaled by intra (0: the
+    field of efield_direct)."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    field = np.zeros((n, 3))
+    st = lib().or_efield_intra(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _d(mpole),
+                               _d(polarity), _d(thole_a), beta, cutoff, float(intra), field)
+    if st:
+        raise OracleError(st)
+    return field
+
+
 def tmatvec(xyz, box, row_ptr, col, polarity, thole_a, beta, cutoff, mu, include_diag=0):
     xyz = _d(xyz)
     n = xyz.shape[0]
@@ -280,6 +298,27 @@ def polarize_pcg_ewald(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, 
     if st not in (OK, E_NOCONV, E_BREAKDOWN):
         raise OracleError(st)
     return mu, {k: getattr(info, k) for k, _ in PcgInfo._fields_}
+
+
+def polarize_pcg2(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta, cutoff, pscale,
+                  tol_debye=1e-5, maxiter=100, mu_guess=None):
+    """Both dipole sets: mu_d from the field without same-molecule pairs,
+    mu_p from the field with them scaled by pscale.  Returns (mu[2,n,3],
+    [info_d, info_p]); info_d's epol is -C/2 mu_d.E_p, info_p's -C/2 mu_p.E_d."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    mu = np.zeros((2, n, 3))
+    info = (PcgInfo * 2)()
+    guess = None
+    if mu_guess is not None:
+        guess_arr = _d(np.asarray(mu_guess).reshape(2, n, 3))
+        guess = guess_arr.ctypes.data_as(C.c_void_p)
+    st = lib().or_polarize_pcg2(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _d(mpole),
+                                _d(polarity), _d(thole_a), beta, cutoff, float(pscale), tol_debye,
+                                int(maxiter), guess, mu, C.byref(info))
+    if st not in (OK, E_NOCONV, E_BREAKDOWN):
+        raise OracleError(st)
+    return mu, [{k: getattr(info[v], k) for k, _ in PcgInfo._fields_} for v in range(2)]
 
 
 def evdw(xyz, box, molid, row_ptr, col, form, rad, eps, cutoff, taper_frac=0.9, dhal=0.07,

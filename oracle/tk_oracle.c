@@ -396,14 +396,14 @@ int or_echarge_real(int n, const double* xyz, double box, const int32_t* molid,
  * section "Hotspots").  Field at i from the multipoles of j, with
  * T1 = -r g1, T2 = r r g2 - I g1, (T3:Theta)_a = -r_a Q g3 + 2 (Theta r)_a g2:
  *   E_i += qj T1 + T2 muj + T3:Thj,     E_j += -qi T1 + T2 mui - T3:Thi,
- * with g_n = B_n - (1 - s l_(2n+1)) R_n, s = 0 for equal molid, else 1
- * (reading: no direct field inside a molecule, Ewald correction kept).
+ * with g_n = B_n - (1 - s l_(2n+1)) R_n, s = intra for equal molid, else 1
+ * (the Ewald correction of the scaled-out part is kept).
  * Plus the Ewald self field c mu_i, c = 4 beta^3 / (3 sqrt(pi)).
  * The field carries no Coulomb constant (units e/A^2). */
-int or_efield_direct(int n, const double* xyz, double box, const int32_t* molid,
-                     const int32_t* row_ptr, const int32_t* col, const double* mpole,
-                     const double* polarity, const double* thole, double beta, double rc,
-                     double* field) {
+static int or_efield_scaled(int n, const double* xyz, double box, const int32_t* molid,
+                            const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                            const double* polarity, const double* thole, double beta, double rc,
+                            double intra, double* field) {
   int st = or_pair_args(n, box, rc);
   if (st) return st;
   double rc2 = rc * rc;
@@ -419,7 +419,7 @@ int or_efield_direct(int n, const double* xyz, double box, const int32_t* molid,
       double r = sqrt(r2), B[4], R[4], l3, l5, l7;
       or_radial(r, beta, 3, B, R);
       or_thole(r, polarity[i], polarity[j], thole[i], thole[j], &l3, &l5, &l7);
-      double s = molid[i] == molid[j] ? 0.0 : 1.0;
+      double s = molid[i] == molid[j] ? intra : 1.0;
       double g1 = B[1] - (1.0 - s * l3) * R[1];
       double g2 = B[2] - (1.0 - s * l5) * R[2];
       double g3 = B[3] - (1.0 - s * l7) * R[3];
@@ -442,6 +442,27 @@ int or_efield_direct(int n, const double* xyz, double box, const int32_t* molid,
     }
   }
   return OR_OK;
+}
+
+/* The field that drives the induced dipoles (reading: no direct field
+ * inside a molecule, intra = 0). */
+int or_efield_direct(int n, const double* xyz, double box, const int32_t* molid,
+                     const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                     const double* polarity, const double* thole, double beta, double rc,
+                     double* field) {
+  return or_efield_scaled(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, 0.0,
+                          field);
+}
+
+/* The same field with same-molecule pairs scaled by intra in [0, 1] (the
+ * second field of the two-right-hand-side solve below). */
+int or_efield_intra(int n, const double* xyz, double box, const int32_t* molid,
+                    const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                    const double* polarity, const double* thole, double beta, double rc,
+                    double intra, double* field) {
+  if (!(intra >= 0.0 && intra <= 1.0)) return OR_E_ARG;
+  return or_efield_scaled(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc,
+                          intra, field);
 }
 
 /* Mutual induced-dipole field (the polarization-solver mat-vec, the largest
@@ -546,18 +567,13 @@ static void or_apply_A(int n, const double* xyz, double box, const int32_t* row_
   free(fld);
 }
 
-static int or_pcg(int n, const double* xyz, double box, const int32_t* molid,
-                  const int32_t* row_ptr, const int32_t* col, const double* mpole,
-                  const double* polarity, const double* thole, double beta, double rc,
-                  const or_recip* rp, double tol_debye, int maxiter, const double* mu_guess,
-                  double* mu_out, or_pcg_info* info) {
-  int st = or_pair_args(n, box, rc);
-  if (st) return st;
-  if (maxiter < 0 || !(tol_debye >= 0.0)) return OR_E_ARG;
-  for (int i = 0; i < n; ++i)
-    if (!(polarity[i] >= 0.0)) return OR_E_ARG;
+/* PCG on A x = b (b given, x = mu_out), E_pol = -1/2 C x.b. */
+static int or_pcg_iterate(int n, const double* xyz, double box, const int32_t* row_ptr,
+                          const int32_t* col, const double* polarity, const double* thole,
+                          double beta, double rc, const or_recip* rp, const double* b,
+                          double tol_debye, int maxiter, const double* mu_guess, double* mu_out,
+                          or_pcg_info* info) {
   size_t m = 3 * (size_t)(n > 0 ? n : 1);
-  double* b = (double*)malloc(sizeof(double) * m);
   double* r = (double*)malloc(sizeof(double) * m);
   double* z = (double*)malloc(sizeof(double) * m);
   double* p = (double*)malloc(sizeof(double) * m);
@@ -565,16 +581,6 @@ static int or_pcg(int n, const double* xyz, double box, const int32_t* molid,
   double* x = mu_out;
   int npol = 0;
   for (int i = 0; i < n; ++i) npol += polarity[i] > 0.0;
-  or_efield_direct(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, b);
-  if (rp) {
-    double e;
-    double* f = (double*)malloc(sizeof(double) * m);
-    double* fr = (double*)malloc(sizeof(double) * m);
-    or_pme_mpole(n, xyz, box, mpole, beta, rp->K, rp->p, &e, f, fr);
-    for (int k = 0; k < 3 * n; ++k) b[k] += fr[k];
-    free(f);
-    free(fr);
-  }
   for (int i = 0; i < n; ++i)
     for (int a = 0; a < 3; ++a) {
       int k = 3 * i + a;
@@ -629,8 +635,43 @@ static int or_pcg(int n, const double* xyz, double box, const int32_t* molid,
   info->rms_debye = rms;
   info->rms_true_debye = or_rmsd(n, z, npol);
   info->epol = -0.5 * OR_COULOMB * epol;
-  free(b); free(r); free(z); free(p); free(q);
+  free(r); free(z); free(p); free(q);
   return status;
+}
+
+static int or_pcg_args(int n, double box, double rc, const double* polarity, double tol_debye,
+                       int maxiter) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  if (maxiter < 0 || !(tol_debye >= 0.0)) return OR_E_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!(polarity[i] >= 0.0)) return OR_E_ARG;
+  return OR_OK;
+}
+
+static int or_pcg(int n, const double* xyz, double box, const int32_t* molid,
+                  const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                  const double* polarity, const double* thole, double beta, double rc,
+                  const or_recip* rp, double tol_debye, int maxiter, const double* mu_guess,
+                  double* mu_out, or_pcg_info* info) {
+  int st = or_pcg_args(n, box, rc, polarity, tol_debye, maxiter);
+  if (st) return st;
+  size_t m = 3 * (size_t)(n > 0 ? n : 1);
+  double* b = (double*)malloc(sizeof(double) * m);
+  or_efield_direct(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, b);
+  if (rp) {
+    double e;
+    double* f = (double*)malloc(sizeof(double) * m);
+    double* fr = (double*)malloc(sizeof(double) * m);
+    or_pme_mpole(n, xyz, box, mpole, beta, rp->K, rp->p, &e, f, fr);
+    for (int k = 0; k < 3 * n; ++k) b[k] += fr[k];
+    free(f);
+    free(fr);
+  }
+  st = or_pcg_iterate(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, rp, b, tol_debye,
+                      maxiter, mu_guess, mu_out, info);
+  free(b);
+  return st;
 }
 
 int or_polarize_pcg(int n, const double* xyz, double box, const int32_t* molid,
@@ -655,6 +696,50 @@ int or_polarize_pcg_ewald(int n, const double* xyz, double box, const int32_t* m
   or_recip rp = {K, p};
   return or_pcg(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, &rp,
                 tol_debye, maxiter, mu_guess, mu_out, info);
+}
+
+/* Two right-hand sides on the same operator (the polarization model of
+ * section "Polarizable AMOEBA force field" with the solver of section
+ * "Hotspots"; batched solves are named among the solver work of section
+ * "Perspectives on Tinker-HP 1.2 performance").  Reading: AMOEBA induces two
+ * dipole sets from two permanent fields that differ only in the factor on
+ * same-molecule pairs: mu_d from E_d (factor 0, or_efield_direct) and mu_p
+ * from E_p (factor pscale, or_efield_intra).  Both solve A mu = E with the
+ * same A, each by its own PCG recurrence (same guess rule, same stopping
+ * test).  The energy is E_pol = -1/2 C mu_d.E_p; by the symmetry of A this is
+ * also -1/2 C mu_p.E_d, up to the residuals.  info[0] is mu_d's solve with
+ * epol = -1/2 C mu_d.E_p; info[1] is mu_p's with epol = -1/2 C mu_p.E_d.
+ * mu_guess (nullable) and mu_out are [2][n][3], mu_d first. */
+int or_polarize_pcg2(int n, const double* xyz, double box, const int32_t* molid,
+                     const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                     const double* polarity, const double* thole, double beta, double rc,
+                     double pscale, double tol_debye, int maxiter, const double* mu_guess,
+                     double* mu_out, or_pcg_info* info) {
+  int st = or_pcg_args(n, box, rc, polarity, tol_debye, maxiter);
+  if (st) return st;
+  if (!(pscale >= 0.0 && pscale <= 1.0)) return OR_E_ARG;
+  size_t m = 3 * (size_t)(n > 0 ? n : 1);
+  double* ed = (double*)malloc(sizeof(double) * m);
+  double* ep = (double*)malloc(sizeof(double) * m);
+  or_efield_scaled(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, 0.0, ed);
+  or_efield_scaled(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, pscale, ep);
+  double* mud = mu_out;
+  double* mup = mu_out + 3 * (size_t)n;
+  int sd = or_pcg_iterate(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, NULL, ed,
+                          tol_debye, maxiter, mu_guess, mud, &info[0]);
+  int sp = or_pcg_iterate(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, NULL, ep,
+                          tol_debye, maxiter, mu_guess ? mu_guess + 3 * (size_t)n : NULL, mup,
+                          &info[1]);
+  double dp = 0.0, pd = 0.0;
+  for (int k = 0; k < 3 * n; ++k) {
+    dp += mud[k] * ep[k];
+    pd += mup[k] * ed[k];
+  }
+  info[0].epol = -0.5 * OR_COULOMB * dp;
+  info[1].epol = -0.5 * OR_COULOMB * pd;
+  free(ed);
+  free(ep);
+  return sd ? sd : sp;
 }
 
 /* ------------------------------------------------------------------------ */
