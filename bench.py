@@ -315,6 +315,27 @@ def tcg_leg(ctx, tk, w):
                                tol_debye=s["tol_debye"], maxiter=s["maxiter"])
     out["epol_tcg1"] = float(e.cpu()[0])
     out["epol_pcg"] = info["epol"]
+    # both dipole sets in one solve (same-molecule factor 0.5 in the second
+    # field), beside the one-set solve; per-launch times of the two mat-vecs
+    def two():
+        return ctx.polarize_pcg2(sysw, l7, mp, pol, th, s["beta"], s["rc_ewald"], 0.5,
+                                 tol_debye=s["tol_debye"], maxiter=s["maxiter"])
+    def one():
+        return ctx.polarize_pcg(sysw, l7, mp, pol, th, s["beta"], s["rc_ewald"],
+                                tol_debye=s["tol_debye"], maxiter=s["maxiter"])
+    out["pcg2_ms"] = round(timed(two, 20, 3) * 1e3, 4)
+    _, i2 = two()
+    out["pcg2_iters"] = [i2[0]["iters"], i2[1]["iters"]]
+    out["epol_pcg2"] = [i2[0]["epol"], i2[1]["epol"]]
+    ctx.profile(True)
+    for _ in range(5):
+        two()
+        one()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    for k in ("pcg_mv_fp64", "pcg2_mv_fp64"):
+        if k in prof:
+            out[k + "_us"] = round(prof[k]["ms"] / prof[k]["launches"] * 1e3, 2)
     return out
 
 
@@ -337,6 +358,13 @@ def frames_leg(ctx, tk, w):
                                                                     s["rc_ewald"]), 20, 3) * 1e3, 4)
     out["empole_lab_ms"] = round(timed(lambda: ctx.empole_real(sysw, l7, mg, s["beta"],
                                                                s["rc_ewald"]), 20, 3) * 1e3, 4)
+    # polarization forces at fixed dipoles, with the frame part
+    mu = torch.as_tensor(np.random.default_rng(9).normal(0, 0.03, (w.n, 3)), device=dev)
+    pol = torch.as_tensor(w.polarity, device=dev)
+    th = torch.as_tensor(w.thole, device=dev)
+    out["epolar_frames_ms"] = round(timed(lambda: ctx.epolar_frames(sysw, l7, ft, fa, loc, pol, th,
+                                                                    mu, s["beta"], s["rc_ewald"]),
+                                          20, 3) * 1e3, 4)
     return out
 
 

@@ -244,6 +244,29 @@ tk_status tk_polarize_pcg_ewald(tk_ctx* ctx, void* stream, const tk_system* sys,
                                 tk_pcg_info* info);
 
 /*
+ * Two dipole sets on one operator: the induced dipoles of the AMOEBA model
+ * (section "Polarizable AMOEBA force field") come from two permanent fields,
+ * solved together by the solver of section "Hotspots" (batched solves of the
+ * solver work in section "Perspectives on Tinker-HP 1.2 performance").
+ * mu_d solves A mu = E_d, the field of tk_efield_direct (no same-molecule
+ * pairs); mu_p solves A mu = E_p, the same field with the damped part of
+ * same-molecule pairs scaled by pscale in [0, 1] (pscale = 0: E_p = E_d).
+ * Each has its own PCG recurrence, guess rule and stopping test as in
+ * tk_polarize_pcg; every mat-vec applies A to both, reading each pair's data
+ * once.  mu_guess: device [2][n][3] (mu_d's block first) or NULL; mu_out:
+ * device [2][n][3], written in stream order.  info: HOST [2], info[0] for
+ * mu_d with epol = -1/2 C mu_d.E_p, info[1] for mu_p with
+ * epol = -1/2 C mu_p.E_d (equal up to the residuals, A being symmetric).
+ * FP64, real space only.  Returns info[0].status if not TK_OK, else
+ * info[1].status.  Synchronises `stream` while solving.
+ */
+tk_status tk_polarize_pcg2(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                           const double* mpole, const double* polarity, const double* thole,
+                           double ewald_beta, double cutoff, double pscale, double tol_debye,
+                           int32_t maxiter, const double* mu_guess, double* mu_out,
+                           tk_pcg_info* info);
+
+/*
  * Local-frame multipoles (the rotation step that section "Hotspots" lists
  * beside the multipole routines).  frame_type: device [n] int32, 0 none,
  * 1 Z-then-X, 2 bisector (TK_FRAME_*); frame_atoms: device [n][2] int32, the

@@ -92,9 +92,10 @@ struct MvEnt {
   int64_t uoff;
 };
 
-// Per cell: alpha and the initial guess (caller's, or alpha * b) in sorted
-// order; count of polarizable atoms into npart[c]; the cell's header and
-// unit entries.
+// Per cell: alpha and the initial guesses (caller's, or alpha * b) of the nv
+// right-hand sides in sorted order (vector v at offset v * 3n, the caller's
+// guess in atom order likewise); count of polarizable atoms into npart[c];
+// the cell's header and unit entries.
 __global__ __launch_bounds__(kCellThreads) void k_cs_setup(PlanView pv, const double* __restrict__ pol,
                                                            const double* __restrict__ guess,
                                                            const int32_t* __restrict__ guess_on,
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_setup(PlanView pv, const do
                                                            double* __restrict__ x,
                                                            double* __restrict__ npart,
                                                            MvHdr* __restrict__ hdr,
-                                                           MvEnt* __restrict__ ent) {
+                                                           MvEnt* __restrict__ ent, int nv) {
   __shared__ double sh[16];
   const int pos = xcd_pos(pv.ncells, blockIdx.x);
   if (pos < 0) return;
@@ -112,14 +113,17 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_setup(PlanView pv, const do
   const int sy = cell_system(pv, c);
   const bool use = guess && (!guess_on || guess_on[sy]);
   double cnt[1] = {0.0};
+  const long vs = 3L * pv.n;
   for (int s = hs + threadIdx.x; s < he; s += kCellThreads) {
     const int i = pv.perm[s];
     const double a = pol[i];
     alpha_s[s] = a;
     cnt[0] += a > 0.0 ? 1.0 : 0.0;
+    for (int v = 0; v < nv; ++v)
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      x[3 * s + k] = use ? (a > 0.0 ? guess[3 * i + k] : 0.0) : a * b[3 * s + k];
+      for (int k = 0; k < 3; ++k)
+        x[v * vs + 3 * s + k] =
+            use ? (a > 0.0 ? guess[v * vs + 3 * i + k] : 0.0) : a * b[v * vs + 3 * s + k];
   }
   if (threadIdx.x < 64) {   // wave 0: the unit entries (exclusive prefixes over the cell's units)
     const int lane = threadIdx.x;
@@ -158,13 +162,13 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_setup(PlanView pv, const do
   if (threadIdx.x == 0) npart[c] = cnt[0];
 }
 
-// One block per system: fresh state.  active (device, nullable): systems
-// outside the solve start as done.
+// One block per system and right-hand side (state sy * nv + v): fresh state.
+// active (device, nullable): systems outside the solve start as done.
 __global__ __launch_bounds__(64) void k_cs_init(PlanView pv, const double* __restrict__ npart,
                                                 PcgState* st, double tol, int maxiter,
-                                                const int32_t* __restrict__ active) {
+                                                const int32_t* __restrict__ active, int nv) {
   __shared__ double sh[16];
-  const int sy = blockIdx.x;
+  const int sy = blockIdx.x / nv;
   double np[1] = {0.0};
   for (int c = pv.sys[sy].cell0 + threadIdx.x; c < pv.sys[sy + 1].cell0; c += 64) np[0] += npart[c];
   wg_sum<1>(np, sh);
@@ -174,7 +178,7 @@ __global__ __launch_bounds__(64) void k_cs_init(PlanView pv, const double* __res
   s0.tol = tol;
   s0.maxiter = maxiter;
   s0.done = active && !active[sy] ? 1 : 0;
-  st[sy] = s0;
+  st[blockIdx.x] = s0;
 }
 
 // ---------------------------------------------------------------------------
@@ -205,10 +209,27 @@ __global__ __launch_bounds__(64) void k_cs_init(PlanView pv, const double* __res
 //          cell of each system records its state and mirrors it to the host.
 // kMode 2: v = x (only once the system has stopped): partials of
 //          |alpha (b - A x)|^2 and x.b.
+//
+// NV right-hand sides on the same operator (the two dipole sets): every
+// per-atom vector holds NV blocks of 3n values (block v at offset v * vs),
+// each with its own state (sy * NV + v), partials (block v of 2 * ncells)
+// and recurrence.  A pair's code and radial factors are read once and applied
+// to all NV operands; a right-hand side that has stopped keeps being
+// multiplied (beta = 0) but its results are not used.  In mode 2 the second
+// partial is x_v . b_(NV-1-v), the cross product that the energy of two
+// dipole sets takes.
 constexpr int kMvThreads = 512;    // mat-vec workgroups: 8 waves per cell
 constexpr int kMvWaves = kMvThreads / 64;
-constexpr int kMvBatch = 4;        // pairs per thread whose loads are issued together
-constexpr int kMvStageBatch = 3;   // staged atoms per thread whose loads are issued together
+// pairs, and staged atoms, per thread whose loads are issued together (fewer
+// with two operands, to keep two workgroups per CU in registers)
+template <int NV>
+constexpr int mv_batch() { return NV == 1 ? 4 : 2; }
+template <int NV>
+constexpr int mv_stage_batch() { return NV == 1 ? 3 : 2; }
+
+// double2 slots per staged atom: x y z and NV operands, padded to 16 bytes
+template <int NV>
+constexpr int mv_slots() { return (3 + 3 * NV + 1) / 2; }
 
 template <class R>
 struct MvArgs {
@@ -228,29 +249,35 @@ struct MvArgs {
   double* q;            // mode 1
   double* r;            // mode 0
   double* z;            // mode 0
-  double* part;         // [2][ncells] per-cell partials
-  const double* pz_cur;    // [2][ncells] partials of r.z | z.z of iteration k
-  const double* pz_prev;   // [2][ncells] of iteration k - 1
-  // full Ewald operator (one system, FP64): the PME field of the operand is
-  // subtracted from A v.  Modes 0, 2: rz = field of x.  Mode 1: rz = field of
-  // z_k, and the field of p_k = z_k + beta p_(k-1) is rz + beta rf_old (the
-  // field is linear), stored in rf_new for the next iteration.
+  double* part;         // [NV][2][ncells] per-cell partials
+  const double* pz_cur;    // [NV][2][ncells] partials of r.z | z.z of iteration k
+  const double* pz_prev;   // [NV][2][ncells] of iteration k - 1
+  // full Ewald operator (one system, one right-hand side, FP64): the PME
+  // field of the operand is subtracted from A v.  Modes 0, 2: rz = field of
+  // x.  Mode 1: rz = field of z_k, and the field of p_k = z_k + beta p_(k-1)
+  // is rz + beta rf_old (the field is linear), stored in rf_new for the next
+  // iteration.
   const double* rz;
   const double* rf_old;
   double* rf_new;
   int k;
   int stage_cap, own_cap;
+  long vs;              // offset between right-hand-side blocks (3n)
   PcgState* st;
   PcgState* host;
 };
 
-template <class R, int kMode, bool kStage, bool kMulti>
+template <class R, int kMode, bool kStage, bool kMulti, int NV>
 __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
+  constexpr int SW = mv_slots<NV>();   // double2 per staged atom
+  constexpr int SD = 2 * SW;           // doubles per staged atom
+  constexpr int kMvStageBatch = mv_stage_batch<NV>();
+  constexpr int kMvBatch = mv_batch<NV>();
   extern __shared__ __align__(16) double lds[];
-  __shared__ double red[3 * 16];
+  __shared__ double red[3 * NV * 16];
   __shared__ int e_role[kEntRow], e_src[kEntRow], e_off[kEntRow], e_pre[kEntRow];
   __shared__ long e_uoff[kEntRow];
-  __shared__ int s_done;
+  __shared__ int s_done[NV];
   const int tid = threadIdx.x, w = tid >> 6;
   const PlanView& pv = A.pv;
   const int ncells = pv.ncells;
@@ -268,57 +295,77 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   }
   const int sy = kMulti ? hd.sy : 0;
   const int c0 = kMulti ? hd.c0 : 0, c1 = kMulti ? hd.c1 : ncells;
-  PcgState* st = A.st + sy;
-  if (tid == 0) s_done = st->done;   // one read per workgroup: all its waves agree
-  double beta = 0.0;
+  PcgState* st = A.st + sy * NV;
+  // one read per workgroup: all its waves agree
+  if (tid < NV) s_done[tid] = st[tid].done;
+  const long vs = NV > 1 ? A.vs : 0;
+  const long pb = 2L * ncells;   // partial block of one right-hand side
+  double beta[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) beta[v] = 0.0;
   if (kMode == 1) {
     const int npol_i = st->npol, maxiter = st->maxiter;
     const double tol = st->tol;
-    double v3[3] = {0.0, 0.0, 0.0};
+    double v3[3 * NV];
+#pragma unroll
+    for (int k = 0; k < 3 * NV; ++k) v3[k] = 0.0;
     for (int cc = c0 + tid; cc < c1; cc += kMvThreads) {
-      v3[0] += A.pz_cur[cc];
-      v3[1] += A.pz_cur[ncells + cc];
-      if (A.k >= 1) v3[2] += A.pz_prev[cc];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        v3[3 * v] += A.pz_cur[v * pb + cc];
+        v3[3 * v + 1] += A.pz_cur[v * pb + ncells + cc];
+        if (A.k >= 1) v3[3 * v + 2] += A.pz_prev[v * pb + cc];
+      }
     }
-    wg_sum<3>(v3, red);   // its barriers also publish the entries and s_done
-    if (s_done) return;
-    const double rz = v3[0], zz = v3[1], rzp = v3[2];
-    const double npol = npol_i > 0 ? (double)npol_i : 1.0;
-    const double rms = kDebye * sqrt(zz / npol);
-    const int stop = rms <= tol ? 1 : A.k >= maxiter ? 2 : 0;
-    if (A.k >= 1) beta = rz / rzp;
-    if (hd.c == c0 && tid == 0) {
-      st->rho = rz;
-      st->zz = zz;
-      st->rms = rms;
-      if (A.k == 0) st->rms0 = rms;
-      st->beta = beta;
-      st->iters = A.k;
-      if (stop) st->done = stop;
-      A.host[sy] = *st;
+    wg_sum<3 * NV>(v3, red);   // its barriers also publish the entries and s_done
+    bool run = false;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (s_done[v]) continue;
+      const double rz = v3[3 * v], zz = v3[3 * v + 1], rzp = v3[3 * v + 2];
+      const double npol = npol_i > 0 ? (double)npol_i : 1.0;
+      const double rms = kDebye * sqrt(zz / npol);
+      const int stop = rms <= tol ? 1 : A.k >= maxiter ? 2 : 0;
+      if (A.k >= 1) beta[v] = rz / rzp;
+      if (hd.c == c0 && tid == 0) {
+        PcgState* sv = st + v;
+        sv->rho = rz;
+        sv->zz = zz;
+        sv->rms = rms;
+        if (A.k == 0) sv->rms0 = rms;
+        sv->beta = beta[v];
+        sv->iters = A.k;
+        if (stop) sv->done = stop;
+        A.host[sy * NV + v] = *sv;
+      }
+      if (stop) beta[v] = 0.0;
+      else run = true;
     }
-    if (stop) return;
+    if (!run) return;
   } else {
     __syncthreads();
-    if (kMode != 2 && s_done) return;
-    if (kMode == 2 && !s_done) return;
+    bool all = true;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) all = all && s_done[v] != 0;
+    if (kMode != 2 && all) return;
+    if (kMode == 2 && !all) return;
   }
   const int ne = hd.ne, hs = hd.hs, nown = hd.nown;
   const double box = hd.box, inv_box = hd.inv_box;
   const long ps = A.pstride;
   // operand v + beta * pold: for k = 0 (and modes 0, 2) beta = 0 and pold = v
   const double* pold = (kMode == 1 && A.k >= 1) ? A.pold : A.v;
-  // LDS: staged atoms, 48 bytes each (x y | z v0 | v1 v2: three 16-byte
-  // reads per atom), then [wave][3][OC] accumulators
+  // LDS: staged atoms, SD doubles each (x y | z v0 | v1 v2 for one
+  // right-hand side: 16-byte reads), then [wave][NV][3][OC] accumulators
   const int SC = kStage ? A.stage_cap : A.own_cap, OC = A.own_cap;
   double2* L2 = (double2*)lds;
-  double* ACC = lds + 6 * SC;
+  double* ACC = lds + SD * SC;
   const int own0 = kStage ? e_off[hd.self_j] : 0;
   const int total = kStage ? e_off[ne] : nown;
   const int T = e_pre[ne];
   // round 2: staging loads, the first pair batch, own alpha and rhs
   int src[kMvStageBatch];
-  double f[kMvStageBatch][6];
+  double f[kMvStageBatch][SD];
   const auto stage_load = [&](int i0) {
 #pragma unroll
     for (int m = 0; m < kMvStageBatch; ++m) {
@@ -343,7 +390,11 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
       f[m][1] = A.pos[ps + sidx];
       f[m][2] = A.pos[2 * ps + sidx];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) f[m][3 + d] = fma(beta, pold[3 * sidx + d], A.v[3 * sidx + d]);
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          f[m][3 + 3 * v + d] = fma(beta[v], pold[v * vs + 3 * sidx + d], A.v[v * vs + 3 * sidx + d]);
+      if (SD > 3 + 3 * NV) f[m][SD - 1] = 0.0;
     }
   };
   const auto stage_store = [&](int i0) {
@@ -352,7 +403,7 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
       if (src[m] < 0) continue;
       const int i = i0 + m * kMvThreads;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) L2[3 * i + k] = make_double2(f[m][2 * k], f[m][2 * k + 1]);
+      for (int k = 0; k < SW; ++k) L2[SW * i + k] = make_double2(f[m][2 * k], f[m][2 * k + 1]);
     }
   };
   // pair batches: entry index, code and factors of kMvBatch pairs per thread,
@@ -380,24 +431,30 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   };
   stage_load(tid);
   batch_load(tid, 0);
-  double al0 = 0.0, rhs0[3] = {0.0, 0.0, 0.0};
+  double al0 = 0.0, rhs0[NV][3];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) rhs0[v][d] = 0.0;
   if (tid < nown) {
     al0 = A.alpha_s[hs + tid];
     if (kMode != 1)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) rhs0[d] = A.rhs[3 * (hs + tid) + d];
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) rhs0[v][d] = A.rhs[v * vs + 3 * (hs + tid) + d];
   }
   stage_store(tid);
   for (int i0 = tid + kMvThreads * kMvStageBatch; i0 < total; i0 += kMvThreads * kMvStageBatch) {
     stage_load(i0);
     stage_store(i0);
   }
-  for (int i = tid; i < kMvWaves * 3 * nown; i += kMvThreads) {
-    const int ww = i / (3 * nown), rem = i - ww * 3 * nown;
-    ACC[ww * 3 * OC + rem] = 0.0;   // [ww][d][t] with rem = d * nown + t
+  for (int i = tid; i < kMvWaves * 3 * NV * nown; i += kMvThreads) {
+    const int ww = i / (3 * NV * nown), rem = i - ww * 3 * NV * nown;
+    ACC[ww * 3 * NV * OC + rem] = 0.0;   // [ww][v][d][t] with rem = (3 v + d) * nown + t
   }
   __syncthreads();
-  double* MY = ACC + w * 3 * OC;   // this wave's copy: MY[d * nown + t]
+  double* MY = ACC + w * 3 * NV * OC;   // this wave's copy: MY[(3 v + d) * nown + t]
   constexpr int kStep = kMvThreads * kMvBatch;
   const auto process = [&](int buf) {
 #pragma unroll
@@ -410,40 +467,50 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
       const int oth = offs + (role == 1 ? a : b);   // LDS index, or sorted index
       const int ownL = own0 + own;
       const R g1 = g1s[buf][m], g2 = g2s[buf][m];
-      double xo[3], vo64[3];
+      double ro[SD];   // the other atom: x y z, then the NV operands
       if (kStage) {
-        const double2 q0 = L2[3 * oth], q1 = L2[3 * oth + 1], q2 = L2[3 * oth + 2];
-        xo[0] = q0.x;
-        xo[1] = q0.y;
-        xo[2] = q1.x;
-        vo64[0] = q1.y;
-        vo64[1] = q2.x;
-        vo64[2] = q2.y;
-      } else {
-        xo[0] = A.pos[oth];
-        xo[1] = A.pos[ps + oth];
-        xo[2] = A.pos[2 * ps + oth];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) vo64[d] = fma(beta, pold[3 * oth + d], A.v[3 * oth + d]);
+        for (int k = 0; k < SW; ++k) {
+          const double2 qk = L2[SW * oth + k];
+          ro[2 * k] = qk.x;
+          ro[2 * k + 1] = qk.y;
+        }
+      } else {
+        ro[0] = A.pos[oth];
+        ro[1] = A.pos[ps + oth];
+        ro[2] = A.pos[2 * ps + oth];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            ro[3 + 3 * v + d] = fma(beta[v], pold[v * vs + 3 * oth + d], A.v[v * vs + 3 * oth + d]);
       }
-      const double2 w0 = L2[3 * ownL], w1 = L2[3 * ownL + 1];
+      const double2 w0 = L2[SW * ownL], w1 = L2[SW * ownL + 1];
       const double xw[3] = {w0.x, w0.y, w1.x};
       R dv[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double t = xo[d] - xw[d];
+        const double t = ro[d] - xw[d];
         dv[d] = R(fma(-box, rint(t * inv_box), t));
       }
-      const R vo[3] = {R(vo64[0]), R(vo64[1]), R(vo64[2])};
-      const R so = (vo[0] * dv[0] + vo[1] * dv[1] + vo[2] * dv[2]) * g2;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) lds_add(&MY[d * nown + own], (double)(dv[d] * so - vo[d] * g1));
+      for (int v = 0; v < NV; ++v) {
+        const R vo[3] = {R(ro[3 + 3 * v]), R(ro[4 + 3 * v]), R(ro[5 + 3 * v])};
+        const R so = (vo[0] * dv[0] + vo[1] * dv[1] + vo[2] * dv[2]) * g2;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          lds_add(&MY[(3 * v + d) * nown + own], (double)(dv[d] * so - vo[d] * g1));
+      }
       if (role == 2) {   // self unit: the other atom is also this cell's
-        const double2 w2 = L2[3 * ownL + 2];
-        const R va[3] = {R(w1.y), R(w2.x), R(w2.y)};
-        const R sa = (va[0] * dv[0] + va[1] * dv[1] + va[2] * dv[2]) * g2;
+        const double* rw = lds + SD * ownL;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) lds_add(&MY[d * nown + b], (double)(dv[d] * sa - va[d] * g1));
+        for (int v = 0; v < NV; ++v) {
+          const R va[3] = {R(rw[3 + 3 * v]), R(rw[4 + 3 * v]), R(rw[5 + 3 * v])};
+          const R sa = (va[0] * dv[0] + va[1] * dv[1] + va[2] * dv[2]) * g2;
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            lds_add(&MY[(3 * v + d) * nown + b], (double)(dv[d] * sa - va[d] * g1));
+        }
       }
     }
   };
@@ -456,50 +523,61 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
     process(1);
   }
   __syncthreads();
-  double sv[2] = {0.0, 0.0};
+  double sv[2 * NV];
+#pragma unroll
+  for (int k = 0; k < 2 * NV; ++k) sv[k] = 0.0;
   for (int t = tid; t < nown; t += kMvThreads) {
     const int s = hs + t;
     const bool first = t == tid;   // alpha and rhs already loaded in round 2
     const double al = first ? al0 : A.alpha_s[s];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double fs = 0.0;
+    for (int v = 0; v < NV; ++v) {
+      const long o = v * vs + 3 * s;
 #pragma unroll
-      for (int ww = 0; ww < kMvWaves; ++ww) fs += ACC[ww * 3 * OC + d * nown + t];
-      const double vv = lds[6 * (own0 + t) + 3 + d];
-      double av = al > 0.0 ? vv / al - (fs + A.cself * vv) : 0.0;   // (A v)_s
-      if (A.rz) {
-        double rf = A.rz[3 * s + d];
-        if (kMode == 1) {
-          if (A.k >= 1) rf = fma(beta, A.rf_old[3 * s + d], rf);
-          A.rf_new[3 * s + d] = rf;
+      for (int d = 0; d < 3; ++d) {
+        double fs = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < kMvWaves; ++ww) fs += ACC[ww * 3 * NV * OC + (3 * v + d) * nown + t];
+        const double vv = lds[SD * (own0 + t) + 3 + 3 * v + d];
+        double av = al > 0.0 ? vv / al - (fs + A.cself * vv) : 0.0;   // (A v)_s
+        if (NV == 1 && A.rz) {
+          double rf = A.rz[3 * s + d];
+          if (kMode == 1) {
+            if (A.k >= 1) rf = fma(beta[0], A.rf_old[3 * s + d], rf);
+            A.rf_new[3 * s + d] = rf;
+          }
+          if (al > 0.0) av -= rf;
         }
-        if (al > 0.0) av -= rf;
-      }
-      if (kMode == 1) {
-        A.pnew[3 * s + d] = vv;
-        A.q[3 * s + d] = av;
-        sv[0] += vv * av;
-      } else {
-        const double bb = first ? rhs0[d] : A.rhs[3 * s + d];
-        const double rr = al > 0.0 ? bb - av : 0.0;
-        const double zz = al * rr;
-        if (kMode == 0) {
-          A.r[3 * s + d] = rr;
-          A.z[3 * s + d] = zz;
-          sv[0] += rr * zz;
-          sv[1] += zz * zz;
+        if (kMode == 1) {
+          A.pnew[o + d] = vv;
+          A.q[o + d] = av;
+          sv[2 * v] += vv * av;
         } else {
-          sv[0] += zz * zz;
-          sv[1] += vv * bb;
+          const double bb = first ? rhs0[v][d] : A.rhs[o + d];
+          const double rr = al > 0.0 ? bb - av : 0.0;
+          const double zz = al * rr;
+          if (kMode == 0) {
+            A.r[o + d] = rr;
+            A.z[o + d] = zz;
+            sv[2 * v] += rr * zz;
+            sv[2 * v + 1] += zz * zz;
+          } else {
+            const int u = NV - 1 - v;   // the other right-hand side (itself for NV = 1)
+            const double bu = first ? rhs0[u][d] : A.rhs[u * vs + 3 * s + d];
+            sv[2 * v] += zz * zz;
+            sv[2 * v + 1] += vv * bu;
+          }
         }
       }
     }
   }
-  wg_sum<2>(sv, red);
+  wg_sum<2 * NV>(sv, red);
   if (tid == 0) {
-    A.part[hd.c] = sv[0];
-    if (kMode != 1) A.part[ncells + hd.c] = sv[1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      A.part[v * pb + hd.c] = sv[2 * v];
+      if (kMode != 1) A.part[v * pb + ncells + hd.c] = sv[2 * v + 1];
+    }
   }
 }
 
@@ -507,82 +585,114 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
 // system's partials (fixed order, in every workgroup), alpha = rho/gamma,
 // x += alpha p, r -= alpha q, z = alpha_i r; partials of r.z and z.z for
 // iteration k + 1.  The cell's atoms are read in the same round as the
-// partials (before alpha is known).
-template <bool kMulti>
+// partials (before alpha is known).  NV right-hand sides as in k_pcg_mv;
+// one that has stopped is left as it is.
+template <bool kMulti, int NV>
 __global__ __launch_bounds__(kCellThreads) void k_cs_update(
     PlanView pv, const MvHdr* __restrict__ hdr, const double* __restrict__ alpha_s,
     const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
     double* __restrict__ r, double* __restrict__ z, const double* __restrict__ pg,
     const double* __restrict__ pz_cur, double* __restrict__ pz_next, int k, PcgState* states,
-    PcgState* host) {
-  __shared__ double sh[2 * 16];
-  __shared__ int s_done;
+    PcgState* host, long vs_) {
+  __shared__ double sh[2 * NV * 16];
+  __shared__ int s_done[NV];
   const int ncells = pv.ncells;
   const int pos = xcd_pos(ncells, blockIdx.x);
   if (pos < 0) return;
   const MvHdr hd = hdr[pos];
   const int sy = kMulti ? hd.sy : 0;
   const int c0 = kMulti ? hd.c0 : 0, c1 = kMulti ? hd.c1 : ncells;
-  PcgState* st = states + sy;
-  if (threadIdx.x == 0) s_done = st->done;   // one read per workgroup: all its waves agree
-  double g2[2] = {0.0, 0.0};
+  PcgState* st = states + sy * NV;
+  const long vs = NV > 1 ? vs_ : 0;
+  const long pb = 2L * ncells;
+  // one read per workgroup: all its waves agree
+  if (threadIdx.x < NV) s_done[threadIdx.x] = st[threadIdx.x].done;
+  double g2[2 * NV];
+#pragma unroll
+  for (int k2 = 0; k2 < 2 * NV; ++k2) g2[k2] = 0.0;
   for (int cc = c0 + threadIdx.x; cc < c1; cc += kCellThreads) {
-    g2[0] += pg[cc];
-    g2[1] += pz_cur[cc];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      g2[2 * v] += pg[v * pb + cc];
+      g2[2 * v + 1] += pz_cur[v * pb + cc];
+    }
   }
   const int hs = hd.hs, nown = hd.nown;
   const int t0 = threadIdx.x;
-  double a0 = 0.0, p0[3] = {}, q0[3] = {}, x0[3] = {}, r0[3] = {};
+  double a0 = 0.0, p0[NV][3], q0[NV][3], x0[NV][3], r0[NV][3];
   if (t0 < nown) {
     const int s = hs + t0;
     a0 = alpha_s[s];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      p0[d] = p[3 * s + d];
-      q0[d] = q[3 * s + d];
-      x0[d] = x[3 * s + d];
-      r0[d] = r[3 * s + d];
-    }
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const long e = v * vs + 3 * s + d;
+        p0[v][d] = p[e];
+        q0[v][d] = q[e];
+        x0[v][d] = x[e];
+        r0[v][d] = r[e];
+      }
   }
-  wg_sum<2>(g2, sh);
-  if (s_done) return;
-  const double gam = g2[0], rho = g2[1];
+  wg_sum<2 * NV>(g2, sh);   // its barriers also publish s_done
   const bool lead = hd.c == c0 && threadIdx.x == 0;
-  if (!(gam > 0.0)) {   // p.Ap <= 0: not positive definite
-    if (lead) {
-      st->gamma = gam;
-      st->iters = k;
-      st->done = 3;
-      host[sy] = *st;
+  bool on[NV], any = false;
+  double al[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    on[v] = !s_done[v];
+    al[v] = 0.0;
+    if (!on[v]) continue;
+    const double gam = g2[2 * v], rho = g2[2 * v + 1];
+    if (!(gam > 0.0)) {   // p.Ap <= 0: not positive definite
+      if (lead) {
+        st[v].gamma = gam;
+        st[v].iters = k;
+        st[v].done = 3;
+        host[sy * NV + v] = st[v];
+      }
+      on[v] = false;
+      continue;
     }
-    return;
+    al[v] = rho / gam;
+    if (lead) {
+      st[v].gamma = gam;
+      st[v].alpha = al[v];
+    }
+    any = true;
   }
-  const double al = rho / gam;
-  if (lead) {
-    st->gamma = gam;
-    st->alpha = al;
-  }
-  double sv[2] = {0.0, 0.0};
+  if (!any) return;
+  double sv[2 * NV];
+#pragma unroll
+  for (int k2 = 0; k2 < 2 * NV; ++k2) sv[k2] = 0.0;
   for (int t = t0; t < nown; t += kCellThreads) {
     const int s = hs + t;
     const bool first = t == t0;
     const double a = first ? a0 : alpha_s[s];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int e = 3 * s + d;
-      x[e] = (first ? x0[d] : x[e]) + al * (first ? p0[d] : p[e]);
-      const double rr = (first ? r0[d] : r[e]) - al * (first ? q0[d] : q[e]);
-      r[e] = rr;
-      const double zz = a * rr;
-      z[e] = zz;
-      sv[0] += rr * zz;
-      sv[1] += zz * zz;
+    for (int v = 0; v < NV; ++v) {
+      if (!on[v]) continue;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const long e = v * vs + 3 * s + d;
+        x[e] = (first ? x0[v][d] : x[e]) + al[v] * (first ? p0[v][d] : p[e]);
+        const double rr = (first ? r0[v][d] : r[e]) - al[v] * (first ? q0[v][d] : q[e]);
+        r[e] = rr;
+        const double zz = a * rr;
+        z[e] = zz;
+        sv[2 * v] += rr * zz;
+        sv[2 * v + 1] += zz * zz;
+      }
     }
   }
-  wg_sum<2>(sv, sh);
+  wg_sum<2 * NV>(sv, sh);
   if (threadIdx.x == 0) {
-    pz_next[hd.c] = sv[0];
-    pz_next[ncells + hd.c] = sv[1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (!on[v]) continue;
+      pz_next[v * pb + hd.c] = sv[2 * v];
+      pz_next[v * pb + ncells + hd.c] = sv[2 * v + 1];
+    }
   }
 }
 
@@ -643,29 +753,35 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_apply(PlanView pv,
   }
 }
 
-// One block per system: true-residual RMS and E_pol = -C/2 x.b from the
-// per-cell partials; mirrored to the host.  Only for stopped systems.
+// One block per system and right-hand side (state sy * nv + v): true-residual
+// RMS and E_pol = -C/2 x_v.b_(nv-1-v) from the per-cell partials; mirrored to
+// the host.  Only once every right-hand side of the system has stopped.
 __global__ __launch_bounds__(64) void k_cs_finish_true(PlanView pv, const double* __restrict__ part,
-                                                       PcgState* states, PcgState* host) {
+                                                       PcgState* states, PcgState* host, int nv) {
   __shared__ double sh[2 * 16];
   __shared__ int s_done;
-  const int sy = blockIdx.x;
+  const int sy = blockIdx.x / nv, vi = blockIdx.x - sy * nv;
   const int ncells = pv.ncells;
-  PcgState* st = states + sy;
-  if (threadIdx.x == 0) s_done = st->done;
+  PcgState* st = states + blockIdx.x;
+  if (threadIdx.x == 0) {
+    int all = 1;
+    for (int u = 0; u < nv; ++u) all &= states[sy * nv + u].done != 0;
+    s_done = all;
+  }
   __syncthreads();
   if (!s_done) return;
+  const double* pv_part = part + vi * 2L * ncells;
   double v[2] = {0.0, 0.0};
   for (int c = pv.sys[sy].cell0 + threadIdx.x; c < pv.sys[sy + 1].cell0; c += 64) {
-    v[0] += part[c];
-    v[1] += part[ncells + c];
+    v[0] += pv_part[c];
+    v[1] += pv_part[ncells + c];
   }
   wg_sum<2>(v, sh);
   if (threadIdx.x != 0) return;
   const double npol = st->npol > 0 ? (double)st->npol : 1.0;
   st->rms_true = kDebye * sqrt(v[0] / npol);
   st->epol = -0.5 * kCoulomb * v[1];
-  host[sy] = *st;
+  host[blockIdx.x] = *st;
 }
 
 // Refinement: keep x in dx and start the correction from z (= alpha r_t) for
@@ -704,10 +820,13 @@ __global__ void k_scatter_out(int n, const int32_t* __restrict__ perm, const dou
 
 template <class R, int kMode, bool kStage>
 tk_status set_lds_attr(size_t lds) {
-  TK_HIP(hipFuncSetAttribute((const void*)k_pcg_mv<R, kMode, kStage, false>,
+  TK_HIP(hipFuncSetAttribute((const void*)k_pcg_mv<R, kMode, kStage, false, 1>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  TK_HIP(hipFuncSetAttribute((const void*)k_pcg_mv<R, kMode, kStage, true>,
+  TK_HIP(hipFuncSetAttribute((const void*)k_pcg_mv<R, kMode, kStage, true, 1>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if constexpr (std::is_same<R, double>::value)   // two right-hand sides: FP64, one system
+    TK_HIP(hipFuncSetAttribute((const void*)k_pcg_mv<R, kMode, kStage, false, 2>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   return TK_OK;
 }
 
@@ -753,6 +872,8 @@ struct Solver {
   PcgState* host_dev;   // its device address
   int32_t* active;      // [nsys] device copy of the refinement mask
   int32_t* active_h;    // pinned staging of the mask
+  int nv = 1;     // right-hand sides (2: FP64, one system, no reciprocal part)
+  long vs = 0;    // offset between right-hand-side blocks of a vector (3n)
   int pme_grid = 0, pme_order = 0;   // full Ewald operator (one system, FP64) when set
   double* rz = nullptr;              // PME field of the current operand
   double* rfb[2] = {nullptr, nullptr};   // PME field of p_k (k even, odd)
@@ -782,6 +903,7 @@ struct Solver {
     a.alpha_s = alpha_s;
     a.stage_cap = P->max_nbhd;
     a.own_cap = P->max_occ;
+    a.vs = vs;
     a.st = state;
     a.host = host_dev;
     return a;
@@ -798,10 +920,16 @@ struct Solver {
       else
         hipLaunchKernelGGL(kern, g, b, mv_lds, st, a);
     };
+    if constexpr (std::is_same<R, double>::value) {
+      if (nv == 2) {
+        go(stage ? k_pcg_mv<R, kMode, true, false, 2> : k_pcg_mv<R, kMode, false, false, 2>);
+        return;
+      }
+    }
     if (nsys > 1)
-      go(stage ? k_pcg_mv<R, kMode, true, true> : k_pcg_mv<R, kMode, false, true>);
+      go(stage ? k_pcg_mv<R, kMode, true, true, 1> : k_pcg_mv<R, kMode, false, true, 1>);
     else
-      go(stage ? k_pcg_mv<R, kMode, true, false> : k_pcg_mv<R, kMode, false, false>);
+      go(stage ? k_pcg_mv<R, kMode, true, false, 1> : k_pcg_mv<R, kMode, false, false, 1>);
   }
 
   // iteration k, first half: convergence test, p_k, q = A p_k
@@ -821,19 +949,25 @@ struct Solver {
       a.rf_old = rfb[(k + 1) & 1];
       a.rf_new = rfb[k & 1];
     }
-    launch_mv<R, 1>(a, "pcg_mv");
+    launch_mv<R, 1>(a, nv == 2 ? "pcg2_mv" : "pcg_mv");
   }
 
   // iteration k, second half: update x, r, z
   void queue_update(int k) {
-    ProfScope ps(ctx, st, "pcg_update");
+    ProfScope ps(ctx, st, nv == 2 ? "pcg2_update" : "pcg_update");
     const int g = xcd_grid(ncells);
-    if (nsys > 1)
-      k_cs_update<true><<<g, kCellThreads, 0, st>>>(pv, hdr, alpha_s, pbuf[k & 1], q, x, r, z, pg,
-                                                    pz[k & 1], pz[(k + 1) & 1], k, state, host_dev);
+    if (nv == 2)
+      k_cs_update<false, 2><<<g, kCellThreads, 0, st>>>(pv, hdr, alpha_s, pbuf[k & 1], q, x, r, z,
+                                                        pg, pz[k & 1], pz[(k + 1) & 1], k, state,
+                                                        host_dev, vs);
+    else if (nsys > 1)
+      k_cs_update<true, 1><<<g, kCellThreads, 0, st>>>(pv, hdr, alpha_s, pbuf[k & 1], q, x, r, z,
+                                                       pg, pz[k & 1], pz[(k + 1) & 1], k, state,
+                                                       host_dev, vs);
     else
-      k_cs_update<false><<<g, kCellThreads, 0, st>>>(pv, hdr, alpha_s, pbuf[k & 1], q, x, r, z, pg,
-                                                     pz[k & 1], pz[(k + 1) & 1], k, state, host_dev);
+      k_cs_update<false, 1><<<g, kCellThreads, 0, st>>>(pv, hdr, alpha_s, pbuf[k & 1], q, x, r, z,
+                                                        pg, pz[k & 1], pz[(k + 1) & 1], k, state,
+                                                        host_dev, vs);
   }
 
   // TmatPh for the on-the-fly FP64 mat-vec of the mixed form
@@ -881,13 +1015,13 @@ struct Solver {
         queue_pme(x, 1);
         a.rz = rz;
       }
-      launch_mv<double, 2>(a, "pcg_mv_residual");
+      launch_mv<double, 2>(a, nv == 2 ? "pcg2_mv_residual" : "pcg_mv_residual");
     } else {
       matvec64_tiles(x);
       k_cs_apply<2><<<ncells, kCellThreads, 0, st>>>(pv, partial, pstride, cself, alpha_s, x, rhs,
                                                      nullptr, nullptr, part, state);
     }
-    k_cs_finish_true<<<nsys, 64, 0, st>>>(pv, part, state, host_dev);
+    k_cs_finish_true<<<nsys * nv, 64, 0, st>>>(pv, part, state, host_dev, nv);
   }
 
   tk_status sync_state() {
@@ -897,7 +1031,7 @@ struct Solver {
   }
 
   bool all_stopped() const {
-    for (int k = 0; k < nsys; ++k)
+    for (int k = 0; k < nsys * nv; ++k)
       if (!host[k].done) return false;
     return true;
   }
@@ -905,7 +1039,7 @@ struct Solver {
   // geometric convergence of the slowest running system: rms_k ~ rms_0 q^k
   int predict_chunk(double tol) const {
     int chunk = 1;
-    for (int k = 0; k < nsys; ++k) {
+    for (int k = 0; k < nsys * nv; ++k) {
       const PcgState& h = host[k];
       if (h.done) continue;
       int c = kChunk;
@@ -929,7 +1063,7 @@ struct Solver {
   template <class R>
   tk_status run(const double* rhs, double tol, int maxiter, int first_chunk, bool residual,
                 const int32_t* act) {
-    k_cs_init<<<nsys, 64, 0, st>>>(pv, npart, state, tol, maxiter, act);
+    k_cs_init<<<nsys * nv, 64, 0, st>>>(pv, npart, state, tol, maxiter, act, nv);
     tk_status s0;
     {
       MvArgs<R> a = mv_args<R>();
@@ -943,7 +1077,7 @@ struct Solver {
         if ((s0 = queue_pme(x, -1))) return s0;
         a.rz = rz;
       }
-      launch_mv<R, 0>(a, "pcg_mv0");
+      launch_mv<R, 0>(a, nv == 2 ? "pcg2_mv0" : "pcg_mv0");
     }
     if ((s0 = queue_pme(z, 0))) return s0;
     queue_mv<R>(0);
@@ -973,14 +1107,15 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                         const double* thole, double ewald_beta, double cutoff, double tol_debye,
                         int32_t maxiter, int prec, const double* mu_guess,
                         const int32_t* guess_on, double* mu_out, tk_pcg_info* info,
-                        int pme_grid, int pme_order) {
+                        int pme_grid, int pme_order, int nv, double pscale) {
   const int nsys = P->nsys;
   if (pme_grid && (prec != TK_FP64 || nsys != 1 || !pme_args_ok(pme_grid, pme_order)))
     return TK_E_ARG;
-  for (int k = 0; k < nsys; ++k) info[k] = tk_pcg_info{};
+  if (nv != 1 && (nv != 2 || prec != TK_FP64 || nsys != 1 || pme_grid)) return TK_E_ARG;
+  for (int k = 0; k < nsys * nv; ++k) info[k] = tk_pcg_info{};
   const int n = P->n;
   if (n == 0) {
-    for (int k = 0; k < nsys; ++k) info[k].converged = 1;
+    for (int k = 0; k < nsys * nv; ++k) info[k].converged = 1;
     return TK_OK;
   }
   Solver S;
@@ -998,15 +1133,18 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   S.prec = prec;
   S.nsys = nsys;
   S.ncells = P->ncells;
+  S.nv = nv;
+  S.vs = 3L * n;
   S.pstride = pad64(n);
   S.gcs = (long)(P->codes.bytes / sizeof(uint32_t));
   // stage whole neighbourhoods in LDS when they fit, else only the own cell
-  const size_t acc = (size_t)kMvWaves * 3 * P->max_occ;
-  S.stage = sizeof(double) * (6 * (size_t)P->max_nbhd + acc) + 4096 <= kMaxLds;
-  S.mv_lds = sizeof(double) * (6 * (size_t)(S.stage ? P->max_nbhd : P->max_occ) + acc);
+  const size_t acc = (size_t)kMvWaves * 3 * nv * P->max_occ;
+  const size_t sd = nv == 2 ? 2 * mv_slots<2>() : 2 * mv_slots<1>();   // doubles per staged atom
+  S.stage = sizeof(double) * (sd * (size_t)P->max_nbhd + acc) + 4096 <= kMaxLds;
+  S.mv_lds = sizeof(double) * (sd * (size_t)(S.stage ? P->max_nbhd : P->max_occ) + acc);
   if (S.mv_lds + 4096 > kMaxLds) return TK_E_CAPACITY;   // a cell beyond the LDS limit
-  const size_t v3 = sizeof(double) * 3 * (size_t)n;
-  const size_t npc = sizeof(double) * 2 * (size_t)S.ncells;
+  const size_t v3 = sizeof(double) * 3 * (size_t)n * nv;
+  const size_t npc = sizeof(double) * 2 * (size_t)S.ncells * nv;
   tk_status s;
   void *alpha_s, *b, *x, *r, *z, *q, *partial = nullptr, *gath, *npart, *part, *dx, *rt, *pb0,
        *pb1, *pz0, *pz1, *pg, *state, *act, *hdr, *ent;
@@ -1020,7 +1158,7 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
       (s = scratch(ctx, "pcg_part", npc, &part)) || (s = scratch(ctx, "pcg_pz0", npc, &pz0)) ||
       (s = scratch(ctx, "pcg_pz1", npc, &pz1)) || (s = scratch(ctx, "pcg_pg", npc, &pg)) ||
       (s = scratch(ctx, "pcg_gathered", sizeof(double) * TmatPh<double>::NG * S.pstride, &gath)) ||
-      (s = scratch(ctx, "pcg_state", sizeof(PcgState) * nsys, &state)) ||
+      (s = scratch(ctx, "pcg_state", sizeof(PcgState) * nsys * nv, &state)) ||
       (s = scratch(ctx, "pcg_hdr", sizeof(MvHdr) * S.ncells, &hdr)) ||
       (s = scratch(ctx, "pcg_ent", sizeof(MvEnt) * kEntRow * S.ncells, &ent)) ||
       (s = scratch(ctx, "pcg_active", sizeof(int32_t) * nsys, &act)) ||
@@ -1056,7 +1194,7 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   if ((s = mv_attributes(S.mv_lds))) return s;
   // pinned: [1024, ...) host state mirrors, then the refinement mask
   void *hbase, *hdev;
-  const size_t mirror = sizeof(PcgState) * nsys;
+  const size_t mirror = sizeof(PcgState) * nsys * nv;
   if ((s = pinned(ctx, 1024 + mirror + sizeof(int32_t) * nsys + 64, &hbase, &hdev))) return s;
   S.host = (PcgState*)((char*)hbase + 1024);
   S.host_dev = (PcgState*)((char*)hdev + 1024);
@@ -1070,6 +1208,10 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                       : launch_efield<float>(ctx, st, *P, &sys1, mpole, polarity, thole,
                                              ewald_beta, cutoff, S.b, 1, (float*)S.gc, S.gcs);
   if (s) return s;
+  // the second right-hand side: same-molecule pairs scaled by pscale
+  if (nv == 2 && (s = launch_efield<double>(ctx, st, *P, &sys1, mpole, polarity, thole, ewald_beta,
+                                            cutoff, S.b + S.vs, 1, nullptr, 0, pscale)))
+    return s;
   if (prec == TK_FP64)   // the FP64 mat-vec reads only coordinates: the ones the field pass gathered
     S.gathered = (double*)ctx->scratch[per_stream("gathered", st)].p;
   else
@@ -1084,15 +1226,16 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                                          pme_order)))
     return s;
   k_cs_setup<<<xcd_grid(S.ncells), kCellThreads, 0, st>>>(S.pv, polarity, mu_guess, guess_on, S.b,
-                                                          S.alpha_s, S.x, S.npart, S.hdr, S.ent);
+                                                          S.alpha_s, S.x, S.npart, S.hdr, S.ent,
+                                                          nv);
   const int slot = (int)(P - ctx->plans);
   int& hint = ctx->pcg_hint[slot][prec == TK_FP64 ? 0 : 1];
   s = prec == TK_FP64 ? S.run<double>(S.b, tol_debye, maxiter, hint, true, nullptr)
                       : S.run<float>(S.b, tol_debye, maxiter, hint, true, nullptr);
   if (s) return s;
   int most = 0;
-  std::vector<int> done(nsys);
-  for (int k = 0; k < nsys; ++k) {
+  std::vector<int> done(nsys * nv);
+  for (int k = 0; k < nsys * nv; ++k) {
     const PcgState& h = S.host[k];
     done[k] = h.done;
     most = std::max(most, h.iters);
@@ -1143,7 +1286,9 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   }
   // the dipoles reach mu_out in stream order; the host already has the
   // solve's outcome, so no further synchronisation
-  k_scatter_out<<<ceil_div(n, 256), 256, 0, st>>>(n, (const int32_t*)P->perm.p, S.x, mu_out);
+  for (int v = 0; v < nv; ++v)
+    k_scatter_out<<<ceil_div(n, 256), 256, 0, st>>>(n, (const int32_t*)P->perm.p, S.x + v * S.vs,
+                                                    mu_out + v * S.vs);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }
@@ -1205,4 +1350,31 @@ extern "C" tk_status tk_polarize_pcg_ewald(tk_ctx* ctx, void* stream, const tk_s
                          mu_out, info, grid, order)))
     return s;
   return info->status;
+}
+
+extern "C" tk_status tk_polarize_pcg2(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                      const tk_nblist* list, const double* mpole,
+                                      const double* polarity, const double* thole,
+                                      double ewald_beta, double cutoff, double pscale,
+                                      double tol_debye, int32_t maxiter, const double* mu_guess,
+                                      double* mu_out, tk_pcg_info* info) {
+  if (!ctx || !info) return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !(tol_debye >= 0.0) || maxiter < 0 ||
+      !(pscale >= 0.0 && pscale <= 1.0))
+    return TK_E_ARG;
+  const Plan* P;
+  if ((s = get_plan(ctx, sys, list, cutoff, &P))) return s;
+  info[0] = info[1] = tk_pcg_info{};
+  if (sys->n == 0) {
+    info[0].converged = info[1].converged = 1;
+    return TK_OK;
+  }
+  if (!mpole || !polarity || !thole || !mu_out) return TK_E_ARG;
+  if ((s = solve_dipoles(ctx, (hipStream_t)stream, P, sys->xyz, sys->molid, mpole, polarity, thole,
+                         ewald_beta, cutoff, tol_debye, maxiter, TK_FP64, mu_guess, nullptr,
+                         mu_out, info, 0, 0, 2, pscale)))
+    return s;
+  return info[0].status ? info[0].status : info[1].status;
 }

@@ -345,6 +345,8 @@ struct EfieldPh {
   using GC = R;
   GC* gc = nullptr;
   long gcs = 0;
+  // factor on the damped part of same-molecule pairs (0: the direct field)
+  double intra = 0.0;
   // field contributions at both atoms (fi at H's atom, fj at K's) in type T
   template <class T>
   __device__ __forceinline__ void eval(const double* LH, const double* LK, int cap, int a, int b,
@@ -354,15 +356,28 @@ struct EfieldPh {
     radial_pair<T, 3>(g, r2, excl, B, Rb);
     T g1, g2, g3;
     T l3, l5, l7;
-    if (!excl || gc) {
+    if (!excl || gc || intra != 0.0) {
       const T r = T(r2) * rsqrt_r(T(r2));
       thole_damp<T>(r, T(LH[14 * cap + a]), T(LK[14 * cap + b]), T(LH[15 * cap + a]),
                     T(LK[15 * cap + b]), l3, l5, l7);
     }
     if (excl) {
-      g1 = B[1] - Rb[1];
-      g2 = B[2] - Rb[2];
-      g3 = B[3] - Rb[3];
+      if (intra == 0.0) {
+        g1 = B[1] - Rb[1];
+        g2 = B[2] - Rb[2];
+        g3 = B[3] - Rb[3];
+      } else if (std::is_same<T, float>::value) {
+        // B carries the FP64 difference B - R; add the scaled damped bare part in FP64
+        const double ri = rsqrt_r(r2);
+        const double R1 = ri * ri * ri, R2 = 3.0 * R1 * ri * ri, R3 = 5.0 * R2 * ri * ri;
+        g1 = T((double)B[1] + intra * (double)l3 * R1);
+        g2 = T((double)B[2] + intra * (double)l5 * R2);
+        g3 = T((double)B[3] + intra * (double)l7 * R3);
+      } else {
+        g1 = B[1] - (T(1) - T(intra) * l3) * Rb[1];
+        g2 = B[2] - (T(1) - T(intra) * l5) * Rb[2];
+        g3 = B[3] - (T(1) - T(intra) * l7) * Rb[3];
+      }
       if (gc) {
         if (std::is_same<T, float>::value) {
           // B carries the FP64 difference B - R; re-add the damped bare part in FP64
@@ -1217,10 +1232,11 @@ template <class R>
 inline tk_status launch_efield(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_system* sys,
                         const double* mpole, const double* polarity, const double* thole,
                         double beta, double cutoff, double* out, int sorted_out,
-                        R* gc = nullptr, long gcs = 0) {
+                        R* gc = nullptr, long gcs = 0, double intra = 0.0) {
   EfieldPh<R> ph;
   ph.gc = gc;
   ph.gcs = gcs;
+  ph.intra = intra;
   ph.xyz = sys->xyz;
   ph.mpole = mpole;
   ph.molid = sys->molid;

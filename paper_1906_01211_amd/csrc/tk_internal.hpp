@@ -258,7 +258,7 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                         const double* thole, double ewald_beta, double cutoff, double tol_debye,
                         int32_t maxiter, int prec, const double* mu_guess,
                         const int32_t* guess_on, double* mu_out, tk_pcg_info* info,
-                        int pme_grid = 0, int pme_order = 0);
+                        int pme_grid = 0, int pme_order = 0, int nv = 1, double pscale = 0.0);
 
 // Checks shared by the pair entry points.
 tk_status check_system(const tk_system* sys);

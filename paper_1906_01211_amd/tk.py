@@ -106,6 +106,8 @@ _SIGS = {
     "tk_pme_mpole": [_vp, _vp, C.POINTER(System), _vp, _d, _i32, _i32, _vp, _vp, _vp],
     "tk_polarize_pcg_ewald": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d,
                               _d, _i32, _i32, _d, _i32, _vp, _vp, C.POINTER(PcgInfo)],
+    "tk_polarize_pcg2": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
+                         _d, _d, _i32, _vp, _vp, C.POINTER(PcgInfo * 2)],
     "tk_rotate_mpole": [_vp, _vp, C.POINTER(System), _vp, _vp, _vp, _vp],
     "tk_empole_frames": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
                          _vp, _vp, _vp],
@@ -343,6 +345,23 @@ class Context:
         if st not in (OK, E_NOCONV, E_BREAKDOWN):
             _check(st, "tk_polarize_pcg_ewald")
         return out, {k: getattr(info, k) for k, _ in PcgInfo._fields_}
+
+    def polarize_pcg2(self, sysref, lst, mpole, polarity, thole, beta, cutoff, pscale,
+                      tol_debye=1e-5, maxiter=100, mu_guess=None):
+        """Both dipole sets: returns (mu[2,n,3] with mu_d first, [info_d, info_p])."""
+        mp = _dev(mpole, torch.float64, self.device)
+        pol = _dev(polarity, torch.float64, self.device)
+        th = _dev(thole, torch.float64, self.device)
+        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device)
+        out = torch.empty((2, sysref.n, 3), dtype=torch.float64, device=self.device)
+        info = (PcgInfo * 2)()
+        st = load().tk_polarize_pcg2(self._h, _stream(self.device), C.byref(sysref.c),
+                                     C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), beta, cutoff,
+                                     float(pscale), tol_debye, int(maxiter), _ptr(g), _ptr(out),
+                                     C.byref(info))
+        if st not in (OK, E_NOCONV, E_BREAKDOWN):
+            _check(st, "tk_polarize_pcg2")
+        return out, [{k: getattr(info[v], k) for k, _ in PcgInfo._fields_} for v in range(2)]
 
     def epolar_real(self, sysref, lst, mpole, polarity, thole, mu, beta, cutoff, prec=FP64):
         mp = _dev(mpole, torch.float64, self.device)

@@ -1,0 +1,130 @@
+"""The two-dipole-set solve (tk_polarize_pcg2) against the FP64 CPU oracle: the
+same iteration counts, iterates within 1e-10 of their largest entry, energies
+within 1e-10 relative; a fixed iteration count; the one-right-hand-side solve
+at pscale = 0; guesses; a set that stops before the other; empty systems."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_01211_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+S = synth.AMOEBA_SETTINGS
+_cache = {}
+
+
+@pytest.fixture(scope="module")
+def tk():
+    import torch
+    from paper_1906_01211_amd import tk as _tk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _tk.load()
+    return _tk
+
+
+@pytest.fixture(scope="module")
+def ctx(tk):
+    c = tk.Context(0)
+    yield c
+    c.close()
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def case(ctx, name):
+    w = _cache.setdefault(name, synth.make(name))
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, 7.001, plan_slot=2)
+    key = (name, "list")
+    if key not in _cache:
+        _cache[key] = O.nblist(w.xyz, w.box, 7.001)
+    rp, cp = _cache[key]
+    return w, sysr, lst, rp, cp
+
+
+def oracle2(w, rp, cp, pscale, **kw):
+    return O.polarize_pcg2(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                           S["beta"], 7.0, pscale, **kw)
+
+
+def check(mu, info, mo, io):
+    for v in range(2):
+        assert info[v]["iters"] == io[v]["iters"], (v, info[v]["iters"], io[v]["iters"])
+        assert info[v]["status"] == io[v]["status"] and info[v]["converged"] == io[v]["converged"]
+        assert np.abs(np_(mu)[v] - mo[v]).max() <= 1e-10 * np.abs(mo[v]).max(), v
+        assert rel(info[v]["epol"], io[v]["epol"]) < 1e-10, v
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+def test_pcg2_converged_fp64(ctx, name):
+    w, sysr, lst, rp, cp = case(ctx, name)
+    print(f"pcg2 {name}", flush=True)
+    mu, info = ctx.polarize_pcg2(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0, 0.5,
+                                 tol_debye=S["tol_debye"])
+    mo, io = oracle2(w, rp, cp, 0.5, tol_debye=S["tol_debye"])
+    check(mu, info, mo, io)
+    for v in range(2):
+        assert info[v]["converged"] == 1
+        assert rel(info[v]["rms_true_debye"], io[v]["rms_true_debye"]) < 1e-6
+    assert np.abs(mo[0] - mo[1]).max() > 1e-3 * np.abs(mo[0]).max()   # the sets differ
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_pcg2_fixed_iterations(ctx, k):
+    w, sysr, lst, rp, cp = case(ctx, "water216")
+    mu, info = ctx.polarize_pcg2(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0, 0.7,
+                                 tol_debye=0.0, maxiter=k)
+    mo, io = oracle2(w, rp, cp, 0.7, tol_debye=0.0, maxiter=k)
+    check(mu, info, mo, io)
+    assert all(i["iters"] == k for i in info)
+    for v in range(2):
+        assert rel(info[v]["rms_debye"], io[v]["rms_debye"]) < 1e-8
+
+
+def test_pcg2_at_pscale_zero_is_the_one_rhs_solve(ctx):
+    w, sysr, lst, rp, cp = case(ctx, "water216")
+    mu, info = ctx.polarize_pcg2(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0, 0.0)
+    m1, i1 = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0)
+    for v in range(2):
+        assert np.array_equal(np_(mu)[v], np_(m1)), v   # same sums in the same order
+        assert info[v]["iters"] == i1["iters"] and info[v]["epol"] == i1["epol"]
+
+
+def test_pcg2_one_set_stops_first(ctx):
+    # mu_p starts from its converged value (0 iterations), mu_d from alpha E_d
+    w, sysr, lst, rp, cp = case(ctx, "water216")
+    mo, io = oracle2(w, rp, cp, 0.5, tol_debye=1e-8)
+    guess = mo.copy()
+    guess[0] = 0.0   # zero guess: mu_d starts from zero (alpha = 0 rows stay zero)
+    mu, info = ctx.polarize_pcg2(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0, 0.5,
+                                 tol_debye=1e-5, mu_guess=guess)
+    mo2, io2 = oracle2(w, rp, cp, 0.5, tol_debye=1e-5, mu_guess=guess)
+    check(mu, info, mo2, io2)
+    assert info[1]["iters"] == 0 and info[0]["iters"] > 3
+
+
+def test_pcg2_arguments_and_empty(ctx, tk):
+    w, sysr, lst, rp, cp = case(ctx, "water216")
+    for bad in (-0.5, 2.0, float("nan")):
+        with pytest.raises(tk.TkError) as e:
+            ctx.polarize_pcg2(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0, bad)
+        assert e.value.status == tk.E_ARG
+    empty = ctx.system(np.zeros((0, 3)), 20.0, np.zeros(0, np.int32))
+    l0 = ctx.nblist(empty, 7.001, plan_slot=6)
+    mu, info = ctx.polarize_pcg2(empty, l0, np.zeros((0, 10)), np.zeros(0), np.zeros(0),
+                                 S["beta"], 7.0, 0.5)
+    assert mu.shape == (2, 0, 3) and all(i["converged"] == 1 for i in info)
+    # the one-rhs solve still works after the two-rhs one (shared scratch)
+    m1, i1 = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0)
+    mo1, io1 = O.polarize_pcg(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                              S["beta"], 7.0)
+    assert i1["iters"] == io1["iters"]
+    assert np.abs(np_(m1) - mo1).max() <= 1e-10 * np.abs(mo1).max()
