@@ -72,6 +72,8 @@ def lib():
         L.or_thole_l9.restype = C.c_double
         L.or_epolar_real.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp, _dp,
                                      C.c_double, C.c_double, _dp, _dp, _dp]
+        L.or_epolar2_real.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
+                                      _dp, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
         L.or_evdw.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, C.c_int, _dp, _dp,
                               C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
         L.or_eself.argtypes = [C.c_int, _dp, C.c_double]
@@ -298,6 +300,23 @@ def polarize_pcg_ewald(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, 
     if st not in (OK, E_NOCONV, E_BREAKDOWN):
         raise OracleError(st)
     return mu, {k: getattr(info, k) for k, _ in PcgInfo._fields_}
+
+
+def epolar2_real(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, mu2, beta, cutoff,
+                 pscale):
+    """Polarization forces at fixed dipole sets mu2[2,n,3] (mu_d, mu_p):
+    (energy[3], force[n,3], virial[3,3]) as epolar_real."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    energy = np.zeros(3)
+    force = np.zeros((n, 3))
+    virial = np.zeros((3, 3))
+    st = lib().or_epolar2_real(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _d(mpole),
+                               _d(polarity), _d(thole_a), _d(np.asarray(mu2).reshape(2, n, 3)),
+                               beta, cutoff, float(pscale), energy, force, virial)
+    if st:
+        raise OracleError(st)
+    return energy, force, virial
 
 
 def polarize_pcg2(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta, cutoff, pscale,

@@ -830,6 +830,81 @@ int or_epolar_real(int n, const double* xyz, double box, const int32_t* molid,
   return OR_OK;
 }
 
+/* Polarization forces with the two dipole sets of or_polarize_pcg2.  The
+ * energy -1/2 C E_d.A^-1 E_p is the stationary value, over (x, y), of
+ *   L(r, x, y) = 1/2 C [ x.A(r) y - x.E_p(r) - y.E_d(r) ],
+ * reached at x = mu_d, y = mu_p (A symmetric).  Reading: the force is
+ * -dL/dr at fixed (mu_d, mu_p): at the solved sets the gradient of E_pol,
+ * at any others that of L.  Its position-dependent part is a sum over listed
+ * pairs with r <= rc:
+ *   e_ip = 1/2 [U(mu_d,i, M_j; gp(pscale)) + U(M_i, mu_d,j; gp(pscale))]
+ *        + 1/2 [U(mu_p,i, M_j; gp(0)) + U(M_i, mu_p,j; gp(0))]
+ *   e_ii = 1/2 [U(mu_d,i, mu_p,j; gm) + U(mu_p,i, mu_d,j; gm)]
+ * with the families of or_epolar_real, gp(s) taking s on same-molecule
+ * pairs: each set meets the field that drives the other.  mu2 is
+ * [2][n][3], mu_d first.  Outputs as or_epolar_real. */
+int or_epolar2_real(int n, const double* xyz, double box, const int32_t* molid,
+                    const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                    const double* polarity, const double* thole, const double* mu2,
+                    double beta, double rc, double pscale, double* energy, double* force,
+                    double* virial) {
+  int st = or_pair_args(n, box, rc);
+  if (st) return st;
+  if (!(pscale >= 0.0 && pscale <= 1.0)) return OR_E_ARG;
+  const double* mud = mu2;
+  const double* mup = mu2 + 3 * (size_t)n;
+  double rc2 = rc * rc;
+  energy[0] = energy[1] = energy[2] = 0.0;
+  for (int k = 0; k < 9; ++k) virial[k] = 0.0;
+  for (int k = 0; k < 3 * n; ++k) force[k] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      int j = col[p];
+      double d[3], r2;
+      or_image(xyz + 3 * i, xyz + 3 * j, box, d, &r2);
+      if (!(r2 <= rc2)) continue;
+      double r = sqrt(r2), B[6], R[6], l[5];
+      or_radial(r, beta, 5, B, R);
+      or_thole(r, polarity[i], polarity[j], thole[i], thole[j], &l[1], &l[2], &l[3]);
+      l[4] = or_thole_l9(r, polarity[i], polarity[j], thole[i], thole[j]);
+      int same = molid[i] == molid[j];
+      double sd = same ? pscale : 1.0, sp = same ? 0.0 : 1.0;
+      double gd[6] = {0.0}, gq[6] = {0.0}, gm[6] = {0.0};
+      for (int k = 1; k <= 4; ++k) {
+        gd[k] = B[k] - (1.0 - sd * l[k]) * R[k];   /* field E_p, met by mu_d */
+        gq[k] = B[k] - (1.0 - sp * l[k]) * R[k];   /* field E_d, met by mu_p */
+        gm[k] = B[k] - (1.0 - l[k]) * R[k];
+      }
+      double di[10] = {0.0}, dj[10] = {0.0}, pi[10] = {0.0}, pj[10] = {0.0};
+      for (int a = 0; a < 3; ++a) {
+        di[1 + a] = mud[3 * i + a];
+        dj[1 + a] = mud[3 * j + a];
+        pi[1 + a] = mup[3 * i + a];
+        pj[1 + a] = mup[3 * j + a];
+      }
+      double e[6], de[6][3];
+      or_mpole_pair(d, di, mpole + 10 * j, gd, &e[0], de[0]);
+      or_mpole_pair(d, mpole + 10 * i, dj, gd, &e[1], de[1]);
+      or_mpole_pair(d, pi, mpole + 10 * j, gq, &e[2], de[2]);
+      or_mpole_pair(d, mpole + 10 * i, pj, gq, &e[3], de[3]);
+      or_mpole_pair(d, di, pj, gm, &e[4], de[4]);
+      or_mpole_pair(d, pi, dj, gm, &e[5], de[5]);
+      energy[1] += 0.5 * (e[0] + e[1] + e[2] + e[3]);
+      energy[2] += 0.5 * (e[4] + e[5]);
+      double g[3];
+      for (int a = 0; a < 3; ++a) {
+        g[a] = 0.5 * (de[0][a] + de[1][a] + de[2][a] + de[3][a] + de[4][a] + de[5][a]);
+        force[3 * i + a] += g[a];
+        force[3 * j + a] -= g[a];
+      }
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) virial[3 * a + b] += d[a] * g[b];
+    }
+  }
+  energy[0] = energy[1] + energy[2];
+  return OR_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* van der Waals (the Halgren 14-7 and LJ 12-6 routines of the Rel profile).
  * HAL, in the quantities of the paper's compute loop (Listing

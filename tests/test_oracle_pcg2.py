@@ -1,11 +1,14 @@
 """Pins of the oracle's two-right-hand-side solve: the field with a scaled
-same-molecule part, and the two dipole sets mu_d (field without same-molecule
-pairs) and mu_p (field with them scaled by pscale) on one operator."""
+same-molecule part, the two dipole sets mu_d (field without same-molecule
+pairs) and mu_p (field with them scaled by pscale) on one operator, and the
+polarization forces with both sets."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_1906_01211_amd import synth
+from tests.test_oracle_polar import BETA, cself, near_cutoff
+from tests.test_oracle_polar import small_water as water_skin
 
 C, DEBYE = O.constants()
 
@@ -141,3 +144,83 @@ def test_pcg2_arguments_and_limits():
                                np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros((0, 10)),
                                np.zeros(0), np.zeros(0), beta, rc, 0.5)
     assert mu.shape == (2, 0, 3) and all(i["converged"] == 1 for i in info)
+
+
+# --- polarization forces with the two sets ---------------------------------
+
+
+def lagrangian_pos(wb, rp, cp, rc, mu2, pscale, xyz):
+    """Position-dependent part of 1/2 C [x.A y - x.E_p - y.E_d] at x = mu_d,
+    y = mu_p, from the field routines."""
+    c = cself(BETA)
+    x, y = mu2
+    ed = O.efield_intra(xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity, wb.thole, BETA, rc,
+                        0.0)
+    ep = O.efield_intra(xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity, wb.thole, BETA, rc,
+                        pscale)
+    ty = O.tmatvec(xyz, wb.box, rp, cp, wb.polarity, wb.thole, BETA, rc, y)
+    p = wb.mpole[:, 1:4]
+    return 0.5 * C * (-np.sum(x * (ty - c * y)) - np.sum(x * (ep - c * p)) -
+                      np.sum(y * (ed - c * p)))
+
+
+def test_two_set_forces_reduce_to_one_set():
+    wb, rp, cp, rc = water_skin()
+    mu = np.random.default_rng(3).normal(0, 0.02, (wb.n, 3))
+    e1, f1, w1 = O.epolar_real(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity, wb.thole,
+                               mu, BETA, rc)
+    e2, f2, w2 = O.epolar2_real(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity, wb.thole,
+                                np.stack([mu, mu]), BETA, rc, 0.0)
+    assert np.allclose(e2, e1, rtol=1e-13, atol=0)
+    assert np.abs(f2 - f1).max() <= 1e-13 * np.abs(f1).max()
+    assert np.abs(w2 - w1).max() <= 1e-13 * np.abs(w1).max()
+
+
+def test_two_set_forces_are_minus_gradient_at_fixed_sets():
+    wb, rp, cp, rc = water_skin()
+    rng = np.random.default_rng(8)
+    mu2 = rng.normal(0, 0.02, (2, wb.n, 3))
+    e, F, _ = O.epolar2_real(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity, wb.thole,
+                             mu2, BETA, rc, 0.6)
+    # the pair energy is the Lagrangian's position-dependent part
+    assert e[0] == pytest.approx(lagrangian_pos(wb, rp, cp, rc, mu2, 0.6, wb.xyz), rel=1e-12)
+    atoms = [0, 1, 2, 31, 44]
+    h = 1e-5
+    assert not near_cutoff(wb, rc, atoms, 10 * h)
+    for i in atoms:
+        for a in range(3):
+            xp, xm = wb.xyz.copy(), wb.xyz.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            g = (lagrangian_pos(wb, rp, cp, rc, mu2, 0.6, xp) -
+                 lagrangian_pos(wb, rp, cp, rc, mu2, 0.6, xm)) / (2 * h)
+            assert F[i, a] == pytest.approx(-g, rel=1e-6, abs=1e-8 * np.abs(F).max())
+    assert np.allclose(F.sum(axis=0), 0.0, atol=1e-11 * np.abs(F).max())
+
+
+def test_two_set_force_is_gradient_of_epol():
+    # at the solved sets the fixed-set force is the gradient of
+    # E_pol = -1/2 C E_d.A^-1 E_p with both sets re-solved at every geometry
+    wb, rp, cp, rc = water_skin(n_w=20, box=8.6, seed=4, rc=3.6)
+
+    def solve(xyz):
+        mu2, info = O.polarize_pcg2(xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity,
+                                    wb.thole, BETA, rc, 0.5, tol_debye=1e-12, maxiter=300)
+        assert all(i["converged"] == 1 for i in info)
+        return mu2, info[0]["epol"]
+    mu2, _ = solve(wb.xyz)
+    _, F, _ = O.epolar2_real(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity, wb.thole,
+                             mu2, BETA, rc, 0.5)
+    _, F1, _ = O.epolar_real(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity, wb.thole,
+                             mu2[0], BETA, rc)
+    assert np.abs(F - F1).max() > 1e-3 * np.abs(F).max()   # not the one-set force
+    h = 1e-5
+    atoms = [0, 5, 33]
+    assert not near_cutoff(wb, rc, atoms, 10 * h)
+    for i in atoms:
+        for a in range(3):
+            xp, xm = wb.xyz.copy(), wb.xyz.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            g = (solve(xp)[1] - solve(xm)[1]) / (2 * h)
+            assert F[i, a] == pytest.approx(-g, rel=1e-6, abs=1e-8 * np.abs(F).max())
