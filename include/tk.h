@@ -267,6 +267,26 @@ tk_status tk_polarize_pcg2(tk_ctx* ctx, void* stream, const tk_system* sys, cons
                            tk_pcg_info* info);
 
 /*
+ * Polarization forces with both dipole sets of tk_polarize_pcg2 (the
+ * polarization gradient routine of section "Hotspots" for the two-set model
+ * of section "Polarizable AMOEBA force field").  E_pol = -1/2 C E_d.A^-1 E_p
+ * is the stationary value of L = 1/2 C [x.A y - x.E_p - y.E_d] at x = mu_d,
+ * y = mu_p; the force is -dL/dx at fixed sets (at the solved sets, the
+ * gradient of E_pol).  Pair energies:
+ *   e_ip = 1/2 [U(mu_d,i, M_j) + U(M_i, mu_d,j)] in the field family of E_p
+ *        + 1/2 [U(mu_p,i, M_j) + U(M_i, mu_p,j)] in the field family of E_d,
+ *   e_ii = 1/2 [U(mu_d,i, mu_p,j) + U(mu_p,i, mu_d,j)] in the mutual family,
+ * the families as tk_epolar_real's, E_p's taking pscale on same-molecule
+ * pairs.  mu2: device [2][n][3], mu_d first.  energy: device [3] (total,
+ * sum of e_ip, sum of e_ii); force: device [n][3]; virial: device [3][3].
+ * FP64.  With mu_d = mu_p and pscale = 0 this is tk_epolar_real.
+ */
+tk_status tk_epolar2_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                          const double* mpole, const double* polarity, const double* thole,
+                          const double* mu2, double ewald_beta, double cutoff, double pscale,
+                          double* energy, double* force, double* virial);
+
+/*
  * Local-frame multipoles (the rotation step that section "Hotspots" lists
  * beside the multipole routines).  frame_type: device [n] int32, 0 none,
  * 1 Z-then-X, 2 bisector (TK_FRAME_*); frame_atoms: device [n][2] int32, the

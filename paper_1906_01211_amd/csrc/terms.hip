@@ -168,6 +168,36 @@ tk_status tk_epolar_real(tk_ctx* ctx, void* stream, const tk_system* sys, const 
   return prec == TK_FP64 ? run(EpolarPh<double>{}) : run(EpolarPh<float>{});
 }
 
+tk_status tk_epolar2_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
+                          const double* mpole, const double* polarity, const double* thole,
+                          const double* mu2, double ewald_beta, double cutoff, double pscale,
+                          double* energy, double* force, double* virial) {
+  const Plan* P;
+  tk_status s = common_args(ctx, sys, list, cutoff, TK_FP64, &P);
+  if (s) return s;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !(pscale >= 0.0 && pscale <= 1.0) ||
+      !energy || !virial)
+    return TK_E_ARG;
+  if (sys->n > 0 && (!mpole || !polarity || !thole || !mu2 || !force)) return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (sys->n == 0) {
+    TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
+    TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
+    return TK_OK;
+  }
+  Epolar2Ph ph;
+  ph.xyz = sys->xyz;
+  ph.mpole = mpole;
+  ph.molid = sys->molid;
+  ph.polarity = polarity;
+  ph.thole = thole;
+  ph.mu2 = mu2;
+  ph.n2 = 3L * sys->n;
+  ph.pscale = pscale;
+  ph.g.set(sys->box, cutoff, ewald_beta);
+  return run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
+}
+
 tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
                   int form, const double* radius_or_sigma, const double* eps, double cutoff,
                   double taper_on_frac, double hal_delta, double hal_gamma, int prec,

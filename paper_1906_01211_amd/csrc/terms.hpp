@@ -1136,6 +1136,164 @@ struct EpolarPh {
   }
 };
 
+// Polarization forces with the two dipole sets (d: driven by the field
+// without same-molecule pairs, p: by the field with them scaled by pscale) at
+// fixed sets.  Each set meets the field that drives the other, and the
+// induced pair term is the sets' bilinear form:
+//   e_ip = 1/2 [U(d_i, M_j; gd) + U(M_i, d_j; gd)] + 1/2 [U(p_i, M_j; gq) + U(M_i, p_j; gq)]
+//   e_ii = 1/2 [U(d_i, p_j; gm) + U(p_i, d_j; gm)]
+// with gd = gq = B - (1 - l) R between molecules and, within one,
+// gd = B - (1 - pscale l) R, gq = B - R.  The induced-permanent terms are
+// one term of the mean set (d + p)/2, plus within a molecule d/2 in
+// pscale l R.  FP64.
+// Fields: x y z | q mu(3) Theta(6) | molid | isa | thole | d(3) | p(3)
+struct Epolar2Ph {
+  static constexpr int NF = 22, NA = 3, NS = 11;
+  static constexpr const char* kName = "epolar2";
+  static constexpr int kWaves = 2;   // waves per unit (pairs.hpp launch_units)
+  static constexpr const char* kTag = "_fp64";
+  __device__ bool skip() const { return false; }
+  __device__ void prologue(int tid, int nt) const { erfcx_stage<double>(tid, nt); }
+  const double* xyz;
+  const double* mpole;
+  const int32_t* molid;
+  const double* polarity;
+  const double* thole;
+  const double* mu2;   // [2][n][3]: d, then p
+  long n2 = 0;         // offset of the p block (3n)
+  double pscale = 0.0;
+  Geom g;
+  __device__ void set_sys(const SysDev& d, int) {
+    g.box = d.box;
+    g.inv_box = d.inv_box;
+  }
+  static constexpr int NG = 22;   // fields gathered once per call (sorted SoA)
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void stage_dyn(double*, int, int, int) const {}
+  __device__ void gather(int i, double* gg) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gg[c] = xyz[3 * i + c];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) gg[3 + k] = mpole[10 * i + k];
+    gg[13] = (double)molid[i];
+    gg[14] = inv_sqrt_alpha(polarity[i]);
+    gg[15] = thole[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      gg[16 + c] = mu2[3 * i + c];
+      gg[19 + c] = mu2[n2 + 3 * i + c];
+    }
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double* sc, long) const {
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
+    if (!(r2 <= g.rc2)) return;
+    const bool excl = LH[13 * cap + a] == LK[13 * cap + b];
+    const double rinv = rsqrt_r(r2), r = r2 * rinv;
+    double B[5], Rb[5];
+    radial<double, 4>(g, r, rinv, B, Rb, r2);
+    double l[4];
+    thole_damp9<double>(r, LH[14 * cap + a], LK[14 * cap + b], LH[15 * cap + a],
+                        LK[15 * cap + b], l);
+    const double* d = dd;
+    const auto dot = [](const double* x, const double* y) {
+      return x[0] * y[0] + x[1] * y[1] + x[2] * y[2];
+    };
+    const auto fld = [&](const double* L, int f, int s, double* v) {
+      v[0] = L[f * cap + s];
+      v[1] = L[(f + 1) * cap + s];
+      v[2] = L[(f + 2) * cap + s];
+    };
+    const double qi = LH[3 * cap + a], qj = LK[3 * cap + b];
+    double ui[3], uj[3], ti[6], tj[6];
+    fld(LH, 4, a, ui);
+    fld(LK, 4, b, uj);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      ti[k] = LH[(7 + k) * cap + a];
+      tj[k] = LK[(7 + k) * cap + b];
+    }
+    const auto tmul = [](const double* t, const double* x, double* y) {
+      y[0] = t[0] * x[0] + t[1] * x[1] + t[2] * x[2];
+      y[1] = t[1] * x[0] + t[3] * x[1] + t[4] * x[2];
+      y[2] = t[2] * x[0] + t[4] * x[1] + t[5] * x[2];
+    };
+    double vi[3], vj[3];
+    tmul(ti, d, vi);
+    tmul(tj, d, vj);
+    const double di = dot(ui, d), dj = dot(uj, d), Qi = dot(d, vi), Qj = dot(d, vj);
+    double de[3] = {0.0, 0.0, 0.0}, eip = 0.0, eii = 0.0;
+    // induced-permanent term of dipoles (pi, pj) in the family gf[1..4]
+    const auto ip = [&](const double* pi, const double* pj, const double* gf) {
+      double tipj[3], tjpi[3];
+      tmul(ti, pj, tipj);
+      tmul(tj, pi, tjpi);
+      const double ei = dot(pi, d), ej = dot(pj, d);
+      const double c1 = qj * ei - qi * ej + dot(pi, uj) + dot(ui, pj);
+      const double c2 = -(ei * dj + di * ej) + 2.0 * (dot(pj, vi) - dot(pi, vj));
+      const double c3 = ei * Qj - ej * Qi;
+      const double sp = c1 * gf[2] + c2 * gf[3] + c3 * gf[4];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double dc1 = qj * pi[c] - qi * pj[c];
+        const double dc2 =
+            -(dj * pi[c] + ei * uj[c] + ej * ui[c] + di * pj[c]) + 2.0 * (tipj[c] - tjpi[c]);
+        const double dc3 = Qj * pi[c] + 2.0 * ei * vj[c] - Qi * pj[c] - 2.0 * ej * vi[c];
+        de[c] += dc1 * gf[1] + dc2 * gf[2] + dc3 * gf[3] - sp * d[c];
+      }
+      eip += c1 * gf[1] + c2 * gf[2] + c3 * gf[3];
+    };
+    double xdi[3], xdj[3], xpi[3], xpj[3];
+    fld(LH, 16, a, xdi);
+    fld(LK, 16, b, xdj);
+    fld(LH, 19, a, xpi);
+    fld(LK, 19, b, xpj);
+    // induced-induced: 1/2 [U(d_i, p_j) + U(p_i, d_j)], U(x_i, y_j) = x.y gm1 - (x.d)(y.d) gm2
+    double gm[4];
+#pragma unroll
+    for (int n = 1; n <= 3; ++n) gm[n] = B[n] - (Rb[n] - l[n - 1] * Rb[n]);
+    const auto bil = [&](const double* x, const double* y) {
+      const double ex = dot(x, d), ey = dot(y, d), xy = dot(x, y);
+      const double sm = xy * gm[2] - ex * ey * gm[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) de[c] += 0.5 * (-(ey * x[c] + ex * y[c]) * gm[2] - sm * d[c]);
+      eii += 0.5 * (xy * gm[1] - ex * ey * gm[2]);
+    };
+    bil(xdi, xpj);
+    bil(xpi, xdj);
+    // pass 0: the mean set (d + p)/2 in gp (between molecules) or B - R
+    // (within one); pass 1, within a molecule: d/2 in pscale l R, which
+    // makes d's family B - (1 - pscale l) R
+    const int passes = excl && pscale != 0.0 ? 2 : 1;
+#pragma unroll 1
+    for (int k = 0; k < passes; ++k) {
+      double gf[5], mi[3], mj[3];
+#pragma unroll
+      for (int n = 1; n <= 4; ++n)
+        gf[n] = k == 1 ? pscale * l[n - 1] * Rb[n]
+                       : excl ? B[n] - Rb[n] : B[n] - (Rb[n] - l[n - 1] * Rb[n]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        mi[c] = 0.5 * (k == 1 ? xdi[c] : xdi[c] + xpi[c]);
+        mj[c] = 0.5 * (k == 1 ? xdj[c] : xdj[c] + xpj[c]);
+      }
+      ip(mi, mj, gf);
+    }
+    sc[0] += kCoulomb * eip;
+    sc[1] += kCoulomb * eii;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double f = kCoulomb * de[c];
+      lds_add(&AH[c * cap + a], f);
+      lds_add(&AK[c * cap + b], -f);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) sc[2 + 3 * c + q] += dd[c] * (kCoulomb * de[q]);
+    }
+  }
+};
+
 // Epilogues of the per-atom reduction.
 struct EpiForce {   // the sums are the atom's force; caller order
   double* force;

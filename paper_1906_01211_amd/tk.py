@@ -108,6 +108,8 @@ _SIGS = {
                               _d, _i32, _i32, _d, _i32, _vp, _vp, C.POINTER(PcgInfo)],
     "tk_polarize_pcg2": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
                          _d, _d, _i32, _vp, _vp, C.POINTER(PcgInfo * 2)],
+    "tk_epolar2_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
+                        _d, _d, _vp, _vp, _vp],
     "tk_rotate_mpole": [_vp, _vp, C.POINTER(System), _vp, _vp, _vp, _vp],
     "tk_empole_frames": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
                          _vp, _vp, _vp],
@@ -374,6 +376,21 @@ class Context:
         _check(load().tk_epolar_real(self._h, _stream(self.device), C.byref(sysref.c),
                                      C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), _ptr(m), beta,
                                      cutoff, prec, _ptr(e), _ptr(f), _ptr(w)), "tk_epolar_real")
+        return e, f, w
+
+    def epolar2_real(self, sysref, lst, mpole, polarity, thole, mu2, beta, cutoff, pscale):
+        """Polarization forces with both dipole sets mu2[2,n,3] (mu_d first)."""
+        mp = _dev(mpole, torch.float64, self.device)
+        pol = _dev(polarity, torch.float64, self.device)
+        th = _dev(thole, torch.float64, self.device)
+        m = _dev(mu2, torch.float64, self.device)
+        e = torch.empty(3, dtype=torch.float64, device=self.device)
+        f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
+        _check(load().tk_epolar2_real(self._h, _stream(self.device), C.byref(sysref.c),
+                                      C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), _ptr(m), beta,
+                                      cutoff, float(pscale), _ptr(e), _ptr(f), _ptr(w)),
+               "tk_epolar2_real")
         return e, f, w
 
     def pme_mpole(self, sysref, mpole, beta, grid, order=5, want_field=True):

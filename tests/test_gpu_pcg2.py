@@ -1,7 +1,9 @@
 """The two-dipole-set solve (tk_polarize_pcg2) against the FP64 CPU oracle: the
 same iteration counts, iterates within 1e-10 of their largest entry, energies
 within 1e-10 relative; a fixed iteration count; the one-right-hand-side solve
-at pscale = 0; guesses; a set that stops before the other; empty systems."""
+at pscale = 0; guesses; a set that stops before the other; empty systems; and
+the polarization forces with both sets (tk_epolar2_real), energies within 1e-10
+relative and forces within 1e-8 of their RMS."""
 import numpy as np
 import pytest
 
@@ -128,3 +130,43 @@ def test_pcg2_arguments_and_empty(ctx, tk):
                               S["beta"], 7.0)
     assert i1["iters"] == io1["iters"]
     assert np.abs(np_(m1) - mo1).max() <= 1e-10 * np.abs(mo1).max()
+
+
+def fmax_rel(got, ref):
+    return np.abs(np.asarray(got) - ref).max() / np.sqrt(np.mean(ref ** 2))
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+def test_epolar2_fp64(ctx, name):
+    w, sysr, lst, rp, cp = case(ctx, name)
+    print(f"epolar2 {name}", flush=True)
+    mu2 = np.random.default_rng(11).normal(0, 0.03, (2, w.n, 3))
+    e, f, vir = ctx.epolar2_real(sysr, lst, w.mpole, w.polarity, w.thole, mu2, S["beta"], 7.0, 0.5)
+    eo, fo, vo = O.epolar2_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, mu2,
+                                S["beta"], 7.0, 0.5)
+    e = np_(e)
+    for k in range(3):
+        assert rel(e[k], eo[k]) < 1e-10, (k, e[k], eo[k])
+    assert fmax_rel(np_(f), fo) < 1e-8
+    assert np.abs(np_(vir) - vo).max() <= 1e-10 * np.abs(vo).max()
+
+
+def test_epolar2_at_solved_sets_and_one_set_limit(ctx, tk):
+    w, sysr, lst, rp, cp = case(ctx, "water216")
+    mu2, _ = ctx.polarize_pcg2(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0, 0.7)
+    m = np_(mu2)
+    e, f, _ = ctx.epolar2_real(sysr, lst, w.mpole, w.polarity, w.thole, mu2, S["beta"], 7.0, 0.7)
+    eo, fo, _ = O.epolar2_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, m,
+                               S["beta"], 7.0, 0.7)
+    assert rel(np_(e)[0], eo[0]) < 1e-10 and fmax_rel(np_(f), fo) < 1e-8
+    # equal sets, pscale 0: the one-set forces
+    mu = m[0]
+    e2, f2, v2 = ctx.epolar2_real(sysr, lst, w.mpole, w.polarity, w.thole, np.stack([mu, mu]),
+                                  S["beta"], 7.0, 0.0)
+    e1, f1, v1 = ctx.epolar_real(sysr, lst, w.mpole, w.polarity, w.thole, mu, S["beta"], 7.0)
+    assert np.allclose(np_(e2), np_(e1), rtol=1e-12, atol=0)
+    assert fmax_rel(np_(f2), np_(f1)) < 1e-12
+    assert np.abs(np_(v2) - np_(v1)).max() <= 1e-12 * np.abs(np_(v1)).max()
+    with pytest.raises(tk.TkError):
+        ctx.epolar2_real(sysr, lst, w.mpole, w.polarity, w.thole, np.stack([mu, mu]), S["beta"],
+                         7.0, 1.5)
