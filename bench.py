@@ -110,6 +110,7 @@ class AmoebaStep:
         self.eps = torch.as_tensor(w.vdw_eps, device=dev)
         self.side = torch.cuda.Stream(device=dev)   # default priority
         self.info = None
+        self.out = None   # the last step's outputs (device tensors), for the accuracy check
 
     def __call__(self):
         import torch
@@ -123,13 +124,14 @@ class AmoebaStep:
         self.side.wait_stream(main)
         l7, l9 = c.nblists(self.sys, [s["rc_ewald"] + s["skin"], s["rc_vdw"] + s["skin"]],
                            [0, 1], streams=[main, self.side])
-        c.empole_real(self.sys, l7, self.mpole, s["beta"], s["rc_ewald"], prec=p)
+        em = c.empole_real(self.sys, l7, self.mpole, s["beta"], s["rc_ewald"], prec=p)
         main.wait_stream(self.side)   # the 9 A list is complete before the solver starts
-        _, self.info = c.polarize_pcg(self.sys, l7, self.mpole, self.pol, self.thole, s["beta"],
-                                      s["rc_ewald"], tol_debye=s["tol_debye"],
-                                      maxiter=s["maxiter"], prec=p)
-        c.evdw(self.sys, l9, self.tk.VDW_HAL, self.rad, self.eps, s["rc_vdw"],
-               s["taper_frac"], s["dhal"], s["ghal"], prec=p)
+        mu, self.info = c.polarize_pcg(self.sys, l7, self.mpole, self.pol, self.thole, s["beta"],
+                                       s["rc_ewald"], tol_debye=s["tol_debye"],
+                                       maxiter=s["maxiter"], prec=p)
+        ev = c.evdw(self.sys, l9, self.tk.VDW_HAL, self.rad, self.eps, s["rc_vdw"],
+                    s["taper_frac"], s["dhal"], s["ghal"], prec=p)
+        self.out = (em, mu, ev)
         return l7, l9
 
     def pair_counts(self):
@@ -162,15 +164,51 @@ def cpu_baseline(w, n7, n9):
     t0 = time.perf_counter()
     rp7, cp7 = O.nblist(w.xyz, w.box, s["rc_ewald"] + s["skin"])
     rp9, cp9 = O.nblist(w.xyz, w.box, s["rc_vdw"] + s["skin"])
-    O.empole_real(w.xyz, w.box, w.molid, rp7, cp7, w.mpole, s["beta"], s["rc_ewald"])
-    _, info = O.polarize_pcg(w.xyz, w.box, w.molid, rp7, cp7, w.mpole, w.polarity, w.thole,
-                             s["beta"], s["rc_ewald"], tol_debye=s["tol_debye"])
-    O.evdw(w.xyz, w.box, w.molid, rp9, cp9, 0, w.vdw_rad, w.vdw_eps, s["rc_vdw"])
+    em = O.empole_real(w.xyz, w.box, w.molid, rp7, cp7, w.mpole, s["beta"], s["rc_ewald"])
+    mu, info = O.polarize_pcg(w.xyz, w.box, w.molid, rp7, cp7, w.mpole, w.polarity, w.thole,
+                              s["beta"], s["rc_ewald"], tol_debye=s["tol_debye"])
+    ev = O.evdw(w.xyz, w.box, w.molid, rp9, cp9, 0, w.vdw_rad, w.vdw_eps, s["rc_vdw"])
     dt = time.perf_counter() - t0
     pairs = n7 * (2 + info["iters"] + 2) + n9
-    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": 1, "kind": "oracle",
+    base = {"value": pairs / dt, "unit": "pair-interactions/s", "cores": 1, "kind": "oracle",
             "sample": f"one full FP64 step of the 23,559-atom water box (serial C oracle, "
                       f"{dt:.2f} s, {info['iters']} PCG iterations)", "seconds": dt}
+    return base, (em, (mu, info), ev)
+
+
+def copy_rate(ctx, mib=1024):
+    """Achievable HBM rate: a device-to-device copy of `mib` MiB (bytes read +
+    written per second, GB/s), best of 5."""
+    import torch
+    src = torch.ones(mib << 17, dtype=torch.float64, device=ctx.device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = 0.0
+    for _ in range(5):
+        t0 = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        best = max(best, 2 * src.numel() * 8 / (time.perf_counter() - t0) / 1e9)
+    del src, dst
+    return round(best, 1)
+
+
+def accuracy(step, ref):
+    """The timed step's outputs against the oracle's on the same inputs."""
+    (e_g, f_g, _), mu_g, (ev_g, fv_g, _) = step.out
+    (e_o, f_o, _), (mu_o, info_o), (ev_o, fv_o, _) = ref
+    debye = 4.80320
+
+    def frel(g, o):
+        return float(np.abs(g.cpu().numpy() - o).max() / np.sqrt(np.mean(o ** 2)))
+    return {"empole_energy_rel": float(abs(e_g.cpu().numpy()[0] - e_o[0]) / abs(e_o[0])),
+            "empole_force_max_over_rms": frel(f_g, f_o),
+            "dipole_max_debye": float(debye * np.abs(mu_g.cpu().numpy() - mu_o).max()),
+            "epol_rel": float(abs(step.info["epol"] - info_o["epol"]) / abs(info_o["epol"])),
+            "pcg_iters_gpu_oracle": [step.info["iters"], info_o["iters"]],
+            "hal_energy_rel": float(abs(float(ev_g.cpu()) - ev_o) / abs(ev_o)),
+            "hal_force_max_over_rms": frel(fv_g, fv_o)}
 
 
 def main():
@@ -207,6 +245,15 @@ def main():
     timed(step, max(2, a.steps // 4), 0)
     prof = ctx.profile_read()
     ctx.profile(False)
+    # per-step wall times of a further pass (each step already synchronises
+    # inside; one more synchronisation closes it)
+    per = []
+    for _ in range(max(20, a.steps)):
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - t0) * 1e3)
+    q10, q50, q90 = np.percentile(per, [10, 50, 90])
     iters = step.info["iters"]
     mv_calls = iters + 2          # initial residual + iterations + final FP64 residual
     pairs = n7 * (1 + 1 + mv_calls) + n9   # empole + efield + mat-vecs + HAL
@@ -242,6 +289,7 @@ def main():
                    "atoms": w.n, "pairs_7A": n7, "pairs_9A_hal": n9,
                    "pcg_iters": iters, "prec": a.prec},
         "solves_per_s": 1e3 / ms,
+        "step_ms_p10_p50_p90": [round(q10, 4), round(q50, 4), round(q90, 4)],
         "kernel_ms_per_step": {k: round(v["ms"] / max(2, a.steps // 4), 5) for k, v in prof.items()},
         "roofline": roof,
     }
@@ -249,8 +297,13 @@ def main():
         out["extras"] = extras(ctx, tk, w, a, prec, n7)
     if not a.no_serving:
         out["serving"] = serving(tk, a.serving_requests)
+    if roof is not None:
+        roof["achievable_copy_gbs"] = copy_rate(ctx)
+        roof["frac_of_achievable"] = round(roof["achieved"] / roof["achievable_copy_gbs"], 4)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, n7, n9)
+        out["cpu_baseline"], ref = cpu_baseline(w, n7, n9)
+        if prec == tk.FP64:   # the last timed-pass step's outputs
+            out["accuracy_vs_oracle"] = accuracy(step, ref)
     ctx.close()
     print(json.dumps(out))
 
