@@ -311,6 +311,36 @@ def test_echarge_fp64_small(ctx):
     assert fmax_rel(np_(f3), fo3) < 1e-8
 
 
+def test_charge_lj_full_size(ctx, tk):
+    # the 96,000-atom charge + LJ box at its full size, as bench.py runs it:
+    # the 12 A list bit-exact, FP64 within 1e-10 / 1e-8, the mixed form within
+    # 1e-6 relative in energy and 1e-4 kcal/mol/A RMS in force
+    print("charge_lj water32000 full size", flush=True)
+    w = _cache.setdefault("water32000_charge_lj", synth.make("water32000_charge_lj"))
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, 12.001, plan_slot=4)
+    rp, cp = O.nblist(w.xyz, w.box, 12.001)
+    assert_list_equal(lst, rp, cp)
+    eo, fo, vo = O.echarge_real(w.xyz, w.box, w.molid, rp, cp, w.charges, 0.34, 12.0)
+    elj, flj, _ = O.evdw(w.xyz, w.box, w.molid, rp, cp, 1, w.vdw_rad, w.vdw_eps, 12.0)
+    e, f, vir = ctx.echarge_real(sysr, lst, w.charges, 0.34, 12.0)
+    for k in range(3):
+        assert rel(np_(e)[k], eo[k]) < 1e-10, k
+    assert fmax_rel(np_(f), fo) < 1e-8
+    assert np.abs(np_(vir) - vo).max() < 1e-10 * np.abs(vo).max()
+    e2, f2, _ = ctx.evdw(sysr, lst, 1, w.vdw_rad, w.vdw_eps, 12.0)
+    assert rel(float(e2), elj) < 1e-10
+    assert fmax_rel(np_(f2), flj) < 1e-8
+    rms = lambda a, b: float(np.sqrt(np.mean(np.sum((a - b) ** 2, axis=1))))
+    em, fm, _ = ctx.echarge_real(sysr, lst, w.charges, 0.34, 12.0, prec=tk.MIXED)
+    for k in range(3):
+        assert rel(np_(em)[k], eo[k]) < 1e-6, k
+    assert rms(np_(fm), fo) <= 1e-4
+    em2, fm2, _ = ctx.evdw(sysr, lst, 1, w.vdw_rad, w.vdw_eps, 12.0, prec=tk.MIXED)
+    assert rel(float(em2), elj) < 1e-6
+    assert rms(np_(fm2), flj) <= 1e-4
+
+
 def test_deterministic_repeat(ctx):
     w, sysr, lst, rp, cp = setup_amoeba(ctx, "water7853", 7.001, 2)
     e1, f1, _ = ctx.empole_real(sysr, lst, w.mpole, S["beta"], 7.0)
