@@ -412,6 +412,7 @@ def pme_mpole(xyz, box, mpole, beta, K, order=5):
 
 
 FRAME_NONE, FRAME_Z_THEN_X, FRAME_BISECTOR = 0, 1, 2
+FRAME_Z_ONLY, FRAME_Z_BISECTOR, FRAME_3FOLD = 3, 4, 5
 
 
 def rotate_mpole(xyz, box, ftype, fatoms, local):

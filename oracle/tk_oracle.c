@@ -1325,55 +1325,61 @@ int or_pme_mpole(int n, const double* xyz, double box, const double* mpole, doub
 /* ------------------------------------------------------------------------ */
 /* Local-frame multipoles (the rotation and torque steps that section
  * "Hotspots" lists beside the multipole routines).  Reading (the paper gives
- * no frame definitions): the usual AMOEBA frames, with d_z = r_zatom - r_i and
- * d_x = r_xatom - r_i (minimum image):
- *   type 0 (none):      R = I;
- *   type 1 (Z-then-X):  z = d_z/|d_z|, x = unit(d_x - (d_x.z) z);
- *   type 2 (bisector):  z = unit(d_z/|d_z| + d_x/|d_x|), x = unit(u_x - (u_x.z) z),
- *                       u_x = d_x/|d_x|;
+ * no frame definitions): the AMOEBA frames, with d_k = r_katom - r_i and
+ * u_k = d_k/|d_k| for the z-, x- and y-atoms (minimum image).  Every type
+ * takes z as below and a vector a, then x = unit(a - (a.z) z):
+ *   type 0 (none):        R = I;
+ *   type 1 (Z-then-X):    z = u_z,                 a = d_x;
+ *   type 2 (bisector):    z = unit(u_z + u_x),     a = u_x;
+ *   type 3 (Z-only):      z = u_z,                 a = the global x axis, or the
+ *                         global y axis when |z_x| > 0.866 (z within 30 degrees
+ *                         of +-x);
+ *   type 4 (Z-bisector):  z = u_z,                 a = u_x + u_y;
+ *   type 5 (3-fold):      z = unit(u_z + u_x + u_y), a = u_x;
  * y = z cross x.  With R = [x y z] (columns), the lab-frame multipoles are
  *   q = q_loc, mu = R mu_loc, Theta = R Theta_loc R^T.
- * Values are carried with their derivatives with respect to the nine
- * coordinates of (r_i, r_zatom, r_xatom) (forward-mode dual numbers), so the
- * rotated multipoles come with their exact Jacobian. */
+ * Values are carried with their derivatives with respect to the twelve
+ * coordinates of (r_i, r_zatom, r_xatom, r_yatom) (forward-mode dual
+ * numbers), so the rotated multipoles come with their exact Jacobian. */
+#define OR_ND 12
 typedef struct {
-  double v, d[9];
+  double v, d[OR_ND];
 } or_dual;
 
 static or_dual od_const(double v) {
   or_dual r;
   r.v = v;
-  for (int k = 0; k < 9; ++k) r.d[k] = 0.0;
+  for (int k = 0; k < OR_ND; ++k) r.d[k] = 0.0;
   return r;
 }
 static or_dual od_add(or_dual a, or_dual b) {
   or_dual r;
   r.v = a.v + b.v;
-  for (int k = 0; k < 9; ++k) r.d[k] = a.d[k] + b.d[k];
+  for (int k = 0; k < OR_ND; ++k) r.d[k] = a.d[k] + b.d[k];
   return r;
 }
 static or_dual od_sub(or_dual a, or_dual b) {
   or_dual r;
   r.v = a.v - b.v;
-  for (int k = 0; k < 9; ++k) r.d[k] = a.d[k] - b.d[k];
+  for (int k = 0; k < OR_ND; ++k) r.d[k] = a.d[k] - b.d[k];
   return r;
 }
 static or_dual od_mul(or_dual a, or_dual b) {
   or_dual r;
   r.v = a.v * b.v;
-  for (int k = 0; k < 9; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  for (int k = 0; k < OR_ND; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
   return r;
 }
 static or_dual od_div(or_dual a, or_dual b) {
   or_dual r;
   r.v = a.v / b.v;
-  for (int k = 0; k < 9; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  for (int k = 0; k < OR_ND; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
   return r;
 }
 static or_dual od_sqrt(or_dual a) {
   or_dual r;
   r.v = sqrt(a.v);
-  for (int k = 0; k < 9; ++k) r.d[k] = a.d[k] / (2.0 * r.v);
+  for (int k = 0; k < OR_ND; ++k) r.d[k] = a.d[k] / (2.0 * r.v);
   return r;
 }
 static or_dual od_dot3(const or_dual* a, const or_dual* b) {
@@ -1384,35 +1390,54 @@ static void od_unit3(const or_dual* a, or_dual* out) {
   for (int c = 0; c < 3; ++c) out[c] = od_div(a[c], nrm);
 }
 
-/* Frame vectors of site i (as duals over r_i, r_zatom, r_xatom), minimum image. */
+/* d_k = r_katom - r_i (minimum image) as duals; slot s (1 z, 2 x, 3 y) of the partials. */
+static void or_frame_vec(const double* xyz, double box, int i, int k, int slot, or_dual* d) {
+  for (int c = 0; c < 3; ++c) {
+    double t = xyz[3 * k + c] - xyz[3 * i + c];
+    d[c] = od_const(t - box * rint(t / box));
+    d[c].d[c] = -1.0;              /* d/dr_i */
+    d[c].d[3 * slot + c] = 1.0;    /* d/dr_katom */
+  }
+}
+
+/* Frame vectors of site i (as duals over r_i, r_zatom, r_xatom, r_yatom). */
 static void or_frame_axes(const double* xyz, double box, int i, int type, int iz, int ix,
-                          or_dual ax[3][3]) {
+                          int iy, or_dual ax[3][3]) {
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) ax[a][b] = od_const(a == b ? 1.0 : 0.0);
   if (type == 0) return;
-  or_dual dz[3], dx[3];
-  for (int c = 0; c < 3; ++c) {
-    double tz = xyz[3 * iz + c] - xyz[3 * i + c], tx = xyz[3 * ix + c] - xyz[3 * i + c];
-    dz[c] = od_const(tz - box * rint(tz / box));
-    dx[c] = od_const(tx - box * rint(tx / box));
-    dz[c].d[c] = -1.0;        /* d/dr_i */
-    dz[c].d[3 + c] = 1.0;     /* d/dr_zatom */
-    dx[c].d[c] = -1.0;
-    dx[c].d[6 + c] = 1.0;     /* d/dr_xatom */
-  }
-  or_dual z[3], x[3], ux[3];
-  if (type == 1) {
-    od_unit3(dz, z);
-    for (int c = 0; c < 3; ++c) ux[c] = dx[c];
-  } else {
-    or_dual uz[3], s[3];
-    od_unit3(dz, uz);
+  or_dual dz[3], uz[3], dx[3], ux[3], dy[3], uy[3], z[3], a[3], x[3];
+  or_frame_vec(xyz, box, i, iz, 1, dz);
+  od_unit3(dz, uz);
+  if (type != 3) {
+    or_frame_vec(xyz, box, i, ix, 2, dx);
     od_unit3(dx, ux);
+  }
+  if (type == 4 || type == 5) {
+    or_frame_vec(xyz, box, i, iy, 3, dy);
+    od_unit3(dy, uy);
+  }
+  if (type == 2) {
+    or_dual s[3];
     for (int c = 0; c < 3; ++c) s[c] = od_add(uz[c], ux[c]);
     od_unit3(s, z);
+  } else if (type == 5) {
+    or_dual s[3];
+    for (int c = 0; c < 3; ++c) s[c] = od_add(od_add(uz[c], ux[c]), uy[c]);
+    od_unit3(s, z);
+  } else {
+    for (int c = 0; c < 3; ++c) z[c] = uz[c];
   }
-  or_dual p = od_dot3(ux, z), w[3];
-  for (int c = 0; c < 3; ++c) w[c] = od_sub(ux[c], od_mul(p, z[c]));
+  for (int c = 0; c < 3; ++c) {
+    if (type == 1) a[c] = dx[c];
+    else if (type == 3) {
+      int near_x = fabs(z[0].v) > 0.866;
+      a[c] = od_const(c == (near_x ? 1 : 0) ? 1.0 : 0.0);
+    } else if (type == 4) a[c] = od_add(ux[c], uy[c]);
+    else a[c] = ux[c];
+  }
+  or_dual p = od_dot3(a, z), w[3];
+  for (int c = 0; c < 3; ++c) w[c] = od_sub(a[c], od_mul(p, z[c]));
   od_unit3(w, x);
   or_dual y[3];
   y[0] = od_sub(od_mul(z[1], x[2]), od_mul(z[2], x[1]));
@@ -1426,10 +1451,10 @@ static void or_frame_axes(const double* xyz, double box, int i, int type, int iz
 }
 
 /* Lab-frame multipoles of site i as duals (10 components, stored layout). */
-static void or_rotate_site(const double* xyz, double box, int i, int type, int iz, int ix,
+static void or_rotate_site(const double* xyz, double box, int i, int type, const int32_t* fa,
                            const double* loc, or_dual out[10]) {
   or_dual R[3][3];
-  or_frame_axes(xyz, box, i, type, iz, ix, R);
+  or_frame_axes(xyz, box, i, type, fa[0], fa[1], fa[2], R);
   double tl[3][3];
   tl[0][0] = loc[4]; tl[0][1] = tl[1][0] = loc[5]; tl[0][2] = tl[2][0] = loc[6];
   tl[1][1] = loc[7]; tl[1][2] = tl[2][1] = loc[8]; tl[2][2] = loc[9];
@@ -1449,13 +1474,20 @@ static void or_rotate_site(const double* xyz, double box, int i, int type, int i
   }
 }
 
+/* Frame atoms per type: z (types 1-5), x (1, 2, 4, 5), y (4, 5); each in
+ * [0, n), none the site itself, all distinct. */
+static int or_frame_natoms(int t) { return t == 0 ? 0 : t == 3 ? 1 : t <= 2 ? 2 : 3; }
+
 static int or_frames_args(int n, const int32_t* ftype, const int32_t* fatoms) {
   for (int i = 0; i < n; ++i) {
     int t = ftype[i];
-    if (t < 0 || t > 2) return OR_E_ARG;
-    if (t > 0) {
-      int iz = fatoms[2 * i], ix = fatoms[2 * i + 1];
-      if (iz < 0 || iz >= n || ix < 0 || ix >= n || iz == i || ix == i || iz == ix) return OR_E_ARG;
+    if (t < 0 || t > 5) return OR_E_ARG;
+    int m = or_frame_natoms(t);
+    for (int k = 0; k < m; ++k) {
+      int a = fatoms[3 * i + k];
+      if (a < 0 || a >= n || a == i) return OR_E_ARG;
+      for (int l = 0; l < k; ++l)
+        if (fatoms[3 * i + l] == a) return OR_E_ARG;
     }
   }
   return OR_OK;
@@ -1466,8 +1498,9 @@ static void or_frames_chain(int n, const int32_t* ftype, const int32_t* fatoms, 
                             const double* G, double* force) {
   for (int i = 0; i < n; ++i) {
     if (ftype[i] == 0) continue;
-    int who[3] = {i, fatoms[2 * i], fatoms[2 * i + 1]};
-    for (int s = 0; s < 3; ++s)
+    int m = or_frame_natoms(ftype[i]);
+    int who[4] = {i, fatoms[3 * i], fatoms[3 * i + 1], fatoms[3 * i + 2]};
+    for (int s = 0; s <= m; ++s)
       for (int a = 0; a < 3; ++a) {
         double g = 0.0;
         for (int c = 0; c < 10; ++c) g += G[10 * i + c] * M[10 * i + c].d[3 * s + a];
@@ -1483,7 +1516,7 @@ int or_rotate_mpole(int n, const double* xyz, double box, const int32_t* ftype,
   if (st) return st;
   for (int i = 0; i < n; ++i) {
     or_dual m[10];
-    or_rotate_site(xyz, box, i, ftype[i], fatoms[2 * i], fatoms[2 * i + 1], local + 10 * i, m);
+    or_rotate_site(xyz, box, i, ftype[i], fatoms + 3 * i, local + 10 * i, m);
     for (int k = 0; k < 10; ++k) global[10 * i + k] = m[k].v;
   }
   return OR_OK;
@@ -1509,7 +1542,7 @@ int or_empole_frames(int n, const double* xyz, double box, const int32_t* molid,
   double* G = (double*)calloc(10 * nn, sizeof(double));
   double vir[9];
   for (int i = 0; i < n; ++i) {
-    or_rotate_site(xyz, box, i, ftype[i], fatoms[2 * i], fatoms[2 * i + 1], local + 10 * i,
+    or_rotate_site(xyz, box, i, ftype[i], fatoms + 3 * i, local + 10 * i,
                    M + 10 * i);
     for (int k = 0; k < 10; ++k) Mg[10 * i + k] = M[10 * i + k].v;
   }
@@ -1561,7 +1594,7 @@ int or_epolar_frames(int n, const double* xyz, double box, const int32_t* molid,
   double* G = (double*)calloc(10 * nn, sizeof(double));
   double vir[9];
   for (int i = 0; i < n; ++i) {
-    or_rotate_site(xyz, box, i, ftype[i], fatoms[2 * i], fatoms[2 * i + 1], local + 10 * i,
+    or_rotate_site(xyz, box, i, ftype[i], fatoms + 3 * i, local + 10 * i,
                    M + 10 * i);
     for (int k = 0; k < 10; ++k) Mg[10 * i + k] = M[10 * i + k].v;
   }

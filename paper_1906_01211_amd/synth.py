@@ -144,21 +144,48 @@ def charge_lj_water_box(n_w: int, box: float, seed: int) -> WaterBox:
 
 
 FRAME_NONE, FRAME_Z_THEN_X, FRAME_BISECTOR = 0, 1, 2
+FRAME_Z_ONLY, FRAME_Z_BISECTOR, FRAME_3FOLD = 3, 4, 5
 
 
 def water_frames(n_w: int):
     """Local-frame topology of n_w waters (atoms O, H1, H2 per molecule): O
     bisector (z atom H1, x atom H2); each H Z-then-X (z atom O, x atom the
-    other H).  Returns (frame_type[n] int32, frame_atoms[n, 2] int32)."""
+    other H).  Returns (frame_type[n] int32, frame_atoms[n, 3] int32: z, x, y
+    atoms, -1 where a type takes none)."""
     n = 3 * n_w
     base = 3 * np.arange(n_w)
     ftype = np.zeros(n, np.int32)
-    fat = np.zeros((n, 2), np.int32)
+    fat = np.full((n, 3), -1, np.int32)
     ftype[base] = FRAME_BISECTOR
     fat[base, 0], fat[base, 1] = base + 1, base + 2
     for h, other in ((1, 2), (2, 1)):
         ftype[base + h] = FRAME_Z_THEN_X
         fat[base + h, 0], fat[base + h, 1] = base, base + other
+    return ftype, fat
+
+
+def mixed_frames(n_w: int):
+    """Every frame type on n_w >= 2 waters (a test topology, not a water
+    model): the O of molecule k is bisector, Z-bisector or 3-fold (k mod 3;
+    z atom H1, x atom H2, y atom the O of molecule k + 1); its H1 is
+    Z-then-X or Z-only and its H2 the other (k mod 2; z atom O, x atom the
+    other H).  Returns (frame_type[n], frame_atoms[n, 3]) as water_frames."""
+    n = 3 * n_w
+    ftype = np.zeros(n, np.int32)
+    fat = np.full((n, 3), -1, np.int32)
+    for k in range(n_w):
+        o, h1, h2 = 3 * k, 3 * k + 1, 3 * k + 2
+        ftype[o] = (FRAME_BISECTOR, FRAME_Z_BISECTOR, FRAME_3FOLD)[k % 3]
+        fat[o, :2] = h1, h2
+        if ftype[o] != FRAME_BISECTOR:
+            fat[o, 2] = 3 * ((k + 1) % n_w)
+        for h, other, t in ((h1, h2, k % 2), (h2, h1, 1 - k % 2)):
+            fat[h, 0] = o
+            if t == 0:
+                ftype[h] = FRAME_Z_THEN_X
+                fat[h, 1] = other
+            else:
+                ftype[h] = FRAME_Z_ONLY
     return ftype, fat
 
 

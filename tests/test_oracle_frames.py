@@ -10,11 +10,14 @@ from paper_1906_01211_amd import synth
 BETA = 0.5446
 
 
-def waters(n_w=27, box=9.4, seed=2):
+def waters(n_w=27, box=9.4, seed=2, frames="water"):
     w = synth.amoeba_water_box(n_w, box, seed)
-    ft, fa = synth.water_frames(n_w)
+    ft, fa = (synth.water_frames if frames == "water" else synth.mixed_frames)(n_w)
     loc = synth.water_local_multipoles(n_w, seed)
     return w, ft, fa, loc
+
+
+FRAME_SETS = ["water", "mixed"]
 
 
 def unit_dipoles_rotated(w, ft, fa, axis):
@@ -45,8 +48,37 @@ def test_frame_axes_orthonormal_and_defined_as_stated():
         assert abs(X[h1] @ zh) < 1e-14 and X[h1] @ d(h1, h2) > 0
 
 
-def test_rotation_keeps_invariants_and_none_is_identity():
-    w, ft, fa, loc = waters()
+def test_mixed_frame_axes_defined_as_stated():
+    w, ft, fa, _ = waters(frames="mixed")
+    assert set(ft.tolist()) == {1, 2, 3, 4, 5}
+    X, Y, Z = (unit_dipoles_rotated(w, ft, fa, a) for a in range(3))
+    for A in (X, Y, Z):
+        assert np.allclose(np.sum(A * A, axis=1), 1.0, atol=1e-14)
+    assert np.allclose(np.cross(Z, X), Y, atol=1e-14)
+    d = lambda i, j: (w.xyz[j] - w.xyz[i]) - w.box * np.rint((w.xyz[j] - w.xyz[i]) / w.box)
+    u = lambda i, j: d(i, j) / np.linalg.norm(d(i, j))
+    seen = set()
+    for i in range(w.n):
+        t, (iz, ix, iy) = int(ft[i]), fa[i]
+        if t == synth.FRAME_Z_ONLY:          # z to the z atom; x from a global axis
+            assert np.allclose(Z[i], u(i, iz), atol=1e-14)
+            ref = np.eye(3)[1] if abs(Z[i][0]) > 0.866 else np.eye(3)[0]
+            assert abs(X[i] @ np.cross(Z[i], ref)) < 1e-14 and X[i] @ ref > 0
+        elif t == synth.FRAME_Z_BISECTOR:    # x in the plane of z and u_x + u_y
+            b = u(i, ix) + u(i, iy)
+            assert np.allclose(Z[i], u(i, iz), atol=1e-14)
+            assert abs(X[i] @ np.cross(Z[i], b)) < 1e-13 and X[i] @ b > 0
+        elif t == synth.FRAME_3FOLD:         # z along u_z + u_x + u_y, x towards u_x
+            s3 = u(i, iz) + u(i, ix) + u(i, iy)
+            assert np.allclose(Z[i], s3 / np.linalg.norm(s3), atol=1e-14)
+            assert abs(X[i] @ np.cross(Z[i], u(i, ix))) < 1e-13 and X[i] @ u(i, ix) > 0
+        seen.add(t)
+    assert {3, 4, 5} <= seen
+
+
+@pytest.mark.parametrize("frames", FRAME_SETS)
+def test_rotation_keeps_invariants_and_none_is_identity(frames):
+    w, ft, fa, loc = waters(frames=frames)
     g = O.rotate_mpole(w.xyz, w.box, ft, fa, loc)
     assert np.array_equal(g[:, 0], loc[:, 0])
     assert np.allclose(np.linalg.norm(g[:, 1:4], axis=1), np.linalg.norm(loc[:, 1:4], axis=1),
@@ -64,10 +96,16 @@ def test_rotation_keeps_invariants_and_none_is_identity():
     assert np.array_equal(none, loc)
 
 
-def test_energy_invariant_under_rigid_rotation_with_frames():
+@pytest.mark.parametrize("frames", FRAME_SETS)
+def test_energy_invariant_under_rigid_rotation_with_frames(frames):
     # isolated cluster in a large box: rotating every position rigidly leaves
     # the local-frame energy unchanged; lab-frame multipoles would not follow
-    w, ft, fa, loc = waters(n_w=8, box=7.0, seed=3)
+    # (Z-only sites excepted: their x comes from a global axis)
+    w, ft, fa, loc = waters(n_w=8, box=7.0, seed=3, frames=frames)
+    ft = np.where(ft == synth.FRAME_Z_ONLY, synth.FRAME_Z_THEN_X, ft).astype(np.int32)
+    fa = fa.copy()
+    for i in np.nonzero((ft == synth.FRAME_Z_THEN_X) & (fa[:, 1] < 0))[0]:
+        fa[i, 1] = 3 * (i // 3) + (2 if i % 3 == 1 else 1)
     box = 60.0
     xyz = w.xyz + 26.0
     rp, cp = O.nblist(xyz, box, 29.0)
@@ -84,10 +122,11 @@ def test_energy_invariant_under_rigid_rotation_with_frames():
     assert abs(e3[0] - e1[0]) > 1e-3 * abs(e1[0])
 
 
-def test_forces_with_torques_are_minus_energy_gradient():
+@pytest.mark.parametrize("frames", FRAME_SETS)
+def test_forces_with_torques_are_minus_energy_gradient(frames):
     # E(x) = real-space multipole energy at the multipoles rotated from the
     # current positions, from the separately pinned rotation and energy
-    w, ft, fa, loc = waters()
+    w, ft, fa, loc = waters(frames=frames)
     rc = 4.0
     rp, cp = O.nblist(w.xyz, w.box, rc + 0.5)
     e, F = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, BETA, rc)
@@ -122,6 +161,15 @@ def test_no_frames_is_plain_multipoles_and_bad_frames():
     badt[3] = 7
     with pytest.raises(O.OracleError):
         O.empole_frames(w.xyz, w.box, w.molid, rp, cp, badt, fa, loc, BETA, 3.4)
+    # types that take a y atom refuse a missing or repeated one
+    mt, ma = synth.mixed_frames(8)
+    k = int(np.nonzero(mt == synth.FRAME_Z_BISECTOR)[0][0])
+    for y in (-1, ma[k, 0], k):
+        bad = ma.copy()
+        bad[k, 2] = y
+        with pytest.raises(O.OracleError):
+            O.rotate_mpole(w.xyz, w.box, mt, bad, loc)
+    O.rotate_mpole(w.xyz, w.box, mt, ma, loc)   # the clean topology is accepted
 
 
 # ---------------------------------------------------------------- vdW hydrogen reduction
@@ -165,10 +213,11 @@ def test_vdw_reduction_sites_and_forces():
         O.vdw_sites(w.xyz, w.box, bad, red)
 
 
-def test_polarization_forces_with_frames_are_minus_gradient():
+@pytest.mark.parametrize("frames", FRAME_SETS)
+def test_polarization_forces_with_frames_are_minus_gradient(frames):
     # at fixed induced dipoles, the polarization pair energy depends on the
     # frame atoms through the rotated permanent multipoles as well
-    w, ft, fa, loc = waters()
+    w, ft, fa, loc = waters(frames=frames)
     rc = 4.0
     rp, cp = O.nblist(w.xyz, w.box, rc + 0.5)
     mu = np.random.default_rng(4).normal(0, 0.03, (w.n, 3))
