@@ -288,20 +288,28 @@ tk_status tk_epolar2_real(tk_ctx* ctx, void* stream, const tk_system* sys, const
 
 /*
  * Local-frame multipoles (the rotation step that section "Hotspots" lists
- * beside the multipole routines).  frame_type: device [n] int32, 0 none,
- * 1 Z-then-X, 2 bisector (TK_FRAME_*); frame_atoms: device [n][2] int32, the
- * z-atom and x-atom of each site (ignored for type 0; distinct, not the site,
- * in [0, n)).  With d_z = r_zatom - r_i, d_x = r_xatom - r_i (minimum image):
- * Z-then-X z = unit(d_z), x = unit(d_x - (d_x.z) z); bisector
- * z = unit(unit(d_z) + unit(d_x)), x = unit(u - (u.z) z), u = unit(d_x);
- * y = z x x.  With R = [x y z]: q = q_loc, mu = R mu_loc,
- * Theta = R Theta_loc R^T.  mpole_local, mpole_global: device [n][10] in
- * the layout of tk_empole_real.  An invalid frame copies the site's local
- * multipoles unchanged.
+ * beside the multipole routines).  frame_type: device [n] int32 (TK_FRAME_*);
+ * frame_atoms: device [n][3] int32, the z-, x- and y-atom of each site.  A
+ * type reads only the atoms it takes (z: types 1-5, x: 1, 2, 4, 5, y: 4, 5);
+ * those are in [0, n), not the site, and distinct.  With d_k = r_katom - r_i
+ * (minimum image) and u_k = unit(d_k), each type takes z and a vector a:
+ *   1 Z-then-X:   z = u_z,                   a = d_x;
+ *   2 bisector:   z = unit(u_z + u_x),       a = u_x;
+ *   3 Z-only:     z = u_z,                   a = the global x axis, or the
+ *                 global y axis when |z_x| > 0.866;
+ *   4 Z-bisector: z = u_z,                   a = u_x + u_y;
+ *   5 3-fold:     z = unit(u_z + u_x + u_y), a = u_x;
+ * then x = unit(a - (a.z) z), y = z x x.  With R = [x y z]: q = q_loc,
+ * mu = R mu_loc, Theta = R Theta_loc R^T.  mpole_local, mpole_global: device
+ * [n][10] in the layout of tk_empole_real.  An invalid frame copies the
+ * site's local multipoles unchanged.
  */
 #define TK_FRAME_NONE 0
 #define TK_FRAME_Z_THEN_X 1
 #define TK_FRAME_BISECTOR 2
+#define TK_FRAME_Z_ONLY 3
+#define TK_FRAME_Z_BISECTOR 4
+#define TK_FRAME_3FOLD 5
 tk_status tk_rotate_mpole(tk_ctx* ctx, void* stream, const tk_system* sys,
                           const int32_t* frame_type, const int32_t* frame_atoms,
                           const double* mpole_local, double* mpole_global);
@@ -311,7 +319,7 @@ tk_status tk_rotate_mpole(tk_ctx* ctx, void* stream, const tk_system* sys,
  * multipoles (the multipole routine with its torque step): the energy of
  * tk_empole_real at the rotated multipoles M(x), and its full gradient, the
  * direct pair forces plus the frame part -sum_c dE/dM_i,c dM_i,c/dx for the
- * site and its two frame atoms.  FP64.  energy: device [3] as
+ * site and its frame atoms.  FP64.  energy: device [3] as
  * tk_empole_real (all three NaN if a frame is invalid); force: device [n][3];
  * mpole_global: device [n][10] receiving the rotated multipoles, or NULL.
  * The frame forces are added with atomics: reproducible to rounding, not

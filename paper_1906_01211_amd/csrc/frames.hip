@@ -2,10 +2,8 @@
 // multipole forces with the frame (torque) part (the rotation and torque
 // steps that section "Hotspots" lists beside the multipole routines).
 //
-// Frames (d_z = r_zatom - r_i, d_x = r_xatom - r_i, minimum image):
-//   0 none:      R = I
-//   1 Z-then-X:  z = unit(d_z), x = unit(d_x - (d_x.z) z)
-//   2 bisector:  z = unit(unit(d_z) + unit(d_x)), x = unit(u - (u.z) z), u = unit(d_x)
+// Frames: the five AMOEBA types (none, Z-then-X, bisector, Z-only,
+// Z-bisector, 3-fold) of up to three frame atoms; see make_frame.
 // y = z x x, R = [x y z] (columns); mu = R mu_loc, Theta = R Theta_loc R^T.
 //
 // Forces: the direct pair forces at the lab-frame multipoles (the multipole
@@ -13,10 +11,10 @@
 // multipole-derivative pair kernel), dE/dR = G_mu mu_loc^T + W R Theta_loc,
 // W the stored-component quadrupole derivative as a symmetric matrix with its
 // diagonal doubled; this is carried back through the frame construction by
-// hand (unit vectors, the Gram-Schmidt step, the cross product) to d_z and
-// d_x, whose atoms receive the forces.  The frame forces of a site go to
-// three atoms and are added with FP64 atomics: at most a few per atom, so the
-// sum is reproducible to rounding but not bitwise.
+// hand (unit vectors, the Gram-Schmidt step, the cross product) to d_z, d_x
+// and d_y, whose atoms receive the forces.  The frame forces of a site go to
+// up to four atoms and are added with FP64 atomics: at most a few per atom,
+// so the sum is reproducible to rounding but not bitwise.
 #include <cmath>
 
 #include "pairs.hpp"
@@ -48,40 +46,72 @@ __device__ __forceinline__ V3 image(const double* xyz, int i, int j, double box,
   return v3(t[0], t[1], t[2]);
 }
 
-// The frame of site i and the intermediates its reverse pass needs.
+// The frame of site i and the intermediates its reverse pass needs.  Every
+// type takes z and a vector a, then x = unit(a - (a.z) z), y = z x x:
+//   1 Z-then-X:   z = u_z,                   a = d_x
+//   2 bisector:   z = unit(u_z + u_x),       a = u_x
+//   3 Z-only:     z = u_z,                   a = global x, or global y when |z_x| > 0.866
+//   4 Z-bisector: z = u_z,                   a = u_x + u_y
+//   5 3-fold:     z = unit(u_z + u_x + u_y), a = u_x
+// with d_k = r_katom - r_i (minimum image) and u_k = d_k / |d_k|.
 struct Frame {
   V3 x, y, z;
-  V3 dz, dx;      // frame vectors
-  V3 uz, ux;      // unit(d_z), unit(d_x) (bisector)
-  V3 a;           // the vector orthogonalised against z (d_x, or ux)
-  double nz, nx, ns, nw;   // |d_z|, |d_x|, |uz + ux|, |a - (a.z) z|
+  V3 dx;            // d_x (Z-then-X)
+  V3 uz, ux, uy;    // unit vectors to the frame atoms
+  V3 a;             // the vector orthogonalised against z
+  double nz, nx, ny, ns, nw;   // |d_z|, |d_x|, |d_y|, |sum| (types 2, 5), |a - (a.z) z|
 };
 
-__device__ __forceinline__ bool frame_ok(int type, int i, int iz, int ix, int n) {
-  if (type == 0) return true;
-  if (type != 1 && type != 2) return false;
-  return iz >= 0 && iz < n && ix >= 0 && ix < n && iz != i && ix != i && iz != ix;
+// frame atoms a type takes: z (1-5), x (1, 2, 4, 5), y (4, 5)
+__device__ __forceinline__ int frame_natoms(int type) {
+  return type == 0 ? 0 : type == 3 ? 1 : type <= 2 ? 2 : 3;
+}
+
+// fa: the site's three frame atoms (z, x, y); those a type takes are in
+// [0, n), not the site, and distinct
+__device__ __forceinline__ bool frame_ok(int type, int i, const int32_t* fa, int n) {
+  if (type < 0 || type > 5) return false;
+  const int m = frame_natoms(type);
+  for (int k = 0; k < m; ++k) {
+    const int a = fa[k];
+    if (a < 0 || a >= n || a == i) return false;
+    for (int l = 0; l < k; ++l)
+      if (fa[l] == a) return false;
+  }
+  return true;
 }
 
 __device__ __forceinline__ Frame make_frame(const double* xyz, double box, double inv_box, int type,
-                                            int i, int iz, int ix) {
+                                            int i, const int32_t* fa) {
   Frame f;
-  f.dz = image(xyz, i, iz, box, inv_box);
-  f.dx = image(xyz, i, ix, box, inv_box);
-  f.nz = sqrt(dot(f.dz, f.dz));
-  f.nx = sqrt(dot(f.dx, f.dx));
-  f.uz = (1.0 / f.nz) * f.dz;
-  f.ux = (1.0 / f.nx) * f.dx;
-  if (type == 1) {
-    f.z = f.uz;
-    f.a = f.dx;
-    f.ns = 0.0;
-  } else {
-    const V3 s = f.uz + f.ux;
+  const V3 dz = image(xyz, i, fa[0], box, inv_box);
+  f.nz = sqrt(dot(dz, dz));
+  f.uz = (1.0 / f.nz) * dz;
+  f.dx = v3(0.0, 0.0, 0.0);
+  f.ux = f.uy = f.dx;
+  f.nx = f.ny = 1.0;
+  if (type != 3) {
+    f.dx = image(xyz, i, fa[1], box, inv_box);
+    f.nx = sqrt(dot(f.dx, f.dx));
+    f.ux = (1.0 / f.nx) * f.dx;
+  }
+  if (type >= 4) {
+    const V3 dy = image(xyz, i, fa[2], box, inv_box);
+    f.ny = sqrt(dot(dy, dy));
+    f.uy = (1.0 / f.ny) * dy;
+  }
+  f.ns = 0.0;
+  if (type == 2 || type == 5) {
+    const V3 s = type == 2 ? f.uz + f.ux : f.uz + f.ux + f.uy;
     f.ns = sqrt(dot(s, s));
     f.z = (1.0 / f.ns) * s;
-    f.a = f.ux;
+  } else {
+    f.z = f.uz;
   }
+  if (type == 1) f.a = f.dx;
+  else if (type == 3) f.a = fabs(f.z.x) > 0.866 ? v3(0.0, 1.0, 0.0) : v3(1.0, 0.0, 0.0);
+  else if (type == 4) f.a = f.ux + f.uy;
+  else f.a = f.ux;
   const V3 w = f.a - dot(f.a, f.z) * f.z;
   f.nw = sqrt(dot(w, w));
   f.x = (1.0 / f.nw) * w;
@@ -118,10 +148,11 @@ __global__ __launch_bounds__(256) void k_frames_rotate(int n, const double* __re
                                                        int* __restrict__ flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int type = ftype[i], iz = fatoms[2 * i], ix = fatoms[2 * i + 1];
+  const int type = ftype[i];
+  const int32_t fa[3] = {fatoms[3 * i], fatoms[3 * i + 1], fatoms[3 * i + 2]};
   const double* l = loc + 10 * i;
   double* o = glob + 10 * i;
-  if (!frame_ok(type, i, iz, ix, n)) {
+  if (!frame_ok(type, i, fa, n)) {
     atomicOr(flag, 1);
 #pragma unroll
     for (int k = 0; k < 10; ++k) o[k] = l[k];
@@ -132,7 +163,7 @@ __global__ __launch_bounds__(256) void k_frames_rotate(int n, const double* __re
     for (int k = 0; k < 10; ++k) o[k] = l[k];
     return;
   }
-  const Frame f = make_frame(xyz, box, 1.0 / box, type, i, iz, ix);
+  const Frame f = make_frame(xyz, box, 1.0 / box, type, i, fa);
   const V3 col[3] = {f.x, f.y, f.z};
   rotate(col, l, o);
 }
@@ -159,9 +190,10 @@ __global__ __launch_bounds__(256) void k_frames_torque(int n, const double* __re
     for (int k = 0; k < 3; ++k) energy[k] = __builtin_nan("");
   }
   if (i >= n) return;
-  const int type = ftype[i], iz = fatoms[2 * i], ix = fatoms[2 * i + 1];
-  if (type == 0 || !frame_ok(type, i, iz, ix, n)) return;
-  const Frame f = make_frame(xyz, box, 1.0 / box, type, i, iz, ix);
+  const int type = ftype[i];
+  const int32_t fa[3] = {fatoms[3 * i], fatoms[3 * i + 1], fatoms[3 * i + 2]};
+  if (type == 0 || !frame_ok(type, i, fa, n)) return;
+  const Frame f = make_frame(xyz, box, 1.0 / box, type, i, fa);
   const double* l = loc + 10 * i;
   const double* g = G + 10 * i;
   const double R[3][3] = {{f.x.x, f.y.x, f.z.x}, {f.x.y, f.y.y, f.z.y}, {f.x.z, f.y.z, f.z.z}};
@@ -190,22 +222,32 @@ __global__ __launch_bounds__(256) void k_frames_torque(int n, const double* __re
   const double az = dot(f.a, f.z), gwz = dot(gw, f.z);
   const V3 ga = gw - gwz * f.z;
   gz = gz - az * gw - gwz * f.a;
-  V3 gdz, gdx;
-  if (type == 1) {   // z = unit(d_z), a = d_x
-    gdz = back_unit(gz, f.z, f.nz);
-    gdx = ga;
-  } else {           // z = unit(uz + ux), a = ux
+  // back through z and a to d_z, d_x, d_y
+  const V3 zero = v3(0.0, 0.0, 0.0);
+  V3 gdz, gdx = zero, gdy = zero;
+  if (type == 2 || type == 5) {   // z = unit(s), s = u_z + u_x (+ u_y)
     const V3 gs = back_unit(gz, f.z, f.ns);
     gdz = back_unit(gs, f.uz, f.nz);
-    gdx = back_unit(gs + ga, f.ux, f.nx);
+    gdx = back_unit(gs + ga, f.ux, f.nx);   // a = u_x
+    if (type == 5) gdy = back_unit(gs, f.uy, f.ny);
+  } else {                        // z = u_z
+    gdz = back_unit(gz, f.uz, f.nz);
+    if (type == 1) gdx = ga;      // a = d_x
+    if (type == 4) {              // a = u_x + u_y
+      gdx = back_unit(ga, f.ux, f.nx);
+      gdy = back_unit(ga, f.uy, f.ny);
+    }                             // type 3: a is fixed
   }
-  // d_z = r_z - r_i, d_x = r_x - r_i; F = -dE/dr
-  const double gzv[3] = {gdz.x, gdz.y, gdz.z}, gxv[3] = {gdx.x, gdx.y, gdx.z};
+  // d_k = r_k - r_i; F = -dE/dr
+  const int m = frame_natoms(type);
+  const double gzv[3] = {gdz.x, gdz.y, gdz.z}, gxv[3] = {gdx.x, gdx.y, gdx.z},
+               gyv[3] = {gdy.x, gdy.y, gdy.z};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    atomicAdd(&force[3 * iz + c], -gzv[c]);
-    atomicAdd(&force[3 * ix + c], -gxv[c]);
-    atomicAdd(&force[3 * i + c], gzv[c] + gxv[c]);
+    atomicAdd(&force[3 * fa[0] + c], -gzv[c]);
+    if (m >= 2) atomicAdd(&force[3 * fa[1] + c], -gxv[c]);
+    if (m >= 3) atomicAdd(&force[3 * fa[2] + c], -gyv[c]);
+    atomicAdd(&force[3 * i + c], gzv[c] + gxv[c] + gyv[c]);
   }
 }
 

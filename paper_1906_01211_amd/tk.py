@@ -404,9 +404,18 @@ class Context:
                                    None if fld is None else _ptr(fld)), "tk_pme_mpole")
         return e, f, fld
 
-    def rotate_mpole(self, sysref, frame_type, frame_atoms, mpole_local):
+    def _frames(self, sysref, frame_type, frame_atoms):
+        """Device frame types [n] and frame atoms [n, 3]; the kernels read three
+        atoms per site, so other shapes are refused here."""
         ft = _dev(frame_type, torch.int32, self.device)
         fa = _dev(frame_atoms, torch.int32, self.device)
+        if tuple(ft.shape) != (sysref.n,) or tuple(fa.shape) != (sysref.n, 3):
+            raise ValueError(f"frame_type must be [{sysref.n}] and frame_atoms [{sysref.n}, 3]; "
+                             f"got {tuple(ft.shape)} and {tuple(fa.shape)}")
+        return ft, fa
+
+    def rotate_mpole(self, sysref, frame_type, frame_atoms, mpole_local):
+        ft, fa = self._frames(sysref, frame_type, frame_atoms)
         ml = _dev(mpole_local, torch.float64, self.device)
         out = torch.empty((sysref.n, 10), dtype=torch.float64, device=self.device)
         _check(load().tk_rotate_mpole(self._h, _stream(self.device), C.byref(sysref.c), _ptr(ft),
@@ -414,8 +423,7 @@ class Context:
         return out
 
     def empole_frames(self, sysref, lst, frame_type, frame_atoms, mpole_local, beta, cutoff):
-        ft = _dev(frame_type, torch.int32, self.device)
-        fa = _dev(frame_atoms, torch.int32, self.device)
+        ft, fa = self._frames(sysref, frame_type, frame_atoms)
         ml = _dev(mpole_local, torch.float64, self.device)
         e = torch.empty(3, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
@@ -456,8 +464,7 @@ class Context:
 
     def epolar_frames(self, sysref, lst, frame_type, frame_atoms, mpole_local, polarity, thole, mu,
                       beta, cutoff):
-        ft = _dev(frame_type, torch.int32, self.device)
-        fa = _dev(frame_atoms, torch.int32, self.device)
+        ft, fa = self._frames(sysref, frame_type, frame_atoms)
         ml = _dev(mpole_local, torch.float64, self.device)
         pol = _dev(polarity, torch.float64, self.device)
         th = _dev(thole, torch.float64, self.device)

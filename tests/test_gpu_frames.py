@@ -1,7 +1,8 @@
-"""Local-frame multipoles (tk_rotate_mpole, tk_empole_frames) against the FP64
-CPU oracle: rotated multipoles to rounding, energies within 1e-10 relative,
-forces (torques included) within 1e-8 of their RMS; invalid frames and
-empty systems."""
+"""Local-frame multipoles (tk_rotate_mpole, tk_empole_frames, tk_epolar_frames)
+against the FP64 CPU oracle, on the water frames and on a topology using all
+five frame types: rotated multipoles to rounding, energies within 1e-10
+relative, forces (torques included) within 1e-8 of their RMS; invalid frames
+and empty systems."""
 import numpy as np
 import pytest
 
@@ -39,10 +40,10 @@ def fmax_rel(got, ref):
     return np.abs(np.asarray(got) - ref).max() / np.sqrt(np.mean(ref ** 2))
 
 
-def case(ctx, name):
+def case(ctx, name, frames="water"):
     w = _cache.setdefault(name, synth.make(name))
     n_w = w.n // 3
-    ft, fa = synth.water_frames(n_w)
+    ft, fa = (synth.water_frames if frames == "water" else synth.mixed_frames)(n_w)
     loc = synth.water_local_multipoles(n_w, 7)
     sysr = ctx.system(w.xyz, w.box, w.molid)
     lst = ctx.nblist(sysr, 7.001, plan_slot=2)
@@ -53,10 +54,11 @@ def case(ctx, name):
     return w, ft, fa, loc, sysr, lst, rp, cp
 
 
+@pytest.mark.parametrize("frames", ["water", "mixed"])
 @pytest.mark.parametrize("name", ["water216", "water7853"])
-def test_frames_fp64(ctx, name):
-    w, ft, fa, loc, sysr, lst, rp, cp = case(ctx, name)
-    print(f"frames {name}", flush=True)
+def test_frames_fp64(ctx, name, frames):
+    w, ft, fa, loc, sysr, lst, rp, cp = case(ctx, name, frames)
+    print(f"frames {name} {frames}", flush=True)
     g = ctx.rotate_mpole(sysr, ft, fa, loc)
     go = O.rotate_mpole(w.xyz, w.box, ft, fa, loc)
     assert np.abs(np_(g) - go).max() <= 1e-13 * np.abs(go).max()
@@ -95,9 +97,19 @@ def test_frames_invalid_and_empty(ctx, tk):
     assert np.array_equal(np_(out)[3], loc[3])   # an invalid frame copies the site
     e, f, _ = ctx.empole_frames(sysr, lst, ft, fa, loc, S["beta"], 7.0)   # clean again
     assert np.all(np.isfinite(np_(e)))
+    # a type that takes a y atom refuses a missing or repeated one
+    mt, ma = synth.mixed_frames(w.n // 3)
+    k = int(np.nonzero(mt == synth.FRAME_3FOLD)[0][0])
+    for y in (-1, ma[k, 1]):
+        bad = ma.copy()
+        bad[k, 2] = y
+        e, _, _ = ctx.empole_frames(sysr, lst, mt, bad, loc, S["beta"], 7.0)
+        assert np.all(np.isnan(np_(e)))
+    with pytest.raises(ValueError):   # frame atoms are [n, 3]
+        ctx.rotate_mpole(sysr, ft, fa[:, :2], loc)
     empty = ctx.system(np.zeros((0, 3)), 20.0, np.zeros(0, np.int32))
     l0 = ctx.nblist(empty, 7.001, plan_slot=6)
-    e, f, _ = ctx.empole_frames(empty, l0, np.zeros(0, np.int32), np.zeros((0, 2), np.int32),
+    e, f, _ = ctx.empole_frames(empty, l0, np.zeros(0, np.int32), np.zeros((0, 3), np.int32),
                                 np.zeros((0, 10)), S["beta"], 7.0)
     assert np.all(np_(e) == 0.0) and f.shape == (0, 3)
 
@@ -130,9 +142,10 @@ def test_vdw_reduction_invalid_parent(ctx):
     assert np.all(np.isnan(sites[4])) and np.all(np.isfinite(np.delete(sites, 4, axis=0)))
 
 
+@pytest.mark.parametrize("frames", ["water", "mixed"])
 @pytest.mark.parametrize("name", ["water216", "water7853"])
-def test_epolar_frames_fp64(ctx, name):
-    w, ft, fa, loc, sysr, lst, rp, cp = case(ctx, name)
+def test_epolar_frames_fp64(ctx, name, frames):
+    w, ft, fa, loc, sysr, lst, rp, cp = case(ctx, name, frames)
     mu = np.random.default_rng(9).normal(0, 0.03, (w.n, 3))
     e, f = ctx.epolar_frames(sysr, lst, ft, fa, loc, w.polarity, w.thole, mu, S["beta"], 7.0)
     eo, fo = O.epolar_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, w.polarity, w.thole, mu,
