@@ -93,14 +93,14 @@ def lib():
                                             C.POINTER(PcgInfo)]
         L.or_rotate_mpole.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _dp, _dp]
         L.or_empole_frames.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _ip, _ip, _dp,
-                                       C.c_double, C.c_double, _dp, _dp]
+                                       C.c_double, C.c_double, _dp, _dp, _dp]
         L.or_vdw_sites.argtypes = [C.c_int, _dp, C.c_double, _ip, _dp, _dp]
         L.or_vdw_forces_to_atoms.argtypes = [C.c_int, _ip, _dp, _dp, _dp]
         L.or_polarize_tcg1.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
                                        C.c_double, C.c_double, _dp, C.POINTER(C.c_double),
                                        C.c_void_p]
         L.or_epolar_frames.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _ip, _ip, _dp,
-                                       _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp]
+                                       _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -427,16 +427,18 @@ def rotate_mpole(xyz, box, ftype, fatoms, local):
 
 
 def empole_frames(xyz, box, molid, row_ptr, col, ftype, fatoms, local, beta, cutoff):
-    """Energies and forces (torques included) with local-frame multipoles."""
+    """Energies, forces (torques included) and virial (frame part included)
+    with local-frame multipoles."""
     xyz = _d(xyz)
     n = xyz.shape[0]
     energy = np.zeros(3)
     force = np.zeros((n, 3))
+    virial = np.zeros((3, 3))
     st = lib().or_empole_frames(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _i(ftype),
-                                _i(fatoms), _d(local), beta, cutoff, energy, force)
+                                _i(fatoms), _d(local), beta, cutoff, energy, force, virial)
     if st:
         raise OracleError(st)
-    return energy, force
+    return energy, force, virial
 
 
 def vdw_sites(xyz, box, parent, red):
@@ -478,14 +480,16 @@ def polarize_tcg1(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta,
 
 def epolar_frames(xyz, box, molid, row_ptr, col, ftype, fatoms, local, polarity, thole_a, mu, beta,
                   cutoff):
-    """Polarization pair energies and forces at fixed mu with local-frame multipoles."""
+    """Polarization pair energies, forces and virial at fixed mu with
+    local-frame multipoles."""
     xyz = _d(xyz)
     n = xyz.shape[0]
     energy = np.zeros(3)
     force = np.zeros((n, 3))
+    virial = np.zeros((3, 3))
     st = lib().or_epolar_frames(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _i(ftype),
                                 _i(fatoms), _d(local), _d(polarity), _d(thole_a), _d(mu), beta,
-                                cutoff, energy, force)
+                                cutoff, energy, force, virial)
     if st:
         raise OracleError(st)
-    return energy, force
+    return energy, force, virial

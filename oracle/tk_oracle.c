@@ -1493,19 +1493,32 @@ static int or_frames_args(int n, const int32_t* ftype, const int32_t* fatoms) {
   return OR_OK;
 }
 
-/* force_k -= sum over sites i with k in their frame of sum_c G_i,c dM_i,c/dx_k */
-static void or_frames_chain(int n, const int32_t* ftype, const int32_t* fatoms, const or_dual* M,
-                            const double* G, double* force) {
+/* force_k -= sum over sites i with k in their frame of sum_c G_i,c dM_i,c/dx_k.
+ * virial (nullable): M_i depends on positions only through the frame vectors
+ * d_k = r_katom - r_i, and dM/dd_k = dM/dr_katom, so the frame part of
+ * W_ab = sum over relative vectors v of v_a dE/dv_b is
+ * sum_i sum_k d_k,a (sum_c G_i,c dM_i,c/dr_katom,b). */
+static void or_frames_chain(int n, const double* xyz, double box, const int32_t* ftype,
+                            const int32_t* fatoms, const or_dual* M, const double* G,
+                            double* force, double* virial) {
   for (int i = 0; i < n; ++i) {
     if (ftype[i] == 0) continue;
     int m = or_frame_natoms(ftype[i]);
     int who[4] = {i, fatoms[3 * i], fatoms[3 * i + 1], fatoms[3 * i + 2]};
-    for (int s = 0; s <= m; ++s)
+    for (int s = 0; s <= m; ++s) {
+      double g[3];
       for (int a = 0; a < 3; ++a) {
-        double g = 0.0;
-        for (int c = 0; c < 10; ++c) g += G[10 * i + c] * M[10 * i + c].d[3 * s + a];
-        force[3 * who[s] + a] -= g;
+        g[a] = 0.0;
+        for (int c = 0; c < 10; ++c) g[a] += G[10 * i + c] * M[10 * i + c].d[3 * s + a];
+        force[3 * who[s] + a] -= g[a];
       }
+      if (virial && s > 0) {
+        double d[3], r2;
+        or_image(xyz + 3 * i, xyz + 3 * who[s], box, d, &r2);
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) virial[3 * a + b] += d[a] * g[b];
+      }
+    }
   }
 }
 
@@ -1528,11 +1541,12 @@ int or_rotate_mpole(int n, const double* xyz, double box, const int32_t* ftype,
  * frame part: with G_i,c = dE/dM_i,c, which is the pair energy with a unit
  * multipole in component c of site i (E is linear in each site's
  * multipoles), the force on atom k gains -sum_i sum_c G_i,c dM_i,c/dx_k over
- * the sites i whose frame contains k.  energy[3] as or_empole_real. */
+ * the sites i whose frame contains k.  energy[3] as or_empole_real; virial
+ * (nullable) [9]: or_empole_real's pair virial at M plus the frame part. */
 int or_empole_frames(int n, const double* xyz, double box, const int32_t* molid,
                      const int32_t* row_ptr, const int32_t* col, const int32_t* ftype,
                      const int32_t* fatoms, const double* local, double beta, double rc,
-                     double* energy, double* force) {
+                     double* energy, double* force, double* virial) {
   int st = or_pair_args(n, box, rc);
   if (st) return st;
   if ((st = or_frames_args(n, ftype, fatoms))) return st;
@@ -1567,7 +1581,9 @@ int or_empole_frames(int n, const double* xyz, double box, const int32_t* molid,
         G[10 * j + c] += e;
       }
     }
-  or_frames_chain(n, ftype, fatoms, M, G, force);
+  or_frames_chain(n, xyz, box, ftype, fatoms, M, G, force, virial ? vir : NULL);
+  if (virial)
+    for (int k = 0; k < 9; ++k) virial[k] = vir[k];
   free(M);
   free(Mg);
   free(G);
@@ -1579,12 +1595,13 @@ int or_empole_frames(int n, const double* xyz, double box, const int32_t* molid,
  * their full gradient.  Only the induced-permanent energy depends on M; its
  * G_i,c is the pair energy U(unit_c at i, mu_j; gp) over the partners j
  * (and U(mu_i, unit_c at j; gp) from the other side), gp the damped family
- * of or_epolar_real.  energy[3] as or_epolar_real. */
+ * of or_epolar_real.  energy[3] as or_epolar_real; virial (nullable) [9]:
+ * or_epolar_real's pair virial at M plus the frame part. */
 int or_epolar_frames(int n, const double* xyz, double box, const int32_t* molid,
                      const int32_t* row_ptr, const int32_t* col, const int32_t* ftype,
                      const int32_t* fatoms, const double* local, const double* polarity,
                      const double* thole, const double* mu, double beta, double rc,
-                     double* energy, double* force) {
+                     double* energy, double* force, double* virial) {
   int st = or_pair_args(n, box, rc);
   if (st) return st;
   if ((st = or_frames_args(n, ftype, fatoms))) return st;
@@ -1627,7 +1644,9 @@ int or_epolar_frames(int n, const double* xyz, double box, const int32_t* molid,
         G[10 * j + c] += e;
       }
     }
-  or_frames_chain(n, ftype, fatoms, M, G, force);
+  or_frames_chain(n, xyz, box, ftype, fatoms, M, G, force, virial ? vir : NULL);
+  if (virial)
+    for (int k = 0; k < 9; ++k) virial[k] = vir[k];
   free(M);
   free(Mg);
   free(G);

@@ -62,8 +62,8 @@ def test_frames_fp64(ctx, name, frames):
     g = ctx.rotate_mpole(sysr, ft, fa, loc)
     go = O.rotate_mpole(w.xyz, w.box, ft, fa, loc)
     assert np.abs(np_(g) - go).max() <= 1e-13 * np.abs(go).max()
-    e, f, mg = ctx.empole_frames(sysr, lst, ft, fa, loc, S["beta"], 7.0)
-    eo, fo = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, S["beta"], 7.0)
+    e, f, mg, vir = ctx.empole_frames(sysr, lst, ft, fa, loc, S["beta"], 7.0)
+    eo, fo, vo = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, S["beta"], 7.0)
     e = np_(e)
     for k in range(3):
         assert abs(e[k] - eo[k]) <= 1e-10 * abs(eo[k]), (k, e[k], eo[k])
@@ -78,11 +78,11 @@ def test_frames_mixed_types_and_reproducible(ctx):
     w, ft, fa, loc, sysr, lst, rp, cp = case(ctx, "water216")
     ft2 = ft.copy()
     ft2[::5] = 0                     # some sites without a frame
-    e, f, _ = ctx.empole_frames(sysr, lst, ft2, fa, loc, S["beta"], 7.0)
-    eo, fo = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, ft2, fa, loc, S["beta"], 7.0)
+    e, f, _, _ = ctx.empole_frames(sysr, lst, ft2, fa, loc, S["beta"], 7.0)
+    eo, fo, vo = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, ft2, fa, loc, S["beta"], 7.0)
     assert abs(np_(e)[0] - eo[0]) <= 1e-10 * abs(eo[0])
     assert fmax_rel(np_(f), fo) < 1e-8
-    e2, f2, _ = ctx.empole_frames(sysr, lst, ft2, fa, loc, S["beta"], 7.0)
+    e2, f2, _, _ = ctx.empole_frames(sysr, lst, ft2, fa, loc, S["beta"], 7.0)
     assert np.array_equal(np_(e), np_(e2))   # energies: fixed-order sums
     assert np.abs(np_(f2) - np_(f)).max() <= 1e-12 * np.abs(fo).max()   # forces: atomics
 
@@ -91,11 +91,11 @@ def test_frames_invalid_and_empty(ctx, tk):
     w, ft, fa, loc, sysr, lst, rp, cp = case(ctx, "water216")
     bad = fa.copy()
     bad[3, 0] = 3                    # the site itself
-    e, _, _ = ctx.empole_frames(sysr, lst, ft, bad, loc, S["beta"], 7.0)
+    e, _, _, _ = ctx.empole_frames(sysr, lst, ft, bad, loc, S["beta"], 7.0)
     assert np.all(np.isnan(np_(e)))
     out = ctx.rotate_mpole(sysr, ft, bad, loc)
     assert np.array_equal(np_(out)[3], loc[3])   # an invalid frame copies the site
-    e, f, _ = ctx.empole_frames(sysr, lst, ft, fa, loc, S["beta"], 7.0)   # clean again
+    e, f, _, _ = ctx.empole_frames(sysr, lst, ft, fa, loc, S["beta"], 7.0)   # clean again
     assert np.all(np.isfinite(np_(e)))
     # a type that takes a y atom refuses a missing or repeated one
     mt, ma = synth.mixed_frames(w.n // 3)
@@ -103,13 +103,13 @@ def test_frames_invalid_and_empty(ctx, tk):
     for y in (-1, ma[k, 1]):
         bad = ma.copy()
         bad[k, 2] = y
-        e, _, _ = ctx.empole_frames(sysr, lst, mt, bad, loc, S["beta"], 7.0)
+        e, _, _, _ = ctx.empole_frames(sysr, lst, mt, bad, loc, S["beta"], 7.0)
         assert np.all(np.isnan(np_(e)))
     with pytest.raises(ValueError):   # frame atoms are [n, 3]
         ctx.rotate_mpole(sysr, ft, fa[:, :2], loc)
     empty = ctx.system(np.zeros((0, 3)), 20.0, np.zeros(0, np.int32))
     l0 = ctx.nblist(empty, 7.001, plan_slot=6)
-    e, f, _ = ctx.empole_frames(empty, l0, np.zeros(0, np.int32), np.zeros((0, 3), np.int32),
+    e, f, _, _ = ctx.empole_frames(empty, l0, np.zeros(0, np.int32), np.zeros((0, 3), np.int32),
                                 np.zeros((0, 10)), S["beta"], 7.0)
     assert np.all(np_(e) == 0.0) and f.shape == (0, 3)
 
@@ -147,8 +147,8 @@ def test_vdw_reduction_invalid_parent(ctx):
 def test_epolar_frames_fp64(ctx, name, frames):
     w, ft, fa, loc, sysr, lst, rp, cp = case(ctx, name, frames)
     mu = np.random.default_rng(9).normal(0, 0.03, (w.n, 3))
-    e, f = ctx.epolar_frames(sysr, lst, ft, fa, loc, w.polarity, w.thole, mu, S["beta"], 7.0)
-    eo, fo = O.epolar_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, w.polarity, w.thole, mu,
+    e, f, vir = ctx.epolar_frames(sysr, lst, ft, fa, loc, w.polarity, w.thole, mu, S["beta"], 7.0)
+    eo, fo, vo = O.epolar_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, w.polarity, w.thole, mu,
                              S["beta"], 7.0)
     e = np_(e)
     for k in range(3):

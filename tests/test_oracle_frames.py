@@ -114,8 +114,8 @@ def test_energy_invariant_under_rigid_rotation_with_frames(frames):
     Rx = np.array([[1.0, 0, 0], [0, np.cos(1.1), -np.sin(1.1)], [0, np.sin(1.1), np.cos(1.1)]])
     c = xyz.mean(axis=0)
     xyz2 = (xyz - c) @ (Rx @ Rz).T + c
-    e1, _ = O.empole_frames(xyz, box, w.molid, rp, cp, ft, fa, loc, 0.0, 29.0)
-    e2, _ = O.empole_frames(xyz2, box, w.molid, rp, cp, ft, fa, loc, 0.0, 29.0)
+    e1, _, _ = O.empole_frames(xyz, box, w.molid, rp, cp, ft, fa, loc, 0.0, 29.0)
+    e2, _, _ = O.empole_frames(xyz2, box, w.molid, rp, cp, ft, fa, loc, 0.0, 29.0)
     assert e2[0] == pytest.approx(e1[0], rel=1e-12)
     lab = O.rotate_mpole(xyz, box, ft, fa, loc)
     e3, _, _ = O.empole_real(xyz2, box, w.molid, rp, cp, lab, 0.0, 29.0)
@@ -129,7 +129,7 @@ def test_forces_with_torques_are_minus_energy_gradient(frames):
     w, ft, fa, loc = waters(frames=frames)
     rc = 4.0
     rp, cp = O.nblist(w.xyz, w.box, rc + 0.5)
-    e, F = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, BETA, rc)
+    e, F, _ = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, BETA, rc)
 
     def E(xyz):
         g = O.rotate_mpole(xyz, w.box, ft, fa, loc)
@@ -150,7 +150,7 @@ def test_no_frames_is_plain_multipoles_and_bad_frames():
     w, ft, fa, loc = waters(n_w=8, box=7.0)
     rp, cp = O.nblist(w.xyz, w.box, 3.4)
     zero = np.zeros(w.n, np.int32)
-    e, F = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, zero, fa, loc, BETA, 3.4)
+    e, F, _ = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, zero, fa, loc, BETA, 3.4)
     e0, F0, _ = O.empole_real(w.xyz, w.box, w.molid, rp, cp, loc, BETA, 3.4)
     assert np.array_equal(e, e0) and np.array_equal(F, F0)
     bad = fa.copy()
@@ -221,7 +221,7 @@ def test_polarization_forces_with_frames_are_minus_gradient(frames):
     rc = 4.0
     rp, cp = O.nblist(w.xyz, w.box, rc + 0.5)
     mu = np.random.default_rng(4).normal(0, 0.03, (w.n, 3))
-    e, F = O.epolar_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, w.polarity, w.thole, mu,
+    e, F, _ = O.epolar_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, w.polarity, w.thole, mu,
                            BETA, rc)
 
     def E(xyz):
@@ -240,3 +240,35 @@ def test_polarization_forces_with_frames_are_minus_gradient(frames):
     g = O.rotate_mpole(w.xyz, w.box, ft, fa, loc)
     _, F0, _ = O.epolar_real(w.xyz, w.box, w.molid, rp, cp, g, w.polarity, w.thole, mu, BETA, rc)
     assert np.abs(F0 - F).max() > 1e-3 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("frames", FRAME_SETS)
+@pytest.mark.parametrize("term", ["empole", "epolar"])
+def test_frame_virial_is_minus_sum_of_x_outer_f(frames, term):
+    # an isolated cluster in a large box: the energy is a function of relative
+    # vectors only (pair vectors and frame vectors), so W = -sum_i x_i (x) F_i
+    # holds for the full tensor, frame part included
+    w, ft, fa, loc = waters(n_w=8, box=7.0, seed=3, frames=frames)
+    box = 60.0
+    xyz = w.xyz + 26.0
+    rp, cp = O.nblist(xyz, box, 29.0)
+    if term == "empole":
+        e, F, W = O.empole_frames(xyz, box, w.molid, rp, cp, ft, fa, loc, BETA, 29.0)
+        _, F0, W0 = O.empole_real(xyz, box, w.molid, rp, cp,
+                                  O.rotate_mpole(xyz, box, ft, fa, loc), BETA, 29.0)
+    else:
+        mu = np.random.default_rng(5).normal(0, 0.03, (w.n, 3))
+        e, F, W = O.epolar_frames(xyz, box, w.molid, rp, cp, ft, fa, loc, w.polarity, w.thole,
+                                  mu, BETA, 29.0)
+        _, F0, W0 = O.epolar_real(xyz, box, w.molid, rp, cp,
+                                  O.rotate_mpole(xyz, box, ft, fa, loc), w.polarity, w.thole, mu,
+                                  BETA, 29.0)
+    ref = -np.einsum("ia,ib->ab", xyz, F)
+    assert np.abs(W - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert np.abs(W - W0).max() > 1e-4 * np.abs(W).max()   # the frame part is not small
+    # no frames: the plain pair virial
+    zero = np.zeros(w.n, np.int32)
+    if term == "empole":
+        _, _, Wn = O.empole_frames(xyz, box, w.molid, rp, cp, zero, fa, loc, BETA, 29.0)
+        _, _, Wr = O.empole_real(xyz, box, w.molid, rp, cp, loc, BETA, 29.0)
+        assert np.array_equal(Wn, Wr)
