@@ -321,15 +321,19 @@ tk_status tk_rotate_mpole(tk_ctx* ctx, void* stream, const tk_system* sys,
  * direct pair forces plus the frame part -sum_c dE/dM_i,c dM_i,c/dx for the
  * site and its frame atoms.  FP64.  energy: device [3] as
  * tk_empole_real (all three NaN if a frame is invalid); force: device [n][3];
- * mpole_global: device [n][10] receiving the rotated multipoles, or NULL.
- * The frame forces are added with atomics: reproducible to rounding, not
- * bitwise.  No virial.
+ * virial: device [3][3] or NULL, W_ab = sum over the relative vectors v the
+ * energy depends on (pair vectors and each site's frame vectors d_k) of
+ * v_a dE/dv_b: tk_empole_real's pair virial at M plus the frame part
+ * sum_k d_k,a dE/dd_k,b (NaN if a frame is invalid); mpole_global: device
+ * [n][10] receiving the rotated multipoles, or NULL.  The frame forces are
+ * added with atomics: reproducible to rounding, not bitwise; the virial's
+ * sums run in a fixed order.
  */
 tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
                            const tk_nblist* list, const int32_t* frame_type,
                            const int32_t* frame_atoms, const double* mpole_local,
                            double ewald_beta, double cutoff, double* energy, double* force,
-                           double* mpole_global);
+                           double* virial, double* mpole_global);
 
 /*
  * Polarization forces at fixed induced dipoles with local-frame multipoles:
@@ -337,13 +341,16 @@ tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
  * their full gradient, the pair forces plus the frame part of the
  * induced-permanent energy (its dE/dM through the rotation, as in
  * tk_empole_frames).  Arguments as tk_empole_frames and tk_epolar_real; FP64;
- * energy: device [3] (NaN if a frame is invalid); no virial.
+ * energy: device [3] (NaN if a frame is invalid); virial: device [3][3] or
+ * NULL, tk_epolar_real's pair virial at M plus the frame part, as in
+ * tk_empole_frames.
  */
 tk_status tk_epolar_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
                            const tk_nblist* list, const int32_t* frame_type,
                            const int32_t* frame_atoms, const double* mpole_local,
                            const double* polarity, const double* thole, const double* mu,
-                           double ewald_beta, double cutoff, double* energy, double* force);
+                           double ewald_beta, double cutoff, double* energy, double* force,
+                           double* virial);
 
 /*
  * vdW hydrogen reduction (AMOEBA's Halgren term puts a hydrogen's vdW site on

@@ -56,7 +56,7 @@ __device__ __forceinline__ V3 image(const double* xyz, int i, int j, double box,
 // with d_k = r_katom - r_i (minimum image) and u_k = d_k / |d_k|.
 struct Frame {
   V3 x, y, z;
-  V3 dx;            // d_x (Z-then-X)
+  V3 dz, dx, dy;    // the frame vectors d_k (zero where a type takes none)
   V3 uz, ux, uy;    // unit vectors to the frame atoms
   V3 a;             // the vector orthogonalised against z
   double nz, nx, ny, ns, nw;   // |d_z|, |d_x|, |d_y|, |sum| (types 2, 5), |a - (a.z) z|
@@ -84,10 +84,10 @@ __device__ __forceinline__ bool frame_ok(int type, int i, const int32_t* fa, int
 __device__ __forceinline__ Frame make_frame(const double* xyz, double box, double inv_box, int type,
                                             int i, const int32_t* fa) {
   Frame f;
-  const V3 dz = image(xyz, i, fa[0], box, inv_box);
-  f.nz = sqrt(dot(dz, dz));
-  f.uz = (1.0 / f.nz) * dz;
-  f.dx = v3(0.0, 0.0, 0.0);
+  f.dz = image(xyz, i, fa[0], box, inv_box);
+  f.nz = sqrt(dot(f.dz, f.dz));
+  f.uz = (1.0 / f.nz) * f.dz;
+  f.dx = f.dy = v3(0.0, 0.0, 0.0);
   f.ux = f.uy = f.dx;
   f.nx = f.ny = 1.0;
   if (type != 3) {
@@ -96,9 +96,9 @@ __device__ __forceinline__ Frame make_frame(const double* xyz, double box, doubl
     f.ux = (1.0 / f.nx) * f.dx;
   }
   if (type >= 4) {
-    const V3 dy = image(xyz, i, fa[2], box, inv_box);
-    f.ny = sqrt(dot(dy, dy));
-    f.uy = (1.0 / f.ny) * dy;
+    f.dy = image(xyz, i, fa[2], box, inv_box);
+    f.ny = sqrt(dot(f.dy, f.dy));
+    f.uy = (1.0 / f.ny) * f.dy;
   }
   f.ns = 0.0;
   if (type == 2 || type == 5) {
@@ -174,7 +174,10 @@ __device__ __forceinline__ V3 back_unit(V3 g, V3 u, double nrm) {
   return (1.0 / nrm) * (g - dot(g, u) * u);
 }
 
-// Frame forces of site i: dE/dM = G (10) -> dE/dR -> dE/d(d_z, d_x).
+// Frame forces of site i: dE/dM = G (10) -> dE/dR -> dE/d(d_z, d_x, d_y).
+// vpart (nullable): per-workgroup partials of the frame virial
+// sum_k d_k (x) dE/dd_k (M depends on positions only through the frame
+// vectors), summed in a fixed order: waves, then the workgroup's waves.
 __global__ __launch_bounds__(256) void k_frames_torque(int n, const double* __restrict__ xyz,
                                                        double box, const int32_t* __restrict__ ftype,
                                                        const int32_t* __restrict__ fatoms,
@@ -182,73 +185,114 @@ __global__ __launch_bounds__(256) void k_frames_torque(int n, const double* __re
                                                        const double* __restrict__ G,
                                                        double* __restrict__ force,
                                                        const int* __restrict__ flag,
-                                                       double* __restrict__ energy) {
+                                                       double* __restrict__ energy,
+                                                       double* __restrict__ vpart) {
   // G: dE/dM per site (10)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0 && flag[0]) {   // a frame was refused: no number is returned as if it were right
 #pragma unroll
     for (int k = 0; k < 3; ++k) energy[k] = __builtin_nan("");
   }
-  if (i >= n) return;
-  const int type = ftype[i];
-  const int32_t fa[3] = {fatoms[3 * i], fatoms[3 * i + 1], fatoms[3 * i + 2]};
-  if (type == 0 || !frame_ok(type, i, fa, n)) return;
-  const Frame f = make_frame(xyz, box, 1.0 / box, type, i, fa);
-  const double* l = loc + 10 * i;
-  const double* g = G + 10 * i;
-  const double R[3][3] = {{f.x.x, f.y.x, f.z.x}, {f.x.y, f.y.y, f.z.y}, {f.x.z, f.y.z, f.z.z}};
-  const double tl[3][3] = {{l[4], l[5], l[6]}, {l[5], l[7], l[8]}, {l[6], l[8], l[9]}};
-  // W: stored-component derivative as a symmetric matrix, diagonal doubled
-  const double W[3][3] = {{2.0 * g[4], g[5], g[6]}, {g[5], 2.0 * g[7], g[8]}, {g[6], g[8], 2.0 * g[9]}};
-  double RT[3][3];
+  double wv[9];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) RT[a][d] = R[a][0] * tl[0][d] + R[a][1] * tl[1][d] + R[a][2] * tl[2][d];
-  double dR[3][3];   // dE/dR_cd = G_mu,c mu_loc,d + (W R Theta_loc)_cd
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      dR[c][d] = g[1 + c] * l[1 + d] + W[c][0] * RT[0][d] + W[c][1] * RT[1][d] + W[c][2] * RT[2][d];
-  V3 gx = v3(dR[0][0], dR[1][0], dR[2][0]);
-  V3 gy = v3(dR[0][1], dR[1][1], dR[2][1]);
-  V3 gz = v3(dR[0][2], dR[1][2], dR[2][2]);
-  // y = z x x
-  gz = gz + cross(f.x, gy);
-  gx = gx + cross(gy, f.z);
-  // x = unit(w), w = a - (a.z) z
-  const V3 gw = back_unit(gx, f.x, f.nw);
-  const double az = dot(f.a, f.z), gwz = dot(gw, f.z);
-  const V3 ga = gw - gwz * f.z;
-  gz = gz - az * gw - gwz * f.a;
-  // back through z and a to d_z, d_x, d_y
-  const V3 zero = v3(0.0, 0.0, 0.0);
-  V3 gdz, gdx = zero, gdy = zero;
-  if (type == 2 || type == 5) {   // z = unit(s), s = u_z + u_x (+ u_y)
-    const V3 gs = back_unit(gz, f.z, f.ns);
-    gdz = back_unit(gs, f.uz, f.nz);
-    gdx = back_unit(gs + ga, f.ux, f.nx);   // a = u_x
-    if (type == 5) gdy = back_unit(gs, f.uy, f.ny);
-  } else {                        // z = u_z
-    gdz = back_unit(gz, f.uz, f.nz);
-    if (type == 1) gdx = ga;      // a = d_x
-    if (type == 4) {              // a = u_x + u_y
-      gdx = back_unit(ga, f.ux, f.nx);
-      gdy = back_unit(ga, f.uy, f.ny);
-    }                             // type 3: a is fixed
+  for (int k = 0; k < 9; ++k) wv[k] = 0.0;
+  const int type = i < n ? ftype[i] : 0;
+  int32_t fa[3] = {-1, -1, -1};
+  if (i < n) {
+    fa[0] = fatoms[3 * i];
+    fa[1] = fatoms[3 * i + 1];
+    fa[2] = fatoms[3 * i + 2];
   }
-  // d_k = r_k - r_i; F = -dE/dr
-  const int m = frame_natoms(type);
-  const double gzv[3] = {gdz.x, gdz.y, gdz.z}, gxv[3] = {gdx.x, gdx.y, gdx.z},
-               gyv[3] = {gdy.x, gdy.y, gdy.z};
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    atomicAdd(&force[3 * fa[0] + c], -gzv[c]);
-    if (m >= 2) atomicAdd(&force[3 * fa[1] + c], -gxv[c]);
-    if (m >= 3) atomicAdd(&force[3 * fa[2] + c], -gyv[c]);
-    atomicAdd(&force[3 * i + c], gzv[c] + gxv[c] + gyv[c]);
+  if (type != 0 && frame_ok(type, i, fa, n)) {
+    const Frame f = make_frame(xyz, box, 1.0 / box, type, i, fa);
+    const double* l = loc + 10 * i;
+    const double* g = G + 10 * i;
+    const double R[3][3] = {{f.x.x, f.y.x, f.z.x}, {f.x.y, f.y.y, f.z.y}, {f.x.z, f.y.z, f.z.z}};
+    const double tl[3][3] = {{l[4], l[5], l[6]}, {l[5], l[7], l[8]}, {l[6], l[8], l[9]}};
+    // W: stored-component derivative as a symmetric matrix, diagonal doubled
+    const double W[3][3] = {{2.0 * g[4], g[5], g[6]}, {g[5], 2.0 * g[7], g[8]}, {g[6], g[8], 2.0 * g[9]}};
+    double RT[3][3];
+  #pragma unroll
+    for (int a = 0; a < 3; ++a)
+  #pragma unroll
+      for (int d = 0; d < 3; ++d) RT[a][d] = R[a][0] * tl[0][d] + R[a][1] * tl[1][d] + R[a][2] * tl[2][d];
+    double dR[3][3];   // dE/dR_cd = G_mu,c mu_loc,d + (W R Theta_loc)_cd
+  #pragma unroll
+    for (int c = 0; c < 3; ++c)
+  #pragma unroll
+      for (int d = 0; d < 3; ++d)
+        dR[c][d] = g[1 + c] * l[1 + d] + W[c][0] * RT[0][d] + W[c][1] * RT[1][d] + W[c][2] * RT[2][d];
+    V3 gx = v3(dR[0][0], dR[1][0], dR[2][0]);
+    V3 gy = v3(dR[0][1], dR[1][1], dR[2][1]);
+    V3 gz = v3(dR[0][2], dR[1][2], dR[2][2]);
+    // y = z x x
+    gz = gz + cross(f.x, gy);
+    gx = gx + cross(gy, f.z);
+    // x = unit(w), w = a - (a.z) z
+    const V3 gw = back_unit(gx, f.x, f.nw);
+    const double az = dot(f.a, f.z), gwz = dot(gw, f.z);
+    const V3 ga = gw - gwz * f.z;
+    gz = gz - az * gw - gwz * f.a;
+    // back through z and a to d_z, d_x, d_y
+    const V3 zero = v3(0.0, 0.0, 0.0);
+    V3 gdz, gdx = zero, gdy = zero;
+    if (type == 2 || type == 5) {   // z = unit(s), s = u_z + u_x (+ u_y)
+      const V3 gs = back_unit(gz, f.z, f.ns);
+      gdz = back_unit(gs, f.uz, f.nz);
+      gdx = back_unit(gs + ga, f.ux, f.nx);   // a = u_x
+      if (type == 5) gdy = back_unit(gs, f.uy, f.ny);
+    } else {                        // z = u_z
+      gdz = back_unit(gz, f.uz, f.nz);
+      if (type == 1) gdx = ga;      // a = d_x
+      if (type == 4) {              // a = u_x + u_y
+        gdx = back_unit(ga, f.ux, f.nx);
+        gdy = back_unit(ga, f.uy, f.ny);
+      }                             // type 3: a is fixed
+    }
+    // d_k = r_k - r_i; F = -dE/dr
+    const int m = frame_natoms(type);
+    const double gzv[3] = {gdz.x, gdz.y, gdz.z}, gxv[3] = {gdx.x, gdx.y, gdx.z},
+                 gyv[3] = {gdy.x, gdy.y, gdy.z};
+  #pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      atomicAdd(&force[3 * fa[0] + c], -gzv[c]);
+      if (m >= 2) atomicAdd(&force[3 * fa[1] + c], -gxv[c]);
+      if (m >= 3) atomicAdd(&force[3 * fa[2] + c], -gyv[c]);
+      atomicAdd(&force[3 * i + c], gzv[c] + gxv[c] + gyv[c]);
+    }
+    const double dzv[3] = {f.dz.x, f.dz.y, f.dz.z}, dxv[3] = {f.dx.x, f.dx.y, f.dx.z},
+                 dyv[3] = {f.dy.x, f.dy.y, f.dy.z};
+  #pragma unroll
+    for (int a = 0; a < 3; ++a)
+  #pragma unroll
+      for (int b = 0; b < 3; ++b)
+        wv[3 * a + b] = dzv[a] * gzv[b] + dxv[a] * gxv[b] + dyv[a] * gyv[b];
   }
+  if (!vpart) return;   // uniform over the launch
+  __shared__ double red[4][9];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    for (int o = 32; o > 0; o >>= 1) wv[k] += __shfl_xor(wv[k], o);
+    if (lane == 0) red[wid][k] = wv[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double t = 0.0;
+    for (int ww = 0; ww < (int)(blockDim.x >> 6); ++ww) t += red[ww][threadIdx.x];
+    vpart[9 * blockIdx.x + threadIdx.x] = t;
+  }
+}
+
+// virial[k] += the frame partials of nb workgroups, in order; NaN when a
+// frame was refused
+__global__ void k_frames_virial(int nb, const double* __restrict__ vpart,
+                                const int* __restrict__ flag, double* __restrict__ virial) {
+  const int k = threadIdx.x;
+  if (k >= 9) return;
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += vpart[9 * b + k];
+  virial[k] = flag[0] ? __builtin_nan("") : virial[k] + t;
 }
 
 // vdW hydrogen reduction: site i at r_p + red_i (r_i - r_p) (minimum image)
@@ -335,7 +379,7 @@ tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
                            const tk_nblist* list, const int32_t* frame_type,
                            const int32_t* frame_atoms, const double* mpole_local,
                            double ewald_beta, double cutoff, double* energy, double* force,
-                           double* mpole_global) {
+                           double* virial, double* mpole_global) {
   if (!ctx) return TK_E_ARG;
   tk_status s = check_system(sys);
   if (s) return s;
@@ -346,12 +390,14 @@ tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
   const int n = sys->n;
   if (n == 0) {
     TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
+    if (virial) TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
     return TK_OK;
   }
   if (!frame_type || !frame_atoms || !mpole_local || !force) return TK_E_ARG;
   void *mg, *G, *vir, *flag;
   if ((s = scratch(ctx, per_stream("frames_G", st).c_str(), sizeof(double) * 10 * (size_t)n, &G)) ||
-      (s = scratch(ctx, per_stream("frames_vir", st).c_str(), sizeof(double) * 9, &vir)) ||
+      (s = scratch(ctx, per_stream("frames_vir", st).c_str(),
+                   sizeof(double) * 9 * (1 + (size_t)ceil_div(n, 256)), &vir)) ||
       (s = scratch(ctx, per_stream("frames_flag", st).c_str(), 64, &flag)))
     return s;
   if (mpole_global) {
@@ -369,7 +415,11 @@ tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
   ph.mpole = (const double*)mg;
   ph.molid = sys->molid;
   ph.g.set(sys->box, cutoff, ewald_beta);
-  if ((s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, (double*)vir))) return s;
+  // the pair virial goes to the caller's array (or scratch); the frame
+  // partials follow it in the scratch
+  double* wpair = virial ? virial : (double*)vir;
+  double* wpart = virial ? (double*)vir + 9 : nullptr;
+  if ((s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, wpair))) return s;
   // dE/dM per site, then the frame forces
   MderivPh<double> pd;
   pd.xyz = sys->xyz;
@@ -381,8 +431,10 @@ tk_status tk_empole_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
     ProfScope ps(ctx, st, "frames_torque");
     k_frames_torque<<<ceil_div(n, 256), 256, 0, st>>>(n, sys->xyz, sys->box, frame_type,
                                                       frame_atoms, mpole_local, (const double*)G,
-                                                      force, (const int*)flag, energy);
+                                                      force, (const int*)flag, energy, wpart);
   }
+  if (virial)
+    k_frames_virial<<<1, 64, 0, st>>>(ceil_div(n, 256), wpart, (const int*)flag, virial);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }
@@ -391,7 +443,8 @@ tk_status tk_epolar_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
                            const tk_nblist* list, const int32_t* frame_type,
                            const int32_t* frame_atoms, const double* mpole_local,
                            const double* polarity, const double* thole, const double* mu,
-                           double ewald_beta, double cutoff, double* energy, double* force) {
+                           double ewald_beta, double cutoff, double* energy, double* force,
+                           double* virial) {
   if (!ctx) return TK_E_ARG;
   tk_status s = check_system(sys);
   if (s) return s;
@@ -402,13 +455,15 @@ tk_status tk_epolar_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
   const int n = sys->n;
   if (n == 0) {
     TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
+    if (virial) TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
     return TK_OK;
   }
   if (!frame_type || !frame_atoms || !mpole_local || !polarity || !thole || !mu || !force)
     return TK_E_ARG;
   void *mg, *G, *vir, *flag;
   if ((s = scratch(ctx, per_stream("frames_G", st).c_str(), sizeof(double) * 10 * (size_t)n, &G)) ||
-      (s = scratch(ctx, per_stream("frames_vir", st).c_str(), sizeof(double) * 9, &vir)) ||
+      (s = scratch(ctx, per_stream("frames_vir", st).c_str(),
+                   sizeof(double) * 9 * (1 + (size_t)ceil_div(n, 256)), &vir)) ||
       (s = scratch(ctx, per_stream("frames_flag", st).c_str(), 64, &flag)) ||
       (s = scratch(ctx, per_stream("frames_M", st).c_str(), sizeof(double) * 10 * (size_t)n, &mg)))
     return s;
@@ -424,7 +479,11 @@ tk_status tk_epolar_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
   ph.thole = thole;
   ph.mu = mu;
   ph.g.set(sys->box, cutoff, ewald_beta);
-  if ((s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, (double*)vir))) return s;
+  // the pair virial goes to the caller's array (or scratch); the frame
+  // partials follow it in the scratch
+  double* wpair = virial ? virial : (double*)vir;
+  double* wpart = virial ? (double*)vir + 9 : nullptr;
+  if ((s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, wpair))) return s;
   // dE/dM of the induced-permanent energy, then the frame forces
   MderivPolPh<double> pd;
   pd.xyz = sys->xyz;
@@ -438,8 +497,10 @@ tk_status tk_epolar_frames(tk_ctx* ctx, void* stream, const tk_system* sys,
     ProfScope ps(ctx, st, "frames_torque");
     k_frames_torque<<<ceil_div(n, 256), 256, 0, st>>>(n, sys->xyz, sys->box, frame_type,
                                                       frame_atoms, mpole_local, (const double*)G,
-                                                      force, (const int*)flag, energy);
+                                                      force, (const int*)flag, energy, wpart);
   }
+  if (virial)
+    k_frames_virial<<<1, 64, 0, st>>>(ceil_div(n, 256), wpart, (const int*)flag, virial);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }

@@ -112,13 +112,13 @@ _SIGS = {
                         _d, _d, _vp, _vp, _vp],
     "tk_rotate_mpole": [_vp, _vp, C.POINTER(System), _vp, _vp, _vp, _vp],
     "tk_empole_frames": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
-                         _vp, _vp, _vp],
+                         _vp, _vp, _vp, _vp],
     "tk_vdw_sites": [_vp, _vp, C.POINTER(System), _vp, _vp, _vp],
     "tk_vdw_site_forces": [_vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "tk_polarize_tcg1": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
                          _vp, _vp, _vp],
     "tk_epolar_frames": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _vp,
-                         _vp, _d, _d, _vp, _vp],
+                         _vp, _d, _d, _vp, _vp, _vp],
     "tk_evdw": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), C.c_int, _vp, _vp, _d, _d, _d, _d,
                 C.c_int, _vp, _vp, _vp],
     "tk_batch_step": [_vp, _vp, C.POINTER(Batch), C.POINTER(StepParams), _vp, _vp, _vp, _vp, _vp,
@@ -166,8 +166,13 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
-def _dev(t, dtype, device):
+def _dev(t, dtype, device, shape=None, what="array"):
+    """A contiguous device tensor of `dtype`; with `shape`, refused (ValueError)
+    unless it has exactly that shape: the kernels index every array by the
+    system's atom count, so a shorter one would be read out of bounds."""
     t = torch.as_tensor(t)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}; got {tuple(t.shape)}")
     return t.to(device=device, dtype=dtype).contiguous()
 
 
@@ -219,7 +224,9 @@ class Context:
     def system(self, xyz, box, molid):
         """Device copies of coordinates and molecule ids; returns a SystemRef."""
         x = _dev(xyz, torch.float64, self.device)
-        m = _dev(molid, torch.int32, self.device)
+        if x.dim() != 2 or x.shape[1] != 3:
+            raise ValueError(f"xyz must have shape (n, 3); got {tuple(x.shape)}")
+        m = _dev(molid, torch.int32, self.device, (x.shape[0],), "molid")
         return SystemRef(x, float(box), m)
 
     def nblist(self, sysref, cutoff, plan_slot=0, cap=None, want_csr=True):
@@ -277,7 +284,7 @@ class Context:
 
     # -- pair terms ------------------------------------------------------------
     def empole_real(self, sysref, lst, mpole, beta, cutoff, prec=FP64):
-        mp = _dev(mpole, torch.float64, self.device)
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
         e = torch.empty(3, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
@@ -287,7 +294,7 @@ class Context:
         return e, f, w
 
     def echarge_real(self, sysref, lst, q, beta, cutoff, prec=FP64):
-        qq = _dev(q, torch.float64, self.device)
+        qq = _dev(q, torch.float64, self.device, (sysref.n,), "q")
         e = torch.empty(3, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
@@ -297,9 +304,9 @@ class Context:
         return e, f, w
 
     def efield_direct(self, sysref, lst, mpole, polarity, thole, beta, cutoff, prec=FP64):
-        mp = _dev(mpole, torch.float64, self.device)
-        pol = _dev(polarity, torch.float64, self.device)
-        th = _dev(thole, torch.float64, self.device)
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
         out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         _check(load().tk_efield_direct(self._h, _stream(self.device), C.byref(sysref.c),
                                        C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), beta, cutoff,
@@ -307,9 +314,9 @@ class Context:
         return out
 
     def tmatvec(self, sysref, lst, polarity, thole, beta, cutoff, mu, include_diag=0, prec=FP64):
-        pol = _dev(polarity, torch.float64, self.device)
-        th = _dev(thole, torch.float64, self.device)
-        m = _dev(mu, torch.float64, self.device)
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        m = _dev(mu, torch.float64, self.device, (sysref.n, 3), "mu")
         out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         _check(load().tk_tmatvec(self._h, _stream(self.device), C.byref(sysref.c), C.byref(lst.c),
                                  _ptr(pol), _ptr(th), beta, cutoff, int(include_diag), prec,
@@ -318,10 +325,11 @@ class Context:
 
     def polarize_pcg(self, sysref, lst, mpole, polarity, thole, beta, cutoff, tol_debye=1e-5,
                      maxiter=100, prec=FP64, mu_guess=None):
-        mp = _dev(mpole, torch.float64, self.device)
-        pol = _dev(polarity, torch.float64, self.device)
-        th = _dev(thole, torch.float64, self.device)
-        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device)
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device,
+                                               (sysref.n, 3), "mu_guess")
         out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         info = PcgInfo()
         st = load().tk_polarize_pcg(self._h, _stream(self.device), C.byref(sysref.c),
@@ -334,10 +342,11 @@ class Context:
 
     def polarize_pcg_ewald(self, sysref, lst, mpole, polarity, thole, beta, cutoff, grid,
                            order=5, tol_debye=1e-5, maxiter=100, mu_guess=None):
-        mp = _dev(mpole, torch.float64, self.device)
-        pol = _dev(polarity, torch.float64, self.device)
-        th = _dev(thole, torch.float64, self.device)
-        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device)
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device,
+                                               (sysref.n, 3), "mu_guess")
         out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         info = PcgInfo()
         st = load().tk_polarize_pcg_ewald(self._h, _stream(self.device), C.byref(sysref.c),
@@ -351,10 +360,11 @@ class Context:
     def polarize_pcg2(self, sysref, lst, mpole, polarity, thole, beta, cutoff, pscale,
                       tol_debye=1e-5, maxiter=100, mu_guess=None):
         """Both dipole sets: returns (mu[2,n,3] with mu_d first, [info_d, info_p])."""
-        mp = _dev(mpole, torch.float64, self.device)
-        pol = _dev(polarity, torch.float64, self.device)
-        th = _dev(thole, torch.float64, self.device)
-        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device)
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device,
+                                               (2, sysref.n, 3), "mu_guess")
         out = torch.empty((2, sysref.n, 3), dtype=torch.float64, device=self.device)
         info = (PcgInfo * 2)()
         st = load().tk_polarize_pcg2(self._h, _stream(self.device), C.byref(sysref.c),
@@ -366,10 +376,10 @@ class Context:
         return out, [{k: getattr(info[v], k) for k, _ in PcgInfo._fields_} for v in range(2)]
 
     def epolar_real(self, sysref, lst, mpole, polarity, thole, mu, beta, cutoff, prec=FP64):
-        mp = _dev(mpole, torch.float64, self.device)
-        pol = _dev(polarity, torch.float64, self.device)
-        th = _dev(thole, torch.float64, self.device)
-        m = _dev(mu, torch.float64, self.device)
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        m = _dev(mu, torch.float64, self.device, (sysref.n, 3), "mu")
         e = torch.empty(3, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
@@ -380,10 +390,10 @@ class Context:
 
     def epolar2_real(self, sysref, lst, mpole, polarity, thole, mu2, beta, cutoff, pscale):
         """Polarization forces with both dipole sets mu2[2,n,3] (mu_d first)."""
-        mp = _dev(mpole, torch.float64, self.device)
-        pol = _dev(polarity, torch.float64, self.device)
-        th = _dev(thole, torch.float64, self.device)
-        m = _dev(mu2, torch.float64, self.device)
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        m = _dev(mu2, torch.float64, self.device, (2, sysref.n, 3), "mu2")
         e = torch.empty(3, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
@@ -394,7 +404,7 @@ class Context:
         return e, f, w
 
     def pme_mpole(self, sysref, mpole, beta, grid, order=5, want_field=True):
-        mp = _dev(mpole, torch.float64, self.device)
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
         e = torch.empty(1, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         fld = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device) if want_field \
@@ -416,7 +426,7 @@ class Context:
 
     def rotate_mpole(self, sysref, frame_type, frame_atoms, mpole_local):
         ft, fa = self._frames(sysref, frame_type, frame_atoms)
-        ml = _dev(mpole_local, torch.float64, self.device)
+        ml = _dev(mpole_local, torch.float64, self.device, (sysref.n, 10), "mpole_local")
         out = torch.empty((sysref.n, 10), dtype=torch.float64, device=self.device)
         _check(load().tk_rotate_mpole(self._h, _stream(self.device), C.byref(sysref.c), _ptr(ft),
                                       _ptr(fa), _ptr(ml), _ptr(out)), "tk_rotate_mpole")
@@ -424,36 +434,40 @@ class Context:
 
     def empole_frames(self, sysref, lst, frame_type, frame_atoms, mpole_local, beta, cutoff):
         ft, fa = self._frames(sysref, frame_type, frame_atoms)
-        ml = _dev(mpole_local, torch.float64, self.device)
+        ml = _dev(mpole_local, torch.float64, self.device, (sysref.n, 10), "mpole_local")
         e = torch.empty(3, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
         mg = torch.empty((sysref.n, 10), dtype=torch.float64, device=self.device)
         _check(load().tk_empole_frames(self._h, _stream(self.device), C.byref(sysref.c),
                                        C.byref(lst.c), _ptr(ft), _ptr(fa), _ptr(ml), beta, cutoff,
-                                       _ptr(e), _ptr(f), _ptr(mg)), "tk_empole_frames")
-        return e, f, mg
+                                       _ptr(e), _ptr(f), _ptr(w), _ptr(mg)), "tk_empole_frames")
+        return e, f, mg, w
 
     def vdw_sites(self, sysref, parent, red):
-        par = _dev(parent, torch.int32, self.device)
-        rd = _dev(red, torch.float64, self.device)
+        par = _dev(parent, torch.int32, self.device, (sysref.n,), "parent")
+        rd = _dev(red, torch.float64, self.device, (sysref.n,), "red")
         out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         _check(load().tk_vdw_sites(self._h, _stream(self.device), C.byref(sysref.c), _ptr(par),
                                    _ptr(rd), _ptr(out)), "tk_vdw_sites")
         return out
 
     def vdw_site_forces(self, parent, red, site_force):
-        par = _dev(parent, torch.int32, self.device)
-        rd = _dev(red, torch.float64, self.device)
         fs = _dev(site_force, torch.float64, self.device)
+        n = fs.shape[0]
+        if fs.dim() != 2 or fs.shape[1] != 3:
+            raise ValueError(f"site_force must have shape (n, 3); got {tuple(fs.shape)}")
+        par = _dev(parent, torch.int32, self.device, (n,), "parent")
+        rd = _dev(red, torch.float64, self.device, (n,), "red")
         out = torch.empty_like(fs)
         _check(load().tk_vdw_site_forces(self._h, _stream(self.device), int(fs.shape[0]), _ptr(par),
                                          _ptr(rd), _ptr(fs), _ptr(out)), "tk_vdw_site_forces")
         return out
 
     def polarize_tcg1(self, sysref, lst, mpole, polarity, thole, beta, cutoff, forces=True):
-        mp = _dev(mpole, torch.float64, self.device)
-        pol = _dev(polarity, torch.float64, self.device)
-        th = _dev(thole, torch.float64, self.device)
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
         mu = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         e = torch.empty(1, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device) if forces else None
@@ -465,22 +479,23 @@ class Context:
     def epolar_frames(self, sysref, lst, frame_type, frame_atoms, mpole_local, polarity, thole, mu,
                       beta, cutoff):
         ft, fa = self._frames(sysref, frame_type, frame_atoms)
-        ml = _dev(mpole_local, torch.float64, self.device)
-        pol = _dev(polarity, torch.float64, self.device)
-        th = _dev(thole, torch.float64, self.device)
-        m = _dev(mu, torch.float64, self.device)
+        ml = _dev(mpole_local, torch.float64, self.device, (sysref.n, 10), "mpole_local")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        m = _dev(mu, torch.float64, self.device, (sysref.n, 3), "mu")
         e = torch.empty(3, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        w = torch.empty((3, 3), dtype=torch.float64, device=self.device)
         _check(load().tk_epolar_frames(self._h, _stream(self.device), C.byref(sysref.c),
                                        C.byref(lst.c), _ptr(ft), _ptr(fa), _ptr(ml), _ptr(pol),
-                                       _ptr(th), _ptr(m), beta, cutoff, _ptr(e), _ptr(f)),
+                                       _ptr(th), _ptr(m), beta, cutoff, _ptr(e), _ptr(f), _ptr(w)),
                "tk_epolar_frames")
-        return e, f
+        return e, f, w
 
     def evdw(self, sysref, lst, form, rad, eps, cutoff, taper_frac=0.9, dhal=0.07, ghal=0.12,
              prec=FP64):
-        r = _dev(rad, torch.float64, self.device)
-        ep = _dev(eps, torch.float64, self.device)
+        r = _dev(rad, torch.float64, self.device, (sysref.n,), "rad")
+        ep = _dev(eps, torch.float64, self.device, (sysref.n,), "eps")
         e = torch.empty(1, dtype=torch.float64, device=self.device)
         f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
         w = torch.empty((3, 3), dtype=torch.float64, device=self.device)

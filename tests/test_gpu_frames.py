@@ -68,6 +68,7 @@ def test_frames_fp64(ctx, name, frames):
     for k in range(3):
         assert abs(e[k] - eo[k]) <= 1e-10 * abs(eo[k]), (k, e[k], eo[k])
     assert fmax_rel(np_(f), fo) < 1e-8
+    assert np.abs(np_(vir) - vo).max() <= 1e-10 * np.abs(vo).max()
     assert np.abs(np_(mg) - go).max() <= 1e-13 * np.abs(go).max()
     # the frame part matters: forces at fixed lab-frame multipoles differ
     _, f_lab, _ = O.empole_real(w.xyz, w.box, w.molid, rp, cp, go, S["beta"], 7.0)
@@ -103,8 +104,8 @@ def test_frames_invalid_and_empty(ctx, tk):
     for y in (-1, ma[k, 1]):
         bad = ma.copy()
         bad[k, 2] = y
-        e, _, _, _ = ctx.empole_frames(sysr, lst, mt, bad, loc, S["beta"], 7.0)
-        assert np.all(np.isnan(np_(e)))
+        e, _, _, w = ctx.empole_frames(sysr, lst, mt, bad, loc, S["beta"], 7.0)
+        assert np.all(np.isnan(np_(e))) and np.all(np.isnan(np_(w)))
     with pytest.raises(ValueError):   # frame atoms are [n, 3]
         ctx.rotate_mpole(sysr, ft, fa[:, :2], loc)
     empty = ctx.system(np.zeros((0, 3)), 20.0, np.zeros(0, np.int32))
@@ -154,3 +155,4 @@ def test_epolar_frames_fp64(ctx, name, frames):
     for k in range(3):
         assert abs(e[k] - eo[k]) <= 1e-10 * abs(eo[k]), (k, e[k], eo[k])
     assert fmax_rel(np_(f), fo) < 1e-8
+    assert np.abs(np_(vir) - vo).max() <= 1e-10 * np.abs(vo).max()
