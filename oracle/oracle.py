@@ -63,6 +63,10 @@ def lib():
         L.or_polarize_pcg2.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
                                        C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
                                        C.c_void_p, _dp, C.POINTER(PcgInfo * 2)]
+        L.or_polarize_pcg2_ewald.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp,
+                                             _dp, C.c_double, C.c_double, C.c_int, C.c_int,
+                                             C.c_double, C.c_double, C.c_int, C.c_void_p, _dp,
+                                             C.POINTER(PcgInfo * 2)]
         L.or_tmatvec.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _dp, _dp, C.c_double,
                                  C.c_double, C.c_int, _dp, _dp]
         L.or_polarize_pcg.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _dp, _dp, _dp,
@@ -335,6 +339,26 @@ def polarize_pcg2(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta,
     st = lib().or_polarize_pcg2(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _d(mpole),
                                 _d(polarity), _d(thole_a), beta, cutoff, float(pscale), tol_debye,
                                 int(maxiter), guess, mu, C.byref(info))
+    if st not in (OK, E_NOCONV, E_BREAKDOWN):
+        raise OracleError(st)
+    return mu, [{k: getattr(info[v], k) for k, _ in PcgInfo._fields_} for v in range(2)]
+
+
+def polarize_pcg2_ewald(xyz, box, molid, row_ptr, col, mpole, polarity, thole_a, beta, cutoff,
+                        grid, pscale, order=5, tol_debye=1e-5, maxiter=100, mu_guess=None):
+    """Both dipole sets with the full Ewald operator; returns as polarize_pcg2."""
+    xyz = _d(xyz)
+    n = xyz.shape[0]
+    mu = np.zeros((2, n, 3))
+    info = (PcgInfo * 2)()
+    guess = None
+    if mu_guess is not None:
+        guess_arr = _d(np.asarray(mu_guess).reshape(2, n, 3))
+        guess = guess_arr.ctypes.data_as(C.c_void_p)
+    st = lib().or_polarize_pcg2_ewald(n, xyz, box, _i(molid), _i(row_ptr), _i(col), _d(mpole),
+                                      _d(polarity), _d(thole_a), beta, cutoff, int(grid),
+                                      int(order), float(pscale), tol_debye, int(maxiter), guess,
+                                      mu, C.byref(info))
     if st not in (OK, E_NOCONV, E_BREAKDOWN):
         raise OracleError(st)
     return mu, [{k: getattr(info[v], k) for k, _ in PcgInfo._fields_} for v in range(2)]

@@ -710,11 +710,11 @@ int or_polarize_pcg_ewald(int n, const double* xyz, double box, const int32_t* m
  * also -1/2 C mu_p.E_d, up to the residuals.  info[0] is mu_d's solve with
  * epol = -1/2 C mu_d.E_p; info[1] is mu_p's with epol = -1/2 C mu_p.E_d.
  * mu_guess (nullable) and mu_out are [2][n][3], mu_d first. */
-int or_polarize_pcg2(int n, const double* xyz, double box, const int32_t* molid,
-                     const int32_t* row_ptr, const int32_t* col, const double* mpole,
-                     const double* polarity, const double* thole, double beta, double rc,
-                     double pscale, double tol_debye, int maxiter, const double* mu_guess,
-                     double* mu_out, or_pcg_info* info) {
+static int or_pcg2(int n, const double* xyz, double box, const int32_t* molid,
+                   const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                   const double* polarity, const double* thole, double beta, double rc,
+                   const or_recip* rp, double pscale, double tol_debye, int maxiter,
+                   const double* mu_guess, double* mu_out, or_pcg_info* info) {
   int st = or_pcg_args(n, box, rc, polarity, tol_debye, maxiter);
   if (st) return st;
   if (!(pscale >= 0.0 && pscale <= 1.0)) return OR_E_ARG;
@@ -723,11 +723,23 @@ int or_polarize_pcg2(int n, const double* xyz, double box, const int32_t* molid,
   double* ep = (double*)malloc(sizeof(double) * m);
   or_efield_scaled(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, 0.0, ed);
   or_efield_scaled(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, pscale, ep);
+  if (rp) {   /* the reciprocal permanent field joins both (no molecule scaling there) */
+    double e;
+    double* f = (double*)malloc(sizeof(double) * m);
+    double* fr = (double*)malloc(sizeof(double) * m);
+    or_pme_mpole(n, xyz, box, mpole, beta, rp->K, rp->p, &e, f, fr);
+    for (int k = 0; k < 3 * n; ++k) {
+      ed[k] += fr[k];
+      ep[k] += fr[k];
+    }
+    free(f);
+    free(fr);
+  }
   double* mud = mu_out;
   double* mup = mu_out + 3 * (size_t)n;
-  int sd = or_pcg_iterate(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, NULL, ed,
+  int sd = or_pcg_iterate(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, rp, ed,
                           tol_debye, maxiter, mu_guess, mud, &info[0]);
-  int sp = or_pcg_iterate(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, NULL, ep,
+  int sp = or_pcg_iterate(n, xyz, box, row_ptr, col, polarity, thole, beta, rc, rp, ep,
                           tol_debye, maxiter, mu_guess ? mu_guess + 3 * (size_t)n : NULL, mup,
                           &info[1]);
   double dp = 0.0, pd = 0.0;
@@ -740,6 +752,29 @@ int or_polarize_pcg2(int n, const double* xyz, double box, const int32_t* molid,
   free(ed);
   free(ep);
   return sd ? sd : sp;
+}
+
+int or_polarize_pcg2(int n, const double* xyz, double box, const int32_t* molid,
+                     const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                     const double* polarity, const double* thole, double beta, double rc,
+                     double pscale, double tol_debye, int maxiter, const double* mu_guess,
+                     double* mu_out, or_pcg_info* info) {
+  return or_pcg2(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, NULL, pscale,
+                 tol_debye, maxiter, mu_guess, mu_out, info);
+}
+
+/* Both sets with the full Ewald operator (as or_polarize_pcg_ewald): the PME
+ * dipole field in A, and the PME field of the permanent multipoles added to
+ * both right-hand sides. */
+int or_polarize_pcg2_ewald(int n, const double* xyz, double box, const int32_t* molid,
+                           const int32_t* row_ptr, const int32_t* col, const double* mpole,
+                           const double* polarity, const double* thole, double beta, double rc,
+                           int K, int p, double pscale, double tol_debye, int maxiter,
+                           const double* mu_guess, double* mu_out, or_pcg_info* info) {
+  if (!(beta > 0.0) || K < 2 * p || p < 5 || p > 8) return OR_E_ARG;
+  or_recip rp = {K, p};
+  return or_pcg2(n, xyz, box, molid, row_ptr, col, mpole, polarity, thole, beta, rc, &rp, pscale,
+                 tol_debye, maxiter, mu_guess, mu_out, info);
 }
 
 /* ------------------------------------------------------------------------ */

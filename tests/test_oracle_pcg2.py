@@ -224,3 +224,38 @@ def test_two_set_force_is_gradient_of_epol():
             xm[i, a] -= h
             g = (solve(xp)[1] - solve(xm)[1]) / (2 * h)
             assert F[i, a] == pytest.approx(-g, rel=1e-6, abs=1e-8 * np.abs(F).max())
+
+
+# --- both sets with the full Ewald operator ---------------------------------
+def test_pcg2_ewald_reduces_to_the_one_set_ewald_solve():
+    wb, rp, cp, beta, rc = small_water()
+    kw = dict(tol_debye=1e-8, maxiter=100)
+    mu1, info1 = O.polarize_pcg_ewald(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity,
+                                      wb.thole, beta, rc, 16, order=5, **kw)
+    mu, info = O.polarize_pcg2_ewald(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity,
+                                     wb.thole, beta, rc, 16, 0.0, order=5, **kw)
+    assert np.array_equal(mu[0], mu1) and np.array_equal(mu[1], mu1)
+    assert all(i["iters"] == info1["iters"] and i["epol"] == info1["epol"] for i in info)
+    distinct = np.arange(wb.n, dtype=np.int32)
+    mu_all, info_all = O.polarize_pcg_ewald(wb.xyz, wb.box, distinct, rp, cp, wb.mpole,
+                                            wb.polarity, wb.thole, beta, rc, 16, order=5, **kw)
+    mu, info = O.polarize_pcg2_ewald(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity,
+                                     wb.thole, beta, rc, 16, 1.0, order=5, **kw)
+    assert np.array_equal(mu[1], mu_all) and info[1]["iters"] == info_all["iters"]
+    assert np.array_equal(mu[0], mu1)
+
+
+def test_pcg2_ewald_energy_forms_agree_and_differ_from_real_space():
+    wb, rp, cp, beta, rc = small_water()
+    mu, info = O.polarize_pcg2_ewald(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity,
+                                     wb.thole, beta, rc, 16, 0.5, order=5, tol_debye=1e-10,
+                                     maxiter=200)
+    assert all(i["converged"] == 1 for i in info)
+    # -C/2 mu_d.E_p = -C/2 mu_p.E_d for the symmetric full operator
+    assert info[0]["epol"] == pytest.approx(info[1]["epol"], rel=1e-9)
+    mr, ir = O.polarize_pcg2(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity, wb.thole,
+                             beta, rc, 0.5, tol_debye=1e-10, maxiter=200)
+    assert abs(info[0]["epol"] - ir[0]["epol"]) > 1e-3 * abs(ir[0]["epol"])
+    with pytest.raises(O.OracleError):
+        O.polarize_pcg2_ewald(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity, wb.thole,
+                              beta, rc, 16, 1.5, order=5)
