@@ -470,6 +470,13 @@ def pme_leg(ctx, tk, w, grid=64, order=5):
     out["pcg_ewald_iters"] = info["ewald"]["iters"]
     out["pcg_real_ms"] = round(timed(real, 10, 2) * 1e3, 4)
     out["pcg_real_iters"] = info["real"]["iters"]
+
+    def ewald2():   # both dipole sets (same-molecule factor 0.5 in the second field)
+        _, info["ewald2"] = ctx.polarize_pcg2_ewald(sysw, l7, mp, pol, th, s["beta"],
+                                                    s["rc_ewald"], grid, 0.5, order=order,
+                                                    tol_debye=s["tol_debye"], maxiter=s["maxiter"])
+    out["pcg2_ewald_ms"] = round(timed(ewald2, 10, 2) * 1e3, 4)
+    out["pcg2_ewald_iters"] = [i["iters"] for i in info["ewald2"]]
     return out
 
 

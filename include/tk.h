@@ -257,14 +257,29 @@ tk_status tk_polarize_pcg_ewald(tk_ctx* ctx, void* stream, const tk_system* sys,
  * device [2][n][3], written in stream order.  info: HOST [2], info[0] for
  * mu_d with epol = -1/2 C mu_d.E_p, info[1] for mu_p with
  * epol = -1/2 C mu_p.E_d (equal up to the residuals, A being symmetric).
- * FP64, real space only.  Returns info[0].status if not TK_OK, else
- * info[1].status.  Synchronises `stream` while solving.
+ * FP64, real space (tk_polarize_pcg2_ewald adds the reciprocal part).
+ * Returns info[0].status if not TK_OK, else info[1].status.  Synchronises `stream` while solving.
  */
 tk_status tk_polarize_pcg2(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
                            const double* mpole, const double* polarity, const double* thole,
                            double ewald_beta, double cutoff, double pscale, double tol_debye,
                            int32_t maxiter, const double* mu_guess, double* mu_out,
                            tk_pcg_info* info);
+
+/*
+ * Both dipole sets with the full Ewald operator: tk_polarize_pcg2 with the
+ * reciprocal space of tk_polarize_pcg_ewald.  The operator gains the PME
+ * field of the dipoles, and both right-hand sides gain the PME field of the
+ * permanent multipoles; the same-molecule scaling stays in real space.
+ * Arguments, outputs and errors as tk_polarize_pcg2; grid and order as
+ * tk_pme_mpole; ewald_beta > 0; FP64.
+ */
+tk_status tk_polarize_pcg2_ewald(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                 const tk_nblist* list, const double* mpole,
+                                 const double* polarity, const double* thole, double ewald_beta,
+                                 double cutoff, int32_t grid, int32_t order, double pscale,
+                                 double tol_debye, int32_t maxiter, const double* mu_guess,
+                                 double* mu_out, tk_pcg_info* info);
 
 /*
  * Polarization forces with both dipole sets of tk_polarize_pcg2 (the

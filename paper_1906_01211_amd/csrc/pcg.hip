@@ -252,11 +252,11 @@ struct MvArgs {
   double* part;         // [NV][2][ncells] per-cell partials
   const double* pz_cur;    // [NV][2][ncells] partials of r.z | z.z of iteration k
   const double* pz_prev;   // [NV][2][ncells] of iteration k - 1
-  // full Ewald operator (one system, one right-hand side, FP64): the PME
-  // field of the operand is subtracted from A v.  Modes 0, 2: rz = field of
-  // x.  Mode 1: rz = field of z_k, and the field of p_k = z_k + beta p_(k-1)
-  // is rz + beta rf_old (the field is linear), stored in rf_new for the next
-  // iteration.
+  // full Ewald operator (one system, FP64): the PME field of the operand is
+  // subtracted from A v (per right-hand side, blocks as the vectors).
+  // Modes 0, 2: rz = field of x.  Mode 1: rz = field of z_k, and the field
+  // of p_k = z_k + beta p_(k-1) is rz + beta rf_old (the field is linear),
+  // stored in rf_new for the next iteration.
   const double* rz;
   const double* rf_old;
   double* rf_new;
@@ -540,11 +540,11 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
         for (int ww = 0; ww < kMvWaves; ++ww) fs += ACC[ww * 3 * NV * OC + (3 * v + d) * nown + t];
         const double vv = lds[SD * (own0 + t) + 3 + 3 * v + d];
         double av = al > 0.0 ? vv / al - (fs + A.cself * vv) : 0.0;   // (A v)_s
-        if (NV == 1 && A.rz) {
-          double rf = A.rz[3 * s + d];
+        if (A.rz) {
+          double rf = A.rz[o + d];
           if (kMode == 1) {
-            if (A.k >= 1) rf = fma(beta[0], A.rf_old[3 * s + d], rf);
-            A.rf_new[3 * s + d] = rf;
+            if (A.k >= 1) rf = fma(beta[v], A.rf_old[o + d], rf);
+            A.rf_new[o + d] = rf;
           }
           if (al > 0.0) av -= rf;
         }
@@ -878,15 +878,21 @@ struct Solver {
   double* rz = nullptr;              // PME field of the current operand
   double* rfb[2] = {nullptr, nullptr};   // PME field of p_k (k even, odd)
 
-  // PME field of v (sorted) into rz; run_when_done as the iteration
-  // kernels: 0 while the solve runs, 1 for the stopped solve's residual,
-  // -1 always
+  // PME field of v (sorted) into rz, per right-hand side; run_when_done as
+  // the iteration kernels, on that right-hand side's state: 0 while it
+  // runs, 1 for its stopped solve's residual, -1 always
   tk_status queue_pme(const double* v, int run_when_done) {
     if (!pme_grid) return TK_OK;
-    const int32_t* done =
-        run_when_done < 0 ? nullptr : (const int32_t*)((const char*)state + offsetof(PcgState, done));
-    return pme_prepared_dipole_field(ctx, st, P->n, P->box, v, beta, pme_grid, pme_order, rz,
-                                     done, run_when_done < 0 ? 0 : run_when_done);
+    for (int k = 0; k < nv; ++k) {
+      const int32_t* done =
+          run_when_done < 0 ? nullptr
+                            : (const int32_t*)((const char*)(state + k) + offsetof(PcgState, done));
+      const tk_status s = pme_prepared_dipole_field(ctx, st, P->n, P->box, v + k * vs, beta,
+                                                    pme_grid, pme_order, rz + k * vs, done,
+                                                    run_when_done < 0 ? 0 : run_when_done);
+      if (s) return s;
+    }
+    return TK_OK;
   }
 
   template <class R>
@@ -1111,7 +1117,7 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   const int nsys = P->nsys;
   if (pme_grid && (prec != TK_FP64 || nsys != 1 || !pme_args_ok(pme_grid, pme_order)))
     return TK_E_ARG;
-  if (nv != 1 && (nv != 2 || prec != TK_FP64 || nsys != 1 || pme_grid)) return TK_E_ARG;
+  if (nv != 1 && (nv != 2 || prec != TK_FP64 || nsys != 1)) return TK_E_ARG;
   for (int k = 0; k < nsys * nv; ++k) info[k] = tk_pcg_info{};
   const int n = P->n;
   if (n == 0) {
@@ -1218,9 +1224,10 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
     S.gather_geometry();
   // full Ewald: the reciprocal permanent field joins the right-hand side (the
   // PME scratch is separate from the gathered coordinates above)
-  if (pme_grid && (s = pme_perm_field_add(ctx, st, &sys1, mpole, ewald_beta, pme_grid, pme_order,
-                                          (const int32_t*)P->perm.p, S.b)))
-    return s;
+  for (int v = 0; v < nv && pme_grid; ++v)
+    if ((s = pme_perm_field_add(ctx, st, &sys1, mpole, ewald_beta, pme_grid, pme_order,
+                                (const int32_t*)P->perm.p, S.b + v * S.vs)))
+      return s;
   // the sites of every iteration's dipole field: sorted and tabulated once
   if (pme_grid && (s = pme_prepare_sites(ctx, st, n, P->box, S.gathered, S.pstride, pme_grid,
                                          pme_order)))
@@ -1375,6 +1382,34 @@ extern "C" tk_status tk_polarize_pcg2(tk_ctx* ctx, void* stream, const tk_system
   if ((s = solve_dipoles(ctx, (hipStream_t)stream, P, sys->xyz, sys->molid, mpole, polarity, thole,
                          ewald_beta, cutoff, tol_debye, maxiter, TK_FP64, mu_guess, nullptr,
                          mu_out, info, 0, 0, 2, pscale)))
+    return s;
+  return info[0].status ? info[0].status : info[1].status;
+}
+
+extern "C" tk_status tk_polarize_pcg2_ewald(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                            const tk_nblist* list, const double* mpole,
+                                            const double* polarity, const double* thole,
+                                            double ewald_beta, double cutoff, int32_t grid,
+                                            int32_t order, double pscale, double tol_debye,
+                                            int32_t maxiter, const double* mu_guess,
+                                            double* mu_out, tk_pcg_info* info) {
+  if (!ctx || !info) return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (!(ewald_beta > 0.0) || !std::isfinite(ewald_beta) || !(tol_debye >= 0.0) || maxiter < 0 ||
+      !(pscale >= 0.0 && pscale <= 1.0) || !pme_args_ok(grid, order))
+    return TK_E_ARG;
+  const Plan* P;
+  if ((s = get_plan(ctx, sys, list, cutoff, &P))) return s;
+  info[0] = info[1] = tk_pcg_info{};
+  if (sys->n == 0) {
+    info[0].converged = info[1].converged = 1;
+    return TK_OK;
+  }
+  if (!mpole || !polarity || !thole || !mu_out) return TK_E_ARG;
+  if ((s = solve_dipoles(ctx, (hipStream_t)stream, P, sys->xyz, sys->molid, mpole, polarity, thole,
+                         ewald_beta, cutoff, tol_debye, maxiter, TK_FP64, mu_guess, nullptr,
+                         mu_out, info, grid, order, 2, pscale)))
     return s;
   return info[0].status ? info[0].status : info[1].status;
 }

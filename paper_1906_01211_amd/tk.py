@@ -108,6 +108,9 @@ _SIGS = {
                               _d, _i32, _i32, _d, _i32, _vp, _vp, C.POINTER(PcgInfo)],
     "tk_polarize_pcg2": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
                          _d, _d, _i32, _vp, _vp, C.POINTER(PcgInfo * 2)],
+    "tk_polarize_pcg2_ewald": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp,
+                               _d, _d, _i32, _i32, _d, _d, _i32, _vp, _vp,
+                               C.POINTER(PcgInfo * 2)],
     "tk_epolar2_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
                         _d, _d, _vp, _vp, _vp],
     "tk_rotate_mpole": [_vp, _vp, C.POINTER(System), _vp, _vp, _vp, _vp],
@@ -387,6 +390,25 @@ class Context:
                                      C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), _ptr(m), beta,
                                      cutoff, prec, _ptr(e), _ptr(f), _ptr(w)), "tk_epolar_real")
         return e, f, w
+
+    def polarize_pcg2_ewald(self, sysref, lst, mpole, polarity, thole, beta, cutoff, grid,
+                            pscale, order=5, tol_debye=1e-5, maxiter=100, mu_guess=None):
+        """Both dipole sets with the full Ewald operator; returns as polarize_pcg2."""
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device,
+                                               (2, sysref.n, 3), "mu_guess")
+        out = torch.empty((2, sysref.n, 3), dtype=torch.float64, device=self.device)
+        info = (PcgInfo * 2)()
+        st = load().tk_polarize_pcg2_ewald(self._h, _stream(self.device), C.byref(sysref.c),
+                                           C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), beta,
+                                           cutoff, int(grid), int(order), float(pscale),
+                                           tol_debye, int(maxiter), _ptr(g), _ptr(out),
+                                           C.byref(info))
+        if st not in (OK, E_NOCONV, E_BREAKDOWN):
+            _check(st, "tk_polarize_pcg2_ewald")
+        return out, [{k: getattr(info[v], k) for k, _ in PcgInfo._fields_} for v in range(2)]
 
     def epolar2_real(self, sysref, lst, mpole, polarity, thole, mu2, beta, cutoff, pscale):
         """Polarization forces with both dipole sets mu2[2,n,3] (mu_d first)."""

@@ -170,3 +170,30 @@ def test_epolar2_at_solved_sets_and_one_set_limit(ctx, tk):
     with pytest.raises(tk.TkError):
         ctx.epolar2_real(sysr, lst, w.mpole, w.polarity, w.thole, np.stack([mu, mu]), S["beta"],
                          7.0, 1.5)
+
+
+@pytest.mark.parametrize("name,K", [("water216", 32), ("water7853", 64)])
+def test_pcg2_ewald_converged(ctx, name, K):
+    w, sysr, lst, rp, cp = case(ctx, name)
+    print(f"pcg2 ewald {name} K={K}", flush=True)
+    mu, info = ctx.polarize_pcg2_ewald(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
+                                       K, 0.5, tol_debye=S["tol_debye"])
+    mo, io = O.polarize_pcg2_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                   S["beta"], 7.0, K, 0.5, tol_debye=S["tol_debye"])
+    check(mu, info, mo, io)
+    for v in range(2):
+        assert info[v]["converged"] == 1
+        # the reciprocal field passes through the 2^-40 fixed-point mesh
+        assert rel(info[v]["rms_true_debye"], io[v]["rms_true_debye"]) < 1e-5
+
+
+def test_pcg2_ewald_fixed_iterations(ctx):
+    w, sysr, lst, rp, cp = case(ctx, "water216")
+    mu, info = ctx.polarize_pcg2_ewald(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
+                                       32, 0.7, tol_debye=0.0, maxiter=3)
+    mo, io = O.polarize_pcg2_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                   S["beta"], 7.0, 32, 0.7, tol_debye=0.0, maxiter=3)
+    check(mu, info, mo, io)
+    for v in range(2):
+        assert info[v]["iters"] == 3
+        assert rel(info[v]["rms_debye"], io[v]["rms_debye"]) < 1e-7
