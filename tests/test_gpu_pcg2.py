@@ -197,3 +197,29 @@ def test_pcg2_ewald_fixed_iterations(ctx):
     for v in range(2):
         assert info[v]["iters"] == 3
         assert rel(info[v]["rms_debye"], io[v]["rms_debye"]) < 1e-7
+
+
+def test_two_set_full_ewald_forces_composed(ctx):
+    # the two-set full-Ewald force as its composition of GPU calls:
+    # tk_epolar2_real + 1/2 [F(M + x + y) - F(M) - F(x) - F(y)] of tk_pme_mpole
+    w, sysr, lst, rp, cp = case(ctx, "water216")
+    K = 32
+    mu2, _ = ctx.polarize_pcg2_ewald(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0, K,
+                                     0.5)
+    m = np_(mu2)
+
+    def dip(v):
+        d = np.zeros((w.n, 10))
+        d[:, 1:4] = v
+        return d
+    mxy = w.mpole.copy()
+    mxy[:, 1:4] += m[0] + m[1]
+    parts = (mxy, w.mpole, dip(m[0]), dip(m[1]))
+    _, f, _ = ctx.epolar2_real(sysr, lst, w.mpole, w.polarity, w.thole, m, S["beta"], 7.0, 0.5)
+    fg = np_(f) + 0.5 * sum(sg * np_(ctx.pme_mpole(sysr, q, S["beta"], K, 5, want_field=False)[1])
+                            for sg, q in zip((1, -1, -1, -1), parts))
+    _, fo, _ = O.epolar2_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, m,
+                              S["beta"], 7.0, 0.5)
+    fo = fo + 0.5 * sum(sg * O.pme_mpole(w.xyz, w.box, q, S["beta"], K, 5)[1]
+                        for sg, q in zip((1, -1, -1, -1), parts))
+    assert fmax_rel(fg, fo) < 1e-8

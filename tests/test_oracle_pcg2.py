@@ -259,3 +259,41 @@ def test_pcg2_ewald_energy_forms_agree_and_differ_from_real_space():
     with pytest.raises(O.OracleError):
         O.polarize_pcg2_ewald(wb.xyz, wb.box, wb.molid, rp, cp, wb.mpole, wb.polarity, wb.thole,
                               beta, rc, 16, 1.5, order=5)
+
+
+def test_two_set_full_ewald_forces_compose():
+    # the reciprocal part of L = 1/2 C [x.A y - x.E_p - y.E_d] at fixed sets is
+    # B(M, x) + B(M, y) + B(x, y) with Q(a) = B(a, a) the PME energy of the
+    # multipoles a, i.e. 1/2 [Q(M + x + y) - Q(M) - Q(x) - Q(y)]; so the
+    # two-set full-Ewald force is epolar2_real plus that combination of four
+    # PME forces, and at the solved sets the gradient of E_pol re-solved
+    w = synth.amoeba_water_box(20, 8.6, 4)
+    rc, beta, K, p = 4.29, 0.9, 16, 5
+    rp, cp = O.nblist(w.xyz, w.box, rc)
+
+    def solve(xyz):
+        mu2, info = O.polarize_pcg2_ewald(xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity,
+                                          w.thole, beta, rc, K, 0.5, order=p, tol_debye=1e-12,
+                                          maxiter=300)
+        assert all(i["converged"] == 1 for i in info)
+        return mu2, info[0]["epol"]
+
+    def dip(v):
+        m = np.zeros((w.n, 10))
+        m[:, 1:4] = v
+        return m
+    mu2, _ = solve(w.xyz)
+    _, F, _ = O.epolar2_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, mu2,
+                             beta, rc, 0.5)
+    mxy = w.mpole.copy()
+    mxy[:, 1:4] += mu2[0] + mu2[1]
+    fq = lambda m: O.pme_mpole(w.xyz, w.box, m, beta, K, p)[1]
+    F = F + 0.5 * (fq(mxy) - fq(w.mpole) - fq(dip(mu2[0])) - fq(dip(mu2[1])))
+    h = 1e-5
+    for i in (0, 5, 33):
+        for a in range(3):
+            xp, xm = w.xyz.copy(), w.xyz.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            g = (solve(xp)[1] - solve(xm)[1]) / (2 * h)
+            assert abs(F[i, a] + g) <= 1e-8 * np.abs(F).max()
