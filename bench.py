@@ -255,6 +255,19 @@ def main():
         per.append((time.perf_counter() - t0) * 1e3)
     q10, q50, q90 = np.percentile(per, [10, 50, 90])
     iters = step.info["iters"]
+    # the polarization solve alone (right-hand side, PCG to tolerance, FP64
+    # true residual) on the step's 7 A list, FP64 and mixed
+    sv = {}
+    l7 = ctx.nblist(step.sys, synth.AMOEBA_SETTINGS["rc_ewald"] + synth.AMOEBA_SETTINGS["skin"],
+                    plan_slot=5)
+    for name, pr in (("fp64", tk.FP64), ("mixed", tk.MIXED)):
+        s_ = synth.AMOEBA_SETTINGS
+        solve_ms = timed(lambda: ctx.polarize_pcg(step.sys, l7, step.mpole, step.pol, step.thole,
+                                                  s_["beta"], s_["rc_ewald"],
+                                                  tol_debye=s_["tol_debye"],
+                                                  maxiter=s_["maxiter"], prec=pr),
+                         max(10, a.steps), 2) * 1e3
+        sv[name] = round(1e3 / solve_ms, 1)
     mv_calls = iters + 2          # initial residual + iterations + final FP64 residual
     pairs = n7 * (1 + 1 + mv_calls) + n9   # empole + efield + mat-vecs + HAL
     value = pairs / (ms * 1e-3)
@@ -288,7 +301,8 @@ def main():
                                "multipoles + Thole polarization + HAL, rc 7/9 A",
                    "atoms": w.n, "pairs_7A": n7, "pairs_9A_hal": n9,
                    "pcg_iters": iters, "prec": a.prec},
-        "solves_per_s": 1e3 / ms,
+        "solves_per_s": 1e3 / ms,   # one solve per step
+        "polarization_solves_per_s": sv,   # the solve alone
         "step_ms_p10_p50_p90": [round(q10, 4), round(q50, 4), round(q90, 4)],
         "kernel_ms_per_step": {k: round(v["ms"] / max(2, a.steps // 4), 5) for k, v in prof.items()},
         "roofline": roof,
