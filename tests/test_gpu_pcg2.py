@@ -223,3 +223,28 @@ def test_two_set_full_ewald_forces_composed(ctx):
     fo = fo + 0.5 * sum(sg * O.pme_mpole(w.xyz, w.box, q, S["beta"], K, 5)[1]
                         for sg, q in zip((1, -1, -1, -1), parts))
     assert fmax_rel(fg, fo) < 1e-8
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33])
+def test_pcg2_and_forces_random_boxes(ctx, seed):
+    # random water counts (not cubes) at the water density, random scale
+    rng = np.random.default_rng(seed)
+    n_w = int(rng.integers(60, 400))
+    box = (n_w / 0.03335) ** (1.0 / 3.0)
+    rc = min(7.0, 0.5 * box - 0.01)
+    ps = float(rng.uniform(0.1, 1.0))
+    w = synth.amoeba_water_box(n_w, box, 5000 + seed)
+    print(f"pcg2 random seed={seed} n_w={n_w} box={box:.2f} rc={rc:.2f} pscale={ps:.3f}", flush=True)
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, rc + 0.001, plan_slot=7)
+    rp, cp = O.nblist(w.xyz, w.box, rc + 0.001)
+    mu, info = ctx.polarize_pcg2(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], rc, ps)
+    mo, io = O.polarize_pcg2(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                             S["beta"], rc, ps)
+    check(mu, info, mo, io)
+    e, f, vir = ctx.epolar2_real(sysr, lst, w.mpole, w.polarity, w.thole, mo, S["beta"], rc, ps)
+    eo, fo, vo = O.epolar2_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, mo,
+                                S["beta"], rc, ps)
+    assert rel(np_(e)[0], eo[0]) < 1e-10
+    assert fmax_rel(np_(f), fo) < 1e-8
+    assert np.abs(np_(vir) - vo).max() <= 1e-10 * np.abs(vo).max()
