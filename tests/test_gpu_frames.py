@@ -156,3 +156,33 @@ def test_epolar_frames_fp64(ctx, name, frames):
         assert abs(e[k] - eo[k]) <= 1e-10 * abs(eo[k]), (k, e[k], eo[k])
     assert fmax_rel(np_(f), fo) < 1e-8
     assert np.abs(np_(vir) - vo).max() <= 1e-10 * np.abs(vo).max()
+
+
+@pytest.mark.parametrize("seed", [51, 52])
+def test_frames_random_boxes(ctx, seed):
+    # every frame type on random water counts (not cubes) and random cutoffs
+    rng = np.random.default_rng(seed)
+    n_w = int(rng.integers(60, 400))
+    box = (n_w / 0.03335) ** (1.0 / 3.0)
+    rc = float(min(rng.uniform(4.0, 7.0), 0.5 * box - 0.01))
+    w = synth.amoeba_water_box(n_w, box, 7000 + seed)
+    ft, fa = synth.mixed_frames(n_w)
+    loc = synth.water_local_multipoles(n_w, seed)
+    print(f"frames random seed={seed} n_w={n_w} box={box:.2f} rc={rc:.2f}", flush=True)
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, rc + 0.001, plan_slot=7)
+    rp, cp = O.nblist(w.xyz, w.box, rc + 0.001)
+    e, f, _, vir = ctx.empole_frames(sysr, lst, ft, fa, loc, S["beta"], rc)
+    eo, fo, vo = O.empole_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, S["beta"], rc)
+    e = np_(e)
+    for k in range(3):
+        assert abs(e[k] - eo[k]) <= 1e-10 * abs(eo[k]), k
+    assert fmax_rel(np_(f), fo) < 1e-8
+    assert np.abs(np_(vir) - vo).max() <= 1e-10 * np.abs(vo).max()
+    mu = rng.normal(0, 0.03, (w.n, 3))
+    e, f, vir = ctx.epolar_frames(sysr, lst, ft, fa, loc, w.polarity, w.thole, mu, S["beta"], rc)
+    eo, fo, vo = O.epolar_frames(w.xyz, w.box, w.molid, rp, cp, ft, fa, loc, w.polarity, w.thole,
+                                 mu, S["beta"], rc)
+    assert abs(np_(e)[0] - eo[0]) <= 1e-10 * abs(eo[0])
+    assert fmax_rel(np_(f), fo) < 1e-8
+    assert np.abs(np_(vir) - vo).max() <= 1e-10 * np.abs(vo).max()

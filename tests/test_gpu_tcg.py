@@ -71,3 +71,23 @@ def test_tcg1_without_forces_and_without_polarizability(ctx):
     mu, e, f = ctx.polarize_tcg1(empty, l0, np.zeros((0, 10)), np.zeros(0), np.zeros(0),
                                  S["beta"], 7.0)
     assert np_(e)[0] == 0.0
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_tcg1_random_boxes(ctx, seed):
+    # random water counts (not cubes) at the water density and random cutoffs
+    rng = np.random.default_rng(seed)
+    n_w = int(rng.integers(60, 400))
+    box = (n_w / 0.03335) ** (1.0 / 3.0)
+    rc = float(min(rng.uniform(4.0, 7.0), 0.5 * box - 0.01))
+    w = synth.amoeba_water_box(n_w, box, 6000 + seed)
+    print(f"tcg1 random seed={seed} n_w={n_w} box={box:.2f} rc={rc:.2f}", flush=True)
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, rc + 0.001, plan_slot=7)
+    rp, cp = O.nblist(w.xyz, w.box, rc + 0.001)
+    mu, e, f = ctx.polarize_tcg1(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], rc)
+    mo, eo, fo = O.polarize_tcg1(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                 S["beta"], rc)
+    assert np.abs(np_(mu) - mo).max() <= 1e-10 * np.abs(mo).max()
+    assert abs(np_(e)[0] - eo) <= 1e-10 * abs(eo)
+    assert fmax_rel(np_(f), fo) < 1e-8
