@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--no-solve-rates", action="store_true",
+                    help="skip the solve-alone rates (kept out of the profiled step traces)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run device-to-device copies of this many MiB (a kernel of known "
                          "traffic for scaling HBM counters)")
@@ -257,10 +259,12 @@ def main():
     iters = step.info["iters"]
     # the polarization solve alone (right-hand side, PCG to tolerance, FP64
     # true residual) on the step's 7 A list, FP64 and mixed
-    sv = {}
-    l7 = ctx.nblist(step.sys, synth.AMOEBA_SETTINGS["rc_ewald"] + synth.AMOEBA_SETTINGS["skin"],
-                    plan_slot=5)
-    for name, pr in (("fp64", tk.FP64), ("mixed", tk.MIXED)):
+    sv = None if a.no_solve_rates else {}
+    if not a.no_solve_rates:
+        l7 = ctx.nblist(step.sys,
+                        synth.AMOEBA_SETTINGS["rc_ewald"] + synth.AMOEBA_SETTINGS["skin"],
+                        plan_slot=5)
+    for name, pr in (() if a.no_solve_rates else (("fp64", tk.FP64), ("mixed", tk.MIXED))):
         s_ = synth.AMOEBA_SETTINGS
         solve_ms = timed(lambda: ctx.polarize_pcg(step.sys, l7, step.mpole, step.pol, step.thole,
                                                   s_["beta"], s_["rc_ewald"],
