@@ -883,6 +883,15 @@ struct Solver {
   // runs, 1 for its stopped solve's residual, -1 always
   tk_status queue_pme(const double* v, int run_when_done) {
     if (!pme_grid) return TK_OK;
+    const auto done_of = [&](int k) {
+      return run_when_done < 0
+                 ? nullptr
+                 : (const int32_t*)((const char*)(state + k) + offsetof(PcgState, done));
+    };
+    if (nv == 2)   // both sets through one packed pass
+      return pme_prepared_dipole_field2(ctx, st, P->n, P->box, v, v + vs, beta, pme_grid,
+                                        pme_order, rz, rz + vs, done_of(0), done_of(1),
+                                        run_when_done < 0 ? 0 : run_when_done);
     for (int k = 0; k < nv; ++k) {
       const int32_t* done =
           run_when_done < 0 ? nullptr

@@ -67,10 +67,17 @@ struct SrcDipole {
 // Launches queued ahead by the iterative solver read its state: with done
 // set, a launch returns at once while *done != 0 (when = 0: the solve has
 // stopped) or while *done == 0 (when = 1: work for the stopped solve only).
+// done2 (two packed right-hand sides): open while either side is open
 struct Gate {
   const int32_t* done = nullptr;
   int when = 0;
-  __device__ bool closed() const { return done && (when ? *done == 0 : *done != 0); }
+  const int32_t* done2 = nullptr;
+  __device__ bool closed() const {
+    if (!done) return false;
+    const bool c1 = when ? *done == 0 : *done != 0;
+    if (!done2) return c1;
+    return c1 && (when ? *done2 == 0 : *done2 != 0);
+  }
 };
 
 // Cardinal B-spline weights th[t][d] = M_P^(d)(w + t) (t = 0..P-1, d = 0..3)
@@ -393,7 +400,9 @@ __device__ __forceinline__ void slot(int ax, int t, int s, int& line, int& k) {
 
 // Forward pass along axis ax (z: from the fixed-point grid; y: in place).
 template <int K>
+// fix2 (nullable): a second real mesh, packed as the imaginary part
 __global__ __launch_bounds__(256) void k_pme_fft_fwd(int ax, const unsigned long long* __restrict__ fix,
+                                                     const unsigned long long* __restrict__ fix2,
                                                      double2* __restrict__ cg, Gate gate) {
   if (gate.closed()) return;
   constexpr int L = Fft<K>::L, LOG = Fft<K>::LOG;
@@ -408,7 +417,10 @@ __global__ __launch_bounds__(256) void k_pme_fft_fwd(int ax, const unsigned long
     long base, stride;
     line_geom<K>(ax, blockIdx.x * L + line, base, stride);
     const long g = base + k * stride;
-    const double2 v = fix ? make_double2((double)(long long)fix[g] * (1.0 / kFix), 0.0) : cg[g];
+    const double2 v =
+        fix ? make_double2((double)(long long)fix[g] * (1.0 / kFix),
+                           fix2 ? (double)(long long)fix2[g] * (1.0 / kFix) : 0.0)
+            : cg[g];
     sh[line * K + bitrev(k, LOG)] = v;
   }
   __syncthreads();
@@ -511,8 +523,10 @@ __global__ __launch_bounds__(256) void k_pme_fft_conv(double2* __restrict__ cg, 
 
 // Inverse pass along axis ax (y: in place; z: real part to phi).
 template <int K>
+// phi2 (nullable): the imaginary part, the potential of a packed second mesh
 __global__ __launch_bounds__(256) void k_pme_fft_inv(int ax, double2* __restrict__ cg,
-                                                     double* __restrict__ phi, Gate gate) {
+                                                     double* __restrict__ phi,
+                                                     double* __restrict__ phi2, Gate gate) {
   if (gate.closed()) return;
   constexpr int L = Fft<K>::L, LOG = Fft<K>::LOG;
   __shared__ double2 sh[L * K];
@@ -536,8 +550,12 @@ __global__ __launch_bounds__(256) void k_pme_fft_inv(int ax, double2* __restrict
     long base, stride;
     line_geom<K>(ax, blockIdx.x * L + line, base, stride);
     const double2 v = sh[line * K + bitrev(k, LOG)];
-    if (phi) phi[base + k * stride] = v.x;
-    else cg[base + k * stride] = v;
+    if (phi) {
+      phi[base + k * stride] = v.x;
+      if (phi2) phi2[base + k * stride] = v.y;
+    } else {
+      cg[base + k * stride] = v;
+    }
   }
 }
 
@@ -803,17 +821,20 @@ __global__ __launch_bounds__(256) void k_pme_energy(const double* __restrict__ e
 }
 
 // Five mesh passes: forward along z, y; forward x, influence function,
-// inverse x; inverse along y, z (real part into phi).
+// inverse x; inverse along y, z (real part into phi).  With fx2 the second
+// real mesh rides in the imaginary part: the influence function is real and
+// even, so the inverse returns its potential as the imaginary part (phi2).
 template <int P, int K>
 void mesh_fft(tk_ctx* ctx, hipStream_t st, const unsigned long long* fx, double2* c2, double* phi,
-              double box, double beta, Gate gate) {
+              double box, double beta, Gate gate, const unsigned long long* fx2 = nullptr,
+              double* phi2 = nullptr) {
   const int nlines = K * K / Fft<K>::L;
   ProfScope ps(ctx, st, "pme_fft");
-  k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(2, fx, c2, gate);
-  k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(1, nullptr, c2, gate);
+  k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(2, fx, fx2, c2, gate);
+  k_pme_fft_fwd<K><<<nlines, 256, 0, st>>>(1, nullptr, nullptr, c2, gate);
   k_pme_fft_conv<P, K><<<nlines, 256, 0, st>>>(c2, box, beta, gate);
-  k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(1, c2, nullptr, gate);
-  k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(2, c2, phi, gate);
+  k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(1, c2, nullptr, nullptr, gate);
+  k_pme_fft_inv<K><<<nlines, 256, 0, st>>>(2, c2, phi, phi2, gate);
 }
 
 // Bin, spread and convolve: the potential phi on the mesh (scratch of this
@@ -905,30 +926,49 @@ tk_status prepare_sites(tk_ctx* ctx, hipStream_t st, int n, double box, const do
   return TK_OK;
 }
 
+// The dipole field of v (and, with v2, of v2 in the same FFT passes: the two
+// meshes packed as one complex mesh), each spread and gathered under its own
+// gate.
 template <int P, int K>
 tk_status field_prepared(tk_ctx* ctx, hipStream_t st, int n, double box, const double* v,
-                         double beta, double* out, Gate gate) {
+                         double beta, double* out, Gate gate, const double* v2 = nullptr,
+                         double* out2 = nullptr, Gate gate2 = Gate{}) {
   Sites S;
   tk_status s;
   if ((s = sites_layout<P, K>(ctx, st, n, S))) return s;
   const long KK = (long)K * K * K;
-  void *fix, *cg, *phi;
+  void *fix, *cg, *phi, *fix2 = nullptr, *phi2 = nullptr;
   if ((s = scratch(ctx, per_stream("pme_fix", st).c_str(), sizeof(unsigned long long) * KK, &fix)) ||
       (s = scratch(ctx, per_stream("pme_c", st).c_str(), sizeof(double2) * KK, &cg)) ||
       (s = scratch(ctx, per_stream("pme_phi", st).c_str(), sizeof(double) * KK, &phi)))
     return s;
+  if (v2 && ((s = scratch(ctx, per_stream("pme_fix2", st).c_str(),
+                          sizeof(unsigned long long) * KK, &fix2)) ||
+             (s = scratch(ctx, per_stream("pme_phi2", st).c_str(), sizeof(double) * KK, &phi2))))
+    return s;
   auto* fx = (unsigned long long*)fix;
+  auto* fx2 = (unsigned long long*)fix2;
   {
     ProfScope ps(ctx, st, "pme_spread");
     k_pme_spread_tab<P, K><<<K * (K / spread_rows<K>()), spread_threads<P>(), 0, st>>>(
         n, S.start, S.list, S.I0, S.TB, v, fx, S.flag, gate);
+    if (v2)
+      k_pme_spread_tab<P, K><<<K * (K / spread_rows<K>()), spread_threads<P>(), 0, st>>>(
+          n, S.start, S.list, S.I0, S.TB, v2, fx2, S.flag, gate2);
   }
-  mesh_fft<P, K>(ctx, st, fx, (double2*)cg, (double*)phi, box, beta, gate);
+  // the passes run while either right-hand side is open
+  const Gate both{gate.done, gate.when, v2 ? gate2.done : nullptr};
+  mesh_fft<P, K>(ctx, st, fx, (double2*)cg, (double*)phi, box, beta, v2 ? both : gate, fx2,
+                 (double*)phi2);
   {
     ProfScope ps(ctx, st, "pme_field");
-    if (n > 0)
+    if (n > 0) {
       k_pme_field_tab<P><<<ceil_div((long)n * 8, 256), 256, 0, st>>>(
           n, K, S.list, S.I0, S.TB, (const double*)phi, S.flag, out, gate);
+      if (v2)
+        k_pme_field_tab<P><<<ceil_div((long)n * 8, 256), 256, 0, st>>>(
+            n, K, S.list, S.I0, S.TB, (const double*)phi2, S.flag, out2, gate2);
+    }
   }
   TK_HIP(hipGetLastError());
   return TK_OK;
@@ -1016,12 +1056,12 @@ tk_status prepare_k(tk_ctx* ctx, hipStream_t st, int n, double box, const double
 }
 template <int P>
 tk_status field_k(tk_ctx* ctx, hipStream_t st, int n, double box, const double* v, double beta,
-                  int K, double* out, Gate gate) {
+                  int K, double* out, Gate gate, const double* v2, double* out2, Gate gate2) {
   switch (K) {
-    case 16: return field_prepared<P, 16>(ctx, st, n, box, v, beta, out, gate);
-    case 32: return field_prepared<P, 32>(ctx, st, n, box, v, beta, out, gate);
-    case 64: return field_prepared<P, 64>(ctx, st, n, box, v, beta, out, gate);
-    case 128: return field_prepared<P, 128>(ctx, st, n, box, v, beta, out, gate);
+    case 16: return field_prepared<P, 16>(ctx, st, n, box, v, beta, out, gate, v2, out2, gate2);
+    case 32: return field_prepared<P, 32>(ctx, st, n, box, v, beta, out, gate, v2, out2, gate2);
+    case 64: return field_prepared<P, 64>(ctx, st, n, box, v, beta, out, gate, v2, out2, gate2);
+    case 128: return field_prepared<P, 128>(ctx, st, n, box, v, beta, out, gate, v2, out2, gate2);
     default: return TK_E_ARG;
   }
 }
@@ -1046,10 +1086,24 @@ tk_status pme_prepared_dipole_field(tk_ctx* ctx, hipStream_t st, int n, double b
   gate.done = done;
   gate.when = run_when_done;
   switch (order) {
-    case 5: return field_k<5>(ctx, st, n, box, v, beta, grid, out, gate);
-    case 6: return field_k<6>(ctx, st, n, box, v, beta, grid, out, gate);
-    case 7: return field_k<7>(ctx, st, n, box, v, beta, grid, out, gate);
-    default: return field_k<8>(ctx, st, n, box, v, beta, grid, out, gate);
+    case 5: return field_k<5>(ctx, st, n, box, v, beta, grid, out, gate, nullptr, nullptr, Gate{});
+    case 6: return field_k<6>(ctx, st, n, box, v, beta, grid, out, gate, nullptr, nullptr, Gate{});
+    case 7: return field_k<7>(ctx, st, n, box, v, beta, grid, out, gate, nullptr, nullptr, Gate{});
+    default: return field_k<8>(ctx, st, n, box, v, beta, grid, out, gate, nullptr, nullptr, Gate{});
+  }
+}
+
+tk_status pme_prepared_dipole_field2(tk_ctx* ctx, hipStream_t st, int n, double box,
+                                     const double* v, const double* v2, double beta, int grid,
+                                     int order, double* out, double* out2, const int32_t* done,
+                                     const int32_t* done2, int run_when_done) {
+  if (!pme_args_ok(grid, order)) return TK_E_ARG;
+  const Gate g1{done, run_when_done, nullptr}, g2{done2, run_when_done, nullptr};
+  switch (order) {
+    case 5: return field_k<5>(ctx, st, n, box, v, beta, grid, out, g1, v2, out2, g2);
+    case 6: return field_k<6>(ctx, st, n, box, v, beta, grid, out, g1, v2, out2, g2);
+    case 7: return field_k<7>(ctx, st, n, box, v, beta, grid, out, g1, v2, out2, g2);
+    default: return field_k<8>(ctx, st, n, box, v, beta, grid, out, g1, v2, out2, g2);
   }
 }
 

@@ -249,6 +249,13 @@ tk_status pme_prepare_sites(tk_ctx* ctx, hipStream_t st, int n, double box, cons
 tk_status pme_prepared_dipole_field(tk_ctx* ctx, hipStream_t st, int n, double box,
                                     const double* v, double beta, int grid, int order,
                                     double* out, const int32_t* done, int run_when_done);
+// The fields of two dipole sets in one pass over the mesh (the two meshes
+// packed into one complex FFT), each set spread and gathered under its own
+// done flag (done2 for v2), the FFT passes while either runs.
+tk_status pme_prepared_dipole_field2(tk_ctx* ctx, hipStream_t st, int n, double box,
+                                     const double* v, const double* v2, double beta, int grid,
+                                     int order, double* out, double* out2, const int32_t* done,
+                                     const int32_t* done2, int run_when_done);
 // b_sorted[3 s + a] += reciprocal field of the permanent multipoles at site perm[s].
 tk_status pme_perm_field_add(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
                              const double* mpole, double beta, int grid, int order,
