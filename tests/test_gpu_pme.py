@@ -205,3 +205,25 @@ def test_full_ewald_polarization_forces(ctx):
     Fo = fo + O.pme_mpole(w.xyz, w.box, m2, beta, K, p)[1] - O.pme_mpole(w.xyz, w.box, w.mpole,
                                                                         beta, K, p)[1]
     assert fmax_rel(F, Fo) < 1e-8
+
+
+def test_pme_point_charges_ewald_split(ctx):
+    # the point-charge (CHARMM-style) path: PME of charges only, against the
+    # oracle's PME, and the total Ewald energy (real space + PME + self term)
+    # the same at two splitting parameters
+    w = synth.charge_lj_water_box(4000, 49.4, 91)
+    q = np.zeros((w.n, 10))
+    q[:, 0] = w.charges
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, 12.001, plan_slot=4)
+    totals = []
+    for beta in (0.34, 0.40):
+        print(f"pme charges beta={beta}", flush=True)
+        er, _, _ = ctx.echarge_real(sysr, lst, w.charges, beta, 12.0)
+        ek, fk, _ = ctx.pme_mpole(sysr, q, beta, 64, 6, want_field=False)
+        totals.append(float(np_(er)[0]) + float(np_(ek)[0]) + O.eself(q, beta))
+        if beta == 0.34:
+            eo, fo, _ = O.pme_mpole(w.xyz, w.box, q, beta, 64, 6)
+            assert abs(np_(ek)[0] - eo) <= 1e-10 * abs(eo)
+            assert fmax_rel(np_(fk), fo) < 1e-8
+    assert abs(totals[0] - totals[1]) <= 1e-5 * abs(totals[0]), totals
