@@ -227,3 +227,24 @@ def test_pme_point_charges_ewald_split(ctx):
             assert abs(np_(ek)[0] - eo) <= 1e-10 * abs(eo)
             assert fmax_rel(np_(fk), fo) < 1e-8
     assert abs(totals[0] - totals[1]) <= 1e-5 * abs(totals[0]), totals
+
+
+def test_multipole_ewald_total_independent_of_split(ctx):
+    # the AMOEBA multipoles of the water box: real space + PME + self energy
+    # is the same at two splitting parameters.  Each piece is 1e4 to 1e5
+    # times the total (the same-molecule terms cancel between the real-space
+    # correction and the self energy), so the check needs a converged real
+    # space (12 A) and PME error well below 1e-5 of the total (128^3, order
+    # 8: at order 6 the totals of the oracle differ by 0.4 kcal/mol)
+    w = _cache.setdefault("water7853", synth.make("water7853"))
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, 12.001, plan_slot=4)
+    totals, pieces = [], []
+    for beta in (0.45, 0.50):
+        print(f"multipole ewald split beta={beta}", flush=True)
+        er, _, _ = ctx.empole_real(sysr, lst, w.mpole, beta, 12.0)
+        ek, _, _ = ctx.pme_mpole(sysr, w.mpole, beta, 128, 8, want_field=False)
+        pieces.append(float(np_(ek)[0]))
+        totals.append(float(np_(er)[0]) + float(np_(ek)[0]) + O.eself(w.mpole, beta))
+    assert abs(totals[0] - totals[1]) <= 1e-5 * abs(totals[0]), totals
+    assert abs(pieces[0] - pieces[1]) > 1.0 * abs(totals[0])   # the pieces move by far more
