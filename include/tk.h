@@ -267,6 +267,23 @@ tk_status tk_polarize_pcg2(tk_ctx* ctx, void* stream, const tk_system* sys, cons
                            tk_pcg_info* info);
 
 /*
+ * Polarization forces at fixed induced dipoles with the full Ewald operator
+ * (the polarization gradient routine of section "Hotspots" with the
+ * reciprocal part of the same section): tk_epolar_real's pair terms plus
+ * the reciprocal part, which at fixed mu is E_pme(M + mu) - E_pme(M) (the
+ * cross term with the permanent multipoles and the dipoles' own
+ * interaction).  The two PME evaluations share one pass over the mesh.  At
+ * the dipoles of tk_polarize_pcg_ewald the force is the gradient of its
+ * E_pol.  energy: device [3] = {total, real-space pair energy (as
+ * tk_epolar_real's [0]), reciprocal part}; force: device [n][3].  grid and
+ * order as tk_pme_mpole; ewald_beta > 0; FP64; no virial.
+ */
+tk_status tk_epolar_ewald(tk_ctx* ctx, void* stream, const tk_system* sys,
+                          const tk_nblist* list, const double* mpole, const double* polarity,
+                          const double* thole, const double* mu, double ewald_beta, double cutoff,
+                          int32_t grid, int32_t order, double* energy, double* force);
+
+/*
  * Both dipole sets with the full Ewald operator: tk_polarize_pcg2 with the
  * reciprocal space of tk_polarize_pcg_ewald.  The operator gains the PME
  * field of the dipoles, and both right-hand sides gain the PME field of the

@@ -841,7 +841,8 @@ void mesh_fft(tk_ctx* ctx, hipStream_t st, const unsigned long long* fx, double2
 // stream), and the spread's refusal flag.
 template <int P, int K, class Src>
 tk_status mesh_potential(tk_ctx* ctx, hipStream_t st, int n, Src src, double box, double beta,
-                         Gate gate, double** phi_out, int** flag_out) {
+                         Gate gate, double** phi_out, int** flag_out, const Src* src2 = nullptr,
+                         double** phi2_out = nullptr) {
   const long KK = (long)K * K * K;
   const size_t nn = n > 0 ? n : 1;
   const int na = n > 0 ? ceil_div(n, 256) : 1;   // sort blocks (one even when empty)
@@ -853,6 +854,11 @@ tk_status mesh_potential(tk_ctx* ctx, hipStream_t st, int n, Src src, double box
       (s = scratch(ctx, per_stream("pme_c", st).c_str(), sizeof(double2) * KK, &cg)) ||
       (s = scratch(ctx, per_stream("pme_phi", st).c_str(), sizeof(double) * KK, &phi)) ||
       (s = scratch(ctx, per_stream("pme_flag", st).c_str(), sizeof(int) * 64, &flag)))
+    return s;
+  void *fix2 = nullptr, *phi2 = nullptr;   // a second source rides in the imaginary part
+  if (src2 && ((s = scratch(ctx, per_stream("pme_fix2", st).c_str(),
+                            sizeof(unsigned long long) * KK, &fix2)) ||
+               (s = scratch(ctx, per_stream("pme_phi2", st).c_str(), sizeof(double) * KK, &phi2))))
     return s;
   auto* fx = (unsigned long long*)fix;
   auto* c2 = (double2*)cg;
@@ -867,8 +873,13 @@ tk_status mesh_potential(tk_ctx* ctx, hipStream_t st, int n, Src src, double box
     k_pme_scatter<<<na, 256, 0, st>>>(n, K, na, bcnt, bin, slot, start, list, gate);
     k_pme_spread<P, K, Src><<<K * (K / spread_rows<K>()), spread_threads<P>(), 0, st>>>(
         src, box, start, list, fx, (int*)flag, gate);
+    if (src2)   // the same sites, so the same bins
+      k_pme_spread<P, K, Src><<<K * (K / spread_rows<K>()), spread_threads<P>(), 0, st>>>(
+          *src2, box, start, list, (unsigned long long*)fix2, (int*)flag, gate);
   }
-  mesh_fft<P, K>(ctx, st, fx, c2, (double*)phi, box, beta, gate);
+  mesh_fft<P, K>(ctx, st, fx, c2, (double*)phi, box, beta, gate,
+                 (const unsigned long long*)fix2, (double*)phi2);
+  if (phi2_out) *phi2_out = (double*)phi2;
   *phi_out = (double*)phi;
   *flag_out = (int*)flag;
   return TK_OK;
@@ -976,25 +987,34 @@ tk_status field_prepared(tk_ctx* ctx, hipStream_t st, int n, double box, const d
 
 template <int P, int K>
 tk_status run_pme(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* mpole,
-                  double beta, double* energy, double* force, double* field) {
+                  double beta, double* energy, double* force, double* field,
+                  const double* m2 = nullptr, double* energy2 = nullptr,
+                  double* force2 = nullptr) {
   const int n = sys->n;
   const int nb = ceil_div((long)n * 8, 256);
-  double* phi;
+  double *phi, *phi2 = nullptr;
   int* flag;
   void* epart;
   tk_status s;
-  if ((s = scratch(ctx, per_stream("pme_part", st).c_str(), sizeof(double) * (nb > 0 ? nb : 1),
-                   &epart)))
+  const size_t nbp = nb > 0 ? nb : 1;
+  if ((s = scratch(ctx, per_stream("pme_part", st).c_str(), sizeof(double) * 2 * nbp, &epart)))
     return s;
-  if ((s = mesh_potential<P, K>(ctx, st, n, SrcMpole{sys->xyz, mpole}, sys->box, beta, Gate{},
-                                &phi, &flag)))
+  const SrcMpole src1{sys->xyz, mpole}, src2{sys->xyz, m2};
+  if ((s = mesh_potential<P, K>(ctx, st, n, src1, sys->box, beta, Gate{}, &phi, &flag,
+                                m2 ? &src2 : nullptr, m2 ? &phi2 : nullptr)))
     return s;
   {
     ProfScope ps(ctx, st, "pme_gather");
-    if (n > 0)
+    if (n > 0) {
       k_pme_gather<P><<<nb, 256, 0, st>>>(n, sys->xyz, mpole, sys->box, K, phi, force, field,
                                            (double*)epart);
+      if (m2)
+        k_pme_gather<P><<<nb, 256, 0, st>>>(n, sys->xyz, m2, sys->box, K, phi2, force2, nullptr,
+                                             (double*)epart + nbp);
+    }
     k_pme_energy<<<1, 256, 0, st>>>((const double*)epart, n > 0 ? nb : 0, flag, energy);
+    if (m2)
+      k_pme_energy<<<1, 256, 0, st>>>((const double*)epart + nbp, n > 0 ? nb : 0, flag, energy2);
   }
   TK_HIP(hipGetLastError());
   return TK_OK;
@@ -1013,24 +1033,27 @@ __global__ __launch_bounds__(256) void k_add_permuted(int n, const int32_t* __re
 
 template <int P>
 tk_status run_pme_k(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* mpole,
-                    double beta, int K, double* energy, double* force, double* field) {
+                    double beta, int K, double* energy, double* force, double* field,
+                    const double* m2, double* energy2, double* force2) {
   switch (K) {
-    case 16: return run_pme<P, 16>(ctx, st, sys, mpole, beta, energy, force, field);
-    case 32: return run_pme<P, 32>(ctx, st, sys, mpole, beta, energy, force, field);
-    case 64: return run_pme<P, 64>(ctx, st, sys, mpole, beta, energy, force, field);
-    case 128: return run_pme<P, 128>(ctx, st, sys, mpole, beta, energy, force, field);
+    case 16: return run_pme<P, 16>(ctx, st, sys, mpole, beta, energy, force, field, m2, energy2, force2);
+    case 32: return run_pme<P, 32>(ctx, st, sys, mpole, beta, energy, force, field, m2, energy2, force2);
+    case 64: return run_pme<P, 64>(ctx, st, sys, mpole, beta, energy, force, field, m2, energy2, force2);
+    case 128:
+      return run_pme<P, 128>(ctx, st, sys, mpole, beta, energy, force, field, m2, energy2, force2);
     default: return TK_E_ARG;
   }
 }
 
 tk_status pme_dispatch(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* mpole,
                        double beta, int K, int order, double* energy, double* force,
-                       double* field) {
+                       double* field, const double* m2 = nullptr, double* energy2 = nullptr,
+                       double* force2 = nullptr) {
   switch (order) {
-    case 5: return run_pme_k<5>(ctx, st, sys, mpole, beta, K, energy, force, field);
-    case 6: return run_pme_k<6>(ctx, st, sys, mpole, beta, K, energy, force, field);
-    case 7: return run_pme_k<7>(ctx, st, sys, mpole, beta, K, energy, force, field);
-    case 8: return run_pme_k<8>(ctx, st, sys, mpole, beta, K, energy, force, field);
+    case 5: return run_pme_k<5>(ctx, st, sys, mpole, beta, K, energy, force, field, m2, energy2, force2);
+    case 6: return run_pme_k<6>(ctx, st, sys, mpole, beta, K, energy, force, field, m2, energy2, force2);
+    case 7: return run_pme_k<7>(ctx, st, sys, mpole, beta, K, energy, force, field, m2, energy2, force2);
+    case 8: return run_pme_k<8>(ctx, st, sys, mpole, beta, K, energy, force, field, m2, energy2, force2);
     default: return TK_E_ARG;
   }
 }
@@ -1105,6 +1128,13 @@ tk_status pme_prepared_dipole_field2(tk_ctx* ctx, hipStream_t st, int n, double 
     case 7: return field_k<7>(ctx, st, n, box, v, beta, grid, out, g1, v2, out2, g2);
     default: return field_k<8>(ctx, st, n, box, v, beta, grid, out, g1, v2, out2, g2);
   }
+}
+
+tk_status pme_mpole_pair(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* m1,
+                         const double* m2, double beta, int grid, int order, double* e1,
+                         double* f1, double* e2, double* f2) {
+  if (!pme_args_ok(grid, order)) return TK_E_ARG;
+  return pme_dispatch(ctx, st, sys, m1, beta, grid, order, e1, f1, nullptr, m2, e2, f2);
 }
 
 tk_status pme_perm_field_add(tk_ctx* ctx, hipStream_t st, const tk_system* sys,

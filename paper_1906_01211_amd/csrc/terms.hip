@@ -48,6 +48,38 @@ tk_status launch_tmat(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_syste
 
 using namespace tk;
 
+namespace tk {
+namespace {
+// M + (0, mu, 0): the permanent multipoles with the induced dipoles added
+__global__ void k_mpole_plus_dipoles(int n, const double* __restrict__ mpole,
+                                     const double* __restrict__ mu, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < 10; ++c) out[10 * i + c] = mpole[10 * i + c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[10 * i + 1 + c] += mu[3 * i + c];
+}
+
+// force += F_pme(M + mu) - F_pme(M); energy = {real + recip, real, recip}
+__global__ void k_epolar_ewald_sum(int n, const double* __restrict__ fa,
+                                   const double* __restrict__ fb, const double* __restrict__ er,
+                                   const double* __restrict__ ek, double* __restrict__ force,
+                                   double* __restrict__ energy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    const double rec = ek[0] - ek[1];
+    energy[0] = er[0] + rec;
+    energy[1] = er[0];
+    energy[2] = rec;
+  }
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) force[3 * i + c] += fa[3 * i + c] - fb[3 * i + c];
+}
+}  // namespace
+}  // namespace tk
+
 extern "C" {
 
 tk_status tk_empole_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
@@ -196,6 +228,50 @@ tk_status tk_epolar2_real(tk_ctx* ctx, void* stream, const tk_system* sys, const
   ph.pscale = pscale;
   ph.g.set(sys->box, cutoff, ewald_beta);
   return run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
+}
+
+tk_status tk_epolar_ewald(tk_ctx* ctx, void* stream, const tk_system* sys,
+                          const tk_nblist* list, const double* mpole, const double* polarity,
+                          const double* thole, const double* mu, double ewald_beta, double cutoff,
+                          int32_t grid, int32_t order, double* energy, double* force) {
+  const Plan* P;
+  tk_status s = common_args(ctx, sys, list, cutoff, TK_FP64, &P);
+  if (s) return s;
+  if (!(ewald_beta > 0.0) || !std::isfinite(ewald_beta) || !pme_args_ok(grid, order) || !energy)
+    return TK_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int n = sys->n;
+  if (n == 0) {
+    TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
+    return TK_OK;
+  }
+  if (!mpole || !polarity || !thole || !mu || !force) return TK_E_ARG;
+  void* buf;   // real-space energies [3] and virial [9], PME energies [2], M + mu, PME forces [2]
+  const size_t nn = (size_t)n;
+  if ((s = scratch(ctx, per_stream("epolar_ewald", st).c_str(),
+                   sizeof(double) * (16 + 10 * nn + 6 * nn), &buf)))
+    return s;
+  double* er = (double*)buf;
+  double* vir = er + 3;
+  double* ek = vir + 9;        // [2]: E_pme(M + mu), E_pme(M)
+  double* msum = ek + 4;       // padded to 16 doubles
+  double* fk = msum + 10 * nn; // [2][n][3]
+  EpolarPh<double> ph;
+  ph.xyz = sys->xyz;
+  ph.mpole = mpole;
+  ph.molid = sys->molid;
+  ph.polarity = polarity;
+  ph.thole = thole;
+  ph.mu = mu;
+  ph.g.set(sys->box, cutoff, ewald_beta);
+  if ((s = run_term(ctx, st, *P, ph, EpiForce{force}, er, vir))) return s;
+  k_mpole_plus_dipoles<<<ceil_div(n, 256), 256, 0, st>>>(n, mpole, mu, msum);
+  if ((s = pme_mpole_pair(ctx, st, sys, msum, mpole, ewald_beta, grid, order, ek, fk, ek + 1,
+                          fk + 3 * nn)))
+    return s;
+  k_epolar_ewald_sum<<<ceil_div(n, 256), 256, 0, st>>>(n, fk, fk + 3 * nn, er, ek, force, energy);
+  TK_HIP(hipGetLastError());
+  return TK_OK;
 }
 
 tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,

@@ -256,6 +256,12 @@ tk_status pme_prepared_dipole_field2(tk_ctx* ctx, hipStream_t st, int n, double 
                                      const double* v, const double* v2, double beta, int grid,
                                      int order, double* out, double* out2, const int32_t* done,
                                      const int32_t* done2, int run_when_done);
+// PME energies and forces of two multipole sets of the same sites in one
+// pass over the mesh (the two meshes packed into one complex FFT).  e1, e2:
+// device [1]; f1, f2: device [n][3].
+tk_status pme_mpole_pair(tk_ctx* ctx, hipStream_t st, const tk_system* sys, const double* m1,
+                         const double* m2, double beta, int grid, int order, double* e1,
+                         double* f1, double* e2, double* f2);
 // b_sorted[3 s + a] += reciprocal field of the permanent multipoles at site perm[s].
 tk_status pme_perm_field_add(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
                              const double* mpole, double beta, int grid, int order,

@@ -111,6 +111,8 @@ _SIGS = {
     "tk_polarize_pcg2_ewald": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp,
                                _d, _d, _i32, _i32, _d, _d, _i32, _vp, _vp,
                                C.POINTER(PcgInfo * 2)],
+    "tk_epolar_ewald": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
+                        _d, _i32, _i32, _vp, _vp],
     "tk_epolar2_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
                         _d, _d, _vp, _vp, _vp],
     "tk_rotate_mpole": [_vp, _vp, C.POINTER(System), _vp, _vp, _vp, _vp],
@@ -409,6 +411,21 @@ class Context:
         if st not in (OK, E_NOCONV, E_BREAKDOWN):
             _check(st, "tk_polarize_pcg2_ewald")
         return out, [{k: getattr(info[v], k) for k, _ in PcgInfo._fields_} for v in range(2)]
+
+    def epolar_ewald(self, sysref, lst, mpole, polarity, thole, mu, beta, cutoff, grid, order=5):
+        """Polarization energies [total, real space, reciprocal] and forces at
+        fixed dipoles with the full Ewald operator."""
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        m = _dev(mu, torch.float64, self.device, (sysref.n, 3), "mu")
+        e = torch.empty(3, dtype=torch.float64, device=self.device)
+        f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        _check(load().tk_epolar_ewald(self._h, _stream(self.device), C.byref(sysref.c),
+                                      C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), _ptr(m), beta,
+                                      cutoff, int(grid), int(order), _ptr(e), _ptr(f)),
+               "tk_epolar_ewald")
+        return e, f
 
     def epolar2_real(self, sysref, lst, mpole, polarity, thole, mu2, beta, cutoff, pscale):
         """Polarization forces with both dipole sets mu2[2,n,3] (mu_d first)."""

@@ -248,3 +248,24 @@ def test_multipole_ewald_total_independent_of_split(ctx):
         totals.append(float(np_(er)[0]) + float(np_(ek)[0]) + O.eself(w.mpole, beta))
     assert abs(totals[0] - totals[1]) <= 1e-5 * abs(totals[0]), totals
     assert abs(pieces[0] - pieces[1]) > 1.0 * abs(totals[0])   # the pieces move by far more
+
+
+@pytest.mark.parametrize("name,K", [("water216", 32), ("water7853", 64)])
+def test_epolar_ewald_one_call(ctx, name, K):
+    # tk_epolar_ewald against the oracle's composition: the real-space
+    # polarization pair terms plus E_pme(M + mu) - E_pme(M) and its forces
+    w, sysr, lst, rp, cp = _ewald_case(ctx, name, K, 5)
+    print(f"epolar ewald {name} K={K}", flush=True)
+    mu = np.random.default_rng(12).normal(0, 0.03, (w.n, 3))
+    e, f = ctx.epolar_ewald(sysr, lst, w.mpole, w.polarity, w.thole, mu, S["beta"], 7.0, K, 5)
+    er, fr, _ = O.epolar_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, mu,
+                              S["beta"], 7.0)
+    m2 = w.mpole.copy()
+    m2[:, 1:4] += mu
+    ea, fa, _ = O.pme_mpole(w.xyz, w.box, m2, S["beta"], K, 5)
+    eb, fb, _ = O.pme_mpole(w.xyz, w.box, w.mpole, S["beta"], K, 5)
+    e = np_(e)
+    assert abs(e[1] - er[0]) <= 1e-10 * abs(er[0])
+    assert abs(e[2] - (ea - eb)) <= 1e-9 * abs(ea - eb)
+    assert abs(e[0] - (er[0] + ea - eb)) <= 1e-9 * abs(er[0] + ea - eb)
+    assert fmax_rel(np_(f), fr + fa - fb) < 1e-8
