@@ -99,7 +99,7 @@ typedef struct {
   int32_t status;      /* TK_OK, TK_E_NOCONV or TK_E_BREAKDOWN */
   int32_t iters;       /* PCG updates performed (mat-vecs after the initial residual) */
   int32_t refinements; /* FP64 refinement rounds (TK_MIXED only) */
-  int32_t converged;   /* 1 if the stopping rule was met */
+  int32_t converged;   /* 1 if the stopping rule was met (TK_MIXED: the FP64 check) */
   double rms_debye;      /* RMS preconditioned residual at exit (solver recurrence) */
   double rms_true_debye; /* same, from a fresh FP64 residual b - A mu */
   double epol;           /* -1/2 C sum_i mu_i . E_perm_i, kcal/mol */
@@ -215,7 +215,9 @@ tk_status tk_tmatvec(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_n
  * each mat-vec: 4.80320 * sqrt(sum |alpha_i r_i|^2 / n_pol) <= tol_debye.
  * After the loop a fresh FP64 residual is formed (info->rms_true_debye);
  * with TK_MIXED, up to 3 FP64-residual refinement rounds are added while it
- * exceeds the tolerance.  mu_out: device [n][3], written in stream order
+ * exceeds the tolerance, and the outcome is that FP64 check: converged = 1
+ * and TK_OK only if rms_true_debye <= tol_debye at the end, else TK_E_NOCONV
+ * (also when the FP32 recurrence met its own test).  mu_out: device [n][3], written in stream order
  * (later work on `stream` sees it).  info: HOST memory, complete on return.
  * Returns info->status.  Synchronises `stream` while solving.
  */

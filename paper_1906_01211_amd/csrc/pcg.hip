@@ -1293,11 +1293,16 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
         info[k].refinements = ref + 1;
         info[k].rms_true_debye = S.host[k].rms_true;
         info[k].epol = S.host[k].epol;
-        if (S.host[k].rms_true <= tol_debye) {
-          info[k].converged = 1;
-          info[k].status = TK_OK;
-        }
       }
+    }
+    // the mixed form's outcome is its FP64 check: converged only when the
+    // true residual meets the tolerance after refinement, whatever the FP32
+    // recurrence reported (a breakdown stays a breakdown)
+    for (int k = 0; k < nsys; ++k) {
+      if (done[k] == 3) continue;
+      const bool ok = info[k].rms_true_debye <= tol_debye;
+      info[k].converged = ok ? 1 : 0;
+      info[k].status = ok ? TK_OK : TK_E_NOCONV;
     }
   }
   // the dipoles reach mu_out in stream order; the host already has the

@@ -700,12 +700,20 @@ template <int P, int K>
 __global__ __launch_bounds__(spread_threads<P>()) void k_pme_spread_tab(
     int n, const int* __restrict__ start, const int* __restrict__ list,
     const int* __restrict__ I0, const double* __restrict__ TB, const double* __restrict__ v,
-    unsigned long long* __restrict__ grid, int* __restrict__ flag, Gate gate) {
-  if (gate.closed()) return;
+    unsigned long long* __restrict__ grid, int* __restrict__ flag, Gate gate,
+    Gate partner = Gate{}, int packed = 0) {
   constexpr int YB = spread_rows<K>();
   constexpr int NYB = K / YB;
-  __shared__ unsigned long long tile[YB * K];
   const int gx = blockIdx.x / NYB, y0 = (blockIdx.x % NYB) * YB;
+  if (gate.closed()) {
+    // Packed with a second set that still runs: this set's part of the
+    // shared FFT must be an empty mesh, not the previous iteration's.
+    if (packed && !partner.closed())
+      for (int i = threadIdx.x; i < YB * K; i += blockDim.x)
+        grid[((long)gx * K + y0 + i / K) * K + i % K] = 0ull;
+    return;
+  }
+  __shared__ unsigned long long tile[YB * K];
   for (int i = threadIdx.x; i < YB * K; i += blockDim.x) tile[i] = 0ull;
   __syncthreads();   // flag: cleared once per solve, by the preparation
   bool bad = false;
@@ -961,11 +969,12 @@ tk_status field_prepared(tk_ctx* ctx, hipStream_t st, int n, double box, const d
   auto* fx2 = (unsigned long long*)fix2;
   {
     ProfScope ps(ctx, st, "pme_spread");
+    const int packed = v2 ? 1 : 0;
     k_pme_spread_tab<P, K><<<K * (K / spread_rows<K>()), spread_threads<P>(), 0, st>>>(
-        n, S.start, S.list, S.I0, S.TB, v, fx, S.flag, gate);
+        n, S.start, S.list, S.I0, S.TB, v, fx, S.flag, gate, gate2, packed);
     if (v2)
       k_pme_spread_tab<P, K><<<K * (K / spread_rows<K>()), spread_threads<P>(), 0, st>>>(
-          n, S.start, S.list, S.I0, S.TB, v2, fx2, S.flag, gate2);
+          n, S.start, S.list, S.I0, S.TB, v2, fx2, S.flag, gate2, gate, packed);
   }
   // the passes run while either right-hand side is open
   const Gate both{gate.done, gate.when, v2 ? gate2.done : nullptr};

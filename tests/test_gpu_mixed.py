@@ -61,6 +61,44 @@ def test_empole_mixed(ctx, tk, name):
     assert rms_err(f.cpu().numpy(), fo) <= 1e-4
 
 
+def field_budget(polarity):
+    # A field error dE moves a dipole by alpha dE.  The dipole budget is 1e-5 D
+    # RMS; the field and the mat-vec must stay ten times inside it:
+    # RMS|dE| * max(alpha) * 4.80320 D/(e A) <= 1e-6 D.
+    return 1e-6 / (DEBYE * float(np.max(polarity)))
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+def test_efield_mixed(ctx, tk, name):
+    # the mixed permanent field (the solver's right-hand side) element by element
+    w, sysr, lst, rp, cp = setup(ctx, name, 7.001, 2)
+    fld = ctx.efield_direct(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
+                            prec=tk.MIXED).cpu().numpy()
+    fo = O.efield_direct(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                         S["beta"], 7.0)
+    assert rms_err(fld, fo) <= field_budget(w.polarity), rms_err(fld, fo)
+    # and no single atom far outside it (FP32 rounding is spread, not concentrated)
+    assert np.abs(fld - fo).max() <= 20 * field_budget(w.polarity)
+    # it is the FP32 form: close to, but not bitwise, the FP64 one
+    f64 = ctx.efield_direct(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0).cpu().numpy()
+    assert not np.array_equal(fld, f64)
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+@pytest.mark.parametrize("diag", [0, 1])
+def test_tmatvec_mixed(ctx, tk, name, diag):
+    w, sysr, lst, rp, cp = setup(ctx, name, 7.001, 2)
+    mu = np.random.default_rng(11).normal(0, 0.05, size=(w.n, 3))
+    out = ctx.tmatvec(sysr, lst, w.polarity, w.thole, S["beta"], 7.0, mu, include_diag=diag,
+                      prec=tk.MIXED).cpu().numpy()
+    oo = O.tmatvec(w.xyz, w.box, rp, cp, w.polarity, w.thole, S["beta"], 7.0, mu, diag)
+    assert rms_err(out, oo) <= field_budget(w.polarity), rms_err(out, oo)
+    assert np.abs(out - oo).max() <= 20 * field_budget(w.polarity)
+    o64 = ctx.tmatvec(sysr, lst, w.polarity, w.thole, S["beta"], 7.0, mu,
+                      include_diag=diag).cpu().numpy()
+    assert not np.array_equal(out, o64)
+
+
 @pytest.mark.parametrize("name", ["water216", "water7853"])
 def test_pcg_mixed_dipoles(ctx, tk, name):
     w, sysr, lst, rp, cp = setup(ctx, name, 7.001, 2)
@@ -116,3 +154,20 @@ def test_charge_lj_mixed(ctx, tk):
     eo2, fo2, _ = O.evdw(w.xyz, w.box, w.molid, rp, cp, 1, w.vdw_rad, w.vdw_eps, 12.0)
     assert abs(float(e2) - eo2) <= 1e-6 * abs(eo2)
     assert rms_err(f2.cpu().numpy(), fo2) <= 1e-4
+
+
+def test_pcg_mixed_reports_failed_check(ctx, tk):
+    # one iteration per solve cannot reach 1e-5 D even with three refinement
+    # rounds (the FP64 solve needs 7): the outcome must say so, from the FP64
+    # residual, not from the FP32 recurrence
+    w, sysr, lst, rp, cp = setup(ctx, "water216", 7.001, 2)
+    mu, info = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
+                                tol_debye=S["tol_debye"], maxiter=1, prec=tk.MIXED)
+    assert info["refinements"] == 3
+    assert info["rms_true_debye"] > S["tol_debye"]
+    assert info["converged"] == 0 and info["status"] == tk.E_NOCONV
+    # the same call with room to converge reports success from the same check
+    mu, info = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
+                                tol_debye=S["tol_debye"], maxiter=100, prec=tk.MIXED)
+    assert info["converged"] == 1 and info["status"] == tk.OK
+    assert info["rms_true_debye"] <= S["tol_debye"]

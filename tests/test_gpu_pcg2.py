@@ -248,3 +248,32 @@ def test_pcg2_and_forces_random_boxes(ctx, seed):
     assert rel(np_(e)[0], eo[0]) < 1e-10
     assert fmax_rel(np_(f), fo) < 1e-8
     assert np.abs(np_(vir) - vo).max() <= 1e-10 * np.abs(vo).max()
+
+
+def test_pcg2_ewald_sets_stop_apart(ctx):
+    # Set 0 starts from the oracle's tightly converged dipoles and stops before
+    # its first iteration; set 1 starts from zero and iterates alone.  The two
+    # sets share each packed complex FFT, so this checks that the stopped
+    # set's half of the mesh no longer feeds the running set's field.
+    w, sysr, lst, rp, cp = case(ctx, "water216")
+    K = 32
+    tight, _ = O.polarize_pcg2_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                     S["beta"], 7.0, K, 0.5, tol_debye=1e-9, maxiter=200)
+    guess = np.stack([tight[0], np.zeros((w.n, 3))])
+    print("pcg2 ewald sets apart water216", flush=True)
+    mu, info = ctx.polarize_pcg2_ewald(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
+                                       K, 0.5, tol_debye=S["tol_debye"], mu_guess=guess)
+    mo, io = O.polarize_pcg2_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                   S["beta"], 7.0, K, 0.5, tol_debye=S["tol_debye"],
+                                   mu_guess=guess)
+    assert io[0]["iters"] == 0 and io[1]["iters"] >= 5
+    check(mu, info, mo, io)
+    # the same with the roles swapped
+    guess = np.stack([np.zeros((w.n, 3)), tight[1]])
+    mu, info = ctx.polarize_pcg2_ewald(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0,
+                                       K, 0.5, tol_debye=S["tol_debye"], mu_guess=guess)
+    mo, io = O.polarize_pcg2_ewald(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                   S["beta"], 7.0, K, 0.5, tol_debye=S["tol_debye"],
+                                   mu_guess=guess)
+    assert io[1]["iters"] == 0 and io[0]["iters"] >= 5
+    check(mu, info, mo, io)

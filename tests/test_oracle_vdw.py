@@ -46,6 +46,31 @@ def test_lj_special_values():
     assert e == 0.0
 
 
+@pytest.mark.parametrize("si,sj,ei,ej", [(3.15, 1.2, 0.152, 0.046), (2.0, 4.5, 0.3, 0.01),
+                                         (3.4, 3.0, 0.1, 0.2)])
+def test_lj_unequal_sigma(si, sj, ei, ej):
+    # Lorentz-Berthelot at unequal sigma and nonzero eps on both sites: the
+    # arithmetic-mean sigma puts the zero at (si+sj)/2 and the minimum -sqrt(ei ej)
+    # at 2^(1/6) (si+sj)/2 with zero slope.  A geometric-mean sigma (or an
+    # arithmetic-mean eps) fails each of these by far more than the tolerance.
+    s = 0.5 * (si + sj)
+    eij = np.sqrt(ei * ej)
+    e0, _ = pair_energy(s, O.VDW_LJ, si, sj, ei, ej)
+    assert abs(e0) < 1e-14
+    rmin = 2 ** (1 / 6) * s
+    e, f = pair_energy(rmin, O.VDW_LJ, si, sj, ei, ej)
+    assert e == pytest.approx(-eij, rel=1e-13)
+    assert abs(f[0, 0]) < 1e-13
+    # away from the special points: the closed form 4 eps_ij [(s/r)^12 - (s/r)^6]
+    r = 1.37 * s
+    e, f = pair_energy(r, O.VDW_LJ, si, sj, ei, ej)
+    sr6 = (s / r) ** 6
+    assert e == pytest.approx(4 * eij * (sr6 * sr6 - sr6), rel=1e-13)
+    # force on the second site along +x: -de/dr
+    assert f[1, 0] == pytest.approx(24 * eij * (2 * sr6 * sr6 - sr6) / r, rel=1e-12)
+    assert abs(s - np.sqrt(si * sj)) > 1e-3   # the cases do separate the two means
+
+
 @pytest.mark.parametrize("form", [O.VDW_HAL, O.VDW_LJ])
 def test_taper(form):
     rc = 9.0
