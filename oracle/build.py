@@ -1,4 +1,5 @@
-"""Build the FP64 CPU oracle (test infrastructure only) as liboracle.so.
+"""Build the FP64 CPU oracle (test infrastructure only) as liboracle.so, and
+its op-counting build as liboracle_ops.so.
 
 The oracle is plain C compiled with gcc, with floating-point contraction
 switched off so that every product and sum is rounded as written.
@@ -19,6 +20,8 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    from oracle import opcount   # its op-counting build (same source, counting scalar)
+    opcount.build(verbose=verbose)
     return LIB
 
 

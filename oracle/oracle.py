@@ -41,7 +41,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             from oracle import build as _b  # noqa: WPS433
             _b.build()
-        L = C.CDLL(LIB_PATH)
+        _lib = configure(C.CDLL(LIB_PATH))
+    return _lib
+
+
+def configure(L):
+    """Declare the argument and result types of the oracle's C functions on a
+    loaded library (the plain build, or its op-counting build)."""
+    if True:   # one block of declarations
         L.or_coulomb_constant.restype = C.c_double
         L.or_debye_factor.restype = C.c_double
         L.or_quantize.argtypes = [C.c_int, _dp, C.c_double, _up]
@@ -105,8 +112,7 @@ def lib():
                                        C.c_void_p]
         L.or_epolar_frames.argtypes = [C.c_int, _dp, C.c_double, _ip, _ip, _ip, _ip, _ip, _dp,
                                        _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
-        _lib = L
-    return _lib
+    return L
 
 
 def _d(a, shape=None):
