@@ -65,7 +65,8 @@ enum {
   TK_E_NOMEM = -6,     /* device allocation failed */
   TK_E_HIP = -7,       /* a HIP runtime call failed */
   TK_E_BUSY = -8,      /* serving: result not ready yet */
-  TK_E_PLAN = -9       /* the list's plan slot is empty or was built for another system */
+  TK_E_PLAN = -9,      /* the list's plan slot is empty or was built for another system */
+  TK_E_TOOBIG = -10    /* allocation-free call: the system needs more than its fixed scratch */
 };
 
 enum { TK_FP64 = 0, TK_MIXED = 1 };
@@ -205,6 +206,25 @@ tk_status tk_efield_direct(tk_ctx* ctx, void* stream, const tk_system* sys, cons
 tk_status tk_tmatvec(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
                      const double* polarity, const double* thole, double ewald_beta,
                      double cutoff, int include_diag, int prec, const double* mu, double* out);
+
+/*
+ * tk_tmatvec for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, result and errors as tk_tmatvec (bitwise the same result), but no
+ * device allocation at all: its scratch is one fixed 32 MiB array in the
+ * library, one copy per device, held until the process ends.  The list's plan
+ * must already exist (tk_nblist_build allocates; this call does not).  Limit:
+ * n <= tk_tmatvec_noalloc_max_atoms() (46,592 atoms), else TK_E_TOOBIG with
+ * nothing launched.  Every call on a device shares that device's array, so
+ * calls that overlap on one device (other streams, other contexts) race and
+ * must be ordered by the caller.
+ */
+tk_status tk_tmatvec_noalloc(tk_ctx* ctx, void* stream, const tk_system* sys,
+                             const tk_nblist* list, const double* polarity, const double* thole,
+                             double ewald_beta, double cutoff, int include_diag, int prec,
+                             const double* mu, double* out);
+/* The largest atom count tk_tmatvec_noalloc accepts. */
+int32_t tk_tmatvec_noalloc_max_atoms(void);
 
 /*
  * Induced dipoles: solve A mu = E_perm (A as in tk_tmatvec, E_perm as in

@@ -395,7 +395,8 @@ static hipEvent_t take_event(tk_ctx* ctx) {
 
 ProfScope::ProfScope(tk_ctx* c, hipStream_t s, const std::string& name, bool kernel_events)
     : ctx(c), st(s) {
-  if (!ctx->prof_on || (!ctx->prof_only.empty() && ctx->prof_only != name)) return;
+  // an empty name is never timed
+  if (!ctx->prof_on || name.empty() || (!ctx->prof_only.empty() && ctx->prof_only != name)) return;
   a = take_event(ctx);
   if (!a) return;
   if (kernel_events) {
@@ -469,8 +470,12 @@ tk_status tk_create(int device, tk_ctx** out) {
   TK_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return TK_E_ARG;
   TK_HIP(hipSetDevice(device));
+  void* fixed = nullptr;   // this device's copy of the allocation-free entry point's scratch
+  tk_status s = tk::noalloc_setup(device, &fixed);
+  if (s) return s;
   tk_ctx* c = new tk_ctx();
   c->device = device;
+  c->noalloc_scratch = fixed;
   *out = c;
   return TK_OK;
 }
@@ -541,6 +546,8 @@ const char* tk_strerror(tk_status s) {
     case TK_E_HIP: return "HIP runtime error";
     case TK_E_BUSY: return "result not ready";
     case TK_E_PLAN: return "neighbour-list plan missing or built for another system";
+    case TK_E_TOOBIG:
+      return "system too large for the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }

@@ -267,4 +267,15 @@ inline void launch_units(const Plan& P, const Ph& ph, double* partial, long pstr
 
 inline long pad64(long n) { return (n + 63) / 64 * 64; }
 
+// Device buffers of one pair-term call, when the caller supplies them (the
+// allocation-free entry points): partial slots [kMaxSlots][NA][pad64(n)],
+// gathered fields [NG][pad64(n)], unit scalars [nunits][NS] and chunk sums
+// [chunks][NS] (the last two only for terms with energies).
+struct TermWs {
+  double* partial = nullptr;
+  double* gathered = nullptr;
+  double* uscal = nullptr;
+  double* cpart = nullptr;
+};
+
 }  // namespace tk

@@ -29,7 +29,7 @@ tk_status common_args(tk_ctx* ctx, const tk_system* sys, const tk_nblist* list, 
 template <class R>
 tk_status launch_tmat(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_system* sys,
                       const double* polarity, const double* thole, double beta, double cutoff,
-                      int include_diag, const double* mu, double* out) {
+                      int include_diag, const double* mu, double* out, const TermWs* ws) {
   TmatPh<R> ph;
   ph.xyz = sys->xyz;
   ph.mu = mu;
@@ -40,7 +40,33 @@ tk_status launch_tmat(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_syste
   ph.molid = sys->molid;
   ph.perm_ = (const int32_t*)P.perm.p;
   EpiMutual epi{out, mu, polarity, ph.g.cself, include_diag};
-  return run_term(ctx, st, P, ph, epi, nullptr, nullptr);
+  return run_term(ctx, st, P, ph, epi, nullptr, nullptr, ws);
+}
+
+size_t tmatvec_ws_doubles(const Plan& P) { return term_ws_doubles<TmatPh<double>>(P); }
+size_t tmatvec_ws_doubles_n(long n) {
+  return (size_t)pad64(n) * (kMaxSlots * TmatPh<double>::NA + TmatPh<double>::NG);
+}
+static_assert(TmatPh<double>::NA == TmatPh<float>::NA && TmatPh<double>::NG == TmatPh<float>::NG,
+              "both precisions take the same buffers");
+
+tk_status tmatvec_checked(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
+                          const tk_nblist* list, const double* polarity, const double* thole,
+                          double ewald_beta, double cutoff, int include_diag, int prec,
+                          const double* mu, double* out, const TermWs* ws,
+                          size_t ws_limit_doubles) {
+  const Plan* P;
+  tk_status s = common_args(ctx, sys, list, cutoff, prec, &P);
+  if (s) return s;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta)) return TK_E_ARG;
+  if (include_diag != 0 && include_diag != 1) return TK_E_ARG;
+  if (sys->n == 0) return TK_OK;
+  if (!polarity || !thole || !mu || !out) return TK_E_ARG;
+  if (ws && tmatvec_ws_doubles(*P) > ws_limit_doubles) return TK_E_TOOBIG;
+  return prec == TK_FP64 ? launch_tmat<double>(ctx, st, *P, sys, polarity, thole, ewald_beta,
+                                               cutoff, include_diag, mu, out, ws)
+                         : launch_tmat<float>(ctx, st, *P, sys, polarity, thole, ewald_beta,
+                                              cutoff, include_diag, mu, out, ws);
 }
 
 
@@ -158,18 +184,8 @@ tk_status tk_efield_direct(tk_ctx* ctx, void* stream, const tk_system* sys, cons
 tk_status tk_tmatvec(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,
                      const double* polarity, const double* thole, double ewald_beta,
                      double cutoff, int include_diag, int prec, const double* mu, double* out) {
-  const Plan* P;
-  tk_status s = common_args(ctx, sys, list, cutoff, prec, &P);
-  if (s) return s;
-  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta)) return TK_E_ARG;
-  if (include_diag != 0 && include_diag != 1) return TK_E_ARG;
-  if (sys->n == 0) return TK_OK;
-  if (!polarity || !thole || !mu || !out) return TK_E_ARG;
-  hipStream_t st = (hipStream_t)stream;
-  return prec == TK_FP64 ? launch_tmat<double>(ctx, st, *P, sys, polarity, thole, ewald_beta,
-                                               cutoff, include_diag, mu, out)
-                         : launch_tmat<float>(ctx, st, *P, sys, polarity, thole, ewald_beta,
-                                              cutoff, include_diag, mu, out);
+  return tmatvec_checked(ctx, (hipStream_t)stream, sys, list, polarity, thole, ewald_beta, cutoff,
+                         include_diag, prec, mu, out, nullptr, 0);
 }
 
 tk_status tk_epolar_real(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nblist* list,

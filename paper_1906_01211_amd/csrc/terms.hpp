@@ -1339,40 +1339,54 @@ struct EpiMutual {   // mutual field (T + cI) mu, or A mu = mu/alpha - field
 // Launch one pair term over a plan: units -> per-atom reduce (Epi) ->
 // per-system energies and virial (terms with unit scalars; energy and virial
 // are device arrays of [nsys][NS - 9] and [nsys][9]).
+template <class Ph>
+inline size_t term_ws_doubles(const Plan& P) {
+  return (size_t)pad64(P.n) * (kMaxSlots * Ph::NA + Ph::NG);
+}
+
 template <class Ph, class Epi>
 tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, const Epi& epi,
-                   double* energy, double* virial) {
+                   double* energy, double* virial, const TermWs* ws = nullptr) {
   const long pstride = pad64(P.n);
   void *partial, *uscal;
   tk_status s;
   const size_t ns1 = Ph::NS > 0 ? Ph::NS : 1;
-  if ((s = scratch(ctx, per_stream("partial", st).c_str(),
-                   sizeof(double) * kMaxSlots * Ph::NA * pstride, &partial)) ||
-      (s = scratch(ctx, per_stream("uscal", st).c_str(), sizeof(double) * (size_t)P.nunits * ns1,
-                   &uscal)))
+  const bool sums = Ph::NS > 0 && energy && virial;
+  if (ws && (!ws->partial || !ws->gathered || (sums && (!ws->uscal || !ws->cpart))))
+    return TK_E_ARG;
+  if (ws) {
+    partial = ws->partial;
+    uscal = ws->uscal;
+  } else if ((s = scratch(ctx, per_stream("partial", st).c_str(),
+                          sizeof(double) * kMaxSlots * Ph::NA * pstride, &partial)) ||
+             (s = scratch(ctx, per_stream("uscal", st).c_str(),
+                          sizeof(double) * (size_t)P.nunits * ns1, &uscal)))
     return s;
   PlanView pv = P.view();
   if (unit_lds_bytes<Ph>(P, 1) > kMaxLds) return TK_E_CAPACITY;
   void* gathered;
-  if ((s = scratch(ctx, per_stream("gathered", st).c_str(), sizeof(double) * Ph::NG * pstride,
-                   &gathered)))
+  if (ws)
+    gathered = ws->gathered;
+  else if ((s = scratch(ctx, per_stream("gathered", st).c_str(),
+                        sizeof(double) * Ph::NG * pstride, &gathered)))
     return s;
   Ph phg = ph;
   phg.sorted = (const double*)gathered;
   phg.gstride = pstride;
   k_gather<Ph><<<ceil_div(P.n, 256), 256, 0, st>>>(pv, phg, (double*)gathered, pstride);
   {
-    ProfScope ps(ctx, st, std::string("units_") + Ph::kName + Ph::kTag);
+    // no timing events on the caller-supplied-buffer path (creating one may allocate)
+    ProfScope ps(ctx, st, ws ? std::string() : std::string("units_") + Ph::kName + Ph::kTag);
     launch_units(P, phg, (double*)partial, pstride, (double*)uscal, st);
   }
-  const bool sums = Ph::NS > 0 && energy && virial;
   const int nchunk = sums ? total_chunks(P) : 0;
-  void* cpart = nullptr;
-  if (sums && (s = scratch(ctx, per_stream("chunk_sums", st).c_str(),
-                           sizeof(double) * ns1 * (size_t)(nchunk > 0 ? nchunk : 1), &cpart)))
+  void* cpart = ws ? ws->cpart : nullptr;
+  if (!ws && sums &&
+      (s = scratch(ctx, per_stream("chunk_sums", st).c_str(),
+                   sizeof(double) * ns1 * (size_t)(nchunk > 0 ? nchunk : 1), &cpart)))
     return s;
   {
-    ProfScope ps(ctx, st, "reduce_atoms");
+    ProfScope ps(ctx, st, ws ? std::string() : std::string("reduce_atoms"));
     const int nb = std::max(ceil_div((long)P.n * kRedLanes, 256), nchunk);
     k_reduce<Ph::NA, Ph::NS, Epi><<<nb, 256, 0, st>>>(pv, (double*)partial, pstride, epi,
                                                       sums ? (const double*)uscal : nullptr,

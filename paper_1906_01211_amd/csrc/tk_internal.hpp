@@ -173,6 +173,7 @@ struct tk_ctx {
   size_t pinned_bytes = 0;
   int pcg_hint[tk::kNumPlans][2] = {};         // last solve's iteration count per plan slot, precision
   bool nb_info_zero[4] = {};                   // per build of a group: its status words are zero
+  void* noalloc_scratch = nullptr;             // device address of the fixed scratch array
 };
 
 namespace tk {
@@ -272,6 +273,23 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                         int32_t maxiter, int prec, const double* mu_guess,
                         const int32_t* guess_on, double* mu_out, tk_pcg_info* info,
                         int pme_grid = 0, int pme_order = 0, int nv = 1, double pscale = 0.0);
+
+// The allocation-free entry point's fixed scratch (noalloc.hip): resolves
+// the device address of this device's copy of the array (once per device;
+// the device must be current) into *addr.
+tk_status noalloc_setup(int device, void** addr);
+struct TermWs;
+// Mutual-field mat-vec with its argument checks (tk_tmatvec); with ws set,
+// every device buffer comes from ws and the call fails with TK_E_TOOBIG when
+// they would need more than ws_limit_doubles doubles.
+tk_status tmatvec_checked(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
+                          const tk_nblist* list, const double* polarity, const double* thole,
+                          double ewald_beta, double cutoff, int include_diag, int prec,
+                          const double* mu, double* out, const TermWs* ws,
+                          size_t ws_limit_doubles);
+// Doubles of scratch the mat-vec takes for n atoms (partial slots and
+// gathered fields, each padded to a multiple of 64 atoms).
+size_t tmatvec_ws_doubles_n(long n);
 
 // Checks shared by the pair entry points.
 tk_status check_system(const tk_system* sys);

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libtk.so")
 
 OK, E_ARG, E_CUTOFF, E_CAPACITY, E_NOCONV, E_BREAKDOWN, E_NOMEM, E_HIP, E_BUSY, E_PLAN = (
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+E_TOOBIG = -10
 FP64, MIXED = 0, 1
 VDW_HAL, VDW_LJ = 0, 1
 MAX_PLANS = 8
@@ -99,6 +100,9 @@ _SIGS = {
                          C.c_int, _vp],
     "tk_tmatvec": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _d, _d, C.c_int,
                    C.c_int, _vp, _vp],
+    "tk_tmatvec_noalloc": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _d, _d,
+                           C.c_int, C.c_int, _vp, _vp],
+    "tk_tmatvec_noalloc_max_atoms": [],
     "tk_polarize_pcg": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d, _d,
                         _i32, C.c_int, _vp, _vp, C.POINTER(PcgInfo)],
     "tk_epolar_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
@@ -327,6 +331,14 @@ class Context:
                                  _ptr(pol), _ptr(th), beta, cutoff, int(include_diag), prec,
                                  _ptr(m), _ptr(out)), "tk_tmatvec")
         return out
+
+    def tmatvec_noalloc(self, sysref, lst, polarity, thole, beta, cutoff, mu, out,
+                        include_diag=0, prec=FP64):
+        """tk_tmatvec_noalloc into the caller's `out` (device [n][3] float64);
+        returns the status (no allocation on the library side)."""
+        return load().tk_tmatvec_noalloc(self._h, _stream(self.device), C.byref(sysref.c),
+                                         C.byref(lst.c), _ptr(polarity), _ptr(thole), beta,
+                                         cutoff, int(include_diag), prec, _ptr(mu), _ptr(out))
 
     def polarize_pcg(self, sysref, lst, mpole, polarity, thole, beta, cutoff, tol_debye=1e-5,
                      maxiter=100, prec=FP64, mu_guess=None):
