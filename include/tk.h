@@ -615,8 +615,21 @@ tk_status tk_server_submit(tk_server* srv, const tk_request* req, uint64_t* id);
 tk_status tk_server_poll(tk_server* srv, uint64_t id, tk_step_result* result, tk_timing* timing,
                          double* force_mpole, double* mu, double* force_vdw);
 tk_status tk_server_release(tk_server* srv, uint64_t id);
-/* Waits for every submitted request, then stops the worker and frees all. */
+/* Lanes, batches and measured device memory of the server (host struct). */
+tk_status tk_server_stats(tk_server* srv, tk_server_usage* out);
+/* Waits for every submitted request, then stops the lanes and frees all. */
 void tk_server_destroy(tk_server* srv);
+
+/*
+ * Device-memory budget of a context: the sum of the device buffers the
+ * context keeps (plans, solver and pair-term scratch; all grow-only) may not
+ * exceed `bytes` (0: no bound, the default).  A call that would need more
+ * returns TK_E_NOMEM before launching anything that uses the missing buffer;
+ * the buffers the context already holds stay valid, so the caller may raise
+ * the budget and call again.  tk_arena_bytes returns what the context holds.
+ */
+tk_status tk_set_arena_budget(tk_ctx* ctx, size_t bytes);
+size_t tk_arena_bytes(const tk_ctx* ctx);
 
 /*
  * Kernel timing (tracing aid).  When enabled, the library brackets its kernel

@@ -14,29 +14,37 @@ tk_status hip_status(hipError_t e, const char* what) {
   return TK_E_HIP;
 }
 
-tk_status ensure(DevBuf& b, size_t bytes) {
+tk_status ensure(tk_ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return TK_OK;
+  size_t want = bytes + bytes / 4;   // headroom so slightly larger inputs reuse it
+  want = (want + 255) & ~size_t(255);
+  // the context's device budget (the old buffer is kept when it refuses)
+  const size_t total = ctx->arena_bytes - b.bytes + want;
+  if (ctx->arena_budget && total > ctx->arena_budget) {
+    if (ctx->arena_budget >= ctx->arena_bytes - b.bytes + bytes) want = bytes;   // no headroom
+    else return TK_E_NOMEM;
+  }
   if (b.p) {
     TK_HIP(hipDeviceSynchronize());   // queued kernels may still use the old buffer
     TK_HIP(hipFree(b.p));
+    ctx->arena_bytes -= b.bytes;
     b.p = nullptr;
     b.bytes = 0;
   }
-  size_t want = bytes + bytes / 4;   // headroom so slightly larger inputs reuse it
-  want = (want + 255) & ~size_t(255);
   hipError_t e = hipMalloc(&b.p, want);
   if (e != hipSuccess) {
     b.p = nullptr;
     return hip_status(e, "hipMalloc");
   }
   b.bytes = want;
+  ctx->arena_bytes += want;
   return TK_OK;
 }
 
 tk_status scratch(tk_ctx* ctx, const char* name, size_t bytes, void** out) {
   DevBuf& b = ctx->scratch[name];
-  tk_status s = ensure(b, bytes);
+  tk_status s = ensure(ctx, b, bytes);
   *out = b.p;
   return s;
 }
@@ -480,6 +488,14 @@ tk_status tk_create(int device, tk_ctx** out) {
   return TK_OK;
 }
 
+tk_status tk_set_arena_budget(tk_ctx* ctx, size_t bytes) {
+  if (!ctx) return TK_E_ARG;
+  ctx->arena_budget = bytes;
+  return TK_OK;
+}
+
+size_t tk_arena_bytes(const tk_ctx* ctx) { return ctx ? ctx->arena_bytes : 0; }
+
 tk_status tk_profile_enable(tk_ctx* ctx, int on, const char* only) {
   if (!ctx) return TK_E_ARG;
   ctx->prof_on = on != 0;
@@ -523,11 +539,15 @@ void tk_destroy(tk_ctx* ctx) {
   };
   for (auto& p : ctx->plans) {
     freeb(p.perm); freeb(p.scell); freeb(p.cell_start); freeb(p.unit_off); freeb(p.unit_cnt);
-    freeb(p.codes); freeb(p.us); freeb(p.slots);
+    freeb(p.codes); freeb(p.us); freeb(p.slots); freeb(p.urec); freeb(p.sysd);
+    freeb(p.cell_sys); freeb(p.bunits); freeb(p.bnslot); freeb(p.bcu); freeb(p.border);
+    freeb(p.tplp);
   }
   for (auto& kv : ctx->tables) {
     freeb(kv.second.units_d);
     freeb(kv.second.nslot_d);
+    freeb(kv.second.cu_d);
+    freeb(kv.second.order_d);
   }
   for (auto& kv : ctx->scratch) freeb(kv.second);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);

@@ -8,7 +8,8 @@
 //      writes each unit's listed pairs into its window and counts, per
 //      (unit role, atom), the pairs whose CSR row is that atom's
 //   -> row lengths + role offsets -> scan  [one host synchronisation]
-//   -> canonical CSR written from the pair codes -> rows ordered by j.
+//   -> dense pair codes, with the canonical CSR entries written from them in
+//      the same pass -> rows ordered by j.
 // Every pair decision is the same exact test, so the plan (what the pair
 // kernels read) and the CSR (what the caller reads) hold the same pair set.
 #include <cmath>
@@ -410,7 +411,18 @@ __global__ __launch_bounds__(64 * kPlanMaxWaves) void k_plan(
 // Per unit: move the unit's pair codes from the regions of its candidate
 // window to its place in the dense code array (windows are sized by
 // candidates, the dense array by listed pairs), regions in (chunk, wave)
-// order; and write the unit's record for the pair kernels (see UnitRec).
+// order; write the unit's record for the pair kernels (see UnitRec); and,
+// when the caller asked for the CSR (col set), put each pair's j into its
+// row at the owner atom's role offset (order inside a role is fixed by the
+// row sort that follows).
+struct CsrOut {
+  const int32_t* perm;
+  const int32_t* slot_off;   // per (role, sorted atom): offset inside the owner's row
+  const int32_t* row_ptr;
+  int32_t* col;              // nullptr: no CSR
+  long pstride;
+  int occ;                   // dynamic LDS: 4 * occ ints
+};
 __global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ woff,
                                                  const uint32_t* __restrict__ windows,
                                                  const int64_t* __restrict__ doff,
@@ -421,14 +433,35 @@ __global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ wof
                                                  const int32_t* __restrict__ cstart,
                                                  const int32_t* __restrict__ unit_cnt,
                                                  const int32_t* __restrict__ cell_sys,
-                                                 UnitRec* __restrict__ rec) {
+                                                 UnitRec* __restrict__ rec, CsrOut csr) {
   __shared__ int rs[kPlanRegions], rd[kPlanRegions + 1];
+  extern __shared__ int csr_lds[];   // pH pK | bH bK (occ each); cursors reuse nothing
+  __shared__ int cH[kMaxCellAtoms], cK[kMaxCellAtoms];
   const int u = blockIdx.x, tid = threadIdx.x;
-  if (tid == 64) {   // a lane of the second wave: the record, beside wave 0's prefix
-    const Unit un = units[u];
-    const int hs = cstart[un.h], ks = cstart[un.k];
-    rec[u] = UnitRec{hs, cstart[un.h + 1] - hs, ks, cstart[un.k + 1] - ks, un.slot_h, un.slot_k,
-                     cell_sys ? cell_sys[un.h] : 0, unit_cnt[u], doff[u]};
+  const Unit un = units[u];
+  const int hs = cstart[un.h], nh = cstart[un.h + 1] - hs;
+  const int ks = cstart[un.k], nk = cstart[un.k + 1] - ks;
+  if (tid == 64)   // a lane of the second wave: the record, beside wave 0's prefix
+    rec[u] = UnitRec{hs, nh, ks, nk, un.slot_h, un.slot_k, cell_sys ? cell_sys[un.h] : 0,
+                     unit_cnt[u], doff[u]};
+  const bool fill = csr.col != nullptr && nh <= csr.occ && nk <= csr.occ;
+  int* pH = csr_lds;
+  int* pK = pH + csr.occ;
+  int* bH = pK + csr.occ;
+  int* bK = bH + csr.occ;
+  if (fill) {
+    for (int t = tid; t < nh; t += 256) {
+      const int i = csr.perm[hs + t];
+      pH[t] = i;
+      cH[t] = 0;
+      bH[t] = csr.row_ptr[i] + csr.slot_off[(long)un.slot_h * csr.pstride + hs + t];
+    }
+    for (int t = tid; t < nk; t += 256) {
+      const int i = csr.perm[ks + t];
+      pK[t] = i;
+      cK[t] = 0;
+      bK[t] = csr.row_ptr[i] + csr.slot_off[(long)un.slot_k * csr.pstride + ks + t];
+    }
   }
   const int2 nf = nfilt[u];
   const int nhf = nf.x, nkf = nf.y;
@@ -473,7 +506,15 @@ __global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ wof
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (t0 + k * 256 < m) dst[t0 + k * 256] = v[k];
+      if (t0 + k * 256 < m) {
+        dst[t0 + k * 256] = v[k];
+        if (fill) {
+          const int a = (int)(v[k] & 0xffffu), b = (int)(v[k] >> 16);
+          const int ia = pH[a], ib = pK[b];
+          if (ia < ib) csr.col[bH[a] + atomicAdd(&cH[a], 1)] = ib;
+          else csr.col[bK[b] + atomicAdd(&cK[b], 1)] = ia;
+        }
+      }
   }
 }
 
@@ -501,62 +542,6 @@ __global__ void k_row_slots(int n, const int32_t* __restrict__ perm, const int32
   int m = run;
   for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
   if ((threadIdx.x & 63) == 0) atomicMax(&info[2], m);
-}
-
-// One wave per unit: each listed pair's j goes into its CSR row, at the
-// owner atom's role offset (order inside a role is fixed by the row sort).
-__global__ __launch_bounds__(256) void k_csr_fill(const Unit* __restrict__ units,
-                                                  const int32_t* __restrict__ cstart,
-                                                  const int32_t* __restrict__ perm, long pstride,
-                                                  const int64_t* __restrict__ unit_off,
-                                                  const int32_t* __restrict__ unit_cnt,
-                                                  const uint32_t* __restrict__ codes,
-                                                  const int32_t* __restrict__ slot_off,
-                                                  const int32_t* __restrict__ row_ptr,
-                                                  int32_t* __restrict__ col, int occ) {
-  // dynamic LDS, occ entries each: pH pK cH cK bH bK
-  extern __shared__ int fill_lds[];
-  int* pH = fill_lds;
-  int* pK = pH + occ;
-  int* cH = pK + occ;
-  int* cK = cH + occ;
-  int* bH = cK + occ;
-  int* bK = bH + occ;
-  const int uidx = blockIdx.x, tid = threadIdx.x;
-  const Unit un = units[uidx];
-  const int hs = cstart[un.h], nh = cstart[un.h + 1] - hs;
-  const int ks = cstart[un.k], nk = cstart[un.k + 1] - ks;
-  if (nh > occ || nk > occ) return;
-  for (int t = tid; t < nh; t += 256) {
-    const int i = perm[hs + t];
-    pH[t] = i;
-    cH[t] = 0;
-    bH[t] = row_ptr[i] + slot_off[(long)un.slot_h * pstride + hs + t];
-  }
-  for (int t = tid; t < nk; t += 256) {
-    const int i = perm[ks + t];
-    pK[t] = i;
-    cK[t] = 0;
-    bK[t] = row_ptr[i] + slot_off[(long)un.slot_k * pstride + ks + t];
-  }
-  __syncthreads();
-  // positions inside a row segment depend on the atomics' order; the row
-  // sort that follows makes every row canonical
-  const uint32_t* src = codes + unit_off[uidx];
-  const int m = unit_cnt[uidx];
-  for (int p0 = tid; p0 < m; p0 += 4 * 256) {
-    uint32_t cd[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) cd[k] = p0 + k * 256 < m ? src[p0 + k * 256] : 0xffffffffu;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (cd[k] == 0xffffffffu) continue;
-      const int a = (int)(cd[k] & 0xffffu), b = (int)(cd[k] >> 16);
-      const int ia = pH[a], ib = pK[b];
-      if (ia < ib) col[bH[a] + atomicAdd(&cH[a], 1)] = ib;
-      else col[bK[b] + atomicAdd(&cK[b], 1)] = ia;
-    }
-  }
 }
 
 // Batch plans: the unit and cell tables of every system, from the per-nc
@@ -744,13 +729,13 @@ tk_status rowsort_attribute(size_t lds) {
 }  // namespace
 
 // Upload a cells-per-edge template table once.
-static tk_status upload_tables(CellTables& T) {
+static tk_status upload_tables(tk_ctx* ctx, CellTables& T) {
   if (T.uploaded) return TK_OK;
   tk_status s;
-  if ((s = ensure(T.units_d, sizeof(Unit) * T.nunits)) ||
-      (s = ensure(T.nslot_d, sizeof(int32_t) * T.ncells)) ||
-      (s = ensure(T.cu_d, sizeof(int32_t) * T.cu.size())) ||
-      (s = ensure(T.order_d, sizeof(int32_t) * T.order.size())))
+  if ((s = ensure(ctx, T.units_d, sizeof(Unit) * T.nunits)) ||
+      (s = ensure(ctx, T.nslot_d, sizeof(int32_t) * T.ncells)) ||
+      (s = ensure(ctx, T.cu_d, sizeof(int32_t) * T.cu.size())) ||
+      (s = ensure(ctx, T.order_d, sizeof(int32_t) * T.order.size())))
     return s;
   TK_HIP(hipMemcpy(T.cu_d.p, T.cu.data(), sizeof(int32_t) * T.cu.size(), hipMemcpyHostToDevice));
   TK_HIP(hipMemcpy(T.order_d.p, T.order.data(), sizeof(int32_t) * T.order.size(),
@@ -833,7 +818,7 @@ static tk_status build_check(tk_ctx* ctx, BuildJob& J) {
     int nc = (int)std::floor(box / cut);
     if (nc < 1) nc = 1;
     CellTables& T = cell_tables(ctx, nc);
-    if ((s = upload_tables(T))) return s;
+    if ((s = upload_tables(ctx, T))) return s;
     J.tabs[k] = &T;
     const uint64_t rq = (uint64_t)std::floor((cut / box) * kTwo32);
     SysDev& d = J.sd[k];
@@ -909,20 +894,20 @@ static tk_status build_begin(tk_ctx* ctx, BuildJob& J, char* hb, char* hdb) {
   const int nn = n > 0 ? n : 1;
   J.pstride = (nn + 63) / 64 * 64;
   tk_status s;
-  if ((s = ensure(P.perm, sizeof(int32_t) * nn)) || (s = ensure(P.scell, sizeof(int32_t) * nn)) ||
-      (s = ensure(P.cell_start, sizeof(int32_t) * (ncells + 1))) ||
-      (s = ensure(P.unit_off, sizeof(int64_t) * (nunits + 1))) ||
-      (s = ensure(P.unit_cnt, sizeof(int32_t) * nunits)) ||
-      (s = ensure(P.us, sizeof(uint4) * nn)) ||
-      (s = ensure(P.slots, sizeof(int32_t) * kMaxSlots * J.pstride)))
+  if ((s = ensure(ctx, P.perm, sizeof(int32_t) * nn)) || (s = ensure(ctx, P.scell, sizeof(int32_t) * nn)) ||
+      (s = ensure(ctx, P.cell_start, sizeof(int32_t) * (ncells + 1))) ||
+      (s = ensure(ctx, P.unit_off, sizeof(int64_t) * (nunits + 1))) ||
+      (s = ensure(ctx, P.unit_cnt, sizeof(int32_t) * nunits)) ||
+      (s = ensure(ctx, P.us, sizeof(uint4) * nn)) ||
+      (s = ensure(ctx, P.slots, sizeof(int32_t) * kMaxSlots * J.pstride)))
     return s;
   const void* sysd_was = P.sysd.p;
-  if ((s = ensure(P.sysd, sizeof(SysDev) * (nsys + 1)))) return s;
+  if ((s = ensure(ctx, P.sysd, sizeof(SysDev) * (nsys + 1)))) return s;
   // candidate windows: scratch of the build (the plan keeps the dense
   // codes); grown to the exact size and rerun if the estimate is short
   J.wb = &ctx->scratch[J.nm("nb_windows")];
   if (J.wb->bytes < sizeof(uint32_t) * (size_t)J.est &&
-      (s = ensure(*J.wb, sizeof(uint32_t) * (size_t)J.est)))
+      (s = ensure(ctx, *J.wb, sizeof(uint32_t) * (size_t)J.est)))
     return s;
   if ((s = scratch(ctx, J.nm("nb_u").c_str(), sizeof(uint32_t) * 3 * nn, &J.u)) ||
       (s = scratch(ctx, J.nm("nb_cell").c_str(), sizeof(int32_t) * nn, &J.cell)) ||
@@ -965,12 +950,12 @@ static tk_status build_begin(tk_ctx* ctx, BuildJob& J, char* hb, char* hdb) {
     for (int k = 0; k < nsys; ++k)
       tp[k] = TplPtrs{(const Unit*)J.tabs[k]->units_d.p, (const int32_t*)J.tabs[k]->nslot_d.p,
                       (const int32_t*)J.tabs[k]->cu_d.p, (const int32_t*)J.tabs[k]->order_d.p};
-    if ((s = ensure(P.tplp, sizeof(TplPtrs) * nsys)) ||
-        (s = ensure(P.bunits, sizeof(Unit) * nunits)) ||
-        (s = ensure(P.bnslot, sizeof(int32_t) * ncells)) ||
-        (s = ensure(P.bcu, sizeof(int32_t) * kCellUnitStride * (size_t)ncells)) ||
-        (s = ensure(P.cell_sys, sizeof(int32_t) * ncells)) ||
-        (s = ensure(P.border, sizeof(int32_t) * ncells)))
+    if ((s = ensure(ctx, P.tplp, sizeof(TplPtrs) * nsys)) ||
+        (s = ensure(ctx, P.bunits, sizeof(Unit) * nunits)) ||
+        (s = ensure(ctx, P.bnslot, sizeof(int32_t) * ncells)) ||
+        (s = ensure(ctx, P.bcu, sizeof(int32_t) * kCellUnitStride * (size_t)ncells)) ||
+        (s = ensure(ctx, P.cell_sys, sizeof(int32_t) * ncells)) ||
+        (s = ensure(ctx, P.border, sizeof(int32_t) * ncells)))
       return s;
     TK_HIP(hipMemcpyAsync(P.tplp.p, tp, sizeof(TplPtrs) * nsys, hipMemcpyHostToDevice, st));
     k_batch_units<<<ceil_div(nunits, 256), 256, 0, st>>>(nunits, nsys, J.sysd,
@@ -1070,7 +1055,7 @@ static tk_status build_finish(tk_ctx* ctx, BuildJob& J) {
     // rerun repeats neither the cell sort nor the neighbourhood sizes)
     const int first_occ = h[1], first_nbhd = h[5];
     const int64_t need = *(int64_t*)(h + 8);
-    if ((s = ensure(*J.wb, sizeof(uint32_t) * (size_t)need))) return s;
+    if ((s = ensure(ctx, *J.wb, sizeof(uint32_t) * (size_t)need))) return s;
     J.occ_cap = kMaxCellAtoms;
     ctx->nb_info_zero[J.job] = false;
     if ((s = enqueue_enumeration(ctx, J))) return s;
@@ -1090,20 +1075,23 @@ static tk_status build_finish(tk_ctx* ctx, BuildJob& J) {
   const int max_row = h[2];
   // dense codes at unit_off (the exclusive scan of the unit counts), and the
   // per-unit records of the pair kernels
-  if ((s = ensure(P.codes, sizeof(uint32_t) * (size_t)(list_pairs > 0 ? list_pairs : 1))) ||
-      (s = ensure(P.urec, sizeof(UnitRec) * (size_t)(nunits > 0 ? nunits : 1))))
+  if ((s = ensure(ctx, P.codes, sizeof(uint32_t) * (size_t)(list_pairs > 0 ? list_pairs : 1))) ||
+      (s = ensure(ctx, P.urec, sizeof(UnitRec) * (size_t)(nunits > 0 ? nunits : 1))))
     return s;
   const int32_t* cstart = (const int32_t*)P.cell_start.p;
+  if (J.row_ptr && list_pairs > J.cap) return TK_E_CAPACITY;
+  const int occ = h[1] > 0 ? h[1] : 1;
   if (n > 0) {
+    // the dense codes, the unit records and (when asked for) the CSR entries
     ProfScope ps(ctx, st, "nblist_compact");
-    k_compact<<<nunits, 256, 0, st>>>((const int64_t*)J.woff, (const uint32_t*)J.wb->p,
-                                     (const int64_t*)P.unit_off.p, (const int32_t*)J.regcnt,
-                                     (const int2*)J.nfilt, J.plan_waves, (uint32_t*)P.codes.p,
-                                     J.units, cstart, (const int32_t*)P.unit_cnt.p, J.cell_sys,
-                                     (UnitRec*)P.urec.p);
+    CsrOut csr{(const int32_t*)P.perm.p, (const int32_t*)P.slots.p, J.rp,
+               J.row_ptr && list_pairs > 0 ? J.col : nullptr, J.pstride, occ};
+    k_compact<<<nunits, 256, sizeof(int) * 4 * (size_t)occ, st>>>(
+        (const int64_t*)J.woff, (const uint32_t*)J.wb->p, (const int64_t*)P.unit_off.p,
+        (const int32_t*)J.regcnt, (const int2*)J.nfilt, J.plan_waves, (uint32_t*)P.codes.p,
+        J.units, cstart, (const int32_t*)P.unit_cnt.p, J.cell_sys, (UnitRec*)P.urec.p, csr);
   }
   if (J.row_ptr) {
-    if (list_pairs > J.cap) return TK_E_CAPACITY;
     const int nb = max_row < kBuckets ? max_row : kBuckets;
     const size_t lds1 = sizeof(int) * (2 * (size_t)max_row + 2 * (size_t)nb);
     if (lds1 > kMaxLds) return TK_E_CAPACITY;
@@ -1112,13 +1100,6 @@ static tk_status build_finish(tk_ctx* ctx, BuildJob& J) {
     const size_t lds = lds1 * rpb;
     if (lds > 65536 && (s = rowsort_attribute(lds))) return s;
     if (n > 0 && list_pairs > 0) {
-      {
-        ProfScope ps(ctx, st, "nblist_csr_fill");
-        const int occ = h[1] > 0 ? h[1] : 1;
-        k_csr_fill<<<nunits, 256, sizeof(int) * 6 * (size_t)occ, st>>>(
-            J.units, cstart, (int32_t*)P.perm.p, J.pstride, (int64_t*)P.unit_off.p,
-            (int32_t*)P.unit_cnt.p, (uint32_t*)P.codes.p, (int32_t*)P.slots.p, J.rp, J.col, occ);
-      }
       {
         ProfScope ps(ctx, st, "nblist_rowsort");
         k_rowsort<<<ceil_div(n, rpb), 64 * rpb, lds, st>>>(n, J.rp, J.col, max_row);

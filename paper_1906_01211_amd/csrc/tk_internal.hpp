@@ -174,6 +174,8 @@ struct tk_ctx {
   int pcg_hint[tk::kNumPlans][2] = {};         // last solve's iteration count per plan slot, precision
   bool nb_info_zero[4] = {};                   // per build of a group: its status words are zero
   void* noalloc_scratch = nullptr;             // device address of the fixed scratch array
+  size_t arena_budget = 0;                     // device bytes the context may hold (0: any)
+  size_t arena_bytes = 0;                      // device bytes it holds (grow-only buffers)
 };
 
 namespace tk {
@@ -187,7 +189,9 @@ tk_status hip_status(hipError_t e, const char* what);
 
 // Grow-only buffers: the first call with a given size allocates, later calls
 // reuse.  Never freed before tk_destroy.
-tk_status ensure(DevBuf& b, size_t bytes);
+// The context's budget, when set, bounds the sum of all its buffers
+// (TK_E_NOMEM beyond it, the old buffer kept).
+tk_status ensure(tk_ctx* ctx, DevBuf& b, size_t bytes);
 tk_status scratch(tk_ctx* ctx, const char* name, size_t bytes, void** out);
 // Pinned host memory that kernels write directly (zero-copy readback).
 tk_status pinned(tk_ctx* ctx, size_t bytes, void** out, void** dev = nullptr);

@@ -137,7 +137,10 @@ _SIGS = {
     "tk_server_submit": [_vp, C.POINTER(Request), C.POINTER(C.c_uint64)],
     "tk_server_poll": [_vp, C.c_uint64, C.POINTER(StepResult), C.POINTER(Timing), _vp, _vp, _vp],
     "tk_server_release": [_vp, C.c_uint64],
+    "tk_server_stats": [_vp, C.POINTER(ServerStats)],
     "tk_server_destroy": [_vp],
+    "tk_set_arena_budget": [_vp, C.c_size_t],
+    "tk_arena_bytes": [_vp],
     "tk_profile_enable": [_vp, C.c_int, C.c_char_p],
     "tk_profile_read": [_vp, _i32, C.c_char_p, _i32, C.POINTER(_i64), C.POINTER(_d)],
     "tk_profile_reset": [_vp],
@@ -162,6 +165,7 @@ def load(path: str = LIB_PATH):
                                                   "tk_server_destroy") else None
         L.tk_strerror.restype = C.c_char_p
         L.tk_server_footprint.restype = C.c_size_t
+        L.tk_arena_bytes.restype = C.c_size_t
         _lib = L
     return _lib
 
@@ -210,6 +214,14 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # -- device-memory budget ------------------------------------------------------
+    def set_arena_budget(self, nbytes):
+        """Bound the device bytes this context may hold (0: no bound)."""
+        _check(load().tk_set_arena_budget(self._h, int(nbytes)), "tk_set_arena_budget")
+
+    def arena_bytes(self):
+        return int(load().tk_arena_bytes(self._h))
 
     # -- kernel timing -----------------------------------------------------------
     def profile(self, on=True, only=None):

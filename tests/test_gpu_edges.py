@@ -112,3 +112,37 @@ def test_one_and_two_atoms(ctx, tk, n):
     ev, fv, _ = ctx.evdw(sysr, lst, tk.VDW_HAL, np.full(n, 3.4), np.full(n, 0.11), 7.0)
     evo, fvo, _ = O.evdw(xyz, box, molid, rp, cp, 0, np.full(n, 3.4), np.full(n, 0.11), 7.0)
     assert rel(float(ev), evo) < 1e-12 if n == 2 else float(ev) == 0.0
+
+
+def test_arena_budget_refuses_then_recovers(tk):
+    """A context with a device budget too small for a list build returns
+    TK_E_NOMEM without touching what it holds; with the budget raised the same
+    calls succeed and match the oracle.  A solve that needs buffers beyond a
+    budget pinned at the current holdings is refused the same way."""
+    c = tk.Context(0)
+    try:
+        w = synth.make("water216")
+        print("arena budget: water216", flush=True)
+        sysr = c.system(w.xyz, w.box, w.molid)
+        c.set_arena_budget(64 << 10)
+        with pytest.raises(tk.TkError) as ei:
+            c.nblist(sysr, 7.001, plan_slot=0)
+        assert ei.value.status == tk.E_NOMEM
+        assert c.arena_bytes() <= 64 << 10
+        c.set_arena_budget(0)
+        lst = c.nblist(sysr, 7.001, plan_slot=0)
+        rp, cp = O.nblist(w.xyz, w.box, 7.001)
+        assert np.array_equal(np_(lst.col), cp)
+        # nothing beyond what the context now holds: the solver's scratch is refused
+        c.set_arena_budget(c.arena_bytes())
+        with pytest.raises(tk.TkError) as ei:
+            c.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0)
+        assert ei.value.status == tk.E_NOMEM
+        c.set_arena_budget(0)
+        mu, info = c.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.0)
+        mo, io = O.polarize_pcg(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                S["beta"], 7.0)
+        assert info["converged"] == 1 and info["iters"] == io["iters"]
+        assert np.abs(np_(mu) - mo).max() <= 1e-10 * np.abs(mo).max()
+    finally:
+        c.close()
