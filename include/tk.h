@@ -247,6 +247,24 @@ tk_status tk_polarize_pcg(tk_ctx* ctx, void* stream, const tk_system* sys, const
                           int prec, const double* mu_guess, double* mu_out, tk_pcg_info* info);
 
 /*
+ * tk_empole_real and tk_polarize_pcg in one call: the permanent multipoles'
+ * energy, forces and virial (as tk_empole_real, same cutoff and Ewald
+ * parameter) and the induced dipoles (as tk_polarize_pcg).  The multipole
+ * terms and the right-hand side E_perm come from one pass over the list,
+ * since both walk the same pairs with the same screened radial functions
+ * (empole1 and efld0_direct2 of section "Hotspots").  energy: device [3]
+ * {total, non-excluded, exclusion correction}; force: device [n][3];
+ * virial: device [9]; written in stream order.  Other arguments, outputs,
+ * errors and synchronisation as tk_polarize_pcg; returns info->status.
+ */
+tk_status tk_empole_polarize(tk_ctx* ctx, void* stream, const tk_system* sys,
+                             const tk_nblist* list, const double* mpole, const double* polarity,
+                             const double* thole, double ewald_beta, double cutoff,
+                             double tol_debye, int32_t maxiter, int prec, const double* mu_guess,
+                             double* mu_out, tk_pcg_info* info, double* energy, double* force,
+                             double* virial);
+
+/*
  * Induced dipoles with the full Ewald operator: tk_polarize_pcg with the
  * reciprocal space included (the reciprocal polarization routine named in
  * section "Hotspots").  The operator is A = diag(1/alpha) - T - cI - R, R mu

@@ -1,6 +1,8 @@
 // One AMOEBA real-space step for a batch of independent systems: both
-// neighbour lists, permanent multipoles, induced dipoles and Halgren 14-7,
-// each as a single set of launches over all systems.
+// neighbour lists, Halgren 14-7, and the permanent multipoles with the
+// induced dipoles (one pass over the 7 A list gives the multipole terms and
+// the solver's right-hand side), each as a single set of launches over all
+// systems.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -22,18 +24,6 @@ tk_status check_params(const tk_step_params* p) {
     return TK_E_ARG;
   if (p->prec != TK_FP64 && p->prec != TK_MIXED) return TK_E_ARG;
   return TK_OK;
-}
-
-template <class R>
-tk_status run_mpole(tk_ctx* ctx, hipStream_t st, const Plan& P, const tk_batch* b,
-                    const double* mpole, const tk_step_params* p, double* force, double* energy,
-                    double* virial) {
-  EmpolePh<R> ph;
-  ph.xyz = b->xyz;
-  ph.mpole = mpole;
-  ph.molid = b->molid;
-  ph.g.set(b->box[0], p->rc_ewald, p->ewald_beta);
-  return run_term(ctx, st, P, ph, EpiForce{force}, energy, virial);
 }
 
 // rc0: the first system's vdW cutoff (the functor's own geometry, used as
@@ -106,10 +96,6 @@ extern "C" tk_status tk_batch_step(tk_ctx* ctx, void* stream, const tk_batch* b,
     if (unit_lds_bytes<EmpolePh<double>>(P7, 1) > kMaxLds ||
         unit_lds_bytes<VdwPh<double>>(P9, 1) > kMaxLds)
       return TK_E_CAPACITY;
-    s = p->prec == TK_FP64
-            ? run_mpole<double>(ctx, st, P7, b, mpole, p, force_mpole, e3, w3)
-            : run_mpole<float>(ctx, st, P7, b, mpole, p, force_mpole, e3, w3);
-    if (s) return s;
     s = p->prec == TK_FP64 ? run_vdw<double>(ctx, st, P9, b, vdw_rad, vdw_eps, p, r9[0],
                                              (const double*)cutd, force_vdw, e1, w1)
                            : run_vdw<float>(ctx, st, P9, b, vdw_rad, vdw_eps, p, r9[0],
@@ -120,9 +106,12 @@ extern "C" tk_status tk_batch_step(tk_ctx* ctx, void* stream, const tk_batch* b,
   }
   std::vector<tk_pcg_info> info(nsys);
   if (n > 0) {
+    // the multipole energies, forces and virial come out of the solver's
+    // right-hand-side pass (one pass over the 7 A list for both)
     if ((s = solve_dipoles(ctx, st, &P7, b->xyz, b->molid, mpole, polarity, thole, p->ewald_beta,
                            p->rc_ewald, p->tol_debye, p->maxiter, p->prec, mu_guess,
-                           (const int32_t*)gon, mu, info.data())))
+                           (const int32_t*)gon, mu, info.data(), 0, 0, 1, 0.0, e3, force_mpole,
+                           w3)))
       return s;
   } else {
     for (auto& i : info) i.converged = 1;

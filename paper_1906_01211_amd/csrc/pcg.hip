@@ -1122,7 +1122,8 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                         const double* thole, double ewald_beta, double cutoff, double tol_debye,
                         int32_t maxiter, int prec, const double* mu_guess,
                         const int32_t* guess_on, double* mu_out, tk_pcg_info* info,
-                        int pme_grid, int pme_order, int nv, double pscale) {
+                        int pme_grid, int pme_order, int nv, double pscale, double* mp_energy,
+                        double* mp_force, double* mp_virial) {
   const int nsys = P->nsys;
   if (pme_grid && (prec != TK_FP64 || nsys != 1 || !pme_args_ok(pme_grid, pme_order)))
     return TK_E_ARG;
@@ -1218,10 +1219,19 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   // right-hand side: permanent field (sorted order); the same pass caches
   // the mat-vec's radial factors
   const tk_system sys1{n, xyz, P->box, molid};
-  s = prec == TK_FP64 ? launch_efield<double>(ctx, st, *P, &sys1, mpole, polarity, thole,
-                                              ewald_beta, cutoff, S.b, 1, (double*)S.gc, S.gcs)
-                      : launch_efield<float>(ctx, st, *P, &sys1, mpole, polarity, thole,
-                                             ewald_beta, cutoff, S.b, 1, (float*)S.gc, S.gcs);
+  if (mp_energy)   // with the multipole energy, forces and virial from the same pass
+    s = prec == TK_FP64
+            ? launch_mpole_field<double>(ctx, st, *P, &sys1, mpole, polarity, thole, ewald_beta,
+                                         cutoff, mp_energy, mp_force, mp_virial, S.b,
+                                         (double*)S.gc, S.gcs)
+            : launch_mpole_field<float>(ctx, st, *P, &sys1, mpole, polarity, thole, ewald_beta,
+                                        cutoff, mp_energy, mp_force, mp_virial, S.b,
+                                        (float*)S.gc, S.gcs);
+  else
+    s = prec == TK_FP64 ? launch_efield<double>(ctx, st, *P, &sys1, mpole, polarity, thole,
+                                                ewald_beta, cutoff, S.b, 1, (double*)S.gc, S.gcs)
+                        : launch_efield<float>(ctx, st, *P, &sys1, mpole, polarity, thole,
+                                               ewald_beta, cutoff, S.b, 1, (float*)S.gc, S.gcs);
   if (s) return s;
   // the second right-hand side: same-molecule pairs scaled by pscale
   if (nv == 2 && (s = launch_efield<double>(ctx, st, *P, &sys1, mpole, polarity, thole, ewald_beta,
@@ -1341,6 +1351,38 @@ extern "C" tk_status tk_polarize_pcg(tk_ctx* ctx, void* stream, const tk_system*
   if ((s = solve_dipoles(ctx, (hipStream_t)stream, P, sys->xyz, sys->molid, mpole, polarity, thole,
                          ewald_beta, cutoff, tol_debye, maxiter, prec, mu_guess, nullptr, mu_out,
                          info, 0, 0)))
+    return s;
+  return info->status;
+}
+
+extern "C" tk_status tk_empole_polarize(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                        const tk_nblist* list, const double* mpole,
+                                        const double* polarity, const double* thole,
+                                        double ewald_beta, double cutoff, double tol_debye,
+                                        int32_t maxiter, int prec, const double* mu_guess,
+                                        double* mu_out, tk_pcg_info* info, double* energy,
+                                        double* force, double* virial) {
+  if (!ctx || !info) return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (prec != TK_FP64 && prec != TK_MIXED) return TK_E_ARG;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !(tol_debye >= 0.0) || maxiter < 0 ||
+      !energy || !virial)
+    return TK_E_ARG;
+  const Plan* P;
+  if ((s = get_plan(ctx, sys, list, cutoff, &P))) return s;
+  *info = tk_pcg_info{};
+  hipStream_t st = (hipStream_t)stream;
+  if (sys->n == 0) {
+    info->converged = 1;
+    TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
+    TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
+    return TK_OK;
+  }
+  if (!mpole || !polarity || !thole || !mu_out || !force) return TK_E_ARG;
+  if ((s = solve_dipoles(ctx, st, P, sys->xyz, sys->molid, mpole, polarity, thole, ewald_beta,
+                         cutoff, tol_debye, maxiter, prec, mu_guess, nullptr, mu_out, info, 0, 0,
+                         1, 0.0, energy, force, virial)))
     return s;
   return info->status;
 }

@@ -9,7 +9,8 @@
 // screened-minus-bare differences cancel badly), pairs closer than 2 A are
 // evaluated entirely in FP64 (their large forces would carry FP32 rounding of
 // the same relative size), and every accumulation (LDS atomics, energies,
-// virial) is FP64.
+// virial) is FP64.  The van der Waals and point-charge terms are evaluated in
+// FP64 in both forms (see VdwPh and ChargePh).
 #pragma once
 
 #include <type_traits>
@@ -273,23 +274,14 @@ struct ChargePh {
     const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
     if (!(r2 <= g.rc2)) return;
     const bool excl = LH[4 * cap + a] == LK[4 * cap + b];
-    double g0, g1;
-    if (std::is_same<R, float>::value && !excl && !(r2 < kMixedCloseR2)) {
-      R B[2], Rb[2];
-      radial_pair<R, 1>(g, r2, false, B, Rb);
-      g1 = (double)B[1];
-      // the energy of a point-charge system is a large cancelling sum: its
-      // screened pair term is evaluated in FP64 even in the mixed form
-      double B0d[1], R0d[1];
-      const double ri = rsqrt_r(r2);
-      radial<double, 0>(g, r2 * ri, ri, B0d, R0d, r2);
-      g0 = B0d[0];
-    } else {   // FP64 form; in the mixed form also excluded and close pairs
-      double B[2], Rb[2];
-      radial_pair<double, 1>(g, r2, excl, B, Rb);
-      g0 = excl ? B[0] - Rb[0] : B[0];
-      g1 = excl ? B[1] - Rb[1] : B[1];
-    }
+    // Both forms evaluate the pair once in FP64: the energy of a point-charge
+    // system is a large cancelling sum that needs its screened term g0 in
+    // FP64, and the FP64 erfc and exponential that give g0 give g1 too, so an
+    // FP32 force on top would cost more than it saves.
+    double B[2], Rb[2];
+    radial_pair<double, 1>(g, r2, excl, B, Rb);
+    const double g0 = excl ? B[0] - Rb[0] : B[0];
+    const double g1 = excl ? B[1] - Rb[1] : B[1];
     const double qq = kCoulomb * LH[3 * cap + a] * LK[3 * cap + b];
     const double en = qq * g0;
     const double f = -qq * g1;
@@ -449,6 +441,177 @@ struct EfieldPh {
     for (int c = 0; c < 3; ++c) {
       lds_add(&AH[c * cap + a], fi[c]);
       lds_add(&AK[c * cap + b], fj[c]);
+    }
+  }
+};
+
+// Permanent multipoles and their field in one pass over the list: the
+// multipole energy, forces and virial (as EmpolePh) and the Thole-damped
+// permanent field at both atoms (as EfieldPh), the two routines of the Rel
+// profile that walk the same pairs with the same radial functions.  The pair
+// vector, B_0..B_5, the quadrupole contractions Theta d and d.Theta.d and the
+// dipole projections are formed once for both; the solver's mutual-field
+// factors are cached per pair code (gc, as EfieldPh).  Accumulators: force
+// (3), field (3).
+// Fields: x y z | q mu(3) Theta(6) | molid | isa | thole
+template <class R>
+struct MpoleFieldPh {
+  static constexpr int NF = 16, NA = 6, NS = 11;
+  static constexpr const char* kName = "mpole_field";
+  static constexpr int kWaves = 2;   // waves per unit (pairs.hpp launch_units)
+  static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
+  __device__ bool skip() const { return false; }
+  __device__ void prologue(int tid, int nt) const { erfcx_stage<R>(tid, nt); }
+  const double* xyz;
+  const double* mpole;
+  const int32_t* molid;
+  const double* polarity;
+  const double* thole;
+  Geom g;
+  __device__ void set_sys(const SysDev& d, int) {
+    g.box = d.box;
+    g.inv_box = d.inv_box;
+  }
+  static constexpr int NG = 16;   // fields gathered once per call (sorted SoA)
+  const double* sorted = nullptr;
+  long gstride = 0;
+  __device__ void stage_dyn(double*, int, int, int) const {}
+  __device__ void gather(int i, double* g) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] = xyz[3 * i + c];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) g[3 + k] = mpole[10 * i + k];
+    g[13] = (double)molid[i];
+    g[14] = inv_sqrt_alpha(polarity[i]);
+    g[15] = thole[i];
+  }
+  using GC = R;
+  GC* gc = nullptr;   // [2][gcs]: g1 | g2 per pair code
+  long gcs = 0;
+  // de: dE/dr (the force on K's atom is -de), en: pair energy, fi/fj: the
+  // permanent field at H's and K's atom, all in type T
+  template <class T>
+  __device__ __forceinline__ void eval(const double* LH, const double* LK, int cap, int a, int b,
+                                       const double* dd, double r2, bool excl, double* de,
+                                       double& en, double* fi, double* fj, long p) const {
+    T B[6], Rb[6];
+    radial_pair<T, 5>(g, r2, excl, B, Rb);
+    T gg[6];
+#pragma unroll
+    for (int n = 0; n < 6; ++n) gg[n] = excl ? B[n] - Rb[n] : B[n];
+    T l3, l5, l7;
+    const T r = T(r2) * rsqrt_r(T(r2));
+    thole_damp<T>(r, T(LH[14 * cap + a]), T(LK[14 * cap + b]), T(LH[15 * cap + a]),
+                  T(LK[15 * cap + b]), l3, l5, l7);
+    // field factors: bare Coulomb removed within a molecule (the permanent
+    // field), Thole-damped otherwise; the mutual factors (damped for every
+    // pair) go to the cache
+    T g1, g2, g3;
+    if (excl) {
+      g1 = B[1] - Rb[1];
+      g2 = B[2] - Rb[2];
+      g3 = B[3] - Rb[3];
+      if (gc) {
+        if (std::is_same<T, float>::value) {
+          // B carries the FP64 difference B - R; re-add the damped bare part in FP64
+          const double ri = rsqrt_r(r2);
+          const double R1 = ri * ri * ri, R2 = 3.0 * R1 * ri * ri;
+          gc[p] = GC((double)B[1] + (double)l3 * R1);
+          gc[gcs + p] = GC((double)B[2] + (double)l5 * R2);
+        } else {
+          gc[p] = GC(B[1] - (T(1) - l3) * Rb[1]);
+          gc[gcs + p] = GC(B[2] - (T(1) - l5) * Rb[2]);
+        }
+      }
+    } else {
+      g1 = B[1] - (T(1) - l3) * Rb[1];
+      g2 = B[2] - (T(1) - l5) * Rb[2];
+      g3 = B[3] - (T(1) - l7) * Rb[3];
+      if (gc) {
+        gc[p] = GC(g1);
+        gc[gcs + p] = GC(g2);
+      }
+    }
+    const T d[3] = {T(dd[0]), T(dd[1]), T(dd[2])};
+    const T qi = T(LH[3 * cap + a]), qj = T(LK[3 * cap + b]);
+    const T ui[3] = {T(LH[4 * cap + a]), T(LH[5 * cap + a]), T(LH[6 * cap + a])};
+    const T uj[3] = {T(LK[4 * cap + b]), T(LK[5 * cap + b]), T(LK[6 * cap + b])};
+    const T ti[6] = {T(LH[7 * cap + a]), T(LH[8 * cap + a]), T(LH[9 * cap + a]),
+                     T(LH[10 * cap + a]), T(LH[11 * cap + a]), T(LH[12 * cap + a])};
+    const T tj[6] = {T(LK[7 * cap + b]), T(LK[8 * cap + b]), T(LK[9 * cap + b]),
+                     T(LK[10 * cap + b]), T(LK[11 * cap + b]), T(LK[12 * cap + b])};
+    auto tmul = [](const T* t, const T* x, T* y) {
+      y[0] = t[0] * x[0] + t[1] * x[1] + t[2] * x[2];
+      y[1] = t[1] * x[0] + t[3] * x[1] + t[4] * x[2];
+      y[2] = t[2] * x[0] + t[4] * x[1] + t[5] * x[2];
+    };
+    auto dot = [](const T* x, const T* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+    T vi[3], vj[3];
+    tmul(ti, d, vi);
+    tmul(tj, d, vj);
+    const T di = dot(ui, d), dj = dot(uj, d), Qi = dot(d, vi), Qj = dot(d, vj);
+    // multipole energy and its gradient
+    const T tt = ti[0] * tj[0] + ti[3] * tj[3] + ti[5] * tj[5] +
+                 T(2) * (ti[1] * tj[1] + ti[2] * tj[2] + ti[4] * tj[4]);
+    const T c0 = qi * qj;
+    const T c1 = qj * di - qi * dj + dot(ui, uj);
+    const T c2 = qi * Qj + qj * Qi - di * dj + T(2) * (dot(uj, vi) - dot(ui, vj) + tt);
+    const T c3 = di * Qj - dj * Qi - T(4) * dot(vi, vj);
+    const T c4 = Qi * Qj;
+    T tiuj[3], tjui[3], tivj[3], tjvi[3];
+    tmul(ti, uj, tiuj);
+    tmul(tj, ui, tjui);
+    tmul(ti, vj, tivj);
+    tmul(tj, vi, tjvi);
+    const T e = c0 * gg[0] + c1 * gg[1] + c2 * gg[2] + c3 * gg[3] + c4 * gg[4];
+    const T sr = c0 * gg[1] + c1 * gg[2] + c2 * gg[3] + c3 * gg[4] + c4 * gg[5];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T dc1 = qj * ui[c] - qi * uj[c];
+      const T dc2 = T(2) * (qi * vj[c] + qj * vi[c]) - dj * ui[c] - di * uj[c] +
+                    T(2) * (tiuj[c] - tjui[c]);
+      const T dc3 = Qj * ui[c] + T(2) * di * vj[c] - Qi * uj[c] - T(2) * dj * vi[c] -
+                    T(4) * (tivj[c] + tjvi[c]);
+      const T dc4 = T(2) * (Qj * vi[c] + Qi * vj[c]);
+      de[c] = kCoulomb * (double)(dc1 * gg[1] + dc2 * gg[2] + dc3 * gg[3] + dc4 * gg[4] - sr * d[c]);
+    }
+    en = kCoulomb * (double)e;
+    // permanent field: at i from j: d(-qj g1 + dj g2 - Qj g3) - uj g1 + 2 vj g2;
+    // at j from i: d(qi g1 + di g2 + Qi g3) - ui g1 - 2 vi g2
+    const T si = -qj * g1 + dj * g2 - Qj * g3;
+    const T sj = qi * g1 + di * g2 + Qi * g3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      fi[c] = (double)(d[c] * si - uj[c] * g1 + T(2) * vj[c] * g2);
+      fj[c] = (double)(d[c] * sj - ui[c] * g1 - T(2) * vi[c] * g2);
+    }
+  }
+  __device__ void pair(const double* LH, const double* LK, int cap, int a, int b, double* AH,
+                       double* AK, double* sc, long p) const {
+    double dd[3];
+    const double r2 = image3(LH, LK, cap, a, b, g.box, g.inv_box, dd);
+    if (!(r2 <= g.rc2)) {
+      if (gc) {
+        gc[p] = GC(0);
+        gc[gcs + p] = GC(0);
+      }
+      return;
+    }
+    const bool excl = LH[13 * cap + a] == LK[13 * cap + b];
+    double de[3], en, fi[3], fj[3];
+    if (std::is_same<R, float>::value && r2 < kMixedCloseR2)
+      eval<double>(LH, LK, cap, a, b, dd, r2, excl, de, en, fi, fj, p);
+    else
+      eval<R>(LH, LK, cap, a, b, dd, r2, excl, de, en, fi, fj, p);
+    sc[excl ? 1 : 0] += en;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lds_add(&AH[c * cap + a], de[c]);
+      lds_add(&AK[c * cap + b], -de[c]);
+      lds_add(&AH[(3 + c) * cap + a], fi[c]);
+      lds_add(&AK[(3 + c) * cap + b], fj[c]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) sc[2 + 3 * c + q] += dd[c] * de[q];
     }
   }
 };
@@ -656,25 +819,14 @@ struct VdwPh {
     double dd[3];
     const double r2 = image3(LH, LK, cap, a, b, box, inv_box, dd);
     if (!(r2 <= rc2)) return;
-    double en, f;
-    if (std::is_same<R, float>::value && !(r2 < kMixedCloseR2)) {
-      R e, dedr, ir;
-      eval<R>(r2, R(LH[3 * cap + a]), R(LK[3 * cap + b]), R(LH[4 * cap + a]), R(LK[4 * cap + b]),
-              e, dedr, ir);
-      f = (double)dedr * (double)ir;
-      // the vdW energy is a sum of cancelling attractive and repulsive terms:
-      // in the mixed form it is evaluated in FP64 (forces stay FP32)
-      double ed, dd64, ird;
-      eval<double>(r2, LH[3 * cap + a], LK[3 * cap + b], LH[4 * cap + a], LK[4 * cap + b], ed, dd64,
-                   ird);
-      en = ed;
-    } else {   // FP64 form; in the mixed form also close pairs
-      double e, dedr, ir;
-      eval<double>(r2, LH[3 * cap + a], LK[3 * cap + b], LH[4 * cap + a], LK[4 * cap + b], e, dedr,
-                   ir);
-      en = e;
-      f = dedr * ir;
-    }
+    // Both forms evaluate the pair once in FP64.  The vdW energy is a sum of
+    // cancelling attractive and repulsive terms that needs FP64, and without
+    // packed FP32 instructions FP32 arithmetic issues at the FP64 rate, so one
+    // FP64 evaluation costs less than an FP32 force plus an FP64 energy.
+    double e, dedr, ir;
+    eval<double>(r2, LH[3 * cap + a], LK[3 * cap + b], LH[4 * cap + a], LK[4 * cap + b], e, dedr,
+                 ir);
+    const double en = e, f = dedr * ir;
     sc[0] += en;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1316,6 +1468,20 @@ struct EpiPermField {   // permanent field + Ewald self field c * mu_perm
   }
 };
 
+struct EpiForceField {   // force (caller order) and permanent field + self field (sorted order)
+  double* force;
+  double* field;
+  const double* mpole;
+  double cself;
+  __device__ void operator()(int s, int i, const double* a) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      force[3 * i + c] = a[c];
+      field[3 * s + c] = a[3 + c] + cself * mpole[10 * i + 1 + c];
+    }
+  }
+};
+
 struct EpiMutual {   // mutual field (T + cI) mu, or A mu = mu/alpha - field
   double* out;
   const double* mu;
@@ -1417,6 +1583,28 @@ inline tk_status launch_efield(tk_ctx* ctx, hipStream_t st, const Plan& P, const
   ph.g.set(sys->box, cutoff, beta);
   EpiPermField e2{out, mpole, ph.g.cself, sorted_out};
   return run_term(ctx, st, P, ph, e2, nullptr, nullptr);
+}
+
+// Multipole energy {total, non-excluded, exclusion correction}, forces and
+// virial (device, caller order) and the permanent field (sorted order) in one
+// pass; the solver's factors into gc.
+template <class R>
+inline tk_status launch_mpole_field(tk_ctx* ctx, hipStream_t st, const Plan& P,
+                                    const tk_system* sys, const double* mpole,
+                                    const double* polarity, const double* thole, double beta,
+                                    double cutoff, double* energy, double* force, double* virial,
+                                    double* field_sorted, R* gc, long gcs) {
+  MpoleFieldPh<R> ph;
+  ph.gc = gc;
+  ph.gcs = gcs;
+  ph.xyz = sys->xyz;
+  ph.mpole = mpole;
+  ph.molid = sys->molid;
+  ph.polarity = polarity;
+  ph.thole = thole;
+  ph.g.set(sys->box, cutoff, beta);
+  EpiForceField epi{force, field_sorted, mpole, ph.g.cself};
+  return run_term(ctx, st, P, ph, epi, energy, virial);
 }
 
 }  // namespace tk

@@ -271,12 +271,16 @@ tk_status pme_mpole_pair(tk_ctx* ctx, hipStream_t st, const tk_system* sys, cons
 tk_status pme_perm_field_add(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
                              const double* mpole, double beta, int grid, int order,
                              const int32_t* perm, double* b_sorted);
+// With mp_energy set, the permanent multipoles' energy [3], forces (caller
+// order) and virial [9] come out of the same pass as the right-hand side.
 tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double* xyz,
                         const int32_t* molid, const double* mpole, const double* polarity,
                         const double* thole, double ewald_beta, double cutoff, double tol_debye,
                         int32_t maxiter, int prec, const double* mu_guess,
                         const int32_t* guess_on, double* mu_out, tk_pcg_info* info,
-                        int pme_grid = 0, int pme_order = 0, int nv = 1, double pscale = 0.0);
+                        int pme_grid = 0, int pme_order = 0, int nv = 1, double pscale = 0.0,
+                        double* mp_energy = nullptr, double* mp_force = nullptr,
+                        double* mp_virial = nullptr);
 
 // The allocation-free entry point's fixed scratch (noalloc.hip): resolves
 // the device address of this device's copy of the array (once per device;

@@ -108,6 +108,8 @@ _SIGS = {
     "tk_epolar_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
                        _d, C.c_int, _vp, _vp, _vp],
     "tk_pme_mpole": [_vp, _vp, C.POINTER(System), _vp, _d, _i32, _i32, _vp, _vp, _vp],
+    "tk_empole_polarize": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d,
+                           _d, _d, _i32, C.c_int, _vp, _vp, C.POINTER(PcgInfo), _vp, _vp, _vp],
     "tk_polarize_pcg_ewald": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d,
                               _d, _i32, _i32, _d, _i32, _vp, _vp, C.POINTER(PcgInfo)],
     "tk_polarize_pcg2": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d,
@@ -368,6 +370,27 @@ class Context:
         if st not in (OK, E_NOCONV, E_BREAKDOWN):
             _check(st, "tk_polarize_pcg")
         return out, {k: getattr(info, k) for k, _ in PcgInfo._fields_}
+
+    def empole_polarize(self, sysref, lst, mpole, polarity, thole, beta, cutoff, tol_debye=1e-5,
+                        maxiter=100, prec=FP64, mu_guess=None):
+        """tk_empole_polarize: (energy[3], force, virial), (mu, info)."""
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device,
+                                               (sysref.n, 3), "mu_guess")
+        out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        e = torch.empty(3, dtype=torch.float64, device=self.device)
+        f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        v = torch.empty(9, dtype=torch.float64, device=self.device)
+        info = PcgInfo()
+        st = load().tk_empole_polarize(self._h, _stream(self.device), C.byref(sysref.c),
+                                       C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), beta, cutoff,
+                                       tol_debye, int(maxiter), prec, _ptr(g), _ptr(out),
+                                       C.byref(info), _ptr(e), _ptr(f), _ptr(v))
+        if st not in (OK, E_NOCONV, E_BREAKDOWN):
+            _check(st, "tk_empole_polarize")
+        return (e, f, v), (out, {k: getattr(info, k) for k, _ in PcgInfo._fields_})
 
     def polarize_pcg_ewald(self, sysref, lst, mpole, polarity, thole, beta, cutoff, grid,
                            order=5, tol_debye=1e-5, maxiter=100, mu_guess=None):

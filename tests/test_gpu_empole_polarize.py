@@ -1,0 +1,116 @@
+"""tk_empole_polarize: the permanent multipoles' energy, forces and virial and
+the induced dipoles from one call (the multipole terms and the permanent field
+in one pass over the list), against the FP64 oracle's empole_real and
+polarize_pcg on the same inputs.
+
+FP64: energies relative 1e-10, forces max |diff| <= 1e-8 of the oracle's RMS,
+dipoles relative 1e-10 (same iteration count).  Mixed: energy 1e-6 relative,
+force RMS error <= 1e-4 kcal/mol/A, dipoles within 1e-5 D RMS of a tightly
+converged FP64 solve."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_01211_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+C, DEBYE = O.constants()
+S = synth.AMOEBA_SETTINGS
+_cache = {}
+
+
+@pytest.fixture(scope="module")
+def tk():
+    import torch
+    from paper_1906_01211_amd import tk as _tk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _tk.load()
+    return _tk
+
+
+@pytest.fixture(scope="module")
+def ctx(tk):
+    c = tk.Context(0)
+    yield c
+    c.close()
+
+
+def setup(ctx, name):
+    w = _cache.setdefault(name, synth.make(name))
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    lst = ctx.nblist(sysr, S["rc_ewald"] + S["skin"], plan_slot=2)
+    key = (name, "list")
+    if key not in _cache:
+        rp, cp = O.nblist(w.xyz, w.box, S["rc_ewald"] + S["skin"])
+        em = O.empole_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, S["beta"], S["rc_ewald"])
+        mo, io = O.polarize_pcg(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                                S["beta"], S["rc_ewald"], tol_debye=S["tol_debye"])
+        _cache[key] = (rp, cp, em, mo, io)
+    return (w, sysr, lst) + _cache[key]
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+def test_empole_polarize_fp64(ctx, tk, name):
+    print(f"empole_polarize fp64 {name}", flush=True)
+    w, sysr, lst, rp, cp, (eo, fo, vo), mo, io = setup(ctx, name)
+    (e, f, v), (mu, info) = ctx.empole_polarize(sysr, lst, w.mpole, w.polarity, w.thole,
+                                                S["beta"], S["rc_ewald"],
+                                                tol_debye=S["tol_debye"])
+    e = e.cpu().numpy()
+    for k in range(3):
+        assert abs(e[k] - eo[k]) <= 1e-10 * abs(eo[k]), (k, e[k], eo[k])
+    f = f.cpu().numpy()
+    assert np.abs(f - fo).max() <= 1e-8 * np.sqrt(np.mean(fo ** 2))
+    assert np.abs(v.cpu().numpy().reshape(np.shape(vo)) - vo).max() <= 1e-10 * np.abs(vo).max()
+    assert info["converged"] == io["converged"] == 1 and info["iters"] == io["iters"]
+    assert np.abs(mu.cpu().numpy() - mo).max() <= 1e-10 * np.abs(mo).max()
+    assert abs(info["epol"] - io["epol"]) <= 1e-10 * abs(io["epol"])
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+def test_empole_polarize_mixed(ctx, tk, name):
+    print(f"empole_polarize mixed {name}", flush=True)
+    w, sysr, lst, rp, cp, (eo, fo, vo), mo, io = setup(ctx, name)
+    (e, f, v), (mu, info) = ctx.empole_polarize(sysr, lst, w.mpole, w.polarity, w.thole,
+                                                S["beta"], S["rc_ewald"],
+                                                tol_debye=S["tol_debye"], prec=tk.MIXED)
+    e = e.cpu().numpy()
+    assert abs(e[0] - eo[0]) <= 1e-6 * abs(eo[0])
+    f = f.cpu().numpy()
+    assert np.sqrt(np.mean(np.sum((f - fo) ** 2, axis=1))) <= 1e-4
+    tight, _ = O.polarize_pcg(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole,
+                              S["beta"], S["rc_ewald"], tol_debye=1e-10, maxiter=200)
+    assert info["converged"] == 1 and info["rms_true_debye"] <= S["tol_debye"]
+    err = DEBYE * np.sqrt(np.mean(np.sum((mu.cpu().numpy() - tight) ** 2, axis=1)))
+    assert err <= 1e-5, err
+
+
+def test_empole_polarize_matches_the_two_calls(ctx, tk):
+    """The fused call against tk_empole_real followed by tk_polarize_pcg on the
+    GPU: the same numbers to the FP64 bar (different summation order only)."""
+    w, sysr, lst, *_ = setup(ctx, "water216")
+    (e, f, v), (mu, info) = ctx.empole_polarize(sysr, lst, w.mpole, w.polarity, w.thole,
+                                                S["beta"], S["rc_ewald"],
+                                                tol_debye=S["tol_debye"])
+    e2, f2, v2 = ctx.empole_real(sysr, lst, w.mpole, S["beta"], S["rc_ewald"])
+    mu2, info2 = ctx.polarize_pcg(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"],
+                                  S["rc_ewald"], tol_debye=S["tol_debye"])
+    assert np.allclose(e.cpu().numpy(), e2.cpu().numpy(), rtol=1e-12, atol=0)
+    assert np.abs(f.cpu().numpy() - f2.cpu().numpy()).max() <= 1e-10 * f2.abs().max().item()
+    assert info["iters"] == info2["iters"]
+    assert np.abs(mu.cpu().numpy() - mu2.cpu().numpy()).max() <= 1e-12 * mu2.abs().max().item()
+
+
+def test_empole_polarize_empty_and_errors(ctx, tk):
+    import torch
+    sysr = ctx.system(np.zeros((0, 3)), 20.0, np.zeros(0, dtype=np.int32))
+    lst = ctx.nblist(sysr, 7.001, plan_slot=2)
+    (e, f, v), (mu, info) = ctx.empole_polarize(sysr, lst, np.zeros((0, 10)), np.zeros(0),
+                                                np.zeros(0), S["beta"], 7.0)
+    assert info["converged"] == 1
+    assert np.all(e.cpu().numpy() == 0.0) and np.all(v.cpu().numpy() == 0.0)
+    w, sysr, lst, *_ = setup(ctx, "water216")
+    with pytest.raises(tk.TkError):
+        ctx.empole_polarize(sysr, lst, w.mpole, w.polarity, w.thole, S["beta"], 7.5)  # > list
