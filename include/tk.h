@@ -585,14 +585,21 @@ tk_status tk_batch_step(tk_ctx* ctx, void* stream, const tk_batch* batch,
                         double* force_vdw, tk_step_result* results);
 
 /*
- * Serving runtime: continuous batching of step requests.  A server owns its
- * own context and HIP stream on `device` and a worker thread.  Requests are
- * queued by tk_server_submit (host arrays, copied at once); the worker forms
- * each batch from the queue in arrival order while the estimated device
- * footprint of the batch stays within hbm_budget bytes (and at most
- * max_batch systems), runs one tk_batch_step on it, and publishes every
- * result; requests that arrive meanwhile join the next batch.  A request
- * whose own footprint exceeds the budget is rejected (TK_E_CAPACITY).
+ * Serving runtime: continuous batching of step requests.  A server runs
+ * three lanes on `device`, each a host thread with its own context, HIP
+ * stream and pinned staging.  Requests are queued by tk_server_submit (host
+ * arrays, copied at once).  An idle lane takes the requests queued at that
+ * moment, in arrival order (at most max_batch), into a batch and runs one
+ * tk_batch_step on its stream; a request arriving while batches are on the
+ * GPU is taken by the next idle lane at once, and its work overlaps theirs.
+ * Admission is by measured device memory: a batch joins a lane while the
+ * lane's projected holdings (the measured bytes per atom of earlier
+ * batches; tk_server_footprint before the first) plus the other lanes'
+ * holdings stay within hbm_budget, and the lane's context is bounded by the
+ * same limit (a batch that would overrun it runs its first request alone
+ * and returns the rest to the queue).  The lanes' device bytes never exceed
+ * the budget.  A system's results are the same whatever batch it runs in.
+ * A request that alone exceeds the budget is rejected (TK_E_CAPACITY).
  * Sessions: a request with a nonzero session id starts its dipole solve from
  * the dipoles of the previous completed request of the same session when
  * the atom count matches (resident guesses; otherwise from alpha * E_perm).
@@ -617,11 +624,21 @@ typedef struct {             /* host timestamps (ns, monotonic clock) and the ba
   int64_t t_submit, t_start, t_done;
   int32_t batch_size;        /* systems in that batch */
   int32_t batch_index;       /* sequence number of the batch */
+  int32_t lane;              /* the lane that ran it */
 } tk_timing;
+
+typedef struct {
+  int32_t lanes, batches;      /* concurrent lanes; batches run so far */
+  size_t budget;               /* hbm_budget */
+  size_t peak_device_bytes;    /* largest measured sum of the lanes' device holdings */
+  size_t device_bytes;         /* their sum now */
+  double bytes_per_atom;       /* measured admission rate (0 before the first batch) */
+} tk_server_usage;
 
 tk_status tk_server_create(int device, const tk_step_params* params, size_t hbm_budget,
                            int32_t max_batch, tk_server** out);
-/* Estimated device bytes of one request of n atoms (the admission measure). */
+/* Estimated device bytes of one request of n atoms (the admission measure
+ * before the server has measured a batch). */
 size_t tk_server_footprint(int32_t n);
 tk_status tk_server_submit(tk_server* srv, const tk_request* req, uint64_t* id);
 /*

@@ -1,12 +1,34 @@
 // Serving runtime: continuous batching of AMOEBA step requests on one GPU.
 //
-// A worker thread owns a context and a stream.  It takes requests from the
-// queue in arrival order into a batch while the batch's estimated device
-// footprint stays within the budget, runs one multi-system step for the whole
-// batch (tk_batch_step), publishes the results, and starts the next batch
-// with whatever has arrived meanwhile.  Host staging is pinned and grow-only.
+// The server runs kLanes lanes.  A lane is a host thread with its own
+// context (plans and scratch), HIP stream and pinned staging.  An idle lane
+// takes the requests queued at that moment, in arrival order, into a batch
+// and runs one multi-system step for the whole batch (tk_batch_step) on its
+// stream; a request that arrives while batches are on the GPU is taken at
+// once by the next idle lane, so its work overlaps theirs on the device (the
+// solver's host synchronisations of one lane leave the GPU to the others).
+// A system's results do not depend on the batch it runs in (every per-system
+// sum has a fixed order), so a request returns the same numbers alone or in
+// the mix.
+//
+// Admission is by measured device memory.  Every lane reports what its
+// context and staging hold after each batch (grow-only buffers: what its
+// largest batch needed).  A batch is admitted to a lane when its
+// reservation, the lane's projected holdings, plus what the other lanes hold
+// or have reserved stays within the budget.  The projection uses the
+// measured bytes per atom (the largest rate any lane has reported on a batch
+// of 4,096 atoms or more, a fixed allowance set apart; a fixed per-atom
+// estimate before that).  The lane's context is bounded by its reservation
+// (tk_set_arena_budget): a batch that would need more fails with TK_E_NOMEM
+// before it launches, and the lane runs its first request alone and returns
+// the others to the head of the queue; a request refused alone goes back to
+// the head of the queue, known to need half as much again, and fails only
+// when refused with the whole budget to itself.  An idle lane whose holdings
+// keep the head request out frees its context (the others keep theirs).  The
+// lanes' device bytes never exceed the budget.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -20,6 +42,8 @@
 #include "tk.h"
 
 namespace {
+
+constexpr int kLanes = 3;
 
 int64_t now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -35,6 +59,7 @@ struct Req {
   std::vector<double> xyz, mpole, pol, thole, rad, eps;
   std::vector<int32_t> molid;
   size_t footprint = 0;
+  size_t need = 0;   // device bytes it is known to need (0: not known)
   tk_timing timing{};
   bool done = false;
   tk_status status = TK_OK;
@@ -73,17 +98,50 @@ struct Dev {
     bytes = want;
     return TK_OK;
   }
-  ~Dev() {
+  void release() {
     if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~Dev() { release(); }
+};
+
+// Device bytes of a batch's staging (inputs 20 doubles and a molecule id per
+// atom, outputs 9 doubles per atom).
+size_t staging_bytes(size_t n) {
+  return sizeof(double) * (20 * n + 1) + sizeof(int32_t) * (n + 1) + sizeof(double) * (9 * n + 1);
+}
+
+// Device bytes of a lane's staging once it has run a batch of n atoms (its
+// buffers only grow: each keeps the larger of its size and what n needs).
+struct Lane;
+size_t staging_after(const Lane& L, size_t n);
+
+struct Lane {
+  int index = 0;
+  tk_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  Pinned h_in, h_mol, h_out;
+  Dev d_in, d_mol, d_out;
+  size_t held = 0;       // device bytes the lane holds (context + staging), as last measured
+  size_t reserved = 0;   // projected bytes of its running batch (>= held while it runs)
+  int64_t max_atoms = 0; // atoms of the largest batch it has run
+  std::thread th;
+  size_t device_bytes() const {
+    return (ctx ? tk_arena_bytes(ctx) : 0) + d_in.bytes + d_mol.bytes + d_out.bytes;
   }
 };
+
+size_t staging_after(const Lane& L, size_t n) {
+  return std::max(L.d_in.bytes, sizeof(double) * (20 * n + 1)) +
+         std::max(L.d_mol.bytes, sizeof(int32_t) * (n + 1)) +
+         std::max(L.d_out.bytes, sizeof(double) * (9 * n + 1));
+}
 
 }  // namespace
 
 struct tk_server {
   int device = 0;
-  tk_ctx* ctx = nullptr;
-  hipStream_t stream = nullptr;
   tk_step_params prm{};
   size_t budget = 0;
   int32_t max_batch = 0;
@@ -94,30 +152,54 @@ struct tk_server {
   std::unordered_map<uint64_t, std::vector<double>> session_mu;   // last dipoles per session
   uint64_t next_id = 1;
   int32_t batches = 0;
-  int inflight = 0;
+  double bytes_per_atom = 0.0;   // measured (0: none yet)
+  size_t peak = 0;               // largest sum of the lanes' measured holdings
   bool stop = false;
-  std::thread worker;
-  // staging: inputs (xyz | mpole | pol | thole | rad | eps | guess), molid, outputs
-  Pinned h_in, h_mol, h_out;
-  Dev d_in, d_mol, d_out;
+  Lane lanes[kLanes];
 
-  void loop();
-  tk_status run(std::vector<std::shared_ptr<Req>>& batch,
-                const std::vector<const std::vector<double>*>& guesses);
+  void loop(Lane& L);
+  // projected device bytes of a batch of `atoms` atoms on a lane
+  size_t project(const Lane& L, int64_t atoms) const;
+  size_t others(const Lane& L) const;
+  tk_status run(Lane& L, std::vector<std::shared_ptr<Req>>& batch,
+                const std::vector<std::vector<double>>& guesses);
 };
 
 extern "C" size_t tk_server_footprint(int32_t n) {
-  // per atom: inputs 164 B (coordinates, molecule id, multipoles, four
-  // parameters, guess) and outputs 72 B; candidate windows of the 9 A list
-  // build ~7.2 KB (transient, shared by both builds); pair codes of both
-  // lists ~1.1 KB; cached mat-vec factors ~1.4 KB; partial-result slots
-  // 0.7 KB; sorted fields and solver vectors ~0.5 KB.  Plus fixed per-system
-  // tables.
+  // the estimate before any batch has been measured: per atom, inputs 164 B
+  // (coordinates, molecule id, multipoles, four parameters, guess) and
+  // outputs 72 B; candidate windows of the 9 A list build ~7.2 KB
+  // (transient, shared by both builds); pair codes of both lists ~1.1 KB;
+  // cached mat-vec factors ~1.4 KB; partial-result slots 0.7 KB; sorted fields
+  // and solver vectors ~0.5 KB.  Plus fixed per-system tables.
   return (size_t)(n > 0 ? n : 0) * 11264 + 256 * 1024;
 }
 
-tk_status tk_server::run(std::vector<std::shared_ptr<Req>>& batch,
-                         const std::vector<const std::vector<double>*>& guesses) {
+// Per-context memory that does not scale with the atoms (cell tables, plan
+// records of small batches, event pools): allowed for beside the measured
+// per-atom rate, which is taken only from batches of kRateAtoms atoms or more.
+constexpr size_t kFixedBytes = size_t(8) << 20;
+constexpr int64_t kRateAtoms = 4096;
+
+size_t tk_server::project(const Lane& L, int64_t atoms) const {
+  // a lane sized for a larger batch already holds what this one needs
+  if (atoms <= L.max_atoms) return L.held;
+  size_t est = kFixedBytes + tk_server_footprint((int32_t)atoms);
+  if (bytes_per_atom > 0.0)   // measured, with 10 % headroom
+    est = kFixedBytes + (size_t)(1.1 * bytes_per_atom * (double)atoms);
+  // buffers only grow: a lane never holds less than it does now
+  return std::max(est, L.held);
+}
+
+size_t tk_server::others(const Lane& L) const {
+  size_t s = 0;
+  for (const Lane& o : lanes)
+    if (&o != &L) s += std::max(o.held, o.reserved);
+  return s;
+}
+
+tk_status tk_server::run(Lane& L, std::vector<std::shared_ptr<Req>>& batch,
+                         const std::vector<std::vector<double>>& guesses) {
   const int nsys = (int)batch.size();
   std::vector<int32_t> off(nsys + 1, 0);
   std::vector<double> box(nsys);
@@ -126,7 +208,7 @@ tk_status tk_server::run(std::vector<std::shared_ptr<Req>>& batch,
   for (int k = 0; k < nsys; ++k) {
     off[k + 1] = off[k] + batch[k]->n;
     box[k] = batch[k]->box;
-    use_guess[k] = guesses[k] != nullptr;
+    use_guess[k] = !guesses[k].empty();
     any_guess |= use_guess[k] != 0;
   }
   const size_t n = (size_t)off[nsys];
@@ -134,13 +216,15 @@ tk_status tk_server::run(std::vector<std::shared_ptr<Req>>& batch,
   const size_t o_xyz = 0, o_mp = 3 * n, o_pol = 13 * n, o_th = 14 * n, o_rad = 15 * n,
                o_eps = 16 * n, o_g = 17 * n, nin = 20 * n;
   tk_status s;
-  if ((s = h_in.ensure(sizeof(double) * (nin + 1))) || (s = d_in.ensure(sizeof(double) * (nin + 1))) ||
-      (s = h_mol.ensure(sizeof(int32_t) * (n + 1))) || (s = d_mol.ensure(sizeof(int32_t) * (n + 1))) ||
-      (s = h_out.ensure(sizeof(double) * (9 * n + 1))) ||
-      (s = d_out.ensure(sizeof(double) * (9 * n + 1))))
+  if ((s = L.h_in.ensure(sizeof(double) * (nin + 1))) ||
+      (s = L.d_in.ensure(sizeof(double) * (nin + 1))) ||
+      (s = L.h_mol.ensure(sizeof(int32_t) * (n + 1))) ||
+      (s = L.d_mol.ensure(sizeof(int32_t) * (n + 1))) ||
+      (s = L.h_out.ensure(sizeof(double) * (9 * n + 1))) ||
+      (s = L.d_out.ensure(sizeof(double) * (9 * n + 1))))
     return s;
-  double* hi = (double*)h_in.p;
-  int32_t* hm = (int32_t*)h_mol.p;
+  double* hi = (double*)L.h_in.p;
+  int32_t* hm = (int32_t*)L.h_mol.p;
   for (int k = 0; k < nsys; ++k) {
     const Req& r = *batch[k];
     const size_t a = (size_t)off[k], na = (size_t)r.n;
@@ -150,26 +234,31 @@ tk_status tk_server::run(std::vector<std::shared_ptr<Req>>& batch,
     std::memcpy(hi + o_th + a, r.thole.data(), sizeof(double) * na);
     std::memcpy(hi + o_rad + a, r.rad.data(), sizeof(double) * na);
     std::memcpy(hi + o_eps + a, r.eps.data(), sizeof(double) * na);
-    if (guesses[k]) std::memcpy(hi + o_g + 3 * a, guesses[k]->data(), sizeof(double) * 3 * na);
+    if (!guesses[k].empty())
+      std::memcpy(hi + o_g + 3 * a, guesses[k].data(), sizeof(double) * 3 * na);
     else std::memset(hi + o_g + 3 * a, 0, sizeof(double) * 3 * na);
     std::memcpy(hm + a, r.molid.data(), sizeof(int32_t) * na);
   }
-  if (hipMemcpyAsync(d_in.p, h_in.p, sizeof(double) * nin, hipMemcpyHostToDevice, stream) ||
-      hipMemcpyAsync(d_mol.p, h_mol.p, sizeof(int32_t) * n, hipMemcpyHostToDevice, stream))
+  if (hipMemcpyAsync(L.d_in.p, L.h_in.p, sizeof(double) * nin, hipMemcpyHostToDevice, L.stream) ||
+      hipMemcpyAsync(L.d_mol.p, L.h_mol.p, sizeof(int32_t) * n, hipMemcpyHostToDevice, L.stream))
     return TK_E_HIP;
-  const double* di = (const double*)d_in.p;
-  double* dout = (double*)d_out.p;
-  tk_batch b{nsys, off.data(), box.data(), di + o_xyz, (const int32_t*)d_mol.p};
+  const double* di = (const double*)L.d_in.p;
+  double* dout = (double*)L.d_out.p;
+  tk_batch b{nsys, off.data(), box.data(), di + o_xyz, (const int32_t*)L.d_mol.p};
   std::vector<tk_step_result> res(nsys);
-  s = tk_batch_step(ctx, stream, &b, &prm, di + o_mp, di + o_pol, di + o_th, di + o_rad,
-                          di + o_eps, any_guess ? di + o_g : nullptr,
-                          any_guess ? use_guess.data() : nullptr, dout, dout + 3 * n,
-                          dout + 6 * n, res.data());
-  if (s) return s;
-  if (hipMemcpyAsync(h_out.p, d_out.p, sizeof(double) * 9 * n, hipMemcpyDeviceToHost, stream) ||
-      hipStreamSynchronize(stream))
+  s = tk_batch_step(L.ctx, L.stream, &b, &prm, di + o_mp, di + o_pol, di + o_th, di + o_rad,
+                    di + o_eps, any_guess ? di + o_g : nullptr,
+                    any_guess ? use_guess.data() : nullptr, dout, dout + 3 * n, dout + 6 * n,
+                    res.data());
+  if (s) {
+    (void)hipStreamSynchronize(L.stream);   // nothing of the batch is left in flight
+    return s;
+  }
+  if (hipMemcpyAsync(L.h_out.p, L.d_out.p, sizeof(double) * 9 * n, hipMemcpyDeviceToHost,
+                     L.stream) ||
+      hipStreamSynchronize(L.stream))
     return TK_E_HIP;
-  const double* ho = (const double*)h_out.p;
+  const double* ho = (const double*)L.h_out.p;
   for (int k = 0; k < nsys; ++k) {
     Req& r = *batch[k];
     const size_t a = (size_t)off[k], na = (size_t)r.n;
@@ -181,55 +270,144 @@ tk_status tk_server::run(std::vector<std::shared_ptr<Req>>& batch,
   return TK_OK;
 }
 
-void tk_server::loop() {
-  (void)hipSetDevice(device);   // the worker thread's device (checked at creation)
+void tk_server::loop(Lane& L) {
+  (void)hipSetDevice(device);   // the lane thread's device (checked at creation)
   for (;;) {
     std::vector<std::shared_ptr<Req>> batch;
-    std::vector<const std::vector<double>*> guesses;
+    std::vector<std::vector<double>> guesses;
+    size_t limit = 0;
     {
       std::unique_lock<std::mutex> lk(m);
-      cv_work.wait(lk, [&] { return stop || !queue.empty(); });
-      if (queue.empty()) return;   // stop requested and nothing left
-      size_t fp = 0;
-      while (!queue.empty() && (int)batch.size() < max_batch) {
-        const std::shared_ptr<Req>& r = queue.front();
-        if (!batch.empty() && fp + r->footprint > budget) break;
-        fp += r->footprint;
-        batch.push_back(r);
-        queue.pop_front();
+      for (;;) {
+        if (stop && queue.empty()) return;   // stop requested and nothing left
+        if (!queue.empty()) {
+          // requests in arrival order while the projection fits
+          const size_t held_elsewhere = others(L);
+          const size_t room = budget - std::min(budget, held_elsewhere);
+          int64_t atoms = 0;
+          for (const auto& r : queue) {
+            if ((int)batch.size() >= max_batch) break;
+            // nothing held anywhere: the head request runs alone whatever the
+            // projection says (its context stays bounded by the budget)
+            const bool alone = batch.empty() && L.held == 0 && held_elsewhere == 0;
+            const size_t want = std::max(project(L, atoms + r->n), r->need) +
+                                staging_bytes((size_t)(atoms + r->n));
+            if (!alone && want > room) break;
+            atoms += r->n;
+            batch.push_back(r);
+          }
+          if (!batch.empty()) {
+            queue.erase(queue.begin(), queue.begin() + (long)batch.size());
+            size_t need = project(L, atoms);
+            for (auto& r : batch) need = std::max(need, r->need);
+            L.reserved = need + staging_bytes((size_t)atoms);
+            limit = room;
+            break;
+          }
+          // the head request does not fit beside what this idle lane holds:
+          // give the memory back (another lane, or this one next time, fits it)
+          if (L.held > 0 && L.ctx) {
+            lk.unlock();
+            tk_destroy(L.ctx);
+            L.ctx = nullptr;
+            L.d_in.release();
+            L.d_mol.release();
+            L.d_out.release();
+            const tk_status cs = tk_create(device, &L.ctx);
+            lk.lock();
+            L.held = 0;
+            L.max_atoms = 0;
+            if (cs) {   // no context: this lane stops taking work
+              L.ctx = nullptr;
+              return;
+            }
+            cv_work.notify_all();   // the other lanes see the room this made
+            continue;
+          }
+        }
+        cv_work.wait(lk);
       }
       for (auto& r : batch) {
-        const std::vector<double>* g = nullptr;
+        std::vector<double> g;
         if (r->session) {
           auto it = session_mu.find(r->session);
-          if (it != session_mu.end() && it->second.size() == 3 * (size_t)r->n) g = &it->second;
+          if (it != session_mu.end() && it->second.size() == 3 * (size_t)r->n) g = it->second;
         }
-        guesses.push_back(g);
+        guesses.push_back(std::move(g));
       }
-      inflight = (int)batch.size();
     }
-    // the session guesses are only replaced by this thread, so the pointers
-    // stay valid while the batch runs
+    // the context may not grow beyond the lane's reservation (the sum of the
+    // reservations stays within the budget, so their holdings do too)
+    int64_t batch_atoms = 0;
+    for (auto& r : batch) batch_atoms += r->n;
+    const size_t stage = staging_after(L, (size_t)batch_atoms);
+    const size_t cap = std::min(L.reserved, limit);
+    (void)tk_set_arena_budget(L.ctx, cap > stage ? cap - stage : 1);
     const int64_t t0 = now_ns();
-    const int32_t index = batches++;
+    int32_t index;
+    {
+      std::lock_guard<std::mutex> lk(m);
+      index = batches++;
+    }
     for (auto& r : batch) {
       r->timing.t_start = t0;
       r->timing.batch_size = (int32_t)batch.size();
       r->timing.batch_index = index;
+      r->timing.lane = L.index;
     }
-    const tk_status s = run(batch, guesses);
+    tk_status s = run(L, batch, guesses);
+    if (s == TK_E_NOMEM && batch.size() > 1) {
+      // the batch needs more than the admission allowed: run its first
+      // request alone and return the others to the head of the queue
+      {
+        std::lock_guard<std::mutex> lk(m);
+        for (size_t k = batch.size(); k-- > 1;) queue.push_front(batch[k]);
+      }
+      cv_work.notify_all();
+      batch.resize(1);
+      guesses.resize(1);
+      batch[0]->timing.batch_size = 1;
+      s = run(L, batch, guesses);
+    }
+    if (s == TK_E_NOMEM) {
+      // refused alone within its reservation: unless that was the whole
+      // budget with nothing held elsewhere, it goes back to the head of the
+      // queue, known to need half as much again (and 16 MiB) more, and waits
+      // for that room
+      std::unique_lock<std::mutex> lk(m);
+      if (others(L) > 0 || cap < budget) {
+        batch[0]->need = std::min(budget, std::max(batch[0]->need, cap + cap / 2 + (16u << 20)));
+        queue.push_front(batch[0]);
+        L.held = L.device_bytes();
+        L.reserved = 0;
+        lk.unlock();
+        cv_work.notify_all();
+        continue;
+      }
+    }
     const int64_t t1 = now_ns();
+    int64_t atoms = 0;
+    for (auto& r : batch) atoms += r->n;
     {
       std::lock_guard<std::mutex> lk(m);
+      L.max_atoms = std::max(L.max_atoms, atoms);
+      L.held = L.device_bytes();
+      L.reserved = 0;
+      if (s == TK_OK && L.max_atoms >= kRateAtoms && L.held > kFixedBytes)
+        bytes_per_atom =
+            std::max(bytes_per_atom, (double)(L.held - kFixedBytes) / (double)L.max_atoms);
+      size_t tot = 0;
+      for (const Lane& o : lanes) tot += o.held;
+      peak = std::max(peak, tot);
       for (auto& r : batch) {
         r->status = s;
         r->timing.t_done = t1;
         r->done = true;
         if (s == TK_OK && r->session) session_mu[r->session] = r->mu;
       }
-      inflight = 0;
     }
     cv_done.notify_all();
+    cv_work.notify_all();   // memory and a lane are free again
   }
 }
 
@@ -239,21 +417,26 @@ tk_status tk_server_create(int device, const tk_step_params* params, size_t hbm_
                            int32_t max_batch, tk_server** out) {
   if (!out || !params || max_batch < 1 || hbm_budget == 0) return TK_E_ARG;
   *out = nullptr;
-  tk_ctx* ctx = nullptr;
-  tk_status s = tk_create(device, &ctx);
-  if (s) return s;
   tk_server* srv = new tk_server();
   srv->device = device;
-  srv->ctx = ctx;
   srv->prm = *params;
   srv->budget = hbm_budget;
   srv->max_batch = max_batch;
-  if (hipStreamCreate(&srv->stream) != hipSuccess) {
-    tk_destroy(ctx);
-    delete srv;
-    return TK_E_HIP;
+  for (int k = 0; k < kLanes; ++k) {
+    Lane& L = srv->lanes[k];
+    L.index = k;
+    tk_status s = tk_create(device, &L.ctx);
+    if (!s && hipStreamCreate(&L.stream) != hipSuccess) s = TK_E_HIP;
+    if (s) {
+      for (int j = 0; j <= k; ++j) {
+        if (srv->lanes[j].stream) (void)hipStreamDestroy(srv->lanes[j].stream);
+        if (srv->lanes[j].ctx) tk_destroy(srv->lanes[j].ctx);
+      }
+      delete srv;
+      return s;
+    }
   }
-  srv->worker = std::thread([srv] { srv->loop(); });
+  for (Lane& L : srv->lanes) L.th = std::thread([srv, &L] { srv->loop(L); });
   *out = srv;
   return TK_OK;
 }
@@ -270,7 +453,13 @@ tk_status tk_server_submit(tk_server* srv, const tk_request* q, uint64_t* id) {
   r->box = q->box;
   r->session = q->session;
   r->footprint = tk_server_footprint(q->n);
-  if (r->footprint > srv->budget) return TK_E_CAPACITY;
+  {   // one request alone must fit the budget (by the measured rate once there is one)
+    std::lock_guard<std::mutex> lk(srv->m);
+    size_t fp = r->footprint;
+    if (srv->bytes_per_atom > 0.0)
+      fp = kFixedBytes + (size_t)(1.1 * srv->bytes_per_atom * (double)q->n);
+    if (fp + staging_bytes((size_t)q->n) > srv->budget) return TK_E_CAPACITY;
+  }
   const size_t n = (size_t)q->n;
   r->xyz.assign(q->xyz, q->xyz + 3 * n);
   r->molid.assign(q->molid, q->molid + n);
@@ -280,6 +469,7 @@ tk_status tk_server_submit(tk_server* srv, const tk_request* q, uint64_t* id) {
   r->rad.assign(q->vdw_rad, q->vdw_rad + n);
   r->eps.assign(q->vdw_eps, q->vdw_eps + n);
   r->timing.t_submit = now_ns();
+  r->timing.lane = -1;
   {
     std::lock_guard<std::mutex> lk(srv->m);
     if (srv->stop) return TK_E_ARG;
@@ -287,7 +477,7 @@ tk_status tk_server_submit(tk_server* srv, const tk_request* q, uint64_t* id) {
     srv->reqs[r->id] = r;
     srv->queue.push_back(r);
   }
-  srv->cv_work.notify_one();
+  srv->cv_work.notify_all();
   *id = r->id;
   return TK_OK;
 }
@@ -322,6 +512,20 @@ tk_status tk_server_release(tk_server* srv, uint64_t id) {
   return TK_OK;
 }
 
+tk_status tk_server_stats(tk_server* srv, tk_server_usage* out) {
+  if (!srv || !out) return TK_E_ARG;
+  std::lock_guard<std::mutex> lk(srv->m);
+  out->lanes = kLanes;
+  out->batches = srv->batches;
+  out->budget = srv->budget;
+  out->peak_device_bytes = srv->peak;
+  size_t held = 0;
+  for (const Lane& L : srv->lanes) held += L.held;
+  out->device_bytes = held;
+  out->bytes_per_atom = srv->bytes_per_atom;
+  return TK_OK;
+}
+
 void tk_server_destroy(tk_server* srv) {
   if (!srv) return;
   {
@@ -329,9 +533,15 @@ void tk_server_destroy(tk_server* srv) {
     srv->stop = true;
   }
   srv->cv_work.notify_all();
-  if (srv->worker.joinable()) srv->worker.join();
-  (void)hipStreamDestroy(srv->stream);
-  tk_destroy(srv->ctx);
+  for (Lane& L : srv->lanes)
+    if (L.th.joinable()) L.th.join();
+  for (Lane& L : srv->lanes) {
+    if (L.stream) (void)hipStreamDestroy(L.stream);
+    L.d_in.release();
+    L.d_mol.release();
+    L.d_out.release();
+    if (L.ctx) tk_destroy(L.ctx);
+  }
   delete srv;
 }
 

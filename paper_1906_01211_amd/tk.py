@@ -67,7 +67,13 @@ class Request(C.Structure):
 
 class Timing(C.Structure):
     _fields_ = [("t_submit", C.c_int64), ("t_start", C.c_int64), ("t_done", C.c_int64),
-                ("batch_size", C.c_int32), ("batch_index", C.c_int32)]
+                ("batch_size", C.c_int32), ("batch_index", C.c_int32), ("lane", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("batches", C.c_int32), ("budget", C.c_size_t),
+                ("peak_device_bytes", C.c_size_t), ("device_bytes", C.c_size_t),
+                ("bytes_per_atom", C.c_double)]
 
 
 def step_params(s, prec=FP64):
@@ -624,7 +630,7 @@ class Context:
 
 
 class Server:
-    """Continuous-batching server (its own context, stream and worker thread)."""
+    """Continuous-batching server (three lanes: thread, context and stream each)."""
 
     def __init__(self, params, hbm_budget, max_batch=256, device=0):
         if not torch.cuda.is_available():
@@ -671,6 +677,11 @@ class Server:
     def release(self, rid):
         _check(load().tk_server_release(self._h, rid), "tk_server_release")
         self._keep.pop(rid, None)
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().tk_server_stats(self._h, C.byref(st)), "tk_server_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
 
     def close(self):
         if self._h:

@@ -7,8 +7,10 @@
   (energies 1e-10 relative, forces 1e-8 of the RMS, converged dipoles with
   the same iteration count), including a box small enough that its vdW
   cutoff is clamped to box/2 - skin.
-- The server returns what the batch step returns, batches within its device
-  budget, rejects requests larger than the budget and starts a session's
+- The server returns what the batch step returns, keeps its lanes' measured
+  device memory within its budget, rejects requests larger than the budget,
+  takes a request that arrives while another batch is on the GPU at once on
+  another lane (bitwise the same results as alone), and starts a session's
   solve from its previous dipoles.
 """
 import time
@@ -166,8 +168,15 @@ def wait(srv, rid, limit=60.0):
 def test_server_matches_batch_and_budget(tk, ctx, systems):
     prm = tk.step_params(S, 0)
     ref = [ctx.batch_step([w], prm) for w in systems]
-    fp = [tk.Server.footprint(w.n) for w in systems]
-    budget = max(fp[2] + fp[3], fp[0] + fp[1] + fp[2])   # forces several batches
+    # the largest system alone, on a fresh context, to size the budget: room
+    # for about two lanes' worth, so admission binds and several batches form
+    big = tk.Context(0)
+    try:
+        big.batch_step([systems[3]], prm)
+        one = big.arena_bytes()
+    finally:
+        big.close()
+    budget = 2 * one + (24 << 20)
     srv = tk.Server(prm, budget, max_batch=8)
     try:
         ids = [srv.submit(w) for w in systems + systems]
@@ -180,18 +189,47 @@ def test_server_matches_batch_and_budget(tk, ctx, systems):
             assert np.array_equal(mu, np_(ref[k][2][0]))
             assert np.array_equal(fv, np_(ref[k][3][0]))
             assert t["t_submit"] <= t["t_start"] <= t["t_done"]
-        # every batch stayed within the budget
-        batches = {}
-        for j, out in enumerate(outs):
-            batches.setdefault(out[1]["batch_index"], []).append(fp[j % len(systems)])
-        assert len(batches) >= 2
-        for b in batches.values():
-            assert len(b) == 1 or sum(b) <= budget
+            assert 0 <= t["lane"] < 3
+        assert len({out[1]["batch_index"] for out in outs}) >= 2
+        st = srv.stats()
+        # measured (not estimated) device bytes of the lanes stayed in the budget
+        assert 0 < st["peak_device_bytes"] <= budget
         for i in ids:
             srv.release(i)
         with pytest.raises(tk.TkError) as e:
-            srv.submit(synth.amoeba_water_box(4000, box_of(4000), 34))
+            srv.submit(synth.amoeba_water_box(40000, box_of(40000), 34))
         assert e.value.status == tk.E_CAPACITY
+    finally:
+        srv.close()
+
+
+def test_server_admits_while_a_batch_runs(tk, ctx, systems):
+    """A request submitted while a large one is on the GPU is taken by another
+    lane at once (it starts before the large one ends), and its results are
+    bitwise those of the same system stepped alone."""
+    prm = tk.step_params(S, 0)
+    large = synth.amoeba_water_box(10000, box_of(10000), 35)   # 30,000 atoms
+    small = systems[1]
+    alone = ctx.batch_step([small], prm)
+    srv = tk.Server(prm, 16 << 30, max_batch=8)
+    try:
+        for rep in range(2):   # first on fresh lanes (the large step is long), then warm
+            a = srv.submit(large)
+            time.sleep(0.001)   # a lane has taken the large request
+            b = srv.submit(small)
+            ob = wait(srv, b)
+            oa = wait(srv, a)
+            ra, ta = oa[0], oa[1]
+            rb, tb = ob[0], ob[1]
+            if rep == 0:
+                assert tb["batch_index"] != ta["batch_index"] and tb["lane"] != ta["lane"]
+                assert tb["t_start"] < ta["t_done"], "the small request waited for the large one"
+                assert tb["t_done"] < ta["t_done"]
+            same_result(rb, alone[0][0])
+            assert np.array_equal(ob[2], np_(alone[1][0]))
+            assert np.array_equal(ob[3], np_(alone[2][0]))
+            assert np.array_equal(ob[4], np_(alone[3][0]))
+            assert ra["pcg"]["converged"] == 1
     finally:
         srv.close()
 
