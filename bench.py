@@ -2,12 +2,13 @@
 
 Step (23,559-atom water box, FP64 unless --prec mixed):
   neighbour list at 7 A (CSR + cell-pair plan), neighbour list at 9 A,
-  permanent-multipole energy/forces/virial (7 A), induced dipoles by PCG to
-  1e-5 D RMS (permanent field + mat-vecs + FP64 true residual), Halgren 14-7
-  energy/forces/virial (9 A).
+  permanent-multipole energy/forces/virial and the permanent field (7 A, one
+  fused pass), induced dipoles by PCG to 1e-5 D RMS (mat-vecs + FP64 true
+  residual), Halgren 14-7 energy/forces/virial (9 A).
 value = real-space pair interactions per second over the whole step (each
-listed pair with r <= rc counted once per kernel evaluation; the mat-vec once
-per call).  Inputs are resident in HBM before the timed region.
+listed pair with r <= rc counted once per routine that evaluates it: the
+multipole energy and the permanent field once each, the mat-vec once per
+call, HAL once).  Inputs are resident in HBM before the timed region.
 
 Prints ONE JSON line.  Extra keys: polarization solves/s, the mixed-precision
 step, the point-charge + LJ path (96,000 atoms, 12 A), the roofline of the
@@ -126,11 +127,13 @@ class AmoebaStep:
         self.side.wait_stream(main)
         l7, l9 = c.nblists(self.sys, [s["rc_ewald"] + s["skin"], s["rc_vdw"] + s["skin"]],
                            [0, 1], streams=[main, self.side])
-        em = c.empole_real(self.sys, l7, self.mpole, s["beta"], s["rc_ewald"], prec=p)
         main.wait_stream(self.side)   # the 9 A list is complete before the solver starts
-        mu, self.info = c.polarize_pcg(self.sys, l7, self.mpole, self.pol, self.thole, s["beta"],
-                                       s["rc_ewald"], tol_debye=s["tol_debye"],
-                                       maxiter=s["maxiter"], prec=p)
+        # multipole energy/forces/virial and the induced dipoles: one call, the
+        # multipole terms and the permanent field from one pass over the list
+        em, (mu, self.info) = c.empole_polarize(self.sys, l7, self.mpole, self.pol, self.thole,
+                                                s["beta"], s["rc_ewald"],
+                                                tol_debye=s["tol_debye"], maxiter=s["maxiter"],
+                                                prec=p)
         ev = c.evdw(self.sys, l9, self.tk.VDW_HAL, self.rad, self.eps, s["rc_vdw"],
                     s["taper_frac"], s["dhal"], s["ghal"], prec=p)
         self.out = (em, mu, ev)
@@ -159,8 +162,64 @@ def timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def cpu_baseline(w, n7, n9):
-    """The CPU oracle on the same step (bounded: one full step of this workload)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# Row-block workers of the all-core leg (forked before the GPU is touched; each
+# runs the unchanged oracle on its block of CSR rows).
+_blk = {}
+
+
+def _block_rows(row_ptr, parts):
+    """Row boundaries splitting the listed pairs into `parts` nearly equal blocks."""
+    n = len(row_ptr) - 1
+    tgt = np.linspace(0, row_ptr[-1], parts + 1)
+    b = np.searchsorted(row_ptr, tgt, side="left")
+    b[0], b[-1] = 0, n
+    return np.maximum.accumulate(b)
+
+
+def _sub_csr(row_ptr, col, r0, r1):
+    base = row_ptr[r0]
+    rp = np.clip(row_ptr, row_ptr[r0], row_ptr[r1]) - base
+    return rp.astype(np.int32), np.ascontiguousarray(col[row_ptr[r0]:row_ptr[r1]])
+
+
+def _blk_work(k):
+    """One worker's share of the step's pair kernels: rows of block k of the
+    7 A list (multipoles, permanent field, `mv` mat-vecs) and of the 9 A list
+    (HAL).  Returns its multipole energy (the blocks' sum is the full one)."""
+    from oracle import oracle as O
+    d = _blk
+    w, s = d["w"], synth.AMOEBA_SETTINGS
+    rp, cp = d["b7"][k]
+    rp9, cp9 = d["b9"][k]
+    e, _, _ = O.empole_real(w.xyz, w.box, w.molid, rp, cp, w.mpole, s["beta"], s["rc_ewald"])
+    O.efield_direct(w.xyz, w.box, w.molid, rp, cp, w.mpole, w.polarity, w.thole, s["beta"],
+                    s["rc_ewald"])
+    v = d["mu"]
+    for _ in range(d["mv"]):
+        O.tmatvec(w.xyz, w.box, rp, cp, w.polarity, w.thole, s["beta"], s["rc_ewald"], v, 1)
+    O.evdw(w.xyz, w.box, w.molid, rp9, cp9, 0, w.vdw_rad, w.vdw_eps, s["rc_vdw"])
+    return float(e[0])
+
+
+def cpu_baseline(w):
+    """The CPU oracle on the benchmark's step, serial (one full step: lists,
+    multipoles, PCG solve, HAL) and on all the host's cores (the same step's
+    pair kernels split by CSR row blocks over one process per core, the unchanged
+    oracle in each; the lists and the PCG vector algebra, a few percent of the
+    serial time, are left out there).  Runs before the GPU is touched (the
+    workers are forked).  Returns the record, the reference outputs and the
+    pair counts at 7 A (r <= 7) and 9 A (r <= 9, other molecules)."""
+    import multiprocessing as mp
     from oracle import oracle as O
     s = synth.AMOEBA_SETTINGS
     t0 = time.perf_counter()
@@ -171,15 +230,42 @@ def cpu_baseline(w, n7, n9):
                               s["beta"], s["rc_ewald"], tol_debye=s["tol_debye"])
     ev = O.evdw(w.xyz, w.box, w.molid, rp9, cp9, 0, w.vdw_rad, w.vdw_eps, s["rc_vdw"])
     dt = time.perf_counter() - t0
-    pairs = n7 * (2 + info["iters"] + 2) + n9
+    n7 = count_pairs(w.xyz, w.box, rp7, cp7, s["rc_ewald"])
+    n9 = count_pairs(w.xyz, w.box, rp9, cp9, s["rc_vdw"], w.molid, skip_same=True)
+    mv = info["iters"] + 2
+    pairs = n7 * (2 + mv) + n9
     base = {"value": pairs / dt, "unit": "pair-interactions/s", "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"one full FP64 step of the 23,559-atom water box (serial C oracle, "
                       f"{dt:.2f} s, {info['iters']} PCG iterations)", "seconds": dt}
+    # all cores: the machine's CPU share (at most 16 workers per GPU)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    P = max(1, min(16, avail))
+    b7, b9 = _block_rows(rp7, P), _block_rows(rp9, P)
+    _blk.update(w=w, mu=mu, mv=mv,
+                b7=[_sub_csr(rp7, cp7, b7[k], b7[k + 1]) for k in range(P)],
+                b9=[_sub_csr(rp9, cp9, b9[k], b9[k + 1]) for k in range(P)])
+    with mp.get_context("fork").Pool(P) as pool:
+        pool.map(_blk_work, range(P))          # warm-up: workers load the oracle
+        t1 = time.perf_counter()
+        parts = pool.map(_blk_work, range(P))
+        dt_all = time.perf_counter() - t1
+    e_sum = float(np.sum(parts))
+    base["all_cores"] = {
+        "value": (n7 * (2 + mv) + n9) / dt_all, "unit": "pair-interactions/s", "cores": P,
+        "host_cpus_visible": avail, "seconds": dt_all,
+        "sample": f"the step's pair kernels (multipoles, permanent field, {mv} mat-vecs, HAL) "
+                  f"split by CSR row blocks over {P} processes",
+        "check_multipole_energy_rel": abs(e_sum - em[0][0]) / abs(em[0][0])}
+    _blk.clear()
     # not timed: dipoles converged far below the tolerance, the reference that
     # the mixed form's dipole error is stated against
     tight, _ = O.polarize_pcg(w.xyz, w.box, w.molid, rp7, cp7, w.mpole, w.polarity, w.thole,
                               s["beta"], s["rc_ewald"], tol_debye=1e-10, maxiter=200)
-    return base, (em, (mu, info), ev, tight)
+    return base, (em, (mu, info), ev, tight), (n7, n9)
 
 
 def copy_rate(ctx, mib=1024):
@@ -236,9 +322,13 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              f"(the path is single-GPU; multi-GPU sharding is described in DESIGN.md)",
+              f"(the path runs on one GPU; its value is one GPU's throughput)",
               file=sys.stderr)
         sys.exit(2)
+    w = synth.make("water7853")
+    cpu = None
+    if not a.no_cpu_baseline:   # before the GPU is touched: its workers are forked
+        cpu = cpu_baseline(w)
     import torch
     from paper_1906_01211_amd import tk
     tk.load()
@@ -251,7 +341,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     prec = tk.FP64 if a.prec == "fp64" else tk.MIXED
-    w = synth.make("water7853")
     step = AmoebaStep(ctx, tk, w, prec)
     n7, n9 = step.pair_counts()
 
@@ -338,8 +427,9 @@ def main():
     if roof is not None:
         roof["achievable_copy_gbs"] = copy_rate(ctx)
         roof["frac_of_achievable"] = round(roof["achieved"] / roof["achievable_copy_gbs"], 4)
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"], ref = cpu_baseline(w, n7, n9)
+    if cpu is not None:
+        out["cpu_baseline"], ref, (n7o, n9o) = cpu
+        assert (n7o, n9o) == (n7, n9), "GPU and oracle lists count different pairs"
         # the last timed-pass step's outputs, and those of the other precision's step
         acc = {a.prec: accuracy(step, ref)}
         if other_step is not None:
