@@ -15,6 +15,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <mutex>
+
 #include "tk_internal.hpp"
 
 namespace tk {
@@ -717,8 +719,11 @@ __global__ __launch_bounds__(64 * kRowsPerBlock) void k_rowsort(int n,
 }
 
 // Dynamic LDS above the default limit must be allowed per kernel.
+// (Process-wide: several contexts on several host threads share it.)
 tk_status rowsort_attribute(size_t lds) {
+  static std::mutex m;
   static size_t done = 0;
+  std::lock_guard<std::mutex> lk(m);
   if (lds <= done) return TK_OK;
   TK_HIP(hipFuncSetAttribute((const void*)k_rowsort, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));

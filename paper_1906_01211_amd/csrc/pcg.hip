@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -831,8 +832,11 @@ tk_status set_lds_attr(size_t lds) {
 }
 
 // Dynamic LDS above the default limit must be allowed per kernel.
+// (Process-wide: several contexts on several host threads share it.)
 tk_status mv_attributes(size_t lds) {
+  static std::mutex m;
   static size_t done = 0;
+  std::lock_guard<std::mutex> lk(m);
   if (lds <= done) return TK_OK;
   tk_status s;
   if ((s = set_lds_attr<double, 0, true>(lds)) || (s = set_lds_attr<double, 1, true>(lds)) ||
@@ -1181,13 +1185,8 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
       (s = scratch(ctx, "pcg_gc", (prec == TK_FP64 ? sizeof(double) : sizeof(float)) * 2 * S.gcs,
                    &S.gc)))
     return s;
-  if (prec == TK_MIXED &&
-      (s = scratch(ctx, per_stream("partial", st).c_str(),
-                   sizeof(double) * kMaxSlots * 3 * S.pstride, &partial)))
-    return s;
   S.alpha_s = (double*)alpha_s; S.b = (double*)b; S.x = (double*)x; S.r = (double*)r;
   S.z = (double*)z; S.q = (double*)q; S.dx = (double*)dx; S.rt = (double*)rt;
-  S.partial = (double*)partial;
   S.gathered = (double*)gath; S.npart = (double*)npart; S.part = (double*)part;
   S.pbuf[0] = (double*)pb0; S.pbuf[1] = (double*)pb1;
   S.pz[0] = (double*)pz0; S.pz[1] = (double*)pz1; S.pg = (double*)pg;
@@ -1237,10 +1236,18 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   if (nv == 2 && (s = launch_efield<double>(ctx, st, *P, &sys1, mpole, polarity, thole, ewald_beta,
                                             cutoff, S.b + S.vs, 1, nullptr, 0, pscale)))
     return s;
-  if (prec == TK_FP64)   // the FP64 mat-vec reads only coordinates: the ones the field pass gathered
+  // Buffers that the pair-term passes share per stream are taken only now:
+  // a pass above may have grown (reallocated) them, the multipole pass
+  // needing six accumulators per slot where the mat-vec needs three.
+  if (prec == TK_FP64) {   // the FP64 mat-vec reads only coordinates: the ones the field pass gathered
     S.gathered = (double*)ctx->scratch[per_stream("gathered", st)].p;
-  else
+  } else {
+    if ((s = scratch(ctx, per_stream("partial", st).c_str(),
+                     sizeof(double) * kMaxSlots * 3 * S.pstride, &partial)))
+      return s;
+    S.partial = (double*)partial;
     S.gather_geometry();
+  }
   // full Ewald: the reciprocal permanent field joins the right-hand side (the
   // PME scratch is separate from the gathered coordinates above)
   for (int v = 0; v < nv && pme_grid; ++v)

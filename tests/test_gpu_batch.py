@@ -130,6 +130,27 @@ def test_batch_mixed_within_budget(tk, ctx, systems):
         assert rmx[k]["pcg"]["rms_true_debye"] <= S["tol_debye"]
 
 
+def test_mixed_step_first_on_a_fresh_context(tk, ctx, systems):
+    """A mixed-form batch step as the first call of a new context (its
+    per-stream pair-term buffers still at the sizes the 14-7 pass gave them;
+    the multipole pass inside the solve grows them) returns bitwise what the
+    same step returns on a context that has run other work before.
+    Regression: the solver used to take the shared accumulator buffer before
+    the multipole pass reallocated it."""
+    prm = tk.step_params(S, 1)
+    batch = systems[::-1]
+    ref = ctx.batch_step(batch, prm)
+    fresh = tk.Context(0)
+    try:
+        got = fresh.batch_step(batch, prm)
+        for k in range(len(batch)):
+            same_result(got[0][k], ref[0][k])
+            for j in (1, 2, 3):
+                assert np.array_equal(np_(got[j][k]), np_(ref[j][k]))
+    finally:
+        fresh.close()
+
+
 def test_batch_guess_per_system(tk, ctx, systems):
     prm = tk.step_params(S, 0)
     res, fm, mu, fv = ctx.batch_step(systems, prm)

@@ -103,6 +103,30 @@ def test_empole_polarize_matches_the_two_calls(ctx, tk):
     assert np.abs(mu.cpu().numpy() - mu2.cpu().numpy()).max() <= 1e-12 * mu2.abs().max().item()
 
 
+def test_empole_polarize_mixed_first_on_a_fresh_context(ctx, tk):
+    """The mixed-form call as the first pair-term work of a new context
+    returns bitwise what it returns on a context that has run before (the
+    multipole pass grows the per-stream accumulator buffer that the mixed
+    solver then uses; the solver must take it after that growth)."""
+    w, sysr, lst, *_ = setup(ctx, "water7853")
+    args = (w.mpole, w.polarity, w.thole, S["beta"], S["rc_ewald"])
+    (e, f, v), (mu, info) = ctx.empole_polarize(sysr, lst, *args, tol_debye=S["tol_debye"],
+                                                prec=tk.MIXED)
+    fresh = tk.Context(0)
+    try:
+        s2 = fresh.system(w.xyz, w.box, w.molid)
+        l2 = fresh.nblist(s2, S["rc_ewald"] + S["skin"], plan_slot=2)
+        (e2, f2, v2), (mu2, info2) = fresh.empole_polarize(s2, l2, *args,
+                                                           tol_debye=S["tol_debye"],
+                                                           prec=tk.MIXED)
+        assert np.array_equal(e.cpu().numpy(), e2.cpu().numpy())
+        assert np.array_equal(f.cpu().numpy(), f2.cpu().numpy())
+        assert np.array_equal(mu.cpu().numpy(), mu2.cpu().numpy())
+        assert info2["iters"] == info["iters"] and info2["converged"] == 1
+    finally:
+        fresh.close()
+
+
 def test_empole_polarize_empty_and_errors(ctx, tk):
     import torch
     sysr = ctx.system(np.zeros((0, 3)), 20.0, np.zeros(0, dtype=np.int32))
