@@ -132,6 +132,18 @@ struct Lane {
   }
 };
 
+// Drops the lane's context and staging and starts a new context: after a
+// refused batch the buffers it grew part of the way are given back, so what
+// the lane holds is always what its successful batches needed.
+tk_status reset_lane(Lane& L, int device) {
+  if (L.ctx) tk_destroy(L.ctx);
+  L.ctx = nullptr;
+  L.d_in.release();
+  L.d_mol.release();
+  L.d_out.release();
+  return tk_create(device, &L.ctx);
+}
+
 size_t staging_after(const Lane& L, size_t n) {
   return std::max(L.d_in.bytes, sizeof(double) * (20 * n + 1)) +
          std::max(L.d_mol.bytes, sizeof(int32_t) * (n + 1)) +
@@ -308,12 +320,7 @@ void tk_server::loop(Lane& L) {
           // give the memory back (another lane, or this one next time, fits it)
           if (L.held > 0 && L.ctx) {
             lk.unlock();
-            tk_destroy(L.ctx);
-            L.ctx = nullptr;
-            L.d_in.release();
-            L.d_mol.release();
-            L.d_out.release();
-            const tk_status cs = tk_create(device, &L.ctx);
+            const tk_status cs = reset_lane(L, device);
             lk.lock();
             L.held = 0;
             L.max_atoms = 0;
@@ -358,7 +365,9 @@ void tk_server::loop(Lane& L) {
     tk_status s = run(L, batch, guesses);
     if (s == TK_E_NOMEM && batch.size() > 1) {
       // the batch needs more than the admission allowed: run its first
-      // request alone and return the others to the head of the queue
+      // request alone (on a new context: the refused batch's partly grown
+      // buffers are given back) and return the others to the head of the
+      // queue
       {
         std::lock_guard<std::mutex> lk(m);
         for (size_t k = batch.size(); k-- > 1;) queue.push_front(batch[k]);
@@ -367,7 +376,13 @@ void tk_server::loop(Lane& L) {
       batch.resize(1);
       guesses.resize(1);
       batch[0]->timing.batch_size = 1;
-      s = run(L, batch, guesses);
+      s = reset_lane(L, device);
+      L.max_atoms = 0;
+      if (s == TK_OK) {
+        const size_t stage1 = staging_after(L, (size_t)batch[0]->n);
+        (void)tk_set_arena_budget(L.ctx, cap > stage1 ? cap - stage1 : 1);
+        s = run(L, batch, guesses);
+      }
     }
     if (s == TK_E_NOMEM) {
       // refused alone within its reservation: unless that was the whole
@@ -378,8 +393,19 @@ void tk_server::loop(Lane& L) {
       if (others(L) > 0 || cap < budget) {
         batch[0]->need = std::min(budget, std::max(batch[0]->need, cap + cap / 2 + (16u << 20)));
         queue.push_front(batch[0]);
+        lk.unlock();
+        const tk_status cs = reset_lane(L, device);   // give the partly grown buffers back
+        lk.lock();
         L.held = L.device_bytes();
+        L.max_atoms = 0;
         L.reserved = 0;
+        if (cs) {   // no context: this lane stops taking work
+          L.ctx = nullptr;
+          L.held = 0;
+          lk.unlock();
+          cv_work.notify_all();
+          return;
+        }
         lk.unlock();
         cv_work.notify_all();
         continue;
@@ -408,6 +434,7 @@ void tk_server::loop(Lane& L) {
     }
     cv_done.notify_all();
     cv_work.notify_all();   // memory and a lane are free again
+    if (!L.ctx) return;     // a new context could not be made: this lane stops
   }
 }
 
@@ -453,11 +480,14 @@ tk_status tk_server_submit(tk_server* srv, const tk_request* q, uint64_t* id) {
   r->box = q->box;
   r->session = q->session;
   r->footprint = tk_server_footprint(q->n);
-  {   // one request alone must fit the budget (by the measured rate once there is one)
+  {   // one request alone must be able to fit the budget: rejected here only
+      // when even the estimate without headroom (the measured rate once there
+      // is one) exceeds it; a request that passes and still needs more fails
+      // when it is refused with the whole budget to itself
     std::lock_guard<std::mutex> lk(srv->m);
     size_t fp = r->footprint;
     if (srv->bytes_per_atom > 0.0)
-      fp = kFixedBytes + (size_t)(1.1 * srv->bytes_per_atom * (double)q->n);
+      fp = kFixedBytes + (size_t)(srv->bytes_per_atom * (double)q->n);
     if (fp + staging_bytes((size_t)q->n) > srv->budget) return TK_E_CAPACITY;
   }
   const size_t n = (size_t)q->n;

@@ -186,8 +186,9 @@ def wait(srv, rid, limit=60.0):
         time.sleep(0.001)
 
 
-def test_server_matches_batch_and_budget(tk, ctx, systems):
-    prm = tk.step_params(S, 0)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_server_matches_batch_and_budget(tk, ctx, systems, prec):
+    prm = tk.step_params(S, prec)
     ref = [ctx.batch_step([w], prm) for w in systems]
     # the largest system alone, on a fresh context, to size the budget: room
     # for about two lanes' worth, so admission binds and several batches form
