@@ -221,10 +221,12 @@ __global__ __launch_bounds__(64) void k_cs_init(PlanView pv, const double* __res
 // dipole sets takes.
 constexpr int kMvThreads = 512;    // mat-vec workgroups: 8 waves per cell
 constexpr int kMvWaves = kMvThreads / 64;
-// pairs, and staged atoms, per thread whose loads are issued together (fewer
-// with two operands, to keep two workgroups per CU in registers)
+// pairs, and staged atoms, per thread whose loads are issued together (two
+// pairs measured fastest for one operand: 21.5 us against 22.8 with four and
+// 29 with eight on the 23,559-atom water box; two operands keep two
+// workgroups per CU in registers)
 template <int NV>
-constexpr int mv_batch() { return NV == 1 ? 4 : 2; }
+constexpr int mv_batch() { return NV == 1 ? 2 : 2; }
 template <int NV>
 constexpr int mv_stage_batch() { return NV == 1 ? 3 : 2; }
 
