@@ -38,15 +38,37 @@ MV_BYTES_PER_ATOM = 24 + 24 + 24 + 8 + 24 + 24
 # fields: pair vector 9, two dot products 10, two field updates 12, scale 2).
 MV_FLOPS_PER_PAIR = 33
 PEAK_FP64_TFLOPS = 78.6
-# FP64 vector issue peak in lane-instructions per second: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz (an FMA, an add and a multiply each take one slot).
-PEAK_FP64_LANE_INSTR = 256 * 64 * 2.4e9
-# FP64 vector instructions per evaluated pair of the polarization-force
-# kernel (k_units<EpolarPh<double>, 2>): static count in its gfx950 assembly,
-# nearly all of it the pair evaluation (radial functions, Thole factors,
-# multipole algebra, gradient, virial).
-EPOLAR_FP64_INSTR_PER_PAIR = 390
 PEAK_FP32_TFLOPS = 157.3
+# Unpacked FP32 vector issue (the form this library is built for) runs at the
+# FP64 vector rate: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
+# Floating-point operations per pair of each routine, counted by the oracle's
+# op-counting build (+ - * / one each, fma two; sqrt, exp, erfc and pow
+# apart): per evaluated pair (r <= rc) and per listed pair (image, distance).
+OPCOUNTS = os.path.join(ROOT, "tests", "golden", "pair_opcounts.json")
+
+
+def algorithmic_flops(routines, evaluated, listed):
+    """Algorithmic FLOPs of one pass over a list: the listed routines' counts
+    per evaluated pair times the evaluated pairs, plus theirs per listed
+    pair times the listed pairs."""
+    with open(OPCOUNTS) as f:
+        c = json.load(f)["counts"]
+    return sum(c[r]["flops_per_evaluated_pair"] * evaluated + c[r]["flops_per_listed_pair"] * listed
+               for r in routines)
+
+
+def valu_entry(prof, name, routines, evaluated, listed, peak, per_launch=1):
+    """Algorithmic FLOP rate of one VALU-bound pair kernel from its HIP-event
+    time (per_launch: passes over the list per launch)."""
+    if name not in prof or prof[name]["launches"] == 0:
+        return None
+    us = prof[name]["ms"] / prof[name]["launches"] * 1e3
+    fl = algorithmic_flops(routines, evaluated, listed) * per_launch
+    return {"routines": list(routines), "avg_launch_us": round(us, 2),
+            "algorithmic_gflop_per_launch": round(fl / 1e9, 4),
+            "tflops": round(fl / (us * 1e-6) / 1e12, 3), "peak_tflops": peak,
+            "frac": round(fl / (us * 1e-6) / 1e12 / peak, 4)}
 PEAK_HBM_GBS = 8000.0
 
 
@@ -142,6 +164,7 @@ class AmoebaStep:
     def pair_counts(self):
         l7, l9 = self()
         self.l7_pairs = l7.npairs
+        self.l9_pairs = l9.npairs
         w, s = self.w, self.s
         n7 = count_pairs(w.xyz, w.box, l7.row_ptr.cpu().numpy(), l7.col.cpu().numpy(),
                          s["rc_ewald"])
@@ -426,6 +449,19 @@ def main():
         "kernel_ms_per_step": {k: round(v["ms"] / max(2, a.steps // 4), 5) for k, v in prof.items()},
         "roofline": roof,
     }
+    # the VALU-bound pair kernels of the step: algorithmic FLOP rate (oracle
+    # op counts x exact pair counts / HIP-event time) against the vector peak
+    tag = "fp64" if prec == tk.FP64 else "fp32"
+    pk = PEAK_FP64_TFLOPS if prec == tk.FP64 else PEAK_FP32_UNPACKED_TFLOPS
+    out["valu_kernels"] = {
+        "units_mpole_field_" + tag: valu_entry(prof, "units_mpole_field_" + tag,
+                                               ("empole_real", "efield_direct"), n7,
+                                               step.l7_pairs, pk),
+        "units_vdw_" + tag: valu_entry(prof, "units_vdw_" + tag, ("evdw_hal",), n9,
+                                       step.l9_pairs, pk),
+        "units_tmat_fp64": valu_entry(prof, "units_tmat_fp64", ("tmatvec",), n7, step.l7_pairs,
+                                      PEAK_FP64_TFLOPS),
+    }
     other_step = None
     if not a.no_extras:
         out["extras"], other_step = extras(ctx, tk, w, a, prec, n7)
@@ -659,9 +695,9 @@ def epolar_leg(ctx, tk, w, n7):
         out[f"call_ms_{name}"] = round(ms, 4)
         out[f"kernel_us_{name}"] = round(kus, 2)
         out[f"pairs_per_s_{name}"] = n7 / (kus * 1e-6)
-        if pr == tk.FP64:
-            out["alu_frac_fp64"] = round(EPOLAR_FP64_INSTR_PER_PAIR * n7 / (kus * 1e-6) /
-                                         PEAK_FP64_LANE_INSTR, 4)
+        fl = algorithmic_flops(("epolar_real",), n7, l7.npairs)
+        out[f"algorithmic_tflops_{name}"] = round(fl / (kus * 1e-6) / 1e12, 3)
+        out[f"algorithmic_frac_{name}"] = round(fl / (kus * 1e-6) / 1e12 / PEAK_FP64_TFLOPS, 4)
     return out
 
 
@@ -736,10 +772,11 @@ def serving(tk, count):
     def arrivals(rate):
         return [r["arrival"] for r in synth.serving_requests(count, rate=rate)]
 
-    def one(prec, budget, max_batch, fracs, base=None):
+    def one(prec, budget, max_batch, fracs, base=None, lanes=3):
         """fracs: offered loads as fractions of `base` req/s (default: this
         configuration's own capacity)."""
-        srv = tk.Server(tk.step_params(synth.AMOEBA_SETTINGS, prec), budget, max_batch)
+        srv = tk.Server(tk.step_params(synth.AMOEBA_SETTINGS, prec), budget, max_batch,
+                        lanes=lanes)
         try:
             for _ in range(2):                          # warm-up: grows the device arena
                 run_stream(srv, systems)
@@ -783,7 +820,8 @@ def serving(tk, count):
         # a tight budget: room for the largest request (30,000 atoms, about
         # 18 KB per atom measured) and little more
         guarded("fp64_budget_1GiB", tk.FP64, 1 << 30, mb, (0.5, 0.8), base=cap)
-        guarded("fp64_one_at_a_time", tk.FP64, big, 1, (0.5, 1.0), base=cap)
+        # the baseline: one lane, one request per batch (one request at a time)
+        guarded("fp64_one_at_a_time", tk.FP64, big, 1, (0.5, 1.0), base=cap, lanes=1)
     return out
 
 

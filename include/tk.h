@@ -637,6 +637,10 @@ typedef struct {
 
 tk_status tk_server_create(int device, const tk_step_params* params, size_t hbm_budget,
                            int32_t max_batch, tk_server** out);
+/* As tk_server_create with `lanes` lanes (1 to 3; TK_E_ARG otherwise).  One
+ * lane with max_batch 1 serves one request at a time. */
+tk_status tk_server_create_lanes(int device, const tk_step_params* params, size_t hbm_budget,
+                                 int32_t max_batch, int32_t lanes, tk_server** out);
 /* Estimated device bytes of one request of n atoms (the admission measure
  * before the server has measured a batch). */
 size_t tk_server_footprint(int32_t n);

@@ -1,6 +1,7 @@
 // Serving runtime: continuous batching of AMOEBA step requests on one GPU.
 //
-// The server runs kLanes lanes.  A lane is a host thread with its own
+// The server runs up to kMaxLanes lanes (three unless the caller asks for
+// fewer).  A lane is a host thread with its own
 // context (plans and scratch), HIP stream and pinned staging.  An idle lane
 // takes the requests queued at that moment, in arrival order, into a batch
 // and runs one multi-system step for the whole batch (tk_batch_step) on its
@@ -43,7 +44,7 @@
 
 namespace {
 
-constexpr int kLanes = 3;
+constexpr int kMaxLanes = 3;
 
 int64_t now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -167,7 +168,8 @@ struct tk_server {
   double bytes_per_atom = 0.0;   // measured (0: none yet)
   size_t peak = 0;               // largest sum of the lanes' measured holdings
   bool stop = false;
-  Lane lanes[kLanes];
+  int nlanes = kMaxLanes;
+  Lane lanes[kMaxLanes];   // lanes past nlanes stay empty (no context, nothing held)
 
   void loop(Lane& L);
   // projected device bytes of a batch of `atoms` atoms on a lane
@@ -440,16 +442,18 @@ void tk_server::loop(Lane& L) {
 
 extern "C" {
 
-tk_status tk_server_create(int device, const tk_step_params* params, size_t hbm_budget,
-                           int32_t max_batch, tk_server** out) {
-  if (!out || !params || max_batch < 1 || hbm_budget == 0) return TK_E_ARG;
+tk_status tk_server_create_lanes(int device, const tk_step_params* params, size_t hbm_budget,
+                                 int32_t max_batch, int32_t lanes, tk_server** out) {
+  if (!out || !params || max_batch < 1 || hbm_budget == 0 || lanes < 1 || lanes > kMaxLanes)
+    return TK_E_ARG;
   *out = nullptr;
   tk_server* srv = new tk_server();
   srv->device = device;
   srv->prm = *params;
   srv->budget = hbm_budget;
   srv->max_batch = max_batch;
-  for (int k = 0; k < kLanes; ++k) {
+  srv->nlanes = lanes;
+  for (int k = 0; k < lanes; ++k) {
     Lane& L = srv->lanes[k];
     L.index = k;
     tk_status s = tk_create(device, &L.ctx);
@@ -463,9 +467,17 @@ tk_status tk_server_create(int device, const tk_step_params* params, size_t hbm_
       return s;
     }
   }
-  for (Lane& L : srv->lanes) L.th = std::thread([srv, &L] { srv->loop(L); });
+  for (int k = 0; k < lanes; ++k) {
+    Lane& L = srv->lanes[k];
+    L.th = std::thread([srv, &L] { srv->loop(L); });
+  }
   *out = srv;
   return TK_OK;
+}
+
+tk_status tk_server_create(int device, const tk_step_params* params, size_t hbm_budget,
+                           int32_t max_batch, tk_server** out) {
+  return tk_server_create_lanes(device, params, hbm_budget, max_batch, kMaxLanes, out);
 }
 
 tk_status tk_server_submit(tk_server* srv, const tk_request* q, uint64_t* id) {
@@ -545,7 +557,7 @@ tk_status tk_server_release(tk_server* srv, uint64_t id) {
 tk_status tk_server_stats(tk_server* srv, tk_server_usage* out) {
   if (!srv || !out) return TK_E_ARG;
   std::lock_guard<std::mutex> lk(srv->m);
-  out->lanes = kLanes;
+  out->lanes = srv->nlanes;
   out->batches = srv->batches;
   out->budget = srv->budget;
   out->peak_device_bytes = srv->peak;

@@ -141,6 +141,8 @@ _SIGS = {
     "tk_batch_step": [_vp, _vp, C.POINTER(Batch), C.POINTER(StepParams), _vp, _vp, _vp, _vp, _vp,
                       _vp, _vp, _vp, _vp, _vp, _vp],
     "tk_server_create": [C.c_int, C.POINTER(StepParams), C.c_size_t, _i32, C.POINTER(_vp)],
+    "tk_server_create_lanes": [C.c_int, C.POINTER(StepParams), C.c_size_t, _i32, _i32,
+                               C.POINTER(_vp)],
     "tk_server_footprint": [_i32],
     "tk_server_submit": [_vp, C.POINTER(Request), C.POINTER(C.c_uint64)],
     "tk_server_poll": [_vp, C.c_uint64, C.POINTER(StepResult), C.POINTER(Timing), _vp, _vp, _vp],
@@ -630,15 +632,17 @@ class Context:
 
 
 class Server:
-    """Continuous-batching server (three lanes: thread, context and stream each)."""
+    """Continuous-batching server (three lanes unless `lanes` says fewer: a
+    thread, context and stream each)."""
 
-    def __init__(self, params, hbm_budget, max_batch=256, device=0):
+    def __init__(self, params, hbm_budget, max_batch=256, device=0, lanes=3):
         if not torch.cuda.is_available():
             raise RuntimeError("libtk needs a ROCm GPU; none is visible")
         self._h = C.c_void_p()
         self._keep = {}
-        _check(load().tk_server_create(device, C.byref(params), int(hbm_budget), int(max_batch),
-                                       C.byref(self._h)), "tk_server_create")
+        _check(load().tk_server_create_lanes(device, C.byref(params), int(hbm_budget),
+                                             int(max_batch), int(lanes), C.byref(self._h)),
+               "tk_server_create_lanes")
 
     @staticmethod
     def footprint(n):

@@ -256,6 +256,31 @@ def test_server_admits_while_a_batch_runs(tk, ctx, systems):
         srv.close()
 
 
+def test_server_one_lane(tk, ctx, systems):
+    """One lane and batches of one: every request runs alone, in arrival order,
+    on lane 0, with the results of the same system stepped alone; a lane
+    count outside 1-3 is rejected."""
+    import ctypes as C
+    prm = tk.step_params(S, 0)
+    ref = [ctx.batch_step([w], prm) for w in systems[:2]]
+    srv = tk.Server(prm, 1 << 30, max_batch=1, lanes=1)
+    try:
+        ids = [srv.submit(w) for w in systems[:2]]
+        outs = [wait(srv, i) for i in ids]
+        for k, out in enumerate(outs):
+            same_result(out[0], ref[k][0][0])
+            assert np.array_equal(out[3], np_(ref[k][2][0]))
+            assert out[1]["lane"] == 0 and out[1]["batch_size"] == 1
+        assert outs[0][1]["t_done"] <= outs[1][1]["t_start"]
+        assert srv.stats()["lanes"] == 1
+    finally:
+        srv.close()
+    h = C.c_void_p()
+    for bad in (0, 4):
+        st = tk.load().tk_server_create_lanes(0, C.byref(prm), 1 << 30, 8, bad, C.byref(h))
+        assert st == tk.E_ARG
+
+
 def test_server_session_guess(tk, systems):
     prm = tk.step_params(S, 0)
     srv = tk.Server(prm, 1 << 30)
