@@ -599,7 +599,9 @@ tk_status tk_batch_step(tk_ctx* ctx, void* stream, const tk_batch* batch,
  * same limit (a batch that would overrun it runs its first request alone
  * and returns the rest to the queue).  The lanes' device bytes never exceed
  * the budget.  A system's results are the same whatever batch it runs in.
- * A request that alone exceeds the budget is rejected (TK_E_CAPACITY).
+ * A request that alone exceeds the budget is rejected (TK_E_CAPACITY).  A
+ * lane that cannot make a new device context stops; when no lane is left,
+ * queued requests complete with TK_E_NOMEM and tk_server_submit returns it.
  * Sessions: a request with a nonzero session id starts its dipole solve from
  * the dipoles of the previous completed request of the same session when
  * the atom count matches (resident guesses; otherwise from alpha * E_perm).

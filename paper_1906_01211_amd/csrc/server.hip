@@ -169,9 +169,13 @@ struct tk_server {
   size_t peak = 0;               // largest sum of the lanes' measured holdings
   bool stop = false;
   int nlanes = kMaxLanes;
+  int alive = 0;   // lanes still taking work
   Lane lanes[kMaxLanes];   // lanes past nlanes stay empty (no context, nothing held)
 
   void loop(Lane& L);
+  // A lane that cannot make a context stops (called with m held); when it
+  // was the last one, the queued requests fail rather than wait for ever.
+  void lane_lost();
   // projected device bytes of a batch of `atoms` atoms on a lane
   size_t project(const Lane& L, int64_t atoms) const;
   size_t others(const Lane& L) const;
@@ -284,6 +288,16 @@ tk_status tk_server::run(Lane& L, std::vector<std::shared_ptr<Req>>& batch,
   return TK_OK;
 }
 
+void tk_server::lane_lost() {
+  if (--alive > 0) return;
+  for (auto& r : queue) {
+    r->status = TK_E_NOMEM;
+    r->done = true;
+  }
+  queue.clear();
+  cv_done.notify_all();
+}
+
 void tk_server::loop(Lane& L) {
   (void)hipSetDevice(device);   // the lane thread's device (checked at creation)
   for (;;) {
@@ -328,6 +342,7 @@ void tk_server::loop(Lane& L) {
             L.max_atoms = 0;
             if (cs) {   // no context: this lane stops taking work
               L.ctx = nullptr;
+              lane_lost();
               return;
             }
             cv_work.notify_all();   // the other lanes see the room this made
@@ -404,6 +419,7 @@ void tk_server::loop(Lane& L) {
         if (cs) {   // no context: this lane stops taking work
           L.ctx = nullptr;
           L.held = 0;
+          lane_lost();
           lk.unlock();
           cv_work.notify_all();
           return;
@@ -436,7 +452,11 @@ void tk_server::loop(Lane& L) {
     }
     cv_done.notify_all();
     cv_work.notify_all();   // memory and a lane are free again
-    if (!L.ctx) return;     // a new context could not be made: this lane stops
+    if (!L.ctx) {           // a new context could not be made: this lane stops
+      std::lock_guard<std::mutex> lk(m);
+      lane_lost();
+      return;
+    }
   }
 }
 
@@ -467,6 +487,7 @@ tk_status tk_server_create_lanes(int device, const tk_step_params* params, size_
       return s;
     }
   }
+  srv->alive = lanes;
   for (int k = 0; k < lanes; ++k) {
     Lane& L = srv->lanes[k];
     L.th = std::thread([srv, &L] { srv->loop(L); });
@@ -515,6 +536,7 @@ tk_status tk_server_submit(tk_server* srv, const tk_request* q, uint64_t* id) {
   {
     std::lock_guard<std::mutex> lk(srv->m);
     if (srv->stop) return TK_E_ARG;
+    if (srv->alive == 0) return TK_E_NOMEM;   // no lane could keep a context
     r->id = srv->next_id++;
     srv->reqs[r->id] = r;
     srv->queue.push_back(r);
