@@ -184,13 +184,14 @@ struct tk_server {
 };
 
 extern "C" size_t tk_server_footprint(int32_t n) {
-  // the estimate before any batch has been measured: per atom, inputs 164 B
-  // (coordinates, molecule id, multipoles, four parameters, guess) and
-  // outputs 72 B; candidate windows of the 9 A list build ~7.2 KB
-  // (transient, shared by both builds); pair codes of both lists ~1.1 KB;
-  // cached mat-vec factors ~1.4 KB; partial-result slots 0.7 KB; sorted fields
-  // and solver vectors ~0.5 KB.  Plus fixed per-system tables.
-  return (size_t)(n > 0 ? n : 0) * 11264 + 256 * 1024;
+  // the estimate before any batch has been measured, from what lanes measure
+  // on water-density systems (17-22 KB per atom for a whole step): candidate
+  // windows of both list builds ~10 KB, pair codes of both lists ~1.1 KB,
+  // cached mat-vec factors ~1.4 KB, the pair terms' partial slots (six
+  // accumulators per slot) ~1.7 KB, gathered fields ~0.7 KB, solver vectors
+  // and their mirrors ~1 KB, staging and per-cell tables the rest.  Plus
+  // fixed per-system tables.
+  return (size_t)(n > 0 ? n : 0) * 20480 + 256 * 1024;
 }
 
 // Per-context memory that does not scale with the atoms (cell tables, plan
