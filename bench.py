@@ -432,7 +432,11 @@ def main():
                 "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": committed_traffic(a.prec),
                 "bytes_per_launch": bpl, "launches": launches, "working_launches": working,
                 "avg_launch_us": round(avg_ms * 1e3, 3),
-                "alu_tflops": round(fl, 3), "alu_frac": round(fl / peak_fl, 4)}
+                "alu_tflops": round(fl, 3), "alu_frac": round(fl / peak_fl, 4),
+                # what the counters say binds it (HBM is not saturated)
+                "limiter": "LDS issue and latency: about a quarter VALU busy, a quarter of "
+                           "LDS cycles bank-conflicted, a fifth of wave time waiting on LDS "
+                           "(profiles/valu_counters_water7853.txt)"}
     out = {
         "metric": "real-space pair-interactions/s + polarization solves/s (mixed vs FP64); p99 lat",
         "value": value, "unit": "pair-interactions/s", "n_gpus": 1, "steps": a.steps,
