@@ -106,20 +106,45 @@ CellTables& cell_tables(tk_ctx* ctx, int nc) {
   }
   t.nunits = (int32_t)t.units.size();
   t.nslot = cnt;
-  // per cell: the units it takes part in (each unique neighbour cell once),
-  // encoded unit * 4 + role (0: the cell is the unit's H, 1: its K, 2: both)
-  t.cu.assign((size_t)t.ncells * kCellUnitStride, 0);
-  for (int u = 0; u < t.nunits; ++u) {
-    const Unit& un = t.units[u];
-    if (un.h == un.k) {
-      int32_t* e = &t.cu[(size_t)un.h * kCellUnitStride];
-      e[1 + e[0]++] = u * 4 + 2;
-    } else {
-      int32_t* e = &t.cu[(size_t)un.h * kCellUnitStride];
-      e[1 + e[0]++] = u * 4 + 0;
-      e = &t.cu[(size_t)un.k * kCellUnitStride];
-      e[1 + e[0]++] = u * 4 + 1;
+  // Dispatch order of the units: by the number of axes on which the two
+  // cells differ (self, face, edge, corner neighbours), cell order inside.
+  // The expected pair count falls steeply along that sequence, so the heavy
+  // units start first and the light ones fill the end of a launch.  Slots
+  // were assigned above, so every atom's partial results (summed in slot
+  // order) do not depend on this order.
+  std::vector<int32_t> rank(t.nunits);   // creation index -> dispatch index
+  {
+    auto axes = [nc](int a, int b) {
+      const int da[3] = {a / (nc * nc), (a / nc) % nc, a % nc};
+      const int db[3] = {b / (nc * nc), (b / nc) % nc, b % nc};
+      return (da[0] != db[0]) + (da[1] != db[1]) + (da[2] != db[2]);
+    };
+    std::vector<Unit> by_type;
+    by_type.reserve(t.nunits);
+    for (int ty = 0; ty <= 3; ++ty)
+      for (int u = 0; u < t.nunits; ++u)
+        if (axes(t.units[u].h, t.units[u].k) == ty) {
+          rank[u] = (int32_t)by_type.size();
+          by_type.push_back(t.units[u]);
+        }
+    // per cell: the units it takes part in (each unique neighbour cell once),
+    // in creation order, encoded dispatch index * 4 + role (0: the cell is
+    // the unit's H, 1: its K, 2: both)
+    t.cu.assign((size_t)t.ncells * kCellUnitStride, 0);
+    for (int u = 0; u < t.nunits; ++u) {
+      const Unit& un = t.units[u];
+      const int32_t r = rank[u];
+      if (un.h == un.k) {
+        int32_t* e = &t.cu[(size_t)un.h * kCellUnitStride];
+        e[1 + e[0]++] = r * 4 + 2;
+      } else {
+        int32_t* e = &t.cu[(size_t)un.h * kCellUnitStride];
+        e[1 + e[0]++] = r * 4 + 0;
+        e = &t.cu[(size_t)un.k * kCellUnitStride];
+        e[1 + e[0]++] = r * 4 + 1;
+      }
     }
+    t.units.swap(by_type);
   }
   // cells grouped by octant (each axis split at ceil(nc/2)), lexicographic inside
   const int half = (nc + 1) / 2;
