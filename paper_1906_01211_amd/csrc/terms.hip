@@ -308,16 +308,13 @@ tk_status tk_evdw(tk_ctx* ctx, void* stream, const tk_system* sys, const tk_nbli
     TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
     return TK_OK;
   }
-  if (prec == TK_FP64) {
-    VdwPh<double> ph;
+  auto run = [&](auto ph) {
     ph.set(sys, form, radius_or_sigma, eps, cutoff, taper_on_frac, hal_delta, hal_gamma);
-    s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
-  } else {
-    VdwPh<float> ph;
-    ph.set(sys, form, radius_or_sigma, eps, cutoff, taper_on_frac, hal_delta, hal_gamma);
-    s = run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
-  }
-  return s;
+    return run_term(ctx, st, *P, ph, EpiForce{force}, energy, virial);
+  };
+  if (form == TK_VDW_HAL)
+    return prec == TK_FP64 ? run(VdwPh<double>{}) : run(VdwPh<float>{});
+  return prec == TK_FP64 ? run(VdwLjPh<double>{}) : run(VdwLjPh<float>{});
 }
 
 }  // extern "C"

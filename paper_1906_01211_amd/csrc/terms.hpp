@@ -246,7 +246,9 @@ template <class R>
 struct ChargePh {
   static constexpr int NF = 5, NA = 3, NS = 11;
   static constexpr const char* kName = "charge";
-  static constexpr int kWaves = 4;   // waves per unit (pairs.hpp launch_units)
+  // waves per unit (pairs.hpp launch_units): on the 12 A lists of the charge
+  // path two measured faster than four (332 against 352 us, 96,000 atoms)
+  static constexpr int kWaves = 2;
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
   __device__ void prologue(int tid, int nt) const { erfcx_stage<R>(tid, nt); }
@@ -837,6 +839,16 @@ struct VdwPh {
       for (int k = 0; k < 3; ++k) sc[1 + 3 * c + k] += dd[c] * f * dd[k];
     }
   }
+};
+
+// The 12-6 form.  It runs on the 12 A lists of the charge path, whose cells
+// hold about twice the atoms of the 9 A cells of the HAL term, and there two
+// waves per unit measured faster than four (269 against 297 us, 96,000
+// atoms), where HAL on the water box wants four (54 against 62 us).
+template <class R>
+struct VdwLjPh : VdwPh<R> {
+  static constexpr const char* kName = "vdw_lj";
+  static constexpr int kWaves = 2;
 };
 
 // Forces of a combination of polarization pair energies (the gradient of a
