@@ -460,7 +460,7 @@ template <class R>
 struct MpoleFieldPh {
   static constexpr int NF = 16, NA = 6, NS = 11;
   static constexpr const char* kName = "mpole_field";
-  static constexpr int kWaves = 1;   // one wave per unit: 96 us against 101 with two (water box)
+  static constexpr int kWaves = 1;   // one wave per unit: 73 us against 89 with two (water box)
   static constexpr const char* kTag = std::is_same<R, double>::value ? "_fp64" : "_fp32";
   __device__ bool skip() const { return false; }
   __device__ void prologue(int tid, int nt) const { erfcx_stage<R>(tid, nt); }
