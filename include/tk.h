@@ -131,6 +131,63 @@ tk_status tk_nblist_build(tk_ctx* ctx, void* stream, const tk_system* sys, doubl
                           int32_t plan_slot, int32_t* row_ptr, int32_t* col, int64_t cap,
                           int64_t* npairs);
 
+/* Sizes a neighbour-list build depends on, as bounds for
+ * tk_nblist_build_async (and as the sizes a build measured). */
+typedef struct {
+  int32_t max_occ;  /* atoms in the fullest cell */
+  int32_t max_row;  /* longest row of the half list */
+  int32_t max_nbhd; /* atoms in the fullest cell with its neighbour cells */
+  int32_t reserved; /* 0 */
+  int64_t windows;  /* candidate pairs: sum over cell pairs of |H| |K| */
+  int64_t npairs;   /* listed pairs */
+} tk_nblist_bounds;
+
+/*
+ * Bounds for later builds of plan slot `plan_slot`, from the sizes its last
+ * synchronous build (tk_nblist_build, tk_nblist_build_multi) measured: each
+ * scaled by 1 + headroom and rounded up (max_occ at most 512, the largest
+ * cell a build accepts).  Host call, no GPU work.  Errors: TK_E_ARG (NULL ctx or out,
+ * slot out of range, headroom < 0 or not finite), TK_E_PLAN (the slot holds
+ * no list from a synchronous build).
+ */
+tk_status tk_nblist_bounds_get(tk_ctx* ctx, int32_t plan_slot, double headroom,
+                               tk_nblist_bounds* out);
+
+/*
+ * The list of tk_nblist_build, queued on `stream` with no host
+ * synchronisation (the stream-ordered form of the list boundary: the list
+ * builders of the Rel profile, section "Hotspots").  Every buffer is sized
+ * from `bounds` (host memory; windows and max_occ size the enumeration,
+ * max_occ, max_row and max_nbhd the LDS of the kernels that use the list)
+ * and from `cap` (entries of col, and of the plan's pair array).
+ * Device outputs, written in stream order before the list's first user runs:
+ *   *npairs_dev (int64) the listed pairs; *status_dev (int32) TK_OK, or
+ *   TK_E_CAPACITY when a measured size exceeds its bound or npairs > cap
+ *   (then col and the plan hold no list: every kernel that uses the plan
+ *   skips its work, and a solve on it returns TK_E_CAPACITY), or the error
+ *   a synchronous build would return (TK_E_CAPACITY for a cell above 512
+ *   atoms);
+ *   report_dev (nullable, device tk_nblist_bounds): the sizes measured
+ *   (windows, max_occ and max_nbhd always; npairs and max_row only when the
+ *   enumeration fitted, else -1), for the caller's next bounds.
+ * row_ptr/col may be NULL (with cap >= 0 still bounding the plan's pairs).
+ * A later call taking this list (tk_nblist with npairs = -1 and this
+ * plan_slot) reads its status on the device.  Host-side argument errors as
+ * tk_nblist_build (bounds: TK_E_ARG if windows, max_occ, max_row or max_nbhd
+ * is < 1 or npairs < 0; max_occ above 512 acts as 512; TK_E_CAPACITY if the
+ * row sort's LDS for max_row exceeds the GPU's).  One system; the first build of a new cell grid also
+ * uploads that grid's cell tables (a synchronous copy, once per grid), and
+ * a buffer that must grow is reallocated after a device synchronisation.
+ * Builds of different plan slots may run concurrently on different streams;
+ * builds of one slot, and the calls that use it, must be ordered by the
+ * caller.
+ */
+tk_status tk_nblist_build_async(tk_ctx* ctx, void* stream, const tk_system* sys, double cutoff,
+                                int32_t plan_slot, const tk_nblist_bounds* bounds,
+                                int32_t* row_ptr, int32_t* col, int64_t cap,
+                                int64_t* npairs_dev, int32_t* status_dev,
+                                tk_nblist_bounds* report_dev);
+
 /*
  * Several neighbour lists of the same atoms (e.g. the Ewald and the vdW list
  * of a step, section "Hotspots": both list builders are on the profile),

@@ -566,7 +566,7 @@ void tk_destroy(tk_ctx* ctx) {
     freeb(p.perm); freeb(p.scell); freeb(p.cell_start); freeb(p.unit_off); freeb(p.unit_cnt);
     freeb(p.codes); freeb(p.us); freeb(p.slots); freeb(p.urec); freeb(p.sysd);
     freeb(p.cell_sys); freeb(p.bunits); freeb(p.bnslot); freeb(p.bcu); freeb(p.border);
-    freeb(p.tplp);
+    freeb(p.tplp); freeb(p.dstat);
   }
   for (auto& kv : ctx->tables) {
     freeb(kv.second.units_d);

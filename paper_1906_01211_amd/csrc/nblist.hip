@@ -422,6 +422,7 @@ struct CsrOut {
   const int32_t* slot_off;   // per (role, sorted atom): offset inside the owner's row
   const int32_t* row_ptr;
   int32_t* col;              // nullptr: no CSR
+  long col_cap;              // entries col holds
   long pstride;
   int occ;                   // dynamic LDS: 4 * occ ints
 };
@@ -435,18 +436,24 @@ __global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ wof
                                                  const int32_t* __restrict__ cstart,
                                                  const int32_t* __restrict__ unit_cnt,
                                                  const int32_t* __restrict__ cell_sys,
-                                                 UnitRec* __restrict__ rec, CsrOut csr) {
+                                                 UnitRec* __restrict__ rec, CsrOut csr,
+                                                 long code_cap,
+                                                 const int32_t* __restrict__ status) {
   __shared__ int rs[kPlanRegions], rd[kPlanRegions + 1];
   extern __shared__ int csr_lds[];   // pH pK | bH bK (occ each); cursors reuse nothing
   __shared__ int cH[kMaxCellAtoms], cK[kMaxCellAtoms];
   const int u = blockIdx.x, tid = threadIdx.x;
+  // a build past its bounds (status set) or codes past the array: nothing
+  // here is safe to follow, and the plan's users skip it
+  if (*status != 0 || doff[gridDim.x] > code_cap) return;
   const Unit un = units[u];
   const int hs = cstart[un.h], nh = cstart[un.h + 1] - hs;
   const int ks = cstart[un.k], nk = cstart[un.k + 1] - ks;
   if (tid == 64)   // a lane of the second wave: the record, beside wave 0's prefix
     rec[u] = UnitRec{hs, nh, ks, nk, un.slot_h, un.slot_k, cell_sys ? cell_sys[un.h] : 0,
                      unit_cnt[u], doff[u]};
-  const bool fill = csr.col != nullptr && nh <= csr.occ && nk <= csr.occ;
+  const bool fill = csr.col != nullptr && nh <= csr.occ && nk <= csr.occ &&
+                    doff[gridDim.x] <= csr.col_cap;
   int* pH = csr_lds;
   int* pK = pH + csr.occ;
   int* bH = pK + csr.occ;
@@ -636,12 +643,56 @@ __global__ __launch_bounds__(256) void k_cand_nbhd(int nunits, int ncells, int n
 // info is left zeroed for the next build.
 __global__ void k_readback(int32_t* __restrict__ info, const int32_t* __restrict__ rp_end,
                            const int64_t* __restrict__ off_end, const int64_t* __restrict__ pairs,
-                           int32_t* __restrict__ host) {
+                           int32_t* __restrict__ host, int32_t* __restrict__ dstat) {
+  dstat[0] = 0;   // the host checks this build before any kernel uses the plan
   for (int k = 0; k < 6; ++k) host[k] = info[k];
   for (int k = 0; k < 8; ++k) info[k] = 0;
   host[3] = (int32_t)*pairs;   // listed pairs, summed over the units
   host[6] = *rp_end;
   *(int64_t*)(host + 8) = *off_end;
+}
+
+// Stream-ordered builds: the system table through a kernel argument (no
+// host staging buffer that a later call could overwrite before the copy
+// runs), the status words cleared, and the outcome checked against the
+// caller's bounds on the device.
+struct SysPair {
+  SysDev s[2];
+};
+__global__ void k_put_sys(SysPair v, SysDev* __restrict__ out, int32_t* __restrict__ info) {
+  if (threadIdx.x < 2) out[threadIdx.x] = v.s[threadIdx.x];
+  if (threadIdx.x < 8) info[threadIdx.x] = 0;
+}
+
+struct AsyncBounds {
+  int32_t max_occ, max_row, max_nbhd;
+  int64_t windows, cap;
+};
+// info: [0] error, [1] max occupancy, [2] max row, [4] enumeration did not
+// fit (windows or staging bound), [5] max neighbourhood.
+__global__ void k_build_status(const int32_t* __restrict__ info, const int32_t* __restrict__ rp_end,
+                               const int64_t* __restrict__ win_end,
+                               const int64_t* __restrict__ pairs, AsyncBounds b,
+                               int64_t* __restrict__ npairs_dev, int32_t* __restrict__ status_dev,
+                               int32_t* __restrict__ dstat, tk_nblist_bounds* __restrict__ report) {
+  const bool fit = info[4] == 0;   // else the unit counts (and rows) were not formed
+  const int64_t np = *pairs;
+  int32_t st = info[0];
+  if (st == 0 && (!fit || info[1] > b.max_occ || info[5] > b.max_nbhd || *win_end > b.windows ||
+                  np > b.cap || info[2] > b.max_row))
+    st = TK_E_CAPACITY;
+  if (st == 0 && (int64_t)*rp_end != np) st = TK_E_HIP;   // rows and units disagree
+  *npairs_dev = fit ? np : -1;
+  *status_dev = st;
+  dstat[0] = st;
+  if (report) {
+    report->max_occ = info[1];
+    report->max_row = fit ? info[2] : -1;
+    report->max_nbhd = info[5];
+    report->reserved = 0;
+    report->windows = *win_end;
+    report->npairs = fit ? np : -1;
+  }
 }
 
 // One wave per CSR row, blockDim.x / 64 rows per workgroup (up to
@@ -652,8 +703,10 @@ constexpr int kRowsPerBlock = 4;
 __global__ __launch_bounds__(64 * kRowsPerBlock) void k_rowsort(int n,
                                                                 const int32_t* __restrict__ row_ptr,
                                                                 int32_t* __restrict__ col,
-                                                                int max_row) {
+                                                                int max_row,
+                                                                const int32_t* __restrict__ status) {
   extern __shared__ int lds[];
+  if (*status != 0) return;   // the build failed: row_ptr and col are not a list
   const int w = threadIdx.x >> 6;
   const int i = blockIdx.x * (blockDim.x >> 6) + w;
   const int lane = lane_id();
@@ -668,7 +721,8 @@ __global__ __launch_bounds__(64 * kRowsPerBlock) void k_rowsort(int n,
     m = row_ptr[i + 1] - start;
   }
   // every wave takes part in the barriers; rows of 0 or 1 entries do no work
-  if (m <= 1) m = 0;
+  // (nor a row longer than the LDS bound, which the build reports)
+  if (m <= 1 || m > max_row) m = 0;
   int jmin = 0x7fffffff, jmax = -1;
   for (int e = lane; e < m; e += 64) {
     const int v = col[start + e];
@@ -770,6 +824,13 @@ struct BuildJob {
   int64_t cap = 0;
   int64_t* npairs_out = nullptr;
   hipStream_t st = nullptr;
+  // stream-ordered form (tk_nblist_build_async): sizes from the caller's
+  // bounds, outcome to device memory, no host synchronisation
+  bool async = false;
+  tk_nblist_bounds bd{};
+  int64_t* npairs_dev = nullptr;
+  int32_t* status_dev = nullptr;
+  tk_nblist_bounds* report_dev = nullptr;
   // state between the phases
   Plan* P = nullptr;
   std::vector<SysDev> sd;
@@ -881,10 +942,20 @@ static tk_status enqueue_enumeration(tk_ctx* ctx, BuildJob& J) {
     TK_HIP(hipMemsetAsync(J.woff, 0, sizeof(int64_t) * (nunits + 1), st));
     TK_HIP(hipMemsetAsync(J.rp, 0, sizeof(int32_t), st));
   }
+  if (J.async) {
+    const AsyncBounds b{std::min(J.bd.max_occ, kMaxCellAtoms), J.bd.max_row, J.bd.max_nbhd,
+                        J.bd.windows, J.cap};
+    k_build_status<<<1, 1, 0, st>>>((const int32_t*)J.info, J.rp + n,
+                                    (const int64_t*)J.woff + nunits,
+                                    (const int64_t*)P.unit_off.p + nunits, b, J.npairs_dev,
+                                    J.status_dev, (int32_t*)P.dstat.p, J.report_dev);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+  }
   // one readback: status, max occupancy, max row, pairs, window overflow,
   // max neighbourhood, list total
   k_readback<<<1, 1, 0, st>>>((int32_t*)J.info, J.rp + n, (int64_t*)J.woff + nunits,
-                              (int64_t*)P.unit_off.p + nunits, J.hd);
+                              (int64_t*)P.unit_off.p + nunits, J.hd, (int32_t*)P.dstat.p);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }
@@ -904,7 +975,8 @@ static tk_status build_begin(tk_ctx* ctx, BuildJob& J, char* hb, char* hdb) {
       (s = ensure(ctx, P.unit_off, sizeof(int64_t) * (nunits + 1))) ||
       (s = ensure(ctx, P.unit_cnt, sizeof(int32_t) * nunits)) ||
       (s = ensure(ctx, P.us, sizeof(uint4) * nn)) ||
-      (s = ensure(ctx, P.slots, sizeof(int32_t) * kMaxSlots * J.pstride)))
+      (s = ensure(ctx, P.slots, sizeof(int32_t) * kMaxSlots * J.pstride)) ||
+      (s = ensure(ctx, P.dstat, 2 * sizeof(int32_t))))
     return s;
   const void* sysd_was = P.sysd.p;
   if ((s = ensure(ctx, P.sysd, sizeof(SysDev) * (nsys + 1)))) return s;
@@ -929,16 +1001,24 @@ static tk_status build_begin(tk_ctx* ctx, BuildJob& J, char* hb, char* hdb) {
                    &J.regcnt)) ||
       (s = scratch(ctx, J.nm("nb_nfilt").c_str(), sizeof(int2) * (size_t)nunits, &J.nfilt)))
     return s;
-  // pinned: this build's readback slot, then its staging region
-  J.h = (int32_t*)(hb + 64 * J.job);
-  J.hd = (int32_t*)(hdb + 64 * J.job);
-  char* stage = J.stage;
   const size_t sys_bytes = sizeof(SysDev) * (nsys + 1);
+  if (J.async) {   // one system (checked by the caller): table and status words by one kernel
+    SysPair v;
+    v.s[0] = sd[0];
+    v.s[1] = sd[1];
+    k_put_sys<<<1, 64, 0, st>>>(v, (SysDev*)P.sysd.p, (int32_t*)J.info);
+    P.h_sys = sd;
+  }
+  // pinned (synchronous builds): this build's readback slot, then its
+  // staging region
+  J.h = J.async ? nullptr : (int32_t*)(hb + 64 * J.job);
+  J.hd = J.async ? nullptr : (int32_t*)(hdb + 64 * J.job);
+  char* stage = J.stage;
   // the previous readback and staging of this context have been consumed
   // (every group synchronises before it returns).  The system table is
   // uploaded only when it differs from the plan's copy.
-  if (P.sysd.p != sysd_was || P.h_sys.size() != sd.size() ||
-      std::memcmp(P.h_sys.data(), sd.data(), sys_bytes) != 0) {
+  if (!J.async && (P.sysd.p != sysd_was || P.h_sys.size() != sd.size() ||
+                   std::memcmp(P.h_sys.data(), sd.data(), sys_bytes) != 0)) {
     std::memcpy(stage, sd.data(), sys_bytes);
     TK_HIP(hipMemcpyAsync(P.sysd.p, stage, sys_bytes, hipMemcpyHostToDevice, st));
     P.h_sys = sd;
@@ -977,9 +1057,12 @@ static tk_status build_begin(tk_ctx* ctx, BuildJob& J, char* hb, char* hdb) {
     J.order = (const int32_t*)P.border.p;
     J.cell_sys = (const int32_t*)P.cell_sys.p;
   }
-  // status words: zero after every completed build (the readback clears them)
-  if (!ctx->nb_info_zero[J.job]) TK_HIP(hipMemsetAsync(J.info, 0, sizeof(int32_t) * 8, st));
-  ctx->nb_info_zero[J.job] = false;
+  // status words: zero after every completed build (the readback clears them;
+  // a stream-ordered build clears them with its system table)
+  if (!J.async) {
+    if (!ctx->nb_info_zero[J.job]) TK_HIP(hipMemsetAsync(J.info, 0, sizeof(int32_t) * 8, st));
+    ctx->nb_info_zero[J.job] = false;
+  }
   const int32_t* cstart = (const int32_t*)P.cell_start.p;
   J.rp = J.row_ptr ? J.row_ptr : (int32_t*)J.rptr;
   int32_t* info = (int32_t*)J.info;
@@ -1040,6 +1123,7 @@ static tk_status build_begin(tk_ctx* ctx, BuildJob& J, char* hb, char* hdb) {
   }
   int occ_cap = (int)std::ceil(3.0 * max_mean);
   J.occ_cap = occ_cap < 64 ? 64 : occ_cap > kMaxCellAtoms ? kMaxCellAtoms : occ_cap;
+  if (J.async) J.occ_cap = std::min(J.bd.max_occ, kMaxCellAtoms);   // the caller's bound
   // waves per unit of the enumeration: more for larger cells
   J.plan_waves = max_mean > 96.0 ? 4 : max_mean > 48.0 ? 2 : 1;
   return enqueue_enumeration(ctx, J);
@@ -1090,11 +1174,12 @@ static tk_status build_finish(tk_ctx* ctx, BuildJob& J) {
     // the dense codes, the unit records and (when asked for) the CSR entries
     ProfScope ps(ctx, st, "nblist_compact");
     CsrOut csr{(const int32_t*)P.perm.p, (const int32_t*)P.slots.p, J.rp,
-               J.row_ptr && list_pairs > 0 ? J.col : nullptr, J.pstride, occ};
+               J.row_ptr && list_pairs > 0 ? J.col : nullptr, (long)J.cap, J.pstride, occ};
     k_compact<<<nunits, 256, sizeof(int) * 4 * (size_t)occ, st>>>(
         (const int64_t*)J.woff, (const uint32_t*)J.wb->p, (const int64_t*)P.unit_off.p,
         (const int32_t*)J.regcnt, (const int2*)J.nfilt, J.plan_waves, (uint32_t*)P.codes.p,
-        J.units, cstart, (const int32_t*)P.unit_cnt.p, J.cell_sys, (UnitRec*)P.urec.p, csr);
+        J.units, cstart, (const int32_t*)P.unit_cnt.p, J.cell_sys, (UnitRec*)P.urec.p, csr,
+        (long)(P.codes.bytes / sizeof(uint32_t)), (const int32_t*)P.dstat.p);
   }
   if (J.row_ptr) {
     const int nb = max_row < kBuckets ? max_row : kBuckets;
@@ -1107,7 +1192,8 @@ static tk_status build_finish(tk_ctx* ctx, BuildJob& J) {
     if (n > 0 && list_pairs > 0) {
       {
         ProfScope ps(ctx, st, "nblist_rowsort");
-        k_rowsort<<<ceil_div(n, rpb), 64 * rpb, lds, st>>>(n, J.rp, J.col, max_row);
+        k_rowsort<<<ceil_div(n, rpb), 64 * rpb, lds, st>>>(n, J.rp, J.col, max_row,
+                                                           (const int32_t*)P.dstat.p);
       }
     }
   }
@@ -1124,6 +1210,8 @@ static tk_status build_finish(tk_ctx* ctx, BuildJob& J) {
   P.max_row = max_row;
   P.max_nbhd = h[5];
   P.npairs = list_pairs;
+  P.windows = *(int64_t*)(h + 8);
+  P.measured = true;
   P.units_p = J.units;
   P.nslot_p = J.nslot;
   P.cu_p = J.cu;
@@ -1169,6 +1257,63 @@ static tk_status build_group(tk_ctx* ctx, BuildJob* jobs, int nj) {
   if (s) return s;
   for (int k = 0; k < nj; ++k)
     if ((s = build_finish(ctx, jobs[k]))) return s;
+  return TK_OK;
+}
+
+// Stream-ordered build, after the enumeration has been queued: the dense
+// codes, unit records and CSR sized from the caller's capacity and bounds.
+// The kernels check the device status that k_build_status wrote (a build
+// past its bounds writes nothing), so nothing here waits for the host.
+static tk_status build_finish_async(tk_ctx* ctx, BuildJob& J) {
+  Plan& P = *J.P;
+  const hipStream_t st = J.st;
+  const int n = J.n, nunits = J.nunits;
+  tk_status s;
+  const int occ = std::max(1, std::min(J.bd.max_occ, kMaxCellAtoms));
+  const int max_row = J.bd.max_row;
+  const int nb = max_row < kBuckets ? max_row : kBuckets;
+  const size_t lds1 = sizeof(int) * (2 * (size_t)max_row + 2 * (size_t)nb);
+  if (J.row_ptr && lds1 > kMaxLds) return TK_E_CAPACITY;
+  if ((s = ensure(ctx, P.codes, sizeof(uint32_t) * (size_t)std::max<int64_t>(J.cap, 1))) ||
+      (s = ensure(ctx, P.urec, sizeof(UnitRec) * (size_t)(nunits > 0 ? nunits : 1))))
+    return s;
+  const int32_t* cstart = (const int32_t*)P.cell_start.p;
+  if (n > 0) {
+    ProfScope ps(ctx, st, "nblist_compact");
+    CsrOut csr{(const int32_t*)P.perm.p, (const int32_t*)P.slots.p, J.rp, J.row_ptr ? J.col : nullptr,
+               (long)J.cap, J.pstride, occ};
+    k_compact<<<nunits, 256, sizeof(int) * 4 * (size_t)occ, st>>>(
+        (const int64_t*)J.woff, (const uint32_t*)J.wb->p, (const int64_t*)P.unit_off.p,
+        (const int32_t*)J.regcnt, (const int2*)J.nfilt, J.plan_waves, (uint32_t*)P.codes.p,
+        J.units, cstart, (const int32_t*)P.unit_cnt.p, J.cell_sys, (UnitRec*)P.urec.p, csr,
+        (long)(P.codes.bytes / sizeof(uint32_t)), (const int32_t*)P.dstat.p);
+  }
+  if (J.row_ptr && n > 0) {
+    const int rpb = lds1 * kRowsPerBlock <= 65536 ? kRowsPerBlock : 1;
+    const size_t lds = lds1 * rpb;
+    if (lds > 65536 && (s = rowsort_attribute(lds))) return s;
+    ProfScope ps(ctx, st, "nblist_rowsort");
+    k_rowsort<<<ceil_div(n, rpb), 64 * rpb, lds, st>>>(n, J.rp, J.col, max_row,
+                                                       (const int32_t*)P.dstat.p);
+  }
+  TK_HIP(hipGetLastError());
+  P.valid = true;
+  P.n = n;
+  P.nsys = J.nsys;
+  P.box = J.spec.box[0];
+  P.cutoff = J.spec.cutoff[0];
+  P.nc = J.sd[0].nc;
+  P.ncells = J.ncells;
+  P.nunits = nunits;
+  P.max_occ = occ;
+  P.max_row = max_row;
+  P.max_nbhd = J.bd.max_nbhd;
+  P.npairs = -1;
+  P.measured = false;
+  P.units_p = J.units;
+  P.nslot_p = J.nslot;
+  P.cu_p = J.cu;
+  P.order_p = J.order;
   return TK_OK;
 }
 
@@ -1244,7 +1389,77 @@ static tk_status nblist_build_multi_impl(tk_ctx* ctx, int nl, void* const* strea
   return build_group(ctx, J, nl);
 }
 
+static tk_status nblist_build_async_impl(tk_ctx* ctx, hipStream_t st, const tk_system* sys,
+                                         double cutoff, int slot, const tk_nblist_bounds* bd,
+                                         int32_t* row_ptr, int32_t* col, int64_t cap,
+                                         int64_t* npairs_dev, int32_t* status_dev,
+                                         tk_nblist_bounds* report) {
+  if (!bd || !npairs_dev || !status_dev || cap < 0) return TK_E_ARG;
+  if (bd->windows < 1 || bd->max_occ < 1 || bd->max_row < 1 || bd->max_nbhd < 1 || bd->npairs < 0)
+    return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (!(cutoff > 0.0) || !std::isfinite(cutoff)) return TK_E_ARG;
+  if (slot < 0 || slot >= TK_MAX_PLANS) return TK_E_ARG;
+  const int32_t atom0[2] = {0, sys->n};
+  int64_t host_np = 0;   // build_check's host count (unused here)
+  BuildJob J;
+  J.slot = slot;
+  J.job = kMaxBuildJobs + slot;   // scratch of its own per slot: slots build concurrently
+  J.n = sys->n;
+  J.xyz = sys->xyz;
+  J.spec = PlanSpec{1, atom0, &sys->box, &cutoff};
+  J.row_ptr = row_ptr;
+  J.col = col;
+  J.cap = cap;
+  J.npairs_out = &host_np;
+  J.st = st;
+  J.async = true;
+  J.bd = *bd;
+  J.npairs_dev = npairs_dev;
+  J.status_dev = status_dev;
+  J.report_dev = report;
+  if ((s = build_check(ctx, J))) return s;
+  J.est = (double)bd->windows;   // the candidate windows: the caller's bound
+  if ((s = build_begin(ctx, J, nullptr, nullptr))) return s;
+  return build_finish_async(ctx, J);
+}
+
+static tk_status nblist_bounds_get_impl(tk_ctx* ctx, int slot, double headroom,
+                                        tk_nblist_bounds* out) {
+  if (!out || slot < 0 || slot >= TK_MAX_PLANS || !(headroom >= 0.0) || !std::isfinite(headroom))
+    return TK_E_ARG;
+  const Plan& P = ctx->plans[slot];
+  if (!P.valid || !P.measured || P.nsys != 1) return TK_E_PLAN;
+  const double f = 1.0 + headroom;
+  auto up32 = [f](int32_t v) { return (int32_t)std::min(std::ceil(f * std::max(v, 1)), 2.0e9); };
+  auto up64 = [f](int64_t v) { return (int64_t)std::ceil(f * (double)std::max<int64_t>(v, 1)); };
+  out->max_occ = std::min(up32(P.max_occ), kMaxCellAtoms);
+  out->max_row = up32(P.max_row);
+  out->max_nbhd = up32(P.max_nbhd);
+  out->reserved = 0;
+  out->windows = up64(P.windows);
+  out->npairs = up64(P.npairs);
+  return TK_OK;
+}
+
 }  // namespace tk
+
+extern "C" tk_status tk_nblist_bounds_get(tk_ctx* ctx, int32_t plan_slot, double headroom,
+                                          tk_nblist_bounds* out) {
+  if (!ctx) return TK_E_ARG;
+  return tk::nblist_bounds_get_impl(ctx, plan_slot, headroom, out);
+}
+
+extern "C" tk_status tk_nblist_build_async(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                           double cutoff, int32_t plan_slot,
+                                           const tk_nblist_bounds* bounds, int32_t* row_ptr,
+                                           int32_t* col, int64_t cap, int64_t* npairs_dev,
+                                           int32_t* status_dev, tk_nblist_bounds* report_dev) {
+  if (!ctx) return TK_E_ARG;
+  return tk::nblist_build_async_impl(ctx, (hipStream_t)stream, sys, cutoff, plan_slot, bounds,
+                                     row_ptr, col, cap, npairs_dev, status_dev, report_dev);
+}
 
 extern "C" tk_status tk_nblist_build(tk_ctx* ctx, void* stream, const tk_system* sys, double cutoff,
                                      int32_t plan_slot, int32_t* row_ptr, int32_t* col, int64_t cap,

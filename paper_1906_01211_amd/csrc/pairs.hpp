@@ -51,6 +51,7 @@ __global__ __launch_bounds__(64 * W) void k_units(PlanView pv, Ph ph, double* __
   extern __shared__ double lds[];
   __shared__ double red[W * NS1];
   if (ph.skip()) return;   // solver finished: nothing to do
+  if (*pv.status != 0) return;   // the list's build failed: its unit records are not valid
   const int u = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const UnitRec un = pv.urec[u];   // one read: cells, slots, system, pairs
@@ -58,6 +59,7 @@ __global__ __launch_bounds__(64 * W) void k_units(PlanView pv, Ph ph, double* __
   const int hs = un.hs, nh = un.nh;
   const int ks = un.ks, nk = un.nk;
   const int cap = pv.max_occ;
+  if (nh > cap || nk > cap) return;   // past the staging bound (a failed build reports it)
   ph.prologue(tid, NT);
   double* LH = lds;
   double* LK = LH + Ph::NF * cap;

@@ -44,7 +44,7 @@ struct PcgState {
   int32_t iters, done, npol, maxiter;
 };
 // done: 0 running, 1 converged (or not part of this solve), 2 iteration limit,
-// 3 breakdown
+// 3 breakdown, 4 the list's build failed (nothing runs)
 
 // Workgroup sums of N values: wave shuffles, then the waves in order.  Every
 // thread gets the sums.  sh holds 16 entries per value.
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(64) void k_cs_init(PlanView pv, const double* __res
   s0.npol = (int)np[0];
   s0.tol = tol;
   s0.maxiter = maxiter;
-  s0.done = active && !active[sy] ? 1 : 0;
+  s0.done = *pv.status != 0 ? 4 : active && !active[sy] ? 1 : 0;
   st[blockIdx.x] = s0;
 }
 
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   const PlanView& pv = A.pv;
   const int ncells = pv.ncells;
   const int pos = xcd_pos(ncells, blockIdx.x);
-  if (pos < 0) return;
+  if (pos < 0 || *pv.status != 0) return;   // no cell here, or the list's build failed
   // round 1: cell table, state, partials
   const MvHdr hd = A.hdr[pos];
   if (tid < kEntRow) {
@@ -366,6 +366,7 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   const int own0 = kStage ? e_off[hd.self_j] : 0;
   const int total = kStage ? e_off[ne] : nown;
   const int T = e_pre[ne];
+  if (total > SC || nown > OC) return;   // past the plan's LDS bounds (a failed build reports it)
   // round 2: staging loads, the first pair batch, own alpha and rhs
   int src[kMvStageBatch];
   double f[kMvStageBatch][SD];
@@ -1269,6 +1270,7 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                       : S.run<float>(S.b, tol_debye, maxiter, hint, true, nullptr);
   if (s) return s;
   int most = 0;
+  bool failed_list = false;
   std::vector<int> done(nsys * nv);
   for (int k = 0; k < nsys * nv; ++k) {
     const PcgState& h = S.host[k];
@@ -1277,10 +1279,16 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
     info[k].iters = h.iters;
     info[k].rms_debye = h.rms;
     info[k].converged = h.done == 1;
-    info[k].status = h.done == 1 ? TK_OK : h.done == 3 ? TK_E_BREAKDOWN : TK_E_NOCONV;
+    info[k].status = h.done == 1   ? TK_OK
+                     : h.done == 3 ? TK_E_BREAKDOWN
+                     : h.done == 4 ? TK_E_CAPACITY
+                                   : TK_E_NOCONV;
     info[k].rms_true_debye = h.rms_true;
     info[k].epol = h.epol;
+    failed_list |= h.done == 4;
   }
+  // a list whose build went past its bounds: nothing was solved
+  if (failed_list) return TK_E_CAPACITY;
   hint = most;
   if (prec == TK_MIXED) {
     // FP64-residual refinement of the systems whose true residual is above

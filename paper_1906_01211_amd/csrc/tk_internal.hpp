@@ -76,6 +76,10 @@ struct PlanView {
   const SysDev* sys;          // [nsys]
   const int32_t* cell_sys;    // [ncells] system of each cell; nullptr when nsys == 1
   const UnitRec* urec;        // [nunits]
+  // build outcome on the device: 0 when the plan is whole.  A build queued
+  // without a host synchronisation (tk_nblist_build_async) can exceed the
+  // caller's bounds; kernels that index plan tables skip their work then.
+  const int32_t* status;
 };
 
 // Workgroups are dispatched to the 8 XCDs round-robin.  Per-cell kernels
@@ -111,7 +115,9 @@ struct Plan {
   double box = 0.0, cutoff = 0.0;
   int32_t nc = 0, ncells = 0, nunits = 0, max_occ = 0, max_row = 0;
   int32_t max_nbhd = 0;   // max over cells of the atoms in the cell's neighbour cells (itself included)
-  int64_t npairs = 0;
+  int64_t npairs = 0;      // -1: built by tk_nblist_build_async (the count is on the device)
+  int64_t windows = 0;     // candidate pairs of the last synchronous build (sum |H| |K|)
+  bool measured = false;   // the sizes above were measured by a synchronous build
   DevBuf perm, scell, cell_start, unit_off, unit_cnt, codes, us, slots, urec;
   const Unit* units_p = nullptr;       // device cell tables (shared by plans with the same
   const int32_t* nslot_p = nullptr;    // nc for one system; built per batch otherwise)
@@ -120,6 +126,7 @@ struct Plan {
   int32_t nsys = 1;
   std::vector<SysDev> h_sys;           // host copy of sysd (as uploaded), with a final entry holding the totals
   DevBuf sysd, cell_sys, bunits, bnslot, bcu, border, tplp;
+  DevBuf dstat;                        // int32 [2]: build outcome (PlanView::status), spare
   PlanView view() const {
     PlanView v;
     v.nsys = nsys;
@@ -133,6 +140,7 @@ struct Plan {
     v.codes = (const uint32_t*)codes.p;
     v.cell_units = cu_p;
     v.cell_order = order_p;
+    v.status = (const int32_t*)dstat.p;
     v.urec = (const UnitRec*)urec.p;
     return v;
   }

@@ -31,6 +31,14 @@ class NbList(C.Structure):
                 ("cutoff", C.c_double), ("plan", C.c_int32)]
 
 
+class NbBounds(C.Structure):
+    _fields_ = [("max_occ", C.c_int32), ("max_row", C.c_int32), ("max_nbhd", C.c_int32),
+                ("reserved", C.c_int32), ("windows", C.c_int64), ("npairs", C.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
 class PcgInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("refinements", C.c_int32),
                 ("converged", C.c_int32), ("rms_debye", C.c_double),
@@ -98,6 +106,9 @@ _SIGS = {
     "tk_nblist_build": [_vp, _vp, C.POINTER(System), _d, _i32, _vp, _vp, _i64, C.POINTER(_i64)],
     "tk_nblist_build_multi": [_vp, _i32, _vp, C.POINTER(System), _vp, _vp, _vp, _vp, _vp,
                               C.POINTER(_i64)],
+    "tk_nblist_bounds_get": [_vp, _i32, _d, C.POINTER(NbBounds)],
+    "tk_nblist_build_async": [_vp, _vp, C.POINTER(System), _d, _i32, C.POINTER(NbBounds), _vp,
+                              _vp, _i64, _vp, _vp, _vp],
     "tk_empole_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _d, _d, C.c_int, _vp,
                        _vp, _vp],
     "tk_echarge_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _d, _d, C.c_int, _vp,
@@ -312,6 +323,34 @@ class Context:
             return [ListRef(rps[i], None if cols[i] is None else cols[i][: npairs[i]],
                             int(npairs[i]), float(cutoffs[i]), int(plan_slots[i]))
                     for i in range(k)]
+
+    def nblist_bounds(self, plan_slot, headroom=0.1):
+        """Bounds for stream-ordered builds of a slot, from its last synchronous build."""
+        b = NbBounds()
+        _check(load().tk_nblist_bounds_get(self._h, int(plan_slot), float(headroom), C.byref(b)),
+               "tk_nblist_bounds_get")
+        return b
+
+    def nblist_async(self, sysref, cutoff, plan_slot, bounds, cap=None, want_csr=True,
+                     stream=None, report=True):
+        """The list queued on `stream` (default: the current one) with no host
+        synchronisation (tk_nblist_build_async); its pair count and status
+        stay on the device (AsyncListRef)."""
+        n = sysref.n
+        if cap is None:
+            cap = int(bounds.npairs)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.stream(st):
+            row_ptr = torch.empty(n + 1, dtype=torch.int32, device=self.device) if want_csr else None
+            col = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device) if want_csr else None
+            npd = torch.empty(1, dtype=torch.int64, device=self.device)
+            std = torch.empty(1, dtype=torch.int32, device=self.device)
+            rep = torch.empty(4, dtype=torch.int64, device=self.device) if report else None
+        _check(load().tk_nblist_build_async(self._h, st.cuda_stream, C.byref(sysref.c), cutoff,
+                                            int(plan_slot), C.byref(bounds), _ptr(row_ptr),
+                                            _ptr(col), int(cap), _ptr(npd), _ptr(std), _ptr(rep)),
+               "tk_nblist_build_async")
+        return AsyncListRef(row_ptr, col, -1, float(cutoff), int(plan_slot), npd, std, rep)
 
     # -- pair terms ------------------------------------------------------------
     def empole_real(self, sysref, lst, mpole, beta, cutoff, prec=FP64):
@@ -725,3 +764,31 @@ class ListRef:
         self.c = NbList(None if self.row_ptr is None else self.row_ptr.data_ptr(),
                         None if self.col is None else self.col.data_ptr(), self.npairs,
                         self.cutoff, self.plan)
+
+
+@dataclass
+class AsyncListRef(ListRef):
+    """A list from tk_nblist_build_async: npairs is -1 on the host; the count,
+    the status and the measured sizes are device tensors (reading them
+    synchronises)."""
+    npairs_dev: torch.Tensor = None
+    status_dev: torch.Tensor = None
+    report_dev: torch.Tensor = None
+
+    def status(self):
+        return int(self.status_dev.item())
+
+    def count(self):
+        return int(self.npairs_dev.item())
+
+    def report(self):
+        r = self.report_dev.cpu()
+        i32 = r[:2].view(torch.int32)
+        return {"max_occ": int(i32[0]), "max_row": int(i32[1]), "max_nbhd": int(i32[2]),
+                "windows": int(r[2]), "npairs": int(r[3])}
+
+    def resolved(self):
+        """The same list with its pair count read back (col cut to it)."""
+        m = self.count()
+        return ListRef(self.row_ptr, None if self.col is None else self.col[:m], m, self.cutoff,
+                       self.plan)
