@@ -86,7 +86,9 @@ typedef struct {
 /* A neighbour list as returned by tk_nblist_build.
  * row_ptr: device [n+1]; col: device [npairs]; row i holds every j > i with
  * |r_ij| <= cutoff (integer test below), ascending.  `plan` names the context
- * slot that holds the same pair set in the cell-pair order the kernels use. */
+ * slot that holds the same pair set in the cell-pair order the kernels use.
+ * A list from tk_nblist_build_async has npairs = -1 (its count is on the
+ * device). */
 typedef struct {
   const int32_t* row_ptr;
   const int32_t* col;
@@ -97,7 +99,8 @@ typedef struct {
 
 /* Outcome of a polarization solve (host memory). */
 typedef struct {
-  int32_t status;      /* TK_OK, TK_E_NOCONV or TK_E_BREAKDOWN */
+  int32_t status;      /* TK_OK, TK_E_NOCONV, TK_E_BREAKDOWN, or TK_E_CAPACITY (the
+                          list's stream-ordered build failed: nothing solved) */
   int32_t iters;       /* PCG updates performed (mat-vecs after the initial residual) */
   int32_t refinements; /* FP64 refinement rounds (TK_MIXED only) */
   int32_t converged;   /* 1 if the stopping rule was met (TK_MIXED: the FP64 check) */
