@@ -181,3 +181,25 @@ def test_async_list_argument_errors(ctx, tk):
         ctx.nblist_bounds(0, -1.0)
     with pytest.raises(tk.TkError):
         ctx.nblist_async(sysr, R7, plan_slot=1, bounds=b, cap=-1)
+
+
+def test_async_plan_only_and_empty(ctx, tk):
+    import torch
+    w = water("water216")
+    sysr = ctx.system(w.xyz, w.box, w.molid)
+    s9 = ctx.nblist(sysr, R9, plan_slot=2)
+    b = ctx.nblist_bounds(2, 0.1)
+    # the plan alone (no CSR): the pair count still bounded by cap
+    a9 = ctx.nblist_async(sysr, R9, plan_slot=3, bounds=b, want_csr=False)
+    assert a9.status() == 0 and a9.count() == s9.npairs
+    T = lambda a: torch.as_tensor(a, device=ctx.device)
+    rad, eps = T(w.vdw_rad), T(w.vdw_eps)
+    out = [ctx.evdw(sysr, lst, tk.VDW_HAL, rad, eps, S["rc_vdw"], S["taper_frac"], S["dhal"],
+                    S["ghal"]) for lst in (s9, a9)]
+    assert float(out[0][0]) == float(out[1][0])
+    assert np.array_equal(np_(out[0][1]), np_(out[1][1]))
+    # a system with no atoms
+    e = ctx.system(np.zeros((0, 3)), w.box, np.zeros(0, dtype=np.int32))
+    a0 = ctx.nblist_async(e, R9, plan_slot=4, bounds=b)
+    assert a0.status() == 0 and a0.count() == 0
+    assert np_(a0.row_ptr).tolist() == [0]
