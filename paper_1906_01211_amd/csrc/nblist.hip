@@ -696,10 +696,12 @@ __global__ void k_build_status(const int32_t* __restrict__ info, const int32_t* 
 }
 
 // One wave per CSR row, blockDim.x / 64 rows per workgroup (up to
-// kRowsPerBlock: tiny one-wave workgroups are dispatch-bound): order the row
-// by j (monotone buckets over [jmin, jmax], then rank inside a bucket).  LDS
-// per wave: A[max_row], G[max_row], cnt, off.
-constexpr int kRowsPerBlock = 4;
+// kRowsPerBlock): order the row by j (monotone buckets over [jmin, jmax],
+// then rank inside a bucket).  LDS per wave: A[max_row], G[max_row], cnt,
+// off.  One row per workgroup measured fastest at every list size (7, 9 and
+// 12 A rows: 22.7, 32.5 and 440 us against 23.2-24.0, 34.1 and 479 us with
+// four rows, whose waves wait at each barrier for the block's longest row).
+constexpr int kRowsPerBlock = 1;
 __global__ __launch_bounds__(64 * kRowsPerBlock) void k_rowsort(int n,
                                                                 const int32_t* __restrict__ row_ptr,
                                                                 int32_t* __restrict__ col,
