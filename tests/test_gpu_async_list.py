@@ -203,3 +203,43 @@ def test_async_plan_only_and_empty(ctx, tk):
     a0 = ctx.nblist_async(e, R9, plan_slot=4, bounds=b)
     assert a0.status() == 0 and a0.count() == 0
     assert np_(a0.row_ptr).tolist() == [0]
+
+
+@pytest.mark.parametrize("n,box,rc,seed", [(1, 10.0, 3.0, 0), (2, 10.0, 5.0, 1), (37, 7.0, 3.4, 2),
+                                           (300, 12.0, 3.0, 3), (500, 20.0, 9.9, 4),
+                                           (1000, 17.0, 2.0, 5)])
+def test_async_list_random_boxes(ctx, n, box, rc, seed):
+    # small grids (one or two cells per edge: repeated neighbour cells) and
+    # sparse ones; bounds from the synchronous build of the same atoms
+    rng = np.random.default_rng(seed)
+    xyz = rng.uniform(-box, 2 * box, size=(n, 3))
+    sysr = ctx.system(xyz, box, np.arange(n) // 3)
+    ctx.nblist(sysr, rc, plan_slot=5)
+    al = ctx.nblist_async(sysr, rc, plan_slot=6, bounds=ctx.nblist_bounds(5, 0.0))
+    assert al.status() == 0
+    rp, cp = O.nblist(xyz, box, rc)
+    r = al.resolved()
+    assert np.array_equal(np_(r.row_ptr), rp)
+    assert np.array_equal(np_(r.col), cp)
+
+
+def test_async_list_clustered(ctx, tk):
+    # cells far denser than the mean (the synchronous build reruns its
+    # enumeration there; the stream-ordered one takes the measured bound)
+    import torch
+    rng = np.random.default_rng(7)
+    box = 30.0
+    xyz = np.concatenate([rng.uniform(11.0, 16.0, size=(300, 3)),
+                          rng.uniform(0.0, box, size=(60, 3))])
+    sysr = ctx.system(xyz, box, np.arange(len(xyz)) // 3)
+    s = ctx.nblist(sysr, 7.001, plan_slot=5)
+    al = ctx.nblist_async(sysr, 7.001, plan_slot=6, bounds=ctx.nblist_bounds(5, 0.05))
+    assert al.status() == 0
+    rp, cp = O.nblist(xyz, box, 7.001)
+    assert np.array_equal(np_(al.resolved().col), cp)
+    # and its plan drives a pair term as the synchronous plan does
+    mp = np.zeros((len(xyz), 10))
+    mp[:, 0] = rng.normal(0.0, 0.3, len(xyz))
+    out = [ctx.empole_real(sysr, lst, mp, 0.4, 7.0) for lst in (s, al)]
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(np_(x), np_(y))
