@@ -307,6 +307,31 @@ tk_status tk_polarize_pcg(tk_ctx* ctx, void* stream, const tk_system* sys, const
                           int prec, const double* mu_guess, double* mu_out, tk_pcg_info* info);
 
 /*
+ * tk_polarize_pcg with no host synchronisation: the same solve (operator,
+ * preconditioner, guess, stopping rule, FP64 true residual) queued on
+ * `stream` as `iterations` PCG steps, 1 <= iterations <= 10000, that stop
+ * early on convergence (the steps queued after it return at once).  For
+ * callers that keep the host off the critical path and know how many steps
+ * their systems need (e.g. the previous solve's count, read later from
+ * info_dev).  The outcome goes to info_dev, DEVICE memory (one tk_pcg_info),
+ * written in stream order: status TK_OK with converged = 1 when the test was
+ * met, TK_E_NOCONV when `iterations` ran out, TK_E_BREAKDOWN, or TK_E_CAPACITY
+ * when the list came from a stream-ordered build that failed (nothing is
+ * solved then and mu_out is not written).  With TK_MIXED there is no FP64
+ * refinement: converged = 1 only if rms_true_debye <= tol_debye.  With
+ * iterations >= the count tk_polarize_pcg takes, mu_out and every info field
+ * equal its result bitwise (TK_MIXED: when it needed no refinement).  An
+ * empty system writes converged = 1.  Returns TK_OK once queued, or an
+ * argument/launch error with nothing written.  Shares the solver scratch of
+ * tk_polarize_pcg: two solves of one context must be ordered.
+ */
+tk_status tk_polarize_pcg_queued(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                 const tk_nblist* list, const double* mpole,
+                                 const double* polarity, const double* thole, double ewald_beta,
+                                 double cutoff, double tol_debye, int32_t iterations, int prec,
+                                 const double* mu_guess, double* mu_out, tk_pcg_info* info_dev);
+
+/*
  * tk_empole_real and tk_polarize_pcg in one call: the permanent multipoles'
  * energy, forces and virial (as tk_empole_real, same cutoff and Ewald
  * parameter) and the induced dipoles (as tk_polarize_pcg).  The multipole

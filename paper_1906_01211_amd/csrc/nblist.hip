@@ -197,7 +197,15 @@ __global__ __launch_bounds__(64) void k_cellsort(const int32_t* __restrict__ cst
   int c = blockIdx.x, start = cstart[c], m = cstart[c + 1] - start;
   if (threadIdx.x == 0) atomicMax(&info[1], m);
   if (m > kMaxCellAtoms) {
+    // the build fails; the cell's slots still get its atoms (unsorted), so
+    // the plan's permutation stays one for the kernels that gather through it
     if (threadIdx.x == 0) atomicMin(&info[0], (int)TK_E_CAPACITY);
+    for (int t = threadIdx.x; t < m; t += 64) {
+      const int e = tmp[start + t];
+      perm[start + t] = e;
+      scell[start + t] = c;
+      us[start + t] = make_uint4(u[3 * e], u[3 * e + 1], u[3 * e + 2], (uint32_t)e);
+    }
     return;
   }
   for (int t = threadIdx.x; t < m; t += 64) idx[t] = tmp[start + t];

@@ -788,6 +788,33 @@ __global__ __launch_bounds__(64) void k_cs_finish_true(PlanView pv, const double
   host[blockIdx.x] = *st;
 }
 
+__global__ void k_pcg_info_empty(tk_pcg_info v, tk_pcg_info* __restrict__ out) { *out = v; }
+
+// Outcome of a queued solve (tk_polarize_pcg_queued) in the caller's device
+// memory: the same fields and rules as the synchronous call's host result;
+// the mixed form's outcome is its FP64 check.
+__global__ void k_pcg_info_out(const PcgState* __restrict__ states, int count, int mixed,
+                               tk_pcg_info* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= count) return;
+  const PcgState h = states[k];
+  tk_pcg_info r{};
+  r.iters = h.iters;
+  r.refinements = 0;
+  r.rms_debye = h.rms;
+  r.rms_true_debye = h.rms_true;
+  r.epol = h.epol;
+  if (h.done == 3 || h.done == 4) {
+    r.status = h.done == 3 ? TK_E_BREAKDOWN : TK_E_CAPACITY;
+    r.converged = 0;
+  } else {
+    const bool ok = mixed ? h.rms_true <= h.tol : h.done == 1;
+    r.status = ok ? TK_OK : TK_E_NOCONV;
+    r.converged = ok ? 1 : 0;
+  }
+  out[k] = r;
+}
+
 // Refinement: keep x in dx and start the correction from z (= alpha r_t) for
 // the systems being refined.
 __global__ void k_refine_begin(PlanView pv, const int32_t* __restrict__ active,
@@ -813,10 +840,11 @@ __global__ void k_refine_end(PlanView pv, const int32_t* __restrict__ active,
   for (int d = 0; d < 3; ++d) x[3 * s + d] = on ? dx[3 * s + d] + x[3 * s + d] : dx[3 * s + d];
 }
 
+// (nothing written when the list's build failed: status nonzero)
 __global__ void k_scatter_out(int n, const int32_t* __restrict__ perm, const double* __restrict__ x,
-                              double* __restrict__ out) {
+                              double* __restrict__ out, const int32_t* __restrict__ status) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+  if (s >= n || *status != 0) return;
   const int i = perm[s];
 #pragma unroll
   for (int c = 0; c < 3; ++c) out[3 * i + c] = x[3 * s + c];
@@ -1120,6 +1148,30 @@ struct Solver {
     }
     return TK_OK;
   }
+
+  // The same iteration, `iters` updates queued with no host synchronisation
+  // (launches after convergence return at once), then the FP64 true
+  // residual.  The state stays on the device.
+  template <class R>
+  void run_queued(const double* rhs, double tol, int iters) {
+    k_cs_init<<<nsys * nv, 64, 0, st>>>(pv, npart, state, tol, iters, nullptr, nv);
+    {
+      MvArgs<R> a = mv_args<R>();
+      a.v = x;
+      a.pold = x;
+      a.rhs = rhs;
+      a.r = r;
+      a.z = z;
+      a.part = pz[0];
+      launch_mv<R, 0>(a, "pcg_mv0");
+    }
+    queue_mv<R>(0);
+    for (int k = 0; k < iters;) {
+      queue_update(k);
+      queue_mv<R>(++k);
+    }
+    queue_true_residual(rhs);
+  }
 };
 
 }  // namespace
@@ -1130,16 +1182,20 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                         int32_t maxiter, int prec, const double* mu_guess,
                         const int32_t* guess_on, double* mu_out, tk_pcg_info* info,
                         int pme_grid, int pme_order, int nv, double pscale, double* mp_energy,
-                        double* mp_force, double* mp_virial) {
+                        double* mp_force, double* mp_virial, int32_t queued,
+                        tk_pcg_info* info_dev) {
   const int nsys = P->nsys;
   if (pme_grid && (prec != TK_FP64 || nsys != 1 || !pme_args_ok(pme_grid, pme_order)))
     return TK_E_ARG;
   if (nv != 1 && (nv != 2 || prec != TK_FP64 || nsys != 1)) return TK_E_ARG;
-  for (int k = 0; k < nsys * nv; ++k) info[k] = tk_pcg_info{};
+  if (queued && (nv != 1 || pme_grid || nsys != 1 || !info_dev)) return TK_E_ARG;
+  if (!queued)
+    for (int k = 0; k < nsys * nv; ++k) info[k] = tk_pcg_info{};
   const int n = P->n;
   if (n == 0) {
-    for (int k = 0; k < nsys * nv; ++k) info[k].converged = 1;
-    return TK_OK;
+    if (!queued)
+      for (int k = 0; k < nsys * nv; ++k) info[k].converged = 1;
+    return TK_OK;   // (the queued entry point writes the empty system's outcome itself)
   }
   Solver S;
   S.ctx = ctx;
@@ -1210,13 +1266,24 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   }
   if (unit_lds_bytes<EfieldPh<double>>(*P, 1) > kMaxLds) return TK_E_CAPACITY;
   if ((s = mv_attributes(S.mv_lds))) return s;
-  // pinned: [1024, ...) host state mirrors, then the refinement mask
-  void *hbase, *hdev;
   const size_t mirror = sizeof(PcgState) * nsys * nv;
-  if ((s = pinned(ctx, 1024 + mirror + sizeof(int32_t) * nsys + 64, &hbase, &hdev))) return s;
-  S.host = (PcgState*)((char*)hbase + 1024);
-  S.host_dev = (PcgState*)((char*)hdev + 1024);
-  S.active_h = (int32_t*)((char*)hbase + 1024 + mirror);
+  if (queued) {
+    // no host reads: the kernels' state mirror goes to device scratch (the
+    // context's pinned buffer may be reallocated by a later call while these
+    // kernels are still queued)
+    void* m;
+    if ((s = scratch(ctx, "pcg_mirror", mirror, &m))) return s;
+    S.host = nullptr;
+    S.host_dev = (PcgState*)m;
+    S.active_h = nullptr;
+  } else {
+    // pinned: [1024, ...) host state mirrors, then the refinement mask
+    void *hbase, *hdev;
+    if ((s = pinned(ctx, 1024 + mirror + sizeof(int32_t) * nsys + 64, &hbase, &hdev))) return s;
+    S.host = (PcgState*)((char*)hbase + 1024);
+    S.host_dev = (PcgState*)((char*)hdev + 1024);
+    S.active_h = (int32_t*)((char*)hbase + 1024 + mirror);
+  }
 
   // right-hand side: permanent field (sorted order); the same pass caches
   // the mat-vec's radial factors
@@ -1264,6 +1331,15 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   k_cs_setup<<<xcd_grid(S.ncells), kCellThreads, 0, st>>>(S.pv, polarity, mu_guess, guess_on, S.b,
                                                           S.alpha_s, S.x, S.npart, S.hdr, S.ent,
                                                           nv);
+  if (queued) {
+    if (prec == TK_FP64) S.run_queued<double>(S.b, tol_debye, queued);
+    else S.run_queued<float>(S.b, tol_debye, queued);
+    k_pcg_info_out<<<1, 64, 0, st>>>(S.state, nsys * nv, prec == TK_MIXED ? 1 : 0, info_dev);
+    k_scatter_out<<<ceil_div(n, 256), 256, 0, st>>>(n, (const int32_t*)P->perm.p, S.x, mu_out,
+                                                    S.pv.status);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+  }
   const int slot = (int)(P - ctx->plans);
   int& hint = ctx->pcg_hint[slot][prec == TK_FP64 ? 0 : 1];
   s = prec == TK_FP64 ? S.run<double>(S.b, tol_debye, maxiter, hint, true, nullptr)
@@ -1336,7 +1412,7 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   // solve's outcome, so no further synchronisation
   for (int v = 0; v < nv; ++v)
     k_scatter_out<<<ceil_div(n, 256), 256, 0, st>>>(n, (const int32_t*)P->perm.p, S.x + v * S.vs,
-                                                    mu_out + v * S.vs);
+                                                    mu_out + v * S.vs, S.pv.status);
   TK_HIP(hipGetLastError());
   return TK_OK;
 }
@@ -1370,6 +1446,36 @@ extern "C" tk_status tk_polarize_pcg(tk_ctx* ctx, void* stream, const tk_system*
                          info, 0, 0)))
     return s;
   return info->status;
+}
+
+extern "C" tk_status tk_polarize_pcg_queued(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                            const tk_nblist* list, const double* mpole,
+                                            const double* polarity, const double* thole,
+                                            double ewald_beta, double cutoff, double tol_debye,
+                                            int32_t iterations, int prec,
+                                            const double* mu_guess, double* mu_out,
+                                            tk_pcg_info* info_dev) {
+  if (!ctx || !info_dev) return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (prec != TK_FP64 && prec != TK_MIXED) return TK_E_ARG;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !(tol_debye >= 0.0) ||
+      iterations < 1 || iterations > 10000)
+    return TK_E_ARG;
+  const Plan* P;
+  if ((s = get_plan(ctx, sys, list, cutoff, &P))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (sys->n == 0) {   // nothing to solve: converged, written in stream order
+    tk_pcg_info e{};
+    e.converged = 1;
+    k_pcg_info_empty<<<1, 1, 0, st>>>(e, info_dev);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+  }
+  if (!mpole || !polarity || !thole || !mu_out) return TK_E_ARG;
+  return solve_dipoles(ctx, st, P, sys->xyz, sys->molid, mpole, polarity, thole, ewald_beta,
+                       cutoff, tol_debye, iterations, prec, mu_guess, nullptr, mu_out, nullptr,
+                       0, 0, 1, 0.0, nullptr, nullptr, nullptr, iterations, info_dev);
 }
 
 extern "C" tk_status tk_empole_polarize(tk_ctx* ctx, void* stream, const tk_system* sys,

@@ -288,7 +288,8 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                         const int32_t* guess_on, double* mu_out, tk_pcg_info* info,
                         int pme_grid = 0, int pme_order = 0, int nv = 1, double pscale = 0.0,
                         double* mp_energy = nullptr, double* mp_force = nullptr,
-                        double* mp_virial = nullptr);
+                        double* mp_virial = nullptr, int32_t queued = 0,
+                        tk_pcg_info* info_dev = nullptr);
 
 // The allocation-free entry point's fixed scratch (noalloc.hip): resolves
 // the device address of this device's copy of the array (once per device;

@@ -122,6 +122,8 @@ _SIGS = {
     "tk_tmatvec_noalloc_max_atoms": [],
     "tk_polarize_pcg": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _d, _d, _d,
                         _i32, C.c_int, _vp, _vp, C.POINTER(PcgInfo)],
+    "tk_polarize_pcg_queued": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp,
+                               _d, _d, _d, _i32, C.c_int, _vp, _vp, _vp],
     "tk_epolar_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
                        _d, C.c_int, _vp, _vp, _vp],
     "tk_pme_mpole": [_vp, _vp, C.POINTER(System), _vp, _d, _i32, _i32, _vp, _vp, _vp],
@@ -417,6 +419,36 @@ class Context:
         if st not in (OK, E_NOCONV, E_BREAKDOWN):
             _check(st, "tk_polarize_pcg")
         return out, {k: getattr(info, k) for k, _ in PcgInfo._fields_}
+
+    def polarize_pcg_queued(self, sysref, lst, mpole, polarity, thole, beta, cutoff, iterations,
+                            tol_debye=1e-5, prec=FP64, mu_guess=None, info_dev=None):
+        """tk_polarize_pcg_queued: (mu, info_dev), both written in stream order
+        on the current stream; info_dev is a device uint8 tensor holding one
+        tk_pcg_info (read it with pcg_info)."""
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device,
+                                               (sysref.n, 3), "mu_guess")
+        out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        if info_dev is None:
+            info_dev = torch.empty(C.sizeof(PcgInfo), dtype=torch.uint8, device=self.device)
+        if (info_dev.device != torch.device(self.device) or info_dev.dtype != torch.uint8
+                or info_dev.numel() < C.sizeof(PcgInfo) or not info_dev.is_contiguous()):
+            raise ValueError("info_dev: contiguous device uint8 tensor of sizeof(tk_pcg_info)")
+        st = load().tk_polarize_pcg_queued(self._h, _stream(self.device), C.byref(sysref.c),
+                                           C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), beta,
+                                           cutoff, tol_debye, int(iterations), prec, _ptr(g),
+                                           _ptr(out), _ptr(info_dev))
+        _check(st, "tk_polarize_pcg_queued")
+        return out, info_dev
+
+    @staticmethod
+    def pcg_info(info_dev):
+        """Decode a device tk_pcg_info (synchronises with its writer)."""
+        raw = bytes(info_dev[:C.sizeof(PcgInfo)].cpu().numpy().tobytes())
+        info = PcgInfo.from_buffer_copy(raw)
+        return {k: getattr(info, k) for k, _ in PcgInfo._fields_}
 
     def empole_polarize(self, sysref, lst, mpole, polarity, thole, beta, cutoff, tol_debye=1e-5,
                         maxiter=100, prec=FP64, mu_guess=None):
