@@ -10,6 +10,13 @@ listed pair with r <= rc counted once per routine that evaluates it: the
 multipole energy and the permanent field once each, the mat-vec once per
 call, HAL once).  Inputs are resident in HBM before the timed region.
 
+The step is stream-ordered: the lists come from the stream-ordered build
+(bounds from a synchronous build of the same box plus 10 %), the solve runs
+the iteration count that the synchronous solve took (a caller carries it from
+step to step) and stops on convergence, and nothing inside a step waits for
+the host.  After the timed loop every step's list status and solve outcome
+are read back: a failed list or an unconverged solve fails the run.
+
 Prints ONE JSON line.  Extra keys: polarization solves/s, the mixed-precision
 step, the point-charge + LJ path (96,000 atoms, 12 A), the roofline of the
 dominant kernel (HIP events inside the library, on the launch stream) and the
@@ -171,6 +178,78 @@ class AmoebaStep:
         n9 = count_pairs(w.xyz, w.box, l9.row_ptr.cpu().numpy(), l9.col.cpu().numpy(), s["rc_vdw"],
                          w.molid, skip_same=True)
         return n7, n9
+
+
+class QueuedAmoebaStep(AmoebaStep):
+    """The same step with no host synchronisation inside it: both lists from
+    the stream-ordered build (bounds: the synchronous build's sizes plus 10 %),
+    the multipole terms and dipoles from the queued fused call with the
+    synchronous solve's iteration count (the count a caller carries from one
+    step to the next), then HAL.  Every list status and solve outcome stays on
+    the device; `check` reads them after the timed loop."""
+
+    def __init__(self, ctx, tk, w, prec, iters):
+        import torch
+        super().__init__(ctx, tk, w, prec)
+        s = self.s
+        ctx.nblists(self.sys, [s["rc_ewald"] + s["skin"], s["rc_vdw"] + s["skin"]], [6, 7])
+        self.b7, self.b9 = ctx.nblist_bounds(6, 0.1), ctx.nblist_bounds(7, 0.1)
+        self.iters = int(iters)
+        self.flags = []   # per step: both list statuses and the solve outcome (device)
+
+    def __call__(self):
+        import torch
+        c, s, p = self.ctx, self.s, self.prec
+        main = torch.cuda.current_stream(c.device)
+        self.side.wait_stream(main)
+        l7 = c.nblist_async(self.sys, s["rc_ewald"] + s["skin"], 6, self.b7, stream=main,
+                            report=False)
+        l9 = c.nblist_async(self.sys, s["rc_vdw"] + s["skin"], 7, self.b9, stream=self.side,
+                            report=False)
+        main.wait_stream(self.side)
+        em, (mu, info_dev) = c.empole_polarize_queued(self.sys, l7, self.mpole, self.pol,
+                                                      self.thole, s["beta"], s["rc_ewald"],
+                                                      self.iters, tol_debye=s["tol_debye"],
+                                                      prec=p)
+        ev = c.evdw(self.sys, l9, self.tk.VDW_HAL, self.rad, self.eps, s["rc_vdw"],
+                    s["taper_frac"], s["dhal"], s["ghal"], prec=p)
+        self.flags.append((l7.status_dev, l9.status_dev, info_dev))   # read after the loop
+        self.out = (em, mu, ev)
+        return l7, l9
+
+    def check(self):
+        """Every step since the last check: lists built, solve converged."""
+        last = None
+        for s7, s9, info_dev in self.flags:
+            last = self.ctx.pcg_info(info_dev)
+            assert int(s7.item()) == 0 and int(s9.item()) == 0, "a queued step's list failed"
+            assert last["converged"] == 1, "a queued step's solve did not converge"
+        self.flags = []
+        if last is not None:
+            self.info = last
+        return last
+
+
+class EveryKth:
+    """Runs `step`, timing the dominant kernel's launches with HIP events in
+    every k-th call only: an event-timed dispatch costs the GPU about 5 us, so
+    timing all eight mat-vecs of every step would add about 40 us to it."""
+
+    def __init__(self, ctx, step, dom, k):
+        self.ctx, self.step, self.dom, self.k = ctx, step, dom, k
+        self.calls = 0
+        self.sampled = 0
+
+    def __call__(self):
+        on = self.calls % self.k == 0
+        if on:
+            self.ctx.profile(True, only=self.dom, reset=False)
+            self.sampled += 1
+        r = self.step()
+        if on:
+            self.ctx.profile(False)
+        self.calls += 1
+        return r
 
 
 def timed(fn, steps, warmup):
@@ -371,22 +450,29 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     prec = tk.FP64 if a.prec == "fp64" else tk.MIXED
-    step = AmoebaStep(ctx, tk, w, prec)
-    n7, n9 = step.pair_counts()
+    # the synchronous step once: exact pair counts from its host-sized lists,
+    # and the iteration count its solve takes (the count a stream-ordered
+    # step carries from the previous step)
+    ref_step = AmoebaStep(ctx, tk, w, prec)
+    n7, n9 = ref_step.pair_counts()
+    step = QueuedAmoebaStep(ctx, tk, w, prec, ref_step.info["iters"])
+    step.l7_pairs, step.l9_pairs = ref_step.l7_pairs, ref_step.l9_pairs
 
     # timed region: the dominant kernel (the solver's per-cell mat-vec) is
     # timed by HIP events that the library records on its launch stream
     dom = "pcg_mv_fp64" if prec == tk.FP64 else "pcg_mv_fp32"
-    ctx.profile(True, only=dom)
-    ms = timed(step, a.steps, a.warmup) * 1e3
+    ctx.profile(True, only=dom)   # clears the counters
+    ctx.profile(False)
+    sampler = EveryKth(ctx, step, dom, 10)
+    ms = timed(sampler, a.steps, a.warmup) * 1e3
     dprof = ctx.profile_read()
+    step.check()   # every timed step: both lists built, the solve converged
     # full kernel breakdown from a separate pass (not used for `value`)
     ctx.profile(True)
     timed(step, max(2, a.steps // 4), 0)
     prof = ctx.profile_read()
     ctx.profile(False)
-    # per-step wall times of a further pass (each step already synchronises
-    # inside; one more synchronisation closes it)
+    # per-step wall times of a further pass (a synchronisation after each step)
     per = []
     for _ in range(max(20, a.steps)):
         t0 = time.perf_counter()
@@ -394,7 +480,7 @@ def main():
         torch.cuda.synchronize()
         per.append((time.perf_counter() - t0) * 1e3)
     q10, q50, q90 = np.percentile(per, [10, 50, 90])
-    iters = step.info["iters"]
+    iters = step.check()["iters"]
     # the polarization solve alone (right-hand side, PCG to tolerance, FP64
     # true residual) on the step's 7 A list, FP64 and mixed
     sv = None if a.no_solve_rates else {}
@@ -419,8 +505,8 @@ def main():
         launches = dprof[dom]["launches"]
         avg_ms = dprof[dom]["ms"] / launches
         # launches per solve: iterations 0..iters-1 do the mat-vec, the last
-        # one only finds convergence and returns
-        solves = a.steps + a.warmup
+        # one only finds convergence and returns (timed solves: every tenth)
+        solves = sampler.sampled
         working = iters * solves
         nl7 = int(step.l7_pairs)
         bpl = MV_BYTES_PER_PAIR[a.prec] * nl7 + MV_BYTES_PER_ATOM * w.n
@@ -431,6 +517,7 @@ def main():
                 "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": committed_traffic(a.prec),
                 "bytes_per_launch": bpl, "launches": launches, "working_launches": working,
+                "timed_steps": f"{solves} of {a.steps + a.warmup} (every tenth)",
                 "avg_launch_us": round(avg_ms * 1e3, 3),
                 "alu_tflops": round(fl, 3), "alu_frac": round(fl / peak_fl, 4),
                 # what the counters say binds it (HBM is not saturated)
@@ -446,7 +533,8 @@ def main():
         "config": {"workload": "water box, 7,853 waters (23,559 atoms), 62.23 A, AMOEBA-style "
                                "multipoles + Thole polarization + HAL, rc 7/9 A",
                    "atoms": w.n, "pairs_7A": n7, "pairs_9A_hal": n9,
-                   "pcg_iters": iters, "prec": a.prec},
+                   "pcg_iters": iters, "prec": a.prec,
+                   "step": "stream-ordered: no host synchronisation inside a step"},
         "solves_per_s": 1e3 / ms,   # one solve per step
         "polarization_solves_per_s": sv,   # the solve alone
         "step_ms_p10_p50_p90": [round(q10, 4), round(q50, 4), round(q90, 4)],
@@ -468,7 +556,7 @@ def main():
     }
     other_step = None
     if not a.no_extras:
-        out["extras"], other_step = extras(ctx, tk, w, a, prec, n7)
+        out["extras"], other_step = extras(ctx, tk, w, a, prec, n7, iters)
     if not a.no_serving:
         out["serving"] = serving(tk, a.serving_requests)
     if roof is not None:
@@ -486,17 +574,37 @@ def main():
     print(json.dumps(out))
 
 
-def extras(ctx, tk, w, a, prec, n7):
+def extras(ctx, tk, w, a, prec, n7, iters):
     """Mixed-vs-FP64 step, the charge + LJ path, the polarization forces, the
     reciprocal-space PME, the local frames and the truncated CG (not part of
     `value`)."""
     import torch
     res = {}
     other = tk.MIXED if prec == tk.FP64 else tk.FP64
-    st = AmoebaStep(ctx, tk, w, other)
+    ref_o = AmoebaStep(ctx, tk, w, other)
+    ref_o()
+    if ref_o.info["refinements"] == 0:   # the queued solve has no FP64 refinement
+        st = QueuedAmoebaStep(ctx, tk, w, other, ref_o.info["iters"])
+        res["other_step_form"] = "stream-ordered"
+    else:
+        st = ref_o
+        res["other_step_form"] = "synchronous (its solve needed FP64 refinement)"
     ms = timed(st, max(3, a.steps // 2), 2) * 1e3
+    if st is not ref_o:
+        st.check()
     res["amoeba_step_ms_" + ("mixed" if other == tk.MIXED else "fp64")] = ms
     res["pcg_iters_other"] = st.info["iters"]
+    # the synchronous step (lists sized through the host, the solve's
+    # outcome read on the host) against the stream-ordered one, interleaved
+    qs = QueuedAmoebaStep(ctx, tk, w, prec, iters)
+    sync_step = AmoebaStep(ctx, tk, w, prec)
+    qms, sms = [], []
+    for _ in range(3):
+        qms.append(timed(qs, max(10, a.steps), 2) * 1e3)
+        qs.check()
+        sms.append(timed(sync_step, max(10, a.steps), 2) * 1e3)
+    res["sync_step"] = {"ms_runs": [round(x, 4) for x in sms],
+                        "stream_ordered_ms_runs": [round(x, 4) for x in qms]}
     wc = synth.make("water32000_charge_lj")
     s = synth.CHARGE_SETTINGS
     sysr = ctx.system(wc.xyz, wc.box, wc.molid)

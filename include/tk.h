@@ -350,6 +350,26 @@ tk_status tk_empole_polarize(tk_ctx* ctx, void* stream, const tk_system* sys,
                              double* virial);
 
 /*
+ * tk_empole_polarize with the solve of tk_polarize_pcg_queued: the multipole
+ * energy, forces and virial (as tk_empole_polarize) and the induced dipoles
+ * from `iterations` queued PCG steps, with no host synchronisation; the
+ * outcome in info_dev (device memory), with the rules of
+ * tk_polarize_pcg_queued.  Every output is written in stream order.  With
+ * iterations >= the count tk_empole_polarize takes, all outputs and info
+ * fields equal its results bitwise (TK_MIXED: when it needed no refinement).
+ * After a failed stream-ordered list build (TK_E_CAPACITY in info_dev) the
+ * energy, forces and virial are not valid either.  Errors as
+ * tk_polarize_pcg_queued, plus TK_E_ARG for NULL energy, force or virial.
+ */
+tk_status tk_empole_polarize_queued(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                    const tk_nblist* list, const double* mpole,
+                                    const double* polarity, const double* thole,
+                                    double ewald_beta, double cutoff, double tol_debye,
+                                    int32_t iterations, int prec, const double* mu_guess,
+                                    double* mu_out, tk_pcg_info* info_dev, double* energy,
+                                    double* force, double* virial);
+
+/*
  * Induced dipoles with the full Ewald operator: tk_polarize_pcg with the
  * reciprocal space included (the reciprocal polarization routine named in
  * section "Hotspots").  The operator is A = diag(1/alpha) - T - cI - R, R mu

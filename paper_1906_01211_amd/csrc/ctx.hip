@@ -525,6 +525,17 @@ tk_status tk_profile_enable(tk_ctx* ctx, int on, const char* only) {
   if (!ctx) return TK_E_ARG;
   ctx->prof_on = on != 0;
   ctx->prof_only = only ? only : "";
+  // the events come from a pool: fill it now, so that timed launches do not
+  // create events on the host between them
+  constexpr size_t kPrefill = 4096;
+  if (ctx->prof_on && ctx->event_pool.size() < kPrefill / 4) {
+    TK_HIP(hipSetDevice(ctx->device));
+    while (ctx->event_pool.size() < kPrefill) {
+      hipEvent_t e = nullptr;
+      TK_HIP(hipEventCreate(&e));
+      ctx->event_pool.push_back(e);
+    }
+  }
   return TK_OK;
 }
 

@@ -1510,6 +1510,39 @@ extern "C" tk_status tk_empole_polarize(tk_ctx* ctx, void* stream, const tk_syst
   return info->status;
 }
 
+extern "C" tk_status tk_empole_polarize_queued(tk_ctx* ctx, void* stream, const tk_system* sys,
+                                               const tk_nblist* list, const double* mpole,
+                                               const double* polarity, const double* thole,
+                                               double ewald_beta, double cutoff,
+                                               double tol_debye, int32_t iterations, int prec,
+                                               const double* mu_guess, double* mu_out,
+                                               tk_pcg_info* info_dev, double* energy,
+                                               double* force, double* virial) {
+  if (!ctx || !info_dev) return TK_E_ARG;
+  tk_status s = check_system(sys);
+  if (s) return s;
+  if (prec != TK_FP64 && prec != TK_MIXED) return TK_E_ARG;
+  if (!(ewald_beta >= 0.0) || !std::isfinite(ewald_beta) || !(tol_debye >= 0.0) ||
+      iterations < 1 || iterations > 10000 || !energy || !virial)
+    return TK_E_ARG;
+  const Plan* P;
+  if ((s = get_plan(ctx, sys, list, cutoff, &P))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (sys->n == 0) {
+    tk_pcg_info e{};
+    e.converged = 1;
+    k_pcg_info_empty<<<1, 1, 0, st>>>(e, info_dev);
+    TK_HIP(hipGetLastError());
+    TK_HIP(hipMemsetAsync(energy, 0, 3 * sizeof(double), st));
+    TK_HIP(hipMemsetAsync(virial, 0, 9 * sizeof(double), st));
+    return TK_OK;
+  }
+  if (!mpole || !polarity || !thole || !mu_out || !force) return TK_E_ARG;
+  return solve_dipoles(ctx, st, P, sys->xyz, sys->molid, mpole, polarity, thole, ewald_beta,
+                       cutoff, tol_debye, iterations, prec, mu_guess, nullptr, mu_out, nullptr,
+                       0, 0, 1, 0.0, energy, force, virial, iterations, info_dev);
+}
+
 extern "C" tk_status tk_polarize_pcg_ewald(tk_ctx* ctx, void* stream, const tk_system* sys,
                                            const tk_nblist* list, const double* mpole,
                                            const double* polarity, const double* thole,

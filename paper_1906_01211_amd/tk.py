@@ -124,6 +124,8 @@ _SIGS = {
                         _i32, C.c_int, _vp, _vp, C.POINTER(PcgInfo)],
     "tk_polarize_pcg_queued": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp,
                                _d, _d, _d, _i32, C.c_int, _vp, _vp, _vp],
+    "tk_empole_polarize_queued": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp,
+                                  _vp, _d, _d, _d, _i32, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp],
     "tk_epolar_real": [_vp, _vp, C.POINTER(System), C.POINTER(NbList), _vp, _vp, _vp, _vp, _d,
                        _d, C.c_int, _vp, _vp, _vp],
     "tk_pme_mpole": [_vp, _vp, C.POINTER(System), _vp, _d, _i32, _i32, _vp, _vp, _vp],
@@ -247,9 +249,11 @@ class Context:
         return int(load().tk_arena_bytes(self._h))
 
     # -- kernel timing -----------------------------------------------------------
-    def profile(self, on=True, only=None):
-        """Time kernel launches with HIP events on their stream (optionally one kernel)."""
-        if on:
+    def profile(self, on=True, only=None, reset=True):
+        """Time kernel launches with HIP events on their stream (optionally one
+        kernel).  Switching on clears the counters (which waits for the timed
+        work) unless reset is False."""
+        if on and reset:
             _check(load().tk_profile_reset(self._h), "tk_profile_reset")
         _check(load().tk_profile_enable(self._h, int(on), None if only is None else only.encode()),
                "tk_profile_enable")
@@ -431,17 +435,44 @@ class Context:
         g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device,
                                                (sysref.n, 3), "mu_guess")
         out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
-        if info_dev is None:
-            info_dev = torch.empty(C.sizeof(PcgInfo), dtype=torch.uint8, device=self.device)
-        if (info_dev.device != torch.device(self.device) or info_dev.dtype != torch.uint8
-                or info_dev.numel() < C.sizeof(PcgInfo) or not info_dev.is_contiguous()):
-            raise ValueError("info_dev: contiguous device uint8 tensor of sizeof(tk_pcg_info)")
+        info_dev = self._info_dev(info_dev)
         st = load().tk_polarize_pcg_queued(self._h, _stream(self.device), C.byref(sysref.c),
                                            C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th), beta,
                                            cutoff, tol_debye, int(iterations), prec, _ptr(g),
                                            _ptr(out), _ptr(info_dev))
         _check(st, "tk_polarize_pcg_queued")
         return out, info_dev
+
+    def empole_polarize_queued(self, sysref, lst, mpole, polarity, thole, beta, cutoff,
+                               iterations, tol_debye=1e-5, prec=FP64, mu_guess=None,
+                               info_dev=None):
+        """tk_empole_polarize_queued: (energy[3], force, virial), (mu, info_dev), all
+        written in stream order on the current stream."""
+        mp = _dev(mpole, torch.float64, self.device, (sysref.n, 10), "mpole")
+        pol = _dev(polarity, torch.float64, self.device, (sysref.n,), "polarity")
+        th = _dev(thole, torch.float64, self.device, (sysref.n,), "thole")
+        g = None if mu_guess is None else _dev(mu_guess, torch.float64, self.device,
+                                               (sysref.n, 3), "mu_guess")
+        out = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        e = torch.empty(3, dtype=torch.float64, device=self.device)
+        f = torch.empty((sysref.n, 3), dtype=torch.float64, device=self.device)
+        v = torch.empty(9, dtype=torch.float64, device=self.device)
+        info_dev = self._info_dev(info_dev)
+        st = load().tk_empole_polarize_queued(self._h, _stream(self.device), C.byref(sysref.c),
+                                              C.byref(lst.c), _ptr(mp), _ptr(pol), _ptr(th),
+                                              beta, cutoff, tol_debye, int(iterations), prec,
+                                              _ptr(g), _ptr(out), _ptr(info_dev), _ptr(e),
+                                              _ptr(f), _ptr(v))
+        _check(st, "tk_empole_polarize_queued")
+        return (e, f, v), (out, info_dev)
+
+    def _info_dev(self, info_dev):
+        if info_dev is None:
+            return torch.empty(C.sizeof(PcgInfo), dtype=torch.uint8, device=self.device)
+        if (info_dev.device != self.device or info_dev.dtype != torch.uint8
+                or info_dev.numel() < C.sizeof(PcgInfo) or not info_dev.is_contiguous()):
+            raise ValueError("info_dev: contiguous device uint8 tensor of sizeof(tk_pcg_info)")
+        return info_dev
 
     @staticmethod
     def pcg_info(info_dev):

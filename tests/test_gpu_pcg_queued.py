@@ -119,7 +119,7 @@ def test_queued_chain_without_sync(ctx):
 
 def test_queued_failed_list(ctx, tk):
     # a stream-ordered list whose build went past a bound: the queued solve
-    # reports TK_E_CAPACITY on the device and leaves mu_out alone
+    # reports TK_E_CAPACITY on the device
     import torch
     w, sysr, lst, mp, pol, th = setup(ctx, "water216")
     b = ctx.nblist_bounds(0, headroom=0.0)
@@ -158,3 +158,37 @@ def test_queued_arguments_and_empty(ctx, tk):
     iq = ctx.pcg_info(idev)
     assert mq.shape == (0, 3)
     assert iq["status"] == 0 and iq["converged"] == 1 and iq["iters"] == 0
+
+
+@pytest.mark.parametrize("name", ["water216", "water7853"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_queued_equals_sync(ctx, tk, name, prec):
+    # tk_empole_polarize_queued: multipole terms and dipoles bitwise those of
+    # tk_empole_polarize
+    w, sysr, lst, mp, pol, th = setup(ctx, name)
+    (e, f, v), (mu, info) = ctx.empole_polarize(sysr, lst, mp, pol, th, S["beta"], S["rc_ewald"],
+                                                tol_debye=S["tol_debye"], maxiter=S["maxiter"],
+                                                prec=prec)
+    assert info["status"] == 0
+    if prec == tk.MIXED and info["refinements"]:
+        pytest.skip("the synchronous mixed solve refined (the queued one does not)")
+    (eq, fq, vq), (mq, idev) = ctx.empole_polarize_queued(sysr, lst, mp, pol, th, S["beta"],
+                                                          S["rc_ewald"], info["iters"] + 2,
+                                                          tol_debye=S["tol_debye"], prec=prec)
+    for x, y in ((eq, e), (fq, f), (vq, v), (mq, mu)):
+        assert np.array_equal(np_(x), np_(y))
+    assert ctx.pcg_info(idev) == info
+
+
+def test_fused_queued_empty(ctx, tk):
+    import torch
+    w = water("water216")
+    e = ctx.system(np.zeros((0, 3)), w.box, np.zeros(0, dtype=np.int32))
+    le = ctx.nblist(e, R7, plan_slot=4)
+    z = torch.zeros((0, 10), dtype=torch.float64, device=ctx.device)
+    z1 = torch.zeros(0, dtype=torch.float64, device=ctx.device)
+    (en, f, v), (mq, idev) = ctx.empole_polarize_queued(e, le, z, z1, z1, S["beta"],
+                                                        S["rc_ewald"], 3)
+    assert np_(en).tolist() == [0.0] * 3 and np_(v).tolist() == [0.0] * 9
+    iq = ctx.pcg_info(idev)
+    assert iq["status"] == 0 and iq["converged"] == 1
