@@ -117,6 +117,9 @@ def parse():
     ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serial-step", action="store_true",
+                    help="run HAL after the solve on one stream (each kernel alone; for "
+                         "kernel traces)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--no-solve-rates", action="store_true",
@@ -185,12 +188,13 @@ class QueuedAmoebaStep(AmoebaStep):
     the stream-ordered build (bounds: the synchronous build's sizes plus 10 %),
     the multipole terms and dipoles from the queued fused call with the
     synchronous solve's iteration count (the count a caller carries from one
-    step to the next), then HAL.  Every list status and solve outcome stays on
-    the device; `check` reads them after the timed loop."""
+    step to the next) on the first stream, HAL on the second.  Every list
+    status and solve outcome stays on the device; `check` reads them after
+    the timed loop."""
 
-    def __init__(self, ctx, tk, w, prec, iters):
-        import torch
+    def __init__(self, ctx, tk, w, prec, iters, serial=False):
         super().__init__(ctx, tk, w, prec)
+        self.serial = serial   # HAL after the solve on the first stream (each kernel alone)
         s = self.s
         ctx.nblists(self.sys, [s["rc_ewald"] + s["skin"], s["rc_vdw"] + s["skin"]], [6, 7])
         self.b7, self.b9 = ctx.nblist_bounds(6, 0.1), ctx.nblist_bounds(7, 0.1)
@@ -206,13 +210,23 @@ class QueuedAmoebaStep(AmoebaStep):
                             report=False)
         l9 = c.nblist_async(self.sys, s["rc_vdw"] + s["skin"], 7, self.b9, stream=self.side,
                             report=False)
-        main.wait_stream(self.side)
+        # HAL on the second stream behind its list, beside the solve: the
+        # solve's launches are latency-bound and leave room on the GPU
+        # (0.601 against 0.660 ms with HAL after the solve on one stream)
+        hal = lambda: c.evdw(self.sys, l9, self.tk.VDW_HAL, self.rad, self.eps, s["rc_vdw"],
+                             s["taper_frac"], s["dhal"], s["ghal"], prec=p)
+        if not self.serial:
+            with torch.cuda.stream(self.side):
+                ev = hal()
+        else:
+            main.wait_stream(self.side)
         em, (mu, info_dev) = c.empole_polarize_queued(self.sys, l7, self.mpole, self.pol,
                                                       self.thole, s["beta"], s["rc_ewald"],
                                                       self.iters, tol_debye=s["tol_debye"],
                                                       prec=p)
-        ev = c.evdw(self.sys, l9, self.tk.VDW_HAL, self.rad, self.eps, s["rc_vdw"],
-                    s["taper_frac"], s["dhal"], s["ghal"], prec=p)
+        if self.serial:
+            ev = hal()
+        main.wait_stream(self.side)
         self.flags.append((l7.status_dev, l9.status_dev, info_dev))   # read after the loop
         self.out = (em, mu, ev)
         return l7, l9
@@ -455,7 +469,7 @@ def main():
     # step carries from the previous step)
     ref_step = AmoebaStep(ctx, tk, w, prec)
     n7, n9 = ref_step.pair_counts()
-    step = QueuedAmoebaStep(ctx, tk, w, prec, ref_step.info["iters"])
+    step = QueuedAmoebaStep(ctx, tk, w, prec, ref_step.info["iters"], serial=a.serial_step)
     step.l7_pairs, step.l9_pairs = ref_step.l7_pairs, ref_step.l9_pairs
 
     # timed region: the dominant kernel (the solver's per-cell mat-vec) is
@@ -467,11 +481,14 @@ def main():
     ms = timed(sampler, a.steps, a.warmup) * 1e3
     dprof = ctx.profile_read()
     step.check()   # every timed step: both lists built, the solve converged
-    # full kernel breakdown from a separate pass (not used for `value`)
+    # full kernel breakdown from a separate pass (not used for `value`), with
+    # HAL after the solve on one stream, so that each kernel runs alone
+    lone = QueuedAmoebaStep(ctx, tk, w, prec, ref_step.info["iters"], serial=True)
     ctx.profile(True)
-    timed(step, max(2, a.steps // 4), 0)
+    timed(lone, max(2, a.steps // 4), 0)
     prof = ctx.profile_read()
     ctx.profile(False)
+    lone.check()
     # per-step wall times of a further pass (a synchronisation after each step)
     per = []
     for _ in range(max(20, a.steps)):
@@ -534,7 +551,9 @@ def main():
                                "multipoles + Thole polarization + HAL, rc 7/9 A",
                    "atoms": w.n, "pairs_7A": n7, "pairs_9A_hal": n9,
                    "pcg_iters": iters, "prec": a.prec,
-                   "step": "stream-ordered: no host synchronisation inside a step"},
+                   "step": "stream-ordered: no host synchronisation inside a step; HAL "
+                           + ("after the solve on one stream" if a.serial_step
+                              else "on a second stream beside the solve")},
         "solves_per_s": 1e3 / ms,   # one solve per step
         "polarization_solves_per_s": sv,   # the solve alone
         "step_ms_p10_p50_p90": [round(q10, 4), round(q50, 4), round(q90, 4)],
