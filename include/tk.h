@@ -177,8 +177,8 @@ tk_status tk_nblist_bounds_get(tk_ctx* ctx, int32_t plan_slot, double headroom,
  * A later call taking this list (tk_nblist with npairs = -1 and this
  * plan_slot) reads its status on the device.  Host-side argument errors as
  * tk_nblist_build (bounds: TK_E_ARG if windows, max_occ, max_row or max_nbhd
- * is < 1 or npairs < 0; max_occ above 512 acts as 512; TK_E_CAPACITY if the
- * row sort's LDS for max_row exceeds the GPU's).  One system; the first build of a new cell grid also
+ * is < 1 or npairs < 0; max_occ above 512 acts as 512; TK_E_CAPACITY if
+ * max_row is above 1024 and the row sort's LDS for it exceeds the GPU's).  One system; the first build of a new cell grid also
  * uploads that grid's cell tables (a synchronous copy, once per grid), and
  * a buffer that must grow is reallocated after a device synchronisation.
  * Builds of different plan slots may run concurrently on different streams;

@@ -801,6 +801,80 @@ __global__ __launch_bounds__(64 * kRowsPerBlock) void k_rowsort(int n,
   }
 }
 
+// Rows of up to kNetMax entries: one wave per row sorts it in registers
+// with a bitonic network (Batcher's merge network on the next power of two,
+// padded with INT_MAX).  Element e of the row sits in lane e % 64, register
+// e / 64, so loads and stores are coalesced; partners 1-32 apart are
+// exchanged by lane shuffles, partners 64 or more apart within the lane.
+// Waves are independent (no LDS, no barriers).
+constexpr int kNetMax = 1024;
+constexpr int kNetRows = 4;   // rows (waves) per workgroup
+
+template <int K>   // registers per lane: the row is padded to 64 K entries
+__device__ __forceinline__ void net_sort_row(int32_t* __restrict__ c, int m) {
+  const int lane = lane_id();
+  int v[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int e = q * 64 + lane;
+    v[q] = e < m ? c[e] : 0x7fffffff;
+  }
+#pragma unroll
+  for (int k = 2; k <= 64 * K; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {   // partner in register q ^ (j / 64) of the same lane
+        const int jq = j >> 6;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          if (q & jq) continue;
+          const int p = q | jq;
+          const bool up = (((q << 6) | lane) & k) == 0;
+          const int lo = min(v[q], v[p]), hi = max(v[q], v[p]);
+          v[q] = up ? lo : hi;
+          v[p] = up ? hi : lo;
+        }
+      } else {         // partner in lane ^ j, same register
+        const bool lower = (lane & j) == 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          const int o = __shfl_xor(v[q], j);
+          const bool up = (((q << 6) | lane) & k) == 0;
+          v[q] = (lower == up) ? min(v[q], o) : max(v[q], o);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int e = q * 64 + lane;
+    if (e < m) c[e] = v[q];
+  }
+}
+
+__global__ __launch_bounds__(64 * kNetRows) void k_rowsort_net(int n,
+                                                               const int32_t* __restrict__ row_ptr,
+                                                               int32_t* __restrict__ col,
+                                                               const int32_t* __restrict__ status) {
+  if (*status != 0) return;   // the build failed: row_ptr and col are not a list
+  const int i = blockIdx.x * kNetRows + (int)(threadIdx.x >> 6);
+  if (i >= n) return;         // wave-uniform: the whole wave leaves
+  const int start = row_ptr[i], m = row_ptr[i + 1] - start;
+  int32_t* c = col + start;
+  if (m <= 1) return;
+  if (m <= 64) net_sort_row<1>(c, m);
+  else if (m <= 128) net_sort_row<2>(c, m);
+  else if (m <= 256) net_sort_row<4>(c, m);
+  else if (m <= 512) net_sort_row<8>(c, m);
+  else if (m <= kNetMax) net_sort_row<16>(c, m);
+  // (longer rows never reach this kernel: the host takes k_rowsort when the
+  // row bound exceeds kNetMax, and a longer row fails the build)
+}
+
+// The row sort for a list whose rows hold at most max_row entries.
+tk_status launch_rowsort(hipStream_t st, int n, const int32_t* row_ptr, int32_t* col, int max_row,
+                         size_t lds1, const int32_t* status);
+
 // Dynamic LDS above the default limit must be allowed per kernel.
 // (Process-wide: several contexts on several host threads share it.)
 tk_status rowsort_attribute(size_t lds) {
@@ -811,6 +885,21 @@ tk_status rowsort_attribute(size_t lds) {
   TK_HIP(hipFuncSetAttribute((const void*)k_rowsort, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
   done = lds;
+  return TK_OK;
+}
+
+tk_status launch_rowsort(hipStream_t st, int n, const int32_t* row_ptr, int32_t* col, int max_row,
+                         size_t lds1, const int32_t* status) {
+  if (max_row <= kNetMax) {
+    k_rowsort_net<<<ceil_div(n, kNetRows), 64 * kNetRows, 0, st>>>(n, row_ptr, col, status);
+    return TK_OK;
+  }
+  // several rows per workgroup while they fit the default LDS limit
+  const int rpb = lds1 * kRowsPerBlock <= 65536 ? kRowsPerBlock : 1;
+  const size_t lds = lds1 * rpb;
+  tk_status s;
+  if (lds > 65536 && (s = rowsort_attribute(lds))) return s;
+  k_rowsort<<<ceil_div(n, rpb), 64 * rpb, lds, st>>>(n, row_ptr, col, max_row, status);
   return TK_OK;
 }
 
@@ -1214,17 +1303,11 @@ static tk_status build_finish(tk_ctx* ctx, BuildJob& J) {
   if (J.row_ptr) {
     const int nb = max_row < kBuckets ? max_row : kBuckets;
     const size_t lds1 = sizeof(int) * (2 * (size_t)max_row + 2 * (size_t)nb);
-    if (lds1 > kMaxLds) return TK_E_CAPACITY;
-    // several rows per workgroup while they fit the default LDS limit
-    const int rpb = lds1 * kRowsPerBlock <= 65536 ? kRowsPerBlock : 1;
-    const size_t lds = lds1 * rpb;
-    if (lds > 65536 && (s = rowsort_attribute(lds))) return s;
+    if (max_row > kNetMax && lds1 > kMaxLds) return TK_E_CAPACITY;
     if (n > 0 && list_pairs > 0) {
-      {
-        ProfScope ps(ctx, st, "nblist_rowsort");
-        k_rowsort<<<ceil_div(n, rpb), 64 * rpb, lds, st>>>(n, J.rp, J.col, max_row,
-                                                           (const int32_t*)P.dstat.p);
-      }
+      ProfScope ps(ctx, st, "nblist_rowsort");
+      if ((s = launch_rowsort(st, n, J.rp, J.col, max_row, lds1, (const int32_t*)P.dstat.p)))
+        return s;
     }
   }
   TK_HIP(hipGetLastError());
@@ -1303,7 +1386,7 @@ static tk_status build_finish_async(tk_ctx* ctx, BuildJob& J) {
   const int max_row = J.bd.max_row;
   const int nb = max_row < kBuckets ? max_row : kBuckets;
   const size_t lds1 = sizeof(int) * (2 * (size_t)max_row + 2 * (size_t)nb);
-  if (J.row_ptr && lds1 > kMaxLds) return TK_E_CAPACITY;
+  if (J.row_ptr && max_row > kNetMax && lds1 > kMaxLds) return TK_E_CAPACITY;
   if ((s = ensure(ctx, P.codes, sizeof(uint32_t) * (size_t)std::max<int64_t>(J.cap, 1))) ||
       (s = ensure(ctx, P.urec, sizeof(UnitRec) * (size_t)(nunits > 0 ? nunits : 1))))
     return s;
@@ -1321,12 +1404,9 @@ static tk_status build_finish_async(tk_ctx* ctx, BuildJob& J) {
                    (long)(P.codes.bytes / sizeof(uint32_t)), (const int32_t*)P.dstat.p);
   }
   if (J.row_ptr && n > 0) {
-    const int rpb = lds1 * kRowsPerBlock <= 65536 ? kRowsPerBlock : 1;
-    const size_t lds = lds1 * rpb;
-    if (lds > 65536 && (s = rowsort_attribute(lds))) return s;
     ProfScope ps(ctx, st, "nblist_rowsort");
-    k_rowsort<<<ceil_div(n, rpb), 64 * rpb, lds, st>>>(n, J.rp, J.col, max_row,
-                                                       (const int32_t*)P.dstat.p);
+    if ((s = launch_rowsort(st, n, J.rp, J.col, max_row, lds1, (const int32_t*)P.dstat.p)))
+      return s;
   }
   TK_HIP(hipGetLastError());
   P.valid = true;
