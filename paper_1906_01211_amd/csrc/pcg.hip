@@ -757,11 +757,35 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_apply(PlanView pv,
   }
 }
 
+// Outcome of a queued solve (tk_polarize_pcg_queued): the same fields and
+// rules as the synchronous call's host result; the mixed form's outcome is
+// its FP64 check.
+__device__ tk_pcg_info pcg_info_of(const PcgState& h, int mixed) {
+  tk_pcg_info r{};
+  r.iters = h.iters;
+  r.refinements = 0;
+  r.rms_debye = h.rms;
+  r.rms_true_debye = h.rms_true;
+  r.epol = h.epol;
+  if (h.done == 3 || h.done == 4) {
+    r.status = h.done == 3 ? TK_E_BREAKDOWN : TK_E_CAPACITY;
+    r.converged = 0;
+  } else {
+    const bool ok = mixed ? h.done != 0 && h.rms_true <= h.tol : h.done == 1;
+    r.status = ok ? TK_OK : TK_E_NOCONV;
+    r.converged = ok ? 1 : 0;
+  }
+  return r;
+}
+
 // One block per system and right-hand side (state sy * nv + v): true-residual
 // RMS and E_pol = -C/2 x_v.b_(nv-1-v) from the per-cell partials; mirrored to
 // the host.  Only once every right-hand side of the system has stopped.
+// info (nullable, device): the queued solve's outcome, one per state.
 __global__ __launch_bounds__(64) void k_cs_finish_true(PlanView pv, const double* __restrict__ part,
-                                                       PcgState* states, PcgState* host, int nv) {
+                                                       PcgState* states, PcgState* host, int nv,
+                                                       tk_pcg_info* __restrict__ info,
+                                                       int mixed) {
   __shared__ double sh[2 * 16];
   __shared__ int s_done;
   const int sy = blockIdx.x / nv, vi = blockIdx.x - sy * nv;
@@ -773,7 +797,10 @@ __global__ __launch_bounds__(64) void k_cs_finish_true(PlanView pv, const double
     s_done = all;
   }
   __syncthreads();
-  if (!s_done) return;
+  if (!s_done) {
+    if (info && threadIdx.x == 0) info[blockIdx.x] = pcg_info_of(*st, mixed);
+    return;
+  }
   const double* pv_part = part + vi * 2L * ncells;
   double v[2] = {0.0, 0.0};
   for (int c = pv.sys[sy].cell0 + threadIdx.x; c < pv.sys[sy + 1].cell0; c += 64) {
@@ -786,34 +813,10 @@ __global__ __launch_bounds__(64) void k_cs_finish_true(PlanView pv, const double
   st->rms_true = kDebye * sqrt(v[0] / npol);
   st->epol = -0.5 * kCoulomb * v[1];
   host[blockIdx.x] = *st;
+  if (info) info[blockIdx.x] = pcg_info_of(*st, mixed);
 }
 
 __global__ void k_pcg_info_empty(tk_pcg_info v, tk_pcg_info* __restrict__ out) { *out = v; }
-
-// Outcome of a queued solve (tk_polarize_pcg_queued) in the caller's device
-// memory: the same fields and rules as the synchronous call's host result;
-// the mixed form's outcome is its FP64 check.
-__global__ void k_pcg_info_out(const PcgState* __restrict__ states, int count, int mixed,
-                               tk_pcg_info* __restrict__ out) {
-  const int k = threadIdx.x;
-  if (k >= count) return;
-  const PcgState h = states[k];
-  tk_pcg_info r{};
-  r.iters = h.iters;
-  r.refinements = 0;
-  r.rms_debye = h.rms;
-  r.rms_true_debye = h.rms_true;
-  r.epol = h.epol;
-  if (h.done == 3 || h.done == 4) {
-    r.status = h.done == 3 ? TK_E_BREAKDOWN : TK_E_CAPACITY;
-    r.converged = 0;
-  } else {
-    const bool ok = mixed ? h.rms_true <= h.tol : h.done == 1;
-    r.status = ok ? TK_OK : TK_E_NOCONV;
-    r.converged = ok ? 1 : 0;
-  }
-  out[k] = r;
-}
 
 // Refinement: keep x in dx and start the correction from z (= alpha r_t) for
 // the systems being refined.
@@ -911,6 +914,7 @@ struct Solver {
   long vs = 0;    // offset between right-hand-side blocks of a vector (3n)
   int pme_grid = 0, pme_order = 0;   // full Ewald operator (one system, FP64) when set
   double* rz = nullptr;              // PME field of the current operand
+  tk_pcg_info* info_out = nullptr;   // queued solve: its outcome (device), by the FP64 residual
   double* rfb[2] = {nullptr, nullptr};   // PME field of p_k (k even, odd)
 
   // PME field of v (sorted) into rz, per right-hand side; run_when_done as
@@ -1071,7 +1075,8 @@ struct Solver {
       k_cs_apply<2><<<ncells, kCellThreads, 0, st>>>(pv, partial, pstride, cself, alpha_s, x, rhs,
                                                      nullptr, nullptr, part, state);
     }
-    k_cs_finish_true<<<nsys * nv, 64, 0, st>>>(pv, part, state, host_dev, nv);
+    k_cs_finish_true<<<nsys * nv, 64, 0, st>>>(pv, part, state, host_dev, nv, info_out,
+                                                prec == TK_MIXED ? 1 : 0);
   }
 
   tk_status sync_state() {
@@ -1332,9 +1337,9 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
                                                           S.alpha_s, S.x, S.npart, S.hdr, S.ent,
                                                           nv);
   if (queued) {
+    S.info_out = info_dev;
     if (prec == TK_FP64) S.run_queued<double>(S.b, tol_debye, queued);
     else S.run_queued<float>(S.b, tol_debye, queued);
-    k_pcg_info_out<<<1, 64, 0, st>>>(S.state, nsys * nv, prec == TK_MIXED ? 1 : 0, info_dev);
     k_scatter_out<<<ceil_div(n, 256), 256, 0, st>>>(n, (const int32_t*)P->perm.p, S.x, mu_out,
                                                     S.pv.status);
     TK_HIP(hipGetLastError());
