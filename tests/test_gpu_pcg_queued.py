@@ -192,3 +192,24 @@ def test_fused_queued_empty(ctx, tk):
     assert np_(en).tolist() == [0.0] * 3 and np_(v).tolist() == [0.0] * 9
     iq = ctx.pcg_info(idev)
     assert iq["status"] == 0 and iq["converged"] == 1
+
+
+def test_queued_mixed_outcome_is_the_fp64_check(ctx, tk):
+    # a tolerance below what the FP32 operator resolves: the synchronous mixed
+    # solve refines in FP64; the queued one does not refine, so it must report
+    # the failed FP64 check (not the FP32 recurrence's test)
+    w, sysr, lst, mp, pol, th = setup(ctx, "water216")
+    _, info = ctx.polarize_pcg(sysr, lst, mp, pol, th, S["beta"], S["rc_ewald"],
+                               tol_debye=1e-10, maxiter=100, prec=tk.MIXED)
+    assert info["refinements"] >= 1
+    _, idev = ctx.polarize_pcg_queued(sysr, lst, mp, pol, th, S["beta"], S["rc_ewald"], 100,
+                                      tol_debye=1e-10, prec=tk.MIXED)
+    iq = ctx.pcg_info(idev)
+    assert iq["rms_true_debye"] > 1e-10
+    assert iq["status"] == E_NOCONV and iq["converged"] == 0 and iq["refinements"] == 0
+    # at the usual tolerance the same queued solve meets its FP64 check
+    _, idev = ctx.polarize_pcg_queued(sysr, lst, mp, pol, th, S["beta"], S["rc_ewald"], 100,
+                                      tol_debye=S["tol_debye"], prec=tk.MIXED)
+    iq = ctx.pcg_info(idev)
+    assert iq["status"] == 0 and iq["converged"] == 1
+    assert iq["rms_true_debye"] <= S["tol_debye"]
