@@ -26,7 +26,10 @@
  *    that stream.  Entry points that return results through host memory
  *    (tk_nblist_build, tk_polarize_pcg, tk_batch_step) synchronise the
  *    stream to produce them; device outputs are always written in stream
- *    order.
+ *    order.  The stream-ordered forms (tk_nblist_build_async,
+ *    tk_polarize_pcg_queued, tk_empole_polarize_queued) return their sizes,
+ *    statuses and outcomes in device memory and never wait for the device
+ *    (except to grow a buffer, once).
  *  - Errors: every call returns a tk_status; argument errors are detected on
  *    the host before any work is queued; no exception crosses the ABI.
  *  - Precision: prec = TK_FP64 (all pair arithmetic in FP64) or TK_MIXED (pair
@@ -38,8 +41,8 @@
  *    queued on different streams may run concurrently where it touches
  *    different memory: the pair terms keep their scratch per stream and the
  *    builds of one tk_nblist_build_multi call have their own; the solver
- *    (tk_polarize_pcg) has one scratch set per context, so two solves of a
- *    context must be ordered, and a plan slot must not be rebuilt while work
+ *    (tk_polarize_pcg and its other forms) has one scratch set per context,
+ *    so two solves of a context must be ordered, and a plan slot must not be rebuilt while work
  *    that reads it is still queued on another stream.
  */
 #ifndef TK_H
