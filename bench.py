@@ -521,8 +521,10 @@ def main():
     if dom in dprof and dprof[dom]["launches"] > 0:
         launches = dprof[dom]["launches"]
         avg_ms = dprof[dom]["ms"] / launches
-        # launches per solve: iterations 0..iters-1 do the mat-vec, the last
-        # one only finds convergence and returns (timed solves: every tenth)
+        # launches per solve: iterations 0..iters-1 each do one mat-vec (the
+        # queued solve takes the last stopping test inside its FP64 residual
+        # launch; the mixed form keeps a launch for it, timed but not counted
+        # as work).  Timed solves: every tenth.
         solves = sampler.sampled
         working = iters * solves
         nl7 = int(step.l7_pairs)

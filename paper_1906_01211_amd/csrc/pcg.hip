@@ -268,6 +268,9 @@ struct MvArgs {
   long vs;              // offset between right-hand-side blocks (3n)
   PcgState* st;
   PcgState* host;
+  // mode 2 only: first take the stopping test of iteration k (as mode 1
+  // would), then the residual of the systems that stopped
+  int check;
 };
 
 template <class R, int kMode, bool kStage, bool kMulti, int NV>
@@ -306,7 +309,7 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
   double beta[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) beta[v] = 0.0;
-  if (kMode == 1) {
+  if (kMode == 1 || (kMode == 2 && A.check)) {
     const int npol_i = st->npol, maxiter = st->maxiter;
     const double tol = st->tol;
     double v3[3 * NV];
@@ -344,7 +347,9 @@ __global__ __launch_bounds__(kMvThreads) void k_pcg_mv(MvArgs<R> A) {
       if (stop) beta[v] = 0.0;
       else run = true;
     }
-    if (!run) return;
+    // mode 1 goes on while a system runs; mode 2 only once all have stopped
+    // (its operand is x itself: every beta is zero then)
+    if (kMode == 1 ? !run : run) return;
   } else {
     __syncthreads();
     bool all = true;
@@ -1057,14 +1062,23 @@ struct Solver {
   }
 
   // FP64 residual of x against rhs (rms_true, and epol from x.rhs), queued
-  // behind the iterations; its kernels run only for stopped systems.
-  void queue_true_residual(const double* rhs) {
+  // behind the iterations; its kernels run only for stopped systems.  With
+  // check_k >= 0 (FP64 path, no PME), the residual launch first takes the
+  // stopping test of iteration check_k, in place of that iteration's own
+  // mat-vec launch (which would only find the stop).
+  void queue_true_residual(const double* rhs, int check_k = -1) {
     if (prec == TK_FP64) {
       MvArgs<double> a = mv_args<double>();
       a.v = x;
       a.pold = x;
       a.rhs = rhs;
       a.part = part;
+      if (check_k >= 0) {
+        a.check = 1;
+        a.k = check_k;
+        a.pz_cur = pz[check_k & 1];
+        a.pz_prev = pz[(check_k + 1) & 1];
+      }
       if (pme_grid) {
         queue_pme(x, 1);
         a.rz = rz;
@@ -1171,11 +1185,13 @@ struct Solver {
       launch_mv<R, 0>(a, "pcg_mv0");
     }
     queue_mv<R>(0);
+    // FP64: the last stopping test rides on the residual launch
+    const bool fold = prec == TK_FP64 && !pme_grid && nv == 1;
     for (int k = 0; k < iters;) {
       queue_update(k);
-      queue_mv<R>(++k);
+      if (++k < iters || !fold) queue_mv<R>(k);
     }
-    queue_true_residual(rhs);
+    queue_true_residual(rhs, fold ? iters : -1);
   }
 };
 
