@@ -219,14 +219,16 @@ static_assert(kRedLanes == 4, "the butterfly above has two steps");
 // Per system: sum its chunk partials in order and write the energies and
 // virial.  Record layout: NS = 11: E_a, E_b, W[9] -> energy {E_a + E_b, E_a,
 // E_b}; NS = 10: E, W[9] -> energy {E}.  One wave per system.
+// The body is shared with the solver's setup kernel, which takes over this
+// launch for the fused multipole pass (every thread of the block calls it).
 template <int NS>
-__global__ __launch_bounds__(64) void k_sum_finish(const double* __restrict__ cpart,
-                                                   const SysDev* __restrict__ sys,
-                                                   double* __restrict__ energy,
-                                                   double* __restrict__ virial) {
+__device__ __forceinline__ void sum_finish_sys(const double* __restrict__ cpart,
+                                               const SysDev* __restrict__ sys,
+                                               double* __restrict__ energy,
+                                               double* __restrict__ virial, int sy) {
   static_assert(NS == 10 || NS == 11, "energy records");
   __shared__ double sh[NS];
-  const int sy = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   const int c0 = sys_chunk0(sys, sy);
   const int nch = (sys[sy + 1].unit0 - sys[sy].unit0 + kChunkUnits - 1) / kChunkUnits;
   if (tid < NS) {
@@ -243,6 +245,23 @@ __global__ __launch_bounds__(64) void k_sum_finish(const double* __restrict__ cp
     if (tid == 0) energy[3 * sy] = sh[0] + sh[1];
   }
 }
+
+template <int NS>
+__global__ __launch_bounds__(64) void k_sum_finish(const double* __restrict__ cpart,
+                                                   const SysDev* __restrict__ sys,
+                                                   double* __restrict__ energy,
+                                                   double* __restrict__ virial) {
+  sum_finish_sys<NS>(cpart, sys, energy, virial, blockIdx.x);
+}
+
+// A pass's energy and virial sums left to a later kernel on the same stream
+// (the solver's setup kernel, for the fused multipole pass of NS = 11).
+struct DeferredSums {
+  const double* cpart = nullptr;   // null: nothing deferred
+  double* energy = nullptr;
+  double* virial = nullptr;
+  int nsys = 0;
+};
 
 // LDS of k_units<Ph, W>: both cells' fields and W accumulator copies each.
 template <class Ph>

@@ -105,8 +105,13 @@ __global__ __launch_bounds__(kCellThreads) void k_cs_setup(PlanView pv, const do
                                                            double* __restrict__ x,
                                                            double* __restrict__ npart,
                                                            MvHdr* __restrict__ hdr,
-                                                           MvEnt* __restrict__ ent, int nv) {
+                                                           MvEnt* __restrict__ ent, int nv,
+                                                           DeferredSums sums, int g0) {
   __shared__ double sh[16];
+  if ((int)blockIdx.x >= g0) {   // blocks past the cells: the fused pass's energy sums
+    sum_finish_sys<11>(sums.cpart, pv.sys, sums.energy, sums.virial, blockIdx.x - g0);
+    return;
+  }
   const int pos = xcd_pos(pv.ncells, blockIdx.x);
   if (pos < 0) return;
   const int c = pv.cell_order[pos];
@@ -1309,14 +1314,17 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   // right-hand side: permanent field (sorted order); the same pass caches
   // the mat-vec's radial factors
   const tk_system sys1{n, xyz, P->box, molid};
+  // (the multipole pass's energy and virial sums are finished by the setup
+  // kernel below, one launch fewer)
+  DeferredSums sums;
   if (mp_energy)   // with the multipole energy, forces and virial from the same pass
     s = prec == TK_FP64
             ? launch_mpole_field<double>(ctx, st, *P, &sys1, mpole, polarity, thole, ewald_beta,
                                          cutoff, mp_energy, mp_force, mp_virial, S.b,
-                                         (double*)S.gc, S.gcs)
+                                         (double*)S.gc, S.gcs, &sums)
             : launch_mpole_field<float>(ctx, st, *P, &sys1, mpole, polarity, thole, ewald_beta,
                                         cutoff, mp_energy, mp_force, mp_virial, S.b,
-                                        (float*)S.gc, S.gcs);
+                                        (float*)S.gc, S.gcs, &sums);
   else
     s = prec == TK_FP64 ? launch_efield<double>(ctx, st, *P, &sys1, mpole, polarity, thole,
                                                 ewald_beta, cutoff, S.b, 1, (double*)S.gc, S.gcs)
@@ -1349,9 +1357,10 @@ tk_status solve_dipoles(tk_ctx* ctx, hipStream_t st, const Plan* P, const double
   if (pme_grid && (s = pme_prepare_sites(ctx, st, n, P->box, S.gathered, S.pstride, pme_grid,
                                          pme_order)))
     return s;
-  k_cs_setup<<<xcd_grid(S.ncells), kCellThreads, 0, st>>>(S.pv, polarity, mu_guess, guess_on, S.b,
-                                                          S.alpha_s, S.x, S.npart, S.hdr, S.ent,
-                                                          nv);
+  const int g0 = xcd_grid(S.ncells);
+  k_cs_setup<<<g0 + (sums.cpart ? sums.nsys : 0), kCellThreads, 0, st>>>(
+      S.pv, polarity, mu_guess, guess_on, S.b, S.alpha_s, S.x, S.npart, S.hdr, S.ent, nv, sums,
+      g0);
   if (queued) {
     S.info_out = info_dev;
     if (prec == TK_FP64) S.run_queued<double>(S.b, tol_debye, queued);

@@ -1524,7 +1524,8 @@ inline size_t term_ws_doubles(const Plan& P) {
 
 template <class Ph, class Epi>
 tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, const Epi& epi,
-                   double* energy, double* virial, const TermWs* ws = nullptr) {
+                   double* energy, double* virial, const TermWs* ws = nullptr,
+                   DeferredSums* defer = nullptr) {
   const long pstride = pad64(P.n);
   void *partial, *uscal;
   tk_status s;
@@ -1571,7 +1572,9 @@ tk_status run_term(tk_ctx* ctx, hipStream_t st, const Plan& P, const Ph& ph, con
                                                       (double*)cpart);
   }
   if constexpr (Ph::NS > 0) {
-    if (sums)
+    if (sums && defer && Ph::NS == 11)   // the caller's next kernel finishes the sums
+      *defer = DeferredSums{(const double*)cpart, energy, virial, P.nsys};
+    else if (sums)
       k_sum_finish<Ph::NS><<<P.nsys, 64, 0, st>>>((const double*)cpart, pv.sys, energy, virial);
   }
   TK_HIP(hipGetLastError());
@@ -1605,7 +1608,8 @@ inline tk_status launch_mpole_field(tk_ctx* ctx, hipStream_t st, const Plan& P,
                                     const tk_system* sys, const double* mpole,
                                     const double* polarity, const double* thole, double beta,
                                     double cutoff, double* energy, double* force, double* virial,
-                                    double* field_sorted, R* gc, long gcs) {
+                                    double* field_sorted, R* gc, long gcs,
+                                    DeferredSums* defer = nullptr) {
   MpoleFieldPh<R> ph;
   ph.gc = gc;
   ph.gcs = gcs;
@@ -1616,7 +1620,7 @@ inline tk_status launch_mpole_field(tk_ctx* ctx, hipStream_t st, const Plan& P,
   ph.thole = thole;
   ph.g.set(sys->box, cutoff, beta);
   EpiForceField epi{force, field_sorted, mpole, ph.g.cself};
-  return run_term(ctx, st, P, ph, epi, energy, virial);
+  return run_term(ctx, st, P, ph, epi, energy, virial, nullptr, defer);
 }
 
 }  // namespace tk
