@@ -556,7 +556,8 @@ static void compact_launch(double codes_per_unit, int nunits, size_t lds, hipStr
 
 // Per sorted atom: the CSR row length (sum over its unit roles, written in
 // caller order) and, in place, the exclusive prefix of its per-role counts.
-__global__ void k_row_slots(int n, const int32_t* __restrict__ perm, const int32_t* __restrict__ scell,
+constexpr int kRowSlotsThreads = 1024;
+__global__ __launch_bounds__(kRowSlotsThreads) void k_row_slots(int n, const int32_t* __restrict__ perm, const int32_t* __restrict__ scell,
                             const int32_t* __restrict__ cell_nslot, long pstride,
                             int32_t* __restrict__ slot_cnt, int32_t* __restrict__ row_cnt,
                             int32_t* __restrict__ info) {
@@ -574,10 +575,17 @@ __global__ void k_row_slots(int n, const int32_t* __restrict__ perm, const int32
     run += c[k];
   }
   if (valid) row_cnt[perm[s]] = run;
-  // longest row: wave maximum, then one atomic per wave (not per atom)
+  // longest row: wave maximum, then the workgroup's, then one atomic per
+  // workgroup (atomics on one word from every XCD serialise)
+  __shared__ int wmax[kRowSlotsThreads / 64];
   int m = run;
   for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
-  if ((threadIdx.x & 63) == 0) atomicMax(&info[2], m);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kRowSlotsThreads / 64; ++w) m = max(m, wmax[w]);
+    atomicMax(&info[2], m);
+  }
 }
 
 // Batch plans: the unit and cell tables of every system, from the per-nc
@@ -1046,7 +1054,8 @@ static tk_status enqueue_enumeration(tk_ctx* ctx, BuildJob& J) {
           (int64_t*)J.cnt64, (int32_t*)J.regcnt, (int2*)J.nfilt, (int32_t*)P.slots.p,
           (int32_t*)J.info, J.occ_cap);
     }
-    k_row_slots<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t*)P.perm.p, (int32_t*)P.scell.p,
+    k_row_slots<<<ceil_div(n, kRowSlotsThreads), kRowSlotsThreads, 0, st>>>(
+        n, (int32_t*)P.perm.p, (int32_t*)P.scell.p,
                                                    J.nslot, J.pstride, (int32_t*)P.slots.p,
                                                    (int32_t*)J.rcnt, (int32_t*)J.info);
     // row pointers, and the dense code offsets (with the unit-based pair
